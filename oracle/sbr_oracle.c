@@ -1,0 +1,992 @@
+/*
+ * sbr_oracle.c -- plain, slow FP64 CPU oracle (TEST INFRASTRUCTURE ONLY).
+ *
+ * Follows Zhou et al., "An Improved Equiangular Division Algorithm for SBR
+ * based Ray Tracing Channel Modeling", step by step, brute force over every
+ * triangle.  Readings of places where the paper is silent or garbled are
+ * stated next to the code that takes them.
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -fopenmp -fPIC
+ *        -shared sbr_oracle.c -lquadmath -lm
+ */
+#include "sbr_oracle.h"
+
+#include <complex.h>
+#include <math.h>
+#include <quadmath.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#if defined(__FP_FAST_FMA) && !defined(ORC_ALLOW_FMA)
+/* Not an error: -ffp-contract=off is what matters; this only documents it. */
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* small FP64 vector helpers; every operation is written in evaluation order */
+/* ------------------------------------------------------------------------ */
+typedef struct { double x, y, z; } v3;
+
+static v3 mk(double x, double y, double z) { v3 r = {x, y, z}; return r; }
+static v3 add(v3 a, v3 b) { return mk(a.x + b.x, a.y + b.y, a.z + b.z); }
+static v3 sub(v3 a, v3 b) { return mk(a.x - b.x, a.y - b.y, a.z - b.z); }
+static v3 scl(double s, v3 a) { return mk(s * a.x, s * a.y, s * a.z); }
+static double dot(v3 a, v3 b) { return (a.x * b.x + a.y * b.y) + a.z * b.z; }
+static v3 cross(v3 a, v3 b)
+{
+    return mk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+static double norm(v3 a) { return sqrt(dot(a, a)); }
+static v3 normalize(v3 a)
+{
+    double r = norm(a);
+    return mk(a.x / r, a.y / r, a.z / r);
+}
+static v3 ld3(const double* p) { return mk(p[0], p[1], p[2]); }
+static void st3(double* p, v3 a) { p[0] = a.x; p[1] = a.y; p[2] = a.z; }
+
+static const double C0 = 299792458.0;            /* speed of light, m/s   */
+static const double PI_D = 3.14159265358979323846; /* nearest double to pi */
+
+/* Correctly rounded transcendental values: binary128 then one rounding. */
+double orc_sin_cr(double x) { return (double)sinq((__float128)x); }
+double orc_acos_cr(double x) { return (double)acosq((__float128)x); }
+static double tan_cr(double x) { return (double)tanq((__float128)x); }
+static double atan_cr(double x) { return (double)atanq((__float128)x); }
+
+/* theta_0 = angle subtended by one icosahedron edge = atan(2) (eq. (4)). */
+static double theta0(void) { return atan_cr(2.0); }
+/* Cone half-angle theta_launch = theta_0 / (sqrt(3) n), eq. (4). */
+static double theta_launch(int32_t n) { return theta0() / (sqrt(3.0) * (double)n); }
+
+/* ======================================================================== */
+/* Launch grid -- Sec. II.B                                                  */
+/* ======================================================================== */
+/* Icosahedron: the 12 cyclic permutations of (0, +-1, +-phi), normalized, in
+ * this fixed order.  Edges are the 30 vertex pairs with positive dot product
+ * (adjacent vertices subtend theta_0; non-adjacent ones have dot <= -1/sqrt5),
+ * listed lexicographically (i < j).  Faces are the 20 mutually adjacent
+ * triples i < j < k, listed lexicographically, each wound so that it is
+ * counter-clockwise seen from outside -- which is clockwise seen from the
+ * launch point O, the paper's "arranged clockwise". */
+typedef struct {
+    v3 V[12];
+    int e[30][2];
+    int f[20][3];
+} ico_t;
+
+static void ico_build(ico_t* ic)
+{
+    double phi = (1.0 + sqrt(5.0)) / 2.0;
+    const double raw[12][3] = {
+        {0, 1, phi}, {0, -1, phi}, {0, 1, -phi}, {0, -1, -phi},
+        {1, phi, 0}, {-1, phi, 0}, {1, -phi, 0}, {-1, -phi, 0},
+        {phi, 0, 1}, {phi, 0, -1}, {-phi, 0, 1}, {-phi, 0, -1}};
+    for (int i = 0; i < 12; ++i) ic->V[i] = normalize(ld3(raw[i]));
+    int ne = 0, nf = 0;
+    int adj[12][12];
+    for (int i = 0; i < 12; ++i)
+        for (int j = 0; j < 12; ++j) adj[i][j] = (i != j) && dot(ic->V[i], ic->V[j]) > 0.0;
+    for (int i = 0; i < 12; ++i)
+        for (int j = i + 1; j < 12; ++j)
+            if (adj[i][j]) { ic->e[ne][0] = i; ic->e[ne][1] = j; ++ne; }
+    for (int i = 0; i < 12; ++i)
+        for (int j = i + 1; j < 12; ++j)
+            for (int k = j + 1; k < 12; ++k)
+                if (adj[i][j] && adj[j][k] && adj[i][k]) {
+                    double s = dot(ic->V[i], cross(ic->V[j], ic->V[k]));
+                    ic->f[nf][0] = i;
+                    ic->f[nf][1] = s > 0.0 ? j : k;
+                    ic->f[nf][2] = s > 0.0 ? k : j;
+                    ++nf;
+                }
+}
+
+/* Point k of m equal-angle steps from P to Q on the great circle (eq. (1):
+ * consecutive points subtend the same angle at O).  The direction is
+ * sin((m-k)th/m) P + sin(k th/m) Q, normalized (the 1/sin(th) factor of the
+ * usual slerp only rescales and is dropped). */
+static v3 arc_point(v3 P, v3 Q, int64_t k, int64_t m)
+{
+    double th = orc_acos_cr(dot(P, Q));
+    double a = ((double)k * th) / (double)m;
+    double b = ((double)(m - k) * th) / (double)m;
+    double sa = orc_sin_cr(a), sb = orc_sin_cr(b);
+    return normalize(add(scl(sb, P), scl(sa, Q)));
+}
+
+/* Rings of one icosahedron face.  Layer 0 is the face boundary: vertices
+ * W0,W1,W2 = the face's corners and m = n equal-angle steps per side.  Layer
+ * a+1 has side m-3; its corners come from eq. (2): X' = P^1 + P^{-1} - P^0,
+ * i.e. the parallelogram completion at each corner using the two ring points
+ * adjacent to it.  Reading: eq. (2) is evaluated on the flat icosahedron face
+ * (Fig. 3b draws B, C, D on the edge AE), so every point is first centrally
+ * projected onto a plane parallel to the face, X' is formed there and then
+ * turned back into a direction.  The plane x.g = 1 with g = A+B+C is used
+ * (any parallel plane gives the same direction, the construction is affine).
+ * Side m' = 0 is the single centre ray normalize(A+B+C); m' < 0 ends. */
+typedef struct {
+    int32_t nl;        /* number of inner layers (a = 1..nl)            */
+    v3* W;             /* [nl][3] corners of layer a (index a-1)         */
+    int64_t* m;        /* [nl] side of layer a (0 = centre point)        */
+    int64_t* start;    /* [nl] first interior index of layer a           */
+} face_rings;
+
+static v3 proj_face(v3 p, v3 g)
+{
+    double w = dot(p, g);
+    return mk(p.x / w, p.y / w, p.z / w);
+}
+
+static void rings_build(face_rings* R, const ico_t* ic, int fi, int32_t n)
+{
+    v3 A = ic->V[ic->f[fi][0]], B = ic->V[ic->f[fi][1]], C = ic->V[ic->f[fi][2]];
+    v3 g = add(add(A, B), C);
+    int32_t cap = n / 3 + 2;
+    R->W = (v3*)malloc(sizeof(v3) * 3 * (size_t)cap);
+    R->m = (int64_t*)malloc(sizeof(int64_t) * (size_t)cap);
+    R->start = (int64_t*)malloc(sizeof(int64_t) * (size_t)cap);
+    v3 W[3] = {A, B, C};
+    int64_t m = n;
+    int32_t nl = 0;
+    int64_t pos = 0;
+    for (;;) {
+        int64_t mp = m - 3;
+        if (mp < 0) break;
+        R->start[nl] = pos;
+        if (mp == 0) {
+            R->W[3 * nl + 0] = R->W[3 * nl + 1] = R->W[3 * nl + 2] = normalize(add(add(A, B), C));
+            R->m[nl] = 0;
+            ++nl;
+            pos += 1;
+            break;
+        }
+        v3 Wn[3];
+        for (int s = 0; s < 3; ++s) {
+            v3 P0 = W[s];
+            v3 P1 = arc_point(W[s], W[(s + 1) % 3], 1, m);      /* next on side s   */
+            v3 Pm = arc_point(W[(s + 2) % 3], W[s], m - 1, m);  /* last on side s-1 */
+            v3 X = sub(add(proj_face(P1, g), proj_face(Pm, g)), proj_face(P0, g));
+            Wn[s] = normalize(X);
+        }
+        for (int s = 0; s < 3; ++s) { W[s] = Wn[s]; R->W[3 * nl + s] = Wn[s]; }
+        R->m[nl] = mp;
+        ++nl;
+        pos += 3 * mp;
+        m = mp;
+    }
+    R->nl = nl;
+}
+
+static void rings_free(face_rings* R)
+{
+    free(R->W); free(R->m); free(R->start);
+}
+
+int64_t orc_num_rays(int32_t n)
+{
+    if (n < 1) return 0;
+    return 10 * (int64_t)n * n + 2;
+}
+
+typedef struct {
+    int32_t n;
+    ico_t ic;
+    face_rings fr[20];
+} grid_t;
+
+static void grid_init(grid_t* G, int32_t n)
+{
+    G->n = n;
+    ico_build(&G->ic);
+    for (int f = 0; f < 20; ++f) rings_build(&G->fr[f], &G->ic, f, n);
+}
+static void grid_free(grid_t* G)
+{
+    for (int f = 0; f < 20; ++f) rings_free(&G->fr[f]);
+}
+
+/* Ray order: 12 vertex rays; then edge interiors, edge by edge, k = 1..n-1
+ * from the lower to the higher vertex index; then face interiors, face by
+ * face, layer by layer, each ring P^0..P^{3m-1} starting at the corner that
+ * descends from the face's first vertex. */
+static v3 grid_dir(const grid_t* G, int64_t idx)
+{
+    const int64_t n = G->n;
+    if (idx < 12) return G->ic.V[idx];
+    idx -= 12;
+    if (idx < 30 * (n - 1)) {
+        int64_t e = idx / (n - 1), k = idx % (n - 1) + 1;
+        return arc_point(G->ic.V[G->ic.e[e][0]], G->ic.V[G->ic.e[e][1]], k, n);
+    }
+    idx -= 30 * (n - 1);
+    int64_t per_face = (n - 1) * (n - 2) / 2;
+    int64_t f = idx / per_face, r = idx % per_face;
+    const face_rings* R = &G->fr[f];
+    int32_t a = 0;
+    while (a + 1 < R->nl && R->start[a + 1] <= r) ++a;
+    r -= R->start[a];
+    int64_t m = R->m[a];
+    const v3* W = &R->W[3 * a];
+    if (m == 0) return W[0];
+    int64_t s = r / m, k = r % m;
+    if (k == 0) return W[s];
+    return arc_point(W[s], W[(s + 1) % 3], k, m);
+}
+
+int orc_launch_dirs(int32_t n, const int64_t* ids, int64_t m, double* out)
+{
+    if (n < 1 || !out) return -1;
+    int64_t N = orc_num_rays(n);
+    if (!ids) m = N;
+    grid_t G;
+    grid_init(&G, n);
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t id = ids ? ids[i] : i;
+        if (id < 0 || id >= N) { bad = 1; continue; }
+        st3(out + 3 * i, grid_dir(&G, id));
+    }
+    grid_free(&G);
+    return bad ? -1 : 0;
+}
+
+/* ======================================================================== */
+/* Scene and closest hit -- Sec. III.A                                       */
+/* ======================================================================== */
+typedef struct {
+    int64_t T;
+    int32_t F;
+    v3 *v0, *e1, *e2;
+    const int32_t *face, *mat;
+    v3* fn;          /* [F] face plane unit normal                        */
+    double* fc;      /* [F] plane offset fn . v0                          */
+    int32_t* fmat;   /* [F] material of the face                          */
+    double t_eps;    /* 1e-9 * diagonal of the scene bounding box         */
+} scene_t;
+
+/* Reading: a face is a planar polygon (face_id); its plane is taken from its
+ * lowest-index triangle, n = normalize(e1 x e2), and so is its material. */
+static int scene_init(scene_t* S, const double* tri_v, const int32_t* face_id,
+                      const int32_t* mat_id, int64_t T)
+{
+    memset(S, 0, sizeof(*S));
+    S->T = T;
+    S->face = face_id;
+    S->mat = mat_id;
+    S->v0 = (v3*)malloc(sizeof(v3) * (size_t)(T > 0 ? T : 1));
+    S->e1 = (v3*)malloc(sizeof(v3) * (size_t)(T > 0 ? T : 1));
+    S->e2 = (v3*)malloc(sizeof(v3) * (size_t)(T > 0 ? T : 1));
+    int32_t F = 0;
+    v3 lo = mk(INFINITY, INFINITY, INFINITY), hi = mk(-INFINITY, -INFINITY, -INFINITY);
+    for (int64_t i = 0; i < T; ++i) {
+        v3 a = ld3(tri_v + 9 * i), b = ld3(tri_v + 9 * i + 3), c = ld3(tri_v + 9 * i + 6);
+        S->v0[i] = a;
+        S->e1[i] = sub(b, a);
+        S->e2[i] = sub(c, a);
+        if (face_id[i] < 0) return -1;
+        if (face_id[i] + 1 > F) F = face_id[i] + 1;
+        v3 p[3] = {a, b, c};
+        for (int q = 0; q < 3; ++q) {
+            lo.x = fmin(lo.x, p[q].x); lo.y = fmin(lo.y, p[q].y); lo.z = fmin(lo.z, p[q].z);
+            hi.x = fmax(hi.x, p[q].x); hi.y = fmax(hi.y, p[q].y); hi.z = fmax(hi.z, p[q].z);
+        }
+    }
+    S->F = F;
+    S->fn = (v3*)calloc((size_t)(F > 0 ? F : 1), sizeof(v3));
+    S->fc = (double*)calloc((size_t)(F > 0 ? F : 1), sizeof(double));
+    S->fmat = (int32_t*)calloc((size_t)(F > 0 ? F : 1), sizeof(int32_t));
+    int32_t* seen = (int32_t*)calloc((size_t)(F > 0 ? F : 1), sizeof(int32_t));
+    for (int64_t i = 0; i < T; ++i) {
+        int32_t f = face_id[i];
+        if (seen[f]) continue;
+        seen[f] = 1;
+        S->fn[f] = normalize(cross(S->e1[i], S->e2[i]));
+        S->fc[f] = dot(S->fn[f], S->v0[i]);
+        S->fmat[f] = mat_id ? mat_id[i] : 0;
+    }
+    free(seen);
+    if (T > 0) {
+        v3 d = sub(hi, lo);
+        S->t_eps = 1e-9 * norm(d);
+    }
+    return 0;
+}
+
+static void scene_free(scene_t* S)
+{
+    free(S->v0); free(S->e1); free(S->e2); free(S->fn); free(S->fc); free(S->fmat);
+}
+
+/* Moller-Trumbore, in exactly this order:
+ *   p = d x e2, det = e1.p (det == 0: miss), s = o - v0,
+ *   u = (s.p)/det, q = s x e1, v = (d.q)/det, t = (e2.q)/det,
+ *   hit iff u >= 0, v >= 0, u + v <= 1 and t_lo < t < t_hi. */
+static int mt_hit(const scene_t* S, int64_t i, v3 o, v3 d, double t_lo, double t_hi, double* t_out)
+{
+    v3 p = cross(d, S->e2[i]);
+    double det = dot(S->e1[i], p);
+    if (det == 0.0) return 0;
+    v3 s = sub(o, S->v0[i]);
+    double u = dot(s, p) / det;
+    v3 q = cross(s, S->e1[i]);
+    double v = dot(d, q) / det;
+    double t = dot(S->e2[i], q) / det;
+    if (u >= 0.0 && v >= 0.0 && u + v <= 1.0 && t > t_lo && t < t_hi) {
+        *t_out = t;
+        return 1;
+    }
+    return 0;
+}
+
+/* Closest hit over every triangle except those of the face just left (a
+ * planar face cannot be hit again right after reflecting on it).  Ties of t
+ * go to the lower face id, then the lower triangle index. */
+static int64_t closest_hit(const scene_t* S, v3 o, v3 d, int32_t prev_face, double* t_out)
+{
+    int64_t best = -1;
+    double bt = INFINITY;
+    for (int64_t i = 0; i < S->T; ++i) {
+        if (S->face[i] == prev_face) continue;
+        double t;
+        if (!mt_hit(S, i, o, d, S->t_eps, INFINITY, &t)) continue;
+        if (best < 0 || t < bt || (t == bt && S->face[i] < S->face[best])) {
+            best = i;
+            bt = t;
+        }
+    }
+    *t_out = best < 0 ? INFINITY : bt;
+    return best;
+}
+
+/* Specular reflection off the face plane: d' = d - 2 (d.n) n (no
+ * renormalization).  Next origin o' = o + t d. */
+static v3 reflect_dir(v3 d, v3 n)
+{
+    double k = 2.0 * dot(d, n);
+    return sub(d, scl(k, n));
+}
+
+/* One traced segment of a ray. */
+typedef struct {
+    v3 o, d;
+    double D;          /* unfolded length from Tx to o                   */
+    double t;          /* parameter of the next hit (+inf: none)         */
+    int64_t tri;       /* next hit triangle (-1: none)                   */
+} seg_t;
+
+/* Trace up to K reflections: fills segs[0..ns-1], returns ns (<= K+1).
+ * Segment j starts after j reflections. */
+static int trace_ray(const scene_t* S, v3 tx, v3 d0, int32_t K, seg_t* segs)
+{
+    v3 o = tx, d = d0;
+    double D = 0.0;
+    int32_t prev = -1;
+    int ns = 0;
+    for (int32_t j = 0; j <= K; ++j) {
+        double t;
+        int64_t tri = closest_hit(S, o, d, prev, &t);
+        segs[ns].o = o; segs[ns].d = d; segs[ns].D = D; segs[ns].t = t; segs[ns].tri = tri;
+        ++ns;
+        if (tri < 0 || j == K) break;
+        int32_t f = S->face[tri];
+        v3 on = add(o, scl(t, d));
+        d = reflect_dir(d, S->fn[f]);
+        D = D + t;
+        o = on;
+        prev = f;
+    }
+    return ns;
+}
+
+/* Reception test and error angle (eq. (3)) for one segment and one Rx.
+ * t* = (Rx - o).d is the foot of the perpendicular; accept iff 0 < t* <= t
+ * (Rx in front of the segment start and before its next hit) and Rx lies
+ * inside the ray cone, d_perp <= theta_launch (D + t*).  Reading: the
+ * propagation distance d_ray of eq. (3) is the unfolded length to the foot
+ * D + t*, so tan(theta_error) = d_perp / (D + t*) is the angle between the
+ * ray and the exact departure direction toward the image of Rx.  With
+ * thl < 0 the cone condition is skipped (used by the precise algorithm). */
+static int capture_seg(const seg_t* sg, v3 rx, double thl, double* tan_out)
+{
+    v3 w = sub(rx, sg->o);
+    double ts = dot(w, sg->d);
+    if (!(ts > 0.0)) return 0;
+    if (!(ts <= sg->t)) return 0;
+    v3 f = sub(w, scl(ts, sg->d));
+    double dp = norm(f);
+    double L = sg->D + ts;
+    if (thl >= 0.0 && !(dp <= thl * L)) return 0;
+    *tan_out = dp / L;
+    return 1;
+}
+
+int orc_trace_rays(const double* tri_v, const int32_t* face_id, int64_t n_tri,
+                   const double tx[3], int32_t n, int32_t K,
+                   const int64_t* ids, int64_t m, int32_t n_threads,
+                   int32_t* out_tri, int32_t* out_face, double* out_t)
+{
+    if (n < 1 || K < 0 || K > ORC_MAX_ORDER || n_tri < 0) return -1;
+    int64_t N = orc_num_rays(n);
+    if (!ids) m = N;
+    scene_t S;
+    if (scene_init(&S, tri_v, face_id, NULL, n_tri)) { scene_free(&S); return -1; }
+    grid_t G;
+    grid_init(&G, n);
+    v3 T = ld3(tx);
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(| : bad)
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t id = ids ? ids[i] : i;
+        if (id < 0 || id >= N) { bad = 1; continue; }
+        seg_t segs[ORC_MAX_ORDER + 1];
+        int ns = trace_ray(&S, T, grid_dir(&G, id), K, segs);
+        for (int j = 0; j <= K; ++j) {
+            int64_t o = i * (K + 1) + j;
+            int64_t tri = j < ns ? segs[j].tri : -1;
+            if (out_tri) out_tri[o] = (int32_t)tri;
+            if (out_face) out_face[o] = tri < 0 ? -1 : face_id[tri];
+            if (out_t) out_t[o] = j < ns ? segs[j].t : INFINITY;
+        }
+    }
+    grid_free(&G);
+    scene_free(&S);
+    return bad ? -1 : 0;
+}
+
+int orc_trace_dirs(const double* tri_v, const int32_t* face_id, int64_t n_tri,
+                   const double tx[3], const double* dirs, int64_t m, int32_t K,
+                   int32_t* out_tri, int32_t* out_face, double* out_t, double* out_D)
+{
+    if (K < 0 || K > ORC_MAX_ORDER || n_tri < 0 || m < 0) return -1;
+    scene_t S;
+    if (scene_init(&S, tri_v, face_id, NULL, n_tri)) { scene_free(&S); return -1; }
+    v3 T = ld3(tx);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < m; ++i) {
+        seg_t segs[ORC_MAX_ORDER + 1];
+        int ns = trace_ray(&S, T, ld3(dirs + 3 * i), K, segs);
+        for (int j = 0; j <= K; ++j) {
+            int64_t o = i * (K + 1) + j;
+            int64_t tri = j < ns ? segs[j].tri : -1;
+            if (out_tri) out_tri[o] = (int32_t)tri;
+            if (out_face) out_face[o] = tri < 0 ? -1 : face_id[tri];
+            if (out_t) out_t[o] = j < ns ? segs[j].t : INFINITY;
+            if (out_D) out_D[o] = j < ns ? segs[j].D : NAN;
+        }
+    }
+    scene_free(&S);
+    return 0;
+}
+
+/* ======================================================================== */
+/* Path test 1 (double counting) -- Sec. III.A                               */
+/* ======================================================================== */
+static int key_cmp(const orc_candidate* a, const orc_candidate* b)
+{
+    if (a->rx != b->rx) return a->rx < b->rx ? -1 : 1;
+    if (a->order != b->order) return a->order < b->order ? -1 : 1;
+    for (int j = 0; j < a->order; ++j)
+        if (a->face[j] != b->face[j]) return a->face[j] < b->face[j] ? -1 : 1;
+    return 0;
+}
+
+/* Same faces: keep the smaller error angle; reading: equal angles keep the
+ * lower launch-ray index. */
+static int cand_cmp(const void* pa, const void* pb)
+{
+    const orc_candidate *a = (const orc_candidate*)pa, *b = (const orc_candidate*)pb;
+    int c = key_cmp(a, b);
+    if (c) return c;
+    if (a->tan_err != b->tan_err) return a->tan_err < b->tan_err ? -1 : 1;
+    if (a->ray != b->ray) return a->ray < b->ray ? -1 : 1;
+    return 0;
+}
+
+/* ======================================================================== */
+/* Precise algorithm -- Sec. III.B                                           */
+/* ======================================================================== */
+/* Trace direction d from Tx through exactly the faces of the path and report
+ * the error angle of Rx on the last segment (no cone condition): the
+ * sub-ray is a usable path only if it meets the same faces in the same order
+ * and Rx lies ahead on its last segment before the next obstacle. */
+typedef struct {
+    double tan_err;
+    double D, Llast;    /* unfolded length to the last reflection, |Rx - p_k| */
+    v3 p[ORC_MAX_ORDER];
+    v3 din[ORC_MAX_ORDER];
+} follow_t;
+
+static int follow_path(const scene_t* S, v3 tx, v3 d0, v3 rx, int32_t k, const int32_t* faces,
+                       follow_t* out)
+{
+    seg_t segs[ORC_MAX_ORDER + 1];
+    int ns = trace_ray(S, tx, d0, k, segs);
+    if (ns != k + 1) return 0;
+    for (int j = 0; j < k; ++j)
+        if (segs[j].tri < 0 || S->face[segs[j].tri] != faces[j]) return 0;
+    double tn;
+    if (!capture_seg(&segs[k], rx, -1.0, &tn)) return 0;
+    if (out) {
+        out->tan_err = tn;
+        out->D = segs[k].D;
+        out->Llast = norm(sub(rx, segs[k].o));
+        for (int j = 0; j < k; ++j) { out->p[j] = segs[j + 1].o; out->din[j] = segs[j].d; }
+    }
+    return 1;
+}
+
+/* Orthonormal basis (u, v) of the plane normal to axis a: e is the
+ * coordinate axis with the smallest |a_i| (ties: lowest i),
+ * u = normalize(e - a_i a), v = a x u. */
+static void basis(v3 a, v3* u, v3* v)
+{
+    double c[3] = {fabs(a.x), fabs(a.y), fabs(a.z)};
+    int i = 0;
+    if (c[1] < c[i]) i = 1;
+    if (c[2] < c[i]) i = 2;
+    v3 e = mk(i == 0 ? 1.0 : 0.0, i == 1 ? 1.0 : 0.0, i == 2 ? 1.0 : 0.0);
+    double ai = i == 0 ? a.x : (i == 1 ? a.y : a.z);
+    *u = normalize(sub(e, scl(ai, a)));
+    *v = cross(a, *u);
+}
+
+/* Sub-ray s of a cone with axis a: the cone's disc (radius rho_prev in the
+ * plane tangent to the unit sphere at a) is covered by six discs of radius
+ * rho = rho_prev / sqrt(3) centred at distance rho from the axis, at phases
+ * 0, 60, ..., 300 degrees (six circles of radius r/sqrt3 at distance r/sqrt3
+ * exactly cover the disc of radius r).  The seventh sub-ray (s = 6) is the
+ * axis itself. */
+static v3 subray(v3 a, v3 u, v3 v, double rho, int s)
+{
+    if (s == 6) return a;
+    const double h = sqrt(3.0) * 0.5;
+    const double cs[6] = {1.0, 0.5, -0.5, -1.0, -0.5, 0.5};
+    const double ss[6] = {0.0, h, h, 0.0, -h, -h};
+    v3 w = add(scl(cs[s], u), scl(ss[s], v));
+    return normalize(add(a, scl(rho, w)));
+}
+
+/* Stop rule "error satisfies the requirement" (reading): with a target error
+ * angle, stop once tan(err) <= tan(target) * Llast / Ltot.  The AOA error of
+ * a path grows from its AOD error roughly by D_k / Llast, so this scale makes
+ * both AOD and AOA meet the target. */
+static int target_met(double tan_err, double tan_tgt, double D, double Llast)
+{
+    double Ltot = D + Llast;
+    double thr = (tan_tgt * Llast) / Ltot;
+    return tan_err <= thr;
+}
+
+typedef struct {
+    v3 axis;
+    double tan_err;
+    int32_t iters;
+    uint32_t flags;
+    follow_t fw;
+} refine_t;
+
+/* One path: start from the winner of path test 1 and iterate. */
+static void refine_path(const scene_t* S, v3 tx, v3 rx, int32_t k, const int32_t* faces,
+                        v3 a0, int32_t n_it, int32_t Sn, double tan_tgt, double thl,
+                        refine_t* R, double* hist)
+{
+    R->axis = a0;
+    R->iters = 0;
+    R->flags = 0;
+    if (!follow_path(S, tx, a0, rx, k, faces, &R->fw)) {
+        /* cannot happen for a captured ray; guarded for external rows */
+        R->tan_err = NAN;
+        R->flags |= 1u;
+        if (hist) hist[0] = NAN;
+        return;
+    }
+    R->tan_err = R->fw.tan_err;
+    if (hist) hist[0] = R->tan_err;
+    double rho = thl;
+    int met = tan_tgt > 0.0 && target_met(R->tan_err, tan_tgt, R->fw.D, R->fw.Llast);
+    if (met) R->flags |= 4u;
+    for (int32_t i = 1; i <= n_it && !met; ++i) {
+        rho = rho / sqrt(3.0);
+        v3 u, v;
+        basis(R->axis, &u, &v);
+        int bs = -1;
+        double bt = INFINITY;
+        v3 bd = R->axis;
+        follow_t bfw;
+        for (int s = 0; s < Sn; ++s) {
+            v3 ds = subray(R->axis, u, v, rho, s);
+            follow_t fw;
+            if (!follow_path(S, tx, ds, rx, k, faces, &fw)) continue;
+            if (fw.tan_err < bt) { bt = fw.tan_err; bs = s; bd = ds; bfw = fw; }
+        }
+        if (bs < 0) {
+            R->flags |= 1u;   /* STALLED: no sub-ray keeps the face sequence */
+            if (hist) for (int32_t q = i; q <= n_it; ++q) hist[q] = R->tan_err;
+            break;
+        }
+        R->axis = bd;
+        R->tan_err = bt;
+        R->fw = bfw;
+        R->iters = i;
+        if (hist) hist[i] = bt;
+        if (tan_tgt > 0.0 && target_met(bt, tan_tgt, bfw.D, bfw.Llast)) {
+            R->flags |= 4u;
+            met = 1;
+        }
+    }
+}
+
+/* ======================================================================== */
+/* Path quantities, validity (path test 2) and power                         */
+/* ======================================================================== */
+/* Fresnel reflection coefficients for relative permittivity er (e^{jwt}
+ * convention, er = e' - j e''), principal complex square root:
+ *   G_perp = (c - sqrt(er - s^2)) / (c + sqrt(er - s^2))
+ *   G_par  = (er c - sqrt(er - s^2)) / (er c + sqrt(er - s^2)).
+ * Reading (the paper gives no power formula): unpolarized average
+ * 0.5 (|G_perp|^2 + |G_par|^2). */
+double orc_fresnel_avg(double c, double er_re, double er_im)
+{
+    double complex er = CMPLX(er_re, er_im);
+    double s2 = 1.0 - c * c;
+    double complex root = csqrt(er - s2);
+    double complex gs = (c - root) / (c + root);
+    double complex gp = (er * c - root) / (er * c + root);
+    double as = cabs(gs), ap = cabs(gp);
+    return 0.5 * (as * as + ap * ap);
+}
+
+/* P_r = P_t + 20 log10(lambda / (4 pi L)) + sum_j 10 log10(R_j)  [dBm] */
+static double path_power(double ptx, double freq, double L, const double* refl, int k)
+{
+    double lambda = C0 / freq;
+    double p = ptx + 20.0 * log10(lambda / (4.0 * PI_D * L));
+    for (int j = 0; j < k; ++j) p += 10.0 * log10(refl[j]);
+    return p;
+}
+
+static double refl_at(const scene_t* S, const double* er, const double* ei, int32_t f, v3 din)
+{
+    double c = fabs(dot(din, S->fn[f])) / norm(din);
+    int32_t mt = S->fmat[f];
+    return orc_fresnel_avg(c, er[mt], ei[mt]);
+}
+
+/* Point inside a face: inside any triangle of the face, barycentric
+ * coordinates with tolerance 1e-9. */
+static int inside_face(const scene_t* S, int32_t f, v3 p)
+{
+    const double tol = 1e-9;
+    for (int64_t i = 0; i < S->T; ++i) {
+        if (S->face[i] != f) continue;
+        v3 w = sub(p, S->v0[i]);
+        double d00 = dot(S->e1[i], S->e1[i]);
+        double d01 = dot(S->e1[i], S->e2[i]);
+        double d11 = dot(S->e2[i], S->e2[i]);
+        double d20 = dot(w, S->e1[i]);
+        double d21 = dot(w, S->e2[i]);
+        double den = d00 * d11 - d01 * d01;
+        if (den == 0.0) continue;
+        double b = (d11 * d20 - d01 * d21) / den;
+        double g = (d00 * d21 - d01 * d20) / den;
+        if (b >= -tol && g >= -tol && b + g <= 1.0 + tol) return 1;
+    }
+    return 0;
+}
+
+/* Segment A -> B blocked by any triangle not of faces fa / fb, hit strictly
+ * inside (1e-9, 1 - 1e-9) of the segment parameter. */
+static int blocked(const scene_t* S, v3 A, v3 B, int32_t fa, int32_t fb)
+{
+    v3 d = sub(B, A);
+    for (int64_t i = 0; i < S->T; ++i) {
+        int32_t f = S->face[i];
+        if (f == fa || f == fb) continue;
+        double t;
+        if (mt_hit(S, i, A, d, 1e-9, 1.0 - 1e-9, &t)) return 1;
+    }
+    return 0;
+}
+
+/* Exact path for a face sequence by the image method: images of Tx mirrored
+ * across the face planes in order, then back-projection from Rx.  Path test
+ * 2 (validity): every back-projection parameter in (0,1), every reflection
+ * point inside its face, no segment blocked. */
+static int exact_solve(const scene_t* S, v3 tx, v3 rx, int32_t k, const int32_t* faces, v3* pts)
+{
+    v3 img[ORC_MAX_ORDER + 1];
+    img[0] = tx;
+    for (int j = 0; j < k; ++j) {
+        int32_t f = faces[j];
+        if (f < 0 || f >= S->F) return 0;
+        v3 n = S->fn[f];
+        double dd = dot(n, img[j]) - S->fc[f];
+        img[j + 1] = sub(img[j], scl(2.0 * dd, n));
+    }
+    int ok = 1;
+    v3 X = rx;
+    for (int j = k - 1; j >= 0; --j) {
+        int32_t f = faces[j];
+        v3 n = S->fn[f];
+        v3 dir = sub(img[j + 1], X);
+        double den = dot(n, dir);
+        double s = (S->fc[f] - dot(n, X)) / den;
+        if (!(s > 0.0 && s < 1.0)) ok = 0;
+        pts[j] = add(X, scl(s, dir));
+        X = pts[j];
+    }
+    if (!ok) return 0;
+    for (int j = 0; j < k; ++j)
+        if (!inside_face(S, faces[j], pts[j])) return 0;
+    v3 A = tx;
+    int32_t fa = -1;
+    for (int j = 0; j < k; ++j) {
+        if (blocked(S, A, pts[j], fa, faces[j])) return 0;
+        A = pts[j];
+        fa = faces[j];
+    }
+    if (blocked(S, A, rx, fa, -1)) return 0;
+    return 1;
+}
+
+static double poly_length(v3 tx, const v3* p, int k, v3 rx)
+{
+    double L = 0.0;
+    v3 prev = tx;
+    for (int j = 0; j < k; ++j) { L = L + norm(sub(p[j], prev)); prev = p[j]; }
+    L = L + norm(sub(rx, prev));
+    return L;
+}
+
+int orc_exact_path(const double* tri_v, const int32_t* face_id, const int32_t* mat_id,
+                   int64_t n_tri, const double* eps_re, const double* eps_im,
+                   const double tx[3], const double rx[3], int32_t order,
+                   const int32_t* faces, double freq_hz, double ptx,
+                   double* points, double* length_m, double* power_dbm, int32_t* valid)
+{
+    if (order < 0 || order > ORC_MAX_ORDER) return -1;
+    scene_t S;
+    if (scene_init(&S, tri_v, face_id, mat_id, n_tri)) { scene_free(&S); return -1; }
+    v3 T = ld3(tx), R = ld3(rx), p[ORC_MAX_ORDER];
+    int ok = exact_solve(&S, T, R, order, faces, p);
+    if (valid) *valid = ok;
+    double L = poly_length(T, p, order, R);
+    if (length_m) *length_m = L;
+    double refl[ORC_MAX_ORDER];
+    v3 prev = T;
+    for (int j = 0; j < order; ++j) {
+        refl[j] = refl_at(&S, eps_re, eps_im, faces[j], sub(p[j], prev));
+        prev = p[j];
+        if (points) st3(points + 3 * j, p[j]);
+    }
+    if (power_dbm) *power_dbm = path_power(ptx, freq_hz, L, refl, order);
+    scene_free(&S);
+    return 0;
+}
+
+/* ======================================================================== */
+/* Whole method                                                              */
+/* ======================================================================== */
+typedef struct { orc_candidate* a; int64_t n, cap; } cvec;
+static int cpush(cvec* v, const orc_candidate* c)
+{
+    if (v->n == v->cap) {
+        int64_t nc = v->cap ? 2 * v->cap : 256;
+        orc_candidate* p = (orc_candidate*)realloc(v->a, sizeof(orc_candidate) * (size_t)nc);
+        if (!p) return -2;
+        v->a = p;
+        v->cap = nc;
+    }
+    v->a[v->n++] = *c;
+    return 0;
+}
+
+static int ray_order_cmp(const void* pa, const void* pb)
+{
+    const orc_candidate *a = (const orc_candidate*)pa, *b = (const orc_candidate*)pb;
+    if (a->ray != b->ray) return a->ray < b->ray ? -1 : 1;
+    if (a->order != b->order) return a->order < b->order ? -1 : 1;
+    if (a->rx != b->rx) return a->rx < b->rx ? -1 : 1;
+    return 0;
+}
+
+int orc_run(const double* tri_v, const int32_t* face_id, const int32_t* mat_id,
+            int64_t T, const double* eps_re, const double* eps_im, int32_t n_mat,
+            const double tx[3], const double* rx, int32_t n_rx, const orc_params* P,
+            orc_candidate** cand_out, int64_t* n_cand_out,
+            orc_candidate** uniq_out, int64_t* n_uniq_out,
+            orc_path** paths_out, int64_t* n_paths_out)
+{
+    if (!P || P->division_n < 1 || P->max_order < 0 || P->max_order > ORC_MAX_ORDER ||
+        P->iterations < 0 || (P->subrays != 6 && P->subrays != 7) || n_rx < 0 || T < 0 ||
+        !(P->freq_hz > 0.0))
+        return -1;
+    for (int64_t i = 0; i < T; ++i)
+        if (mat_id && (mat_id[i] < 0 || mat_id[i] >= n_mat)) return -1;
+    scene_t S;
+    if (scene_init(&S, tri_v, face_id, mat_id, T)) { scene_free(&S); return -1; }
+    const int32_t n = P->division_n, K = P->max_order;
+    const int64_t N = orc_num_rays(n);
+    const double thl = theta_launch(n);
+    const v3 TX = ld3(tx);
+    grid_t G;
+    grid_init(&G, n);
+#ifdef _OPENMP
+    if (P->n_threads > 0) omp_set_num_threads(P->n_threads);
+    int nth = omp_get_max_threads();
+#else
+    int nth = 1;
+#endif
+    /* 1. launch, trace and capture every ray */
+    cvec* tv = (cvec*)calloc((size_t)nth, sizeof(cvec));
+#pragma omp parallel
+    {
+#ifdef _OPENMP
+        int me = omp_get_thread_num();
+#else
+        int me = 0;
+#endif
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t r = 0; r < N; ++r) {
+            seg_t segs[ORC_MAX_ORDER + 1];
+            int ns = trace_ray(&S, TX, grid_dir(&G, r), K, segs);
+            orc_candidate c;
+            memset(&c, 0, sizeof(c));
+            c.ray = r;
+            for (int j = 0; j < ns; ++j) {
+                c.order = j;
+                for (int q = 0; q < ORC_MAX_ORDER; ++q)
+                    c.face[q] = q < j ? S.face[segs[q].tri] : -1;
+                for (int32_t x = 0; x < n_rx; ++x) {
+                    double tn;
+                    if (!capture_seg(&segs[j], ld3(rx + 3 * x), thl, &tn)) continue;
+                    c.rx = x;
+                    c.tan_err = tn;
+                    cpush(&tv[me], &c);
+                }
+            }
+        }
+    }
+    int64_t nc = 0;
+    for (int t = 0; t < nth; ++t) nc += tv[t].n;
+    orc_candidate* cand = (orc_candidate*)malloc(sizeof(orc_candidate) * (size_t)(nc > 0 ? nc : 1));
+    nc = 0;
+    for (int t = 0; t < nth; ++t) {
+        if (tv[t].n) memcpy(cand + nc, tv[t].a, sizeof(orc_candidate) * (size_t)tv[t].n);
+        nc += tv[t].n;
+        free(tv[t].a);
+    }
+    free(tv);
+    qsort(cand, (size_t)nc, sizeof(orc_candidate), ray_order_cmp);
+
+    /* 2. path test 1 */
+    orc_candidate* srt = (orc_candidate*)malloc(sizeof(orc_candidate) * (size_t)(nc > 0 ? nc : 1));
+    if (nc) memcpy(srt, cand, sizeof(orc_candidate) * (size_t)nc);
+    qsort(srt, (size_t)nc, sizeof(orc_candidate), cand_cmp);
+    int64_t nu = 0;
+    for (int64_t i = 0; i < nc; ++i)
+        if (i == 0 || key_cmp(&srt[i], &srt[nu - 1]) != 0) srt[nu++] = srt[i];
+
+    /* 3. precise algorithm, 4. path quantities and path test 2 */
+    double tan_tgt = 0.0;
+    if (P->target_err_deg > 0.0) tan_tgt = tan_cr((P->target_err_deg * PI_D) / 180.0);
+    orc_path* out = (orc_path*)calloc((size_t)(nu > 0 ? nu : 1), sizeof(orc_path));
+    int32_t* keep = (int32_t*)calloc((size_t)(nu > 0 ? nu : 1), sizeof(int32_t));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < nu; ++i) {
+        const orc_candidate* c = &srt[i];
+        v3 R = ld3(rx + 3 * c->rx);
+        refine_t rf;
+        refine_path(&S, TX, R, c->order, c->face, grid_dir(&G, c->ray), P->iterations,
+                    P->subrays, tan_tgt, thl, &rf, NULL);
+        orc_path* o = &out[i];
+        o->rx = c->rx;
+        o->order = c->order;
+        for (int q = 0; q < ORC_MAX_ORDER; ++q) o->face[q] = c->face[q];
+        o->launch_ray = c->ray;
+        o->iters_used = rf.iters;
+        o->flags = rf.flags;
+        o->init_tan_err = c->tan_err;
+        o->tan_err = rf.tan_err;
+        st3(o->axis, rf.axis);
+        const int k = c->order;
+        /* refined path: Tx -> hit points of the final axis ray -> Rx */
+        double L = poly_length(TX, rf.fw.p, k, R);
+        o->length_m = L;
+        o->delay_s = L / C0;
+        st3(o->aod, rf.axis);
+        v3 last = k > 0 ? rf.fw.p[k - 1] : TX;
+        st3(o->aoa, normalize(sub(last, R)));
+        double refl[ORC_MAX_ORDER];
+        for (int j = 0; j < k; ++j) refl[j] = refl_at(&S, eps_re, eps_im, c->face[j], rf.fw.din[j]);
+        o->power_dbm = path_power(P->tx_power_dbm, P->freq_hz, L, refl, k);
+        o->err_angle_deg = atan_cr(rf.tan_err) * (180.0 / PI_D);
+        /* exact path for the same faces */
+        v3 ep[ORC_MAX_ORDER];
+        int ok = exact_solve(&S, TX, R, k, c->face, ep);
+        double EL = poly_length(TX, ep, k, R);
+        o->exact_length_m = EL;
+        o->exact_delay_s = EL / C0;
+        v3 first = k > 0 ? ep[0] : R;
+        st3(o->exact_aod, normalize(sub(first, TX)));
+        v3 elast = k > 0 ? ep[k - 1] : TX;
+        st3(o->exact_aoa, normalize(sub(elast, R)));
+        v3 prev = TX;
+        for (int j = 0; j < k; ++j) {
+            refl[j] = refl_at(&S, eps_re, eps_im, c->face[j], sub(ep[j], prev));
+            prev = ep[j];
+        }
+        o->exact_power_dbm = path_power(P->tx_power_dbm, P->freq_hz, EL, refl, k);
+        if (!ok) o->flags |= 2u;
+        keep[i] = ok || P->keep_invalid;
+    }
+    int64_t np = 0;
+    for (int64_t i = 0; i < nu; ++i)
+        if (keep[i]) out[np++] = out[i];
+    free(keep);
+    grid_free(&G);
+    scene_free(&S);
+
+    if (cand_out) *cand_out = cand; else free(cand);
+    if (n_cand_out) *n_cand_out = nc;
+    if (uniq_out) *uniq_out = srt; else free(srt);
+    if (n_uniq_out) *n_uniq_out = nu;
+    if (paths_out) *paths_out = out; else free(out);
+    if (n_paths_out) *n_paths_out = np;
+    return 0;
+}
+
+void orc_free(void* p) { free(p); }
+
+int orc_refine_history(const double* tri_v, const int32_t* face_id, int64_t T,
+                       const double tx[3], const orc_params* P,
+                       const double* rx, const int32_t* order, const int32_t* faces,
+                       const double* axis0, int64_t m, double* hist)
+{
+    if (!P || P->division_n < 1 || (P->subrays != 6 && P->subrays != 7) || P->iterations < 0)
+        return -1;
+    scene_t S;
+    if (scene_init(&S, tri_v, face_id, NULL, T)) { scene_free(&S); return -1; }
+    const double thl = theta_launch(P->division_n);
+    const int32_t n_it = P->iterations;
+#ifdef _OPENMP
+    if (P->n_threads > 0) omp_set_num_threads(P->n_threads);
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < m; ++i) {
+        refine_t rf;
+        double* h = hist + i * (n_it + 1);
+        for (int32_t q = 0; q <= n_it; ++q) h[q] = NAN;
+        refine_path(&S, ld3(tx), ld3(rx + 3 * i), order[i], faces + ORC_MAX_ORDER * i,
+                    ld3(axis0 + 3 * i), n_it, P->subrays, 0.0, thl, &rf, h);
+    }
+    scene_free(&S);
+    return 0;
+}
