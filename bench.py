@@ -1,0 +1,178 @@
+"""Benchmark of the SBR hot path on one MI355X.
+
+One step = one sbr_trace call over the whole path: equiangular launch
+(recomputed every step), BVH traversal with specular bounces and cone
+reception, path test 1, the precise algorithm, image solve / path test 2 /
+power, and the canonical emit.  The scene (BVH) is uploaded once before the
+timed region; Tx/Rx positions (64 x 24 B) and the path list travel with
+every call.
+
+Workload: the Manhattan grid (8 x 8 box buildings on a 40 m pitch plus
+ground, 770 triangles), Tx at 25 m, 64 Rx at 1.5 m on street centrelines,
+n = 200 (400,002 rays), up to 6 reflections, 5 iterations of 7 sub-rays,
+28 GHz -- seeded synthetic stand-in for the paper's scenes.
+
+Prints ONE JSON line (metric, value = launched rays per second of whole-step
+time, refined paths per second, roofline of the trace kernel, CPU oracle
+baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "rays/s + refined paths/s at ≤0.01° AOA/AOD error; batched vs plain, 1 GPU"
+HBM_PEAK_GBS = 8000.0
+NODE_BYTES = 64     # BVH2 node: two FP32 child boxes + child references
+TRI_BYTES = 80      # FP64 triangle record (v0, e1, e2, face, index)
+RAY_BYTES = 24      # FP64 launch direction read per ray
+EVENT_BYTES = 56    # reception event record written
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def angle_deg(a, b):
+    c = np.cross(a, b)
+    return np.degrees(np.arctan2(np.linalg.norm(c, axis=-1), np.sum(a * b, axis=-1)))
+
+
+def accurate_mask(p, tol_deg=0.01):
+    return (angle_deg(p["aod"], p["exact_aod"]) <= tol_deg) & \
+        (angle_deg(p["aoa"], p["exact_aoa"]) <= tol_deg) & ((p["flags"] & 2) == 0)
+
+
+def cpu_baseline(cfg, budget_s=10.0, max_runs=20):
+    """The FP64 CPU oracle, as it stands, on the same workload (whole runs
+    repeated until about budget_s of CPU wall time)."""
+    from oracle import oracle as orc
+    orc.build()
+    n_rays = 10 * cfg["params"]["division_n"] ** 2 + 2
+    runs, t0 = 0, time.perf_counter()
+    paths = None
+    while runs < max_runs and (runs == 0 or time.perf_counter() - t0 < budget_s):
+        paths = orc.run(cfg["scene"], cfg["tx"], cfg["rx"], **cfg["params"])["paths"]
+        runs += 1
+    dt = time.perf_counter() - t0
+    try:
+        cores = int(os.environ["OMP_NUM_THREADS"])
+    except (KeyError, ValueError):
+        cores = len(os.sched_getaffinity(0))
+    return {
+        "value": n_rays * runs / dt,
+        "unit": "rays/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": "%d full run(s) of the same workload (%d rays, %d Rx), %.1f s" % (
+            runs, n_rays, len(cfg["rx"]), dt),
+        "refined_paths_per_s": float(accurate_mask(paths).sum()) * runs / dt,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2208_10009_amd import sbr, scenes
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    cfg = scenes.manhattan_config(args.seed)
+    prm = cfg["params"]
+    ctx = sbr.Context(0)
+    sc = ctx.scene(cfg["scene"])
+    n_rays = 10 * prm["division_n"] ** 2 + 2
+
+    counts = sc.trace_counters(cfg["tx"], cfg["rx"], **prm)
+    log("counts", counts)
+    for _ in range(args.warmup):
+        sc.trace(cfg["tx"], cfg["rx"], fresh_grid=True, **prm)
+
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        paths, st = sc.trace(cfg["tx"], cfg["rx"], fresh_grid=True, **prm)
+        stats.append(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = 1e3 * wall / args.steps
+
+    good = int(accurate_mask(paths).sum())
+    stage = {k: float(np.mean([s[k] for s in stats]))
+             for k in ("ms_launch", "ms_trace", "ms_dedup", "ms_refine", "ms_solve", "ms_emit",
+                       "ms_total")}
+    log("stages (mean ms):", json.dumps(stage))
+    ms_paths_stage = stage["ms_dedup"] + stage["ms_refine"] + stage["ms_solve"] + stage["ms_emit"]
+
+    alg_bytes = (counts["nodes"] * NODE_BYTES + counts["tris"] * TRI_BYTES + n_rays * RAY_BYTES
+                 + counts["events"] * EVENT_BYTES)
+    achieved = alg_bytes / (stage["ms_trace"] * 1e-3) / 1e9
+    roofline = {
+        "kernel": "k_trace",
+        "bound": "hbm",
+        "achieved": round(achieved, 2),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 5),
+        "traffic": None,
+        "algorithmic_bytes_per_launch": int(alg_bytes),
+        "kernel_ms": round(stage["ms_trace"], 5),
+    }
+    out = {
+        "metric": METRIC,
+        "value": n_rays * args.steps / wall,
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "manhattan_8x8_770tri_n200_k6_i5_s7_rx64",
+            "triangles": len(cfg["scene"]["tri"]), "rays": n_rays, "rx": len(cfg["rx"]),
+            "max_order": prm["max_order"], "iterations": prm["iterations"],
+            "subrays": prm["subrays"], "freq_hz": prm["freq_hz"], "mode": "plain",
+        },
+        "refined_paths_per_s": good / (ms_step * 1e-3),
+        "refined_paths_per_s_stage": good / (ms_paths_stage * 1e-3) if ms_paths_stage > 0 else None,
+        "paths": int(len(paths)),
+        "paths_within_0.01deg": good,
+        "trace_rays_per_s": n_rays / (stage["ms_trace"] * 1e-3),
+        "stage_ms": {k: round(v, 5) for k, v in stage.items()},
+        "counts": counts,
+        "roofline": roofline,
+    }
+    sc.close()
+    ctx.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

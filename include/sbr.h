@@ -1,0 +1,190 @@
+/*
+ * sbr.h -- C ABI of the MI355X (gfx950) shooting-and-bouncing-ray tracer with
+ * equiangular launch and the iterative precise algorithm of Zhou et al.,
+ * "An Improved Equiangular Division Algorithm for SBR based Ray Tracing
+ * Channel Modeling" (arXiv 2208.10009).
+ *
+ * The problem (Sec. I and Sec. IV): given a scene of planar faces with
+ * materials, one transmitter (Tx) and a set of receivers (Rx), return the
+ * propagation paths with their delay, angle of departure (AOD), angle of
+ * arrival (AOA) and power.  Every stage of the computation runs in HIP
+ * kernels on one GPU; the host only validates arguments, builds the BVH and
+ * moves inputs and results.
+ *
+ * Conventions shared by every entry point:
+ *  - All geometry is FP64, metres, right-handed; inputs are caller-owned host
+ *    arrays, read during the call and never retained.
+ *  - Outputs are caller-allocated host arrays.  Calls that return a list take
+ *    a capacity; when it is too small they return SBR_E_CAPACITY, write the
+ *    required count to *n_out and nothing else.
+ *  - Every call is synchronous: results are complete on return.
+ *  - On error nothing is left half-built; sbr_last_error() gives a message.
+ *  - A context is bound to one device and one HIP stream and must be used by
+ *    one thread at a time.  Scenes belong to the context that created them.
+ */
+#ifndef SBR_H
+#define SBR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SBR_MAX_ORDER 8 /* highest reflection order a path may have */
+
+typedef int32_t sbr_status;
+#define SBR_OK 0
+#define SBR_E_INVALID_ARG (-1) /* a pointer, size or parameter is out of range   */
+#define SBR_E_NO_SCENE (-2)    /* scene handle is NULL or destroyed              */
+#define SBR_E_NO_BVH (-3)      /* sbr_bvh_build was not called on the scene      */
+#define SBR_E_CAPACITY (-4)    /* output too small; *n_out = required count      */
+#define SBR_E_OOM (-5)         /* device or host allocation failed               */
+#define SBR_E_DEVICE (-6)      /* a HIP call failed (message has the HIP error)  */
+#define SBR_E_INTERNAL (-7)    /* internal consistency check failed              */
+
+typedef struct sbr_context sbr_context;
+typedef struct sbr_scene sbr_scene;
+
+/* Relative permittivity er = re + j im of a material (e^{jwt} convention, so
+ * lossy materials have im < 0, e.g. 15 - 1j). */
+typedef struct {
+    double re, im;
+} sbr_complex;
+
+/* Trace parameters (Sec. II.B and Sec. III). */
+typedef struct {
+    int32_t max_order;     /* K: specular reflections per ray, 0..SBR_MAX_ORDER        */
+    int32_t division_n;    /* n >= 1: icosahedron edges split into n equal angles,
+                              10 n^2 + 2 launch rays (Sec. III.B, with eq. (4))       */
+    int32_t iterations;    /* I >= 0: precise-algorithm iterations (Sec. III.B);
+                              0 gives the plain SBR result ("traditional SBR")        */
+    int32_t subrays;       /* 6 (the paper's six sub-cones) or 7 (six plus the axis)  */
+    double target_err_deg; /* > 0: a path stops iterating once its error angle is
+                              below target * L_last / L_total; <= 0: exactly I
+                              iterations                                             */
+    double freq_hz;        /* carrier frequency, > 0                                 */
+    double tx_power_dbm;   /* transmit power                                          */
+    uint32_t flags;        /* SBR_FLAG_*                                              */
+    int32_t reserved;      /* must be 0                                               */
+} sbr_trace_params;
+
+#define SBR_FLAG_KEEP_INVALID 1u /* keep paths that fail path test 2 (flag INVALID) */
+#define SBR_FLAG_FRESH_GRID 2u   /* recompute the launch directions even when cached */
+
+/* Path flags (sbr_path.flags). */
+#define SBR_PATH_STALLED 1u    /* an iteration found no sub-ray with the same faces  */
+#define SBR_PATH_INVALID 2u    /* failed path test 2 (validity, Sec. III.A)          */
+#define SBR_PATH_TARGET_MET 4u /* stopped early on target_err_deg                   */
+
+/* One path (Sec. III and Sec. IV).  "Refined" fields come from the precise
+ * algorithm's final ray; "exact_" fields from the image-method solve of the
+ * same face sequence, which also decides path test 2.  Angles are unit
+ * vectors: aod points from Tx along the departing ray, aoa points from Rx
+ * back toward the last interaction (or Tx). */
+typedef struct {
+    int32_t rx;                  /* receiver index                                   */
+    int32_t order;               /* number of reflections k                          */
+    int32_t face[SBR_MAX_ORDER]; /* face ids hit in order; -1 beyond order           */
+    int64_t launch_ray;          /* launch ray that won path test 1                  */
+    int32_t iters_used;          /* iterations that improved the path                */
+    uint32_t flags;              /* SBR_PATH_*                                       */
+    double tan_err;              /* tan of the error angle of the reported ray       */
+    double axis[3];              /* reported departure direction                     */
+    double delay_s, aod[3], aoa[3], power_dbm, err_angle_deg, length_m;
+    double exact_delay_s, exact_aod[3], exact_aoa[3], exact_power_dbm, exact_length_m;
+    double init_tan_err;         /* tan error angle of the path-test-1 winner        */
+} sbr_path;
+
+/* A reception event before path test 1 (Sec. III.A, eq. (3)). */
+typedef struct {
+    int32_t rx, order, face[SBR_MAX_ORDER];
+    int64_t ray;
+    double tan_err;
+} sbr_candidate;
+
+/* Per-call timings (ms, measured with HIP events on the context stream) and
+ * counts. */
+typedef struct {
+    int64_t n_rays, n_candidates, n_unique, n_paths;
+    double ms_launch, ms_trace, ms_dedup, ms_refine, ms_solve, ms_emit, ms_total;
+    int64_t reserved[4];
+} sbr_trace_stats;
+
+/* BVH build options; NULL means defaults (leaf size 4, 16 SAH bins). */
+typedef struct {
+    int32_t max_leaf_size; /* 1..16 */
+    int32_t sah_bins;      /* 4..64 */
+} sbr_bvh_params;
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t the
+ * caller owns (for example torch's current stream) or NULL for the default
+ * stream.  Errors: SBR_E_INVALID_ARG (bad device / out == NULL), SBR_E_DEVICE. */
+sbr_status sbr_context_create(int32_t device, void* hip_stream, sbr_context** out);
+/* Release the context and every device buffer it holds.  Scenes created on it
+ * must be destroyed first (SBR_E_INVALID_ARG otherwise). */
+sbr_status sbr_context_destroy(sbr_context* ctx);
+
+/* Scene (Sec. IV: faces with material information).  xyz [n_vertices][3];
+ * tri [n_triangles][3] vertex indices; face_id [n_triangles] >= 0 names the
+ * planar polygon ("face") a triangle belongs to -- a face's plane and
+ * material are those of its lowest-index triangle and every triangle of a face
+ * must lie in that plane (relative 1e-9); mat_id [n_triangles] indexes
+ * eps_r [n_materials].  Degenerate triangles are accepted and never hit.
+ * Errors: SBR_E_INVALID_ARG (index out of range, non-finite vertex, face not
+ * planar), SBR_E_OOM, SBR_E_DEVICE. */
+sbr_status sbr_scene_upload(sbr_context* ctx, const double* xyz, int64_t n_vertices,
+                            const int32_t* tri, const int32_t* face_id, const int32_t* mat_id,
+                            int64_t n_triangles, const sbr_complex* eps_r, int32_t n_materials,
+                            sbr_scene** out);
+/* Build the acceleration structure (binned SAH BVH with conservative FP32
+ * boxes; not part of the paper's method, which leaves acceleration open). */
+sbr_status sbr_bvh_build(sbr_scene* scene, const sbr_bvh_params* params);
+sbr_status sbr_scene_destroy(sbr_scene* scene);
+
+/* The whole method (Sec. II-III): equiangular launch from tx, SBR tracing with
+ * specular reflection up to max_order, cone reception at every rx (eq. (3)),
+ * path test 1 (one path per receiver and face sequence, the smaller error
+ * angle wins), the precise algorithm, path test 2 and the path quantities.
+ * rx [n_rx][3] (n_rx may be 0).  Paths are written to out[0..*n_out) sorted by
+ * (rx, order, face sequence).  stats may be NULL. */
+sbr_status sbr_trace(sbr_scene* scene, const double tx[3], const double* rx, int32_t n_rx,
+                     const sbr_trace_params* params, sbr_path* out, int64_t capacity,
+                     int64_t* n_out, sbr_trace_stats* stats);
+
+/* The reception events before path test 1 (same launch, trace and reception
+ * as sbr_trace), sorted by (rx, order, face sequence, tan_err, ray). */
+sbr_status sbr_candidates(sbr_scene* scene, const double tx[3], const double* rx, int32_t n_rx,
+                          const sbr_trace_params* params, sbr_candidate* out, int64_t capacity,
+                          int64_t* n_out);
+
+/* Launch directions of Sec. II.B for division n (10 n^2 + 2 unit vectors,
+ * FP64), copied to out [count][3] for ray indices first..first+count-1. */
+sbr_status sbr_launch_grid(sbr_context* ctx, int32_t n, int64_t first, int64_t count,
+                           double* out);
+
+/* Per-ray trace of launch rays first..first+count-1 (Sec. III.A):
+ * out_tri [count][max_order+1] is the triangle (input index) closing each
+ * segment, -1 when the segment leaves the scene or was not reached;
+ * out_t [count][max_order+1] the segment's ray parameter (+inf: none).
+ * Either output may be NULL. */
+sbr_status sbr_trace_rays(sbr_scene* scene, const double tx[3], int32_t n, int32_t max_order,
+                          int64_t first, int64_t count, int32_t* out_tri, double* out_t);
+
+/* Work counts of the trace stage of sbr_trace with the same arguments, from
+ * an instrumented copy of the trace kernel: counts[0] segments traced
+ * (ray-bounces), counts[1] BVH nodes visited (64 B each), counts[2]
+ * ray-triangle tests (80 B triangle records), counts[3] reception events.
+ * They define the algorithmic bytes of the trace kernel for its roofline. */
+sbr_status sbr_trace_counters(sbr_scene* scene, const double tx[3], const double* rx,
+                              int32_t n_rx, const sbr_trace_params* params, int64_t counts[4]);
+
+const char* sbr_status_string(sbr_status status);
+/* Message of the last failing call on ctx (empty if none); valid until the
+ * next call on ctx.  ctx may be NULL for failures of sbr_context_create. */
+const char* sbr_last_error(const sbr_context* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SBR_H */

@@ -1,0 +1,747 @@
+// api.hip -- C ABI (include/sbr.h): contexts, scenes, BVH upload and the
+// orchestration of the trace stages on one HIP stream.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "geom.h"
+#include "internal.h"
+
+using namespace sbr;
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    template <class T>
+    T* as() const { return (T*)p; }
+};
+
+hipError_t ensure(DevBuf& b, size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    if (b.cap >= bytes) return hipSuccess;
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e == hipSuccess) b.cap = bytes;
+    return e;
+}
+
+void release(DevBuf& b)
+{
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+
+// Device-side counters read back between stages.
+struct Counters {
+    unsigned long long cand;
+    int32_t err;
+    int32_t n_unique;
+    int32_t n_paths;
+    int32_t pad;
+};
+
+}  // namespace
+
+struct sbr_context {
+    int32_t device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    int32_t n_scenes = 0;
+    std::map<int32_t, DevBuf> grids;  // division n -> [3][N] FP64 directions
+    DevBuf grid_scratch, rx, cand, idx, flags, offs, scan, uniq, refine, paths, keep, outp,
+        counters, rays_tri, rays_t, tally;
+    Counters* host_ctr = nullptr;  // pinned
+    hipEvent_t ev[8] = {};
+};
+
+struct sbr_scene {
+    sbr_context* ctx = nullptr;
+    int64_t T = 0;
+    int32_t F = 0, M = 0;
+    std::vector<double> tri_v;  // [T][9]
+    std::vector<int32_t> face, mat;
+    std::vector<double> eps;     // [M][2]
+    std::vector<double> fplane;  // [F][4]
+    std::vector<int32_t> fmat;   // [F]
+    double t_eps = 0.0, R_s = 0.0;
+    bool has_bvh = false;
+    int32_t bvh_depth = 0;
+    DevBuf nodes, tris, d_fplane, d_fmat, fstart, ftris, d_eps;
+};
+
+namespace {
+
+sbr_status fail(sbr_context* c, sbr_status st, const char* fmt, ...)
+    __attribute__((format(printf, 3, 4)));
+sbr_status fail(sbr_context* c, sbr_status st, const char* fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return st;
+}
+
+thread_local std::string g_create_err;
+
+#define HIPCHK(ctx, expr)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail((ctx), e_ == hipErrorOutOfMemory ? SBR_E_OOM : SBR_E_DEVICE,        \
+                        "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+    } while (0)
+
+bool finite3(const double* p) { return isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]); }
+
+sbr_status get_grid(sbr_context* c, int32_t n, GridDev* g, bool* built, bool fresh = false)
+{
+    int64_t N = 10 * (int64_t)n * n + 2;
+    auto it = c->grids.find(n);
+    *built = false;
+    if (it != c->grids.end() && fresh) {
+        HIPCHK(c, ensure(c->grid_scratch, grid_scratch_bytes(n)));
+        GridDev gd{it->second.as<double>(), N, n};
+        HIPCHK(c, launch_grid(gd, c->stream, c->grid_scratch.p));
+        *built = true;
+    }
+    if (it == c->grids.end()) {
+        DevBuf b;
+        HIPCHK(c, ensure(b, sizeof(double) * 3 * (size_t)N));
+        HIPCHK(c, ensure(c->grid_scratch, grid_scratch_bytes(n)));
+        GridDev gd{b.as<double>(), N, n};
+        hipError_t e = launch_grid(gd, c->stream, c->grid_scratch.p);
+        if (e != hipSuccess) {
+            release(b);
+            return fail(c, SBR_E_DEVICE, "launch grid: %s", hipGetErrorString(e));
+        }
+        it = c->grids.emplace(n, b).first;
+        *built = true;
+    }
+    *g = GridDev{it->second.as<double>(), N, n};
+    return SBR_OK;
+}
+
+SceneDev scene_dev(const sbr_scene* s)
+{
+    SceneDev S;
+    S.nodes = s->nodes.as<const BvhNode>();
+    S.tris = s->tris.as<const TriD>();
+    S.fplane = s->d_fplane.as<const double>();
+    S.fmat = s->d_fmat.as<const int32_t>();
+    S.fstart = s->fstart.as<const int32_t>();
+    S.ftris = s->ftris.as<const int32_t>();
+    S.eps = s->d_eps.as<const double>();
+    S.n_tri = (int32_t)s->T;
+    S.n_face = s->F;
+    S.t_eps = s->t_eps;
+    return S;
+}
+
+// Box widening that makes FP32 traversal conservative for rays starting at
+// tx or inside the scene: 2^-20 max(|tx|_inf, scene max |coordinate|).
+float traversal_delta(const sbr_scene* s, const double* tx)
+{
+    double R = s->R_s;
+    for (int i = 0; i < 3; ++i) R = std::max(R, fabs(tx[i]));
+    double d = ldexp(R, -20);
+    float f = (float)d;
+    if ((double)f < d) f = nextafterf(f, INFINITY);
+    return std::max(f, 1e-30f);
+}
+
+// theta_launch = theta_0 / (sqrt(3) n), eq. (4).
+double theta_launch(int32_t n) { return kTheta0 / (sqrt(3.0) * (double)n); }
+
+sbr_status check_params(sbr_context* c, const sbr_trace_params* p)
+{
+    if (!p) return fail(c, SBR_E_INVALID_ARG, "params is NULL");
+    if (p->max_order < 0 || p->max_order > SBR_MAX_ORDER)
+        return fail(c, SBR_E_INVALID_ARG, "max_order %d outside 0..%d", p->max_order, SBR_MAX_ORDER);
+    if (p->division_n < 1 || p->division_n > 10000)
+        return fail(c, SBR_E_INVALID_ARG, "division_n %d outside 1..10000", p->division_n);
+    if (p->iterations < 0 || p->iterations > 200)
+        return fail(c, SBR_E_INVALID_ARG, "iterations %d outside 0..200", p->iterations);
+    if (p->subrays != 6 && p->subrays != 7)
+        return fail(c, SBR_E_INVALID_ARG, "subrays must be 6 or 7 (got %d)", p->subrays);
+    if (!(p->freq_hz > 0.0) || !isfinite(p->freq_hz))
+        return fail(c, SBR_E_INVALID_ARG, "freq_hz must be finite and > 0");
+    if (!isfinite(p->tx_power_dbm) || !isfinite(p->target_err_deg) || p->target_err_deg >= 45.0)
+        return fail(c, SBR_E_INVALID_ARG, "tx_power_dbm / target_err_deg out of range");
+    if (p->reserved != 0 || (p->flags & ~(SBR_FLAG_KEEP_INVALID | SBR_FLAG_FRESH_GRID)))
+        return fail(c, SBR_E_INVALID_ARG, "unknown flags or reserved != 0");
+    return SBR_OK;
+}
+
+sbr_status check_scene(sbr_scene* s)
+{
+    if (!s || !s->ctx) return SBR_E_NO_SCENE;
+    if (!s->has_bvh) return fail(s->ctx, SBR_E_NO_BVH, "sbr_bvh_build has not been called");
+    return SBR_OK;
+}
+
+// Launch, trace and reception, then the sort of the events and path test 1.
+// On return (SBR_OK) the context holds: cand (n_cand events), idx (sorted
+// permutation), flags/offs and uniq (n_uniq unique paths).
+struct Front {
+    int64_t n_cand = 0, n_uniq = 0, N = 0;
+    GridDev g;
+    TraceArgs ta;
+    float ms_launch = 0, ms_trace = 0, ms_dedup = 0;
+};
+
+sbr_status run_front(sbr_scene* s, const double* tx, const double* rx, int32_t n_rx,
+                     const sbr_trace_params* p, bool need_unique, Front* fr,
+                     unsigned long long* tallies = nullptr)
+{
+    sbr_context* c = s->ctx;
+    hipStream_t st = c->stream;
+    HIPCHK(c, hipEventRecord(c->ev[0], st));
+    bool built;
+    sbr_status r = get_grid(c, p->division_n, &fr->g, &built, (p->flags & SBR_FLAG_FRESH_GRID) != 0);
+    if (r) return r;
+    HIPCHK(c, hipEventRecord(c->ev[1], st));
+    fr->N = fr->g.N;
+
+    HIPCHK(c, ensure(c->rx, sizeof(double) * 3 * (size_t)std::max(n_rx, 1)));
+    if (n_rx > 0)
+        HIPCHK(c, hipMemcpyAsync(c->rx.p, rx, sizeof(double) * 3 * (size_t)n_rx,
+                                 hipMemcpyHostToDevice, st));
+    HIPCHK(c, ensure(c->counters, sizeof(Counters)));
+    TraceArgs& A = fr->ta;
+    for (int i = 0; i < 3; ++i) A.tx[i] = tx[i];
+    A.rx = c->rx.as<const double>();
+    A.n_rx = n_rx;
+    A.K = p->max_order;
+    A.thl = theta_launch(p->division_n);
+    A.delta = traversal_delta(s, tx);
+    SceneDev S = scene_dev(s);
+
+    int64_t cap = std::max<int64_t>(65536, (int64_t)(c->cand.cap / sizeof(sbr_candidate)));
+    Counters* hc = c->host_ctr;
+    for (;;) {
+        HIPCHK(c, ensure(c->cand, sizeof(sbr_candidate) * (size_t)cap));
+        HIPCHK(c, hipMemsetAsync(c->counters.p, 0, sizeof(Counters), st));
+        if (tallies) HIPCHK(c, hipMemsetAsync(tallies, 0, 4 * sizeof(unsigned long long), st));
+        HIPCHK(c, hipEventRecord(c->ev[7], st));
+        HIPCHK(c, launch_trace(S, fr->g, A, 0, fr->N, c->cand.as<sbr_candidate>(), cap,
+                               &c->counters.as<Counters>()->cand, nullptr, nullptr,
+                               &c->counters.as<Counters>()->err, st, tallies));
+        HIPCHK(c, hipEventRecord(c->ev[2], st));
+        HIPCHK(c, hipMemcpyAsync(hc, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        if (hc->err) return fail(c, SBR_E_INTERNAL, "traversal stack overflow");
+        if ((int64_t)hc->cand <= cap) break;
+        if (hc->cand >= (1ull << 31))
+            return fail(c, SBR_E_CAPACITY, "%llu reception events exceed 2^31", hc->cand);
+        cap = (int64_t)(hc->cand + hc->cand / 4 + 1024);
+    }
+    fr->n_cand = (int64_t)hc->cand;
+    HIPCHK(c, hipEventElapsedTime(&fr->ms_launch, c->ev[0], c->ev[1]));
+    if (!built) fr->ms_launch = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&fr->ms_trace, c->ev[7], c->ev[2]));
+
+    // sort + path test 1
+    int64_t C = fr->n_cand;
+    int64_t P2 = pow2_at_least(C);
+    HIPCHK(c, ensure(c->idx, sizeof(uint32_t) * (size_t)P2));
+    HIPCHK(c, launch_sort_candidates(c->cand.as<sbr_candidate>(), C, c->idx.as<uint32_t>(), st));
+    if (need_unique) {
+        HIPCHK(c, ensure(c->flags, sizeof(int32_t) * (size_t)std::max<int64_t>(C, 1)));
+        HIPCHK(c, ensure(c->offs, sizeof(int32_t) * (size_t)std::max<int64_t>(C, 1)));
+        HIPCHK(c, ensure(c->scan, scan_scratch_bytes(C)));
+        HIPCHK(c, launch_heads(c->cand.as<sbr_candidate>(), c->idx.as<uint32_t>(), C,
+                               c->flags.as<int32_t>(), st));
+        HIPCHK(c, launch_scan(c->flags.as<int32_t>(), c->offs.as<int32_t>(), C,
+                              &c->counters.as<Counters>()->n_unique, c->scan.p, st));
+        HIPCHK(c, hipMemcpyAsync(hc, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        fr->n_uniq = hc->n_unique;
+        HIPCHK(c, ensure(c->uniq, sizeof(sbr_candidate) * (size_t)std::max<int64_t>(fr->n_uniq, 1)));
+        HIPCHK(c, launch_gather_unique(c->cand.as<sbr_candidate>(), c->idx.as<uint32_t>(),
+                                       c->flags.as<int32_t>(), c->offs.as<int32_t>(), C,
+                                       c->uniq.as<sbr_candidate>(), st));
+    }
+    HIPCHK(c, hipEventRecord(c->ev[3], st));
+    HIPCHK(c, hipEventSynchronize(c->ev[3]));
+    HIPCHK(c, hipEventElapsedTime(&fr->ms_dedup, c->ev[2], c->ev[3]));
+    return SBR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sbr_status_string(sbr_status s)
+{
+    switch (s) {
+        case SBR_OK: return "ok";
+        case SBR_E_INVALID_ARG: return "invalid argument";
+        case SBR_E_NO_SCENE: return "no scene";
+        case SBR_E_NO_BVH: return "no BVH";
+        case SBR_E_CAPACITY: return "output capacity too small";
+        case SBR_E_OOM: return "out of memory";
+        case SBR_E_DEVICE: return "HIP device error";
+        case SBR_E_INTERNAL: return "internal error";
+        default: return "unknown status";
+    }
+}
+
+const char* sbr_last_error(const sbr_context* ctx)
+{
+    return ctx ? ctx->err.c_str() : g_create_err.c_str();
+}
+
+sbr_status sbr_context_create(int32_t device, void* hip_stream, sbr_context** out)
+{
+    g_create_err.clear();
+    if (!out) {
+        g_create_err = "out is NULL";
+        return SBR_E_INVALID_ARG;
+    }
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0) {
+        g_create_err = std::string("no HIP device: ") + hipGetErrorString(e);
+        return SBR_E_DEVICE;
+    }
+    if (device < 0 || device >= count) {
+        g_create_err = "device index out of range";
+        return SBR_E_INVALID_ARG;
+    }
+    e = hipSetDevice(device);
+    if (e != hipSuccess) {
+        g_create_err = std::string("hipSetDevice: ") + hipGetErrorString(e);
+        return SBR_E_DEVICE;
+    }
+    sbr_context* c = new sbr_context();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    for (auto& ev : c->ev) {
+        e = hipEventCreate(&ev);
+        if (e != hipSuccess) break;
+    }
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->host_ctr, sizeof(Counters), 0);
+    if (e != hipSuccess) {
+        g_create_err = std::string("context setup: ") + hipGetErrorString(e);
+        for (auto& ev : c->ev)
+            if (ev) (void)hipEventDestroy(ev);
+        delete c;
+        return SBR_E_DEVICE;
+    }
+    *out = c;
+    return SBR_OK;
+}
+
+sbr_status sbr_context_destroy(sbr_context* c)
+{
+    if (!c) return SBR_E_INVALID_ARG;
+    if (c->n_scenes > 0) return fail(c, SBR_E_INVALID_ARG, "%d scene(s) still alive", c->n_scenes);
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& kv : c->grids) release(kv.second);
+    DevBuf* bufs[] = {&c->grid_scratch, &c->rx,    &c->cand,  &c->idx,  &c->flags,
+                      &c->offs,         &c->scan,  &c->uniq,  &c->refine, &c->paths,
+                      &c->keep,         &c->outp,  &c->counters, &c->rays_tri, &c->rays_t, &c->tally};
+    for (DevBuf* b : bufs) release(*b);
+    for (auto& ev : c->ev)
+        if (ev) (void)hipEventDestroy(ev);
+    if (c->host_ctr) (void)hipHostFree(c->host_ctr);
+    delete c;
+    return SBR_OK;
+}
+
+sbr_status sbr_scene_upload(sbr_context* c, const double* xyz, int64_t nv, const int32_t* tri,
+                            const int32_t* face_id, const int32_t* mat_id, int64_t T,
+                            const sbr_complex* eps_r, int32_t M, sbr_scene** out)
+{
+    if (!c) return SBR_E_INVALID_ARG;
+    c->err.clear();
+    if (!out) return fail(c, SBR_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (nv < 0 || T < 0 || T >= (1ll << 31) || M < 0)
+        return fail(c, SBR_E_INVALID_ARG, "negative or too large sizes");
+    if (T > 0 && (!xyz || !tri || !face_id || !mat_id || !eps_r || M < 1))
+        return fail(c, SBR_E_INVALID_ARG, "NULL scene array");
+    for (int64_t i = 0; i < nv; ++i)
+        if (!finite3(xyz + 3 * i)) return fail(c, SBR_E_INVALID_ARG, "vertex %lld not finite", (long long)i);
+    for (int32_t m = 0; m < M; ++m)
+        if (!isfinite(eps_r[m].re) || !isfinite(eps_r[m].im))
+            return fail(c, SBR_E_INVALID_ARG, "eps_r[%d] not finite", m);
+    sbr_scene* s = new sbr_scene();
+    s->ctx = c;
+    s->T = T;
+    s->M = M;
+    s->tri_v.resize((size_t)T * 9);
+    s->face.assign(face_id, face_id + T);
+    s->mat.assign(mat_id, mat_id + T);
+    s->eps.resize((size_t)std::max(M, 1) * 2);
+    for (int32_t m = 0; m < M; ++m) {
+        s->eps[2 * m] = eps_r[m].re;
+        s->eps[2 * m + 1] = eps_r[m].im;
+    }
+    int32_t F = 0;
+    d3 lo = mk(INFINITY, INFINITY, INFINITY), hi = mk(-INFINITY, -INFINITY, -INFINITY);
+    double R = 0.0;
+    for (int64_t t = 0; t < T; ++t) {
+        for (int v = 0; v < 3; ++v) {
+            int32_t vi = tri[3 * t + v];
+            if (vi < 0 || vi >= nv) {
+                delete s;
+                return fail(c, SBR_E_INVALID_ARG, "triangle %lld: vertex index out of range", (long long)t);
+            }
+            const double* P = xyz + 3 * (size_t)vi;
+            for (int q = 0; q < 3; ++q) s->tri_v[9 * t + 3 * v + q] = P[q];
+            lo.x = fmin(lo.x, P[0]); lo.y = fmin(lo.y, P[1]); lo.z = fmin(lo.z, P[2]);
+            hi.x = fmax(hi.x, P[0]); hi.y = fmax(hi.y, P[1]); hi.z = fmax(hi.z, P[2]);
+            R = std::max(R, std::max(fabs(P[0]), std::max(fabs(P[1]), fabs(P[2]))));
+        }
+        if (face_id[t] < 0 || mat_id[t] < 0 || mat_id[t] >= M) {
+            delete s;
+            return fail(c, SBR_E_INVALID_ARG, "triangle %lld: face or material id out of range", (long long)t);
+        }
+        F = std::max(F, face_id[t] + 1);
+    }
+    s->F = F;
+    s->R_s = R;
+    if (T > 0) s->t_eps = 1e-9 * norm(sub(hi, lo));
+    double diag = T > 0 ? norm(sub(hi, lo)) : 0.0;
+    // Face planes: the lowest-index triangle of each face, n = normalize(e1 x e2).
+    s->fplane.assign((size_t)std::max(F, 1) * 4, 0.0);
+    s->fmat.assign((size_t)std::max(F, 1), 0);
+    std::vector<char> seen((size_t)std::max(F, 1), 0);
+    for (int64_t t = 0; t < T; ++t) {
+        int32_t f = face_id[t];
+        if (seen[f]) continue;
+        seen[f] = 1;
+        const double* V = &s->tri_v[9 * t];
+        d3 v0 = ld3(V), e1 = sub(ld3(V + 3), v0), e2 = sub(ld3(V + 6), v0);
+        d3 cr = cross(e1, e2);
+        if (!(norm(cr) > 0.0)) {
+            delete s;
+            return fail(c, SBR_E_INVALID_ARG, "face %d: its first triangle is degenerate", f);
+        }
+        d3 n = normalize(cr);
+        s->fplane[4 * f + 0] = n.x;
+        s->fplane[4 * f + 1] = n.y;
+        s->fplane[4 * f + 2] = n.z;
+        s->fplane[4 * f + 3] = dot(n, v0);
+        s->fmat[f] = mat_id[t];
+    }
+    for (int64_t t = 0; t < T; ++t) {
+        int32_t f = face_id[t];
+        d3 n = ld3(&s->fplane[4 * f]);
+        for (int v = 0; v < 3; ++v) {
+            double dist = fabs(dot(n, ld3(&s->tri_v[9 * t + 3 * v])) - s->fplane[4 * f + 3]);
+            if (!(dist <= 1e-9 * diag + 1e-300)) {
+                delete s;
+                return fail(c, SBR_E_INVALID_ARG, "triangle %lld is not in the plane of face %d",
+                            (long long)t, f);
+            }
+        }
+    }
+    c->n_scenes += 1;
+    *out = s;
+    return SBR_OK;
+}
+
+sbr_status sbr_bvh_build(sbr_scene* s, const sbr_bvh_params* bp)
+{
+    if (!s || !s->ctx) return SBR_E_NO_SCENE;
+    sbr_context* c = s->ctx;
+    c->err.clear();
+    int leaf = bp ? bp->max_leaf_size : 4, bins = bp ? bp->sah_bins : 16;
+    if (leaf < 1 || leaf > 16 || bins < 4 || bins > 64)
+        return fail(c, SBR_E_INVALID_ARG, "bvh params out of range");
+    std::vector<BvhNode> nodes;
+    std::vector<int32_t> perm;
+    s->bvh_depth = build_bvh(s->tri_v.data(), s->T, leaf, bins, nodes, perm);
+    if (s->bvh_depth >= kTraceStack) return fail(c, SBR_E_INTERNAL, "BVH too deep");
+    std::vector<TriD> tris((size_t)s->T);
+    std::vector<int32_t> pos_of((size_t)s->T);
+    for (int64_t q = 0; q < s->T; ++q) {
+        int32_t t = perm[q];
+        const double* V = &s->tri_v[9 * (size_t)t];
+        TriD& d = tris[q];
+        d.v0x = V[0]; d.v0y = V[1]; d.v0z = V[2];
+        d.e1x = V[3] - V[0]; d.e1y = V[4] - V[1]; d.e1z = V[5] - V[2];
+        d.e2x = V[6] - V[0]; d.e2y = V[7] - V[1]; d.e2z = V[8] - V[2];
+        d.face = s->face[t];
+        d.orig = t;
+        pos_of[t] = (int32_t)q;
+    }
+    // CSR of triangles per face (positions in leaf order, input order within a face)
+    std::vector<int32_t> fstart((size_t)s->F + 1, 0), ftris((size_t)s->T);
+    for (int64_t t = 0; t < s->T; ++t) fstart[s->face[t] + 1] += 1;
+    for (int32_t f = 0; f < s->F; ++f) fstart[f + 1] += fstart[f];
+    std::vector<int32_t> fill(fstart.begin(), fstart.end() - 1);
+    for (int64_t t = 0; t < s->T; ++t) ftris[fill[s->face[t]]++] = pos_of[t];
+
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, ensure(s->nodes, sizeof(BvhNode) * nodes.size()));
+    HIPCHK(c, ensure(s->tris, sizeof(TriD) * tris.size()));
+    HIPCHK(c, ensure(s->d_fplane, sizeof(double) * s->fplane.size()));
+    HIPCHK(c, ensure(s->d_fmat, sizeof(int32_t) * s->fmat.size()));
+    HIPCHK(c, ensure(s->fstart, sizeof(int32_t) * fstart.size()));
+    HIPCHK(c, ensure(s->ftris, sizeof(int32_t) * ftris.size()));
+    HIPCHK(c, ensure(s->d_eps, sizeof(double) * s->eps.size()));
+    HIPCHK(c, hipMemcpy(s->nodes.p, nodes.data(), sizeof(BvhNode) * nodes.size(), hipMemcpyHostToDevice));
+    if (!tris.empty())
+        HIPCHK(c, hipMemcpy(s->tris.p, tris.data(), sizeof(TriD) * tris.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(s->d_fplane.p, s->fplane.data(), sizeof(double) * s->fplane.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(s->d_fmat.p, s->fmat.data(), sizeof(int32_t) * s->fmat.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(s->fstart.p, fstart.data(), sizeof(int32_t) * fstart.size(), hipMemcpyHostToDevice));
+    if (!ftris.empty())
+        HIPCHK(c, hipMemcpy(s->ftris.p, ftris.data(), sizeof(int32_t) * ftris.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(s->d_eps.p, s->eps.data(), sizeof(double) * s->eps.size(), hipMemcpyHostToDevice));
+    s->has_bvh = true;
+    return SBR_OK;
+}
+
+sbr_status sbr_scene_destroy(sbr_scene* s)
+{
+    if (!s || !s->ctx) return SBR_E_NO_SCENE;
+    (void)hipSetDevice(s->ctx->device);
+    (void)hipStreamSynchronize(s->ctx->stream);
+    DevBuf* bufs[] = {&s->nodes, &s->tris, &s->d_fplane, &s->d_fmat, &s->fstart, &s->ftris, &s->d_eps};
+    for (DevBuf* b : bufs) release(*b);
+    s->ctx->n_scenes -= 1;
+    s->ctx = nullptr;
+    delete s;
+    return SBR_OK;
+}
+
+sbr_status sbr_launch_grid(sbr_context* c, int32_t n, int64_t first, int64_t count, double* out)
+{
+    if (!c) return SBR_E_INVALID_ARG;
+    c->err.clear();
+    if (n < 1 || n > 10000) return fail(c, SBR_E_INVALID_ARG, "n outside 1..10000");
+    int64_t N = 10 * (int64_t)n * n + 2;
+    if (first < 0 || count < 0 || first + count > N || (count > 0 && !out))
+        return fail(c, SBR_E_INVALID_ARG, "ray range outside 0..%lld", (long long)N);
+    HIPCHK(c, hipSetDevice(c->device));
+    GridDev g;
+    bool built;
+    sbr_status r = get_grid(c, n, &g, &built);
+    if (r) return r;
+    if (count == 0) return SBR_OK;
+    std::vector<double> tmp((size_t)count * 3);
+    for (int a = 0; a < 3; ++a)
+        HIPCHK(c, hipMemcpyAsync(tmp.data() + a * count, g.dir + a * N + first,
+                                 sizeof(double) * (size_t)count, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int64_t i = 0; i < count; ++i)
+        for (int a = 0; a < 3; ++a) out[3 * i + a] = tmp[a * count + i];
+    return SBR_OK;
+}
+
+sbr_status sbr_trace_rays(sbr_scene* s, const double tx[3], int32_t n, int32_t K, int64_t first,
+                          int64_t count, int32_t* out_tri, double* out_t)
+{
+    sbr_status r = check_scene(s);
+    if (r) return r;
+    sbr_context* c = s->ctx;
+    c->err.clear();
+    if (!tx || !finite3(tx)) return fail(c, SBR_E_INVALID_ARG, "tx missing or not finite");
+    if (n < 1 || n > 10000 || K < 0 || K > SBR_MAX_ORDER)
+        return fail(c, SBR_E_INVALID_ARG, "n or max_order out of range");
+    int64_t N = 10 * (int64_t)n * n + 2;
+    if (first < 0 || count < 0 || first + count > N)
+        return fail(c, SBR_E_INVALID_ARG, "ray range outside 0..%lld", (long long)N);
+    HIPCHK(c, hipSetDevice(c->device));
+    GridDev g;
+    bool built;
+    r = get_grid(c, n, &g, &built);
+    if (r) return r;
+    if (count == 0) return SBR_OK;
+    size_t cells = (size_t)count * (K + 1);
+    HIPCHK(c, ensure(c->rays_tri, sizeof(int32_t) * cells));
+    HIPCHK(c, ensure(c->rays_t, sizeof(double) * cells));
+    HIPCHK(c, ensure(c->counters, sizeof(Counters)));
+    HIPCHK(c, hipMemsetAsync(c->counters.p, 0, sizeof(Counters), c->stream));
+    TraceArgs A;
+    for (int i = 0; i < 3; ++i) A.tx[i] = tx[i];
+    A.rx = nullptr;
+    A.n_rx = 0;
+    A.K = K;
+    A.thl = theta_launch(n);
+    A.delta = traversal_delta(s, tx);
+    HIPCHK(c, launch_trace(scene_dev(s), g, A, first, count, nullptr, 0,
+                           &c->counters.as<Counters>()->cand, c->rays_tri.as<int32_t>(),
+                           c->rays_t.as<double>(), &c->counters.as<Counters>()->err, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->host_ctr, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, c->stream));
+    if (out_tri)
+        HIPCHK(c, hipMemcpyAsync(out_tri, c->rays_tri.p, sizeof(int32_t) * cells, hipMemcpyDeviceToHost, c->stream));
+    if (out_t)
+        HIPCHK(c, hipMemcpyAsync(out_t, c->rays_t.p, sizeof(double) * cells, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->host_ctr->err) return fail(c, SBR_E_INTERNAL, "traversal stack overflow");
+    return SBR_OK;
+}
+
+static sbr_status check_trace_inputs(sbr_scene* s, const double* tx, const double* rx,
+                                     int32_t n_rx, const sbr_trace_params* p, int64_t capacity,
+                                     const void* out, int64_t* n_out)
+{
+    sbr_status r = check_scene(s);
+    if (r) return r;
+    sbr_context* c = s->ctx;
+    c->err.clear();
+    if (!n_out) return fail(c, SBR_E_INVALID_ARG, "n_out is NULL");
+    *n_out = 0;
+    if (!tx || !finite3(tx)) return fail(c, SBR_E_INVALID_ARG, "tx missing or not finite");
+    if (n_rx < 0 || (n_rx > 0 && !rx)) return fail(c, SBR_E_INVALID_ARG, "bad rx array");
+    for (int32_t x = 0; x < n_rx; ++x)
+        if (!finite3(rx + 3 * x)) return fail(c, SBR_E_INVALID_ARG, "rx %d not finite", x);
+    if (capacity < 0 || (capacity > 0 && !out)) return fail(c, SBR_E_INVALID_ARG, "bad output array");
+    return check_params(c, p);
+}
+
+sbr_status sbr_candidates(sbr_scene* s, const double tx[3], const double* rx, int32_t n_rx,
+                          const sbr_trace_params* p, sbr_candidate* out, int64_t capacity,
+                          int64_t* n_out)
+{
+    sbr_status r = check_trace_inputs(s, tx, rx, n_rx, p, capacity, out, n_out);
+    if (r) return r;
+    sbr_context* c = s->ctx;
+    HIPCHK(c, hipSetDevice(c->device));
+    Front fr;
+    r = run_front(s, tx, rx, n_rx, p, false, &fr);
+    if (r) return r;
+    *n_out = fr.n_cand;
+    if (fr.n_cand > capacity)
+        return fail(c, SBR_E_CAPACITY, "%lld events, capacity %lld", (long long)fr.n_cand, (long long)capacity);
+    if (fr.n_cand == 0) return SBR_OK;
+    HIPCHK(c, ensure(c->uniq, sizeof(sbr_candidate) * (size_t)fr.n_cand));
+    HIPCHK(c, launch_gather_sorted(c->cand.as<sbr_candidate>(), c->idx.as<uint32_t>(), fr.n_cand,
+                                   c->uniq.as<sbr_candidate>(), c->stream));
+    HIPCHK(c, hipMemcpyAsync(out, c->uniq.p, sizeof(sbr_candidate) * (size_t)fr.n_cand,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SBR_OK;
+}
+
+sbr_status sbr_trace_counters(sbr_scene* s, const double tx[3], const double* rx, int32_t n_rx,
+                              const sbr_trace_params* p, int64_t counts[4])
+{
+    int64_t dummy;
+    sbr_status r = check_trace_inputs(s, tx, rx, n_rx, p, 0, nullptr, &dummy);
+    if (r) return r;
+    sbr_context* c = s->ctx;
+    if (!counts) return fail(c, SBR_E_INVALID_ARG, "counts is NULL");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, ensure(c->tally, 4 * sizeof(unsigned long long)));
+    Front fr;
+    r = run_front(s, tx, rx, n_rx, p, false, &fr, c->tally.as<unsigned long long>());
+    if (r) return r;
+    unsigned long long h[4];
+    HIPCHK(c, hipMemcpy(h, c->tally.p, sizeof h, hipMemcpyDeviceToHost));
+    for (int i = 0; i < 4; ++i) counts[i] = (int64_t)h[i];
+    return SBR_OK;
+}
+
+sbr_status sbr_trace(sbr_scene* s, const double tx[3], const double* rx, int32_t n_rx,
+                     const sbr_trace_params* p, sbr_path* out, int64_t capacity, int64_t* n_out,
+                     sbr_trace_stats* stats)
+{
+    sbr_status r = check_trace_inputs(s, tx, rx, n_rx, p, capacity, out, n_out);
+    if (r) return r;
+    sbr_context* c = s->ctx;
+    hipStream_t st = c->stream;
+    HIPCHK(c, hipSetDevice(c->device));
+    Front fr;
+    r = run_front(s, tx, rx, n_rx, p, true, &fr);
+    if (r) return r;
+    const int64_t U = fr.n_uniq;
+    SceneDev S = scene_dev(s);
+    Counters* hc = c->host_ctr;
+
+    // precise algorithm
+    RefineArgs ra;
+    for (int i = 0; i < 3; ++i) ra.tx[i] = tx[i];
+    ra.rx = c->rx.as<const double>();
+    ra.thl = fr.ta.thl;
+    ra.tan_tgt = p->target_err_deg > 0.0 ? tan_cr((p->target_err_deg * kPi) / 180.0) : 0.0;
+    ra.iterations = p->iterations;
+    ra.subrays = p->subrays;
+    HIPCHK(c, ensure(c->refine, sizeof(RefineOut) * (size_t)std::max<int64_t>(U, 1)));
+    HIPCHK(c, launch_refine(S, fr.g, ra, c->uniq.as<sbr_candidate>(), U,
+                            c->refine.as<RefineOut>(), fr.ta.delta,
+                            &c->counters.as<Counters>()->err, st));
+    HIPCHK(c, hipEventRecord(c->ev[4], st));
+
+    // path quantities, path test 2, power
+    SolveArgs sa;
+    for (int i = 0; i < 3; ++i) sa.tx[i] = tx[i];
+    sa.rx = c->rx.as<const double>();
+    sa.freq_hz = p->freq_hz;
+    sa.tx_power_dbm = p->tx_power_dbm;
+    sa.keep_invalid = (p->flags & SBR_FLAG_KEEP_INVALID) ? 1 : 0;
+    HIPCHK(c, ensure(c->paths, sizeof(sbr_path) * (size_t)std::max<int64_t>(U, 1)));
+    HIPCHK(c, ensure(c->keep, sizeof(int32_t) * (size_t)std::max<int64_t>(U, 1)));
+    HIPCHK(c, ensure(c->offs, sizeof(int32_t) * (size_t)std::max<int64_t>(U, 1)));
+    HIPCHK(c, ensure(c->scan, scan_scratch_bytes(U)));
+    HIPCHK(c, launch_solve(S, sa, c->uniq.as<sbr_candidate>(), c->refine.as<RefineOut>(), U,
+                           c->paths.as<sbr_path>(), c->keep.as<int32_t>(), fr.ta.delta,
+                           &c->counters.as<Counters>()->err, st));
+    HIPCHK(c, hipEventRecord(c->ev[5], st));
+
+    // emit: stable compaction of kept paths (already in canonical order)
+    HIPCHK(c, launch_scan(c->keep.as<int32_t>(), c->offs.as<int32_t>(), U,
+                          &c->counters.as<Counters>()->n_paths, c->scan.p, st));
+    HIPCHK(c, hipMemcpyAsync(hc, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (hc->err) return fail(c, SBR_E_INTERNAL, "traversal stack overflow");
+    const int64_t P = hc->n_paths;
+    *n_out = P;
+    if (P > capacity) {
+        return fail(c, SBR_E_CAPACITY, "%lld paths, capacity %lld", (long long)P, (long long)capacity);
+    }
+    HIPCHK(c, ensure(c->outp, sizeof(sbr_path) * (size_t)std::max<int64_t>(P, 1)));
+    HIPCHK(c, launch_compact_paths(c->paths.as<sbr_path>(), c->keep.as<int32_t>(),
+                                   c->offs.as<int32_t>(), U, c->outp.as<sbr_path>(), st));
+    if (P > 0)
+        HIPCHK(c, hipMemcpyAsync(out, c->outp.p, sizeof(sbr_path) * (size_t)P,
+                                 hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipEventRecord(c->ev[6], st));
+    HIPCHK(c, hipEventSynchronize(c->ev[6]));
+    if (stats) {
+        memset(stats, 0, sizeof(*stats));
+        stats->n_rays = fr.N;
+        stats->n_candidates = fr.n_cand;
+        stats->n_unique = U;
+        stats->n_paths = P;
+        float a = 0, b = 0, e = 0, tot = 0;
+        (void)hipEventElapsedTime(&a, c->ev[3], c->ev[4]);
+        (void)hipEventElapsedTime(&b, c->ev[4], c->ev[5]);
+        (void)hipEventElapsedTime(&e, c->ev[5], c->ev[6]);
+        (void)hipEventElapsedTime(&tot, c->ev[0], c->ev[6]);
+        stats->ms_launch = fr.ms_launch;
+        stats->ms_trace = fr.ms_trace;
+        stats->ms_dedup = fr.ms_dedup;
+        stats->ms_refine = a;
+        stats->ms_solve = b;
+        stats->ms_emit = e;
+        stats->ms_total = tot;
+    }
+    return SBR_OK;
+}
+
+}  // extern "C"

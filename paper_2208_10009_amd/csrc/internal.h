@@ -1,0 +1,141 @@
+// internal.h -- declarations shared by the library's host and device sources
+// (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/sbr.h"
+
+namespace sbr {
+
+// One triangle for the FP64 ray-triangle test, in BVH leaf order: v0 and the
+// edges e1 = v1 - v0, e2 = v2 - v0, its face and its index in the input.
+struct TriD {
+    double v0x, v0y, v0z, e1x, e1y, e1z, e2x, e2y, e2z;
+    int32_t face, orig;
+};
+static_assert(sizeof(TriD) == 80, "TriD layout");
+
+// BVH2 node, 64 bytes: the FP32 boxes of both children (rounded outward)
+// and, per child, (index, count): count > 0 is a leaf of `count` triangles
+// starting at `index` in leaf order, count == 0 an inner node, count < 0 an
+// empty child.  Packed as 4 x 16 B for aligned vector loads:
+//   a = lo0.xyz hi0.x | b = hi0.yz lo1.xy | c = lo1.z hi1.xyz | m = c0 c1 n0 n1
+struct BvhNode {
+    float a[4], b[4], c[4];
+    int32_t m[4];
+};
+static_assert(sizeof(BvhNode) == 64, "BvhNode layout");
+
+constexpr int kMaxBvhDepth = 48;   // builder cap; traversal stack bound
+constexpr int kTraceStack = 64;
+
+// Host-side BVH build (binned SAH).  tri_v is [T][9] FP64 vertices.
+// perm receives the leaf order (input indices); returns the depth reached.
+int build_bvh(const double* tri_v, int64_t T, int max_leaf, int bins,
+              std::vector<BvhNode>& nodes, std::vector<int32_t>& perm);
+
+// Device view of a scene, passed by value to kernels.
+struct SceneDev {
+    const BvhNode* nodes;
+    const TriD* tris;       // leaf order
+    const double* fplane;   // [F][4]: unit normal, offset n.v0
+    const int32_t* fmat;    // [F]
+    const int32_t* fstart;  // [F+1] CSR of triangles per face
+    const int32_t* ftris;   // positions in `tris`
+    const double* eps;      // [M][2] relative permittivity re, im
+    int32_t n_tri, n_face;
+    double t_eps;           // 1e-9 x scene bounding-box diagonal
+};
+
+// Launch-grid tables for one division n (device, FP64 SoA).
+struct GridDev {
+    double* dir;       // [3][N]: x, y, z
+    int64_t N;
+    int32_t n;
+};
+
+// Per-call trace parameters as the kernels see them.
+struct TraceArgs {
+    double tx[3];
+    const double* rx;     // [n_rx][3] device
+    int32_t n_rx;
+    int32_t K;            // max order
+    double thl;           // theta_launch (rad)
+    float delta;          // box inflation (m) making FP32 traversal conservative
+};
+
+// ---- launchers (kernels.hip) -------------------------------------------
+hipError_t launch_grid(GridDev g, hipStream_t s, void* scratch);
+size_t grid_scratch_bytes(int32_t n);
+
+// Trace rays [first, first+count): reception events appended to cand (up to
+// cap; *cand_count counts all), optional per-ray tri/t outputs.  With
+// tallies non-NULL the counting variant adds (segments, nodes visited,
+// triangles tested, events) to tallies[0..3].
+hipError_t launch_trace(const SceneDev& S, const GridDev& g, const TraceArgs& A, int64_t first,
+                        int64_t count, sbr_candidate* cand, int64_t cap,
+                        unsigned long long* cand_count, int32_t* out_tri, double* out_t,
+                        int32_t* err_flag, hipStream_t s, unsigned long long* tallies = nullptr);
+
+// Sort candidates (sbr_candidate records) by (rx, order, faces, tan, ray);
+// idx (pow2_at_least(n) entries) receives the permutation.
+hipError_t launch_sort_candidates(const sbr_candidate* cand, int64_t n, uint32_t* idx,
+                                  hipStream_t s);
+int64_t pow2_at_least(int64_t n);
+
+// head flags of the sorted candidates: 1 where the key differs from the
+// previous entry.
+hipError_t launch_heads(const sbr_candidate* cand, const uint32_t* idx, int64_t n,
+                        int32_t* flags, hipStream_t s);
+
+// Exclusive scan of int32 flags -> int32 offsets, total written to *total.
+size_t scan_scratch_bytes(int64_t n);
+hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* total, void* scratch,
+                       hipStream_t s);
+
+// Gather the unique candidates (heads) into uniq in sorted order.
+hipError_t launch_gather_unique(const sbr_candidate* cand, const uint32_t* idx,
+                                const int32_t* flags, const int32_t* offs, int64_t n,
+                                sbr_candidate* uniq, hipStream_t s);
+
+// Per-path state after the precise algorithm.
+struct RefineOut {
+    double axis[3];
+    double tan_err;
+    int32_t iters;
+    uint32_t flags;
+};
+
+struct RefineArgs {
+    double tx[3];
+    const double* rx;
+    double thl;
+    double tan_tgt;   // <= 0: no target
+    int32_t iterations, subrays;
+};
+
+hipError_t launch_refine(const SceneDev& S, const GridDev& g, const RefineArgs& A,
+                         const sbr_candidate* uniq, int64_t U, RefineOut* out, float delta,
+                         int32_t* err, hipStream_t s);
+
+struct SolveArgs {
+    double tx[3];
+    const double* rx;
+    double freq_hz, tx_power_dbm;
+    int32_t keep_invalid;
+};
+
+hipError_t launch_solve(const SceneDev& S, const SolveArgs& A, const sbr_candidate* uniq,
+                        const RefineOut* rf, int64_t U, sbr_path* paths, int32_t* keep,
+                        float delta, int32_t* err, hipStream_t s);
+
+hipError_t launch_compact_paths(const sbr_path* paths, const int32_t* keep, const int32_t* offs,
+                                int64_t U, sbr_path* out, hipStream_t s);
+
+hipError_t launch_gather_sorted(const sbr_candidate* cand, const uint32_t* idx, int64_t n,
+                                sbr_candidate* out, hipStream_t s);
+
+}  // namespace sbr

@@ -18,3 +18,15 @@ def orc():
     from oracle import oracle as O
     O.build()
     return O
+
+
+@pytest.fixture(scope="session")
+def gpu():
+    """A library context on cuda:0.  Fails (never skips) when the HIP library
+    or the device is missing, so a GPU run cannot pass on a fallback."""
+    import torch
+    from paper_2208_10009_amd import sbr
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    ctx = sbr.Context(0)
+    yield ctx
+    ctx.close()
