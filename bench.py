@@ -86,6 +86,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes 5 times (calibrates "
+                         "the FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -97,6 +100,14 @@ def main():
     from paper_2208_10009_amd import sbr, scenes
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    if args.copy_probe:
+        x = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log("copy probe: 5 x %d bytes" % (x.numel() * 4))
+        return
     cfg = scenes.manhattan_config(args.seed)
     prm = cfg["params"]
     ctx = sbr.Context(0)
