@@ -61,7 +61,7 @@ struct sbr_context {
     int32_t n_scenes = 0;
     std::map<int32_t, DevBuf> grids;  // division n -> [3][N] FP64 directions
     DevBuf grid_scratch, rx, cand, idx, flags, offs, scan, uniq, refine, paths, keep, outp,
-        counters, rays_tri, rays_t, tally;
+        counters, rays_tri, rays_t, tally, fact;
     Counters* host_ctr = nullptr;  // pinned
     hipEvent_t ev[8] = {};
 };
@@ -118,7 +118,7 @@ sbr_status get_grid(sbr_context* c, int32_t n, GridDev* g, bool* built, bool fre
     if (it != c->grids.end() && fresh) {
         HIPCHK(c, ensure(c->grid_scratch, grid_scratch_bytes(n)));
         GridDev gd{it->second.as<double>(), N, n};
-        HIPCHK(c, launch_grid(gd, c->stream, c->grid_scratch.p));
+        HIPCHK(c, launch_grid(gd, c->stream, c->grid_scratch.p, c->fact.as<const dd>()));
         *built = true;
     }
     if (it == c->grids.end()) {
@@ -126,7 +126,7 @@ sbr_status get_grid(sbr_context* c, int32_t n, GridDev* g, bool* built, bool fre
         HIPCHK(c, ensure(b, sizeof(double) * 3 * (size_t)N));
         HIPCHK(c, ensure(c->grid_scratch, grid_scratch_bytes(n)));
         GridDev gd{b.as<double>(), N, n};
-        hipError_t e = launch_grid(gd, c->stream, c->grid_scratch.p);
+        hipError_t e = launch_grid(gd, c->stream, c->grid_scratch.p, c->fact.as<const dd>());
         if (e != hipSuccess) {
             release(b);
             return fail(c, SBR_E_DEVICE, "launch grid: %s", hipGetErrorString(e));
@@ -164,6 +164,17 @@ float traversal_delta(const sbr_scene* s, const double* tx)
     float f = (float)d;
     if ((double)f < d) f = nextafterf(f, INFINITY);
     return std::max(f, 1e-30f);
+}
+
+const dd* host_inv_fact()
+{
+    static dd tab[kFactN];
+    static bool done = false;
+    if (!done) {
+        make_inv_fact(tab);
+        done = true;
+    }
+    return tab;
 }
 
 // theta_launch = theta_0 / (sqrt(3) n), eq. (4).
@@ -339,6 +350,9 @@ sbr_status sbr_context_create(int32_t device, void* hip_stream, sbr_context** ou
         if (e != hipSuccess) break;
     }
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->host_ctr, sizeof(Counters), 0);
+    if (e == hipSuccess) e = ensure(c->fact, sizeof(dd) * kFactN);
+    if (e == hipSuccess) e = hipMemcpy(c->fact.p, host_inv_fact(), sizeof(dd) * kFactN,
+                                       hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         g_create_err = std::string("context setup: ") + hipGetErrorString(e);
         for (auto& ev : c->ev)
@@ -359,7 +373,8 @@ sbr_status sbr_context_destroy(sbr_context* c)
     for (auto& kv : c->grids) release(kv.second);
     DevBuf* bufs[] = {&c->grid_scratch, &c->rx,    &c->cand,  &c->idx,  &c->flags,
                       &c->offs,         &c->scan,  &c->uniq,  &c->refine, &c->paths,
-                      &c->keep,         &c->outp,  &c->counters, &c->rays_tri, &c->rays_t, &c->tally};
+                      &c->keep,         &c->outp,  &c->counters, &c->rays_tri, &c->rays_t, &c->tally,
+                      &c->fact};
     for (DevBuf* b : bufs) release(*b);
     for (auto& ev : c->ev)
         if (ev) (void)hipEventDestroy(ev);
@@ -678,7 +693,7 @@ sbr_status sbr_trace(sbr_scene* s, const double tx[3], const double* rx, int32_t
     for (int i = 0; i < 3; ++i) ra.tx[i] = tx[i];
     ra.rx = c->rx.as<const double>();
     ra.thl = fr.ta.thl;
-    ra.tan_tgt = p->target_err_deg > 0.0 ? tan_cr((p->target_err_deg * kPi) / 180.0) : 0.0;
+    ra.tan_tgt = p->target_err_deg > 0.0 ? tan_cr((p->target_err_deg * kPi) / 180.0, host_inv_fact()) : 0.0;
     ra.iterations = p->iterations;
     ra.subrays = p->subrays;
     HIPCHK(c, ensure(c->refine, sizeof(RefineOut) * (size_t)std::max<int64_t>(U, 1)));

@@ -109,52 +109,60 @@ SBR_HD dd dd_div(dd a, dd b)
     return dd_add(q, dd{q3, 0.0});
 }
 
-// sin and cos of a double-double argument |x| <= 1.6 by their Taylor series;
-// the remainder after 20 terms is below 1.6^41/41! < 1e-41.
-SBR_HD void dd_sincos(dd x, dd* s, dd* c)
+// 1/k! for k = 0 .. kFactN-1 in double-double (relative error ~1e-31),
+// built by repeated double-double division; the device copy lives in the
+// context and is passed to the kernels that need it.
+constexpr int kFactN = 36;
+SBR_HD void make_inv_fact(dd* f)
 {
-    dd x2 = dd_mul(x, x);
-    dd ts = x, tc = dd{1.0, 0.0};
-    dd ss = x, cc = dd{1.0, 0.0};
-    for (int k = 1; k <= 20; ++k) {
-        double a = (double)(2 * k), b = (double)(2 * k + 1), c0 = (double)(2 * k - 1);
-        // ts_k = -ts_{k-1} x^2 / ((2k)(2k+1)),  tc_k = -tc_{k-1} x^2 / ((2k-1)(2k))
-        ts = dd_neg(dd_div(dd_mul(ts, x2), dd{a * b, 0.0}));
-        tc = dd_neg(dd_div(dd_mul(tc, x2), dd{c0 * a, 0.0}));
-        ss = dd_add(ss, ts);
-        cc = dd_add(cc, tc);
-    }
-    *s = ss;
-    *c = cc;
+    f[0] = dd{1.0, 0.0};
+    for (int k = 1; k < kFactN; ++k) f[k] = dd_div(f[k - 1], dd{(double)k, 0.0});
 }
 
-// Correctly rounded sin(x) for 0 <= x <= 1.6.
-SBR_HD double sin_cr(double x)
+// sin and cos of a double-double argument |x| <= 1.6 by their Taylor series
+// in Horner form over t = x^2 with 18 terms each: the first omitted terms are
+// below 1.6^35/35! < 1e-33 and 1.6^36/36! < 1e-34.
+SBR_HD void dd_sincos(dd x, const dd* f, dd* s, dd* c)
 {
-    dd s, c;
-    dd_sincos(dd{x, 0.0}, &s, &c);
+    dd t = dd_mul(x, x);
+    dd as = f[35], ac = f[34];
+    for (int k = 16; k >= 0; --k) {
+        as = dd_sub(f[2 * k + 1], dd_mul(t, as));
+        ac = dd_sub(f[2 * k], dd_mul(t, ac));
+    }
+    *s = dd_mul(x, as);
+    *c = ac;
+}
+
+// Correctly rounded sin(x) for 0 <= x <= 1.6 (the sine series alone).
+SBR_HD double sin_cr(double x, const dd* f)
+{
+    dd xx = dd{x, 0.0};
+    dd t = dd_mul(xx, xx);
+    dd as = f[35];
+    for (int k = 16; k >= 0; --k) as = dd_sub(f[2 * k + 1], dd_mul(t, as));
+    dd s = dd_mul(xx, as);
     return s.hi + s.lo;
 }
 
-// Correctly rounded acos(x) for cos(1.6) <= x < 1: two Newton steps on
-// cos(y) = x in double-double from the library's acos.
-SBR_HD double acos_cr(double x)
+// Correctly rounded acos(x) for cos(1.6) <= x < 1: one Newton step on
+// cos(y) = x in double-double from the library's acos (error ~1 ulp, so the
+// step leaves an error of order ulp^2).
+SBR_HD double acos_cr(double x, const dd* f)
 {
     dd y = dd{acos(x), 0.0};
-    for (int it = 0; it < 2; ++it) {
-        dd s, c;
-        dd_sincos(y, &s, &c);
-        // y <- y + (cos y - x) / sin y
-        y = dd_add(y, dd_div(dd_sub(c, dd{x, 0.0}), s));
-    }
+    dd s, c;
+    dd_sincos(y, f, &s, &c);
+    // y <- y + (cos y - x) / sin y
+    y = dd_add(y, dd_div(dd_sub(c, dd{x, 0.0}), s));
     return y.hi + y.lo;
 }
 
 // Correctly rounded tan(x) for 0 <= x <= 1.5 (sin/cos in double-double).
-SBR_HD double tan_cr(double x)
+SBR_HD double tan_cr(double x, const dd* f)
 {
     dd s, c;
-    dd_sincos(dd{x, 0.0}, &s, &c);
+    dd_sincos(dd{x, 0.0}, f, &s, &c);
     dd t = dd_div(s, c);
     return t.hi + t.lo;
 }

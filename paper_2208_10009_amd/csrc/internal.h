@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "../../include/sbr.h"
+#include "geom.h"
 
 namespace sbr {
 
@@ -68,7 +69,7 @@ struct TraceArgs {
 };
 
 // ---- launchers (kernels.hip) -------------------------------------------
-hipError_t launch_grid(GridDev g, hipStream_t s, void* scratch);
+hipError_t launch_grid(GridDev g, hipStream_t s, void* scratch, const dd* fact);
 size_t grid_scratch_bytes(int32_t n);
 
 // Trace rays [first, first+count): reception events appended to cand (up to

@@ -73,12 +73,12 @@ __device__ static void ico_build(GridHdr* H)
 // Point k of m equal-angle steps from P to Q along their great circle: the
 // angles subtended at the centre by consecutive points are equal (eq. (1)).
 // Direction sin((m-k) th/m) P + sin(k th/m) Q, normalized.
-__device__ static d3 arc_point(d3 P, d3 Q, int64_t k, int64_t m)
+__device__ static d3 arc_point(d3 P, d3 Q, int64_t k, int64_t m, const dd* fact)
 {
-    double th = acos_cr(dot(P, Q));
+    double th = acos_cr(dot(P, Q), fact);
     double a = ((double)k * th) / (double)m;
     double b = ((double)(m - k) * th) / (double)m;
-    double sa = sin_cr(a), sb = sin_cr(b);
+    double sa = sin_cr(a, fact), sb = sin_cr(b, fact);
     return normalize(add(scl(sb, P), scl(sa, Q)));
 }
 
@@ -89,55 +89,70 @@ __device__ static d3 proj_face(d3 p, d3 g)
     return mk(p.x / w, p.y / w, p.z / w);
 }
 
-// One block: thread 0 builds the icosahedron, then thread f builds the ring
-// corners of face f.  Layer 0 is the face boundary (corners = face vertices,
-// n equal-angle steps per side).  The corners of the next layer follow
-// eq. (2): the corner moves by the sum of the vectors to its two neighbours
-// on the ring, evaluated on the flat face (the construction of Fig. 3b), and
-// the new side has three steps fewer.  Side 0 is the single face-centre ray;
-// negative sides end the face (the three innermost cases).
-__global__ void k_grid_setup(int32_t n, char* scratch)
+// Ring corners of every face, layer by layer.  Layer 0 is the face boundary
+// (corners = face vertices, n equal-angle steps per side).  The corners of
+// the next layer follow eq. (2): each corner moves by the sum of the vectors
+// to its two neighbours on the ring, evaluated on the flat face (the
+// construction of Fig. 3b), and the new side has three steps fewer.  Side 0
+// is the single face-centre ray; negative sides end the face (the three
+// innermost cases).  The layers depend on each other, so one block walks
+// them in order: 120 threads compute the 20 x 3 x 2 neighbour points of a
+// layer, then 60 threads form the next corners.
+__global__ __launch_bounds__(128) void k_grid_setup(int32_t n, char* scratch,
+                                                    const dd* __restrict__ fact)
 {
     GridHdr* H = (GridHdr*)scratch;
     d3* rings = (d3*)(scratch + sizeof(GridHdr));
     __shared__ GridHdr sh;
-    if (threadIdx.x == 0) {
+    __shared__ d3 W[20][3];
+    __shared__ d3 P[20][3][2];
+    const int t = threadIdx.x;
+    if (t == 0) {
         ico_build(&sh);
         *H = sh;
     }
     __syncthreads();
-    int f = threadIdx.x;
-    if (f >= 20) return;
-    d3 A = sh.V[sh.f[f][0]], B = sh.V[sh.f[f][1]], C = sh.V[sh.f[f][2]];
-    d3 g = add(add(A, B), C);
-    d3 W[3] = {A, B, C};
-    d3* out = rings + (size_t)f * 3 * ring_cap(n);
+    const int f60 = t / 3, s60 = t % 3;
+    if (t < 60) W[f60][s60] = sh.V[sh.f[f60][s60]];
+    __syncthreads();
+    d3 g = mk(0.0, 0.0, 0.0);
+    if (t < 60) {
+        d3 A = sh.V[sh.f[f60][0]], B = sh.V[sh.f[f60][1]], C = sh.V[sh.f[f60][2]];
+        g = add(add(A, B), C);
+    }
+    const size_t cap3 = 3 * (size_t)ring_cap(n);
     int64_t m = n;
-    int a = 0;
-    for (;;) {
+    for (int a = 0;; ++a) {
         int64_t mp = m - 3;
         if (mp < 0) break;
         if (mp == 0) {
-            d3 c = normalize(add(add(A, B), C));
-            out[3 * a + 0] = c;
-            out[3 * a + 1] = c;
-            out[3 * a + 2] = c;
+            if (t < 20) {
+                d3 A = sh.V[sh.f[t][0]], B = sh.V[sh.f[t][1]], C = sh.V[sh.f[t][2]];
+                d3 c = normalize(add(add(A, B), C));
+                d3* out = rings + (size_t)t * cap3 + 3 * a;
+                out[0] = c;
+                out[1] = c;
+                out[2] = c;
+            }
             break;
         }
-        d3 Wn[3];
-        for (int s = 0; s < 3; ++s) {
-            d3 P0 = W[s];
-            d3 P1 = arc_point(W[s], W[(s + 1) % 3], 1, m);
-            d3 Pm = arc_point(W[(s + 2) % 3], W[s], m - 1, m);
-            d3 X = sub(add(proj_face(P1, g), proj_face(Pm, g)), proj_face(P0, g));
-            Wn[s] = normalize(X);
+        if (t < 120) {
+            int f = t / 6, s = (t % 6) >> 1, w = t & 1;
+            P[f][s][w] = w == 0 ? arc_point(W[f][s], W[f][(s + 1) % 3], 1, m, fact)
+                                : arc_point(W[f][(s + 2) % 3], W[f][s], m - 1, m, fact);
         }
-        for (int s = 0; s < 3; ++s) {
-            W[s] = Wn[s];
-            out[3 * a + s] = Wn[s];
+        __syncthreads();
+        d3 Wn = mk(0.0, 0.0, 0.0);
+        if (t < 60) {
+            d3 X = sub(add(proj_face(P[f60][s60][0], g), proj_face(P[f60][s60][1], g)),
+                       proj_face(W[f60][s60], g));
+            Wn = normalize(X);
+            rings[(size_t)f60 * cap3 + 3 * a + s60] = Wn;
         }
+        __syncthreads();
+        if (t < 60) W[f60][s60] = Wn;
+        __syncthreads();
         m = mp;
-        ++a;
     }
 }
 
@@ -146,7 +161,7 @@ __global__ void k_grid_setup(int32_t n, char* scratch)
 // by face, layer by layer, each ring starting at the corner that descends
 // from the face's first vertex and following the winding.
 __global__ void k_grid_dirs(int32_t n, int64_t N, const char* __restrict__ scratch,
-                            double* __restrict__ dir)
+                            const dd* __restrict__ fact, double* __restrict__ dir)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
@@ -160,7 +175,7 @@ __global__ void k_grid_dirs(int32_t n, int64_t N, const char* __restrict__ scrat
         idx -= 12;
         if (idx < 30 * (int64_t)(n - 1)) {
             int64_t e = idx / (n - 1), k = idx % (n - 1) + 1;
-            r = arc_point(H->V[H->e[e][0]], H->V[H->e[e][1]], k, n);
+            r = arc_point(H->V[H->e[e][0]], H->V[H->e[e][1]], k, n, fact);
         } else {
             idx -= 30 * (int64_t)(n - 1);
             int64_t per_face = (int64_t)(n - 1) * (n - 2) / 2;
@@ -179,7 +194,7 @@ __global__ void k_grid_dirs(int32_t n, int64_t N, const char* __restrict__ scrat
                 r = W[0];
             } else {
                 int64_t s = q / m, k = q % m;
-                r = k == 0 ? W[s] : arc_point(W[s], W[(s + 1) % 3], k, m);
+                r = k == 0 ? W[s] : arc_point(W[s], W[(s + 1) % 3], k, m, fact);
             }
         }
     }
@@ -188,12 +203,12 @@ __global__ void k_grid_dirs(int32_t n, int64_t N, const char* __restrict__ scrat
     dir[2 * N + i] = r.z;
 }
 
-hipError_t launch_grid(GridDev g, hipStream_t s, void* scratch)
+hipError_t launch_grid(GridDev g, hipStream_t s, void* scratch, const dd* fact)
 {
-    hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(64), 0, s, g.n, (char*)scratch);
+    hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(128), 0, s, g.n, (char*)scratch, fact);
     int64_t blocks = (g.N + 255) / 256;
     hipLaunchKernelGGL(k_grid_dirs, dim3((unsigned)blocks), dim3(256), 0, s, g.n, g.N,
-                       (const char*)scratch, g.dir);
+                       (const char*)scratch, fact, g.dir);
     return hipGetLastError();
 }
 
