@@ -176,6 +176,7 @@ def main():
         "trace_rays_per_s": n_rays / (stage["ms_trace"] * 1e-3),
         "stage_ms": {k: round(v, 5) for k, v in stage.items()},
         "counts": counts,
+        "lds": {k: int(stats[-1][k]) for k in ("lds_bytes", "lds_nodes", "lds_tris", "lds_max")},
         "roofline": roofline,
     }
     sc.close()

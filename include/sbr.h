@@ -103,12 +103,13 @@ typedef struct {
     double tan_err;
 } sbr_candidate;
 
-/* Per-call timings (ms, measured with HIP events on the context stream) and
- * counts. */
+/* Per-call timings (ms, measured with HIP events on the context stream),
+ * counts, and the LDS staging of the trace kernel (bytes per workgroup, BVH
+ * nodes and triangles held in LDS, device limit per workgroup). */
 typedef struct {
     int64_t n_rays, n_candidates, n_unique, n_paths;
     double ms_launch, ms_trace, ms_dedup, ms_refine, ms_solve, ms_emit, ms_total;
-    int64_t reserved[4];
+    int64_t lds_bytes, lds_nodes, lds_tris, lds_max;
 } sbr_trace_stats;
 
 /* BVH build options; NULL means defaults (leaf size 4, 16 SAH bins). */

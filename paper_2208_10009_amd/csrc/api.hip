@@ -3,6 +3,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -61,9 +62,17 @@ struct sbr_context {
     int32_t n_scenes = 0;
     std::map<int32_t, DevBuf> grids;  // division n -> [3][N] FP64 directions
     DevBuf grid_scratch, rx, cand, idx, flags, offs, scan, uniq, refine, paths, keep, outp,
-        counters, rays_tri, rays_t, tally, fact;
+        counters, rays_tri, rays_t, tally;
     Counters* host_ctr = nullptr;  // pinned
     hipEvent_t ev[8] = {};
+    // LDS staging of the traversal kernels: budget per block (0 = traverse
+    // from global memory with a private stack), lanes per block of the trace
+    // kernel, LDS stack entries per lane.  Defaults can be overridden with
+    // SBR_LDS_BUDGET, SBR_TRACE_BLOCK, SBR_STACK_DEPTH.
+    int32_t lds_max = 65536, lds_budget = 65536, trace_block = 256, stack_depth = 24;
+    // path counts up to which the refinement uses the two-iteration lookahead
+    // (64 lanes per path); SBR_LOOKAHEAD_PATHS overrides
+    int64_t lookahead_max_paths = 4096;
 };
 
 struct sbr_scene {
@@ -78,6 +87,7 @@ struct sbr_scene {
     double t_eps = 0.0, R_s = 0.0;
     bool has_bvh = false;
     int32_t bvh_depth = 0;
+    int64_t n_nodes = 0;
     DevBuf nodes, tris, d_fplane, d_fmat, fstart, ftris, d_eps;
 };
 
@@ -118,7 +128,7 @@ sbr_status get_grid(sbr_context* c, int32_t n, GridDev* g, bool* built, bool fre
     if (it != c->grids.end() && fresh) {
         HIPCHK(c, ensure(c->grid_scratch, grid_scratch_bytes(n)));
         GridDev gd{it->second.as<double>(), N, n};
-        HIPCHK(c, launch_grid(gd, c->stream, c->grid_scratch.p, c->fact.as<const dd>()));
+        HIPCHK(c, launch_grid(gd, c->stream, c->grid_scratch.p));
         *built = true;
     }
     if (it == c->grids.end()) {
@@ -126,7 +136,7 @@ sbr_status get_grid(sbr_context* c, int32_t n, GridDev* g, bool* built, bool fre
         HIPCHK(c, ensure(b, sizeof(double) * 3 * (size_t)N));
         HIPCHK(c, ensure(c->grid_scratch, grid_scratch_bytes(n)));
         GridDev gd{b.as<double>(), N, n};
-        hipError_t e = launch_grid(gd, c->stream, c->grid_scratch.p, c->fact.as<const dd>());
+        hipError_t e = launch_grid(gd, c->stream, c->grid_scratch.p);
         if (e != hipSuccess) {
             release(b);
             return fail(c, SBR_E_DEVICE, "launch grid: %s", hipGetErrorString(e));
@@ -150,6 +160,7 @@ SceneDev scene_dev(const sbr_scene* s)
     S.eps = s->d_eps.as<const double>();
     S.n_tri = (int32_t)s->T;
     S.n_face = s->F;
+    S.n_node = (int32_t)s->n_nodes;
     S.t_eps = s->t_eps;
     return S;
 }
@@ -166,15 +177,23 @@ float traversal_delta(const sbr_scene* s, const double* tx)
     return std::max(f, 1e-30f);
 }
 
-const dd* host_inv_fact()
+int env_int(const char* name, int dflt, int lo, int hi)
 {
-    static dd tab[kFactN];
-    static bool done = false;
-    if (!done) {
-        make_inv_fact(tab);
-        done = true;
+    const char* v = getenv(name);
+    if (!v || !*v) return dflt;
+    long x = strtol(v, nullptr, 10);
+    return (int)std::min<long>(hi, std::max<long>(lo, x));
+}
+
+LdsPlan plan_for(const sbr_scene* s, int block)
+{
+    const sbr_context* c = s->ctx;
+    if (c->lds_budget <= 0) {  // global-memory traversal, private stack
+        LdsPlan L{};
+        L.block = block;
+        return L;
     }
-    return tab;
+    return make_lds_plan(s->n_nodes, s->T, block, c->stack_depth, c->lds_budget);
 }
 
 // theta_launch = theta_0 / (sqrt(3) n), eq. (4).
@@ -214,6 +233,7 @@ struct Front {
     int64_t n_cand = 0, n_uniq = 0, N = 0;
     GridDev g;
     TraceArgs ta;
+    LdsPlan lp;
     float ms_launch = 0, ms_trace = 0, ms_dedup = 0;
 };
 
@@ -243,6 +263,7 @@ sbr_status run_front(sbr_scene* s, const double* tx, const double* rx, int32_t n
     A.thl = theta_launch(p->division_n);
     A.delta = traversal_delta(s, tx);
     SceneDev S = scene_dev(s);
+    fr->lp = plan_for(s, c->trace_block);
 
     int64_t cap = std::max<int64_t>(65536, (int64_t)(c->cand.cap / sizeof(sbr_candidate)));
     Counters* hc = c->host_ctr;
@@ -251,7 +272,7 @@ sbr_status run_front(sbr_scene* s, const double* tx, const double* rx, int32_t n
         HIPCHK(c, hipMemsetAsync(c->counters.p, 0, sizeof(Counters), st));
         if (tallies) HIPCHK(c, hipMemsetAsync(tallies, 0, 4 * sizeof(unsigned long long), st));
         HIPCHK(c, hipEventRecord(c->ev[7], st));
-        HIPCHK(c, launch_trace(S, fr->g, A, 0, fr->N, c->cand.as<sbr_candidate>(), cap,
+        HIPCHK(c, launch_trace(S, fr->lp, fr->g, A, 0, fr->N, c->cand.as<sbr_candidate>(), cap,
                                &c->counters.as<Counters>()->cand, nullptr, nullptr,
                                &c->counters.as<Counters>()->err, st, tallies));
         HIPCHK(c, hipEventRecord(c->ev[2], st));
@@ -296,6 +317,28 @@ sbr_status run_front(sbr_scene* s, const double* tx, const double* rx, int32_t n
 }
 
 }  // namespace
+
+namespace sbr {
+LdsPlan make_lds_plan(int64_t NN, int64_t T, int block, int depth, int budget)
+{
+    LdsPlan L;
+    L.block = block;
+    int64_t per_entry = 4 * (int64_t)block;
+    depth = (int)std::min<int64_t>(depth, std::max<int64_t>(0, budget / per_entry));
+    L.depth = depth;
+    int64_t avail = (int64_t)budget - per_entry * depth;
+    if (NN * (int64_t)sizeof(BvhNode) + T * (int64_t)sizeof(TriD) <= avail) {
+        L.n_nodes = (int32_t)NN;
+        L.n_tris = (int32_t)T;
+    } else {
+        L.n_nodes = (int32_t)std::min<int64_t>(NN, avail / (int64_t)sizeof(BvhNode));
+        L.n_tris = 0;
+    }
+    L.stack_off = (int32_t)(L.n_nodes * (int64_t)sizeof(BvhNode) + L.n_tris * (int64_t)sizeof(TriD));
+    L.bytes = (int32_t)(L.stack_off + per_entry * depth);
+    return L;
+}
+}  // namespace sbr
 
 extern "C" {
 
@@ -350,9 +393,21 @@ sbr_status sbr_context_create(int32_t device, void* hip_stream, sbr_context** ou
         if (e != hipSuccess) break;
     }
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->host_ctr, sizeof(Counters), 0);
-    if (e == hipSuccess) e = ensure(c->fact, sizeof(dd) * kFactN);
-    if (e == hipSuccess) e = hipMemcpy(c->fact.p, host_inv_fact(), sizeof(dd) * kFactN,
-                                       hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) ==
+                hipSuccess && v > 0)
+            c->lds_max = v;
+        if (trace_set_lds_limit(c->lds_max) != hipSuccess ||
+            refine_set_lds_limit(c->lds_max) != hipSuccess) {
+            (void)hipGetLastError();
+            c->lds_max = 65536;
+        }
+        c->lds_budget = env_int("SBR_LDS_BUDGET", 0, 0, c->lds_max);
+        c->trace_block = env_int("SBR_TRACE_BLOCK", 256, 64, 1024) / 64 * 64;
+        c->stack_depth = env_int("SBR_STACK_DEPTH", 24, 0, kTraceStack);
+        c->lookahead_max_paths = env_int("SBR_LOOKAHEAD_PATHS", 4096, 0, 1 << 30);
+    }
     if (e != hipSuccess) {
         g_create_err = std::string("context setup: ") + hipGetErrorString(e);
         for (auto& ev : c->ev)
@@ -373,8 +428,7 @@ sbr_status sbr_context_destroy(sbr_context* c)
     for (auto& kv : c->grids) release(kv.second);
     DevBuf* bufs[] = {&c->grid_scratch, &c->rx,    &c->cand,  &c->idx,  &c->flags,
                       &c->offs,         &c->scan,  &c->uniq,  &c->refine, &c->paths,
-                      &c->keep,         &c->outp,  &c->counters, &c->rays_tri, &c->rays_t, &c->tally,
-                      &c->fact};
+                      &c->keep,         &c->outp,  &c->counters, &c->rays_tri, &c->rays_t, &c->tally};
     for (DevBuf* b : bufs) release(*b);
     for (auto& ev : c->ev)
         if (ev) (void)hipEventDestroy(ev);
@@ -487,7 +541,8 @@ sbr_status sbr_bvh_build(sbr_scene* s, const sbr_bvh_params* bp)
         return fail(c, SBR_E_INVALID_ARG, "bvh params out of range");
     std::vector<BvhNode> nodes;
     std::vector<int32_t> perm;
-    s->bvh_depth = build_bvh(s->tri_v.data(), s->T, leaf, bins, nodes, perm);
+    s->bvh_depth = build_bvh(s->tri_v.data(), s->T, leaf, bins, c->lds_budget > 0, nodes, perm);
+    s->n_nodes = (int64_t)nodes.size();
     if (s->bvh_depth >= kTraceStack) return fail(c, SBR_E_INTERNAL, "BVH too deep");
     std::vector<TriD> tris((size_t)s->T);
     std::vector<int32_t> pos_of((size_t)s->T);
@@ -598,7 +653,7 @@ sbr_status sbr_trace_rays(sbr_scene* s, const double tx[3], int32_t n, int32_t K
     A.K = K;
     A.thl = theta_launch(n);
     A.delta = traversal_delta(s, tx);
-    HIPCHK(c, launch_trace(scene_dev(s), g, A, first, count, nullptr, 0,
+    HIPCHK(c, launch_trace(scene_dev(s), plan_for(s, c->trace_block), g, A, first, count, nullptr, 0,
                            &c->counters.as<Counters>()->cand, c->rays_tri.as<int32_t>(),
                            c->rays_t.as<double>(), &c->counters.as<Counters>()->err, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->host_ctr, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, c->stream));
@@ -693,11 +748,13 @@ sbr_status sbr_trace(sbr_scene* s, const double tx[3], const double* rx, int32_t
     for (int i = 0; i < 3; ++i) ra.tx[i] = tx[i];
     ra.rx = c->rx.as<const double>();
     ra.thl = fr.ta.thl;
-    ra.tan_tgt = p->target_err_deg > 0.0 ? tan_cr((p->target_err_deg * kPi) / 180.0, host_inv_fact()) : 0.0;
+    ra.tan_tgt = p->target_err_deg > 0.0 ? tan_cr((p->target_err_deg * kPi) / 180.0) : 0.0;
     ra.iterations = p->iterations;
     ra.subrays = p->subrays;
+    ra.lookahead_max_paths = c->lookahead_max_paths;
     HIPCHK(c, ensure(c->refine, sizeof(RefineOut) * (size_t)std::max<int64_t>(U, 1)));
-    HIPCHK(c, launch_refine(S, fr.g, ra, c->uniq.as<sbr_candidate>(), U,
+    const LdsPlan lp256 = plan_for(s, 256);
+    HIPCHK(c, launch_refine(S, lp256, fr.g, ra, c->uniq.as<sbr_candidate>(), U,
                             c->refine.as<RefineOut>(), fr.ta.delta,
                             &c->counters.as<Counters>()->err, st));
     HIPCHK(c, hipEventRecord(c->ev[4], st));
@@ -713,7 +770,7 @@ sbr_status sbr_trace(sbr_scene* s, const double tx[3], const double* rx, int32_t
     HIPCHK(c, ensure(c->keep, sizeof(int32_t) * (size_t)std::max<int64_t>(U, 1)));
     HIPCHK(c, ensure(c->offs, sizeof(int32_t) * (size_t)std::max<int64_t>(U, 1)));
     HIPCHK(c, ensure(c->scan, scan_scratch_bytes(U)));
-    HIPCHK(c, launch_solve(S, sa, c->uniq.as<sbr_candidate>(), c->refine.as<RefineOut>(), U,
+    HIPCHK(c, launch_solve(S, lp256, sa, c->uniq.as<sbr_candidate>(), c->refine.as<RefineOut>(), U,
                            c->paths.as<sbr_path>(), c->keep.as<int32_t>(), fr.ta.delta,
                            &c->counters.as<Counters>()->err, st));
     HIPCHK(c, hipEventRecord(c->ev[5], st));
@@ -755,6 +812,10 @@ sbr_status sbr_trace(sbr_scene* s, const double tx[3], const double* rx, int32_t
         stats->ms_solve = b;
         stats->ms_emit = e;
         stats->ms_total = tot;
+        stats->lds_bytes = fr.lp.bytes;
+        stats->lds_nodes = fr.lp.n_nodes;
+        stats->lds_tris = fr.lp.n_tris;
+        stats->lds_max = c->lds_max;
     }
     return SBR_OK;
 }

@@ -205,7 +205,7 @@ struct Builder {
 
 }  // namespace
 
-int build_bvh(const double* tri_v, int64_t T, int max_leaf, int bins,
+int build_bvh(const double* tri_v, int64_t T, int max_leaf, int bins, bool bfs,
               std::vector<BvhNode>& nodes, std::vector<int32_t>& perm)
 {
     Builder B;
@@ -244,7 +244,36 @@ int build_bvh(const double* tri_v, int64_t T, int max_leaf, int bins,
         }
     }
     B.emit(0, L, R);
-    nodes.swap(B.nodes);
+    if (!bfs) {
+        // depth-first order: the near child usually follows its parent in memory
+        nodes.swap(B.nodes);
+        perm.swap(B.idx);
+        return B.depth_reached;
+    }
+    // Renumber the inner nodes breadth-first, so that the top levels of the
+    // tree form a prefix of the node array (the part staged in LDS).
+    const size_t NN = B.nodes.size();
+    std::vector<int32_t> order;
+    order.reserve(NN);
+    std::vector<int32_t> new_id(NN, -1);
+    order.push_back(0);
+    new_id[0] = 0;
+    for (size_t q = 0; q < order.size(); ++q) {
+        const BvhNode& nd = B.nodes[order[q]];
+        for (int c = 0; c < 2; ++c) {
+            if (nd.m[2 + c] != 0) continue;  // leaf or empty child
+            int32_t ch = nd.m[c];
+            new_id[ch] = (int32_t)order.size();
+            order.push_back(ch);
+        }
+    }
+    nodes.resize(order.size());
+    for (size_t q = 0; q < order.size(); ++q) {
+        BvhNode nd = B.nodes[order[q]];
+        for (int c = 0; c < 2; ++c)
+            if (nd.m[2 + c] == 0) nd.m[c] = new_id[nd.m[c]];
+        nodes[q] = nd;
+    }
     perm.swap(B.idx);
     return B.depth_reached;
 }

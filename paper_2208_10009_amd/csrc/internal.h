@@ -30,12 +30,14 @@ struct BvhNode {
 };
 static_assert(sizeof(BvhNode) == 64, "BvhNode layout");
 
-constexpr int kMaxBvhDepth = 48;   // builder cap; traversal stack bound
+constexpr int kMaxBvhDepth = 48;   // builder cap; traversal stack bound (< kTraceStack)
 constexpr int kTraceStack = 64;
 
-// Host-side BVH build (binned SAH).  tri_v is [T][9] FP64 vertices.
-// perm receives the leaf order (input indices); returns the depth reached.
-int build_bvh(const double* tri_v, int64_t T, int max_leaf, int bins,
+// Host-side BVH build (binned SAH).  tri_v is [T][9] FP64 vertices.  Inner
+// nodes are numbered depth-first, or breadth-first with bfs (so that the top
+// levels form a prefix for LDS staging).  perm receives the leaf order
+// (input indices); returns the depth reached.
+int build_bvh(const double* tri_v, int64_t T, int max_leaf, int bins, bool bfs,
               std::vector<BvhNode>& nodes, std::vector<int32_t>& perm);
 
 // Device view of a scene, passed by value to kernels.
@@ -47,9 +49,21 @@ struct SceneDev {
     const int32_t* fstart;  // [F+1] CSR of triangles per face
     const int32_t* ftris;   // positions in `tris`
     const double* eps;      // [M][2] relative permittivity re, im
-    int32_t n_tri, n_face;
+    int32_t n_tri, n_face, n_node;
     double t_eps;           // 1e-9 x scene bounding-box diagonal
 };
+
+// Per-launch LDS plan of a traversal kernel: the first n_nodes BVH nodes and
+// the first n_tris triangles are copied into LDS, followed by a per-lane
+// stack of `depth` entries (stride `block`) at byte offset stack_off.
+struct LdsPlan {
+    int32_t n_nodes, n_tris, depth, stack_off, block;
+    int32_t bytes;  // dynamic LDS per block
+};
+
+// Largest LDS plan for a block of `block` lanes with `depth` stack entries
+// in `budget` bytes: everything when the scene fits, else a node prefix.
+LdsPlan make_lds_plan(int64_t n_nodes, int64_t n_tris, int block, int depth, int budget);
 
 // Launch-grid tables for one division n (device, FP64 SoA).
 struct GridDev {
@@ -69,17 +83,19 @@ struct TraceArgs {
 };
 
 // ---- launchers (kernels.hip) -------------------------------------------
-hipError_t launch_grid(GridDev g, hipStream_t s, void* scratch, const dd* fact);
+hipError_t launch_grid(GridDev g, hipStream_t s, void* scratch);
 size_t grid_scratch_bytes(int32_t n);
 
 // Trace rays [first, first+count): reception events appended to cand (up to
 // cap; *cand_count counts all), optional per-ray tri/t outputs.  With
 // tallies non-NULL the counting variant adds (segments, nodes visited,
 // triangles tested, events) to tallies[0..3].
-hipError_t launch_trace(const SceneDev& S, const GridDev& g, const TraceArgs& A, int64_t first,
-                        int64_t count, sbr_candidate* cand, int64_t cap,
+hipError_t launch_trace(const SceneDev& S, const LdsPlan& L, const GridDev& g, const TraceArgs& A,
+                        int64_t first, int64_t count, sbr_candidate* cand, int64_t cap,
                         unsigned long long* cand_count, int32_t* out_tri, double* out_t,
                         int32_t* err_flag, hipStream_t s, unsigned long long* tallies = nullptr);
+hipError_t trace_set_lds_limit(int bytes);
+hipError_t refine_set_lds_limit(int bytes);
 
 // Sort candidates (sbr_candidate records) by (rx, order, faces, tan, ray);
 // idx (pow2_at_least(n) entries) receives the permutation.
@@ -116,11 +132,12 @@ struct RefineArgs {
     double thl;
     double tan_tgt;   // <= 0: no target
     int32_t iterations, subrays;
+    int64_t lookahead_max_paths;  // up to this many paths: two-iteration lookahead
 };
 
-hipError_t launch_refine(const SceneDev& S, const GridDev& g, const RefineArgs& A,
-                         const sbr_candidate* uniq, int64_t U, RefineOut* out, float delta,
-                         int32_t* err, hipStream_t s);
+hipError_t launch_refine(const SceneDev& S, const LdsPlan& L, const GridDev& g,
+                         const RefineArgs& A, const sbr_candidate* uniq, int64_t U,
+                         RefineOut* out, float delta, int32_t* err, hipStream_t s);
 
 struct SolveArgs {
     double tx[3];
@@ -129,9 +146,9 @@ struct SolveArgs {
     int32_t keep_invalid;
 };
 
-hipError_t launch_solve(const SceneDev& S, const SolveArgs& A, const sbr_candidate* uniq,
-                        const RefineOut* rf, int64_t U, sbr_path* paths, int32_t* keep,
-                        float delta, int32_t* err, hipStream_t s);
+hipError_t launch_solve(const SceneDev& S, const LdsPlan& L, const SolveArgs& A,
+                        const sbr_candidate* uniq, const RefineOut* rf, int64_t U,
+                        sbr_path* paths, int32_t* keep, float delta, int32_t* err, hipStream_t s);
 
 hipError_t launch_compact_paths(const sbr_path* paths, const int32_t* keep, const int32_t* offs,
                                 int64_t U, sbr_path* out, hipStream_t s);

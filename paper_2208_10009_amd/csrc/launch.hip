@@ -1,0 +1,207 @@
+// launch.hip -- equiangular icosahedral launch directions (Sec. II.B) for
+// gfx950: ring corners of the 20 faces layer by layer, then one thread per
+// ray.  Every value is bit-identical to the correctly rounded FP64 grid (see
+// geom.h for the double-double trigonometry).
+#include <math.h>
+
+#include "geom.h"
+#include "internal.h"
+
+namespace sbr {
+
+// ===========================================================================
+// Launch grid (Sec. II.B)
+// ===========================================================================
+// Icosahedron: the 12 cyclic permutations of (0, +-1, +-phi), normalized, in a
+// fixed order; edges are the 30 pairs i < j of adjacent vertices (positive
+// dot product), listed lexicographically; faces are the 20 mutually adjacent
+// triples i < j < k, lexicographically, wound counter-clockwise seen from
+// outside (clockwise seen from the launch point, the paper's ordering).
+struct GridHdr {
+    d3 V[12];
+    int32_t e[30][2];
+    int32_t f[20][3];
+};
+
+__host__ __device__ static inline int64_t ring_cap(int32_t n) { return n / 3 + 2; }
+
+size_t grid_scratch_bytes(int32_t n)
+{
+    return sizeof(GridHdr) + sizeof(d3) * 3 * 20 * (size_t)ring_cap(n);
+}
+
+__device__ static void ico_build(GridHdr* H)
+{
+    const double phi = (1.0 + sqrt(5.0)) / 2.0;
+    const double raw[12][3] = {{0, 1, phi},  {0, -1, phi},  {0, 1, -phi},  {0, -1, -phi},
+                               {1, phi, 0},  {-1, phi, 0},  {1, -phi, 0},  {-1, -phi, 0},
+                               {phi, 0, 1},  {phi, 0, -1},  {-phi, 0, 1},  {-phi, 0, -1}};
+    for (int i = 0; i < 12; ++i) H->V[i] = normalize(ld3(raw[i]));
+    int ne = 0, nf = 0;
+    for (int i = 0; i < 12; ++i)
+        for (int j = i + 1; j < 12; ++j)
+            if (dot(H->V[i], H->V[j]) > 0.0) {
+                H->e[ne][0] = i;
+                H->e[ne][1] = j;
+                ++ne;
+            }
+    for (int i = 0; i < 12; ++i)
+        for (int j = i + 1; j < 12; ++j)
+            for (int k = j + 1; k < 12; ++k) {
+                bool a = dot(H->V[i], H->V[j]) > 0.0, b = dot(H->V[j], H->V[k]) > 0.0,
+                     c = dot(H->V[i], H->V[k]) > 0.0;
+                if (a && b && c) {
+                    double s = dot(H->V[i], cross(H->V[j], H->V[k]));
+                    H->f[nf][0] = i;
+                    H->f[nf][1] = s > 0.0 ? j : k;
+                    H->f[nf][2] = s > 0.0 ? k : j;
+                    ++nf;
+                }
+            }
+}
+
+// Point k of m equal-angle steps from P to Q along their great circle: the
+// angles subtended at the centre by consecutive points are equal (eq. (1)).
+// Direction sin((m-k) th/m) P + sin(k th/m) Q, normalized.
+__device__ static d3 arc_point(d3 P, d3 Q, int64_t k, int64_t m)
+{
+    double th = acos_cr(dot(P, Q));
+    double a = ((double)k * th) / (double)m;
+    double b = ((double)(m - k) * th) / (double)m;
+    double sa = sin_cr(a), sb = sin_cr(b);
+    return normalize(add(scl(sb, P), scl(sa, Q)));
+}
+
+// Central projection onto the plane x.g = 1 parallel to the face.
+__device__ static d3 proj_face(d3 p, d3 g)
+{
+    double w = dot(p, g);
+    return mk(p.x / w, p.y / w, p.z / w);
+}
+
+// Ring corners of every face, layer by layer.  Layer 0 is the face boundary
+// (corners = face vertices, n equal-angle steps per side).  The corners of
+// the next layer follow eq. (2): each corner moves by the sum of the vectors
+// to its two neighbours on the ring, evaluated on the flat face (the
+// construction of Fig. 3b), and the new side has three steps fewer.  Side 0
+// is the single face-centre ray; negative sides end the face (the three
+// innermost cases).  The layers depend on each other, so one block walks
+// them in order: 120 threads compute the 20 x 3 x 2 neighbour points of a
+// layer, then 60 threads form the next corners.
+__global__ __launch_bounds__(128) void k_grid_setup(int32_t n, char* scratch)
+{
+    GridHdr* H = (GridHdr*)scratch;
+    d3* rings = (d3*)(scratch + sizeof(GridHdr));
+    __shared__ GridHdr sh;
+    __shared__ d3 W[20][3];
+    __shared__ d3 P[20][3][2];
+    const int t = threadIdx.x;
+    if (t == 0) {
+        ico_build(&sh);
+        *H = sh;
+    }
+    __syncthreads();
+    const int f60 = t / 3, s60 = t % 3;
+    if (t < 60) W[f60][s60] = sh.V[sh.f[f60][s60]];
+    __syncthreads();
+    d3 g = mk(0.0, 0.0, 0.0);
+    if (t < 60) {
+        d3 A = sh.V[sh.f[f60][0]], B = sh.V[sh.f[f60][1]], C = sh.V[sh.f[f60][2]];
+        g = add(add(A, B), C);
+    }
+    const size_t cap3 = 3 * (size_t)ring_cap(n);
+    int64_t m = n;
+    for (int a = 0;; ++a) {
+        int64_t mp = m - 3;
+        if (mp < 0) break;
+        if (mp == 0) {
+            if (t < 20) {
+                d3 A = sh.V[sh.f[t][0]], B = sh.V[sh.f[t][1]], C = sh.V[sh.f[t][2]];
+                d3 c = normalize(add(add(A, B), C));
+                d3* out = rings + (size_t)t * cap3 + 3 * a;
+                out[0] = c;
+                out[1] = c;
+                out[2] = c;
+            }
+            break;
+        }
+        if (t < 120) {
+            // w = 0: first step from corner s toward s+1; w = 1: last step
+            // from corner s-1 toward s (the two ring neighbours of corner s)
+            int f = t / 6, s = (t % 6) >> 1, w = t & 1;
+            d3 Pa = w == 0 ? W[f][s] : W[f][(s + 2) % 3];
+            d3 Pb = w == 0 ? W[f][(s + 1) % 3] : W[f][s];
+            P[f][s][w] = arc_point(Pa, Pb, w == 0 ? 1 : m - 1, m);
+        }
+        __syncthreads();
+        d3 Wn = mk(0.0, 0.0, 0.0);
+        if (t < 60) {
+            d3 X = sub(add(proj_face(P[f60][s60][0], g), proj_face(P[f60][s60][1], g)),
+                       proj_face(W[f60][s60], g));
+            Wn = normalize(X);
+            rings[(size_t)f60 * cap3 + 3 * a + s60] = Wn;
+        }
+        __syncthreads();
+        if (t < 60) W[f60][s60] = Wn;
+        __syncthreads();
+        m = mp;
+    }
+}
+
+// Ray order: the 12 vertex rays; then edge interiors, edge by edge, steps
+// 1..n-1 from the lower to the higher vertex index; then face interiors, face
+// by face, layer by layer, each ring starting at the corner that descends
+// from the face's first vertex and following the winding.
+__global__ void k_grid_dirs(int32_t n, int64_t N, const char* __restrict__ scratch,
+                            double* __restrict__ dir)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const GridHdr* H = (const GridHdr*)scratch;
+    const d3* rings = (const d3*)(scratch + sizeof(GridHdr));
+    d3 r;
+    int64_t idx = i;
+    if (idx < 12) {
+        r = H->V[idx];
+    } else {
+        idx -= 12;
+        if (idx < 30 * (int64_t)(n - 1)) {
+            int64_t e = idx / (n - 1), k = idx % (n - 1) + 1;
+            r = arc_point(H->V[H->e[e][0]], H->V[H->e[e][1]], k, n);
+        } else {
+            idx -= 30 * (int64_t)(n - 1);
+            int64_t per_face = (int64_t)(n - 1) * (n - 2) / 2;
+            int64_t f = idx / per_face, q = idx % per_face;
+            int a = 0;
+            int64_t m = n - 3;
+            for (;;) {
+                int64_t sz = m > 0 ? 3 * m : 1;
+                if (q < sz) break;
+                q -= sz;
+                ++a;
+                m -= 3;
+            }
+            const d3* W = rings + (size_t)f * 3 * ring_cap(n) + 3 * a;
+            if (m == 0) {
+                r = W[0];
+            } else {
+                int64_t s = q / m, k = q % m;
+                r = k == 0 ? W[s] : arc_point(W[s], W[(s + 1) % 3], k, m);
+            }
+        }
+    }
+    dir[i] = r.x;
+    dir[N + i] = r.y;
+    dir[2 * N + i] = r.z;
+}
+
+hipError_t launch_grid(GridDev g, hipStream_t s, void* scratch)
+{
+    hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(128), 0, s, g.n, (char*)scratch);
+    int64_t blocks = (g.N + 255) / 256;
+    hipLaunchKernelGGL(k_grid_dirs, dim3((unsigned)blocks), dim3(256), 0, s, g.n, g.N,
+                       (const char*)scratch, g.dir);
+    return hipGetLastError();
+}
+
+}  // namespace sbr

@@ -1,0 +1,572 @@
+// refine.hip -- the iterative precise algorithm (Sec. III.B) and the path
+// quantities, path test 2 and power (Sec. III.A, Sec. IV).
+#include <math.h>
+
+#include "traverse.h"
+
+namespace sbr {
+
+// ===========================================================================
+// Iterative precise algorithm (Sec. III.B)
+// ===========================================================================
+// Orthonormal basis (u, v) of the plane normal to the unit axis a: e is the
+// coordinate axis with the smallest |a_i| (ties: lowest i),
+// u = normalize(e - a_i a), v = a x u.
+__device__ static inline void basis(d3 a, d3* u, d3* v)
+{
+    double c0 = fabs(a.x), c1 = fabs(a.y), c2 = fabs(a.z);
+    int i = 0;
+    double ci = c0;
+    if (c1 < ci) {
+        i = 1;
+        ci = c1;
+    }
+    if (c2 < ci) i = 2;
+    d3 e = mk(i == 0 ? 1.0 : 0.0, i == 1 ? 1.0 : 0.0, i == 2 ? 1.0 : 0.0);
+    double ai = i == 0 ? a.x : (i == 1 ? a.y : a.z);
+    *u = normalize(sub(e, scl(ai, a)));
+    *v = cross(a, *u);
+}
+
+// Sub-ray s of a cone with axis a: the cone's disc (radius rho_prev in the
+// plane tangent to the unit sphere at a) is covered by six discs of radius
+// rho = rho_prev / sqrt(3) whose centres sit at distance rho from the axis at
+// phases 0, 60, ..., 300 degrees; sub-ray 6 is the axis itself.
+__device__ static inline d3 subray(d3 a, d3 u, d3 v, double rho, int s)
+{
+    if (s == 6) return a;
+    const double h = sqrt(3.0) * 0.5;
+    double cs, ss;
+    switch (s) {
+        case 0: cs = 1.0; ss = 0.0; break;
+        case 1: cs = 0.5; ss = h; break;
+        case 2: cs = -0.5; ss = h; break;
+        case 3: cs = -1.0; ss = 0.0; break;
+        case 4: cs = -0.5; ss = -h; break;
+        default: cs = 0.5; ss = -h; break;
+    }
+    d3 w = add(scl(cs, u), scl(ss, v));
+    return normalize(add(a, scl(rho, w)));
+}
+
+// Stop rule: with a target error angle, stop once
+// tan(err) <= tan(target) * L_last / L_total (the AOA error grows from the AOD
+// error by about L_total / L_last, so both meet the target).
+__device__ static inline bool target_met(double tan_err, double tan_tgt, double D, double Llast)
+{
+    double Ltot = D + Llast;
+    double thr = (tan_tgt * Llast) / Ltot;
+    return tan_err <= thr;
+}
+
+// Start of the precise algorithm for one path: the launch ray that won path
+// test 1 is the first axis.  Its error angle is the reception event's (the
+// event was produced by the same FP64 arithmetic as a replay), so without a
+// target no replay is needed; with a target the replay gives the unfolded
+// lengths of the stop rule.  Returns false if the replay does not reproduce
+// the path.
+template <bool LDS>
+__device__ static inline bool start_path(const SceneDev& S, const LdsPlan& L, const RefineArgs& A,
+                                         const sbr_candidate& c, d3 tx, d3 rx, d3 axis,
+                                         float delta, int32_t* err, double* tan, bool* met)
+{
+    *met = false;
+    if (!(A.tan_tgt > 0.0)) {
+        *tan = c.tan_err;
+        return true;
+    }
+    Follow F0;
+    if (!follow<LDS>(S, L, tx, axis, rx, c.order, c.face, delta, &F0, nullptr, nullptr, err))
+        return false;
+    *tan = F0.tan_err;
+    *met = target_met(F0.tan_err, A.tan_tgt, F0.D, F0.Llast);
+    return true;
+}
+
+__device__ static inline RefineOut stalled_at_start(d3 axis)
+{
+    RefineOut o;
+    st3(o.axis, axis);
+    o.tan_err = NAN;
+    o.iters = 0;
+    o.flags = SBR_PATH_STALLED;
+    return o;
+}
+
+// Eight lanes per path: lane s traces sub-ray s (s < subrays); the group
+// keeps the smallest error angle (ties: lower s) as the next axis.
+template <bool LDS>
+__global__ __launch_bounds__(256) void k_refine(SceneDev S, LdsPlan L, GridDev g, RefineArgs A,
+                                                float delta,
+                                                const sbr_candidate* __restrict__ uniq, int64_t U,
+                                                RefineOut* __restrict__ out,
+                                                int32_t* __restrict__ err)
+{
+    if (LDS) stage_scene(S, L);
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t p = gid >> 3;
+    int s = (int)(gid & 7);
+    if (p >= U) return;
+    const sbr_candidate c = uniq[p];
+    const d3 tx = mk(A.tx[0], A.tx[1], A.tx[2]);
+    const d3 rx = mk(A.rx[3 * c.rx], A.rx[3 * c.rx + 1], A.rx[3 * c.rx + 2]);
+    d3 axis = mk(g.dir[c.ray], g.dir[g.N + c.ray], g.dir[2 * g.N + c.ray]);
+    double tan;
+    bool met;
+    if (!start_path<LDS>(S, L, A, c, tx, rx, axis, delta, err, &tan, &met)) {
+        if (s == 0) out[p] = stalled_at_start(axis);
+        return;
+    }
+    uint32_t flags = met ? SBR_PATH_TARGET_MET : 0u;
+    int32_t iters = 0;
+    double rho = A.thl;
+    for (int i = 1; i <= A.iterations && !met; ++i) {
+        rho = rho / sqrt(3.0);
+        d3 u, v;
+        basis(axis, &u, &v);
+        Follow F;
+        bool ok = false;
+        if (s < A.subrays)
+            ok = follow<LDS>(S, L, tx, subray(axis, u, v, rho, s), rx, c.order, c.face, delta, &F,
+                             nullptr, nullptr, err);
+        double bt = ok ? F.tan_err : INFINITY;
+        int bs = ok ? s : 8;
+        double myD = ok ? F.D : 0.0, myL = ok ? F.Llast : 0.0;
+#pragma unroll
+        for (int off = 1; off < 8; off <<= 1) {
+            double ot = __shfl_xor(bt, off, 8);
+            int os = __shfl_xor(bs, off, 8);
+            if (ot < bt || (ot == bt && os < bs)) {
+                bt = ot;
+                bs = os;
+            }
+        }
+        if (bs >= 8) {
+            flags |= SBR_PATH_STALLED;
+            break;
+        }
+        double wD = __shfl(myD, bs, 8), wL = __shfl(myL, bs, 8);
+        axis = subray(axis, u, v, rho, bs);
+        tan = bt;
+        iters = i;
+        if (A.tan_tgt > 0.0 && target_met(bt, A.tan_tgt, wD, wL)) {
+            flags |= SBR_PATH_TARGET_MET;
+            met = true;
+        }
+    }
+    if (s == 0) {
+        RefineOut o;
+        st3(o.axis, axis);
+        o.tan_err = tan;
+        o.iters = iters;
+        o.flags = flags;
+        out[p] = o;
+    }
+}
+
+// One wave per path, two iterations per step.  Lane (s1, 7) traces first-level
+// sub-ray s1; lane (s1, s2), s2 < subrays, traces sub-ray s2 of the cone that
+// first-level sub-ray s1 would open in the next iteration.  Once the
+// first-level winner b1 is known, the second-level winner among lanes
+// (b1, *) is the next iteration's.  Every sub-ray is computed with exactly the
+// arithmetic of the one-iteration-at-a-time order, so the result is the same
+// bit for bit; the latency of two iterations becomes that of one.
+template <bool LDS>
+__global__ __launch_bounds__(256) void k_refine_la(SceneDev S, LdsPlan L, GridDev g, RefineArgs A,
+                                                   float delta,
+                                                   const sbr_candidate* __restrict__ uniq,
+                                                   int64_t U, RefineOut* __restrict__ out,
+                                                   int32_t* __restrict__ err)
+{
+    if (LDS) stage_scene(S, L);
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t p = gid >> 6;
+    const int lane = (int)(gid & 63);
+    const int s1 = lane >> 3, s2 = lane & 7;
+    if (p >= U) return;
+    const sbr_candidate c = uniq[p];
+    const d3 tx = mk(A.tx[0], A.tx[1], A.tx[2]);
+    const d3 rx = mk(A.rx[3 * c.rx], A.rx[3 * c.rx + 1], A.rx[3 * c.rx + 2]);
+    d3 axis = mk(g.dir[c.ray], g.dir[g.N + c.ray], g.dir[2 * g.N + c.ray]);
+    double tan;
+    bool met;
+    if (!start_path<LDS>(S, L, A, c, tx, rx, axis, delta, err, &tan, &met)) {
+        if (lane == 0) out[p] = stalled_at_start(axis);
+        return;
+    }
+    uint32_t flags = met ? SBR_PATH_TARGET_MET : 0u;
+    int32_t iters = 0;
+    double rho = A.thl;
+    for (int i = 1; i <= A.iterations && !met; i += 2) {
+        const double rho1 = rho / sqrt(3.0);
+        const double rho2 = rho1 / sqrt(3.0);
+        d3 u, v;
+        basis(axis, &u, &v);
+        const bool two = i + 1 <= A.iterations;
+        const bool lvl1 = s2 == 7 && s1 < A.subrays;
+        const bool lvl2 = two && s2 < A.subrays && s1 < A.subrays;
+        Follow F;
+        bool ok = false;
+        if (lvl1 || lvl2) {
+            d3 dt = subray(axis, u, v, rho1, s1);
+            if (lvl2) {
+                d3 u2, v2;
+                basis(dt, &u2, &v2);
+                dt = subray(dt, u2, v2, rho2, s2);
+            }
+            ok = follow<LDS>(S, L, tx, dt, rx, c.order, c.face, delta, &F, nullptr, nullptr, err);
+        }
+        const double myD = ok ? F.D : 0.0, myL = ok ? F.Llast : 0.0;
+        // first level: argmin over lanes (s1, 7)
+        double k1 = (lvl1 && ok) ? F.tan_err : INFINITY;
+        int b1 = (lvl1 && ok) ? s1 : 8;
+#pragma unroll
+        for (int off = 8; off < 64; off <<= 1) {
+            double ot = __shfl_xor(k1, off);
+            int ob = __shfl_xor(b1, off);
+            if (ot < k1 || (ot == k1 && ob < b1)) {
+                k1 = ot;
+                b1 = ob;
+            }
+        }
+        k1 = __shfl(k1, 7);
+        b1 = __shfl(b1, 7);
+        if (b1 >= 8) {
+            flags |= SBR_PATH_STALLED;
+            break;
+        }
+        double wD = __shfl(myD, b1 * 8 + 7), wL = __shfl(myL, b1 * 8 + 7);
+        axis = subray(axis, u, v, rho1, b1);
+        tan = k1;
+        iters = i;
+        rho = rho1;
+        if (A.tan_tgt > 0.0 && target_met(k1, A.tan_tgt, wD, wL)) {
+            flags |= SBR_PATH_TARGET_MET;
+            break;
+        }
+        if (!two) break;
+        // second level: argmin over lanes (b1, s2)
+        double k2 = (lvl2 && ok && s1 == b1) ? F.tan_err : INFINITY;
+        int b2 = (lvl2 && ok && s1 == b1) ? s2 : 8;
+#pragma unroll
+        for (int off = 1; off < 8; off <<= 1) {
+            double ot = __shfl_xor(k2, off);
+            int ob = __shfl_xor(b2, off);
+            if (ot < k2 || (ot == k2 && ob < b2)) {
+                k2 = ot;
+                b2 = ob;
+            }
+        }
+        k2 = __shfl(k2, b1 * 8);
+        b2 = __shfl(b2, b1 * 8);
+        if (b2 >= 8) {
+            flags |= SBR_PATH_STALLED;
+            break;
+        }
+        wD = __shfl(myD, b1 * 8 + b2);
+        wL = __shfl(myL, b1 * 8 + b2);
+        basis(axis, &u, &v);
+        axis = subray(axis, u, v, rho2, b2);
+        tan = k2;
+        iters = i + 1;
+        rho = rho2;
+        if (A.tan_tgt > 0.0 && target_met(k2, A.tan_tgt, wD, wL)) {
+            flags |= SBR_PATH_TARGET_MET;
+            break;
+        }
+    }
+    if (lane == 0) {
+        RefineOut o;
+        st3(o.axis, axis);
+        o.tan_err = tan;
+        o.iters = iters;
+        o.flags = flags;
+        out[p] = o;
+    }
+}
+
+hipError_t launch_refine(const SceneDev& S, const LdsPlan& L, const GridDev& g,
+                         const RefineArgs& A, const sbr_candidate* uniq, int64_t U,
+                         RefineOut* out, float delta, int32_t* err, hipStream_t s)
+{
+    if (U <= 0) return hipSuccess;
+    // Few paths: the hardware is mostly idle, so spend 64 lanes per path on
+    // the two-iteration lookahead; many paths: 8 lanes per path.
+    const bool la = U <= A.lookahead_max_paths && A.iterations >= 2;
+    int64_t threads = U * (la ? 64 : 8);
+    dim3 grid((unsigned)((threads + L.block - 1) / L.block));
+    if (la && L.bytes > 0)
+        hipLaunchKernelGGL(k_refine_la<true>, grid, dim3(L.block), L.bytes, s, S, L, g, A, delta,
+                           uniq, U, out, err);
+    else if (la)
+        hipLaunchKernelGGL(k_refine_la<false>, grid, dim3(L.block), 0, s, S, L, g, A, delta, uniq,
+                           U, out, err);
+    else if (L.bytes > 0)
+        hipLaunchKernelGGL(k_refine<true>, grid, dim3(L.block), L.bytes, s, S, L, g, A, delta,
+                           uniq, U, out, err);
+    else
+        hipLaunchKernelGGL(k_refine<false>, grid, dim3(L.block), 0, s, S, L, g, A, delta, uniq, U,
+                           out, err);
+    return hipGetLastError();
+}
+
+// ===========================================================================
+// Path quantities, path test 2 and power (Sec. III.A, Sec. IV)
+// ===========================================================================
+struct cx {
+    double re, im;
+};
+__device__ static inline cx cadd(cx a, cx b) { return cx{a.re + b.re, a.im + b.im}; }
+__device__ static inline cx csub(cx a, cx b) { return cx{a.re - b.re, a.im - b.im}; }
+__device__ static inline cx cmulr(cx a, double r) { return cx{a.re * r, a.im * r}; }
+__device__ static inline cx cdiv(cx a, cx b)
+{
+    double den = b.re * b.re + b.im * b.im;
+    return cx{(a.re * b.re + a.im * b.im) / den, (a.im * b.re - a.re * b.im) / den};
+}
+__device__ static inline double cabs2(cx a) { return a.re * a.re + a.im * a.im; }
+// principal square root
+__device__ static inline cx csqrt_p(cx z)
+{
+    double r = hypot(z.re, z.im);
+    if (r == 0.0) return cx{0.0, 0.0};
+    if (z.re >= 0.0) {
+        double t = sqrt(0.5 * (r + z.re));
+        return cx{t, z.im / (2.0 * t)};
+    }
+    double t = sqrt(0.5 * (r - z.re));
+    return cx{fabs(z.im) / (2.0 * t), copysign(t, z.im)};
+}
+
+// Fresnel reflection for relative permittivity er at incidence cosine c:
+//   G_perp = (c - sqrt(er - s^2)) / (c + sqrt(er - s^2)),
+//   G_par  = (er c - sqrt(er - s^2)) / (er c + sqrt(er - s^2)),
+// and the unpolarized power reflectance 0.5 (|G_perp|^2 + |G_par|^2).
+__device__ static inline double fresnel_avg(double c, cx er)
+{
+    double s2 = 1.0 - c * c;
+    cx root = csqrt_p(csub(er, cx{s2, 0.0}));
+    cx cc = cx{c, 0.0};
+    cx gs = cdiv(csub(cc, root), cadd(cc, root));
+    cx erc = cmulr(er, c);
+    cx gp = cdiv(csub(erc, root), cadd(erc, root));
+    return 0.5 * (cabs2(gs) + cabs2(gp));
+}
+
+__device__ static inline double refl_at(const SceneDev& S, int32_t f, d3 din)
+{
+    d3 n = face_normal(S, f);
+    double c = fabs(dot(din, n)) / norm(din);
+    int32_t m = S.fmat[f];
+    return fresnel_avg(c, cx{S.eps[2 * m], S.eps[2 * m + 1]});
+}
+
+// P_r = P_t + 20 log10(lambda / (4 pi L)) + sum_j 10 log10(R_j)   [dBm]
+__device__ static inline double path_power(double ptx, double freq, double L, const double* refl,
+                                           int k)
+{
+    double lambda = kC0 / freq;
+    double p = ptx + 20.0 * log10(lambda / (4.0 * kPi * L));
+    for (int j = 0; j < k; ++j) p += 10.0 * log10(refl[j]);
+    return p;
+}
+
+// Point p inside face f: inside any of its triangles, barycentric tolerance 1e-9.
+template <bool LDS>
+__device__ static bool inside_face(const SceneDev& S, const LdsPlan& L, int32_t f, d3 p)
+{
+    const double tol = 1e-9;
+    for (int32_t q = S.fstart[f]; q < S.fstart[f + 1]; ++q) {
+        TriD T = tri_at<LDS>(S, L, S.ftris[q]);
+        d3 v0 = mk(T.v0x, T.v0y, T.v0z), e1 = mk(T.e1x, T.e1y, T.e1z), e2 = mk(T.e2x, T.e2y, T.e2z);
+        d3 w = sub(p, v0);
+        double d00 = dot(e1, e1);
+        double d01 = dot(e1, e2);
+        double d11 = dot(e2, e2);
+        double d20 = dot(w, e1);
+        double d21 = dot(w, e2);
+        double den = d00 * d11 - d01 * d01;
+        if (den == 0.0) continue;
+        double b = (d11 * d20 - d01 * d21) / den;
+        double gg = (d00 * d21 - d01 * d20) / den;
+        if (b >= -tol && gg >= -tol && b + gg <= 1.0 + tol) return true;
+    }
+    return false;
+}
+
+// Segment A -> B blocked by a triangle not of faces fa / fb, hit strictly
+// inside (1e-9, 1 - 1e-9) of the segment parameter.
+template <bool LDS>
+__device__ static bool blocked(const SceneDev& S, const LdsPlan& L, d3 A, d3 B, int32_t fa,
+                               int32_t fb, float delta, int32_t* err)
+{
+    HitRec h;
+    return traverse<true, false, LDS>(S, L, A, sub(B, A), fa, fb, 1e-9, 1.0 - 1e-9, delta, &h,
+                                      err) >= 0;
+}
+
+// Image-method points of a face sequence: images of Tx mirrored across the
+// face planes in order, then back-projection from Rx.  Returns false when a
+// back-projection parameter falls outside (0, 1) (first part of path test 2);
+// the points are computed either way.
+__device__ static bool image_points(const SceneDev& S, d3 tx, d3 rx, int k, const int32_t* faces,
+                                    d3* pts)
+{
+    d3 img[SBR_MAX_ORDER + 1];
+    img[0] = tx;
+    for (int j = 0; j < k; ++j) {
+        int32_t f = faces[j];
+        d3 n = face_normal(S, f);
+        double c = S.fplane[4 * (size_t)f + 3];
+        double dd = dot(n, img[j]) - c;
+        img[j + 1] = sub(img[j], scl(2.0 * dd, n));
+    }
+    bool ok = true;
+    d3 X = rx;
+    for (int j = k - 1; j >= 0; --j) {
+        int32_t f = faces[j];
+        d3 n = face_normal(S, f);
+        double c = S.fplane[4 * (size_t)f + 3];
+        d3 dir = sub(img[j + 1], X);
+        double den = dot(n, dir);
+        double s = (c - dot(n, X)) / den;
+        if (!(s > 0.0 && s < 1.0)) ok = false;
+        pts[j] = add(X, scl(s, dir));
+        X = pts[j];
+    }
+    return ok;
+}
+
+__device__ static inline double poly_length(d3 tx, const d3* p, int k, d3 rx)
+{
+    double L = 0.0;
+    d3 prev = tx;
+    for (int j = 0; j < k; ++j) {
+        L = L + norm(sub(p[j], prev));
+        prev = p[j];
+    }
+    L = L + norm(sub(rx, prev));
+    return L;
+}
+
+// Sixteen lanes per path.  Lane 0 replays the refined ray and forms the
+// refined quantities; lane 1 + j checks segment j of the image-method path
+// (reflection point j inside its face, segment j unobstructed), so path
+// test 2 costs one traversal of latency instead of k + 1.
+template <bool LDS>
+__global__ __launch_bounds__(256) void k_solve(SceneDev S, LdsPlan L, SolveArgs A, float delta,
+                                               const sbr_candidate* __restrict__ uniq,
+                                               const RefineOut* __restrict__ rf, int64_t U,
+                                               sbr_path* __restrict__ paths,
+                                               int32_t* __restrict__ keep,
+                                               int32_t* __restrict__ err)
+{
+    if (LDS) stage_scene(S, L);
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t p = gid >> 4;
+    int lane = (int)(gid & 15);
+    if (p >= U) return;
+    const sbr_candidate c = uniq[p];
+    const int k = c.order;
+    const d3 tx = mk(A.tx[0], A.tx[1], A.tx[2]);
+    const d3 rx = mk(A.rx[3 * c.rx], A.rx[3 * c.rx + 1], A.rx[3 * c.rx + 2]);
+    d3 ep[SBR_MAX_ORDER];
+    const bool geo_ok = image_points(S, tx, rx, k, c.face, ep);
+    bool bad = false;
+    if (geo_ok && lane >= 1 && lane <= k + 1) {
+        int j = lane - 1;
+        if (j < k && !inside_face<LDS>(S, L, c.face[j], ep[j])) {
+            bad = true;
+        } else {
+            d3 Pa = j == 0 ? tx : ep[j - 1];
+            d3 Pb = j < k ? ep[j] : rx;
+            int32_t fa = j == 0 ? -1 : c.face[j - 1];
+            int32_t fb = j < k ? c.face[j] : -1;
+            bad = blocked<LDS>(S, L, Pa, Pb, fa, fb, delta, err);
+        }
+    }
+    unsigned long long mask = __ballot(bad);
+    const int base = (int)(threadIdx.x & 63) & ~15;
+    const bool any_bad = ((mask >> base) & 0xffffull) != 0;
+    if (lane != 0) return;
+
+    const RefineOut R = rf[p];
+    d3 axis = ld3(R.axis);
+    d3 pts[SBR_MAX_ORDER], din[SBR_MAX_ORDER];
+    for (int j = 0; j < SBR_MAX_ORDER; ++j) {
+        pts[j] = mk(0.0, 0.0, 0.0);
+        din[j] = mk(0.0, 0.0, 0.0);
+    }
+    Follow F;
+    follow<LDS>(S, L, tx, axis, rx, k, c.face, delta, &F, pts, din, err);
+
+    sbr_path o;
+    o.rx = c.rx;
+    o.order = k;
+    for (int q = 0; q < SBR_MAX_ORDER; ++q) o.face[q] = c.face[q];
+    o.launch_ray = c.ray;
+    o.iters_used = R.iters;
+    o.flags = R.flags;
+    o.init_tan_err = c.tan_err;
+    o.tan_err = R.tan_err;
+    st3(o.axis, axis);
+    // refined path: Tx -> reflection points of the final ray -> Rx
+    double Lr = poly_length(tx, pts, k, rx);
+    o.length_m = Lr;
+    o.delay_s = Lr / kC0;
+    st3(o.aod, axis);
+    d3 last = k > 0 ? pts[k - 1] : tx;
+    st3(o.aoa, normalize(sub(last, rx)));
+    double refl[SBR_MAX_ORDER];
+    for (int j = 0; j < k; ++j) refl[j] = refl_at(S, c.face[j], din[j]);
+    o.power_dbm = path_power(A.tx_power_dbm, A.freq_hz, Lr, refl, k);
+    o.err_angle_deg = atan(R.tan_err) * (180.0 / kPi);
+    // exact path of the same faces
+    const bool ok = geo_ok && !any_bad;
+    double EL = poly_length(tx, ep, k, rx);
+    o.exact_length_m = EL;
+    o.exact_delay_s = EL / kC0;
+    d3 firstp = k > 0 ? ep[0] : rx;
+    st3(o.exact_aod, normalize(sub(firstp, tx)));
+    d3 elast = k > 0 ? ep[k - 1] : tx;
+    st3(o.exact_aoa, normalize(sub(elast, rx)));
+    d3 prev = tx;
+    for (int j = 0; j < k; ++j) {
+        refl[j] = refl_at(S, c.face[j], sub(ep[j], prev));
+        prev = ep[j];
+    }
+    o.exact_power_dbm = path_power(A.tx_power_dbm, A.freq_hz, EL, refl, k);
+    if (!ok) o.flags |= SBR_PATH_INVALID;
+    paths[p] = o;
+    keep[p] = (ok || A.keep_invalid) ? 1 : 0;
+}
+
+hipError_t launch_solve(const SceneDev& S, const LdsPlan& L, const SolveArgs& A,
+                        const sbr_candidate* uniq, const RefineOut* rf, int64_t U,
+                        sbr_path* paths, int32_t* keep, float delta, int32_t* err, hipStream_t s)
+{
+    if (U <= 0) return hipSuccess;
+    int64_t threads = U * 16;
+    dim3 grid((unsigned)((threads + L.block - 1) / L.block));
+    if (L.bytes > 0)
+        hipLaunchKernelGGL(k_solve<true>, grid, dim3(L.block), L.bytes, s, S, L, A, delta, uniq,
+                           rf, U, paths, keep, err);
+    else
+        hipLaunchKernelGGL(k_solve<false>, grid, dim3(L.block), 0, s, S, L, A, delta, uniq, rf, U,
+                           paths, keep, err);
+    return hipGetLastError();
+}
+
+hipError_t refine_set_lds_limit(int bytes)
+{
+    hipError_t e = hipFuncSetAttribute((const void*)k_refine<true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)k_refine_la<true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_solve<true>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+}  // namespace sbr

@@ -1,0 +1,287 @@
+// traverse.h -- BVH traversal with FP64 ray-triangle decisions, shared by the
+// trace, refinement and solve kernels.
+//
+// Memory plan per workgroup (dynamic LDS, see LdsPlan): the first n_nodes BVH
+// nodes (the top levels: nodes are numbered breadth-first), all triangles
+// when they fit, and a per-lane traversal stack of `depth` entries.  Deeper
+// nodes are read from global memory, and stack entries beyond `depth` spill
+// to a private array.
+//
+// Conservativeness.  The FP32 ray (o32, d32) differs from the FP64 ray by at
+// most 2^-24 (|o| + t|d|) per component at parameter t; for any point of the
+// scene this is below 3 * 2^-24 R, R = max(|Tx|, scene extent).  Each FP32
+// box already contains its triangles (outward rounding) and is widened by
+// delta = 2^-20 R > 3 * 2^-24 R plus the rounding of the widening itself, so
+// the FP32 ray passes through the widened box wherever the FP64 ray passes
+// through the true box.  The slab arithmetic then errs by a few ulp in t,
+// covered by the factor 1 + 2^-20 on the exit and pruning bounds.  Culling
+// therefore never removes a triangle that the FP64 test would accept.
+#pragma once
+#include <math.h>
+
+#include "geom.h"
+#include "internal.h"
+
+namespace sbr {
+
+extern __shared__ float4 g_smem4[];
+
+// Copy the staged part of the scene into LDS (every thread of the block must
+// call this before any traversal).
+__device__ static inline void stage_scene(const SceneDev& S, const LdsPlan& L)
+{
+    const float4* sn = (const float4*)S.nodes;
+    for (int i = threadIdx.x; i < 4 * L.n_nodes; i += blockDim.x) g_smem4[i] = sn[i];
+    const float4* st = (const float4*)S.tris;
+    float4* dt = g_smem4 + 4 * L.n_nodes;
+    for (int i = threadIdx.x; i < 5 * L.n_tris; i += blockDim.x) dt[i] = st[i];
+    __syncthreads();
+}
+
+// Moller-Trumbore in exactly this order:
+//   p = d x e2, det = e1.p (0: miss), s = o - v0, u = (s.p)/det,
+//   q = s x e1, v = (d.q)/det, t = (e2.q)/det,
+//   hit iff u >= 0, v >= 0, u + v <= 1 and t_lo < t < t_hi.
+__device__ static inline bool mt_hit(const TriD& T, d3 o, d3 d, double t_lo, double t_hi,
+                                     double* t_out)
+{
+    d3 e1 = mk(T.e1x, T.e1y, T.e1z), e2 = mk(T.e2x, T.e2y, T.e2z);
+    d3 p = cross(d, e2);
+    double det = dot(e1, p);
+    if (det == 0.0) return false;
+    d3 s = sub(o, mk(T.v0x, T.v0y, T.v0z));
+    double u = dot(s, p) / det;
+    if (!(u >= 0.0)) return false;
+    d3 q = cross(s, e1);
+    double v = dot(d, q) / det;
+    if (!(v >= 0.0) || !(u + v <= 1.0)) return false;
+    double t = dot(e2, q) / det;
+    if (t > t_lo && t < t_hi) {
+        *t_out = t;
+        return true;
+    }
+    return false;
+}
+
+__device__ static inline TriD unpack_tri(float4 fa, float4 fb, float4 fc, float4 fd, float4 fe)
+{
+    double2 a = __builtin_bit_cast(double2, fa), b = __builtin_bit_cast(double2, fb),
+            c = __builtin_bit_cast(double2, fc), d = __builtin_bit_cast(double2, fd),
+            e = __builtin_bit_cast(double2, fe);
+    TriD T;
+    T.v0x = a.x; T.v0y = a.y; T.v0z = b.x; T.e1x = b.y; T.e1y = c.x;
+    T.e1z = c.y; T.e2x = d.x; T.e2y = d.y; T.e2z = e.x;
+    int2 fi = __builtin_bit_cast(int2, e.y);
+    T.face = fi.x;
+    T.orig = fi.y;
+    return T;
+}
+
+// Triangle i (leaf order), from LDS when staged (LDS instances only).
+template <bool LDS>
+__device__ static inline TriD tri_at(const SceneDev& S, const LdsPlan& L, int32_t i)
+{
+    if (LDS && i < L.n_tris) {
+        const float4* q = g_smem4 + 4 * L.n_nodes + 5 * i;
+        return unpack_tri(q[0], q[1], q[2], q[3], q[4]);
+    }
+    const float4* q = (const float4*)(S.tris + i);
+    return unpack_tri(q[0], q[1], q[2], q[3], q[4]);
+}
+
+struct HitRec {
+    double t;
+    int32_t pos, face, orig;
+};
+
+struct Tally {
+    uint32_t nodes, tris;
+};
+
+// Closest hit (ANY = false: smallest t; equal t -> lower face id -> lower
+// input index) or any hit (ANY = true) of the ray o + t d, t_lo < t < t_hi,
+// ignoring triangles of faces xa and xb.  Returns the leaf-order position of
+// the hit or -1.  LDS = false reads everything from global memory and keeps
+// the stack in private memory (no LDS plan needed).
+template <bool ANY, bool COUNT, bool LDS>
+__device__ static int32_t traverse(const SceneDev& S, const LdsPlan& L, d3 o, d3 d, int32_t xa,
+                                   int32_t xb, double t_lo, double t_hi, float delta, HitRec* h,
+                                   int32_t* err, Tally* tally = nullptr)
+{
+    const float slack = 1.0f + 9.5367431640625e-07f;  // 1 + 2^-20
+    float ox = (float)o.x, oy = (float)o.y, oz = (float)o.z;
+    float dx = (float)d.x, dy = (float)d.y, dz = (float)d.z;
+    dx = dx >= 0.0f ? fmaxf(dx, 1e-20f) : fminf(dx, -1e-20f);
+    dy = dy >= 0.0f ? fmaxf(dy, 1e-20f) : fminf(dy, -1e-20f);
+    dz = dz >= 0.0f ? fmaxf(dz, 1e-20f) : fminf(dz, -1e-20f);
+    const float ix = 1.0f / dx, iy = 1.0f / dy, iz = 1.0f / dz;
+    // lo - delta - o = lo - (o + delta);  hi + delta - o = hi - (o - delta)
+    const float lx = ox + delta, ly = oy + delta, lz = oz + delta;
+    const float hx = ox - delta, hy = oy - delta, hz = oz - delta;
+
+    h->pos = -1;
+    h->t = INFINITY;
+    h->face = 0x7fffffff;
+    h->orig = 0x7fffffff;
+    float tb = isinf(t_hi) ? INFINITY : (float)t_hi * slack;
+
+    int32_t* lst = LDS ? (int32_t*)(g_smem4) + (L.stack_off >> 2) + threadIdx.x : nullptr;
+    const int bd = blockDim.x;
+    const int ldepth = LDS ? L.depth : 0;
+    int32_t ost[kTraceStack];
+    int sp = 0;
+    int32_t node = 0;
+    for (;;) {
+        float4 a, b, c, mf;
+        if (LDS && node < L.n_nodes) {
+            const float4* np = g_smem4 + 4 * node;
+            a = np[0]; b = np[1]; c = np[2]; mf = np[3];
+        } else {
+            const float4* np = (const float4*)(S.nodes + node);
+            a = np[0]; b = np[1]; c = np[2]; mf = np[3];
+        }
+        const int4 m = __builtin_bit_cast(int4, mf);
+        if (COUNT) tally->nodes += 1;
+        // child 0: lo (a.x a.y a.z) hi (a.w b.x b.y); child 1: lo (b.z b.w c.x) hi (c.y c.z c.w)
+        float t0x = (a.x - lx) * ix, t1x = (a.w - hx) * ix;
+        float t0y = (a.y - ly) * iy, t1y = (b.x - hy) * iy;
+        float t0z = (a.z - lz) * iz, t1z = (b.y - hz) * iz;
+        float tn0 = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fminf(t0z, t1z));
+        float tf0 = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)) * slack;
+        float u0x = (b.z - lx) * ix, u1x = (c.y - hx) * ix;
+        float u0y = (b.w - ly) * iy, u1y = (c.z - hy) * iy;
+        float u0z = (c.x - lz) * iz, u1z = (c.w - hz) * iz;
+        float tn1 = fmaxf(fmaxf(fminf(u0x, u1x), fminf(u0y, u1y)), fminf(u0z, u1z));
+        float tf1 = fminf(fminf(fmaxf(u0x, u1x), fmaxf(u0y, u1y)), fmaxf(u0z, u1z)) * slack;
+        bool hit0 = m.z >= 0 && tn0 <= tf0 && tf0 >= 0.0f && tn0 <= tb;
+        bool hit1 = m.w >= 0 && tn1 <= tf1 && tf1 >= 0.0f && tn1 <= tb;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            bool hl = side == 0 ? (hit0 && m.z > 0) : (hit1 && m.w > 0);
+            if (!hl) continue;
+            int32_t first = side == 0 ? m.x : m.y;
+            int32_t cnt = side == 0 ? m.z : m.w;
+            for (int32_t i = first; i < first + cnt; ++i) {
+                TriD T = tri_at<LDS>(S, L, i);
+                if (COUNT) tally->tris += 1;
+                if (T.face == xa || T.face == xb) continue;
+                double t;
+                if (!mt_hit(T, o, d, t_lo, t_hi, &t)) continue;
+                if (ANY) {
+                    h->pos = i;
+                    h->t = t;
+                    h->face = T.face;
+                    h->orig = T.orig;
+                    return i;
+                }
+                bool better = h->pos < 0 || t < h->t ||
+                              (t == h->t && (T.face < h->face ||
+                                             (T.face == h->face && T.orig < h->orig)));
+                if (better) {
+                    h->pos = i;
+                    h->t = t;
+                    h->face = T.face;
+                    h->orig = T.orig;
+                    tb = (float)t * slack;
+                    if ((double)tb < t) tb = nextafterf(tb, INFINITY);
+                }
+            }
+        }
+        bool go0 = hit0 && m.z == 0 && tn0 <= tb;
+        bool go1 = hit1 && m.w == 0 && tn1 <= tb;
+        if (go0 && go1) {
+            bool first0 = tn0 <= tn1;
+            int32_t nearc = first0 ? m.x : m.y, farc = first0 ? m.y : m.x;
+            if (sp >= kTraceStack) {
+                atomicOr(err, 1);
+                return h->pos;
+            }
+            if (LDS && sp < ldepth) lst[sp * bd] = farc;
+            else ost[sp - ldepth] = farc;
+            ++sp;
+            node = nearc;
+        } else if (go0) {
+            node = m.x;
+        } else if (go1) {
+            node = m.y;
+        } else {
+            if (sp == 0) break;
+            --sp;
+            node = (LDS && sp < ldepth) ? lst[sp * bd] : ost[sp - ldepth];
+        }
+    }
+    return h->pos;
+}
+
+__device__ static inline d3 face_normal(const SceneDev& S, int32_t f)
+{
+    const double* p = S.fplane + 4 * (size_t)f;
+    return mk(p[0], p[1], p[2]);
+}
+
+// Reception test and error angle (eq. (3)) of one segment (origin o,
+// direction d, unfolded length D at o, next hit at t) for one Rx.  The foot
+// of the perpendicular is at t* = (Rx - o).d; accepted iff 0 < t* <= t and,
+// with thl >= 0, Rx lies inside the ray cone d_perp <= thl (D + t*).  The
+// error angle's tangent is d_perp / (D + t*): the distance to Rx over the
+// propagation distance of the ray.
+__device__ static inline bool capture(d3 o, d3 d, double D, double t, d3 rx, double thl,
+                                      double* tan_out)
+{
+    d3 w = sub(rx, o);
+    double ts = dot(w, d);
+    if (!(ts > 0.0)) return false;
+    if (!(ts <= t)) return false;
+    d3 f = sub(w, scl(ts, d));
+    double dp = norm(f);
+    double L = D + ts;
+    if (thl >= 0.0 && !(dp <= thl * L)) return false;
+    *tan_out = dp / L;
+    return true;
+}
+
+struct Follow {
+    double tan_err, D, Llast;
+};
+
+// Trace direction d0 from Tx through exactly the faces of a path of order k
+// and report the error angle of Rx on the last segment (no cone condition).
+// A sub-ray is a usable path only if it meets the same faces in the same
+// order and Rx lies ahead on its last segment before the next obstacle.
+// With pts/din non-NULL the reflection points and incoming directions are
+// stored.
+template <bool LDS>
+__device__ static bool follow(const SceneDev& S, const LdsPlan& L, d3 tx, d3 d0, d3 rx, int k,
+                              const int32_t* faces, float delta, Follow* F, d3* pts, d3* din,
+                              int32_t* err)
+{
+    d3 o = tx, d = d0;
+    double D = 0.0;
+    int32_t prev = -1;
+    for (int j = 0;; ++j) {
+        HitRec h;
+        int32_t hit =
+            traverse<false, false, LDS>(S, L, o, d, prev, prev, S.t_eps, INFINITY, delta, &h, err);
+        if (j == k) {
+            double t = hit < 0 ? INFINITY : h.t;
+            double tn;
+            if (!capture(o, d, D, t, rx, -1.0, &tn)) return false;
+            F->tan_err = tn;
+            F->D = D;
+            F->Llast = norm(sub(rx, o));
+            return true;
+        }
+        if (hit < 0 || h.face != faces[j]) return false;
+        d3 nf = face_normal(S, h.face);
+        d3 on = add(o, scl(h.t, d));
+        if (din) din[j] = d;
+        double k2 = 2.0 * dot(d, nf);
+        d = sub(d, scl(k2, nf));
+        D = D + h.t;
+        o = on;
+        if (pts) pts[j] = on;
+        prev = h.face;
+    }
+}
+
+}  // namespace sbr

@@ -73,11 +73,12 @@ class TraceStats(C.Structure):
         ("ms_launch", C.c_double), ("ms_trace", C.c_double), ("ms_dedup", C.c_double),
         ("ms_refine", C.c_double), ("ms_solve", C.c_double), ("ms_emit", C.c_double),
         ("ms_total", C.c_double),
-        ("reserved", C.c_int64 * 4),
+        ("lds_bytes", C.c_int64), ("lds_nodes", C.c_int64), ("lds_tris", C.c_int64),
+        ("lds_max", C.c_int64),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 PATH_DTYPE = np.dtype([

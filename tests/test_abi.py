@@ -124,3 +124,22 @@ def test_scene_generators_are_seeded():
     assert np.array_equal(a["rx"], b["rx"])
     assert len(a["scene"]["tri"]) == 770
     assert len(scenes.shoebox_config(0)["scene"]["tri"]) == 12
+
+
+def test_factorial_table_is_exact_double_double():
+    """The library's 1/k! literals (used by its correctly rounded sin/acos) are
+    the double-double split of the exact rationals: hi = 1/k! rounded to
+    nearest, lo = (1/k! - hi) rounded to nearest."""
+    import math
+    from fractions import Fraction
+    src = open(os.path.join(ROOT, "paper_2208_10009_amd", "csrc", "geom.h")).read()
+    body = src[src.index("kInvFact[kFactN] = {"):]
+    body = body[:body.index("};")]
+    pairs = re.findall(r"\{([^,{}]+),\s*([^,{}]+)\}", body)
+    assert len(pairs) == 36
+    for k, (hi_s, lo_s) in enumerate(pairs):
+        hi = float.fromhex(hi_s.strip()) if "0x" in hi_s else float(hi_s)
+        lo = float.fromhex(lo_s.strip()) if "0x" in lo_s else float(lo_s)
+        x = Fraction(1, math.factorial(k))
+        assert hi == float(x), k
+        assert lo == float(x - Fraction(hi)), k

@@ -285,3 +285,52 @@ def test_deterministic_reruns(gpu):
     finally:
         sc.close()
     assert a.tobytes() == b.tobytes()
+
+
+def _trace_with_env(env, cfg, **prm):
+    import os
+    from paper_2208_10009_amd import sbr
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        ctx = sbr.Context(0)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    try:
+        sc = ctx.scene(cfg["scene"])
+        p, _ = sc.trace(cfg["tx"], cfg["rx"], **prm)
+        sc.close()
+    finally:
+        ctx.close()
+    return p
+
+
+@pytest.mark.parametrize("prm", [dict(iterations=5, subrays=7), dict(iterations=4, subrays=6),
+                                 dict(iterations=9, subrays=7, target_err_deg=0.01)])
+def test_refine_lookahead_matches_single_step(gpu, orc, prm):
+    """The two-iteration lookahead kernel (64 lanes per path) and the
+    one-iteration kernel (8 lanes per path) give byte-identical paths, and
+    both match the oracle."""
+    cfg = scenes.manhattan_config(2, n_rx=24)
+    full = dict(cfg["params"], division_n=80, **prm)
+    a = _trace_with_env({"SBR_LOOKAHEAD_PATHS": "0"}, cfg, **full)
+    b = _trace_with_env({"SBR_LOOKAHEAD_PATHS": "100000"}, cfg, **full)
+    assert a.tobytes() == b.tobytes()
+    o = orc.run(cfg["scene"], cfg["tx"], cfg["rx"], **full)["paths"]
+    _compare_paths(a, o)
+
+
+def test_lds_staged_traversal_matches(gpu, orc):
+    """LDS-staged traversal (node prefix, triangles and stack in LDS) gives
+    the same paths as global-memory traversal."""
+    cfg = scenes.manhattan_config(3, n_rx=16)
+    prm = dict(cfg["params"], division_n=80)
+    a = _trace_with_env({"SBR_LDS_BUDGET": "0"}, cfg, **prm)
+    b = _trace_with_env({"SBR_LDS_BUDGET": "65536", "SBR_STACK_DEPTH": "4"}, cfg, **prm)
+    c = _trace_with_env({"SBR_LDS_BUDGET": "163840", "SBR_TRACE_BLOCK": "512"}, cfg, **prm)
+    assert a.tobytes() == b.tobytes() == c.tobytes()
+    _compare_paths(a, orc.run(cfg["scene"], cfg["tx"], cfg["rx"], **prm)["paths"])
