@@ -62,8 +62,10 @@ struct sbr_context {
     int32_t n_scenes = 0;
     std::map<int32_t, DevBuf> grids;  // division n -> [3][N] FP64 directions
     DevBuf grid_scratch, rx, cand, idx, flags, offs, scan, uniq, refine, paths, keep, outp,
-        counters, rays_tri, rays_t, tally;
+        counters, rays_tri, rays_t, tally, geom;
     Counters* host_ctr = nullptr;  // pinned
+    sbr_path* host_paths = nullptr;  // pinned staging of the path list
+    int64_t host_paths_cap = 0;
     hipEvent_t ev[8] = {};
     // LDS staging of the traversal kernels: budget per block (0 = traverse
     // from global memory with a private stack), lanes per block of the trace
@@ -231,6 +233,7 @@ sbr_status check_scene(sbr_scene* s)
 // permutation), flags/offs and uniq (n_uniq unique paths).
 struct Front {
     int64_t n_cand = 0, n_uniq = 0, N = 0;
+    bool small = false;  // path test 1 ran in one workgroup; n_uniq is on the device
     GridDev g;
     TraceArgs ta;
     LdsPlan lp;
@@ -291,6 +294,15 @@ sbr_status run_front(sbr_scene* s, const double* tx, const double* rx, int32_t n
 
     // sort + path test 1
     int64_t C = fr->n_cand;
+    if (need_unique && C <= kSmallEvents) {
+        HIPCHK(c, ensure(c->uniq, sizeof(sbr_candidate) * (size_t)std::max<int64_t>(C, 1)));
+        HIPCHK(c, launch_dedup_small(c->cand.as<sbr_candidate>(), C, c->uniq.as<sbr_candidate>(),
+                                     &c->counters.as<Counters>()->n_unique, st));
+        fr->small = true;
+        fr->n_uniq = -1;
+        HIPCHK(c, hipEventRecord(c->ev[3], st));
+        return SBR_OK;
+    }
     int64_t P2 = pow2_at_least(C);
     HIPCHK(c, ensure(c->idx, sizeof(uint32_t) * (size_t)P2));
     HIPCHK(c, launch_sort_candidates(c->cand.as<sbr_candidate>(), C, c->idx.as<uint32_t>(), st));
@@ -311,8 +323,17 @@ sbr_status run_front(sbr_scene* s, const double* tx, const double* rx, int32_t n
                                        c->uniq.as<sbr_candidate>(), st));
     }
     HIPCHK(c, hipEventRecord(c->ev[3], st));
-    HIPCHK(c, hipEventSynchronize(c->ev[3]));
-    HIPCHK(c, hipEventElapsedTime(&fr->ms_dedup, c->ev[2], c->ev[3]));
+    return SBR_OK;
+}
+
+sbr_status ensure_host_paths(sbr_context* c, int64_t n)
+{
+    if (n <= c->host_paths_cap) return SBR_OK;
+    if (c->host_paths) (void)hipHostFree(c->host_paths);
+    c->host_paths = nullptr;
+    c->host_paths_cap = 0;
+    HIPCHK(c, hipHostMalloc((void**)&c->host_paths, sizeof(sbr_path) * (size_t)n, 0));
+    c->host_paths_cap = n;
     return SBR_OK;
 }
 
@@ -428,11 +449,13 @@ sbr_status sbr_context_destroy(sbr_context* c)
     for (auto& kv : c->grids) release(kv.second);
     DevBuf* bufs[] = {&c->grid_scratch, &c->rx,    &c->cand,  &c->idx,  &c->flags,
                       &c->offs,         &c->scan,  &c->uniq,  &c->refine, &c->paths,
-                      &c->keep,         &c->outp,  &c->counters, &c->rays_tri, &c->rays_t, &c->tally};
+                      &c->keep,         &c->outp,  &c->counters, &c->rays_tri, &c->rays_t, &c->tally,
+                      &c->geom};
     for (DevBuf* b : bufs) release(*b);
     for (auto& ev : c->ev)
         if (ev) (void)hipEventDestroy(ev);
     if (c->host_ctr) (void)hipHostFree(c->host_ctr);
+    if (c->host_paths) (void)hipHostFree(c->host_paths);
     delete c;
     return SBR_OK;
 }
@@ -739,7 +762,10 @@ sbr_status sbr_trace(sbr_scene* s, const double tx[3], const double* rx, int32_t
     Front fr;
     r = run_front(s, tx, rx, n_rx, p, true, &fr);
     if (r) return r;
-    const int64_t U = fr.n_uniq;
+    // U_max bounds the number of unique paths; with the one-workgroup path
+    // test 1 the exact count stays on the device and the kernels read it.
+    const int64_t Umax = fr.small ? fr.n_cand : fr.n_uniq;
+    const int32_t* ndev = fr.small ? &c->counters.as<Counters>()->n_unique : nullptr;
     SceneDev S = scene_dev(s);
     Counters* hc = c->host_ctr;
 
@@ -752,10 +778,12 @@ sbr_status sbr_trace(sbr_scene* s, const double tx[3], const double* rx, int32_t
     ra.iterations = p->iterations;
     ra.subrays = p->subrays;
     ra.lookahead_max_paths = c->lookahead_max_paths;
-    HIPCHK(c, ensure(c->refine, sizeof(RefineOut) * (size_t)std::max<int64_t>(U, 1)));
+    const size_t U1 = (size_t)std::max<int64_t>(Umax, 1);
+    HIPCHK(c, ensure(c->refine, sizeof(RefineOut) * U1));
+    HIPCHK(c, ensure(c->geom, sizeof(PathGeom) * U1));
     const LdsPlan lp256 = plan_for(s, 256);
-    HIPCHK(c, launch_refine(S, lp256, fr.g, ra, c->uniq.as<sbr_candidate>(), U,
-                            c->refine.as<RefineOut>(), fr.ta.delta,
+    HIPCHK(c, launch_refine(S, lp256, fr.g, ra, c->uniq.as<sbr_candidate>(), Umax, ndev,
+                            c->refine.as<RefineOut>(), c->geom.as<PathGeom>(), fr.ta.delta,
                             &c->counters.as<Counters>()->err, st));
     HIPCHK(c, hipEventRecord(c->ev[4], st));
 
@@ -766,48 +794,75 @@ sbr_status sbr_trace(sbr_scene* s, const double tx[3], const double* rx, int32_t
     sa.freq_hz = p->freq_hz;
     sa.tx_power_dbm = p->tx_power_dbm;
     sa.keep_invalid = (p->flags & SBR_FLAG_KEEP_INVALID) ? 1 : 0;
-    HIPCHK(c, ensure(c->paths, sizeof(sbr_path) * (size_t)std::max<int64_t>(U, 1)));
-    HIPCHK(c, ensure(c->keep, sizeof(int32_t) * (size_t)std::max<int64_t>(U, 1)));
-    HIPCHK(c, ensure(c->offs, sizeof(int32_t) * (size_t)std::max<int64_t>(U, 1)));
-    HIPCHK(c, ensure(c->scan, scan_scratch_bytes(U)));
-    HIPCHK(c, launch_solve(S, lp256, sa, c->uniq.as<sbr_candidate>(), c->refine.as<RefineOut>(), U,
-                           c->paths.as<sbr_path>(), c->keep.as<int32_t>(), fr.ta.delta,
-                           &c->counters.as<Counters>()->err, st));
+    HIPCHK(c, ensure(c->paths, sizeof(sbr_path) * U1));
+    HIPCHK(c, ensure(c->keep, sizeof(int32_t) * U1));
+    HIPCHK(c, ensure(c->offs, sizeof(int32_t) * U1));
+    HIPCHK(c, ensure(c->scan, scan_scratch_bytes(Umax)));
+    HIPCHK(c, launch_solve(S, lp256, sa, c->uniq.as<sbr_candidate>(), c->refine.as<RefineOut>(),
+                           c->geom.as<const PathGeom>(), Umax, ndev, c->paths.as<sbr_path>(),
+                           c->keep.as<int32_t>(), fr.ta.delta, &c->counters.as<Counters>()->err,
+                           st));
     HIPCHK(c, hipEventRecord(c->ev[5], st));
 
     // emit: stable compaction of kept paths (already in canonical order)
-    HIPCHK(c, launch_scan(c->keep.as<int32_t>(), c->offs.as<int32_t>(), U,
-                          &c->counters.as<Counters>()->n_paths, c->scan.p, st));
-    HIPCHK(c, hipMemcpyAsync(hc, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipStreamSynchronize(st));
-    if (hc->err) return fail(c, SBR_E_INTERNAL, "traversal stack overflow");
-    const int64_t P = hc->n_paths;
-    *n_out = P;
-    if (P > capacity) {
-        return fail(c, SBR_E_CAPACITY, "%lld paths, capacity %lld", (long long)P, (long long)capacity);
-    }
-    HIPCHK(c, ensure(c->outp, sizeof(sbr_path) * (size_t)std::max<int64_t>(P, 1)));
-    HIPCHK(c, launch_compact_paths(c->paths.as<sbr_path>(), c->keep.as<int32_t>(),
-                                   c->offs.as<int32_t>(), U, c->outp.as<sbr_path>(), st));
-    if (P > 0)
-        HIPCHK(c, hipMemcpyAsync(out, c->outp.p, sizeof(sbr_path) * (size_t)P,
+    int64_t P = 0, U = fr.n_uniq;
+    if (fr.small) {
+        // one workgroup compacts; the list (at most Umax records) and the
+        // counts come back in one round trip
+        HIPCHK(c, ensure(c->outp, sizeof(sbr_path) * U1));
+        HIPCHK(c, launch_emit_small(c->paths.as<sbr_path>(), c->keep.as<int32_t>(), Umax, ndev,
+                                    c->outp.as<sbr_path>(), &c->counters.as<Counters>()->n_paths,
+                                    st));
+        r = ensure_host_paths(c, (int64_t)U1);
+        if (r) return r;
+        HIPCHK(c, hipMemcpyAsync(c->host_paths, c->outp.p, sizeof(sbr_path) * (size_t)Umax,
                                  hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipEventRecord(c->ev[6], st));
-    HIPCHK(c, hipEventSynchronize(c->ev[6]));
+        HIPCHK(c, hipMemcpyAsync(hc, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipEventRecord(c->ev[6], st));
+        HIPCHK(c, hipEventSynchronize(c->ev[6]));
+        if (hc->err) return fail(c, SBR_E_INTERNAL, "traversal stack overflow");
+        P = hc->n_paths;
+        U = hc->n_unique;
+        *n_out = P;
+        if (P > capacity)
+            return fail(c, SBR_E_CAPACITY, "%lld paths, capacity %lld", (long long)P,
+                        (long long)capacity);
+        if (P > 0) memcpy(out, c->host_paths, sizeof(sbr_path) * (size_t)P);
+    } else {
+        HIPCHK(c, launch_scan(c->keep.as<int32_t>(), c->offs.as<int32_t>(), U,
+                              &c->counters.as<Counters>()->n_paths, c->scan.p, st));
+        HIPCHK(c, hipMemcpyAsync(hc, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        if (hc->err) return fail(c, SBR_E_INTERNAL, "traversal stack overflow");
+        P = hc->n_paths;
+        *n_out = P;
+        if (P > capacity)
+            return fail(c, SBR_E_CAPACITY, "%lld paths, capacity %lld", (long long)P,
+                        (long long)capacity);
+        HIPCHK(c, ensure(c->outp, sizeof(sbr_path) * (size_t)std::max<int64_t>(P, 1)));
+        HIPCHK(c, launch_compact_paths(c->paths.as<sbr_path>(), c->keep.as<int32_t>(),
+                                       c->offs.as<int32_t>(), U, c->outp.as<sbr_path>(), st));
+        if (P > 0)
+            HIPCHK(c, hipMemcpyAsync(out, c->outp.p, sizeof(sbr_path) * (size_t)P,
+                                     hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipEventRecord(c->ev[6], st));
+        HIPCHK(c, hipEventSynchronize(c->ev[6]));
+    }
     if (stats) {
         memset(stats, 0, sizeof(*stats));
         stats->n_rays = fr.N;
         stats->n_candidates = fr.n_cand;
         stats->n_unique = U;
         stats->n_paths = P;
-        float a = 0, b = 0, e = 0, tot = 0;
+        float a = 0, b = 0, e = 0, tot = 0, dd = 0;
+        (void)hipEventElapsedTime(&dd, c->ev[2], c->ev[3]);
         (void)hipEventElapsedTime(&a, c->ev[3], c->ev[4]);
         (void)hipEventElapsedTime(&b, c->ev[4], c->ev[5]);
         (void)hipEventElapsedTime(&e, c->ev[5], c->ev[6]);
         (void)hipEventElapsedTime(&tot, c->ev[0], c->ev[6]);
         stats->ms_launch = fr.ms_launch;
         stats->ms_trace = fr.ms_trace;
-        stats->ms_dedup = fr.ms_dedup;
+        stats->ms_dedup = dd;
         stats->ms_refine = a;
         stats->ms_solve = b;
         stats->ms_emit = e;

@@ -118,6 +118,13 @@ hipError_t launch_gather_unique(const sbr_candidate* cand, const uint32_t* idx,
                                 const int32_t* flags, const int32_t* offs, int64_t n,
                                 sbr_candidate* uniq, hipStream_t s);
 
+// Reflection points and incoming directions of a path's reported ray, stored
+// by the refinement for the winning sub-ray (valid when iterations > 0).
+struct PathGeom {
+    d3 pts[SBR_MAX_ORDER];
+    d3 din[SBR_MAX_ORDER];
+};
+
 // Per-path state after the precise algorithm.
 struct RefineOut {
     double axis[3];
@@ -135,9 +142,11 @@ struct RefineArgs {
     int64_t lookahead_max_paths;  // up to this many paths: two-iteration lookahead
 };
 
+// U_max paths (the first min(U_max, *n_dev) when n_dev is non-NULL).
 hipError_t launch_refine(const SceneDev& S, const LdsPlan& L, const GridDev& g,
-                         const RefineArgs& A, const sbr_candidate* uniq, int64_t U,
-                         RefineOut* out, float delta, int32_t* err, hipStream_t s);
+                         const RefineArgs& A, const sbr_candidate* uniq, int64_t U_max,
+                         const int32_t* n_dev, RefineOut* out, PathGeom* geom, float delta,
+                         int32_t* err, hipStream_t s);
 
 struct SolveArgs {
     double tx[3];
@@ -147,13 +156,23 @@ struct SolveArgs {
 };
 
 hipError_t launch_solve(const SceneDev& S, const LdsPlan& L, const SolveArgs& A,
-                        const sbr_candidate* uniq, const RefineOut* rf, int64_t U,
-                        sbr_path* paths, int32_t* keep, float delta, int32_t* err, hipStream_t s);
+                        const sbr_candidate* uniq, const RefineOut* rf, const PathGeom* geom,
+                        int64_t U_max, const int32_t* n_dev, sbr_path* paths, int32_t* keep,
+                        float delta, int32_t* err, hipStream_t s);
 
 hipError_t launch_compact_paths(const sbr_path* paths, const int32_t* keep, const int32_t* offs,
                                 int64_t U, sbr_path* out, hipStream_t s);
 
 hipError_t launch_gather_sorted(const sbr_candidate* cand, const uint32_t* idx, int64_t n,
                                 sbr_candidate* out, hipStream_t s);
+
+// Up to kSmallEvents reception events, path test 1 and the final compaction
+// run in one workgroup each and leave their counts on the device.
+constexpr int kSmallEvents = 4096;
+hipError_t launch_dedup_small(const sbr_candidate* C, int64_t n, sbr_candidate* U,
+                              int32_t* n_unique, hipStream_t s);
+hipError_t launch_emit_small(const sbr_path* paths, const int32_t* keep, int64_t U_max,
+                             const int32_t* n_dev, sbr_path* out, int32_t* n_paths, hipStream_t s);
+
 
 }  // namespace sbr

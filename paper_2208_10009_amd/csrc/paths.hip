@@ -263,3 +263,111 @@ hipError_t launch_compact_paths(const sbr_path* paths, const int32_t* keep, cons
 }
 
 }  // namespace sbr
+
+namespace sbr {
+
+// ===========================================================================
+// Single-workgroup variants for up to kSmallEvents events: one launch each,
+// no host round trip in between (the counts stay on the device).
+// ===========================================================================
+// Sort (bitonic, in LDS), path test 1 (heads of equal keys) and compaction of
+// the winners, in sorted order; writes the number of unique paths to
+// *n_unique.
+__global__ __launch_bounds__(1024) void k_dedup_small(const sbr_candidate* __restrict__ C,
+                                                      int32_t n, sbr_candidate* __restrict__ U,
+                                                      int32_t* __restrict__ n_unique)
+{
+    __shared__ uint32_t idx[kSmallEvents];
+    __shared__ int32_t part[1024];
+    const int t = threadIdx.x;
+    int P = 1;
+    while (P < n) P <<= 1;
+    for (int i = t; i < P; i += 1024) idx[i] = i < n ? (uint32_t)i : 0xffffffffu;
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int q = t; q < P / 2; q += 1024) {
+                int i = 2 * q - (q & (j - 1));
+                int l = i + j;
+                bool asc = (i & k) == 0;
+                uint32_t a = idx[i], b = idx[l];
+                bool swap = asc ? cand_less(C, b, a) : cand_less(C, a, b);
+                if (swap) {
+                    idx[i] = b;
+                    idx[l] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    int h[4], sum = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int i = 4 * t + q;
+        h[q] = (i < n && (i == 0 || key_cmp(C[idx[i]], C[idx[i - 1]]) != 0)) ? 1 : 0;
+        sum += h[q];
+    }
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = part[t] - sum;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (h[q]) U[run++] = C[idx[4 * t + q]];
+    if (t == 1023) *n_unique = part[1023];
+}
+
+hipError_t launch_dedup_small(const sbr_candidate* C, int64_t n, sbr_candidate* U,
+                              int32_t* n_unique, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dedup_small, dim3(1), dim3(1024), 0, s, C, (int32_t)n, U, n_unique);
+    return hipGetLastError();
+}
+
+// Stable compaction of the kept paths (path test 2) of the first
+// min(U_max, *n_dev) records; writes the count to *n_paths.
+__global__ __launch_bounds__(1024) void k_emit_small(const sbr_path* __restrict__ paths,
+                                                     const int32_t* __restrict__ keep,
+                                                     int32_t U_max, const int32_t* __restrict__ n_dev,
+                                                     sbr_path* __restrict__ out,
+                                                     int32_t* __restrict__ n_paths)
+{
+    __shared__ int32_t part[1024];
+    const int t = threadIdx.x;
+    const int U = min(U_max, *n_dev);
+    int h[4], sum = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int i = 4 * t + q;
+        h[q] = (i < U && keep[i]) ? 1 : 0;
+        sum += h[q];
+    }
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = part[t] - sum;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (h[q]) out[run++] = paths[4 * t + q];
+    if (t == 1023) *n_paths = part[1023];
+}
+
+hipError_t launch_emit_small(const sbr_path* paths, const int32_t* keep, int64_t U_max,
+                             const int32_t* n_dev, sbr_path* out, int32_t* n_paths, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_emit_small, dim3(1), dim3(1024), 0, s, paths, keep, (int32_t)U_max, n_dev,
+                       out, n_paths);
+    return hipGetLastError();
+}
+
+}  // namespace sbr

@@ -59,6 +59,15 @@ __device__ static inline bool target_met(double tan_err, double tan_tgt, double 
     return tan_err <= thr;
 }
 
+// Reflection points and incoming directions of the winning sub-ray.
+__device__ static inline void store_geom(PathGeom* g, int k, const d3* pts, const d3* din)
+{
+    for (int j = 0; j < k; ++j) {
+        g->pts[j] = pts[j];
+        g->din[j] = din[j];
+    }
+}
+
 // Start of the precise algorithm for one path: the launch ray that won path
 // test 1 is the first axis.  Its error angle is the reception event's (the
 // event was produced by the same FP64 arithmetic as a replay), so without a
@@ -98,14 +107,17 @@ __device__ static inline RefineOut stalled_at_start(d3 axis)
 template <bool LDS>
 __global__ __launch_bounds__(256) void k_refine(SceneDev S, LdsPlan L, GridDev g, RefineArgs A,
                                                 float delta,
-                                                const sbr_candidate* __restrict__ uniq, int64_t U,
+                                                const sbr_candidate* __restrict__ uniq,
+                                                int64_t U_max, const int32_t* __restrict__ n_dev,
                                                 RefineOut* __restrict__ out,
+                                                PathGeom* __restrict__ geom,
                                                 int32_t* __restrict__ err)
 {
     if (LDS) stage_scene(S, L);
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t p = gid >> 3;
     int s = (int)(gid & 7);
+    const int64_t U = n_dev ? min(U_max, (int64_t)*n_dev) : U_max;
     if (p >= U) return;
     const sbr_candidate c = uniq[p];
     const d3 tx = mk(A.tx[0], A.tx[1], A.tx[2]);
@@ -126,9 +138,10 @@ __global__ __launch_bounds__(256) void k_refine(SceneDev S, LdsPlan L, GridDev g
         basis(axis, &u, &v);
         Follow F;
         bool ok = false;
+        d3 gp[SBR_MAX_ORDER], gd[SBR_MAX_ORDER];
         if (s < A.subrays)
             ok = follow<LDS>(S, L, tx, subray(axis, u, v, rho, s), rx, c.order, c.face, delta, &F,
-                             nullptr, nullptr, err);
+                             gp, gd, err);
         double bt = ok ? F.tan_err : INFINITY;
         int bs = ok ? s : 8;
         double myD = ok ? F.D : 0.0, myL = ok ? F.Llast : 0.0;
@@ -146,6 +159,8 @@ __global__ __launch_bounds__(256) void k_refine(SceneDev S, LdsPlan L, GridDev g
             break;
         }
         double wD = __shfl(myD, bs, 8), wL = __shfl(myL, bs, 8);
+        if (s == bs) store_geom(geom + p, c.order, gp, gd);
+        __threadfence_block();
         axis = subray(axis, u, v, rho, bs);
         tan = bt;
         iters = i;
@@ -175,7 +190,10 @@ template <bool LDS>
 __global__ __launch_bounds__(256) void k_refine_la(SceneDev S, LdsPlan L, GridDev g, RefineArgs A,
                                                    float delta,
                                                    const sbr_candidate* __restrict__ uniq,
-                                                   int64_t U, RefineOut* __restrict__ out,
+                                                   int64_t U_max,
+                                                   const int32_t* __restrict__ n_dev,
+                                                   RefineOut* __restrict__ out,
+                                                   PathGeom* __restrict__ geom,
                                                    int32_t* __restrict__ err)
 {
     if (LDS) stage_scene(S, L);
@@ -183,6 +201,7 @@ __global__ __launch_bounds__(256) void k_refine_la(SceneDev S, LdsPlan L, GridDe
     int64_t p = gid >> 6;
     const int lane = (int)(gid & 63);
     const int s1 = lane >> 3, s2 = lane & 7;
+    const int64_t U = n_dev ? min(U_max, (int64_t)*n_dev) : U_max;
     if (p >= U) return;
     const sbr_candidate c = uniq[p];
     const d3 tx = mk(A.tx[0], A.tx[1], A.tx[2]);
@@ -207,6 +226,7 @@ __global__ __launch_bounds__(256) void k_refine_la(SceneDev S, LdsPlan L, GridDe
         const bool lvl2 = two && s2 < A.subrays && s1 < A.subrays;
         Follow F;
         bool ok = false;
+        d3 gp[SBR_MAX_ORDER], gd[SBR_MAX_ORDER];
         if (lvl1 || lvl2) {
             d3 dt = subray(axis, u, v, rho1, s1);
             if (lvl2) {
@@ -214,7 +234,7 @@ __global__ __launch_bounds__(256) void k_refine_la(SceneDev S, LdsPlan L, GridDe
                 basis(dt, &u2, &v2);
                 dt = subray(dt, u2, v2, rho2, s2);
             }
-            ok = follow<LDS>(S, L, tx, dt, rx, c.order, c.face, delta, &F, nullptr, nullptr, err);
+            ok = follow<LDS>(S, L, tx, dt, rx, c.order, c.face, delta, &F, gp, gd, err);
         }
         const double myD = ok ? F.D : 0.0, myL = ok ? F.Llast : 0.0;
         // first level: argmin over lanes (s1, 7)
@@ -236,6 +256,8 @@ __global__ __launch_bounds__(256) void k_refine_la(SceneDev S, LdsPlan L, GridDe
             break;
         }
         double wD = __shfl(myD, b1 * 8 + 7), wL = __shfl(myL, b1 * 8 + 7);
+        if (lane == b1 * 8 + 7) store_geom(geom + p, c.order, gp, gd);
+        __threadfence_block();
         axis = subray(axis, u, v, rho1, b1);
         tan = k1;
         iters = i;
@@ -265,6 +287,8 @@ __global__ __launch_bounds__(256) void k_refine_la(SceneDev S, LdsPlan L, GridDe
         }
         wD = __shfl(myD, b1 * 8 + b2);
         wL = __shfl(myL, b1 * 8 + b2);
+        if (lane == b1 * 8 + b2) store_geom(geom + p, c.order, gp, gd);
+        __threadfence_block();
         basis(axis, &u, &v);
         axis = subray(axis, u, v, rho2, b2);
         tan = k2;
@@ -287,7 +311,8 @@ __global__ __launch_bounds__(256) void k_refine_la(SceneDev S, LdsPlan L, GridDe
 
 hipError_t launch_refine(const SceneDev& S, const LdsPlan& L, const GridDev& g,
                          const RefineArgs& A, const sbr_candidate* uniq, int64_t U,
-                         RefineOut* out, float delta, int32_t* err, hipStream_t s)
+                         const int32_t* n_dev, RefineOut* out, PathGeom* geom, float delta,
+                         int32_t* err, hipStream_t s)
 {
     if (U <= 0) return hipSuccess;
     // Few paths: the hardware is mostly idle, so spend 64 lanes per path on
@@ -297,16 +322,16 @@ hipError_t launch_refine(const SceneDev& S, const LdsPlan& L, const GridDev& g,
     dim3 grid((unsigned)((threads + L.block - 1) / L.block));
     if (la && L.bytes > 0)
         hipLaunchKernelGGL(k_refine_la<true>, grid, dim3(L.block), L.bytes, s, S, L, g, A, delta,
-                           uniq, U, out, err);
+                           uniq, U, n_dev, out, geom, err);
     else if (la)
         hipLaunchKernelGGL(k_refine_la<false>, grid, dim3(L.block), 0, s, S, L, g, A, delta, uniq,
-                           U, out, err);
+                           U, n_dev, out, geom, err);
     else if (L.bytes > 0)
         hipLaunchKernelGGL(k_refine<true>, grid, dim3(L.block), L.bytes, s, S, L, g, A, delta,
-                           uniq, U, out, err);
+                           uniq, U, n_dev, out, geom, err);
     else
         hipLaunchKernelGGL(k_refine<false>, grid, dim3(L.block), 0, s, S, L, g, A, delta, uniq, U,
-                           out, err);
+                           n_dev, out, geom, err);
     return hipGetLastError();
 }
 
@@ -456,7 +481,9 @@ __device__ static inline double poly_length(d3 tx, const d3* p, int k, d3 rx)
 template <bool LDS>
 __global__ __launch_bounds__(256) void k_solve(SceneDev S, LdsPlan L, SolveArgs A, float delta,
                                                const sbr_candidate* __restrict__ uniq,
-                                               const RefineOut* __restrict__ rf, int64_t U,
+                                               const RefineOut* __restrict__ rf,
+                                               const PathGeom* __restrict__ geom, int64_t U_max,
+                                               const int32_t* __restrict__ n_dev,
                                                sbr_path* __restrict__ paths,
                                                int32_t* __restrict__ keep,
                                                int32_t* __restrict__ err)
@@ -465,6 +492,7 @@ __global__ __launch_bounds__(256) void k_solve(SceneDev S, LdsPlan L, SolveArgs 
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t p = gid >> 4;
     int lane = (int)(gid & 15);
+    const int64_t U = n_dev ? min(U_max, (int64_t)*n_dev) : U_max;
     if (p >= U) return;
     const sbr_candidate c = uniq[p];
     const int k = c.order;
@@ -497,8 +525,16 @@ __global__ __launch_bounds__(256) void k_solve(SceneDev S, LdsPlan L, SolveArgs 
         pts[j] = mk(0.0, 0.0, 0.0);
         din[j] = mk(0.0, 0.0, 0.0);
     }
-    Follow F;
-    follow<LDS>(S, L, tx, axis, rx, k, c.face, delta, &F, pts, din, err);
+    if (R.iters > 0) {
+        // the refinement stored the geometry of its final winning sub-ray
+        for (int j = 0; j < k; ++j) {
+            pts[j] = geom[p].pts[j];
+            din[j] = geom[p].din[j];
+        }
+    } else {
+        Follow F;
+        follow<LDS>(S, L, tx, axis, rx, k, c.face, delta, &F, pts, din, err);
+    }
 
     sbr_path o;
     o.rx = c.rx;
@@ -542,18 +578,19 @@ __global__ __launch_bounds__(256) void k_solve(SceneDev S, LdsPlan L, SolveArgs 
 }
 
 hipError_t launch_solve(const SceneDev& S, const LdsPlan& L, const SolveArgs& A,
-                        const sbr_candidate* uniq, const RefineOut* rf, int64_t U,
-                        sbr_path* paths, int32_t* keep, float delta, int32_t* err, hipStream_t s)
+                        const sbr_candidate* uniq, const RefineOut* rf, const PathGeom* geom,
+                        int64_t U, const int32_t* n_dev, sbr_path* paths, int32_t* keep,
+                        float delta, int32_t* err, hipStream_t s)
 {
     if (U <= 0) return hipSuccess;
     int64_t threads = U * 16;
     dim3 grid((unsigned)((threads + L.block - 1) / L.block));
     if (L.bytes > 0)
         hipLaunchKernelGGL(k_solve<true>, grid, dim3(L.block), L.bytes, s, S, L, A, delta, uniq,
-                           rf, U, paths, keep, err);
+                           rf, geom, U, n_dev, paths, keep, err);
     else
-        hipLaunchKernelGGL(k_solve<false>, grid, dim3(L.block), 0, s, S, L, A, delta, uniq, rf, U,
-                           paths, keep, err);
+        hipLaunchKernelGGL(k_solve<false>, grid, dim3(L.block), 0, s, S, L, A, delta, uniq, rf,
+                           geom, U, n_dev, paths, keep, err);
     return hipGetLastError();
 }
 

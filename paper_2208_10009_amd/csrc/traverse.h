@@ -233,8 +233,16 @@ __device__ static inline bool capture(d3 o, d3 d, double D, double t, d3 rx, dou
     if (!(ts > 0.0)) return false;
     if (!(ts <= t)) return false;
     d3 f = sub(w, scl(ts, d));
-    double dp = norm(f);
     double L = D + ts;
+    double ff = dot(f, f);
+    if (thl >= 0.0) {
+        // Cheap exact reject: when ff exceeds (thl L)^2 by more than 1e-9
+        // relative, the rounded sqrt(ff) exceeds the rounded thl L whatever
+        // the rounding of the three products, so the test below would fail.
+        double lim = thl * L;
+        if (ff > (lim * lim) * (1.0 + 1e-9)) return false;
+    }
+    double dp = sqrt(ff);
     if (thl >= 0.0 && !(dp <= thl * L)) return false;
     *tan_out = dp / L;
     return true;

@@ -334,3 +334,23 @@ def test_lds_staged_traversal_matches(gpu, orc):
     c = _trace_with_env({"SBR_LDS_BUDGET": "163840", "SBR_TRACE_BLOCK": "512"}, cfg, **prm)
     assert a.tobytes() == b.tobytes() == c.tobytes()
     _compare_paths(a, orc.run(cfg["scene"], cfg["tx"], cfg["rx"], **prm)["paths"])
+
+
+def test_many_events_multikernel_path(gpu, orc):
+    """More than 4096 reception events: path test 1 and the final compaction
+    take the multi-kernel sort/scan route; results still match the oracle."""
+    cfg = scenes.shoebox_config(7)
+    rng = np.random.default_rng(11)
+    rx = rng.uniform(0.2, 0.8, size=(160, 3)) * np.array([10.0, 8.0, 3.0])
+    prm = dict(cfg["params"], iterations=2)
+    sc = gpu.scene(cfg["scene"])
+    try:
+        g, st = sc.trace(cfg["tx"], rx, **prm)
+        cands = sc.candidates(cfg["tx"], rx, **prm)
+    finally:
+        sc.close()
+    assert st["n_candidates"] > 4096
+    r = orc.run(cfg["scene"], cfg["tx"], rx, **prm)
+    _compare_paths(g, r["paths"])
+    o = _sorted_oracle_cands(r["candidates"])
+    assert len(cands) == len(o) and np.array_equal(cands["ray"], o["ray"])
