@@ -85,6 +85,61 @@ def cpu_baseline(cfg, budget_s=10.0, max_runs=20):
     }
 
 
+def batch_vs_plain(ctx, scenes, torch, seed=0, steps=2):
+    """The batched workload (16 box-building cities of 200-50k triangles,
+    256 Tx/Rx pairs spread unevenly over them, n in 50-400, K in 3-8), each
+    pair refined to 0.01 deg: one sbr_trace_batch call (persistent trace
+    over all jobs) against one sbr_trace call per pair.  Launch grids are
+    cached (both sides), the scenes' BVHs are built beforehand."""
+    b = scenes.batch_config(seed)
+    jobs = [dict(j, iterations=30, target_err_deg=0.01) for j in b["jobs"]]
+    n_rays = sum(10 * j["division_n"] ** 2 + 2 for j in jobs)
+    t0 = time.perf_counter()
+    scs = [ctx.scene(s) for s in b["scenes"]]
+    build_s = time.perf_counter() - t0
+    ctx.trace_batch(scs, jobs, b["rx"])  # warm-up: launch grids of every n
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pb, stb = ctx.trace_batch(scs, jobs, b["rx"])
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / steps
+
+    def plain_pass():
+        got = []
+        for j in jobs:
+            prm = {k: v for k, v in j.items() if k not in ("scene", "tx", "rx_first", "n_rx")}
+            rx = b["rx"][j["rx_first"]:j["rx_first"] + j["n_rx"]]
+            p, _ = scs[j["scene"]].trace(j["tx"], rx, **prm)
+            got.append(p)
+        return np.concatenate(got)
+
+    plain_pass()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pp = plain_pass()
+    torch.cuda.synchronize()
+    tp = (time.perf_counter() - t0) / steps
+    for sc in scs:
+        sc.close()
+    gb, gp = int(accurate_mask(pb).sum()), int(accurate_mask(pp).sum())
+    return {
+        "workload": "batch_16scenes_200-50k_tri_256pairs_n50-400_k3-8_target0.01deg",
+        "triangles": [int(len(s["tri"])) for s in b["scenes"]], "pairs": len(jobs),
+        "rays": int(n_rays), "bvh_build_s": round(build_s, 3),
+        "batched": {"ms": round(1e3 * tb, 3), "rays_per_s": n_rays / tb,
+                    "paths": int(len(pb)), "within_0.01deg": gb,
+                    "refined_paths_per_s": gb / tb,
+                    "stage_ms": {k: round(float(stb[k]), 4) for k in
+                                 ("ms_launch", "ms_trace", "ms_dedup", "ms_refine", "ms_solve",
+                                  "ms_emit", "ms_total")}},
+        "plain": {"ms": round(1e3 * tp, 3), "rays_per_s": n_rays / tp, "paths": int(len(pp)),
+                  "within_0.01deg": gp, "refined_paths_per_s": gp / tp},
+        "speedup": tp / tb,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +147,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched-vs-plain comparison on the 256-pair workload")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 5 times (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -210,6 +267,8 @@ def main():
         "roofline": roofline,
     }
     sc.close()
+    if not args.no_batch:
+        out["batched"] = batch_vs_plain(ctx, scenes, torch)
     ctx.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg)

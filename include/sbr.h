@@ -153,6 +153,32 @@ sbr_status sbr_trace(sbr_scene* scene, const double tx[3], const double* rx, int
                      const sbr_trace_params* params, sbr_path* out, int64_t capacity,
                      int64_t* n_out, sbr_trace_stats* stats);
 
+/* One job of a batched trace: transmitter tx on scenes[scene], its receivers
+ * rx[rx_first .. rx_first + n_rx) of the batch's receiver array (a receiver
+ * belongs to at most one job), and its own trace parameters. */
+typedef struct {
+    int32_t scene;
+    int32_t rx_first;
+    int32_t n_rx;
+    int32_t reserved; /* must be 0 */
+    double tx[3];
+    sbr_trace_params params;
+} sbr_job;
+
+/* Many transmitter/receiver jobs over several scenes in one pass of the path:
+ * one persistent trace launch whose device queue hands out ray packets of all
+ * jobs, one path test 1 over all reception events, one refinement and one
+ * solve launch over all paths.  Each job's paths are exactly those sbr_trace
+ * returns for it alone, with sbr_path.rx numbering the batch's receiver
+ * array; the list is sorted by (rx, order, face sequence).  rx [n_rx_total][3]
+ * host FP64.  All scenes must belong to ctx and have a BVH.  Errors as for
+ * sbr_trace, plus SBR_E_INVALID_ARG for a job whose scene index, receiver
+ * slice or parameters are out of range. */
+sbr_status sbr_trace_batch(sbr_context* ctx, sbr_scene* const* scenes, int32_t n_scenes,
+                           const sbr_job* jobs, int32_t n_jobs, const double* rx,
+                           int32_t n_rx_total, sbr_path* out, int64_t capacity, int64_t* n_out,
+                           sbr_trace_stats* stats);
+
 /* The reception events before path test 1 (same launch, trace and reception
  * as sbr_trace), sorted by (rx, order, face sequence, tan_err, ray). */
 sbr_status sbr_candidates(sbr_scene* scene, const double tx[3], const double* rx, int32_t n_rx,

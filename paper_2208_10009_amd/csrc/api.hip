@@ -50,7 +50,7 @@ struct Counters {
     int32_t err;
     int32_t n_unique;
     int32_t n_paths;
-    int32_t pad;
+    uint32_t queue;  // packets handed out by the persistent trace kernel
 };
 
 }  // namespace
@@ -62,7 +62,7 @@ struct sbr_context {
     int32_t n_scenes = 0;
     std::map<int32_t, DevBuf> grids;  // division n -> [3][N] FP64 directions
     DevBuf grid_scratch, rx, cand, idx, flags, offs, scan, uniq, refine, paths, keep, outp,
-        counters, rays_tri, rays_t, tally, geom;
+        counters, rays_tri, rays_t, tally, geom, d_jobs, d_scenes, d_rxjob;
     Counters* host_ctr = nullptr;  // pinned
     sbr_path* host_paths = nullptr;  // pinned staging of the path list
     int64_t host_paths_cap = 0;
@@ -75,6 +75,9 @@ struct sbr_context {
     // path counts up to which the refinement uses the two-iteration lookahead
     // (64 lanes per path); SBR_LOOKAHEAD_PATHS overrides
     int64_t lookahead_max_paths = 4096;
+    // persistent trace: 64-ray groups per queue packet, resident workgroups
+    // (SBR_TRACE_CHUNK, SBR_TRACE_BLOCKS)
+    int32_t trace_chunk = 1, persist_blocks = 2048;
 };
 
 struct sbr_scene {
@@ -228,56 +231,135 @@ sbr_status check_scene(sbr_scene* s)
     return SBR_OK;
 }
 
-// Launch, trace and reception, then the sort of the events and path test 1.
-// On return (SBR_OK) the context holds: cand (n_cand events), idx (sorted
-// permutation), flags/offs and uniq (n_uniq unique paths).
-struct Front {
-    int64_t n_cand = 0, n_uniq = 0, N = 0;
+// One call of the trace pipeline: jobs over scenes, the receivers of all
+// jobs, and what the front half (launch, trace, path test 1) produced.
+struct Call {
+    std::vector<JobDev> jobs;
+    std::vector<const sbr_scene*> scenes;
+    std::vector<int32_t> rx_job;
+    const double* rx = nullptr;  // host [n_rx][3]
+    int32_t n_rx = 0;
+    int64_t n_rays = 0, n_packets = 0;
+    int32_t chunk = 1;
+    CallDev dev{};
+    LdsPlan lp{};
+    SceneDev s0{};
+    int64_t n_cand = 0, n_uniq = 0;
     bool small = false;  // path test 1 ran in one workgroup; n_uniq is on the device
-    GridDev g;
-    TraceArgs ta;
-    LdsPlan lp;
-    float ms_launch = 0, ms_trace = 0, ms_dedup = 0;
+    bool grids_built = false;
+    float ms_launch = 0, ms_trace = 0;
 };
 
-sbr_status run_front(sbr_scene* s, const double* tx, const double* rx, int32_t n_rx,
-                     const sbr_trace_params* p, bool need_unique, Front* fr,
-                     unsigned long long* tallies = nullptr)
+// Add a job: its launch directions (cached per division n), parameters and
+// packets of 64 x chunk rays.
+sbr_status add_job(sbr_context* c, Call& call, int32_t scene_idx, const double* tx,
+                   int32_t rx_first, int32_t n_rx, const sbr_trace_params* p, int64_t ray_begin,
+                   int64_t ray_count)
 {
-    sbr_context* c = s->ctx;
+    GridDev g;
+    bool built = false;
+    sbr_status r = get_grid(c, p->division_n, &g, &built, (p->flags & SBR_FLAG_FRESH_GRID) != 0);
+    if (r) return r;
+    call.grids_built = call.grids_built || built;
+    const sbr_scene* s = call.scenes[scene_idx];
+    JobDev J{};
+    for (int i = 0; i < 3; ++i) J.tx[i] = tx[i];
+    J.thl = theta_launch(p->division_n);
+    J.tan_tgt = p->target_err_deg > 0.0 ? tan_cr((p->target_err_deg * kPi) / 180.0) : 0.0;
+    J.freq_hz = p->freq_hz;
+    J.tx_power_dbm = p->tx_power_dbm;
+    J.dir = g.dir;
+    J.N = g.N;
+    J.ray_begin = ray_begin;
+    J.ray_count = ray_count;
+    J.packet_first = call.n_packets;
+    J.scene = scene_idx;
+    J.rx_first = rx_first;
+    J.n_rx = n_rx;
+    J.K = p->max_order;
+    J.iterations = p->iterations;
+    J.subrays = p->subrays;
+    J.keep_invalid = (p->flags & SBR_FLAG_KEEP_INVALID) ? 1 : 0;
+    J.delta = traversal_delta(s, tx);
+    const int64_t per = 64 * (int64_t)call.chunk;
+    call.n_packets += (ray_count + per - 1) / per;
+    call.n_rays += ray_count;
+    for (int32_t x = 0; x < n_rx; ++x) call.rx_job[rx_first + x] = (int32_t)call.jobs.size();
+    call.jobs.push_back(J);
+    return SBR_OK;
+}
+
+// Copy the job, scene and receiver tables to the device.
+sbr_status upload_call(sbr_context* c, Call& call)
+{
     hipStream_t st = c->stream;
-    HIPCHK(c, hipEventRecord(c->ev[0], st));
-    bool built;
-    sbr_status r = get_grid(c, p->division_n, &fr->g, &built, (p->flags & SBR_FLAG_FRESH_GRID) != 0);
+    std::vector<SceneDev> sd;
+    for (const sbr_scene* s : call.scenes) sd.push_back(scene_dev(s));
+    HIPCHK(c, ensure(c->d_jobs, sizeof(JobDev) * std::max<size_t>(call.jobs.size(), 1)));
+    HIPCHK(c, ensure(c->d_scenes, sizeof(SceneDev) * std::max<size_t>(sd.size(), 1)));
+    HIPCHK(c, ensure(c->rx, sizeof(double) * 3 * (size_t)std::max(call.n_rx, 1)));
+    HIPCHK(c, ensure(c->d_rxjob, sizeof(int32_t) * (size_t)std::max(call.n_rx, 1)));
+    if (!call.jobs.empty())
+        HIPCHK(c, hipMemcpyAsync(c->d_jobs.p, call.jobs.data(), sizeof(JobDev) * call.jobs.size(),
+                                 hipMemcpyHostToDevice, st));
+    if (!sd.empty())
+        HIPCHK(c, hipMemcpyAsync(c->d_scenes.p, sd.data(), sizeof(SceneDev) * sd.size(),
+                                 hipMemcpyHostToDevice, st));
+    if (call.n_rx > 0) {
+        HIPCHK(c, hipMemcpyAsync(c->rx.p, call.rx, sizeof(double) * 3 * (size_t)call.n_rx,
+                                 hipMemcpyHostToDevice, st));
+        HIPCHK(c, hipMemcpyAsync(c->d_rxjob.p, call.rx_job.data(), sizeof(int32_t) * call.rx_job.size(),
+                                 hipMemcpyHostToDevice, st));
+    }
+    call.dev.jobs = c->d_jobs.as<const JobDev>();
+    call.dev.scenes = c->d_scenes.as<const SceneDev>();
+    call.dev.rx = c->rx.as<const double>();
+    call.dev.rx_job = c->d_rxjob.as<const int32_t>();
+    call.dev.n_jobs = (int32_t)call.jobs.size();
+    call.dev.chunk = call.chunk;
+    call.dev.n_packets = call.n_packets;
+    // LDS staging only when every job traces the same scene
+    bool one_scene = call.scenes.size() == 1;
+    call.s0 = sd.empty() ? SceneDev{} : sd[0];
+    if (one_scene) {
+        call.lp = plan_for(call.scenes[0], c->trace_block);
+    } else {
+        call.lp = LdsPlan{};
+        call.lp.block = 256;
+    }
+    return SBR_OK;
+}
+
+int trace_blocks(const sbr_context* c, const Call& call)
+{
+    int64_t per_block = std::max<int64_t>(1, call.lp.block / 64);
+    int64_t want = (call.n_packets + per_block - 1) / per_block;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(want, c->persist_blocks));
+}
+
+// Launch, trace and reception, then path test 1.  On return the context
+// holds cand (n_cand events) and, with need_unique, uniq (the path-test-1
+// winners, n_uniq or -- small -- a count on the device).  Without
+// need_unique, idx holds the sorted permutation of the events.
+sbr_status run_front(sbr_context* c, Call& call, bool need_unique, int32_t* out_tri,
+                     double* out_t, unsigned long long* tallies)
+{
+    hipStream_t st = c->stream;
+    sbr_status r = upload_call(c, call);
     if (r) return r;
     HIPCHK(c, hipEventRecord(c->ev[1], st));
-    fr->N = fr->g.N;
-
-    HIPCHK(c, ensure(c->rx, sizeof(double) * 3 * (size_t)std::max(n_rx, 1)));
-    if (n_rx > 0)
-        HIPCHK(c, hipMemcpyAsync(c->rx.p, rx, sizeof(double) * 3 * (size_t)n_rx,
-                                 hipMemcpyHostToDevice, st));
     HIPCHK(c, ensure(c->counters, sizeof(Counters)));
-    TraceArgs& A = fr->ta;
-    for (int i = 0; i < 3; ++i) A.tx[i] = tx[i];
-    A.rx = c->rx.as<const double>();
-    A.n_rx = n_rx;
-    A.K = p->max_order;
-    A.thl = theta_launch(p->division_n);
-    A.delta = traversal_delta(s, tx);
-    SceneDev S = scene_dev(s);
-    fr->lp = plan_for(s, c->trace_block);
-
     int64_t cap = std::max<int64_t>(65536, (int64_t)(c->cand.cap / sizeof(sbr_candidate)));
     Counters* hc = c->host_ctr;
+    Counters* dc = c->counters.as<Counters>();
     for (;;) {
         HIPCHK(c, ensure(c->cand, sizeof(sbr_candidate) * (size_t)cap));
         HIPCHK(c, hipMemsetAsync(c->counters.p, 0, sizeof(Counters), st));
         if (tallies) HIPCHK(c, hipMemsetAsync(tallies, 0, 4 * sizeof(unsigned long long), st));
         HIPCHK(c, hipEventRecord(c->ev[7], st));
-        HIPCHK(c, launch_trace(S, fr->lp, fr->g, A, 0, fr->N, c->cand.as<sbr_candidate>(), cap,
-                               &c->counters.as<Counters>()->cand, nullptr, nullptr,
-                               &c->counters.as<Counters>()->err, st, tallies));
+        HIPCHK(c, launch_trace(call.dev, call.lp, call.s0, trace_blocks(c, call), &dc->queue,
+                               c->cand.as<sbr_candidate>(), cap, &dc->cand, out_tri, out_t,
+                               &dc->err, st, tallies));
         HIPCHK(c, hipEventRecord(c->ev[2], st));
         HIPCHK(c, hipMemcpyAsync(hc, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipStreamSynchronize(st));
@@ -287,19 +369,19 @@ sbr_status run_front(sbr_scene* s, const double* tx, const double* rx, int32_t n
             return fail(c, SBR_E_CAPACITY, "%llu reception events exceed 2^31", hc->cand);
         cap = (int64_t)(hc->cand + hc->cand / 4 + 1024);
     }
-    fr->n_cand = (int64_t)hc->cand;
-    HIPCHK(c, hipEventElapsedTime(&fr->ms_launch, c->ev[0], c->ev[1]));
-    if (!built) fr->ms_launch = 0.0f;
-    HIPCHK(c, hipEventElapsedTime(&fr->ms_trace, c->ev[7], c->ev[2]));
+    call.n_cand = (int64_t)hc->cand;
+    HIPCHK(c, hipEventElapsedTime(&call.ms_launch, c->ev[0], c->ev[1]));
+    if (!call.grids_built) call.ms_launch = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&call.ms_trace, c->ev[7], c->ev[2]));
 
     // sort + path test 1
-    int64_t C = fr->n_cand;
+    const int64_t C = call.n_cand;
     if (need_unique && C <= kSmallEvents) {
         HIPCHK(c, ensure(c->uniq, sizeof(sbr_candidate) * (size_t)std::max<int64_t>(C, 1)));
         HIPCHK(c, launch_dedup_small(c->cand.as<sbr_candidate>(), C, c->uniq.as<sbr_candidate>(),
-                                     &c->counters.as<Counters>()->n_unique, st));
-        fr->small = true;
-        fr->n_uniq = -1;
+                                     &dc->n_unique, st));
+        call.small = true;
+        call.n_uniq = -1;
         HIPCHK(c, hipEventRecord(c->ev[3], st));
         return SBR_OK;
     }
@@ -312,12 +394,12 @@ sbr_status run_front(sbr_scene* s, const double* tx, const double* rx, int32_t n
         HIPCHK(c, ensure(c->scan, scan_scratch_bytes(C)));
         HIPCHK(c, launch_heads(c->cand.as<sbr_candidate>(), c->idx.as<uint32_t>(), C,
                                c->flags.as<int32_t>(), st));
-        HIPCHK(c, launch_scan(c->flags.as<int32_t>(), c->offs.as<int32_t>(), C,
-                              &c->counters.as<Counters>()->n_unique, c->scan.p, st));
+        HIPCHK(c, launch_scan(c->flags.as<int32_t>(), c->offs.as<int32_t>(), C, &dc->n_unique,
+                              c->scan.p, st));
         HIPCHK(c, hipMemcpyAsync(hc, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipStreamSynchronize(st));
-        fr->n_uniq = hc->n_unique;
-        HIPCHK(c, ensure(c->uniq, sizeof(sbr_candidate) * (size_t)std::max<int64_t>(fr->n_uniq, 1)));
+        call.n_uniq = hc->n_unique;
+        HIPCHK(c, ensure(c->uniq, sizeof(sbr_candidate) * (size_t)std::max<int64_t>(call.n_uniq, 1)));
         HIPCHK(c, launch_gather_unique(c->cand.as<sbr_candidate>(), c->idx.as<uint32_t>(),
                                        c->flags.as<int32_t>(), c->offs.as<int32_t>(), C,
                                        c->uniq.as<sbr_candidate>(), st));
@@ -335,6 +417,126 @@ sbr_status ensure_host_paths(sbr_context* c, int64_t n)
     HIPCHK(c, hipHostMalloc((void**)&c->host_paths, sizeof(sbr_path) * (size_t)n, 0));
     c->host_paths_cap = n;
     return SBR_OK;
+}
+
+// The back half: precise algorithm, path quantities / path test 2 / power,
+// and the canonical emit into out.
+sbr_status run_paths(sbr_context* c, Call& call, sbr_path* out, int64_t capacity, int64_t* n_out,
+                     sbr_trace_stats* stats)
+{
+    hipStream_t st = c->stream;
+    Counters* hc = c->host_ctr;
+    Counters* dc = c->counters.as<Counters>();
+    sbr_status r;
+    // U_max bounds the number of unique paths; with the one-workgroup path
+    // test 1 the exact count stays on the device and the kernels read it.
+    const int64_t Umax = call.small ? call.n_cand : call.n_uniq;
+    const int32_t* ndev = call.small ? &dc->n_unique : nullptr;
+    const size_t U1 = (size_t)std::max<int64_t>(Umax, 1);
+    HIPCHK(c, ensure(c->refine, sizeof(RefineOut) * U1));
+    HIPCHK(c, ensure(c->geom, sizeof(PathGeom) * U1));
+    LdsPlan lp256 = call.scenes.size() == 1 ? plan_for(call.scenes[0], 256) : LdsPlan{};
+    lp256.block = 256;
+    const bool lookahead = Umax <= c->lookahead_max_paths;
+    HIPCHK(c, launch_refine(call.dev, lp256, call.s0, c->uniq.as<sbr_candidate>(), Umax, ndev,
+                            lookahead, c->refine.as<RefineOut>(), c->geom.as<PathGeom>(),
+                            &dc->err, st));
+    HIPCHK(c, hipEventRecord(c->ev[4], st));
+
+    HIPCHK(c, ensure(c->paths, sizeof(sbr_path) * U1));
+    HIPCHK(c, ensure(c->keep, sizeof(int32_t) * U1));
+    HIPCHK(c, ensure(c->offs, sizeof(int32_t) * U1));
+    HIPCHK(c, ensure(c->scan, scan_scratch_bytes(Umax)));
+    HIPCHK(c, launch_solve(call.dev, lp256, call.s0, c->uniq.as<sbr_candidate>(),
+                           c->refine.as<RefineOut>(), c->geom.as<const PathGeom>(), Umax, ndev,
+                           c->paths.as<sbr_path>(), c->keep.as<int32_t>(), &dc->err, st));
+    HIPCHK(c, hipEventRecord(c->ev[5], st));
+
+    // emit: stable compaction of kept paths (already in canonical order)
+    int64_t P = 0, U = call.n_uniq;
+    if (call.small) {
+        // one workgroup compacts; the list (at most Umax records) and the
+        // counts come back in one round trip
+        HIPCHK(c, ensure(c->outp, sizeof(sbr_path) * U1));
+        HIPCHK(c, launch_emit_small(c->paths.as<sbr_path>(), c->keep.as<int32_t>(), Umax, ndev,
+                                    c->outp.as<sbr_path>(), &dc->n_paths, st));
+        r = ensure_host_paths(c, (int64_t)U1);
+        if (r) return r;
+        if (Umax > 0)
+            HIPCHK(c, hipMemcpyAsync(c->host_paths, c->outp.p, sizeof(sbr_path) * (size_t)Umax,
+                                     hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipMemcpyAsync(hc, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipEventRecord(c->ev[6], st));
+        HIPCHK(c, hipEventSynchronize(c->ev[6]));
+        if (hc->err) return fail(c, SBR_E_INTERNAL, "traversal stack overflow");
+        P = hc->n_paths;
+        U = hc->n_unique;
+        *n_out = P;
+        if (P > capacity)
+            return fail(c, SBR_E_CAPACITY, "%lld paths, capacity %lld", (long long)P,
+                        (long long)capacity);
+        if (P > 0) memcpy(out, c->host_paths, sizeof(sbr_path) * (size_t)P);
+    } else {
+        HIPCHK(c, launch_scan(c->keep.as<int32_t>(), c->offs.as<int32_t>(), U, &dc->n_paths,
+                              c->scan.p, st));
+        HIPCHK(c, hipMemcpyAsync(hc, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        if (hc->err) return fail(c, SBR_E_INTERNAL, "traversal stack overflow");
+        P = hc->n_paths;
+        *n_out = P;
+        if (P > capacity)
+            return fail(c, SBR_E_CAPACITY, "%lld paths, capacity %lld", (long long)P,
+                        (long long)capacity);
+        HIPCHK(c, ensure(c->outp, sizeof(sbr_path) * (size_t)std::max<int64_t>(P, 1)));
+        HIPCHK(c, launch_compact_paths(c->paths.as<sbr_path>(), c->keep.as<int32_t>(),
+                                       c->offs.as<int32_t>(), U, c->outp.as<sbr_path>(), st));
+        if (P > 0)
+            HIPCHK(c, hipMemcpyAsync(out, c->outp.p, sizeof(sbr_path) * (size_t)P,
+                                     hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipEventRecord(c->ev[6], st));
+        HIPCHK(c, hipEventSynchronize(c->ev[6]));
+    }
+    if (stats) {
+        memset(stats, 0, sizeof(*stats));
+        stats->n_rays = call.n_rays;
+        stats->n_candidates = call.n_cand;
+        stats->n_unique = U;
+        stats->n_paths = P;
+        float a = 0, b = 0, e = 0, tot = 0, dd = 0;
+        (void)hipEventElapsedTime(&dd, c->ev[2], c->ev[3]);
+        (void)hipEventElapsedTime(&a, c->ev[3], c->ev[4]);
+        (void)hipEventElapsedTime(&b, c->ev[4], c->ev[5]);
+        (void)hipEventElapsedTime(&e, c->ev[5], c->ev[6]);
+        (void)hipEventElapsedTime(&tot, c->ev[0], c->ev[6]);
+        stats->ms_launch = call.ms_launch;
+        stats->ms_trace = call.ms_trace;
+        stats->ms_dedup = dd;
+        stats->ms_refine = a;
+        stats->ms_solve = b;
+        stats->ms_emit = e;
+        stats->ms_total = tot;
+        stats->lds_bytes = call.lp.bytes;
+        stats->lds_nodes = call.lp.n_nodes;
+        stats->lds_tris = call.lp.n_tris;
+        stats->lds_max = c->lds_max;
+    }
+    return SBR_OK;
+}
+
+// A call with one job on one scene.
+sbr_status single_call(sbr_scene* s, Call& call, const double* tx, const double* rx,
+                       int32_t n_rx, const sbr_trace_params* p, int64_t ray_begin,
+                       int64_t ray_count)
+{
+    sbr_context* c = s->ctx;
+    call.scenes.push_back(s);
+    call.rx = rx;
+    call.n_rx = n_rx;
+    call.rx_job.assign((size_t)n_rx, 0);
+    call.chunk = c->trace_chunk;
+    HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
+    int64_t N = 10 * (int64_t)p->division_n * p->division_n + 2;
+    return add_job(c, call, 0, tx, 0, n_rx, p, ray_begin, ray_count < 0 ? N : ray_count);
 }
 
 }  // namespace
@@ -428,6 +630,8 @@ sbr_status sbr_context_create(int32_t device, void* hip_stream, sbr_context** ou
         c->trace_block = env_int("SBR_TRACE_BLOCK", 256, 64, 1024) / 64 * 64;
         c->stack_depth = env_int("SBR_STACK_DEPTH", 24, 0, kTraceStack);
         c->lookahead_max_paths = env_int("SBR_LOOKAHEAD_PATHS", 4096, 0, 1 << 30);
+        c->trace_chunk = env_int("SBR_TRACE_CHUNK", 1, 1, 64);
+        c->persist_blocks = env_int("SBR_TRACE_BLOCKS", 2048, 1, 1 << 20);
     }
     if (e != hipSuccess) {
         g_create_err = std::string("context setup: ") + hipGetErrorString(e);
@@ -450,7 +654,7 @@ sbr_status sbr_context_destroy(sbr_context* c)
     DevBuf* bufs[] = {&c->grid_scratch, &c->rx,    &c->cand,  &c->idx,  &c->flags,
                       &c->offs,         &c->scan,  &c->uniq,  &c->refine, &c->paths,
                       &c->keep,         &c->outp,  &c->counters, &c->rays_tri, &c->rays_t, &c->tally,
-                      &c->geom};
+                      &c->geom,         &c->d_jobs, &c->d_scenes, &c->d_rxjob};
     for (DevBuf* b : bufs) release(*b);
     for (auto& ev : c->ev)
         if (ev) (void)hipEventDestroy(ev);
@@ -659,33 +863,28 @@ sbr_status sbr_trace_rays(sbr_scene* s, const double tx[3], int32_t n, int32_t K
     if (first < 0 || count < 0 || first + count > N)
         return fail(c, SBR_E_INVALID_ARG, "ray range outside 0..%lld", (long long)N);
     HIPCHK(c, hipSetDevice(c->device));
-    GridDev g;
-    bool built;
-    r = get_grid(c, n, &g, &built);
-    if (r) return r;
     if (count == 0) return SBR_OK;
+    sbr_trace_params p{};
+    p.max_order = K;
+    p.division_n = n;
+    p.iterations = 0;
+    p.subrays = 6;
+    p.freq_hz = 1.0;
+    Call call;
+    r = single_call(s, call, tx, nullptr, 0, &p, first, count);
+    if (r) return r;
     size_t cells = (size_t)count * (K + 1);
     HIPCHK(c, ensure(c->rays_tri, sizeof(int32_t) * cells));
     HIPCHK(c, ensure(c->rays_t, sizeof(double) * cells));
-    HIPCHK(c, ensure(c->counters, sizeof(Counters)));
-    HIPCHK(c, hipMemsetAsync(c->counters.p, 0, sizeof(Counters), c->stream));
-    TraceArgs A;
-    for (int i = 0; i < 3; ++i) A.tx[i] = tx[i];
-    A.rx = nullptr;
-    A.n_rx = 0;
-    A.K = K;
-    A.thl = theta_launch(n);
-    A.delta = traversal_delta(s, tx);
-    HIPCHK(c, launch_trace(scene_dev(s), plan_for(s, c->trace_block), g, A, first, count, nullptr, 0,
-                           &c->counters.as<Counters>()->cand, c->rays_tri.as<int32_t>(),
-                           c->rays_t.as<double>(), &c->counters.as<Counters>()->err, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->host_ctr, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, c->stream));
+    r = run_front(c, call, false, c->rays_tri.as<int32_t>(), c->rays_t.as<double>(), nullptr);
+    if (r) return r;
     if (out_tri)
-        HIPCHK(c, hipMemcpyAsync(out_tri, c->rays_tri.p, sizeof(int32_t) * cells, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(out_tri, c->rays_tri.p, sizeof(int32_t) * cells,
+                                 hipMemcpyDeviceToHost, c->stream));
     if (out_t)
-        HIPCHK(c, hipMemcpyAsync(out_t, c->rays_t.p, sizeof(double) * cells, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(out_t, c->rays_t.p, sizeof(double) * cells, hipMemcpyDeviceToHost,
+                                 c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (c->host_ctr->err) return fail(c, SBR_E_INTERNAL, "traversal stack overflow");
     return SBR_OK;
 }
 
@@ -715,17 +914,20 @@ sbr_status sbr_candidates(sbr_scene* s, const double tx[3], const double* rx, in
     if (r) return r;
     sbr_context* c = s->ctx;
     HIPCHK(c, hipSetDevice(c->device));
-    Front fr;
-    r = run_front(s, tx, rx, n_rx, p, false, &fr);
+    Call call;
+    r = single_call(s, call, tx, rx, n_rx, p, 0, -1);
     if (r) return r;
-    *n_out = fr.n_cand;
-    if (fr.n_cand > capacity)
-        return fail(c, SBR_E_CAPACITY, "%lld events, capacity %lld", (long long)fr.n_cand, (long long)capacity);
-    if (fr.n_cand == 0) return SBR_OK;
-    HIPCHK(c, ensure(c->uniq, sizeof(sbr_candidate) * (size_t)fr.n_cand));
-    HIPCHK(c, launch_gather_sorted(c->cand.as<sbr_candidate>(), c->idx.as<uint32_t>(), fr.n_cand,
-                                   c->uniq.as<sbr_candidate>(), c->stream));
-    HIPCHK(c, hipMemcpyAsync(out, c->uniq.p, sizeof(sbr_candidate) * (size_t)fr.n_cand,
+    r = run_front(c, call, false, nullptr, nullptr, nullptr);
+    if (r) return r;
+    *n_out = call.n_cand;
+    if (call.n_cand > capacity)
+        return fail(c, SBR_E_CAPACITY, "%lld events, capacity %lld", (long long)call.n_cand,
+                    (long long)capacity);
+    if (call.n_cand == 0) return SBR_OK;
+    HIPCHK(c, ensure(c->uniq, sizeof(sbr_candidate) * (size_t)call.n_cand));
+    HIPCHK(c, launch_gather_sorted(c->cand.as<sbr_candidate>(), c->idx.as<uint32_t>(),
+                                   call.n_cand, c->uniq.as<sbr_candidate>(), c->stream));
+    HIPCHK(c, hipMemcpyAsync(out, c->uniq.p, sizeof(sbr_candidate) * (size_t)call.n_cand,
                              hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return SBR_OK;
@@ -741,8 +943,10 @@ sbr_status sbr_trace_counters(sbr_scene* s, const double tx[3], const double* rx
     if (!counts) return fail(c, SBR_E_INVALID_ARG, "counts is NULL");
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, ensure(c->tally, 4 * sizeof(unsigned long long)));
-    Front fr;
-    r = run_front(s, tx, rx, n_rx, p, false, &fr, c->tally.as<unsigned long long>());
+    Call call;
+    r = single_call(s, call, tx, rx, n_rx, p, 0, -1);
+    if (r) return r;
+    r = run_front(c, call, false, nullptr, nullptr, c->tally.as<unsigned long long>());
     if (r) return r;
     unsigned long long h[4];
     HIPCHK(c, hipMemcpy(h, c->tally.p, sizeof h, hipMemcpyDeviceToHost));
@@ -757,122 +961,65 @@ sbr_status sbr_trace(sbr_scene* s, const double tx[3], const double* rx, int32_t
     sbr_status r = check_trace_inputs(s, tx, rx, n_rx, p, capacity, out, n_out);
     if (r) return r;
     sbr_context* c = s->ctx;
-    hipStream_t st = c->stream;
     HIPCHK(c, hipSetDevice(c->device));
-    Front fr;
-    r = run_front(s, tx, rx, n_rx, p, true, &fr);
+    Call call;
+    r = single_call(s, call, tx, rx, n_rx, p, 0, -1);
     if (r) return r;
-    // U_max bounds the number of unique paths; with the one-workgroup path
-    // test 1 the exact count stays on the device and the kernels read it.
-    const int64_t Umax = fr.small ? fr.n_cand : fr.n_uniq;
-    const int32_t* ndev = fr.small ? &c->counters.as<Counters>()->n_unique : nullptr;
-    SceneDev S = scene_dev(s);
-    Counters* hc = c->host_ctr;
+    r = run_front(c, call, true, nullptr, nullptr, nullptr);
+    if (r) return r;
+    return run_paths(c, call, out, capacity, n_out, stats);
+}
 
-    // precise algorithm
-    RefineArgs ra;
-    for (int i = 0; i < 3; ++i) ra.tx[i] = tx[i];
-    ra.rx = c->rx.as<const double>();
-    ra.thl = fr.ta.thl;
-    ra.tan_tgt = p->target_err_deg > 0.0 ? tan_cr((p->target_err_deg * kPi) / 180.0) : 0.0;
-    ra.iterations = p->iterations;
-    ra.subrays = p->subrays;
-    ra.lookahead_max_paths = c->lookahead_max_paths;
-    const size_t U1 = (size_t)std::max<int64_t>(Umax, 1);
-    HIPCHK(c, ensure(c->refine, sizeof(RefineOut) * U1));
-    HIPCHK(c, ensure(c->geom, sizeof(PathGeom) * U1));
-    const LdsPlan lp256 = plan_for(s, 256);
-    HIPCHK(c, launch_refine(S, lp256, fr.g, ra, c->uniq.as<sbr_candidate>(), Umax, ndev,
-                            c->refine.as<RefineOut>(), c->geom.as<PathGeom>(), fr.ta.delta,
-                            &c->counters.as<Counters>()->err, st));
-    HIPCHK(c, hipEventRecord(c->ev[4], st));
-
-    // path quantities, path test 2, power
-    SolveArgs sa;
-    for (int i = 0; i < 3; ++i) sa.tx[i] = tx[i];
-    sa.rx = c->rx.as<const double>();
-    sa.freq_hz = p->freq_hz;
-    sa.tx_power_dbm = p->tx_power_dbm;
-    sa.keep_invalid = (p->flags & SBR_FLAG_KEEP_INVALID) ? 1 : 0;
-    HIPCHK(c, ensure(c->paths, sizeof(sbr_path) * U1));
-    HIPCHK(c, ensure(c->keep, sizeof(int32_t) * U1));
-    HIPCHK(c, ensure(c->offs, sizeof(int32_t) * U1));
-    HIPCHK(c, ensure(c->scan, scan_scratch_bytes(Umax)));
-    HIPCHK(c, launch_solve(S, lp256, sa, c->uniq.as<sbr_candidate>(), c->refine.as<RefineOut>(),
-                           c->geom.as<const PathGeom>(), Umax, ndev, c->paths.as<sbr_path>(),
-                           c->keep.as<int32_t>(), fr.ta.delta, &c->counters.as<Counters>()->err,
-                           st));
-    HIPCHK(c, hipEventRecord(c->ev[5], st));
-
-    // emit: stable compaction of kept paths (already in canonical order)
-    int64_t P = 0, U = fr.n_uniq;
-    if (fr.small) {
-        // one workgroup compacts; the list (at most Umax records) and the
-        // counts come back in one round trip
-        HIPCHK(c, ensure(c->outp, sizeof(sbr_path) * U1));
-        HIPCHK(c, launch_emit_small(c->paths.as<sbr_path>(), c->keep.as<int32_t>(), Umax, ndev,
-                                    c->outp.as<sbr_path>(), &c->counters.as<Counters>()->n_paths,
-                                    st));
-        r = ensure_host_paths(c, (int64_t)U1);
+sbr_status sbr_trace_batch(sbr_context* c, sbr_scene* const* scenes, int32_t n_scenes,
+                           const sbr_job* jobs, int32_t n_jobs, const double* rx,
+                           int32_t n_rx_total, sbr_path* out, int64_t capacity, int64_t* n_out,
+                           sbr_trace_stats* stats)
+{
+    if (!c) return SBR_E_INVALID_ARG;
+    c->err.clear();
+    if (!n_out) return fail(c, SBR_E_INVALID_ARG, "n_out is NULL");
+    *n_out = 0;
+    if (n_scenes < 1 || !scenes || n_jobs < 0 || (n_jobs > 0 && !jobs) || n_rx_total < 0 ||
+        (n_rx_total > 0 && !rx) || capacity < 0 || (capacity > 0 && !out))
+        return fail(c, SBR_E_INVALID_ARG, "bad batch arrays or sizes");
+    for (int32_t i = 0; i < n_scenes; ++i) {
+        if (!scenes[i] || scenes[i]->ctx != c)
+            return fail(c, SBR_E_NO_SCENE, "scene %d missing or from another context", i);
+        if (!scenes[i]->has_bvh) return fail(c, SBR_E_NO_BVH, "scene %d has no BVH", i);
+    }
+    for (int32_t x = 0; x < n_rx_total; ++x)
+        if (!finite3(rx + 3 * x)) return fail(c, SBR_E_INVALID_ARG, "rx %d not finite", x);
+    std::vector<char> used((size_t)n_rx_total, 0);
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        const sbr_job& J = jobs[j];
+        if (J.scene < 0 || J.scene >= n_scenes || J.reserved != 0 || J.n_rx < 0 ||
+            J.rx_first < 0 || (int64_t)J.rx_first + J.n_rx > n_rx_total || !finite3(J.tx))
+            return fail(c, SBR_E_INVALID_ARG, "job %d: bad scene, receivers or tx", j);
+        for (int32_t x = 0; x < J.n_rx; ++x) {
+            if (used[J.rx_first + x])
+                return fail(c, SBR_E_INVALID_ARG, "receiver %d belongs to two jobs", J.rx_first + x);
+            used[J.rx_first + x] = 1;
+        }
+        sbr_status r = check_params(c, &J.params);
         if (r) return r;
-        HIPCHK(c, hipMemcpyAsync(c->host_paths, c->outp.p, sizeof(sbr_path) * (size_t)Umax,
-                                 hipMemcpyDeviceToHost, st));
-        HIPCHK(c, hipMemcpyAsync(hc, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
-        HIPCHK(c, hipEventRecord(c->ev[6], st));
-        HIPCHK(c, hipEventSynchronize(c->ev[6]));
-        if (hc->err) return fail(c, SBR_E_INTERNAL, "traversal stack overflow");
-        P = hc->n_paths;
-        U = hc->n_unique;
-        *n_out = P;
-        if (P > capacity)
-            return fail(c, SBR_E_CAPACITY, "%lld paths, capacity %lld", (long long)P,
-                        (long long)capacity);
-        if (P > 0) memcpy(out, c->host_paths, sizeof(sbr_path) * (size_t)P);
-    } else {
-        HIPCHK(c, launch_scan(c->keep.as<int32_t>(), c->offs.as<int32_t>(), U,
-                              &c->counters.as<Counters>()->n_paths, c->scan.p, st));
-        HIPCHK(c, hipMemcpyAsync(hc, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
-        HIPCHK(c, hipStreamSynchronize(st));
-        if (hc->err) return fail(c, SBR_E_INTERNAL, "traversal stack overflow");
-        P = hc->n_paths;
-        *n_out = P;
-        if (P > capacity)
-            return fail(c, SBR_E_CAPACITY, "%lld paths, capacity %lld", (long long)P,
-                        (long long)capacity);
-        HIPCHK(c, ensure(c->outp, sizeof(sbr_path) * (size_t)std::max<int64_t>(P, 1)));
-        HIPCHK(c, launch_compact_paths(c->paths.as<sbr_path>(), c->keep.as<int32_t>(),
-                                       c->offs.as<int32_t>(), U, c->outp.as<sbr_path>(), st));
-        if (P > 0)
-            HIPCHK(c, hipMemcpyAsync(out, c->outp.p, sizeof(sbr_path) * (size_t)P,
-                                     hipMemcpyDeviceToHost, st));
-        HIPCHK(c, hipEventRecord(c->ev[6], st));
-        HIPCHK(c, hipEventSynchronize(c->ev[6]));
     }
-    if (stats) {
-        memset(stats, 0, sizeof(*stats));
-        stats->n_rays = fr.N;
-        stats->n_candidates = fr.n_cand;
-        stats->n_unique = U;
-        stats->n_paths = P;
-        float a = 0, b = 0, e = 0, tot = 0, dd = 0;
-        (void)hipEventElapsedTime(&dd, c->ev[2], c->ev[3]);
-        (void)hipEventElapsedTime(&a, c->ev[3], c->ev[4]);
-        (void)hipEventElapsedTime(&b, c->ev[4], c->ev[5]);
-        (void)hipEventElapsedTime(&e, c->ev[5], c->ev[6]);
-        (void)hipEventElapsedTime(&tot, c->ev[0], c->ev[6]);
-        stats->ms_launch = fr.ms_launch;
-        stats->ms_trace = fr.ms_trace;
-        stats->ms_dedup = dd;
-        stats->ms_refine = a;
-        stats->ms_solve = b;
-        stats->ms_emit = e;
-        stats->ms_total = tot;
-        stats->lds_bytes = fr.lp.bytes;
-        stats->lds_nodes = fr.lp.n_nodes;
-        stats->lds_tris = fr.lp.n_tris;
-        stats->lds_max = c->lds_max;
+    HIPCHK(c, hipSetDevice(c->device));
+    Call call;
+    for (int32_t i = 0; i < n_scenes; ++i) call.scenes.push_back(scenes[i]);
+    call.rx = rx;
+    call.n_rx = n_rx_total;
+    call.rx_job.assign((size_t)n_rx_total, 0);
+    call.chunk = c->trace_chunk;
+    HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        const sbr_job& J = jobs[j];
+        int64_t N = 10 * (int64_t)J.params.division_n * J.params.division_n + 2;
+        sbr_status r = add_job(c, call, J.scene, J.tx, J.rx_first, J.n_rx, &J.params, 0, N);
+        if (r) return r;
     }
-    return SBR_OK;
+    sbr_status r = run_front(c, call, true, nullptr, nullptr, nullptr);
+    if (r) return r;
+    return run_paths(c, call, out, capacity, n_out, stats);
 }
 
 }  // extern "C"

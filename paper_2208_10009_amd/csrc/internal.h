@@ -40,7 +40,7 @@ constexpr int kTraceStack = 64;
 int build_bvh(const double* tri_v, int64_t T, int max_leaf, int bins, bool bfs,
               std::vector<BvhNode>& nodes, std::vector<int32_t>& perm);
 
-// Device view of a scene, passed by value to kernels.
+// Device view of a scene.
 struct SceneDev {
     const BvhNode* nodes;
     const TriD* tris;       // leaf order
@@ -54,8 +54,10 @@ struct SceneDev {
 };
 
 // Per-launch LDS plan of a traversal kernel: the first n_nodes BVH nodes and
-// the first n_tris triangles are copied into LDS, followed by a per-lane
-// stack of `depth` entries (stride `block`) at byte offset stack_off.
+// the first n_tris triangles of the (single) scene are copied into LDS,
+// followed by a per-lane stack of `depth` entries (stride `block`) at byte
+// offset stack_off.  bytes == 0: traverse from global memory with a private
+// stack.
 struct LdsPlan {
     int32_t n_nodes, n_tris, depth, stack_off, block;
     int32_t bytes;  // dynamic LDS per block
@@ -72,26 +74,47 @@ struct GridDev {
     int32_t n;
 };
 
-// Per-call trace parameters as the kernels see them.
-struct TraceArgs {
+// One job of a trace call: a transmitter, its receivers (a slice of the
+// call's receiver array) and its parameters, on one scene.  A plain trace is
+// a call with one job.
+struct JobDev {
     double tx[3];
-    const double* rx;     // [n_rx][3] device
-    int32_t n_rx;
-    int32_t K;            // max order
-    double thl;           // theta_launch (rad)
-    float delta;          // box inflation (m) making FP32 traversal conservative
+    double thl;            // theta_launch (rad), eq. (4)
+    double tan_tgt;        // tan(target error angle); <= 0: fixed iterations
+    double freq_hz, tx_power_dbm;
+    const double* dir;     // launch directions [3][N] for this job's division n
+    int64_t N;             // rays of the division
+    int64_t ray_begin;     // launch rays traced: [ray_begin, ray_begin + ray_count)
+    int64_t ray_count;
+    int64_t packet_first;  // index of the job's first ray packet in the call
+    int32_t scene, rx_first, n_rx, K;
+    int32_t iterations, subrays, keep_invalid;
+    float delta;           // box inflation (m) making FP32 traversal conservative
 };
 
-// ---- launchers (kernels.hip) -------------------------------------------
+// Everything the kernels of one call see.
+struct CallDev {
+    const JobDev* jobs;
+    const SceneDev* scenes;
+    const double* rx;       // [n_rx_total][3]: receivers of all jobs
+    const int32_t* rx_job;  // job of each receiver
+    int32_t n_jobs;
+    int32_t chunk;          // 64-ray groups per packet
+    int64_t n_packets;
+};
+
+// ---- launchers -----------------------------------------------------------
 hipError_t launch_grid(GridDev g, hipStream_t s, void* scratch);
 size_t grid_scratch_bytes(int32_t n);
 
-// Trace rays [first, first+count): reception events appended to cand (up to
-// cap; *cand_count counts all), optional per-ray tri/t outputs.  With
-// tallies non-NULL the counting variant adds (segments, nodes visited,
-// triangles tested, events) to tallies[0..3].
-hipError_t launch_trace(const SceneDev& S, const LdsPlan& L, const GridDev& g, const TraceArgs& A,
-                        int64_t first, int64_t count, sbr_candidate* cand, int64_t cap,
+// Persistent trace + reception over all packets of the call.  Reception
+// events are appended to cand (up to cap; *cand_count counts all); queue is a
+// zeroed packet counter.  With out_tri/out_t (single-job calls) the per-ray
+// hits are written at (ray - ray_begin) * (K + 1) + segment.  With tallies
+// the counting variant adds (segments, nodes visited, triangles tested,
+// events) to tallies[0..3].  s0 is the scene staged in LDS when L.bytes > 0.
+hipError_t launch_trace(const CallDev& call, const LdsPlan& L, const SceneDev& s0, int blocks,
+                        uint32_t* queue, sbr_candidate* cand, int64_t cap,
                         unsigned long long* cand_count, int32_t* out_tri, double* out_t,
                         int32_t* err_flag, hipStream_t s, unsigned long long* tallies = nullptr);
 hipError_t trace_set_lds_limit(int bytes);
@@ -133,32 +156,18 @@ struct RefineOut {
     uint32_t flags;
 };
 
-struct RefineArgs {
-    double tx[3];
-    const double* rx;
-    double thl;
-    double tan_tgt;   // <= 0: no target
-    int32_t iterations, subrays;
-    int64_t lookahead_max_paths;  // up to this many paths: two-iteration lookahead
-};
+// U_max paths (the first min(U_max, *n_dev) when n_dev is non-NULL).  With
+// lookahead, one wave per path resolves two iterations per step; otherwise
+// eight lanes per path take one iteration per step.
+hipError_t launch_refine(const CallDev& call, const LdsPlan& L, const SceneDev& s0,
+                         const sbr_candidate* uniq, int64_t U_max, const int32_t* n_dev,
+                         bool lookahead, RefineOut* out, PathGeom* geom, int32_t* err,
+                         hipStream_t s);
 
-// U_max paths (the first min(U_max, *n_dev) when n_dev is non-NULL).
-hipError_t launch_refine(const SceneDev& S, const LdsPlan& L, const GridDev& g,
-                         const RefineArgs& A, const sbr_candidate* uniq, int64_t U_max,
-                         const int32_t* n_dev, RefineOut* out, PathGeom* geom, float delta,
-                         int32_t* err, hipStream_t s);
-
-struct SolveArgs {
-    double tx[3];
-    const double* rx;
-    double freq_hz, tx_power_dbm;
-    int32_t keep_invalid;
-};
-
-hipError_t launch_solve(const SceneDev& S, const LdsPlan& L, const SolveArgs& A,
+hipError_t launch_solve(const CallDev& call, const LdsPlan& L, const SceneDev& s0,
                         const sbr_candidate* uniq, const RefineOut* rf, const PathGeom* geom,
                         int64_t U_max, const int32_t* n_dev, sbr_path* paths, int32_t* keep,
-                        float delta, int32_t* err, hipStream_t s);
+                        int32_t* err, hipStream_t s);
 
 hipError_t launch_compact_paths(const sbr_path* paths, const int32_t* keep, const int32_t* offs,
                                 int64_t U, sbr_path* out, hipStream_t s);
@@ -173,6 +182,5 @@ hipError_t launch_dedup_small(const sbr_candidate* C, int64_t n, sbr_candidate* 
                               int32_t* n_unique, hipStream_t s);
 hipError_t launch_emit_small(const sbr_path* paths, const int32_t* keep, int64_t U_max,
                              const int32_t* n_dev, sbr_path* out, int32_t* n_paths, hipStream_t s);
-
 
 }  // namespace sbr

@@ -75,12 +75,12 @@ __device__ static inline void store_geom(PathGeom* g, int k, const d3* pts, cons
 // lengths of the stop rule.  Returns false if the replay does not reproduce
 // the path.
 template <bool LDS>
-__device__ static inline bool start_path(const SceneDev& S, const LdsPlan& L, const RefineArgs& A,
+__device__ static inline bool start_path(const SceneDev& S, const LdsPlan& L, double tan_tgt,
                                          const sbr_candidate& c, d3 tx, d3 rx, d3 axis,
                                          float delta, int32_t* err, double* tan, bool* met)
 {
     *met = false;
-    if (!(A.tan_tgt > 0.0)) {
+    if (!(tan_tgt > 0.0)) {
         *tan = c.tan_err;
         return true;
     }
@@ -88,7 +88,7 @@ __device__ static inline bool start_path(const SceneDev& S, const LdsPlan& L, co
     if (!follow<LDS>(S, L, tx, axis, rx, c.order, c.face, delta, &F0, nullptr, nullptr, err))
         return false;
     *tan = F0.tan_err;
-    *met = target_met(F0.tan_err, A.tan_tgt, F0.D, F0.Llast);
+    *met = target_met(F0.tan_err, tan_tgt, F0.D, F0.Llast);
     return true;
 }
 
@@ -105,42 +105,44 @@ __device__ static inline RefineOut stalled_at_start(d3 axis)
 // Eight lanes per path: lane s traces sub-ray s (s < subrays); the group
 // keeps the smallest error angle (ties: lower s) as the next axis.
 template <bool LDS>
-__global__ __launch_bounds__(256) void k_refine(SceneDev S, LdsPlan L, GridDev g, RefineArgs A,
-                                                float delta,
+__global__ __launch_bounds__(256) void k_refine(CallDev call, LdsPlan L, SceneDev s0,
                                                 const sbr_candidate* __restrict__ uniq,
                                                 int64_t U_max, const int32_t* __restrict__ n_dev,
                                                 RefineOut* __restrict__ out,
                                                 PathGeom* __restrict__ geom,
                                                 int32_t* __restrict__ err)
 {
-    if (LDS) stage_scene(S, L);
+    if (LDS) stage_scene(s0, L);
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t p = gid >> 3;
     int s = (int)(gid & 7);
     const int64_t U = n_dev ? min(U_max, (int64_t)*n_dev) : U_max;
     if (p >= U) return;
     const sbr_candidate c = uniq[p];
-    const d3 tx = mk(A.tx[0], A.tx[1], A.tx[2]);
-    const d3 rx = mk(A.rx[3 * c.rx], A.rx[3 * c.rx + 1], A.rx[3 * c.rx + 2]);
-    d3 axis = mk(g.dir[c.ray], g.dir[g.N + c.ray], g.dir[2 * g.N + c.ray]);
+    int jb = call.rx_job[c.rx];
+    const JobDev J = call.jobs[jb];
+    const SceneDev S = LDS ? s0 : call.scenes[J.scene];
+    const d3 tx = mk(J.tx[0], J.tx[1], J.tx[2]);
+    const d3 rx = mk(call.rx[3 * c.rx], call.rx[3 * c.rx + 1], call.rx[3 * c.rx + 2]);
+    d3 axis = mk(J.dir[c.ray], J.dir[J.N + c.ray], J.dir[2 * J.N + c.ray]);
     double tan;
     bool met;
-    if (!start_path<LDS>(S, L, A, c, tx, rx, axis, delta, err, &tan, &met)) {
+    if (!start_path<LDS>(S, L, J.tan_tgt, c, tx, rx, axis, J.delta, err, &tan, &met)) {
         if (s == 0) out[p] = stalled_at_start(axis);
         return;
     }
     uint32_t flags = met ? SBR_PATH_TARGET_MET : 0u;
     int32_t iters = 0;
-    double rho = A.thl;
-    for (int i = 1; i <= A.iterations && !met; ++i) {
+    double rho = J.thl;
+    for (int i = 1; i <= J.iterations && !met; ++i) {
         rho = rho / sqrt(3.0);
         d3 u, v;
         basis(axis, &u, &v);
         Follow F;
         bool ok = false;
         d3 gp[SBR_MAX_ORDER], gd[SBR_MAX_ORDER];
-        if (s < A.subrays)
-            ok = follow<LDS>(S, L, tx, subray(axis, u, v, rho, s), rx, c.order, c.face, delta, &F,
+        if (s < J.subrays)
+            ok = follow<LDS>(S, L, tx, subray(axis, u, v, rho, s), rx, c.order, c.face, J.delta, &F,
                              gp, gd, err);
         double bt = ok ? F.tan_err : INFINITY;
         int bs = ok ? s : 8;
@@ -164,7 +166,7 @@ __global__ __launch_bounds__(256) void k_refine(SceneDev S, LdsPlan L, GridDev g
         axis = subray(axis, u, v, rho, bs);
         tan = bt;
         iters = i;
-        if (A.tan_tgt > 0.0 && target_met(bt, A.tan_tgt, wD, wL)) {
+        if (J.tan_tgt > 0.0 && target_met(bt, J.tan_tgt, wD, wL)) {
             flags |= SBR_PATH_TARGET_MET;
             met = true;
         }
@@ -187,8 +189,7 @@ __global__ __launch_bounds__(256) void k_refine(SceneDev S, LdsPlan L, GridDev g
 // arithmetic of the one-iteration-at-a-time order, so the result is the same
 // bit for bit; the latency of two iterations becomes that of one.
 template <bool LDS>
-__global__ __launch_bounds__(256) void k_refine_la(SceneDev S, LdsPlan L, GridDev g, RefineArgs A,
-                                                   float delta,
+__global__ __launch_bounds__(256) void k_refine_la(CallDev call, LdsPlan L, SceneDev s0,
                                                    const sbr_candidate* __restrict__ uniq,
                                                    int64_t U_max,
                                                    const int32_t* __restrict__ n_dev,
@@ -196,7 +197,7 @@ __global__ __launch_bounds__(256) void k_refine_la(SceneDev S, LdsPlan L, GridDe
                                                    PathGeom* __restrict__ geom,
                                                    int32_t* __restrict__ err)
 {
-    if (LDS) stage_scene(S, L);
+    if (LDS) stage_scene(s0, L);
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t p = gid >> 6;
     const int lane = (int)(gid & 63);
@@ -204,26 +205,30 @@ __global__ __launch_bounds__(256) void k_refine_la(SceneDev S, LdsPlan L, GridDe
     const int64_t U = n_dev ? min(U_max, (int64_t)*n_dev) : U_max;
     if (p >= U) return;
     const sbr_candidate c = uniq[p];
-    const d3 tx = mk(A.tx[0], A.tx[1], A.tx[2]);
-    const d3 rx = mk(A.rx[3 * c.rx], A.rx[3 * c.rx + 1], A.rx[3 * c.rx + 2]);
-    d3 axis = mk(g.dir[c.ray], g.dir[g.N + c.ray], g.dir[2 * g.N + c.ray]);
+    int jb = call.rx_job[c.rx];
+    jb = __builtin_amdgcn_readfirstlane(jb);  // one path per wave
+    const JobDev J = call.jobs[jb];
+    const SceneDev S = LDS ? s0 : call.scenes[J.scene];
+    const d3 tx = mk(J.tx[0], J.tx[1], J.tx[2]);
+    const d3 rx = mk(call.rx[3 * c.rx], call.rx[3 * c.rx + 1], call.rx[3 * c.rx + 2]);
+    d3 axis = mk(J.dir[c.ray], J.dir[J.N + c.ray], J.dir[2 * J.N + c.ray]);
     double tan;
     bool met;
-    if (!start_path<LDS>(S, L, A, c, tx, rx, axis, delta, err, &tan, &met)) {
+    if (!start_path<LDS>(S, L, J.tan_tgt, c, tx, rx, axis, J.delta, err, &tan, &met)) {
         if (lane == 0) out[p] = stalled_at_start(axis);
         return;
     }
     uint32_t flags = met ? SBR_PATH_TARGET_MET : 0u;
     int32_t iters = 0;
-    double rho = A.thl;
-    for (int i = 1; i <= A.iterations && !met; i += 2) {
+    double rho = J.thl;
+    for (int i = 1; i <= J.iterations && !met; i += 2) {
         const double rho1 = rho / sqrt(3.0);
         const double rho2 = rho1 / sqrt(3.0);
         d3 u, v;
         basis(axis, &u, &v);
-        const bool two = i + 1 <= A.iterations;
-        const bool lvl1 = s2 == 7 && s1 < A.subrays;
-        const bool lvl2 = two && s2 < A.subrays && s1 < A.subrays;
+        const bool two = i + 1 <= J.iterations;
+        const bool lvl1 = s2 == 7 && s1 < J.subrays;
+        const bool lvl2 = two && s2 < J.subrays && s1 < J.subrays;
         Follow F;
         bool ok = false;
         d3 gp[SBR_MAX_ORDER], gd[SBR_MAX_ORDER];
@@ -234,7 +239,7 @@ __global__ __launch_bounds__(256) void k_refine_la(SceneDev S, LdsPlan L, GridDe
                 basis(dt, &u2, &v2);
                 dt = subray(dt, u2, v2, rho2, s2);
             }
-            ok = follow<LDS>(S, L, tx, dt, rx, c.order, c.face, delta, &F, gp, gd, err);
+            ok = follow<LDS>(S, L, tx, dt, rx, c.order, c.face, J.delta, &F, gp, gd, err);
         }
         const double myD = ok ? F.D : 0.0, myL = ok ? F.Llast : 0.0;
         // first level: argmin over lanes (s1, 7)
@@ -262,7 +267,7 @@ __global__ __launch_bounds__(256) void k_refine_la(SceneDev S, LdsPlan L, GridDe
         tan = k1;
         iters = i;
         rho = rho1;
-        if (A.tan_tgt > 0.0 && target_met(k1, A.tan_tgt, wD, wL)) {
+        if (J.tan_tgt > 0.0 && target_met(k1, J.tan_tgt, wD, wL)) {
             flags |= SBR_PATH_TARGET_MET;
             break;
         }
@@ -294,7 +299,7 @@ __global__ __launch_bounds__(256) void k_refine_la(SceneDev S, LdsPlan L, GridDe
         tan = k2;
         iters = i + 1;
         rho = rho2;
-        if (A.tan_tgt > 0.0 && target_met(k2, A.tan_tgt, wD, wL)) {
+        if (J.tan_tgt > 0.0 && target_met(k2, J.tan_tgt, wD, wL)) {
             flags |= SBR_PATH_TARGET_MET;
             break;
         }
@@ -309,29 +314,26 @@ __global__ __launch_bounds__(256) void k_refine_la(SceneDev S, LdsPlan L, GridDe
     }
 }
 
-hipError_t launch_refine(const SceneDev& S, const LdsPlan& L, const GridDev& g,
-                         const RefineArgs& A, const sbr_candidate* uniq, int64_t U,
-                         const int32_t* n_dev, RefineOut* out, PathGeom* geom, float delta,
-                         int32_t* err, hipStream_t s)
+hipError_t launch_refine(const CallDev& call, const LdsPlan& L, const SceneDev& s0,
+                         const sbr_candidate* uniq, int64_t U, const int32_t* n_dev,
+                         bool lookahead, RefineOut* out, PathGeom* geom, int32_t* err,
+                         hipStream_t s)
 {
     if (U <= 0) return hipSuccess;
-    // Few paths: the hardware is mostly idle, so spend 64 lanes per path on
-    // the two-iteration lookahead; many paths: 8 lanes per path.
-    const bool la = U <= A.lookahead_max_paths && A.iterations >= 2;
-    int64_t threads = U * (la ? 64 : 8);
+    int64_t threads = U * (lookahead ? 64 : 8);
     dim3 grid((unsigned)((threads + L.block - 1) / L.block));
-    if (la && L.bytes > 0)
-        hipLaunchKernelGGL(k_refine_la<true>, grid, dim3(L.block), L.bytes, s, S, L, g, A, delta,
-                           uniq, U, n_dev, out, geom, err);
-    else if (la)
-        hipLaunchKernelGGL(k_refine_la<false>, grid, dim3(L.block), 0, s, S, L, g, A, delta, uniq,
+    if (lookahead && L.bytes > 0)
+        hipLaunchKernelGGL(k_refine_la<true>, grid, dim3(L.block), L.bytes, s, call, L, s0, uniq,
                            U, n_dev, out, geom, err);
-    else if (L.bytes > 0)
-        hipLaunchKernelGGL(k_refine<true>, grid, dim3(L.block), L.bytes, s, S, L, g, A, delta,
-                           uniq, U, n_dev, out, geom, err);
-    else
-        hipLaunchKernelGGL(k_refine<false>, grid, dim3(L.block), 0, s, S, L, g, A, delta, uniq, U,
+    else if (lookahead)
+        hipLaunchKernelGGL(k_refine_la<false>, grid, dim3(L.block), 0, s, call, L, s0, uniq, U,
                            n_dev, out, geom, err);
+    else if (L.bytes > 0)
+        hipLaunchKernelGGL(k_refine<true>, grid, dim3(L.block), L.bytes, s, call, L, s0, uniq, U,
+                           n_dev, out, geom, err);
+    else
+        hipLaunchKernelGGL(k_refine<false>, grid, dim3(L.block), 0, s, call, L, s0, uniq, U, n_dev,
+                           out, geom, err);
     return hipGetLastError();
 }
 
@@ -479,7 +481,7 @@ __device__ static inline double poly_length(d3 tx, const d3* p, int k, d3 rx)
 // (reflection point j inside its face, segment j unobstructed), so path
 // test 2 costs one traversal of latency instead of k + 1.
 template <bool LDS>
-__global__ __launch_bounds__(256) void k_solve(SceneDev S, LdsPlan L, SolveArgs A, float delta,
+__global__ __launch_bounds__(256) void k_solve(CallDev call, LdsPlan L, SceneDev s0,
                                                const sbr_candidate* __restrict__ uniq,
                                                const RefineOut* __restrict__ rf,
                                                const PathGeom* __restrict__ geom, int64_t U_max,
@@ -488,16 +490,19 @@ __global__ __launch_bounds__(256) void k_solve(SceneDev S, LdsPlan L, SolveArgs 
                                                int32_t* __restrict__ keep,
                                                int32_t* __restrict__ err)
 {
-    if (LDS) stage_scene(S, L);
+    if (LDS) stage_scene(s0, L);
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t p = gid >> 4;
     int lane = (int)(gid & 15);
     const int64_t U = n_dev ? min(U_max, (int64_t)*n_dev) : U_max;
     if (p >= U) return;
     const sbr_candidate c = uniq[p];
+    const JobDev J = call.jobs[call.rx_job[c.rx]];
+    const SceneDev S = LDS ? s0 : call.scenes[J.scene];
+    const float delta = J.delta;
     const int k = c.order;
-    const d3 tx = mk(A.tx[0], A.tx[1], A.tx[2]);
-    const d3 rx = mk(A.rx[3 * c.rx], A.rx[3 * c.rx + 1], A.rx[3 * c.rx + 2]);
+    const d3 tx = mk(J.tx[0], J.tx[1], J.tx[2]);
+    const d3 rx = mk(call.rx[3 * c.rx], call.rx[3 * c.rx + 1], call.rx[3 * c.rx + 2]);
     d3 ep[SBR_MAX_ORDER];
     const bool geo_ok = image_points(S, tx, rx, k, c.face, ep);
     bool bad = false;
@@ -555,7 +560,7 @@ __global__ __launch_bounds__(256) void k_solve(SceneDev S, LdsPlan L, SolveArgs 
     st3(o.aoa, normalize(sub(last, rx)));
     double refl[SBR_MAX_ORDER];
     for (int j = 0; j < k; ++j) refl[j] = refl_at(S, c.face[j], din[j]);
-    o.power_dbm = path_power(A.tx_power_dbm, A.freq_hz, Lr, refl, k);
+    o.power_dbm = path_power(J.tx_power_dbm, J.freq_hz, Lr, refl, k);
     o.err_angle_deg = atan(R.tan_err) * (180.0 / kPi);
     // exact path of the same faces
     const bool ok = geo_ok && !any_bad;
@@ -571,26 +576,26 @@ __global__ __launch_bounds__(256) void k_solve(SceneDev S, LdsPlan L, SolveArgs 
         refl[j] = refl_at(S, c.face[j], sub(ep[j], prev));
         prev = ep[j];
     }
-    o.exact_power_dbm = path_power(A.tx_power_dbm, A.freq_hz, EL, refl, k);
+    o.exact_power_dbm = path_power(J.tx_power_dbm, J.freq_hz, EL, refl, k);
     if (!ok) o.flags |= SBR_PATH_INVALID;
     paths[p] = o;
-    keep[p] = (ok || A.keep_invalid) ? 1 : 0;
+    keep[p] = (ok || J.keep_invalid) ? 1 : 0;
 }
 
-hipError_t launch_solve(const SceneDev& S, const LdsPlan& L, const SolveArgs& A,
+hipError_t launch_solve(const CallDev& call, const LdsPlan& L, const SceneDev& s0,
                         const sbr_candidate* uniq, const RefineOut* rf, const PathGeom* geom,
                         int64_t U, const int32_t* n_dev, sbr_path* paths, int32_t* keep,
-                        float delta, int32_t* err, hipStream_t s)
+                        int32_t* err, hipStream_t s)
 {
     if (U <= 0) return hipSuccess;
     int64_t threads = U * 16;
     dim3 grid((unsigned)((threads + L.block - 1) / L.block));
     if (L.bytes > 0)
-        hipLaunchKernelGGL(k_solve<true>, grid, dim3(L.block), L.bytes, s, S, L, A, delta, uniq,
-                           rf, geom, U, n_dev, paths, keep, err);
-    else
-        hipLaunchKernelGGL(k_solve<false>, grid, dim3(L.block), 0, s, S, L, A, delta, uniq, rf,
+        hipLaunchKernelGGL(k_solve<true>, grid, dim3(L.block), L.bytes, s, call, L, s0, uniq, rf,
                            geom, U, n_dev, paths, keep, err);
+    else
+        hipLaunchKernelGGL(k_solve<false>, grid, dim3(L.block), 0, s, call, L, s0, uniq, rf, geom,
+                           U, n_dev, paths, keep, err);
     return hipGetLastError();
 }
 

@@ -39,7 +39,7 @@ PATH_TARGET_MET = 4
 EXPORTS = (
     "sbr_context_create", "sbr_context_destroy", "sbr_scene_upload", "sbr_bvh_build",
     "sbr_scene_destroy", "sbr_trace", "sbr_candidates", "sbr_launch_grid", "sbr_trace_rays",
-    "sbr_trace_counters",
+    "sbr_trace_counters", "sbr_trace_batch",
     "sbr_status_string", "sbr_last_error",
 )
 
@@ -56,6 +56,11 @@ class TraceParams(C.Structure):
         ("flags", C.c_uint32),
         ("reserved", C.c_int32),
     ]
+
+
+class Job(C.Structure):
+    _fields_ = [("scene", C.c_int32), ("rx_first", C.c_int32), ("n_rx", C.c_int32),
+                ("reserved", C.c_int32), ("tx", C.c_double * 3), ("params", TraceParams)]
 
 
 class Complex(C.Structure):
@@ -146,6 +151,8 @@ def lib(load_torch: bool = True):
     L.sbr_launch_grid.argtypes = [vp, C.c_int32, C.c_int64, C.c_int64, dp]
     L.sbr_trace_rays.argtypes = [vp, dp, C.c_int32, C.c_int32, C.c_int64, C.c_int64, ip, dp]
     L.sbr_trace_counters.argtypes = [vp, dp, dp, C.c_int32, C.POINTER(TraceParams), lp]
+    L.sbr_trace_batch.argtypes = [vp, C.POINTER(vp), C.c_int32, C.POINTER(Job), C.c_int32, dp,
+                                  C.c_int32, vp, C.c_int64, lp, C.POINTER(TraceStats)]
     for name in EXPORTS:
         getattr(L, name).restype = getattr(L, name).restype or C.c_int32
     L.sbr_status_string.restype = C.c_char_p
@@ -203,6 +210,31 @@ class Context:
 
     def scene(self, scene: dict, max_leaf_size: int = 4, sah_bins: int = 16) -> "Scene":
         return Scene(self, scene, max_leaf_size, sah_bins)
+
+    def trace_batch(self, scenes, jobs, rx, capacity: int | None = None):
+        """sbr_trace_batch.  scenes: list of Scene; jobs: list of dicts with
+        scene (index), tx, rx_first, n_rx and trace parameters (as for
+        Scene.trace); rx: [n_rx_total, 3].  Returns (paths, stats)."""
+        rxa = np.ascontiguousarray(rx, np.float64).reshape(-1, 3)
+        sh = (C.c_void_p * len(scenes))(*[s.h for s in scenes])
+        arr = (Job * max(len(jobs), 1))()
+        for i, j in enumerate(jobs):
+            prm = {k: v for k, v in j.items() if k not in ("scene", "tx", "rx_first", "n_rx")}
+            arr[i] = Job(int(j["scene"]), int(j["rx_first"]), int(j["n_rx"]), 0,
+                         (C.c_double * 3)(*[float(v) for v in j["tx"]]), make_params(**prm))
+        cap = capacity if capacity is not None else 16384
+        while True:
+            out = np.zeros(max(cap, 1), PATH_DTYPE)
+            n = C.c_int64()
+            stats = TraceStats()
+            st = lib().sbr_trace_batch(self.h, sh, len(scenes), arr, len(jobs), _d(rxa), len(rxa),
+                                       out.ctypes.data_as(C.c_void_p), cap, C.byref(n),
+                                       C.byref(stats))
+            if st == E_CAPACITY and capacity is None:
+                cap = n.value
+                continue
+            self._check(st)
+            return out[: n.value].copy(), stats.as_dict()
 
     def close(self):
         for s in list(self.scenes):

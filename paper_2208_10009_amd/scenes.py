@@ -141,3 +141,62 @@ def manhattan_config(seed=0, n_rx=64):
         "rx": rx,
         "params": dict(max_order=6, division_n=200, iterations=5, subrays=7, freq_hz=28e9),
     }
+
+
+def box_city(seed, n_buildings, pitch=40.0):
+    """A square grid of closed box buildings (12 triangles, 6 faces each) on
+    `pitch` m centres (footprints U(20, 30) m, heights U(10, 60) m, concrete)
+    plus a ground quad one pitch beyond the grid (15 - 1j): 12 n + 2
+    triangles.  Streets run along x = pitch i and y = pitch j."""
+    rng = np.random.default_rng(seed)
+    side = int(np.ceil(np.sqrt(max(n_buildings, 1))))
+    b = SceneBuilder()
+    placed = 0
+    for i in range(side):
+        for j in range(side):
+            if placed == n_buildings:
+                break
+            cx, cy = pitch * i + pitch / 2, pitch * j + pitch / 2
+            w, d = rng.uniform(20.0, 30.0, size=2)
+            h = rng.uniform(10.0, 60.0)
+            b.box((cx - w / 2, cy - d / 2, 0.0), (cx + w / 2, cy + d / 2, h), 0)
+            placed += 1
+    lo, hi = -pitch, pitch * side + pitch
+    b.quad((lo, lo, 0.0), (hi, lo, 0.0), (hi, hi, 0.0), (lo, hi, 0.0), 1)
+    return b.scene([CONCRETE, GROUND]), side * pitch
+
+
+def _street_point(rng, extent, pitch, z):
+    along = rng.uniform(0.0, extent)
+    line = rng.integers(0, int(extent // pitch) + 1) * pitch
+    return np.array([along, line, z]) if rng.integers(0, 2) else np.array([line, along, z])
+
+
+def batch_config(seed=0, n_scenes=16, n_pairs=256, tri_min=200, tri_max=50000, n_range=(50, 400),
+                 order_range=(3, 8), iterations=5, subrays=7):
+    """Batched workload: n_scenes seeded box-building cities whose triangle
+    counts are log-uniform in [tri_min, tri_max], and n_pairs Tx/Rx pairs
+    spread unevenly over them (Dirichlet(0.5) shares), each with its own
+    division n (uniform in n_range, 10 n^2 + 2 rays) and maximum order
+    (uniform in order_range); Tx 5-30 m and Rx 1.5 m above street centrelines,
+    28 GHz."""
+    rng = np.random.default_rng(seed + 5000)
+    tris = np.exp(rng.uniform(np.log(tri_min), np.log(tri_max), size=n_scenes))
+    scenes, extents = [], []
+    for s in range(n_scenes):
+        sc, ext = box_city(seed * 100 + s, max(1, int(round((tris[s] - 2) / 12))))
+        scenes.append(sc)
+        extents.append(ext)
+    share = rng.dirichlet(np.full(n_scenes, 0.5))
+    counts = rng.multinomial(n_pairs, share)
+    jobs, rx = [], []
+    for s in range(n_scenes):
+        for _ in range(counts[s]):
+            tx = _street_point(rng, extents[s], 40.0, rng.uniform(5.0, 30.0))
+            rx.append(_street_point(rng, extents[s], 40.0, 1.5))
+            jobs.append(dict(scene=s, tx=tx, rx_first=len(rx) - 1, n_rx=1,
+                             max_order=int(rng.integers(order_range[0], order_range[1] + 1)),
+                             division_n=int(rng.integers(n_range[0], n_range[1] + 1)),
+                             iterations=iterations, subrays=subrays, freq_hz=28e9))
+    return {"name": "batch_%dscenes_%dpairs" % (n_scenes, n_pairs), "scenes": scenes,
+            "jobs": jobs, "rx": np.array(rx, np.float64).reshape(-1, 3)}

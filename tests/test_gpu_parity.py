@@ -354,3 +354,83 @@ def test_many_events_multikernel_path(gpu, orc):
     _compare_paths(g, r["paths"])
     o = _sorted_oracle_cands(r["candidates"])
     assert len(cands) == len(o) and np.array_equal(cands["ray"], o["ray"])
+
+
+# ---------------------------------------------------------------- batched --
+def _small_batch(seed=3):
+    return scenes.batch_config(seed, n_scenes=4, n_pairs=10, tri_min=100, tri_max=2000,
+                               n_range=(15, 45), order_range=(1, 5), iterations=4)
+
+
+def _individual(gpu, b):
+    """Each job traced alone with sbr_trace, receivers renumbered to the
+    batch's array."""
+    scs = [gpu.scene(s) for s in b["scenes"]]
+    parts = []
+    try:
+        for j in b["jobs"]:
+            prm = {k: v for k, v in j.items() if k not in ("scene", "tx", "rx_first", "n_rx")}
+            rx = b["rx"][j["rx_first"]:j["rx_first"] + j["n_rx"]]
+            p, _ = scs[j["scene"]].trace(j["tx"], rx, **prm)
+            p["rx"] += j["rx_first"]
+            parts.append(p)
+    finally:
+        for s in scs:
+            s.close()
+    allp = np.concatenate(parts) if parts else np.zeros(0, parts[0].dtype)
+    order = np.lexsort((*[allp["face"][:, j] for j in range(7, -1, -1)], allp["order"],
+                        allp["rx"]))
+    return allp[order]
+
+
+def test_batch_equals_individual_traces(gpu):
+    """sbr_trace_batch (one persistent trace launch over all jobs and scenes)
+    returns byte for byte the paths of the jobs traced one by one."""
+    b = _small_batch()
+    ref = _individual(gpu, b)
+    scs = [gpu.scene(s) for s in b["scenes"]]
+    try:
+        got, st = gpu.trace_batch(scs, b["jobs"], b["rx"])
+    finally:
+        for s in scs:
+            s.close()
+    assert len(ref) > 10
+    assert st["n_rays"] == sum(10 * j["division_n"] ** 2 + 2 for j in b["jobs"])
+    assert got.tobytes() == ref.tobytes()
+
+
+def test_batch_job_matches_oracle(gpu, orc):
+    b = _small_batch(5)
+    scs = [gpu.scene(s) for s in b["scenes"]]
+    try:
+        got, _ = gpu.trace_batch(scs, b["jobs"], b["rx"])
+    finally:
+        for s in scs:
+            s.close()
+    for j in b["jobs"][:4]:
+        prm = {k: v for k, v in j.items() if k not in ("scene", "tx", "rx_first", "n_rx")}
+        rx = b["rx"][j["rx_first"]:j["rx_first"] + j["n_rx"]]
+        o = orc.run(b["scenes"][j["scene"]], j["tx"], rx, **prm)["paths"]
+        g = got[(got["rx"] >= j["rx_first"]) & (got["rx"] < j["rx_first"] + j["n_rx"])].copy()
+        g["rx"] -= j["rx_first"]
+        _compare_paths(g, o)
+
+
+def test_batch_argument_errors(gpu):
+    from paper_2208_10009_amd import sbr
+    b = _small_batch()
+    scs = [gpu.scene(s) for s in b["scenes"][:2]]
+    try:
+        bad = [dict(b["jobs"][0], scene=5)]
+        with pytest.raises(sbr.SbrError) as e:
+            gpu.trace_batch(scs, bad, b["rx"])
+        assert e.value.status == sbr.E_INVALID_ARG
+        bad = [dict(b["jobs"][0], scene=0, rx_first=0, n_rx=2),
+               dict(b["jobs"][1], scene=1, rx_first=1, n_rx=1)]
+        with pytest.raises(sbr.SbrError):
+            gpu.trace_batch(scs, bad, b["rx"])  # receiver 1 in two jobs
+        p, st = gpu.trace_batch(scs, [], b["rx"])
+        assert len(p) == 0 and st["n_rays"] == 0
+    finally:
+        for s in scs:
+            s.close()
