@@ -91,6 +91,7 @@ def batch_vs_plain(ctx, scenes, torch, seed=0, steps=2):
     pair refined to 0.01 deg: one sbr_trace_batch call (persistent trace
     over all jobs) against one sbr_trace call per pair.  Launch grids are
     cached (both sides), the scenes' BVHs are built beforehand."""
+    from paper_2208_10009_amd import autotune
     b = scenes.batch_config(seed)
     jobs = [dict(j, iterations=30, target_err_deg=0.01) for j in b["jobs"]]
     n_rays = sum(10 * j["division_n"] ** 2 + 2 for j in jobs)
@@ -98,6 +99,11 @@ def batch_vs_plain(ctx, scenes, torch, seed=0, steps=2):
     scs = [ctx.scene(s) for s in b["scenes"]]
     build_s = time.perf_counter() - t0
     ctx.trace_batch(scs, jobs, b["rx"])  # warm-up: launch grids of every n
+    base = ctx.tuning()
+    best, trials = autotune.autotune(
+        ctx, lambda: ctx.trace_batch(scs, jobs, b["rx"]),
+        space={"trace_chunk": [1, 2, 4], "persist_blocks": [1024, 2048, 4096, 8192],
+               "lookahead_max_paths": [0, 4096]}, warmup=0, steps=1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -114,6 +120,7 @@ def batch_vs_plain(ctx, scenes, torch, seed=0, steps=2):
             got.append(p)
         return np.concatenate(got)
 
+    ctx.set_tuning(**base)  # one call per pair: the default tuning
     plain_pass()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -123,11 +130,13 @@ def batch_vs_plain(ctx, scenes, torch, seed=0, steps=2):
     tp = (time.perf_counter() - t0) / steps
     for sc in scs:
         sc.close()
+    ctx.set_tuning(**base)
     gb, gp = int(accurate_mask(pb).sum()), int(accurate_mask(pp).sum())
     return {
         "workload": "batch_16scenes_200-50k_tri_256pairs_n50-400_k3-8_target0.01deg",
         "triangles": [int(len(s["tri"])) for s in b["scenes"]], "pairs": len(jobs),
         "rays": int(n_rays), "bvh_build_s": round(build_s, 3),
+        "tuning": best, "tuning_trials": len(trials),
         "batched": {"ms": round(1e3 * tb, 3), "rays_per_s": n_rays / tb,
                     "paths": int(len(pb)), "within_0.01deg": gb,
                     "refined_paths_per_s": gb / tb,
@@ -135,6 +144,7 @@ def batch_vs_plain(ctx, scenes, torch, seed=0, steps=2):
                                  ("ms_launch", "ms_trace", "ms_dedup", "ms_refine", "ms_solve",
                                   "ms_emit", "ms_total")}},
         "plain": {"ms": round(1e3 * tp, 3), "rays_per_s": n_rays / tp, "paths": int(len(pp)),
+                  "tuning": base,
                   "within_0.01deg": gp, "refined_paths_per_s": gp / tp},
         "speedup": tp / tb,
     }
@@ -179,6 +189,12 @@ def main():
 
     counts = sc.trace_counters(cfg["tx"], cfg["rx"], **prm)
     log("counts", counts)
+    from paper_2208_10009_amd import autotune
+    best, _ = autotune.autotune(
+        ctx, lambda: sc.trace(cfg["tx"], cfg["rx"], **prm),
+        space={"trace_chunk": [1, 2], "persist_blocks": [1024, 2048, 4096],
+               "lds_budget": [0], "lookahead_max_paths": [4096]}, warmup=1, steps=5)
+    log("tuning", best)
 
     def timed(steps, warmup, **kw):
         for _ in range(warmup):
@@ -264,6 +280,7 @@ def main():
         "stage_ms": {k: round(v, 5) for k, v in stage.items()},
         "counts": counts,
         "lds": {k: int(stats[-1][k]) for k in ("lds_bytes", "lds_nodes", "lds_tris", "lds_max")},
+        "tuning": ctx.tuning(),
         "roofline": roofline,
     }
     sc.close()

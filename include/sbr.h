@@ -118,6 +118,28 @@ typedef struct {
     int32_t sah_bins;      /* 4..64 */
 } sbr_bvh_params;
 
+/* Launch tuning of a context (the results never depend on it).  The trace
+ * kernel is persistent: waves take packets of 64 * trace_chunk rays from a
+ * device queue; persist_blocks workgroups are launched.  lds_budget > 0
+ * stages the BVH's top nodes (and all triangles when they fit) plus a
+ * stack_depth-entry traversal stack per lane in LDS, with trace_block lanes
+ * per workgroup; 0 traverses from global memory (256 lanes per workgroup).
+ * The refinement resolves two iterations per step with one wave per path
+ * when there are at most lookahead_max_paths paths. */
+typedef struct {
+    int32_t trace_chunk;         /* 1..64                                   */
+    int32_t persist_blocks;      /* >= 1                                    */
+    int32_t trace_block;         /* 64..1024, multiple of 64 (LDS staging)  */
+    int32_t stack_depth;         /* 0..64                                   */
+    int32_t lds_budget;          /* bytes, 0..device limit per workgroup    */
+    int32_t reserved;            /* must be 0                               */
+    int64_t lookahead_max_paths; /* >= 0                                    */
+} sbr_tuning;
+
+sbr_status sbr_context_get_tuning(const sbr_context* ctx, sbr_tuning* out);
+/* Errors: SBR_E_INVALID_ARG when a field is out of range. */
+sbr_status sbr_context_set_tuning(sbr_context* ctx, const sbr_tuning* tuning);
+
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t the
  * caller owns (for example torch's current stream) or NULL for the default
  * stream.  Errors: SBR_E_INVALID_ARG (bad device / out == NULL), SBR_E_DEVICE. */

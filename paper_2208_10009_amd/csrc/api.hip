@@ -195,7 +195,7 @@ LdsPlan plan_for(const sbr_scene* s, int block)
     const sbr_context* c = s->ctx;
     if (c->lds_budget <= 0) {  // global-memory traversal, private stack
         LdsPlan L{};
-        L.block = block;
+        L.block = 256;
         return L;
     }
     return make_lds_plan(s->n_nodes, s->T, block, c->stack_depth, c->lds_budget);
@@ -641,6 +641,38 @@ sbr_status sbr_context_create(int32_t device, void* hip_stream, sbr_context** ou
         return SBR_E_DEVICE;
     }
     *out = c;
+    return SBR_OK;
+}
+
+sbr_status sbr_context_get_tuning(const sbr_context* c, sbr_tuning* t)
+{
+    if (!c || !t) return SBR_E_INVALID_ARG;
+    t->trace_chunk = c->trace_chunk;
+    t->persist_blocks = c->persist_blocks;
+    t->trace_block = c->trace_block;
+    t->stack_depth = c->stack_depth;
+    t->lds_budget = c->lds_budget;
+    t->reserved = 0;
+    t->lookahead_max_paths = c->lookahead_max_paths;
+    return SBR_OK;
+}
+
+sbr_status sbr_context_set_tuning(sbr_context* c, const sbr_tuning* t)
+{
+    if (!c) return SBR_E_INVALID_ARG;
+    c->err.clear();
+    if (!t) return fail(c, SBR_E_INVALID_ARG, "tuning is NULL");
+    if (t->trace_chunk < 1 || t->trace_chunk > 64 || t->persist_blocks < 1 ||
+        t->trace_block < 64 || t->trace_block > 1024 || t->trace_block % 64 != 0 ||
+        t->stack_depth < 0 || t->stack_depth > kTraceStack || t->lds_budget < 0 ||
+        t->lds_budget > c->lds_max || t->reserved != 0 || t->lookahead_max_paths < 0)
+        return fail(c, SBR_E_INVALID_ARG, "tuning field out of range");
+    c->trace_chunk = t->trace_chunk;
+    c->persist_blocks = t->persist_blocks;
+    c->trace_block = t->trace_block;
+    c->stack_depth = t->stack_depth;
+    c->lds_budget = t->lds_budget;
+    c->lookahead_max_paths = t->lookahead_max_paths;
     return SBR_OK;
 }
 

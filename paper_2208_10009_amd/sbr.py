@@ -39,7 +39,7 @@ PATH_TARGET_MET = 4
 EXPORTS = (
     "sbr_context_create", "sbr_context_destroy", "sbr_scene_upload", "sbr_bvh_build",
     "sbr_scene_destroy", "sbr_trace", "sbr_candidates", "sbr_launch_grid", "sbr_trace_rays",
-    "sbr_trace_counters", "sbr_trace_batch",
+    "sbr_trace_counters", "sbr_trace_batch", "sbr_context_get_tuning", "sbr_context_set_tuning",
     "sbr_status_string", "sbr_last_error",
 )
 
@@ -61,6 +61,16 @@ class TraceParams(C.Structure):
 class Job(C.Structure):
     _fields_ = [("scene", C.c_int32), ("rx_first", C.c_int32), ("n_rx", C.c_int32),
                 ("reserved", C.c_int32), ("tx", C.c_double * 3), ("params", TraceParams)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("trace_chunk", C.c_int32), ("persist_blocks", C.c_int32),
+                ("trace_block", C.c_int32), ("stack_depth", C.c_int32),
+                ("lds_budget", C.c_int32), ("reserved", C.c_int32),
+                ("lookahead_max_paths", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class Complex(C.Structure):
@@ -151,6 +161,8 @@ def lib(load_torch: bool = True):
     L.sbr_launch_grid.argtypes = [vp, C.c_int32, C.c_int64, C.c_int64, dp]
     L.sbr_trace_rays.argtypes = [vp, dp, C.c_int32, C.c_int32, C.c_int64, C.c_int64, ip, dp]
     L.sbr_trace_counters.argtypes = [vp, dp, dp, C.c_int32, C.POINTER(TraceParams), lp]
+    L.sbr_context_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
+    L.sbr_context_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
     L.sbr_trace_batch.argtypes = [vp, C.POINTER(vp), C.c_int32, C.POINTER(Job), C.c_int32, dp,
                                   C.c_int32, vp, C.c_int64, lp, C.POINTER(TraceStats)]
     for name in EXPORTS:
@@ -207,6 +219,20 @@ class Context:
         out = np.empty((count, 3), np.float64)
         self._check(lib().sbr_launch_grid(self.h, n, first, count, _d(out)))
         return out
+
+    def tuning(self) -> dict:
+        """sbr_context_get_tuning"""
+        t = Tuning()
+        self._check(lib().sbr_context_get_tuning(self.h, C.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        """sbr_context_set_tuning: update some fields, keep the others."""
+        cur = self.tuning()
+        cur.update(kw)
+        t = Tuning(cur["trace_chunk"], cur["persist_blocks"], cur["trace_block"],
+                   cur["stack_depth"], cur["lds_budget"], 0, cur["lookahead_max_paths"])
+        self._check(lib().sbr_context_set_tuning(self.h, C.byref(t)))
 
     def scene(self, scene: dict, max_leaf_size: int = 4, sah_bins: int = 16) -> "Scene":
         return Scene(self, scene, max_leaf_size, sah_bins)

@@ -434,3 +434,27 @@ def test_batch_argument_errors(gpu):
     finally:
         for s in scs:
             s.close()
+
+
+def test_tuning_roundtrip_and_invariance(gpu):
+    """Launch tuning (packet size, persistent workgroups, LDS staging, the
+    refinement lookahead) changes scheduling only: results are byte-identical."""
+    from paper_2208_10009_amd import sbr
+    cfg = scenes.manhattan_config(6, n_rx=12)
+    prm = dict(cfg["params"], division_n=70)
+    base = gpu.tuning()
+    sc = gpu.scene(cfg["scene"])
+    try:
+        ref, _ = sc.trace(cfg["tx"], cfg["rx"], **prm)
+        for t in (dict(trace_chunk=3, persist_blocks=7), dict(persist_blocks=1),
+                  dict(lds_budget=65536, stack_depth=8, trace_block=512),
+                  dict(lookahead_max_paths=0, trace_chunk=64)):
+            gpu.set_tuning(**dict(base, **t))
+            assert gpu.tuning()["trace_chunk"] == dict(base, **t)["trace_chunk"]
+            got, _ = sc.trace(cfg["tx"], cfg["rx"], **prm)
+            assert got.tobytes() == ref.tobytes(), t
+        with pytest.raises(sbr.SbrError):
+            gpu.set_tuning(trace_block=100)
+    finally:
+        gpu.set_tuning(**base)
+        sc.close()
