@@ -17,7 +17,8 @@
  *  - Outputs are caller-allocated host arrays.  Calls that return a list take
  *    a capacity; when it is too small they return SBR_E_CAPACITY, write the
  *    required count to *n_out and nothing else.
- *  - Every call is synchronous: results are complete on return.
+ *  - Every call is synchronous: results are complete on return (except
+ *    sbr_path_gradients, which works on device arrays in stream order).
  *  - On error nothing is left half-built; sbr_last_error() gives a message.
  *  - A context is bound to one device and one HIP stream and must be used by
  *    one thread at a time.  Scenes belong to the context that created them.
@@ -219,6 +220,29 @@ sbr_status sbr_launch_grid(sbr_context* ctx, int32_t n, int64_t first, int64_t c
  * Either output may be NULL. */
 sbr_status sbr_trace_rays(sbr_scene* scene, const double tx[3], int32_t n, int32_t max_order,
                           int64_t first, int64_t count, int32_t* out_tri, double* out_t);
+
+/* Differentiable path quantities at fixed interaction sequences (the
+ * gradients of the paths sbr_trace returns with respect to transmitter and
+ * receiver positions and the materials' permittivities).  For path i with
+ * order[i] reflections on faces[i][0..order[i]) -- a face sequence sbr_trace
+ * returned -- the path is the image-method path between tx[i] and rx[i] that
+ * the precise algorithm converges to.  values[i][0..8) = delay (s), AOD unit
+ * vector (3), AOA unit vector (3), power (dBm), computed as in sbr_path's
+ * exact_* fields but with the permittivities eps [n_materials][2] (re, im)
+ * given here instead of the scene's.  With upstream [n_paths][8] (dLoss /
+ * dvalue), grad_tx[i], grad_rx[i] ([n_paths][3]) receive dLoss / dposition and
+ * grad_eps ([n_materials][2], caller-zeroed) accumulates dLoss / d(re, im) over
+ * all paths.  Any of values / upstream may be NULL.
+ * ALL ARRAYS ARE DEVICE MEMORY; the work is queued on the context's stream and
+ * the call returns without waiting (stream order makes the results visible to
+ * later work on that stream).  Rows whose order or face ids lie outside the
+ * scene get NaN values and zero position gradients.  Errors: SBR_E_INVALID_ARG
+ * (NULL arrays, n_paths < 0, freq_hz <= 0). */
+sbr_status sbr_path_gradients(sbr_scene* scene, int64_t n_paths, const double* tx,
+                              const double* rx, const int32_t* order, const int32_t* faces,
+                              const double* eps, double freq_hz, double tx_power_dbm,
+                              const double* upstream, double* values, double* grad_tx,
+                              double* grad_rx, double* grad_eps);
 
 /* Work counts of the trace stage of sbr_trace with the same arguments, from
  * an instrumented copy of the trace kernel: counts[0] segments traced

@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libsbr.so")
-SOURCES = ["api.hip", "launch.hip", "trace.hip", "paths.hip", "refine.hip", "bvh_build.cpp"]
+SOURCES = ["api.hip", "launch.hip", "trace.hip", "paths.hip", "refine.hip", "grad.hip",
+           "bvh_build.cpp"]
 ARCH = "gfx950"
 
 

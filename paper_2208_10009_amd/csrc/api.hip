@@ -1054,4 +1054,40 @@ sbr_status sbr_trace_batch(sbr_context* c, sbr_scene* const* scenes, int32_t n_s
     return run_paths(c, call, out, capacity, n_out, stats);
 }
 
+sbr_status sbr_path_gradients(sbr_scene* s, int64_t n_paths, const double* tx, const double* rx,
+                              const int32_t* order, const int32_t* faces, const double* eps,
+                              double freq_hz, double tx_power_dbm, const double* upstream,
+                              double* values, double* grad_tx, double* grad_rx, double* grad_eps)
+{
+    sbr_status r = check_scene(s);
+    if (r) return r;
+    sbr_context* c = s->ctx;
+    c->err.clear();
+    if (n_paths < 0) return fail(c, SBR_E_INVALID_ARG, "n_paths < 0");
+    if (!(freq_hz > 0.0) || !isfinite(freq_hz) || !isfinite(tx_power_dbm))
+        return fail(c, SBR_E_INVALID_ARG, "freq_hz / tx_power_dbm out of range");
+    if (n_paths > 0 && (!tx || !rx || !order || !faces || !eps))
+        return fail(c, SBR_E_INVALID_ARG, "NULL input array");
+    if (upstream && (!grad_tx || !grad_rx || !grad_eps))
+        return fail(c, SBR_E_INVALID_ARG, "upstream gradients given but no gradient outputs");
+    if (n_paths == 0) return SBR_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    GradArgs A;
+    A.tx = tx;
+    A.rx = rx;
+    A.order = order;
+    A.faces = faces;
+    A.eps = eps;
+    A.up = upstream;
+    A.val = values;
+    A.gtx = grad_tx;
+    A.grx = grad_rx;
+    A.geps = grad_eps;
+    A.P = n_paths;
+    A.freq_hz = freq_hz;
+    A.tx_power_dbm = tx_power_dbm;
+    HIPCHK(c, launch_path_grad(scene_dev(s), A, c->stream));
+    return SBR_OK;
+}
+
 }  // extern "C"

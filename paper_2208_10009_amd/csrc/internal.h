@@ -183,4 +183,21 @@ hipError_t launch_dedup_small(const sbr_candidate* C, int64_t n, sbr_candidate* 
 hipError_t launch_emit_small(const sbr_path* paths, const int32_t* keep, int64_t U_max,
                              const int32_t* n_dev, sbr_path* out, int32_t* n_paths, hipStream_t s);
 
+// Differentiable path quantities (grad.hip); all pointers are device memory.
+struct GradArgs {
+    const double* tx;      // [P][3]
+    const double* rx;      // [P][3]
+    const int32_t* order;  // [P]
+    const int32_t* faces;  // [P][8]
+    const double* eps;     // [M][2]
+    const double* up;      // [P][8] upstream gradients or NULL
+    double* val;           // [P][8] values or NULL
+    double* gtx;           // [P][3]
+    double* grx;           // [P][3]
+    double* geps;          // [M][2], accumulated
+    int64_t P;
+    double freq_hz, tx_power_dbm;
+};
+hipError_t launch_path_grad(const SceneDev& S, const GradArgs& A, hipStream_t s);
+
 }  // namespace sbr

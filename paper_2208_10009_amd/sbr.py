@@ -40,7 +40,7 @@ EXPORTS = (
     "sbr_context_create", "sbr_context_destroy", "sbr_scene_upload", "sbr_bvh_build",
     "sbr_scene_destroy", "sbr_trace", "sbr_candidates", "sbr_launch_grid", "sbr_trace_rays",
     "sbr_trace_counters", "sbr_trace_batch", "sbr_context_get_tuning", "sbr_context_set_tuning",
-    "sbr_status_string", "sbr_last_error",
+    "sbr_path_gradients", "sbr_status_string", "sbr_last_error",
 )
 
 

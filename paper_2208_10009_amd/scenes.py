@@ -200,3 +200,30 @@ def batch_config(seed=0, n_scenes=16, n_pairs=256, tri_min=200, tri_max=50000, n
                              iterations=iterations, subrays=subrays, freq_hz=28e9))
     return {"name": "batch_%dscenes_%dpairs" % (n_scenes, n_pairs), "scenes": scenes,
             "jobs": jobs, "rx": np.array(rx, np.float64).reshape(-1, 3)}
+
+
+NOMINAL_EPS = (5.3 - 0.4j, 3.8 - 0.1j, 6.3 - 0.05j, 15.0 - 1.0j)
+
+
+def materials_city(seed=0, n_rx=1024, eps=None):
+    """The Manhattan grid with four materials: every building is concrete,
+    brick or glass (seeded choice) and the ground is soil; the hidden
+    permittivities are the nominal ones perturbed by a seeded factor
+    (real part x U(0.9, 1.1), imaginary part x U(0.8, 1.2)) unless eps is
+    given.  n_rx receivers at 1.5 m on street centrelines."""
+    rng = np.random.default_rng(seed + 7000)
+    cfg = manhattan_config(seed, n_rx=n_rx)
+    scene = dict(cfg["scene"])
+    mat = scene["mat_id"].copy()
+    n_build = (len(mat) - 2) // 12
+    kinds = rng.integers(0, 3, size=n_build)
+    mat[:12 * n_build] = np.repeat(kinds, 12)
+    mat[12 * n_build:] = 3
+    scene["mat_id"] = mat.astype(np.int32)
+    if eps is None:
+        nom = np.array(NOMINAL_EPS)
+        eps = (nom.real * rng.uniform(0.9, 1.1, 4)) + 1j * (nom.imag * rng.uniform(0.8, 1.2, 4))
+    scene["eps_r"] = np.asarray(eps, np.complex128)
+    return {"name": "materials_city_4mat_rx%d" % n_rx, "scene": scene, "tx": cfg["tx"],
+            "rx": cfg["rx"], "params": dict(cfg["params"], iterations=10,
+                                             target_err_deg=0.01)}

@@ -1,0 +1,180 @@
+"""GPU tests of the differentiable path quantities (sbr_path_gradients through
+torch.autograd): values against the trace's exact solve, gradients against
+FP64 central differences of the CPU oracle's independent image-method solve
+and against closed forms, and an Adam fit that recovers hidden
+permittivities from a synthetic power delay profile."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2208_10009_amd import scenes
+
+pytestmark = pytest.mark.gpu
+C0 = 299792458.0
+LN10 = math.log(10.0)
+
+
+def unit(v):
+    v = np.asarray(v, float)
+    return v / np.linalg.norm(v)
+
+
+def oracle_values(orc, scene, tx, rx, faces, freq=28e9):
+    """(delay, AOD, AOA, power) of the image-method path, from the oracle."""
+    pts, L, P, valid = orc.exact_path(scene, tx, rx, faces, freq_hz=freq)
+    k = len(faces)
+    first = pts[0] if k else rx
+    last = pts[k - 1] if k else tx
+    return np.concatenate([[L / C0], unit(first - tx), unit(last - rx), [P]]), valid
+
+
+@pytest.fixture(scope="module")
+def city(gpu):
+    import torch
+    cfg = scenes.materials_city(1, n_rx=48)
+    prm = dict(cfg["params"], division_n=90, max_order=4)
+    sc = gpu.scene(cfg["scene"])
+    paths, _ = sc.trace(cfg["tx"], cfg["rx"], **prm)
+    yield cfg, sc, paths, torch
+    sc.close()
+
+
+def _tensors(cfg, paths, torch):
+    from paper_2208_10009_amd import diff
+    rx, order, faces = diff.path_tensors(paths, cfg["rx"])
+    tx = torch.as_tensor(np.repeat(cfg["tx"][None], len(paths), 0), device="cuda")
+    eps = torch.as_tensor(np.stack([cfg["scene"]["eps_r"].real, cfg["scene"]["eps_r"].imag], 1),
+                          device="cuda")
+    return tx, rx, eps, order, faces
+
+
+def test_values_match_exact_solve(city):
+    from paper_2208_10009_amd import diff
+    cfg, sc, paths, torch = city
+    assert len(paths) > 30 and (paths["order"] >= 2).any()
+    tx, rx, eps, order, faces = _tensors(cfg, paths, torch)
+    v = diff.path_quantities(sc, tx, rx, eps, order, faces).cpu().numpy()
+    assert np.allclose(v[:, 0], paths["exact_delay_s"], rtol=1e-12, atol=0)
+    assert np.allclose(v[:, 1:4], paths["exact_aod"], atol=1e-12)
+    assert np.allclose(v[:, 4:7], paths["exact_aoa"], atol=1e-12)
+    assert np.allclose(v[:, 7], paths["exact_power_dbm"], atol=1e-9)
+
+
+def test_gradients_match_oracle_central_differences(city, orc):
+    """d(sum_i w_i . values_i) / d(tx, rx, eps) from the adjoint kernel against
+    FP64 central differences (h = 1e-6) of the oracle's image-method solve."""
+    from paper_2208_10009_amd import diff
+    cfg, sc, paths, torch = city
+    rng = np.random.default_rng(0)
+    pick = np.unique(np.concatenate([np.where(paths["order"] == k)[0][:3] for k in range(5)]))
+    sub = paths[pick]
+    tx, rx, eps, order, faces = _tensors(cfg, sub, torch)
+    tx.requires_grad_(True)
+    rx.requires_grad_(True)
+    eps.requires_grad_(True)
+    # weights scaled so every output contributes O(1)
+    w = rng.normal(size=(len(sub), 8)) * np.array([1e7, 1, 1, 1, 1, 1, 1, 0.1])
+    wt = torch.as_tensor(w, device="cuda")
+    loss = (diff.path_quantities(sc, tx, rx, eps, order, faces) * wt).sum()
+    loss.backward()
+    gtx, grx, geps = tx.grad.cpu().numpy(), rx.grad.cpu().numpy(), eps.grad.cpu().numpy()
+
+    h = 1e-6
+    scene = cfg["scene"]
+    geps_fd = np.zeros_like(geps)
+    for i, q in enumerate(sub):
+        f = list(q["face"][: q["order"]])
+        t0, r0 = cfg["tx"].copy(), cfg["rx"][q["rx"]].copy()
+
+        def L(t, r, sc_=scene):
+            v, valid = oracle_values(orc, sc_, t, r, f)
+            assert valid
+            return float(w[i] @ v)
+
+        for a in range(3):
+            e = np.zeros(3)
+            e[a] = h
+            fd_t = (L(t0 + e, r0) - L(t0 - e, r0)) / (2 * h)
+            fd_r = (L(t0, r0 + e) - L(t0, r0 - e)) / (2 * h)
+            assert abs(gtx[i, a] - fd_t) <= 1e-5 * max(1.0, abs(fd_t)), (i, a, gtx[i, a], fd_t)
+            assert abs(grx[i, a] - fd_r) <= 1e-5 * max(1.0, abs(fd_r)), (i, a, grx[i, a], fd_r)
+        for m in range(4):
+            for part, dz in ((0, h), (1, 1j * h)):
+                sp, sm = dict(scene), dict(scene)
+                sp["eps_r"] = scene["eps_r"].copy()
+                sm["eps_r"] = scene["eps_r"].copy()
+                sp["eps_r"][m] += dz
+                sm["eps_r"][m] -= dz
+                geps_fd[m, part] += (L(t0, r0, sp) - L(t0, r0, sm)) / (2 * h)
+    assert np.allclose(geps, geps_fd, rtol=1e-5, atol=1e-6), (geps, geps_fd)
+    assert np.abs(geps).max() > 1e-3  # materials are exercised
+
+
+def test_closed_form_gradients(gpu):
+    """Line of sight and the two-ray ground reflection: delay gradients are the
+    unit vectors of the (unfolded) path divided by c; the LOS power gradient
+    is -20 / (L ln 10) times the unit vector."""
+    import torch
+    from paper_2208_10009_amd import diff
+    scene = scenes.two_ray()
+    sc = gpu.scene(scene)
+    try:
+        ht, hr, D = 30.0, 1.5, 200.0
+        tx = torch.tensor([[0.0, 0.0, ht], [0.0, 0.0, ht]], device="cuda", dtype=torch.float64,
+                          requires_grad=True)
+        rx = torch.tensor([[D, 0.0, hr], [D, 0.0, hr]], device="cuda", dtype=torch.float64,
+                          requires_grad=True)
+        eps = torch.tensor([[15.0, -1.0]], device="cuda", dtype=torch.float64)
+        order = torch.tensor([0, 1], device="cuda", dtype=torch.int32)
+        faces = torch.full((2, 8), -1, device="cuda", dtype=torch.int32)
+        faces[1, 0] = 0
+        v = diff.path_quantities(sc, tx, rx, eps, order, faces)
+        v[:, 0].sum().backward()
+        Llos = math.hypot(D, ht - hr)
+        Lref = math.hypot(D, ht + hr)
+        vd = v.detach().cpu().numpy()
+        assert abs(vd[0, 0] - Llos / C0) < 1e-18 and abs(vd[1, 0] - Lref / C0) < 1e-18
+        g_rx = rx.grad.cpu().numpy()
+        assert np.allclose(g_rx[0], np.array([D, 0, hr - ht]) / Llos / C0, rtol=1e-10)
+        assert np.allclose(g_rx[1], np.array([D, 0, hr + ht]) / Lref / C0, rtol=1e-10)
+        assert np.allclose(tx.grad.cpu().numpy()[1], np.array([-D, 0, ht + hr]) / Lref / C0,
+                           rtol=1e-10)
+        tx.grad = None
+        rx.grad = None
+        v = diff.path_quantities(sc, tx, rx, eps, order, faces)
+        v[0, 7].backward()
+        assert np.allclose(rx.grad.cpu().numpy()[0],
+                           -20.0 / (Llos * LN10) * np.array([D, 0, hr - ht]) / Llos, rtol=1e-9)
+    finally:
+        sc.close()
+
+
+def test_adam_fit_recovers_permittivities(gpu):
+    """Synthetic PDP from hidden permittivities: Adam on eps (starting from the
+    nominal values) drives the power misfit to ~0 and recovers the real parts
+    of every material the paths reflect on."""
+    import torch
+    from paper_2208_10009_amd import diff
+    cfg = scenes.materials_city(2, n_rx=96)
+    prm = dict(cfg["params"], division_n=90, max_order=3)
+    sc = gpu.scene(cfg["scene"])
+    try:
+        paths, _ = sc.trace(cfg["tx"], cfg["rx"], **prm)
+        paths = paths[paths["order"] >= 1]
+        rx, order, faces = diff.path_tensors(paths, cfg["rx"])
+        tx = torch.as_tensor(cfg["tx"], device="cuda")
+        target = torch.as_tensor(paths["exact_power_dbm"], device="cuda")
+        hidden = np.stack([cfg["scene"]["eps_r"].real, cfg["scene"]["eps_r"].imag], 1)
+        nom = np.array(scenes.NOMINAL_EPS)
+        eps0 = torch.as_tensor(np.stack([nom.real, nom.imag], 1), device="cuda")
+        eps, losses = diff.fit_permittivity(sc, tx, rx, order, faces, target, eps0, steps=600,
+                                            lr=0.05)
+    finally:
+        sc.close()
+    eps = eps.cpu().numpy()
+    used = np.unique(cfg["scene"]["mat_id"][np.isin(cfg["scene"]["face_id"],
+                                                    paths["face"][paths["face"] >= 0])])
+    assert losses[-1] < 1e-4 * losses[0], (losses[0], losses[-1])
+    for m in used:
+        assert abs(eps[m, 0] - hidden[m, 0]) < 0.02 * abs(hidden[m, 0]), (m, eps[m], hidden[m])
