@@ -140,6 +140,11 @@ def lib():
         L.orc_free.argtypes = [C.c_void_p]
         L.orc_refine_history.argtypes = [dp, ip, C.c_int64, dp, C.POINTER(Params), dp, ip, ip,
                                          dp, C.c_int64, dp]
+        L.orc_ray_events.argtypes = [dp, ip, C.c_int64, dp, C.c_int32, C.c_int32, dp, C.c_int32,
+                                     lp, C.c_int64, C.c_int32, C.POINTER(C.POINTER(_Cand)), lp]
+        L.orc_path_records.argtypes = [dp, ip, ip, C.c_int64, dp, dp, C.c_int32, dp, dp,
+                                       C.c_int32, C.POINTER(Params), C.c_void_p, C.c_int64,
+                                       C.c_void_p]
         L.orc_exact_path.argtypes = [dp, ip, ip, C.c_int64, dp, dp, dp, dp, C.c_int32, ip,
                                      C.c_double, C.c_double, dp, dp, dp, ip]
     return _lib
@@ -273,6 +278,39 @@ def run(scene, tx, rx, **kw):
         "unique": _take(up, nu.value, CAND_DTYPE),
         "paths": _take(pp, npth.value, PATH_DTYPE),
     }
+
+
+def ray_events(scene, tx, rx, n, max_order, ids, threads=0):
+    """Reception events of the launch rays `ids` only (step 1 of run())."""
+    tri_v, face, _, _, _ = _scene_arrays(scene)
+    txa = np.ascontiguousarray(tx, dtype=np.float64)
+    rxa = np.ascontiguousarray(np.asarray(rx, dtype=np.float64).reshape(-1, 3))
+    ids = np.ascontiguousarray(ids, dtype=np.int64)
+    cp = C.POINTER(_Cand)()
+    nc = C.c_int64()
+    rc = lib().orc_ray_events(_d(tri_v), _i(face), len(face), _d(txa), n, max_order, _d(rxa),
+                              len(rxa), _l(ids), len(ids), threads, C.byref(cp), C.byref(nc))
+    if rc:
+        raise ValueError("orc_ray_events failed (%d)" % rc)
+    return _take(cp, nc.value, CAND_DTYPE)
+
+
+def path_records(scene, tx, rx, winners, **kw):
+    """Path records (steps 3-4 of run()) for given path-test-1 winners
+    (a CAND_DTYPE array); invalid paths are flagged, not dropped."""
+    tri_v, face, mat, er, ei = _scene_arrays(scene)
+    txa = np.ascontiguousarray(tx, dtype=np.float64)
+    rxa = np.ascontiguousarray(np.asarray(rx, dtype=np.float64).reshape(-1, 3))
+    win = np.ascontiguousarray(winners, dtype=CAND_DTYPE)
+    out = np.zeros(len(win), PATH_DTYPE)
+    prm = make_params(**kw)
+    rc = lib().orc_path_records(_d(tri_v), _i(face), _i(mat), len(face), _d(er), _d(ei), len(er),
+                                _d(txa), _d(rxa), len(rxa), C.byref(prm),
+                                win.ctypes.data_as(C.c_void_p), len(win),
+                                out.ctypes.data_as(C.c_void_p))
+    if rc:
+        raise ValueError("orc_path_records failed (%d)" % rc)
+    return out
 
 
 def refine_history(scene, tx, rx_rows, orders, faces, axes, **kw):

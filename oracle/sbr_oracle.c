@@ -817,6 +817,82 @@ static int ray_order_cmp(const void* pa, const void* pb)
     return 0;
 }
 
+/* Step 1 for one launch ray r: trace it (Sec. III.A) and append a reception
+ * event for every (segment, Rx) pair that passes the cone test, eq. (3). */
+static void ray_events(const scene_t* S, v3 TX, const grid_t* G, int64_t r, int32_t K,
+                       const double* rx, int32_t n_rx, double thl, cvec* out)
+{
+    seg_t segs[ORC_MAX_ORDER + 1];
+    int ns = trace_ray(S, TX, grid_dir(G, r), K, segs);
+    orc_candidate c;
+    memset(&c, 0, sizeof(c));
+    c.ray = r;
+    for (int j = 0; j < ns; ++j) {
+        c.order = j;
+        for (int q = 0; q < ORC_MAX_ORDER; ++q)
+            c.face[q] = q < j ? S->face[segs[q].tri] : -1;
+        for (int32_t x = 0; x < n_rx; ++x) {
+            double tn;
+            if (!capture_seg(&segs[j], ld3(rx + 3 * x), thl, &tn)) continue;
+            c.rx = x;
+            c.tan_err = tn;
+            cpush(out, &c);
+        }
+    }
+}
+
+/* Steps 3-4 for one path-test-1 winner c: the precise algorithm (Sec. III.B)
+ * from c's launch ray, the refined path's quantities (Sec. IV), the exact
+ * image-method solve and path test 2.  Fills *o; returns the validity. */
+static int path_record(const scene_t* S, v3 TX, const grid_t* G, const double* rx,
+                       const orc_candidate* c, const orc_params* P, const double* eps_re,
+                       const double* eps_im, double tan_tgt, double thl, orc_path* o)
+{
+    v3 R = ld3(rx + 3 * c->rx);
+    refine_t rf;
+    refine_path(S, TX, R, c->order, c->face, grid_dir(G, c->ray), P->iterations, P->subrays,
+                tan_tgt, thl, &rf, NULL);
+    o->rx = c->rx;
+    o->order = c->order;
+    for (int q = 0; q < ORC_MAX_ORDER; ++q) o->face[q] = c->face[q];
+    o->launch_ray = c->ray;
+    o->iters_used = rf.iters;
+    o->flags = rf.flags;
+    o->init_tan_err = c->tan_err;
+    o->tan_err = rf.tan_err;
+    st3(o->axis, rf.axis);
+    const int k = c->order;
+    /* refined path: Tx -> hit points of the final axis ray -> Rx */
+    double L = poly_length(TX, rf.fw.p, k, R);
+    o->length_m = L;
+    o->delay_s = L / C0;
+    st3(o->aod, rf.axis);
+    v3 last = k > 0 ? rf.fw.p[k - 1] : TX;
+    st3(o->aoa, normalize(sub(last, R)));
+    double refl[ORC_MAX_ORDER];
+    for (int j = 0; j < k; ++j) refl[j] = refl_at(S, eps_re, eps_im, c->face[j], rf.fw.din[j]);
+    o->power_dbm = path_power(P->tx_power_dbm, P->freq_hz, L, refl, k);
+    o->err_angle_deg = atan_cr(rf.tan_err) * (180.0 / PI_D);
+    /* exact path for the same faces */
+    v3 ep[ORC_MAX_ORDER];
+    int ok = exact_solve(S, TX, R, k, c->face, ep);
+    double EL = poly_length(TX, ep, k, R);
+    o->exact_length_m = EL;
+    o->exact_delay_s = EL / C0;
+    v3 first = k > 0 ? ep[0] : R;
+    st3(o->exact_aod, normalize(sub(first, TX)));
+    v3 elast = k > 0 ? ep[k - 1] : TX;
+    st3(o->exact_aoa, normalize(sub(elast, R)));
+    v3 prev = TX;
+    for (int j = 0; j < k; ++j) {
+        refl[j] = refl_at(S, eps_re, eps_im, c->face[j], sub(ep[j], prev));
+        prev = ep[j];
+    }
+    o->exact_power_dbm = path_power(P->tx_power_dbm, P->freq_hz, EL, refl, k);
+    if (!ok) o->flags |= 2u;
+    return ok;
+}
+
 int orc_run(const double* tri_v, const int32_t* face_id, const int32_t* mat_id,
             int64_t T, const double* eps_re, const double* eps_im, int32_t n_mat,
             const double tx[3], const double* rx, int32_t n_rx, const orc_params* P,
@@ -854,25 +930,7 @@ int orc_run(const double* tri_v, const int32_t* face_id, const int32_t* mat_id,
         int me = 0;
 #endif
 #pragma omp for schedule(dynamic, 256)
-        for (int64_t r = 0; r < N; ++r) {
-            seg_t segs[ORC_MAX_ORDER + 1];
-            int ns = trace_ray(&S, TX, grid_dir(&G, r), K, segs);
-            orc_candidate c;
-            memset(&c, 0, sizeof(c));
-            c.ray = r;
-            for (int j = 0; j < ns; ++j) {
-                c.order = j;
-                for (int q = 0; q < ORC_MAX_ORDER; ++q)
-                    c.face[q] = q < j ? S.face[segs[q].tri] : -1;
-                for (int32_t x = 0; x < n_rx; ++x) {
-                    double tn;
-                    if (!capture_seg(&segs[j], ld3(rx + 3 * x), thl, &tn)) continue;
-                    c.rx = x;
-                    c.tan_err = tn;
-                    cpush(&tv[me], &c);
-                }
-            }
-        }
+        for (int64_t r = 0; r < N; ++r) ray_events(&S, TX, &G, r, K, rx, n_rx, thl, &tv[me]);
     }
     int64_t nc = 0;
     for (int t = 0; t < nth; ++t) nc += tv[t].n;
@@ -901,51 +959,8 @@ int orc_run(const double* tri_v, const int32_t* face_id, const int32_t* mat_id,
     int32_t* keep = (int32_t*)calloc((size_t)(nu > 0 ? nu : 1), sizeof(int32_t));
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t i = 0; i < nu; ++i) {
-        const orc_candidate* c = &srt[i];
-        v3 R = ld3(rx + 3 * c->rx);
-        refine_t rf;
-        refine_path(&S, TX, R, c->order, c->face, grid_dir(&G, c->ray), P->iterations,
-                    P->subrays, tan_tgt, thl, &rf, NULL);
-        orc_path* o = &out[i];
-        o->rx = c->rx;
-        o->order = c->order;
-        for (int q = 0; q < ORC_MAX_ORDER; ++q) o->face[q] = c->face[q];
-        o->launch_ray = c->ray;
-        o->iters_used = rf.iters;
-        o->flags = rf.flags;
-        o->init_tan_err = c->tan_err;
-        o->tan_err = rf.tan_err;
-        st3(o->axis, rf.axis);
-        const int k = c->order;
-        /* refined path: Tx -> hit points of the final axis ray -> Rx */
-        double L = poly_length(TX, rf.fw.p, k, R);
-        o->length_m = L;
-        o->delay_s = L / C0;
-        st3(o->aod, rf.axis);
-        v3 last = k > 0 ? rf.fw.p[k - 1] : TX;
-        st3(o->aoa, normalize(sub(last, R)));
-        double refl[ORC_MAX_ORDER];
-        for (int j = 0; j < k; ++j) refl[j] = refl_at(&S, eps_re, eps_im, c->face[j], rf.fw.din[j]);
-        o->power_dbm = path_power(P->tx_power_dbm, P->freq_hz, L, refl, k);
-        o->err_angle_deg = atan_cr(rf.tan_err) * (180.0 / PI_D);
-        /* exact path for the same faces */
-        v3 ep[ORC_MAX_ORDER];
-        int ok = exact_solve(&S, TX, R, k, c->face, ep);
-        double EL = poly_length(TX, ep, k, R);
-        o->exact_length_m = EL;
-        o->exact_delay_s = EL / C0;
-        v3 first = k > 0 ? ep[0] : R;
-        st3(o->exact_aod, normalize(sub(first, TX)));
-        v3 elast = k > 0 ? ep[k - 1] : TX;
-        st3(o->exact_aoa, normalize(sub(elast, R)));
-        v3 prev = TX;
-        for (int j = 0; j < k; ++j) {
-            refl[j] = refl_at(&S, eps_re, eps_im, c->face[j], sub(ep[j], prev));
-            prev = ep[j];
-        }
-        o->exact_power_dbm = path_power(P->tx_power_dbm, P->freq_hz, EL, refl, k);
-        if (!ok) o->flags |= 2u;
-        keep[i] = ok || P->keep_invalid;
+        keep[i] = path_record(&S, TX, &G, rx, &srt[i], P, eps_re, eps_im, tan_tgt, thl, &out[i]) ||
+                  P->keep_invalid;
     }
     int64_t np = 0;
     for (int64_t i = 0; i < nu; ++i)
@@ -964,6 +979,79 @@ int orc_run(const double* tri_v, const int32_t* face_id, const int32_t* mat_id,
 }
 
 void orc_free(void* p) { free(p); }
+
+int orc_ray_events(const double* tri_v, const int32_t* face_id, int64_t T, const double tx[3],
+                   int32_t n, int32_t K, const double* rx, int32_t n_rx, const int64_t* ids,
+                   int64_t m, int32_t n_threads, orc_candidate** out, int64_t* n_out)
+{
+    if (n < 1 || K < 0 || K > ORC_MAX_ORDER || T < 0 || n_rx < 0 || m < 0 || !ids || !out ||
+        !n_out)
+        return -1;
+    const int64_t N = orc_num_rays(n);
+    for (int64_t i = 0; i < m; ++i)
+        if (ids[i] < 0 || ids[i] >= N) return -1;
+    scene_t S;
+    if (scene_init(&S, tri_v, face_id, NULL, T)) { scene_free(&S); return -1; }
+    grid_t G;
+    grid_init(&G, n);
+    const double thl = theta_launch(n);
+    const v3 TX = ld3(tx);
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+    cvec* per = (cvec*)calloc((size_t)(m > 0 ? m : 1), sizeof(cvec));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < m; ++i) ray_events(&S, TX, &G, ids[i], K, rx, n_rx, thl, &per[i]);
+    int64_t nc = 0;
+    for (int64_t i = 0; i < m; ++i) nc += per[i].n;
+    orc_candidate* all = (orc_candidate*)malloc(sizeof(orc_candidate) * (size_t)(nc > 0 ? nc : 1));
+    nc = 0;
+    for (int64_t i = 0; i < m; ++i) {
+        if (per[i].n) memcpy(all + nc, per[i].a, sizeof(orc_candidate) * (size_t)per[i].n);
+        nc += per[i].n;
+        free(per[i].a);
+    }
+    free(per);
+    grid_free(&G);
+    scene_free(&S);
+    *out = all;
+    *n_out = nc;
+    return 0;
+}
+
+int orc_path_records(const double* tri_v, const int32_t* face_id, const int32_t* mat_id,
+                     int64_t T, const double* eps_re, const double* eps_im, int32_t n_mat,
+                     const double tx[3], const double* rx, int32_t n_rx, const orc_params* P,
+                     const orc_candidate* win, int64_t m, orc_path* out)
+{
+    if (!P || P->division_n < 1 || P->max_order < 0 || P->max_order > ORC_MAX_ORDER ||
+        P->iterations < 0 || (P->subrays != 6 && P->subrays != 7) || n_rx < 0 || T < 0 ||
+        m < 0 || !(P->freq_hz > 0.0))
+        return -1;
+    const int64_t N = orc_num_rays(P->division_n);
+    for (int64_t i = 0; i < T; ++i)
+        if (mat_id && (mat_id[i] < 0 || mat_id[i] >= n_mat)) return -1;
+    for (int64_t i = 0; i < m; ++i)
+        if (win[i].rx < 0 || win[i].rx >= n_rx || win[i].order < 0 ||
+            win[i].order > P->max_order || win[i].ray < 0 || win[i].ray >= N)
+            return -1;
+    scene_t S;
+    if (scene_init(&S, tri_v, face_id, mat_id, T)) { scene_free(&S); return -1; }
+    grid_t G;
+    grid_init(&G, P->division_n);
+    const double thl = theta_launch(P->division_n);
+    double tan_tgt = 0.0;
+    if (P->target_err_deg > 0.0) tan_tgt = tan_cr((P->target_err_deg * PI_D) / 180.0);
+#ifdef _OPENMP
+    if (P->n_threads > 0) omp_set_num_threads(P->n_threads);
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < m; ++i)
+        (void)path_record(&S, ld3(tx), &G, rx, &win[i], P, eps_re, eps_im, tan_tgt, thl, &out[i]);
+    grid_free(&G);
+    scene_free(&S);
+    return 0;
+}
 
 int orc_refine_history(const double* tri_v, const int32_t* face_id, int64_t T,
                        const double tx[3], const orc_params* P,

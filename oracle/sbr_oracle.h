@@ -88,6 +88,21 @@ int orc_run(const double* tri_v, const int32_t* face_id, const int32_t* mat_id,
             orc_path** paths, int64_t* n_paths);
 void orc_free(void* p);
 
+/* Step 1 alone for the launch rays ids[0..m-1]: their reception events, in
+ * the order (ids order, segment, rx), returned in a malloc'd array. */
+int orc_ray_events(const double* tri_v, const int32_t* face_id, int64_t n_tri,
+                   const double tx[3], int32_t n, int32_t max_order, const double* rx,
+                   int32_t n_rx, const int64_t* ids, int64_t m, int32_t n_threads,
+                   orc_candidate** out, int64_t* n_out);
+
+/* Steps 3-4 alone for given path-test-1 winners win[0..m-1] (rx, order,
+ * faces, launch ray, tan_err): out[i] is the record orc_run produces for
+ * that winner, with the INVALID flag set but nothing dropped. */
+int orc_path_records(const double* tri_v, const int32_t* face_id, const int32_t* mat_id,
+                     int64_t n_tri, const double* eps_re, const double* eps_im, int32_t n_mat,
+                     const double tx[3], const double* rx, int32_t n_rx, const orc_params* prm,
+                     const orc_candidate* win, int64_t m, orc_path* out);
+
 /* Precise algorithm on given (rx, face sequence, start axis, start tan) rows;
  * records tan(theta_error) after every iteration in err_hist[row][0..iters]. */
 int orc_refine_history(const double* tri_v, const int32_t* face_id, int64_t n_tri,
