@@ -126,14 +126,17 @@ typedef struct {
  * stack_depth-entry traversal stack per lane in LDS, with trace_block lanes
  * per workgroup; 0 traverses from global memory (256 lanes per workgroup).
  * The refinement resolves two iterations per step with one wave per path
- * when there are at most lookahead_max_paths paths. */
+ * when there are at most lookahead_max_paths paths.  A job with at least
+ * rx_tree_min receivers tests reception through a ball tree over its
+ * receivers (a conservative cull before the exact test of eq. (3)) instead of
+ * testing every receiver on every segment. */
 typedef struct {
     int32_t trace_chunk;         /* 1..64                                   */
     int32_t persist_blocks;      /* >= 1                                    */
     int32_t trace_block;         /* 64..1024, multiple of 64 (LDS staging)  */
     int32_t stack_depth;         /* 0..64                                   */
     int32_t lds_budget;          /* bytes, 0..device limit per workgroup    */
-    int32_t reserved;            /* must be 0                               */
+    int32_t rx_tree_min;         /* >= 1                                    */
     int64_t lookahead_max_paths; /* >= 0                                    */
 } sbr_tuning;
 

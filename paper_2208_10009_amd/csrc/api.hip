@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <string>
 #include <vector>
@@ -62,7 +63,7 @@ struct sbr_context {
     int32_t n_scenes = 0;
     std::map<int32_t, DevBuf> grids;  // division n -> [3][N] FP64 directions
     DevBuf grid_scratch, rx, cand, idx, flags, offs, scan, uniq, refine, paths, keep, outp,
-        counters, rays_tri, rays_t, tally, geom, d_jobs, d_scenes, d_rxjob;
+        counters, rays_tri, rays_t, tally, geom, d_jobs, d_scenes, d_rxjob, d_rxnodes, d_rxperm;
     Counters* host_ctr = nullptr;  // pinned
     sbr_path* host_paths = nullptr;  // pinned staging of the path list
     int64_t host_paths_cap = 0;
@@ -78,6 +79,7 @@ struct sbr_context {
     // persistent trace: 64-ray groups per queue packet, resident workgroups
     // (SBR_TRACE_CHUNK, SBR_TRACE_BLOCKS)
     int32_t trace_chunk = 1, persist_blocks = 2048;
+    int32_t rx_tree_min = 64;
 };
 
 struct sbr_scene {
@@ -237,6 +239,8 @@ struct Call {
     std::vector<JobDev> jobs;
     std::vector<const sbr_scene*> scenes;
     std::vector<int32_t> rx_job;
+    std::vector<RxNode> rx_nodes;  // receiver trees of the jobs that have one
+    std::vector<int32_t> rx_perm;  // receiver indices in tree-leaf order
     const double* rx = nullptr;  // host [n_rx][3]
     int32_t n_rx = 0;
     int64_t n_rays = 0, n_packets = 0;
@@ -249,6 +253,51 @@ struct Call {
     bool grids_built = false;
     float ms_launch = 0, ms_trace = 0;
 };
+
+// Ball tree over the receivers perm[lo, hi) (global indices into rx), built
+// in preorder by median splits on the widest axis; returns the node index.
+int32_t build_rx_tree(const double* rx, std::vector<int32_t>& perm, int32_t lo, int32_t hi,
+                      std::vector<RxNode>& nodes)
+{
+    const int32_t me = (int32_t)nodes.size();
+    nodes.push_back(RxNode{});
+    double bl[3] = {INFINITY, INFINITY, INFINITY}, bh[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int32_t i = lo; i < hi; ++i)
+        for (int a = 0; a < 3; ++a) {
+            bl[a] = std::min(bl[a], rx[3 * perm[i] + a]);
+            bh[a] = std::max(bh[a], rx[3 * perm[i] + a]);
+        }
+    RxNode nd{};
+    for (int a = 0; a < 3; ++a) nd.c[a] = 0.5 * (bl[a] + bh[a]);
+    double r2 = 0.0;
+    for (int32_t i = lo; i < hi; ++i) {
+        double dx = rx[3 * perm[i]] - nd.c[0], dy = rx[3 * perm[i] + 1] - nd.c[1],
+               dz = rx[3 * perm[i] + 2] - nd.c[2];
+        r2 = std::max(r2, dx * dx + dy * dy + dz * dz);
+    }
+    nd.rho = std::sqrt(r2) * (1.0 + 1e-12);
+    if (hi - lo <= kRxLeaf) {
+        nd.first = lo;
+        nd.count = hi - lo;
+    } else {
+        int ax = 0;
+        for (int a = 1; a < 3; ++a)
+            if (bh[a] - bl[a] > bh[ax] - bl[ax]) ax = a;
+        const int32_t mid = lo + (hi - lo) / 2;
+        std::nth_element(perm.begin() + lo, perm.begin() + mid, perm.begin() + hi,
+                         [&](int32_t a, int32_t b) {
+                             double xa = rx[3 * a + ax], xb = rx[3 * b + ax];
+                             return xa < xb || (xa == xb && a < b);
+                         });
+        (void)build_rx_tree(rx, perm, lo, mid, nodes);
+        (void)build_rx_tree(rx, perm, mid, hi, nodes);
+        nd.first = -1;
+        nd.count = 0;
+    }
+    nd.skip = (int32_t)nodes.size();
+    nodes[me] = nd;
+    return me;
+}
 
 // Add a job: its launch directions (cached per division n), parameters and
 // packets of 64 x chunk rays.
@@ -281,6 +330,14 @@ sbr_status add_job(sbr_context* c, Call& call, int32_t scene_idx, const double* 
     J.subrays = p->subrays;
     J.keep_invalid = (p->flags & SBR_FLAG_KEEP_INVALID) ? 1 : 0;
     J.delta = traversal_delta(s, tx);
+    J.rx_root = -1;
+    if (n_rx > 0 && n_rx >= c->rx_tree_min) {
+        if (call.rx_perm.size() != (size_t)call.n_rx) {
+            call.rx_perm.resize((size_t)call.n_rx);
+            for (int32_t x = 0; x < call.n_rx; ++x) call.rx_perm[x] = x;
+        }
+        J.rx_root = build_rx_tree(call.rx, call.rx_perm, rx_first, rx_first + n_rx, call.rx_nodes);
+    }
     const int64_t per = 64 * (int64_t)call.chunk;
     call.n_packets += (ray_count + per - 1) / per;
     call.n_rays += ray_count;
@@ -315,6 +372,18 @@ sbr_status upload_call(sbr_context* c, Call& call)
     call.dev.scenes = c->d_scenes.as<const SceneDev>();
     call.dev.rx = c->rx.as<const double>();
     call.dev.rx_job = c->d_rxjob.as<const int32_t>();
+    call.dev.rx_nodes = nullptr;
+    call.dev.rx_perm = nullptr;
+    if (!call.rx_nodes.empty()) {
+        HIPCHK(c, ensure(c->d_rxnodes, sizeof(RxNode) * call.rx_nodes.size()));
+        HIPCHK(c, ensure(c->d_rxperm, sizeof(int32_t) * call.rx_perm.size()));
+        HIPCHK(c, hipMemcpyAsync(c->d_rxnodes.p, call.rx_nodes.data(),
+                                 sizeof(RxNode) * call.rx_nodes.size(), hipMemcpyHostToDevice, st));
+        HIPCHK(c, hipMemcpyAsync(c->d_rxperm.p, call.rx_perm.data(),
+                                 sizeof(int32_t) * call.rx_perm.size(), hipMemcpyHostToDevice, st));
+        call.dev.rx_nodes = c->d_rxnodes.as<const RxNode>();
+        call.dev.rx_perm = c->d_rxperm.as<const int32_t>();
+    }
     call.dev.n_jobs = (int32_t)call.jobs.size();
     call.dev.chunk = call.chunk;
     call.dev.n_packets = call.n_packets;
@@ -632,6 +701,7 @@ sbr_status sbr_context_create(int32_t device, void* hip_stream, sbr_context** ou
         c->lookahead_max_paths = env_int("SBR_LOOKAHEAD_PATHS", 4096, 0, 1 << 30);
         c->trace_chunk = env_int("SBR_TRACE_CHUNK", 1, 1, 64);
         c->persist_blocks = env_int("SBR_TRACE_BLOCKS", 2048, 1, 1 << 20);
+        c->rx_tree_min = env_int("SBR_RX_TREE_MIN", 64, 1, 0x7fffffff);
     }
     if (e != hipSuccess) {
         g_create_err = std::string("context setup: ") + hipGetErrorString(e);
@@ -652,7 +722,7 @@ sbr_status sbr_context_get_tuning(const sbr_context* c, sbr_tuning* t)
     t->trace_block = c->trace_block;
     t->stack_depth = c->stack_depth;
     t->lds_budget = c->lds_budget;
-    t->reserved = 0;
+    t->rx_tree_min = c->rx_tree_min;
     t->lookahead_max_paths = c->lookahead_max_paths;
     return SBR_OK;
 }
@@ -665,13 +735,14 @@ sbr_status sbr_context_set_tuning(sbr_context* c, const sbr_tuning* t)
     if (t->trace_chunk < 1 || t->trace_chunk > 64 || t->persist_blocks < 1 ||
         t->trace_block < 64 || t->trace_block > 1024 || t->trace_block % 64 != 0 ||
         t->stack_depth < 0 || t->stack_depth > kTraceStack || t->lds_budget < 0 ||
-        t->lds_budget > c->lds_max || t->reserved != 0 || t->lookahead_max_paths < 0)
+        t->lds_budget > c->lds_max || t->rx_tree_min < 1 || t->lookahead_max_paths < 0)
         return fail(c, SBR_E_INVALID_ARG, "tuning field out of range");
     c->trace_chunk = t->trace_chunk;
     c->persist_blocks = t->persist_blocks;
     c->trace_block = t->trace_block;
     c->stack_depth = t->stack_depth;
     c->lds_budget = t->lds_budget;
+    c->rx_tree_min = t->rx_tree_min;
     c->lookahead_max_paths = t->lookahead_max_paths;
     return SBR_OK;
 }
@@ -686,7 +757,8 @@ sbr_status sbr_context_destroy(sbr_context* c)
     DevBuf* bufs[] = {&c->grid_scratch, &c->rx,    &c->cand,  &c->idx,  &c->flags,
                       &c->offs,         &c->scan,  &c->uniq,  &c->refine, &c->paths,
                       &c->keep,         &c->outp,  &c->counters, &c->rays_tri, &c->rays_t, &c->tally,
-                      &c->geom,         &c->d_jobs, &c->d_scenes, &c->d_rxjob};
+                      &c->geom,         &c->d_jobs, &c->d_scenes, &c->d_rxjob,
+                      &c->d_rxnodes,    &c->d_rxperm};
     for (DevBuf* b : bufs) release(*b);
     for (auto& ev : c->ev)
         if (ev) (void)hipEventDestroy(ev);

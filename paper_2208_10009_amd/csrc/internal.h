@@ -74,6 +74,19 @@ struct GridDev {
     int32_t n;
 };
 
+// Ball-tree node over receivers (48 B), in depth-first preorder: the ball
+// (centre c, radius rho) holds every receiver below.  count > 0: a leaf of
+// the receivers perm[first .. first + count) (global receiver indices);
+// count == 0: an inner node whose left child is the next node.  skip is the
+// node after this subtree, where a walk goes when the ball is rejected.
+struct RxNode {
+    double c[3];
+    double rho;
+    int32_t first, count, skip, pad;
+};
+static_assert(sizeof(RxNode) == 48, "RxNode layout");
+constexpr int kRxLeaf = 4;
+
 // One job of a trace call: a transmitter, its receivers (a slice of the
 // call's receiver array) and its parameters, on one scene.  A plain trace is
 // a call with one job.
@@ -90,6 +103,7 @@ struct JobDev {
     int32_t scene, rx_first, n_rx, K;
     int32_t iterations, subrays, keep_invalid;
     float delta;           // box inflation (m) making FP32 traversal conservative
+    int32_t rx_root;       // root of the job's receiver tree; -1: test every receiver
 };
 
 // Everything the kernels of one call see.
@@ -98,6 +112,8 @@ struct CallDev {
     const SceneDev* scenes;
     const double* rx;       // [n_rx_total][3]: receivers of all jobs
     const int32_t* rx_job;  // job of each receiver
+    const RxNode* rx_nodes; // receiver trees of the jobs that have one
+    const int32_t* rx_perm; // receiver indices in tree-leaf order
     int32_t n_jobs;
     int32_t chunk;          // 64-ray groups per packet
     int64_t n_packets;

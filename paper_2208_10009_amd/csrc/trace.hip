@@ -1,7 +1,8 @@
 // trace.hip -- SBR tracing and reception (Sec. III.A): closest hit per
 // segment, specular reflection up to K bounces, and the cone reception test
 // of every receiver on every segment (eq. (3)), fused, one lane per launch
-// ray.  The kernel is persistent: waves take packets of 64 x chunk rays from
+// ray.  Jobs with many receivers walk a ball tree over them and run the
+// exact test only where a conservative cull lets a receiver through.  The kernel is persistent: waves take packets of 64 x chunk rays from
 // a device queue until it is empty, so jobs of uneven size and rays of uneven
 // length are balanced over the machine.  A packet never spans two jobs, so
 // the job and its scene are uniform across a wave.
@@ -14,7 +15,9 @@ namespace sbr {
 // Launch ray r of job J: trace, receive, record.
 template <bool COUNT, bool LDS>
 __device__ static inline void trace_ray(const SceneDev& S, const LdsPlan& L, const JobDev& J,
-                                        const double* __restrict__ rx_all, int64_t r,
+                                        const double* __restrict__ rx_all,
+                                        const RxNode* __restrict__ rx_nodes,
+                                        const int32_t* __restrict__ rx_perm, int64_t r,
                                         sbr_candidate* __restrict__ cand, int64_t cap,
                                         unsigned long long* __restrict__ ccount,
                                         int32_t* __restrict__ out_tri, double* __restrict__ out_t,
@@ -38,11 +41,11 @@ __device__ static inline void trace_ray(const SceneDev& S, const LdsPlan& L, con
         double t = hit < 0 ? INFINITY : h.t;
         if (out_tri) out_tri[ro + j] = hit < 0 ? -1 : h.orig;
         if (out_t) out_t[ro + j] = t;
-        for (int x = 0; x < J.n_rx; ++x) {
-            const int32_t gx = J.rx_first + x;
+        // reception test of receiver gx on this segment; events are appended
+        auto receive = [&](int32_t gx) {
             double tn;
             d3 rx = mk(rx_all[3 * gx], rx_all[3 * gx + 1], rx_all[3 * gx + 2]);
-            if (!capture(o, d, D, t, rx, J.thl, &tn)) continue;
+            if (!capture(o, d, D, t, rx, J.thl, &tn)) return;
             if (COUNT) *events += 1;
             unsigned long long pos = atomicAdd(ccount, 1ull);
             if ((int64_t)pos < cap) {
@@ -54,6 +57,24 @@ __device__ static inline void trace_ray(const SceneDev& S, const LdsPlan& L, con
                 c.ray = r;
                 c.tan_err = tn;
                 cand[pos] = c;
+            }
+        };
+        if (J.rx_root < 0) {
+            for (int x = 0; x < J.n_rx; ++x) receive(J.rx_first + x);
+        } else {
+            // stackless preorder walk of the job's receiver tree
+            int32_t nd = J.rx_root;
+            const int32_t end = rx_nodes[nd].skip;
+            while (nd != end) {
+                const RxNode N = rx_nodes[nd];
+                if (!rx_ball_may_capture(o, d, D, t, mk(N.c[0], N.c[1], N.c[2]), N.rho, J.thl)) {
+                    nd = N.skip;
+                } else if (N.count == 0) {
+                    nd = nd + 1;
+                } else {
+                    for (int q = 0; q < N.count; ++q) receive(rx_perm[N.first + q]);
+                    nd = N.skip;
+                }
             }
         }
         if (hit < 0 || j == K) {
@@ -113,8 +134,8 @@ __global__ __launch_bounds__(LDS ? 1024 : 256) void k_trace(CallDev call, LdsPla
         for (int c = 0; c < call.chunk; ++c) {
             const int64_t r = base + 64 * c + lane;
             if (r < end)
-                trace_ray<COUNT, LDS>(S, L, J, call.rx, r, cand, cap, ccount, out_tri, out_t, err,
-                                      &tl, &segs, &events);
+                trace_ray<COUNT, LDS>(S, L, J, call.rx, call.rx_nodes, call.rx_perm, r, cand, cap,
+                                      ccount, out_tri, out_t, err, &tl, &segs, &events);
         }
     }
     if (COUNT) {

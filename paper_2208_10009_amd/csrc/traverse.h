@@ -248,6 +248,28 @@ __device__ static inline bool capture(d3 o, d3 d, double D, double t, d3 rx, dou
     return true;
 }
 
+// Can any receiver inside the ball (c, rho) of a receiver-tree node pass the
+// reception test of the segment (o, d, D, t)?  For x in the ball, t*(x)
+// differs from t*(c) by at most rho |d|, and the distance from x to the ray
+// line from that of c by at most rho (x -> (x - o) - ((x - o).d) d has norm 1
+// for |d| = 1 + O(eps)).  So a capture needs 0 < t*(c) + rho |d|,
+// t*(c) - rho |d| <= t and d_perp(c) <= thl (D + t*(c) + rho |d|) + rho.  The
+// radius r used here widens rho by 1e-6 relative and by 1e-9 of the lengths
+// involved, far above the rounding of this test or of capture(), so the cull
+// never drops a receiver that capture() accepts.
+__device__ static inline bool rx_ball_may_capture(d3 o, d3 d, double D, double t, d3 c,
+                                                  double rho, double thl)
+{
+    d3 v = sub(c, o);
+    double tc = dot(v, d);
+    double r = rho * (1.0 + 1e-6) + 1e-9 * (D + (fabs(v.x) + fabs(v.y) + fabs(v.z)));
+    if (tc + r <= 0.0) return false;
+    if (tc - r > t) return false;
+    d3 w = sub(v, scl(tc, d));
+    double A = thl * (D + tc + r) + r;
+    return dot(w, w) <= A * A;
+}
+
 struct Follow {
     double tan_err, D, Llast;
 };

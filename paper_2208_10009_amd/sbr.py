@@ -66,11 +66,11 @@ class Job(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("trace_chunk", C.c_int32), ("persist_blocks", C.c_int32),
                 ("trace_block", C.c_int32), ("stack_depth", C.c_int32),
-                ("lds_budget", C.c_int32), ("reserved", C.c_int32),
+                ("lds_budget", C.c_int32), ("rx_tree_min", C.c_int32),
                 ("lookahead_max_paths", C.c_int64)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class Complex(C.Structure):
@@ -230,8 +230,7 @@ class Context:
         """sbr_context_set_tuning: update some fields, keep the others."""
         cur = self.tuning()
         cur.update(kw)
-        t = Tuning(cur["trace_chunk"], cur["persist_blocks"], cur["trace_block"],
-                   cur["stack_depth"], cur["lds_budget"], 0, cur["lookahead_max_paths"])
+        t = Tuning(**cur)
         self._check(lib().sbr_context_set_tuning(self.h, C.byref(t)))
 
     def scene(self, scene: dict, max_leaf_size: int = 4, sah_bins: int = 16) -> "Scene":

@@ -227,3 +227,109 @@ def materials_city(seed=0, n_rx=1024, eps=None):
     return {"name": "materials_city_4mat_rx%d" % n_rx, "scene": scene, "tx": cfg["tx"],
             "rx": cfg["rx"], "params": dict(cfg["params"], iterations=10,
                                              target_err_deg=0.01)}
+
+
+def _terrain_height(x, y, coef):
+    """Smooth seeded terrain: a sum of a few planar sinusoids (metres)."""
+    z = np.zeros(np.broadcast(x, y).shape)
+    for a, kx, ky, ph in coef:
+        z = z + a * np.sin(kx * x + ky * y + ph)
+    return z
+
+
+def large_city(seed=0, n_buildings=2000, quads=477, extent=1700.0, margin=50.0, plaza=40.0):
+    """Procedural city: n_buildings extruded convex polygons (4-12 vertices at
+    jittered angles on a circle of radius U(5, 15) m, so every polygon is
+    convex; centres rejected when the circles, widened by 2 m each, overlap
+    or reach into the central plaza), heights lognormal (median 25 m,
+    sigma 0.5), on a heightfield terrain of quads x quads cells over
+    [-margin, extent + margin]^2 (two triangles per cell, each its own face,
+    since terrain cells are not planar).  Walls are one face per polygon
+    edge and run from 2 m below the lowest terrain point under the footprint
+    to the roof; roofs are one fan-triangulated face.  Concrete buildings
+    (material 0), ground 15 - 1j (material 1).  Returns (scene, info) with
+    the terrain coefficients for placing Tx/Rx on it."""
+    rng = np.random.default_rng(seed + 9000)
+    coef = [(rng.uniform(1.0, 4.0), *(rng.normal(size=2) * 2 * np.pi / rng.uniform(300, 900)),
+             rng.uniform(0, 2 * np.pi)) for _ in range(4)]
+    # building footprints by rejection on a hash grid of 40 m cells
+    cell = 40.0
+    grid = {}
+    placed = []
+    c0 = extent / 2
+    attempts = 0
+    while len(placed) < n_buildings:
+        attempts += 1
+        if attempts > 200 * n_buildings:
+            raise RuntimeError("could not place %d buildings" % n_buildings)
+        r = rng.uniform(5.0, 15.0)
+        cx, cy = rng.uniform(r, extent - r, size=2)
+        if np.hypot(cx - c0, cy - c0) < plaza + r + 2.0:
+            continue
+        gx, gy = int(cx // cell), int(cy // cell)
+        ok = True
+        for i in range(gx - 1, gx + 2):
+            for j in range(gy - 1, gy + 2):
+                for (px, py, pr) in grid.get((i, j), ()):
+                    if np.hypot(cx - px, cy - py) < r + pr + 4.0:
+                        ok = False
+                        break
+                if not ok:
+                    break
+            if not ok:
+                break
+        if not ok:
+            continue
+        grid.setdefault((gx, gy), []).append((cx, cy, r))
+        placed.append((cx, cy, r))
+    b = SceneBuilder()
+    for (cx, cy, r) in placed:
+        m = int(rng.integers(4, 13))
+        step = 2 * np.pi / m
+        ang = rng.uniform(0, 2 * np.pi) + step * np.arange(m) + rng.uniform(-0.3, 0.3, m) * step
+        px, py = cx + r * np.cos(ang), cy + r * np.sin(ang)
+        ground = _terrain_height(np.append(px, cx), np.append(py, cy), coef)
+        z0 = ground.min() - 2.0
+        z1 = ground[-1] + rng.lognormal(np.log(25.0), 0.5)
+        # walls: one quad face per edge
+        for e in range(m):
+            a, q = e, (e + 1) % m
+            b.quad((px[a], py[a], z0), (px[q], py[q], z0), (px[q], py[q], z1),
+                   (px[a], py[a], z1), 0)
+        # roof: one fan-triangulated face
+        v = np.stack([px, py, np.full(m, z1)], 1)
+        t = [(0, i, i + 1) for i in range(1, m - 1)]
+        b.add(v, t, [0] * len(t), 0)
+    # terrain
+    xs = np.linspace(-margin, extent + margin, quads + 1)
+    X, Y = np.meshgrid(xs, xs, indexing="ij")
+    Z = _terrain_height(X, Y, coef)
+    verts = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1)
+    i, j = np.meshgrid(np.arange(quads), np.arange(quads), indexing="ij")
+    v00 = (i * (quads + 1) + j).ravel()
+    v10, v01, v11 = v00 + (quads + 1), v00 + 1, v00 + quads + 2
+    tris = np.empty((2 * len(v00), 3), np.int64)
+    tris[0::2] = np.stack([v00, v10, v11], 1)
+    tris[1::2] = np.stack([v00, v11, v01], 1)
+    b.add(verts, tris, np.arange(len(tris)), 1)
+    return b.scene([CONCRETE, GROUND]), {"coef": coef, "extent": extent, "buildings": placed}
+
+
+def large_city_config(seed=0, n_buildings=2000, quads=477, grid=32):
+    """Large procedural city (about 500k triangles): Tx 30 m above the
+    terrain at the plaza in the centre, grid x grid receivers 1.5 m above the
+    terrain on a regular grid over the city (some fall inside buildings and
+    receive nothing), n = 1000 (10,000,002 rays), up to 8 reflections,
+    5 iterations with 6 sub-rays."""
+    scene, info = large_city(seed, n_buildings=n_buildings, quads=quads)
+    ext, coef = info["extent"], info["coef"]
+    c = ext / 2
+    tx = np.array([c, c, float(_terrain_height(c, c, coef)) + 30.0])
+    g = (np.arange(grid) + 0.5) * (ext / grid)
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    rx = np.stack([X.ravel(), Y.ravel(), _terrain_height(X.ravel(), Y.ravel(), coef) + 1.5], 1)
+    return {
+        "name": "large_city_%dtri_rx%d_n1000_k8" % (len(scene["tri"]), len(rx)),
+        "scene": scene, "tx": tx, "rx": rx,
+        "params": dict(max_order=8, division_n=1000, iterations=5, subrays=6, freq_hz=28e9),
+    }

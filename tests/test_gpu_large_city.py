@@ -1,0 +1,159 @@
+"""GPU parity at the large-city size (about 500k triangles, 1024 receivers,
+n = 1000: 10,000,002 launch rays, up to 8 reflections), where the brute-force
+oracle cannot run whole, plus the receiver ball tree that this size needs.
+
+At full size the oracle computes sampled outputs one by one:
+  * per-ray triangle sequences and segment parameters of seeded blocks of
+    launch rays: bit-exact;
+  * the reception events of sampled launch rays: bit-exact (a ray's events
+    depend on that ray alone).  The sample is seeded random rays (captures
+    are rare: about one ray per path and receiver, so these mostly check
+    that no event is invented or missed) plus the rays of a seeded sample of
+    the reported events (which checks the events themselves);
+  * path test 1 on that sample: every sampled event's key is a path whose
+    winner is at least as good (smaller tan, ties to the lower ray);
+  * seeded output paths recomputed from their winners (precise algorithm,
+    path quantities, path test 2): the parity bar of the smaller configs.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2208_10009_amd import scenes
+from parity_util import bits, compare_paths, key_of
+
+pytestmark = pytest.mark.gpu
+EV_ORDER = ("ray", "order", "rx")
+
+
+def _sorted_events(ev):
+    return ev[np.lexsort(tuple(ev[f] for f in reversed(EV_ORDER)))]
+
+
+def _same_events(g, o):
+    g, o = _sorted_events(g), _sorted_events(o)
+    assert len(g) == len(o)
+    for f in ("rx", "order", "face", "ray"):
+        assert np.array_equal(g[f], o[f]), f
+    assert np.array_equal(bits(g["tan_err"]), bits(o["tan_err"]))
+
+
+@pytest.fixture(scope="module")
+def city(gpu):
+    t0 = time.time()
+    cfg = scenes.large_city_config(0)
+    t1 = time.time()
+    sc = gpu.scene(cfg["scene"])
+    print("\nlarge city: %d triangles, generated in %.1f s, uploaded + BVH in %.1f s"
+          % (len(cfg["scene"]["tri"]), t1 - t0, time.time() - t1), flush=True)
+    yield cfg, sc
+    sc.close()
+
+
+@pytest.fixture(scope="module")
+def city_run(city):
+    cfg, sc = city
+    t0 = time.time()
+    cand = sc.candidates(cfg["tx"], cfg["rx"], **cfg["params"])
+    paths, st = sc.trace(cfg["tx"], cfg["rx"], keep_invalid=True, **cfg["params"])
+    print("large city: %d events, %d paths (%.1f s); trace %.1f ms, refine %.1f ms"
+          % (len(cand), len(paths), time.time() - t0, st["ms_trace"], st["ms_refine"]),
+          flush=True)
+    return cand, paths, st
+
+
+def test_large_city_size(city):
+    cfg, _ = city
+    assert 490_000 <= len(cfg["scene"]["tri"]) <= 510_000
+    assert len(cfg["rx"]) == 1024 and cfg["params"]["division_n"] == 1000
+
+
+def test_large_city_rays_sampled(city, orc):
+    cfg, sc = city
+    n, K = 1000, 8
+    N = 10 * n * n + 2
+    rng = np.random.default_rng(11)
+    starts = np.sort(rng.choice(N // 128 - 1, 48, replace=False)) * 128
+    starts = np.append(starts, N - 128)  # the ragged end of the index range
+    ids = (starts[:, None] + np.arange(128)).ravel()
+    o_tri, _, o_t = orc.trace_rays(cfg["scene"], cfg["tx"], n, K, ids=ids)
+    for b, s0 in enumerate(starts):
+        g_tri, g_t = sc.trace_rays(cfg["tx"], n, K, first=int(s0), count=128)
+        sl = slice(128 * b, 128 * (b + 1))
+        assert np.array_equal(g_tri, o_tri[sl]), int(s0)
+        assert np.array_equal(bits(g_t), bits(o_t[sl])), int(s0)
+    assert (o_tri[:, 1] >= 0).sum() > 500  # many rays reflect at least once
+
+
+def test_large_city_events_and_test1_sampled(city, city_run, orc):
+    cfg, _ = city
+    cand, paths, _ = city_run
+    n = 1000
+    N = 10 * n * n + 2
+    rng = np.random.default_rng(12)
+    picked = cand["ray"][rng.choice(len(cand), min(400, len(cand)), replace=False)]
+    ids = np.unique(np.concatenate([rng.choice(N, 6000, replace=False), picked]))
+    o = orc.ray_events(cfg["scene"], cfg["tx"], cfg["rx"], n, 8, ids)
+    g = cand[np.isin(cand["ray"], ids)]
+    _same_events(g, o)
+    assert len(o) >= 400, len(o)
+    assert len(np.unique(o["order"])) >= 4
+    # path test 1 against the sample: the winner of each key is no worse
+    win = {key_of(p): p for p in paths}
+    for e in o:
+        p = win[key_of(e)]
+        te, tp = float(e["tan_err"]), float(p["init_tan_err"])
+        assert tp < te or (tp == te and int(p["launch_ray"]) <= int(e["ray"]))
+
+
+def test_large_city_paths_sampled(city, city_run, orc):
+    cfg, _ = city
+    cand, paths, st = city_run
+    # canonical order, one path per key, every key of the events present
+    keys = [key_of(p) for p in paths]
+    assert keys == sorted(keys) and len(set(keys)) == len(keys)
+    assert st["n_unique"] == len(paths) == len({key_of(c) for c in cand})
+    assert (paths["order"] >= 4).any()
+    rng = np.random.default_rng(13)
+    pick = np.unique(np.concatenate([
+        rng.choice(np.where(paths["order"] == k)[0], min(6, int((paths["order"] == k).sum())),
+                   replace=False) for k in range(9) if (paths["order"] == k).any()]))
+    sub = paths[pick]
+    win = np.zeros(len(sub), orc.CAND_DTYPE)
+    for f in ("rx", "order", "face"):
+        win[f] = sub[f]
+    win["ray"] = sub["launch_ray"]
+    win["tan_err"] = sub["init_tan_err"]
+    o = orc.path_records(cfg["scene"], cfg["tx"], cfg["rx"], win, **cfg["params"])
+    compare_paths(sub, o)
+    # each winner's event is the oracle's reception of that launch ray
+    ev = orc.ray_events(cfg["scene"], cfg["tx"], cfg["rx"], 1000, 8, np.unique(sub["launch_ray"]))
+    have = {key_of(e) + (int(e["ray"]), int(bits(e["tan_err"])[0])) for e in ev}
+    for p in sub:
+        assert key_of(p) + (int(p["launch_ray"]), int(bits(p["init_tan_err"])[0])) in have
+
+
+def test_rx_tree_matches_linear_and_oracle(gpu, orc):
+    """1024 receivers on the Manhattan grid: reception through the receiver
+    ball tree and by testing every receiver give byte-identical events and
+    paths, equal to the oracle's."""
+    cfg = scenes.manhattan_config(3, n_rx=1024)
+    prm = dict(cfg["params"], division_n=60, max_order=4, iterations=3)
+    sc = gpu.scene(cfg["scene"])
+    base = gpu.tuning()
+    out = {}
+    try:
+        for name, m in (("tree", 1), ("linear", 2**31 - 1)):
+            gpu.set_tuning(**dict(base, rx_tree_min=m))
+            out[name] = (sc.candidates(cfg["tx"], cfg["rx"], **prm),
+                         sc.trace(cfg["tx"], cfg["rx"], **prm)[0])
+    finally:
+        gpu.set_tuning(**base)
+        sc.close()
+    assert out["tree"][0].tobytes() == out["linear"][0].tobytes()
+    assert out["tree"][1].tobytes() == out["linear"][1].tobytes()
+    o = orc.run(cfg["scene"], cfg["tx"], cfg["rx"], **prm)
+    _same_events(out["tree"][0], o["candidates"])
+    compare_paths(out["tree"][1], o["paths"])
+    assert len(o["paths"]) > 1000

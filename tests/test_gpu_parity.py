@@ -18,24 +18,8 @@ from paper_2208_10009_amd import scenes
 
 pytestmark = pytest.mark.gpu
 
-DELAY_RTOL = 1e-6
-ANGLE_TOL_DEG = 1e-4
-POWER_TOL_DB = 1e-3
-
-
-def angle_deg(a, b):
-    a = np.asarray(a, float)
-    b = np.asarray(b, float)
-    c = np.cross(a, b)
-    return np.degrees(np.arctan2(np.linalg.norm(c, axis=-1), np.sum(a * b, axis=-1)))
-
-
-def bits(x):
-    return np.ascontiguousarray(x, np.float64).view(np.uint64)
-
-
-def key_of(rec):
-    return (int(rec["rx"]), int(rec["order"])) + tuple(int(f) for f in rec["face"])
+from parity_util import (ANGLE_TOL_DEG, DELAY_RTOL, POWER_TOL_DB, angle_deg, bits,  # noqa: F401
+                         compare_paths as _compare_paths, key_of)
 
 
 # ----------------------------------------------------------- launch grid --
@@ -161,23 +145,6 @@ def test_candidates_manhattan_full(gpu, orc):
 
 
 # ------------------------------------------------------------ full paths --
-def _compare_paths(g, o):
-    assert len(g) == len(o)
-    for f in ("rx", "order", "face", "launch_ray", "iters_used", "flags"):
-        assert np.array_equal(g[f], o[f]), f
-    # the refinement is decided in FP64 with the oracle's operation order
-    assert np.array_equal(bits(g["tan_err"]), bits(o["tan_err"]))
-    assert np.array_equal(bits(g["axis"]), bits(o["axis"]))
-    assert np.array_equal(bits(g["init_tan_err"]), bits(o["init_tan_err"]))
-    for f in ("delay_s", "exact_delay_s", "length_m", "exact_length_m"):
-        assert np.all(np.abs(g[f] - o[f]) <= DELAY_RTOL * np.abs(o[f])), f
-    for f in ("aod", "aoa", "exact_aod", "exact_aoa"):
-        assert np.all(angle_deg(g[f], o[f]) <= ANGLE_TOL_DEG), f
-    assert np.all(np.abs(g["err_angle_deg"] - o["err_angle_deg"]) <= ANGLE_TOL_DEG)
-    for f in ("power_dbm", "exact_power_dbm"):
-        assert np.all(np.abs(g[f] - o[f]) <= POWER_TOL_DB), f
-
-
 def _run_both(gpu, orc, cfg, **prm):
     sc = gpu.scene(cfg["scene"])
     try:
@@ -448,13 +415,15 @@ def test_tuning_roundtrip_and_invariance(gpu):
         ref, _ = sc.trace(cfg["tx"], cfg["rx"], **prm)
         for t in (dict(trace_chunk=3, persist_blocks=7), dict(persist_blocks=1),
                   dict(lds_budget=65536, stack_depth=8, trace_block=512),
-                  dict(lookahead_max_paths=0, trace_chunk=64)):
+                  dict(lookahead_max_paths=0, trace_chunk=64), dict(rx_tree_min=1)):
             gpu.set_tuning(**dict(base, **t))
             assert gpu.tuning()["trace_chunk"] == dict(base, **t)["trace_chunk"]
             got, _ = sc.trace(cfg["tx"], cfg["rx"], **prm)
             assert got.tobytes() == ref.tobytes(), t
         with pytest.raises(sbr.SbrError):
             gpu.set_tuning(trace_block=100)
+        with pytest.raises(sbr.SbrError):
+            gpu.set_tuning(rx_tree_min=0)
     finally:
         gpu.set_tuning(**base)
         sc.close()
