@@ -44,6 +44,39 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRACE_SOURCES = ("trace.hip", "traverse.h", "internal.h", "geom.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_trace_hbm_traffic.txt")
+
+
+def trace_source_hash():
+    """SHA-256 over the sources the trace kernel is compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRACE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2208_10009_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per k_trace launch for `workload` from the counter summary
+    (FETCH_SIZE + WRITE_SIZE, calibrated), or None when the summary is
+    missing or was taken from other kernel sources."""
+    try:
+        lines = open(TRAFFIC_FILE).read().split("\n")
+    except OSError:
+        return None
+    kv = {}
+    for ln in lines:
+        ln = ln.strip()
+        if ln and not ln.startswith("#") and "=" in ln:
+            k, v = ln.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != trace_source_hash() or workload + ".bytes" not in kv:
+        return None
+    return int(kv[workload + ".bytes"])
+
+
 def angle_deg(a, b):
     c = np.cross(a, b)
     return np.degrees(np.arctan2(np.linalg.norm(c, axis=-1), np.sum(a * b, axis=-1)))
@@ -150,6 +183,69 @@ def batch_vs_plain(ctx, scenes, torch, seed=0, steps=2):
     }
 
 
+def large_city_leg(ctx, scenes, torch, steps=5):
+    """The large procedural city (about 500k triangles, 1024 Rx on a 32 x 32
+    grid, n = 1000: 10,000,002 rays, K = 8, I = 5, S = 6), one sbr_trace call
+    per step with the launch grid recomputed: rays/s, stage times, the trace
+    kernel's roofline, and refined paths/s in the 0.01 deg target mode."""
+    cfg = scenes.large_city_config(0)
+    prm = cfg["params"]
+    n_rays = 10 * prm["division_n"] ** 2 + 2
+    t0 = time.perf_counter()
+    sc = ctx.scene(cfg["scene"])
+    build_s = time.perf_counter() - t0
+    counts = sc.trace_counters(cfg["tx"], cfg["rx"], **prm)
+    from paper_2208_10009_amd import autotune
+    entry_tuning = ctx.tuning()
+    best, _ = autotune.autotune(
+        ctx, lambda: sc.trace(cfg["tx"], cfg["rx"], **prm),
+        space={"trace_chunk": [1, 2], "persist_blocks": [1024, 2048, 4096],
+               "rx_tree_min": [16, 1 << 30], "lds_budget": [0, 24 * 4 * 256],
+               "stack_depth": [24]}, warmup=1, steps=2)
+    log("large city tuning", best)
+
+    def run(kw):
+        sc.trace(cfg["tx"], cfg["rx"], **kw)
+        torch.cuda.synchronize()
+        stats = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            paths, st = sc.trace(cfg["tx"], cfg["rx"], **kw)
+            stats.append(st)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        stage = {k: round(float(np.mean([x[k] for x in stats])), 4)
+                 for k in ("ms_launch", "ms_trace", "ms_dedup", "ms_refine", "ms_solve",
+                           "ms_emit", "ms_total")}
+        return paths, ms, stage
+
+    paths, ms, stage = run(dict(prm, fresh_grid=True))
+    tpaths, tms, tstage = run(dict(prm, iterations=30, target_err_deg=0.01, fresh_grid=True))
+    sc.close()
+    tuning = ctx.tuning()
+    ctx.set_tuning(**entry_tuning)
+    alg = (counts["nodes"] * NODE_BYTES + counts["tris"] * TRI_BYTES + n_rays * RAY_BYTES
+           + counts["events"] * EVENT_BYTES)
+    ach = alg / (stage["ms_trace"] * 1e-3) / 1e9
+    tgood = int(accurate_mask(tpaths).sum())
+    return {
+        "workload": cfg["name"] + "_i5_s6",
+        "triangles": int(len(cfg["scene"]["tri"])), "rx": int(len(cfg["rx"])), "rays": n_rays,
+        "bvh_build_s": round(build_s, 3),
+        "ms_per_step": round(ms, 4), "rays_per_s": n_rays / (ms * 1e-3),
+        "trace_rays_per_s": n_rays / (stage["ms_trace"] * 1e-3),
+        "paths": int(len(paths)), "stage_ms": stage, "counts": counts,
+        "tuning": tuning,
+        "roofline": {"kernel": "k_trace", "bound": "hbm", "achieved": round(ach, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5),
+                     "traffic": measured_traffic(cfg["name"] + "_i5_s6"),
+                     "algorithmic_bytes_per_launch": int(alg)},
+        "refined_paths_per_s": tgood / (tms * 1e-3),
+        "refined_paths": {"paths": int(len(tpaths)), "within_0.01deg": tgood,
+                          "ms_per_step": round(tms, 4), "stage_ms": tstage},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +255,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-vs-plain comparison on the 256-pair workload")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the large-city (500k triangles, 10M rays, 1024 Rx) leg")
+    ap.add_argument("--large-only", action="store_true",
+                    help="run only the large-city leg and print its JSON object (profiling)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 5 times (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -181,6 +281,11 @@ def main():
         torch.cuda.synchronize()
         log("copy probe: 5 x %d bytes" % (x.numel() * 4))
         return
+    if args.large_only:
+        ctx = sbr.Context(0)
+        print(json.dumps(large_city_leg(ctx, scenes, torch)), flush=True)
+        ctx.close()
+        return
     cfg = scenes.manhattan_config(args.seed)
     prm = cfg["params"]
     ctx = sbr.Context(0)
@@ -193,7 +298,8 @@ def main():
     best, _ = autotune.autotune(
         ctx, lambda: sc.trace(cfg["tx"], cfg["rx"], **prm),
         space={"trace_chunk": [1, 2], "persist_blocks": [1024, 2048, 4096],
-               "lds_budget": [0], "lookahead_max_paths": [4096]}, warmup=1, steps=5)
+               "lds_budget": [0, 24 * 4 * 256], "stack_depth": [24],
+               "lookahead_max_paths": [4096], "rx_tree_min": [16, 1 << 30]}, warmup=1, steps=5)
     log("tuning", best)
 
     def timed(steps, warmup, **kw):
@@ -241,7 +347,7 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 5),
-        "traffic": None,
+        "traffic": measured_traffic("manhattan_8x8_770tri_n200_k6_i5_s7_rx64"),
         "algorithmic_bytes_per_launch": int(alg_bytes),
         "kernel_ms": round(stage["ms_trace"], 5),
         "dominant_stage": dominant,
@@ -284,6 +390,9 @@ def main():
         "roofline": roofline,
     }
     sc.close()
+    if not args.no_large:
+        out["large_city"] = large_city_leg(ctx, scenes, torch)
+        log("large city", json.dumps(out["large_city"]))
     if not args.no_batch:
         out["batched"] = batch_vs_plain(ctx, scenes, torch)
     ctx.close()

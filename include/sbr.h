@@ -124,7 +124,9 @@ typedef struct {
  * device queue; persist_blocks workgroups are launched.  lds_budget > 0
  * stages the BVH's top nodes (and all triangles when they fit) plus a
  * stack_depth-entry traversal stack per lane in LDS, with trace_block lanes
- * per workgroup; 0 traverses from global memory (256 lanes per workgroup).
+ * per workgroup (a budget of just 4 * stack_depth * trace_block bytes keeps
+ * only the stack there); 0 traverses from global memory with a private stack
+ * (256 lanes per workgroup).
  * The refinement resolves two iterations per step with one wave per path
  * when there are at most lookahead_max_paths paths.  A job with at least
  * rx_tree_min receivers tests reception through a ball tree over its
@@ -133,7 +135,7 @@ typedef struct {
 typedef struct {
     int32_t trace_chunk;         /* 1..64                                   */
     int32_t persist_blocks;      /* >= 1                                    */
-    int32_t trace_block;         /* 64..1024, multiple of 64 (LDS staging)  */
+    int32_t trace_block;         /* 64..256, multiple of 64 (LDS staging)   */
     int32_t stack_depth;         /* 0..64                                   */
     int32_t lds_budget;          /* bytes, 0..device limit per workgroup    */
     int32_t rx_tree_min;         /* >= 1                                    */

@@ -696,7 +696,7 @@ sbr_status sbr_context_create(int32_t device, void* hip_stream, sbr_context** ou
             c->lds_max = 65536;
         }
         c->lds_budget = env_int("SBR_LDS_BUDGET", 0, 0, c->lds_max);
-        c->trace_block = env_int("SBR_TRACE_BLOCK", 256, 64, 1024) / 64 * 64;
+        c->trace_block = env_int("SBR_TRACE_BLOCK", 256, 64, 256) / 64 * 64;
         c->stack_depth = env_int("SBR_STACK_DEPTH", 24, 0, kTraceStack);
         c->lookahead_max_paths = env_int("SBR_LOOKAHEAD_PATHS", 4096, 0, 1 << 30);
         c->trace_chunk = env_int("SBR_TRACE_CHUNK", 1, 1, 64);
@@ -733,7 +733,7 @@ sbr_status sbr_context_set_tuning(sbr_context* c, const sbr_tuning* t)
     c->err.clear();
     if (!t) return fail(c, SBR_E_INVALID_ARG, "tuning is NULL");
     if (t->trace_chunk < 1 || t->trace_chunk > 64 || t->persist_blocks < 1 ||
-        t->trace_block < 64 || t->trace_block > 1024 || t->trace_block % 64 != 0 ||
+        t->trace_block < 64 || t->trace_block > 256 || t->trace_block % 64 != 0 ||
         t->stack_depth < 0 || t->stack_depth > kTraceStack || t->lds_budget < 0 ||
         t->lds_budget > c->lds_max || t->rx_tree_min < 1 || t->lookahead_max_paths < 0)
         return fail(c, SBR_E_INVALID_ARG, "tuning field out of range");

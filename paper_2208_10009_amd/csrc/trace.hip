@@ -2,105 +2,74 @@
 // segment, specular reflection up to K bounces, and the cone reception test
 // of every receiver on every segment (eq. (3)), fused, one lane per launch
 // ray.  Jobs with many receivers walk a ball tree over them and run the
-// exact test only where a conservative cull lets a receiver through.  The kernel is persistent: waves take packets of 64 x chunk rays from
-// a device queue until it is empty, so jobs of uneven size and rays of uneven
-// length are balanced over the machine.  A packet never spans two jobs, so
-// the job and its scene are uniform across a wave.
+// exact test only where a conservative cull lets a receiver through.  The
+// kernel is persistent: waves take packets of 64 x chunk rays from a device
+// queue until it is empty, so jobs of uneven size are balanced over the
+// machine, and lanes whose ray has ended take the packet's next ray, so rays
+// of uneven length keep the lanes busy.
 #include <math.h>
 
 #include "traverse.h"
 
 namespace sbr {
 
-// Launch ray r of job J: trace, receive, record.
-template <bool COUNT, bool LDS>
-__device__ static inline void trace_ray(const SceneDev& S, const LdsPlan& L, const JobDev& J,
-                                        const double* __restrict__ rx_all,
-                                        const RxNode* __restrict__ rx_nodes,
-                                        const int32_t* __restrict__ rx_perm, int64_t r,
-                                        sbr_candidate* __restrict__ cand, int64_t cap,
-                                        unsigned long long* __restrict__ ccount,
-                                        int32_t* __restrict__ out_tri, double* __restrict__ out_t,
-                                        int32_t* __restrict__ err, Tally* tl, uint32_t* segs,
-                                        uint32_t* events)
-{
-    const int K = J.K;
-    const int64_t ro = (r - J.ray_begin) * (K + 1);
-    d3 o = mk(J.tx[0], J.tx[1], J.tx[2]);
-    d3 d = mk(J.dir[r], J.dir[J.N + r], J.dir[2 * J.N + r]);
-    double D = 0.0;
-    int32_t prev = -1;
+// Per-lane state of the ray a lane is tracing: its current segment starts at
+// o with direction d after j reflections on faces[0..j), unfolded length D.
+struct RayState {
+    d3 o, d;
+    double D;
+    int64_t r;  // launch ray index; -1: the lane is idle
+    int32_t prev, j;
     int32_t faces[SBR_MAX_ORDER];
+};
+
+__device__ static inline void start_ray(const JobDev& J, int64_t r, RayState& R)
+{
+    R.r = r;
+    R.o = mk(J.tx[0], J.tx[1], J.tx[2]);
+    R.d = mk(J.dir[r], J.dir[J.N + r], J.dir[2 * J.N + r]);
+    R.D = 0.0;
+    R.prev = -1;
+    R.j = 0;
 #pragma unroll
-    for (int q = 0; q < SBR_MAX_ORDER; ++q) faces[q] = -1;
-    for (int j = 0; j <= K; ++j) {
-        HitRec h;
-        int32_t hit = traverse<false, COUNT, LDS>(S, L, o, d, prev, prev, S.t_eps, INFINITY,
-                                                  J.delta, &h, err, tl);
-        if (COUNT) *segs += 1;
-        double t = hit < 0 ? INFINITY : h.t;
-        if (out_tri) out_tri[ro + j] = hit < 0 ? -1 : h.orig;
-        if (out_t) out_t[ro + j] = t;
-        // reception test of receiver gx on this segment; events are appended
-        auto receive = [&](int32_t gx) {
-            double tn;
-            d3 rx = mk(rx_all[3 * gx], rx_all[3 * gx + 1], rx_all[3 * gx + 2]);
-            if (!capture(o, d, D, t, rx, J.thl, &tn)) return;
-            if (COUNT) *events += 1;
-            unsigned long long pos = atomicAdd(ccount, 1ull);
-            if ((int64_t)pos < cap) {
-                sbr_candidate c;
-                c.rx = gx;
-                c.order = j;
+    for (int q = 0; q < SBR_MAX_ORDER; ++q) R.faces[q] = -1;
+}
+
+// Append the reception event of receiver gx on the lane's current segment
+// (closed by the hit at t) when it passes the cone test of eq. (3).
+__device__ static inline void receive(const JobDev& J, const double* __restrict__ rx_all,
+                                      const RayState& R, double t, int32_t gx,
+                                      sbr_candidate* __restrict__ cand, int64_t cap,
+                                      unsigned long long* __restrict__ ccount, uint32_t* events,
+                                      bool count)
+{
+    double tn;
+    d3 rx = mk(rx_all[3 * gx], rx_all[3 * gx + 1], rx_all[3 * gx + 2]);
+    if (!capture(R.o, R.d, R.D, t, rx, J.thl, &tn)) return;
+    if (count) *events += 1;
+    unsigned long long pos = atomicAdd(ccount, 1ull);
+    if ((int64_t)pos < cap) {
+        sbr_candidate c;
+        c.rx = gx;
+        c.order = R.j;
 #pragma unroll
-                for (int q = 0; q < SBR_MAX_ORDER; ++q) c.face[q] = q < j ? faces[q] : -1;
-                c.ray = r;
-                c.tan_err = tn;
-                cand[pos] = c;
-            }
-        };
-        if (J.rx_root < 0) {
-            for (int x = 0; x < J.n_rx; ++x) receive(J.rx_first + x);
-        } else {
-            // stackless preorder walk of the job's receiver tree
-            int32_t nd = J.rx_root;
-            const int32_t end = rx_nodes[nd].skip;
-            while (nd != end) {
-                const RxNode N = rx_nodes[nd];
-                if (!rx_ball_may_capture(o, d, D, t, mk(N.c[0], N.c[1], N.c[2]), N.rho, J.thl)) {
-                    nd = N.skip;
-                } else if (N.count == 0) {
-                    nd = nd + 1;
-                } else {
-                    for (int q = 0; q < N.count; ++q) receive(rx_perm[N.first + q]);
-                    nd = N.skip;
-                }
-            }
-        }
-        if (hit < 0 || j == K) {
-            if (out_tri || out_t)
-                for (int q = j + 1; q <= K; ++q) {
-                    if (out_tri) out_tri[ro + q] = -1;
-                    if (out_t) out_t[ro + q] = INFINITY;
-                }
-            break;
-        }
-        // specular reflection on the face plane: o' = o + t d,
-        // d' = d - (2 d.n) n (no renormalization), D' = D + t
-        int32_t f = h.face;
-        d3 nf = face_normal(S, f);
-        d3 on = add(o, scl(t, d));
-        double k2 = 2.0 * dot(d, nf);
-        d = sub(d, scl(k2, nf));
-        D = D + t;
-        o = on;
-        prev = f;
-        faces[j] = f;
+        for (int q = 0; q < SBR_MAX_ORDER; ++q) c.face[q] = q < R.j ? R.faces[q] : -1;
+        c.ray = R.r;
+        c.tan_err = tn;
+        cand[pos] = c;
     }
 }
 
+// Persistent trace.  A wave takes a packet of 64 x chunk consecutive launch
+// rays of one job and hands them out to its lanes; each round, every busy
+// lane traces one segment (closest hit), runs the reception test of its
+// job's receivers on it and reflects, and a lane whose ray has ended takes
+// the packet's next ray.  Lanes thus stay busy while rays of different
+// lengths (escaping at once or bouncing K times) share a wave.  The wave
+// takes a new packet only when all its lanes are idle, so the job and its
+// scene stay uniform across the wave.
 template <bool COUNT, bool LDS>
-__global__ __launch_bounds__(LDS ? 1024 : 256) void k_trace(CallDev call, LdsPlan L, SceneDev s0,
+__global__ __launch_bounds__(256) void k_trace(CallDev call, LdsPlan L, SceneDev s0,
                                                uint32_t* __restrict__ queue,
                                                sbr_candidate* __restrict__ cand, int64_t cap,
                                                unsigned long long* __restrict__ ccount,
@@ -111,32 +80,96 @@ __global__ __launch_bounds__(LDS ? 1024 : 256) void k_trace(CallDev call, LdsPla
 {
     if (LDS) stage_scene(s0, L);
     const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1ull;
     Tally tl{0u, 0u};
     uint32_t segs = 0, events = 0;
+    JobDev J{};
+    SceneDev S = s0;
+    int64_t next = 0, pend = 0;  // rays of the current packet not yet handed out
+    RayState R;
+    R.r = -1;
     for (;;) {
-        uint32_t pk = 0;
-        if (lane == 0) pk = atomicAdd(queue, 1u);
-        pk = __builtin_amdgcn_readfirstlane(__shfl(pk, 0));
-        if ((int64_t)pk >= call.n_packets) break;
-        // the job of packet pk: the last job whose first packet is <= pk
-        int lo = 0, hi = call.n_jobs - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (call.jobs[mid].packet_first <= (int64_t)pk)
-                lo = mid;
-            else
-                hi = mid - 1;
+        const uint64_t idle = __ballot(R.r < 0);
+        if (idle != 0 && next < pend) {
+            const int64_t mine = next + __popcll(idle & below);
+            if (R.r < 0 && mine < pend) start_ray(J, mine, R);
+            next = min(pend, next + (int64_t)__popcll(idle));
         }
-        const JobDev J = call.jobs[lo];
-        const SceneDev S = LDS ? s0 : call.scenes[J.scene];
-        const int64_t base = J.ray_begin + ((int64_t)pk - J.packet_first) * 64 * call.chunk;
-        const int64_t end = J.ray_begin + J.ray_count;
-        for (int c = 0; c < call.chunk; ++c) {
-            const int64_t r = base + 64 * c + lane;
-            if (r < end)
-                trace_ray<COUNT, LDS>(S, L, J, call.rx, call.rx_nodes, call.rx_perm, r, cand, cap,
-                                      ccount, out_tri, out_t, err, &tl, &segs, &events);
+        if (__ballot(R.r >= 0) == 0) {
+            uint32_t pk = 0;
+            if (lane == 0) pk = atomicAdd(queue, 1u);
+            pk = __builtin_amdgcn_readfirstlane(__shfl(pk, 0));
+            if ((int64_t)pk >= call.n_packets) break;
+            // the job of packet pk: the last job whose first packet is <= pk
+            int lo = 0, hi = call.n_jobs - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (call.jobs[mid].packet_first <= (int64_t)pk)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            J = call.jobs[lo];
+            if (!LDS) S = call.scenes[J.scene];
+            next = J.ray_begin + ((int64_t)pk - J.packet_first) * 64 * call.chunk;
+            pend = min(next + 64 * (int64_t)call.chunk, J.ray_begin + J.ray_count);
+            continue;
         }
+        if (R.r < 0) continue;
+        // one segment: closest hit, excluding the face just reflected on
+        const int K = J.K;
+        HitRec h;
+        const int32_t hit = traverse<false, COUNT, LDS>(S, L, R.o, R.d, R.prev, R.prev, S.t_eps,
+                                                        INFINITY, J.delta, &h, err, &tl);
+        if (COUNT) segs += 1;
+        const double t = hit < 0 ? INFINITY : h.t;
+        const int64_t ro = (R.r - J.ray_begin) * (K + 1);
+        if (out_tri) out_tri[ro + R.j] = hit < 0 ? -1 : h.orig;
+        if (out_t) out_t[ro + R.j] = t;
+        // reception on the segment
+        if (J.rx_root < 0) {
+            for (int x = 0; x < J.n_rx; ++x)
+                receive(J, call.rx, R, t, J.rx_first + x, cand, cap, ccount, &events, COUNT);
+        } else {
+            // stackless preorder walk of the job's receiver tree
+            int32_t nd = J.rx_root;
+            const int32_t end = call.rx_nodes[nd].skip;
+            while (nd != end) {
+                const RxNode N = call.rx_nodes[nd];
+                if (!rx_ball_may_capture(R.o, R.d, R.D, t, mk(N.c[0], N.c[1], N.c[2]), N.rho,
+                                         J.thl)) {
+                    nd = N.skip;
+                } else if (N.count == 0) {
+                    nd = nd + 1;
+                } else {
+                    for (int q = 0; q < N.count; ++q)
+                        receive(J, call.rx, R, t, call.rx_perm[N.first + q], cand, cap, ccount,
+                                &events, COUNT);
+                    nd = N.skip;
+                }
+            }
+        }
+        if (hit < 0 || R.j == K) {
+            if (out_tri || out_t)
+                for (int q = R.j + 1; q <= K; ++q) {
+                    if (out_tri) out_tri[ro + q] = -1;
+                    if (out_t) out_t[ro + q] = INFINITY;
+                }
+            R.r = -1;
+            continue;
+        }
+        // specular reflection on the face plane: o' = o + t d,
+        // d' = d - (2 d.n) n (no renormalization), D' = D + t
+        const int32_t f = h.face;
+        const d3 nf = face_normal(S, f);
+        const d3 on = add(R.o, scl(t, R.d));
+        const double k2 = 2.0 * dot(R.d, nf);
+        R.d = sub(R.d, scl(k2, nf));
+        R.D = R.D + t;
+        R.o = on;
+        R.prev = f;
+        R.faces[R.j] = f;
+        R.j += 1;
     }
     if (COUNT) {
         atomicAdd(&tallies[0], (unsigned long long)segs);

@@ -292,14 +292,15 @@ def test_refine_lookahead_matches_single_step(gpu, orc, prm):
 
 
 def test_lds_staged_traversal_matches(gpu, orc):
-    """LDS-staged traversal (node prefix, triangles and stack in LDS) gives
-    the same paths as global-memory traversal."""
+    """LDS-staged traversal (node prefix, triangles and stack in LDS, or the
+    stack alone) gives the same paths as global-memory traversal."""
     cfg = scenes.manhattan_config(3, n_rx=16)
     prm = dict(cfg["params"], division_n=80)
     a = _trace_with_env({"SBR_LDS_BUDGET": "0"}, cfg, **prm)
     b = _trace_with_env({"SBR_LDS_BUDGET": "65536", "SBR_STACK_DEPTH": "4"}, cfg, **prm)
-    c = _trace_with_env({"SBR_LDS_BUDGET": "163840", "SBR_TRACE_BLOCK": "512"}, cfg, **prm)
-    assert a.tobytes() == b.tobytes() == c.tobytes()
+    c = _trace_with_env({"SBR_LDS_BUDGET": "163840", "SBR_TRACE_BLOCK": "128"}, cfg, **prm)
+    d = _trace_with_env({"SBR_LDS_BUDGET": "24576", "SBR_STACK_DEPTH": "24"}, cfg, **prm)
+    assert a.tobytes() == b.tobytes() == c.tobytes() == d.tobytes()
     _compare_paths(a, orc.run(cfg["scene"], cfg["tx"], cfg["rx"], **prm)["paths"])
 
 
@@ -414,7 +415,8 @@ def test_tuning_roundtrip_and_invariance(gpu):
     try:
         ref, _ = sc.trace(cfg["tx"], cfg["rx"], **prm)
         for t in (dict(trace_chunk=3, persist_blocks=7), dict(persist_blocks=1),
-                  dict(lds_budget=65536, stack_depth=8, trace_block=512),
+                  dict(lds_budget=65536, stack_depth=8, trace_block=128),
+                  dict(lds_budget=24 * 4 * 256, stack_depth=24),
                   dict(lookahead_max_paths=0, trace_chunk=64), dict(rx_tree_min=1)):
             gpu.set_tuning(**dict(base, **t))
             assert gpu.tuning()["trace_chunk"] == dict(base, **t)["trace_chunk"]
