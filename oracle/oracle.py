@@ -55,6 +55,7 @@ class Params(C.Structure):
         ("tx_power_dbm", C.c_double),
         ("keep_invalid", C.c_int32),
         ("n_threads", C.c_int32),
+        ("launch", C.c_int32),
     ]
 
 
@@ -122,14 +123,17 @@ def lib():
         L.orc_num_rays.restype = C.c_int64
         L.orc_num_rays.argtypes = [C.c_int32]
         L.orc_launch_dirs.argtypes = [C.c_int32, lp, C.c_int64, dp]
+        L.orc_num_rays_m.restype = C.c_int64
+        L.orc_num_rays_m.argtypes = [C.c_int32, C.c_int32]
+        L.orc_launch_dirs_m.argtypes = [C.c_int32, C.c_int32, lp, C.c_int64, dp]
         L.orc_sin_cr.restype = C.c_double
         L.orc_sin_cr.argtypes = [C.c_double]
         L.orc_acos_cr.restype = C.c_double
         L.orc_acos_cr.argtypes = [C.c_double]
         L.orc_fresnel_avg.restype = C.c_double
         L.orc_fresnel_avg.argtypes = [C.c_double, C.c_double, C.c_double]
-        L.orc_trace_rays.argtypes = [dp, ip, C.c_int64, dp, C.c_int32, C.c_int32, lp, C.c_int64,
-                                     C.c_int32, ip, ip, dp]
+        L.orc_trace_rays.argtypes = [dp, ip, C.c_int64, dp, C.c_int32, C.c_int32, C.c_int32, lp,
+                                     C.c_int64, C.c_int32, ip, ip, dp]
         L.orc_trace_dirs.argtypes = [dp, ip, C.c_int64, dp, dp, C.c_int64, C.c_int32, ip, ip,
                                      dp, dp]
         L.orc_run.argtypes = [dp, ip, ip, C.c_int64, dp, dp, C.c_int32, dp, dp, C.c_int32,
@@ -140,8 +144,9 @@ def lib():
         L.orc_free.argtypes = [C.c_void_p]
         L.orc_refine_history.argtypes = [dp, ip, C.c_int64, dp, C.POINTER(Params), dp, ip, ip,
                                          dp, C.c_int64, dp]
-        L.orc_ray_events.argtypes = [dp, ip, C.c_int64, dp, C.c_int32, C.c_int32, dp, C.c_int32,
-                                     lp, C.c_int64, C.c_int32, C.POINTER(C.POINTER(_Cand)), lp]
+        L.orc_ray_events.argtypes = [dp, ip, C.c_int64, dp, C.c_int32, C.c_int32, C.c_int32, dp,
+                                     C.c_int32, lp, C.c_int64, C.c_int32,
+                                     C.POINTER(C.POINTER(_Cand)), lp]
         L.orc_path_records.argtypes = [dp, ip, ip, C.c_int64, dp, dp, C.c_int32, dp, dp,
                                        C.c_int32, C.POINTER(Params), C.c_void_p, C.c_int64,
                                        C.c_void_p]
@@ -174,19 +179,22 @@ def _scene_arrays(scene):
     return tri_v, face, mat, er, ei
 
 
-def num_rays(n: int) -> int:
-    return int(lib().orc_num_rays(n))
+EQUIANGULAR, EQUIDISTANT_ICOSA, EQUIDISTANT_OCTA = 0, 1, 2
 
 
-def launch_dirs(n: int, ids=None) -> np.ndarray:
+def num_rays(n: int, launch: int = EQUIANGULAR) -> int:
+    return int(lib().orc_num_rays_m(launch, n))
+
+
+def launch_dirs(n: int, ids=None, launch: int = EQUIANGULAR) -> np.ndarray:
     if ids is None:
-        m = num_rays(n)
+        m = num_rays(n, launch)
         out = np.empty((m, 3), np.float64)
-        rc = lib().orc_launch_dirs(n, None, 0, _d(out))
+        rc = lib().orc_launch_dirs_m(launch, n, None, 0, _d(out))
     else:
         ids = np.ascontiguousarray(ids, dtype=np.int64)
         out = np.empty((len(ids), 3), np.float64)
-        rc = lib().orc_launch_dirs(n, _l(ids), len(ids), _d(out))
+        rc = lib().orc_launch_dirs_m(launch, n, _l(ids), len(ids), _d(out))
     if rc:
         raise ValueError("orc_launch_dirs failed (%d)" % rc)
     return out
@@ -204,12 +212,12 @@ def fresnel_avg(cos_i: float, eps: complex) -> float:
     return lib().orc_fresnel_avg(cos_i, eps.real, eps.imag)
 
 
-def trace_rays(scene, tx, n, max_order, ids=None, threads=0):
+def trace_rays(scene, tx, n, max_order, ids=None, threads=0, launch=EQUIANGULAR):
     """Per-ray closest hits of segments 0..K: (tri, face, t) arrays [m, K+1]."""
     tri_v, face, _, _, _ = _scene_arrays(scene)
     txa = np.ascontiguousarray(tx, dtype=np.float64)
     if ids is None:
-        m = num_rays(n)
+        m = num_rays(n, launch)
         idp = None
     else:
         ids = np.ascontiguousarray(ids, dtype=np.int64)
@@ -218,7 +226,7 @@ def trace_rays(scene, tx, n, max_order, ids=None, threads=0):
     ot = np.empty((m, max_order + 1), np.int32)
     of = np.empty((m, max_order + 1), np.int32)
     oT = np.empty((m, max_order + 1), np.float64)
-    rc = lib().orc_trace_rays(_d(tri_v), _i(face), len(face), _d(txa), n, max_order, idp,
+    rc = lib().orc_trace_rays(_d(tri_v), _i(face), len(face), _d(txa), n, launch, max_order, idp,
                               m, threads, _i(ot), _i(of), _d(oT))
     if rc:
         raise ValueError("orc_trace_rays failed (%d)" % rc)
@@ -243,9 +251,10 @@ def trace_dirs(scene, tx, dirs, max_order):
 
 
 def make_params(max_order=3, division_n=20, iterations=3, subrays=6, target_err_deg=0.0,
-                freq_hz=28e9, tx_power_dbm=0.0, keep_invalid=False, threads=0) -> Params:
+                freq_hz=28e9, tx_power_dbm=0.0, keep_invalid=False, threads=0,
+                launch=EQUIANGULAR) -> Params:
     return Params(max_order, division_n, iterations, subrays, target_err_deg, freq_hz,
-                  tx_power_dbm, int(bool(keep_invalid)), threads)
+                  tx_power_dbm, int(bool(keep_invalid)), threads, launch)
 
 
 def _take(ptr, n, dtype):
@@ -280,7 +289,7 @@ def run(scene, tx, rx, **kw):
     }
 
 
-def ray_events(scene, tx, rx, n, max_order, ids, threads=0):
+def ray_events(scene, tx, rx, n, max_order, ids, threads=0, launch=EQUIANGULAR):
     """Reception events of the launch rays `ids` only (step 1 of run())."""
     tri_v, face, _, _, _ = _scene_arrays(scene)
     txa = np.ascontiguousarray(tx, dtype=np.float64)
@@ -288,7 +297,7 @@ def ray_events(scene, tx, rx, n, max_order, ids, threads=0):
     ids = np.ascontiguousarray(ids, dtype=np.int64)
     cp = C.POINTER(_Cand)()
     nc = C.c_int64()
-    rc = lib().orc_ray_events(_d(tri_v), _i(face), len(face), _d(txa), n, max_order, _d(rxa),
+    rc = lib().orc_ray_events(_d(tri_v), _i(face), len(face), _d(txa), n, launch, max_order, _d(rxa),
                               len(rxa), _l(ids), len(ids), threads, C.byref(cp), C.byref(nc))
     if rc:
         raise ValueError("orc_ray_events failed (%d)" % rc)

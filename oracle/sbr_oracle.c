@@ -58,8 +58,16 @@ static double atan_cr(double x) { return (double)atanq((__float128)x); }
 
 /* theta_0 = angle subtended by one icosahedron edge = atan(2) (eq. (4)). */
 static double theta0(void) { return atan_cr(2.0); }
-/* Cone half-angle theta_launch = theta_0 / (sqrt(3) n), eq. (4). */
-static double theta_launch(int32_t n) { return theta0() / (sqrt(3.0) * (double)n); }
+/* Cone half-angle theta_launch = theta_0 / (sqrt(3) n), eq. (4), theta_0 the
+ * angle subtended by a polyhedron edge.  Reading: the equidistant grids of
+ * Sec. II.A keep the same rule with their own edge angle (atan 2 for the
+ * icosahedron, pi/2 for the octahedron). */
+static double theta_launch_m(int32_t method, int32_t n)
+{
+    double th = method == ORC_LAUNCH_EQUIDISTANT_OCTA ? PI_D / 2.0 : theta0();
+    return th / (sqrt(3.0) * (double)n);
+}
+static double theta_launch(int32_t n) { return theta_launch_m(ORC_LAUNCH_EQUIANGULAR, n); }
 
 /* ======================================================================== */
 /* Launch grid -- Sec. II.B                                                  */
@@ -191,20 +199,101 @@ int64_t orc_num_rays(int32_t n)
     return 10 * (int64_t)n * n + 2;
 }
 
+int64_t orc_num_rays_m(int32_t method, int32_t n)
+{
+    if (n < 1 || method < 0 || method > ORC_LAUNCH_EQUIDISTANT_OCTA) return 0;
+    return (method == ORC_LAUNCH_EQUIDISTANT_OCTA ? 4 : 10) * (int64_t)n * n + 2;
+}
+
+/* A regular polyhedron with triangular faces for the equidistant grids of
+ * Sec. II.A: vertices, edges (adjacent pairs i < j, lexicographic) and faces
+ * (mutually adjacent triples i < j < k, lexicographic, wound counter-clockwise
+ * seen from outside).  The icosahedron is the one above; the octahedron has
+ * the vertices +x, -x, +y, -y, +z, -z in this order (adjacent: not
+ * antipodal). */
 typedef struct {
-    int32_t n;
+    int nv, ne, nf;
+    v3 V[12];
+    int e[30][2];
+    int f[20][3];
+} poly_t;
+
+static void poly_build(poly_t* P, int32_t method)
+{
+    if (method == ORC_LAUNCH_EQUIDISTANT_OCTA) {
+        const double raw[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+        P->nv = 6;
+        for (int i = 0; i < 6; ++i) P->V[i] = ld3(raw[i]);
+        P->ne = P->nf = 0;
+        for (int i = 0; i < 6; ++i)
+            for (int j = i + 1; j < 6; ++j)
+                if (dot(P->V[i], P->V[j]) > -0.5) { P->e[P->ne][0] = i; P->e[P->ne][1] = j; ++P->ne; }
+        for (int i = 0; i < 6; ++i)
+            for (int j = i + 1; j < 6; ++j)
+                for (int k = j + 1; k < 6; ++k)
+                    if (dot(P->V[i], P->V[j]) > -0.5 && dot(P->V[j], P->V[k]) > -0.5 &&
+                        dot(P->V[i], P->V[k]) > -0.5) {
+                        double sg = dot(P->V[i], cross(P->V[j], P->V[k]));
+                        P->f[P->nf][0] = i;
+                        P->f[P->nf][1] = sg > 0.0 ? j : k;
+                        P->f[P->nf][2] = sg > 0.0 ? k : j;
+                        ++P->nf;
+                    }
+        return;
+    }
+    ico_t ic;
+    ico_build(&ic);
+    P->nv = 12; P->ne = 30; P->nf = 20;
+    memcpy(P->V, ic.V, sizeof(ic.V));
+    memcpy(P->e, ic.e, sizeof(ic.e));
+    memcpy(P->f, ic.f, sizeof(ic.f));
+}
+
+/* Equidistant division (Sec. II.A): points at equal spacing on the flat
+ * faces, projected onto the sphere.  Order: vertices; edge interiors edge by
+ * edge, k = 1..n-1 from the lower vertex, at (n-k) V_i + k V_j; face
+ * interiors face by face, rows i = 1..n-2 and j = 1..n-1-i, at
+ * (n-i-j) A + i B + j C for the face's corners A, B, C; each normalized. */
+static v3 equidistant_dir(const poly_t* P, int32_t n, int64_t idx)
+{
+    if (idx < P->nv) return P->V[idx];
+    idx -= P->nv;
+    if (idx < (int64_t)P->ne * (n - 1)) {
+        int64_t e = idx / (n - 1), k = idx % (n - 1) + 1;
+        return normalize(add(scl((double)(n - k), P->V[P->e[e][0]]), scl((double)k, P->V[P->e[e][1]])));
+    }
+    idx -= (int64_t)P->ne * (n - 1);
+    int64_t per_face = (int64_t)(n - 1) * (n - 2) / 2;
+    int64_t f = idx / per_face, q = idx % per_face;
+    int64_t i = 1;
+    while (q >= n - 1 - i) { q -= n - 1 - i; ++i; }
+    int64_t j = q + 1, a = n - i - j;
+    v3 A = P->V[P->f[f][0]], B = P->V[P->f[f][1]], C = P->V[P->f[f][2]];
+    return normalize(add(add(scl((double)a, A), scl((double)i, B)), scl((double)j, C)));
+}
+
+typedef struct {
+    int32_t n, method;
     ico_t ic;
     face_rings fr[20];
+    poly_t poly;
 } grid_t;
 
-static void grid_init(grid_t* G, int32_t n)
+static void grid_init_m(grid_t* G, int32_t method, int32_t n)
 {
     G->n = n;
+    G->method = method;
+    if (method != ORC_LAUNCH_EQUIANGULAR) {
+        poly_build(&G->poly, method);
+        return;
+    }
     ico_build(&G->ic);
     for (int f = 0; f < 20; ++f) rings_build(&G->fr[f], &G->ic, f, n);
 }
+static void grid_init(grid_t* G, int32_t n) { grid_init_m(G, ORC_LAUNCH_EQUIANGULAR, n); }
 static void grid_free(grid_t* G)
 {
+    if (G->method != ORC_LAUNCH_EQUIANGULAR) return;
     for (int f = 0; f < 20; ++f) rings_free(&G->fr[f]);
 }
 
@@ -215,6 +304,7 @@ static void grid_free(grid_t* G)
 static v3 grid_dir(const grid_t* G, int64_t idx)
 {
     const int64_t n = G->n;
+    if (G->method != ORC_LAUNCH_EQUIANGULAR) return equidistant_dir(&G->poly, G->n, idx);
     if (idx < 12) return G->ic.V[idx];
     idx -= 12;
     if (idx < 30 * (n - 1)) {
@@ -238,11 +328,16 @@ static v3 grid_dir(const grid_t* G, int64_t idx)
 
 int orc_launch_dirs(int32_t n, const int64_t* ids, int64_t m, double* out)
 {
-    if (n < 1 || !out) return -1;
-    int64_t N = orc_num_rays(n);
+    return orc_launch_dirs_m(ORC_LAUNCH_EQUIANGULAR, n, ids, m, out);
+}
+
+int orc_launch_dirs_m(int32_t method, int32_t n, const int64_t* ids, int64_t m, double* out)
+{
+    if (n < 1 || !out || method < 0 || method > ORC_LAUNCH_EQUIDISTANT_OCTA) return -1;
+    int64_t N = orc_num_rays_m(method, n);
     if (!ids) m = N;
     grid_t G;
-    grid_init(&G, n);
+    grid_init_m(&G, method, n);
     int bad = 0;
 #pragma omp parallel for schedule(static) reduction(| : bad)
     for (int64_t i = 0; i < m; ++i) {
@@ -425,17 +520,19 @@ static int capture_seg(const seg_t* sg, v3 rx, double thl, double* tan_out)
 }
 
 int orc_trace_rays(const double* tri_v, const int32_t* face_id, int64_t n_tri,
-                   const double tx[3], int32_t n, int32_t K,
+                   const double tx[3], int32_t n, int32_t launch, int32_t K,
                    const int64_t* ids, int64_t m, int32_t n_threads,
                    int32_t* out_tri, int32_t* out_face, double* out_t)
 {
-    if (n < 1 || K < 0 || K > ORC_MAX_ORDER || n_tri < 0) return -1;
-    int64_t N = orc_num_rays(n);
+    if (n < 1 || K < 0 || K > ORC_MAX_ORDER || n_tri < 0 || launch < 0 ||
+        launch > ORC_LAUNCH_EQUIDISTANT_OCTA)
+        return -1;
+    int64_t N = orc_num_rays_m(launch, n);
     if (!ids) m = N;
     scene_t S;
     if (scene_init(&S, tri_v, face_id, NULL, n_tri)) { scene_free(&S); return -1; }
     grid_t G;
-    grid_init(&G, n);
+    grid_init_m(&G, launch, n);
     v3 T = ld3(tx);
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
@@ -902,18 +999,18 @@ int orc_run(const double* tri_v, const int32_t* face_id, const int32_t* mat_id,
 {
     if (!P || P->division_n < 1 || P->max_order < 0 || P->max_order > ORC_MAX_ORDER ||
         P->iterations < 0 || (P->subrays != 6 && P->subrays != 7) || n_rx < 0 || T < 0 ||
-        !(P->freq_hz > 0.0))
+        !(P->freq_hz > 0.0) || P->launch < 0 || P->launch > ORC_LAUNCH_EQUIDISTANT_OCTA)
         return -1;
     for (int64_t i = 0; i < T; ++i)
         if (mat_id && (mat_id[i] < 0 || mat_id[i] >= n_mat)) return -1;
     scene_t S;
     if (scene_init(&S, tri_v, face_id, mat_id, T)) { scene_free(&S); return -1; }
     const int32_t n = P->division_n, K = P->max_order;
-    const int64_t N = orc_num_rays(n);
-    const double thl = theta_launch(n);
+    const int64_t N = orc_num_rays_m(P->launch, n);
+    const double thl = theta_launch_m(P->launch, n);
     const v3 TX = ld3(tx);
     grid_t G;
-    grid_init(&G, n);
+    grid_init_m(&G, P->launch, n);
 #ifdef _OPENMP
     if (P->n_threads > 0) omp_set_num_threads(P->n_threads);
     int nth = omp_get_max_threads();
@@ -981,20 +1078,21 @@ int orc_run(const double* tri_v, const int32_t* face_id, const int32_t* mat_id,
 void orc_free(void* p) { free(p); }
 
 int orc_ray_events(const double* tri_v, const int32_t* face_id, int64_t T, const double tx[3],
-                   int32_t n, int32_t K, const double* rx, int32_t n_rx, const int64_t* ids,
-                   int64_t m, int32_t n_threads, orc_candidate** out, int64_t* n_out)
+                   int32_t n, int32_t launch, int32_t K, const double* rx, int32_t n_rx,
+                   const int64_t* ids, int64_t m, int32_t n_threads, orc_candidate** out,
+                   int64_t* n_out)
 {
     if (n < 1 || K < 0 || K > ORC_MAX_ORDER || T < 0 || n_rx < 0 || m < 0 || !ids || !out ||
-        !n_out)
+        !n_out || launch < 0 || launch > ORC_LAUNCH_EQUIDISTANT_OCTA)
         return -1;
-    const int64_t N = orc_num_rays(n);
+    const int64_t N = orc_num_rays_m(launch, n);
     for (int64_t i = 0; i < m; ++i)
         if (ids[i] < 0 || ids[i] >= N) return -1;
     scene_t S;
     if (scene_init(&S, tri_v, face_id, NULL, T)) { scene_free(&S); return -1; }
     grid_t G;
-    grid_init(&G, n);
-    const double thl = theta_launch(n);
+    grid_init_m(&G, launch, n);
+    const double thl = theta_launch_m(launch, n);
     const v3 TX = ld3(tx);
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
@@ -1026,9 +1124,9 @@ int orc_path_records(const double* tri_v, const int32_t* face_id, const int32_t*
 {
     if (!P || P->division_n < 1 || P->max_order < 0 || P->max_order > ORC_MAX_ORDER ||
         P->iterations < 0 || (P->subrays != 6 && P->subrays != 7) || n_rx < 0 || T < 0 ||
-        m < 0 || !(P->freq_hz > 0.0))
+        m < 0 || !(P->freq_hz > 0.0) || P->launch < 0 || P->launch > ORC_LAUNCH_EQUIDISTANT_OCTA)
         return -1;
-    const int64_t N = orc_num_rays(P->division_n);
+    const int64_t N = orc_num_rays_m(P->launch, P->division_n);
     for (int64_t i = 0; i < T; ++i)
         if (mat_id && (mat_id[i] < 0 || mat_id[i] >= n_mat)) return -1;
     for (int64_t i = 0; i < m; ++i)
@@ -1038,8 +1136,8 @@ int orc_path_records(const double* tri_v, const int32_t* face_id, const int32_t*
     scene_t S;
     if (scene_init(&S, tri_v, face_id, mat_id, T)) { scene_free(&S); return -1; }
     grid_t G;
-    grid_init(&G, P->division_n);
-    const double thl = theta_launch(P->division_n);
+    grid_init_m(&G, P->launch, P->division_n);
+    const double thl = theta_launch_m(P->launch, P->division_n);
     double tan_tgt = 0.0;
     if (P->target_err_deg > 0.0) tan_tgt = tan_cr((P->target_err_deg * PI_D) / 180.0);
 #ifdef _OPENMP
@@ -1062,7 +1160,7 @@ int orc_refine_history(const double* tri_v, const int32_t* face_id, int64_t T,
         return -1;
     scene_t S;
     if (scene_init(&S, tri_v, face_id, NULL, T)) { scene_free(&S); return -1; }
-    const double thl = theta_launch(P->division_n);
+    const double thl = theta_launch_m(P->launch, P->division_n);
     const int32_t n_it = P->iterations;
 #ifdef _OPENMP
     if (P->n_threads > 0) omp_set_num_threads(P->n_threads);

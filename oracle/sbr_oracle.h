@@ -26,11 +26,20 @@
 
 #define ORC_MAX_ORDER 8
 
+/* Launch methods: the equiangular icosahedral division of Sec. II.B and the
+ * equidistant divisions of Sec. II.A on the icosahedron and octahedron. */
+#define ORC_LAUNCH_EQUIANGULAR 0
+#define ORC_LAUNCH_EQUIDISTANT_ICOSA 1
+#define ORC_LAUNCH_EQUIDISTANT_OCTA 2
+
 /* Launch grid: Sec. II.B, eqs. (1)-(2) and the innermost-layer cases;
  * ray count 10 n^2 + 2 stated with eq. (4). */
 int64_t orc_num_rays(int32_t n);
 /* Directions for ray indices ids[0..m-1] (ids == NULL: all rays in order). */
 int orc_launch_dirs(int32_t n, const int64_t* ids, int64_t m, double* out_xyz);
+/* The same for any launch method (4 n^2 + 2 rays for the octahedron). */
+int64_t orc_num_rays_m(int32_t method, int32_t n);
+int orc_launch_dirs_m(int32_t method, int32_t n, const int64_t* ids, int64_t m, double* out_xyz);
 /* Correctly rounded helpers exposed for pin tests. */
 double orc_sin_cr(double x);
 double orc_acos_cr(double x);
@@ -45,6 +54,7 @@ typedef struct {
     double  tx_power_dbm;
     int32_t keep_invalid;   /* keep paths that fail the validity test          */
     int32_t n_threads;      /* OpenMP threads, <= 0: runtime default           */
+    int32_t launch;         /* ORC_LAUNCH_*                                    */
 } orc_params;
 
 typedef struct {
@@ -68,7 +78,7 @@ typedef struct {
 /* Per-ray closest hits of segments 0..K (ray "ids", or all if ids == NULL):
  * out_tri/out_face [m][K+1] (-1 = no hit), out_t [m][K+1] (+inf = no hit). */
 int orc_trace_rays(const double* tri_v, const int32_t* face_id, int64_t n_tri,
-                   const double tx[3], int32_t n, int32_t max_order,
+                   const double tx[3], int32_t n, int32_t launch, int32_t max_order,
                    const int64_t* ids, int64_t m, int32_t n_threads,
                    int32_t* out_tri, int32_t* out_face, double* out_t);
 
@@ -91,7 +101,8 @@ void orc_free(void* p);
 /* Step 1 alone for the launch rays ids[0..m-1]: their reception events, in
  * the order (ids order, segment, rx), returned in a malloc'd array. */
 int orc_ray_events(const double* tri_v, const int32_t* face_id, int64_t n_tri,
-                   const double tx[3], int32_t n, int32_t max_order, const double* rx,
+                   const double tx[3], int32_t n, int32_t launch, int32_t max_order,
+                   const double* rx,
                    int32_t n_rx, const int64_t* ids, int64_t m, int32_t n_threads,
                    orc_candidate** out, int64_t* n_out);
 

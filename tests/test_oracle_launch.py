@@ -212,17 +212,108 @@ def test_layer_sizes_and_innermost_cases(orc, n):
             off += m3
 
 
+OCTA_SIGNED_PERMS = [np.diag(sg)[list(pm)] for pm in
+                     [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
+                     for sg in [(a, b, c) for a in (1, -1) for b in (1, -1) for c in (1, -1)]]
+
+
+def _same_set(P, Q, tol):
+    assert P.shape == Q.shape
+    d = np.abs(P[:, None, :] - Q[None, :, :]).max(axis=2)
+    return d.min(axis=1).max() < tol and d.min(axis=0).max() < tol
+
+
+@pytest.mark.parametrize("launch", [1, 2])
+def test_equidistant_counts_norms_and_vertices(orc, launch):
+    """Sec. II.A: 10 n^2 + 2 (icosahedron) or 4 n^2 + 2 (octahedron) unit
+    directions; n = 1 gives the polyhedron's vertices."""
+    per = 10 if launch == 1 else 4
+    for n in range(1, 13):
+        d = orc.launch_dirs(n, launch=launch)
+        assert len(d) == orc.num_rays(n, launch) == per * n * n + 2
+        assert np.abs(np.linalg.norm(d, axis=1) - 1.0).max() < 4.5e-16
+    V = ico_vertex_set() if launch == 1 else octa_faces()[0]
+    assert _same_set(orc.launch_dirs(1, launch=launch), V, 1e-15)
+
+
+def test_equidistant_octahedron_n2_closed_form(orc):
+    """n = 2 on the octahedron: the 6 axes and the 12 edge midpoints
+    (+-1, +-1, 0)/sqrt(2) and permutations."""
+    r = 1.0 / math.sqrt(2.0)
+    mids = [p for p in ([a, b, 0.0] for a in (r, -r) for b in (r, -r))]
+    mids = [np.array(m)[list(pm)] for m in mids for pm in [(0, 1, 2), (0, 2, 1), (2, 0, 1)]]
+    want = np.concatenate([octa_faces()[0], np.array(mids)])
+    assert _same_set(orc.launch_dirs(2, launch=2), want, 2e-16)
+
+
+@pytest.mark.parametrize("launch,n", [(1, 7), (1, 12), (2, 9), (2, 14)])
+def test_equidistant_points_are_equally_spaced_on_the_faces(orc, launch, n):
+    """The defining property of equidistant division: centrally projected back
+    onto the flat polyhedron faces, the face-interior points are exactly the
+    barycentric lattice {(a, b, c)/n : a, b, c >= 1} and the edge points divide
+    each edge chord into n equal parts."""
+    d = orc.launch_dirs(n, launch=launch)
+    nv, ne = (12, 30) if launch == 1 else (6, 12)
+    V = d[:nv]  # the vertex rays come first (pinned as a set above)
+    faces = [(i, j, k) for i in range(nv) for j in range(i + 1, nv) for k in range(j + 1, nv)
+             if min(V[i] @ V[j], V[j] @ V[k], V[i] @ V[k]) > (0 if launch == 1 else -0.5)]
+    # edges: adjacent vertex pairs i < j in lexicographic order, as documented
+    edges = [(i, j) for i in range(nv) for j in range(i + 1, nv)
+             if V[i] @ V[j] > (0 if launch == 1 else -0.5)]
+    assert len(edges) == ne and len(faces) == (20 if launch == 1 else 8)
+    E = d[nv: nv + ne * (n - 1)].reshape(ne, n - 1, 3)
+    for (i, j), pts in zip(edges, E):
+        # p ~ (1 - s) Vi + s Vj  =>  s = (p x Vi) . (Vj x Vi) / |Vj x Vi|^2 on the chord
+        s = np.array([np.linalg.lstsq(np.stack([V[i], V[j] - V[i]], 1), p, rcond=None)[0]
+                      for p in pts])
+        s = s[:, 1] / s[:, 0]
+        assert np.abs(s - np.arange(1, n) / n).max() < 1e-13
+    F = d[nv + ne * (n - 1):].reshape(len(faces), (n - 1) * (n - 2) // 2, 3)
+    want = sorted((a, b, n - a - b) for a in range(1, n) for b in range(1, n) if n - a - b >= 1)
+    for pts in F:
+        # the face the block belongs to: the one whose vertices span it positively
+        lam = None
+        for f in faces:
+            M = V[list(f)].T
+            L = np.linalg.solve(M, pts.T).T
+            if (L > 0).all():
+                lam = L / L.sum(axis=1, keepdims=True) * n
+                break
+        assert lam is not None
+        got = sorted(tuple(int(round(x)) for x in row) for row in lam)
+        assert np.abs(lam - np.round(lam)).max() < 1e-11
+        cyc = {tuple(np.roll(w, k)) for w in want for k in range(3)}
+        assert all(g in cyc for g in got) and len(set(got)) == len(want)
+
+
+@pytest.mark.parametrize("launch,n", [(1, 6), (2, 7)])
+def test_equidistant_symmetry(orc, launch, n):
+    """The point set is invariant under the polyhedron's symmetry group (60
+    rotations of the icosahedron; 48 signed permutations for the octahedron)
+    and equals an independent lattice-and-project construction."""
+    d = orc.launch_dirs(n, launch=launch)
+    group = ico_rotations() if launch == 1 else OCTA_SIGNED_PERMS
+    assert len(group) == (60 if launch == 1 else 48)
+    for R in group[:: 5 if launch == 1 else 3]:
+        assert _same_set(d @ R.T, d, 1e-14)
+    if launch == 1:
+        V = ico_vertex_set()
+        ref = equidistant_grid(V, ico_faces(V), n)
+    else:
+        Vo, Fo = octa_faces()
+        ref = equidistant_grid(Vo, Fo, n)
+    assert _same_set(d, ref, 1e-14)
+
+
 def test_equiangular_more_uniform_than_equidistant(orc):
     """Sec. II.B / Fig. 2: at the same ray count, equiangular division on the
     icosahedron is more uniform than equidistant division on the icosahedron,
     which is more uniform than equidistant division on the octahedron."""
     n = 21
     d = orc.launch_dirs(n)
-    V = ico_vertex_set()
-    eq_ico = equidistant_grid(V, ico_faces(V), n)
+    eq_ico = orc.launch_dirs(n, launch=1)
     assert len(eq_ico) == len(d) == 4412
-    Vo, Fo = octa_faces()
-    eq_oct = equidistant_grid(Vo, Fo, 33)   # 4 * 33^2 + 2 = 4358 rays
+    eq_oct = orc.launch_dirs(33, launch=2)   # 4 * 33^2 + 2 = 4358 rays
     assert len(eq_oct) == 4358
 
     def stats(P):
