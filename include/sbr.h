@@ -56,8 +56,9 @@ typedef struct {
 /* Trace parameters (Sec. II.B and Sec. III). */
 typedef struct {
     int32_t max_order;     /* K: specular reflections per ray, 0..SBR_MAX_ORDER        */
-    int32_t division_n;    /* n >= 1: icosahedron edges split into n equal angles,
-                              10 n^2 + 2 launch rays (Sec. III.B, with eq. (4))       */
+    int32_t division_n;    /* n >= 1: polyhedron edges split into n parts; with the
+                              equiangular icosahedron 10 n^2 + 2 launch rays
+                              (Sec. III.B, with eq. (4))                              */
     int32_t iterations;    /* I >= 0: precise-algorithm iterations (Sec. III.B);
                               0 gives the plain SBR result ("traditional SBR")        */
     int32_t subrays;       /* 6 (the paper's six sub-cones) or 7 (six plus the axis)  */
@@ -67,8 +68,19 @@ typedef struct {
     double freq_hz;        /* carrier frequency, > 0                                 */
     double tx_power_dbm;   /* transmit power                                          */
     uint32_t flags;        /* SBR_FLAG_*                                              */
-    int32_t reserved;      /* must be 0                                               */
+    int32_t launch;        /* SBR_LAUNCH_*: launch grid (0: the paper's equiangular)  */
 } sbr_trace_params;
+
+/* Launch grids.  EQUIANGULAR is the paper's method (Sec. II.B: equal angles
+ * along icosahedron edges and rings, eqs. (1)-(2)), 10 n^2 + 2 rays.  The
+ * equidistant divisions it is compared with (Sec. II.A, Fig. 2) space points
+ * equally on the flat faces of the icosahedron (10 n^2 + 2 rays) or the
+ * octahedron (4 n^2 + 2 rays) and project them onto the sphere.  The cone
+ * half-angle is theta_edge / (sqrt(3) n), eq. (4), with the polyhedron's edge
+ * angle theta_edge (atan 2 for the icosahedron, pi / 2 for the octahedron). */
+#define SBR_LAUNCH_EQUIANGULAR 0
+#define SBR_LAUNCH_EQUIDISTANT_ICOSA 1
+#define SBR_LAUNCH_EQUIDISTANT_OCTA 2
 
 #define SBR_FLAG_KEEP_INVALID 1u /* keep paths that fail path test 2 (flag INVALID) */
 #define SBR_FLAG_FRESH_GRID 2u   /* recompute the launch directions even when cached */
@@ -213,18 +225,21 @@ sbr_status sbr_candidates(sbr_scene* scene, const double tx[3], const double* rx
                           const sbr_trace_params* params, sbr_candidate* out, int64_t capacity,
                           int64_t* n_out);
 
-/* Launch directions of Sec. II.B for division n (10 n^2 + 2 unit vectors,
- * FP64), copied to out [count][3] for ray indices first..first+count-1. */
-sbr_status sbr_launch_grid(sbr_context* ctx, int32_t n, int64_t first, int64_t count,
-                           double* out);
+/* Launch directions of method `launch` (SBR_LAUNCH_*) for division n
+ * (unit vectors, FP64), copied to out [count][3] for ray indices
+ * first..first+count-1. */
+sbr_status sbr_launch_grid(sbr_context* ctx, int32_t launch, int32_t n, int64_t first,
+                           int64_t count, double* out);
 
-/* Per-ray trace of launch rays first..first+count-1 (Sec. III.A):
+/* Per-ray trace of launch rays first..first+count-1 of a launch grid
+ * (Sec. III.A):
  * out_tri [count][max_order+1] is the triangle (input index) closing each
  * segment, -1 when the segment leaves the scene or was not reached;
  * out_t [count][max_order+1] the segment's ray parameter (+inf: none).
  * Either output may be NULL. */
-sbr_status sbr_trace_rays(sbr_scene* scene, const double tx[3], int32_t n, int32_t max_order,
-                          int64_t first, int64_t count, int32_t* out_tri, double* out_t);
+sbr_status sbr_trace_rays(sbr_scene* scene, const double tx[3], int32_t launch, int32_t n,
+                          int32_t max_order, int64_t first, int64_t count, int32_t* out_tri,
+                          double* out_t);
 
 /* Differentiable path quantities at fixed interaction sequences (the
  * gradients of the paths sbr_trace returns with respect to transmitter and

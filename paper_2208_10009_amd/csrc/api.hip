@@ -127,14 +127,16 @@ thread_local std::string g_create_err;
 
 bool finite3(const double* p) { return isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]); }
 
-sbr_status get_grid(sbr_context* c, int32_t n, GridDev* g, bool* built, bool fresh = false)
+sbr_status get_grid(sbr_context* c, int32_t launch, int32_t n, GridDev* g, bool* built,
+                    bool fresh = false)
 {
-    int64_t N = 10 * (int64_t)n * n + 2;
-    auto it = c->grids.find(n);
+    const int64_t N = num_rays(launch, n);
+    const int32_t key = launch * 100000 + n;
+    auto it = c->grids.find(key);
     *built = false;
     if (it != c->grids.end() && fresh) {
         HIPCHK(c, ensure(c->grid_scratch, grid_scratch_bytes(n)));
-        GridDev gd{it->second.as<double>(), N, n};
+        GridDev gd{it->second.as<double>(), N, n, launch};
         HIPCHK(c, launch_grid(gd, c->stream, c->grid_scratch.p));
         *built = true;
     }
@@ -142,16 +144,16 @@ sbr_status get_grid(sbr_context* c, int32_t n, GridDev* g, bool* built, bool fre
         DevBuf b;
         HIPCHK(c, ensure(b, sizeof(double) * 3 * (size_t)N));
         HIPCHK(c, ensure(c->grid_scratch, grid_scratch_bytes(n)));
-        GridDev gd{b.as<double>(), N, n};
+        GridDev gd{b.as<double>(), N, n, launch};
         hipError_t e = launch_grid(gd, c->stream, c->grid_scratch.p);
         if (e != hipSuccess) {
             release(b);
             return fail(c, SBR_E_DEVICE, "launch grid: %s", hipGetErrorString(e));
         }
-        it = c->grids.emplace(n, b).first;
+        it = c->grids.emplace(key, b).first;
         *built = true;
     }
-    *g = GridDev{it->second.as<double>(), N, n};
+    *g = GridDev{it->second.as<double>(), N, n, launch};
     return SBR_OK;
 }
 
@@ -203,8 +205,13 @@ LdsPlan plan_for(const sbr_scene* s, int block)
     return make_lds_plan(s->n_nodes, s->T, block, c->stack_depth, c->lds_budget);
 }
 
-// theta_launch = theta_0 / (sqrt(3) n), eq. (4).
-double theta_launch(int32_t n) { return kTheta0 / (sqrt(3.0) * (double)n); }
+// theta_launch = theta_0 / (sqrt(3) n), eq. (4); the equidistant grids use
+// their polyhedron's edge angle (pi / 2 for the octahedron).
+double theta_launch(int32_t launch, int32_t n)
+{
+    const double th = launch == SBR_LAUNCH_EQUIDISTANT_OCTA ? kPi / 2.0 : kTheta0;
+    return th / (sqrt(3.0) * (double)n);
+}
 
 sbr_status check_params(sbr_context* c, const sbr_trace_params* p)
 {
@@ -221,8 +228,10 @@ sbr_status check_params(sbr_context* c, const sbr_trace_params* p)
         return fail(c, SBR_E_INVALID_ARG, "freq_hz must be finite and > 0");
     if (!isfinite(p->tx_power_dbm) || !isfinite(p->target_err_deg) || p->target_err_deg >= 45.0)
         return fail(c, SBR_E_INVALID_ARG, "tx_power_dbm / target_err_deg out of range");
-    if (p->reserved != 0 || (p->flags & ~(SBR_FLAG_KEEP_INVALID | SBR_FLAG_FRESH_GRID)))
-        return fail(c, SBR_E_INVALID_ARG, "unknown flags or reserved != 0");
+    if (p->flags & ~(SBR_FLAG_KEEP_INVALID | SBR_FLAG_FRESH_GRID))
+        return fail(c, SBR_E_INVALID_ARG, "unknown flags");
+    if (p->launch < SBR_LAUNCH_EQUIANGULAR || p->launch > SBR_LAUNCH_EQUIDISTANT_OCTA)
+        return fail(c, SBR_E_INVALID_ARG, "unknown launch method %d", p->launch);
     return SBR_OK;
 }
 
@@ -307,13 +316,14 @@ sbr_status add_job(sbr_context* c, Call& call, int32_t scene_idx, const double* 
 {
     GridDev g;
     bool built = false;
-    sbr_status r = get_grid(c, p->division_n, &g, &built, (p->flags & SBR_FLAG_FRESH_GRID) != 0);
+    sbr_status r = get_grid(c, p->launch, p->division_n, &g, &built,
+                            (p->flags & SBR_FLAG_FRESH_GRID) != 0);
     if (r) return r;
     call.grids_built = call.grids_built || built;
     const sbr_scene* s = call.scenes[scene_idx];
     JobDev J{};
     for (int i = 0; i < 3; ++i) J.tx[i] = tx[i];
-    J.thl = theta_launch(p->division_n);
+    J.thl = theta_launch(p->launch, p->division_n);
     J.tan_tgt = p->target_err_deg > 0.0 ? tan_cr((p->target_err_deg * kPi) / 180.0) : 0.0;
     J.freq_hz = p->freq_hz;
     J.tx_power_dbm = p->tx_power_dbm;
@@ -604,7 +614,7 @@ sbr_status single_call(sbr_scene* s, Call& call, const double* tx, const double*
     call.rx_job.assign((size_t)n_rx, 0);
     call.chunk = c->trace_chunk;
     HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
-    int64_t N = 10 * (int64_t)p->division_n * p->division_n + 2;
+    int64_t N = num_rays(p->launch, p->division_n);
     return add_job(c, call, 0, tx, 0, n_rx, p, ray_begin, ray_count < 0 ? N : ray_count);
 }
 
@@ -929,18 +939,21 @@ sbr_status sbr_scene_destroy(sbr_scene* s)
     return SBR_OK;
 }
 
-sbr_status sbr_launch_grid(sbr_context* c, int32_t n, int64_t first, int64_t count, double* out)
+sbr_status sbr_launch_grid(sbr_context* c, int32_t launch, int32_t n, int64_t first,
+                           int64_t count, double* out)
 {
     if (!c) return SBR_E_INVALID_ARG;
     c->err.clear();
     if (n < 1 || n > 10000) return fail(c, SBR_E_INVALID_ARG, "n outside 1..10000");
-    int64_t N = 10 * (int64_t)n * n + 2;
+    if (launch < SBR_LAUNCH_EQUIANGULAR || launch > SBR_LAUNCH_EQUIDISTANT_OCTA)
+        return fail(c, SBR_E_INVALID_ARG, "unknown launch method %d", launch);
+    int64_t N = num_rays(launch, n);
     if (first < 0 || count < 0 || first + count > N || (count > 0 && !out))
         return fail(c, SBR_E_INVALID_ARG, "ray range outside 0..%lld", (long long)N);
     HIPCHK(c, hipSetDevice(c->device));
     GridDev g;
     bool built;
-    sbr_status r = get_grid(c, n, &g, &built);
+    sbr_status r = get_grid(c, launch, n, &g, &built);
     if (r) return r;
     if (count == 0) return SBR_OK;
     std::vector<double> tmp((size_t)count * 3);
@@ -953,17 +966,18 @@ sbr_status sbr_launch_grid(sbr_context* c, int32_t n, int64_t first, int64_t cou
     return SBR_OK;
 }
 
-sbr_status sbr_trace_rays(sbr_scene* s, const double tx[3], int32_t n, int32_t K, int64_t first,
-                          int64_t count, int32_t* out_tri, double* out_t)
+sbr_status sbr_trace_rays(sbr_scene* s, const double tx[3], int32_t launch, int32_t n, int32_t K,
+                          int64_t first, int64_t count, int32_t* out_tri, double* out_t)
 {
     sbr_status r = check_scene(s);
     if (r) return r;
     sbr_context* c = s->ctx;
     c->err.clear();
     if (!tx || !finite3(tx)) return fail(c, SBR_E_INVALID_ARG, "tx missing or not finite");
-    if (n < 1 || n > 10000 || K < 0 || K > SBR_MAX_ORDER)
-        return fail(c, SBR_E_INVALID_ARG, "n or max_order out of range");
-    int64_t N = 10 * (int64_t)n * n + 2;
+    if (n < 1 || n > 10000 || K < 0 || K > SBR_MAX_ORDER || launch < SBR_LAUNCH_EQUIANGULAR ||
+        launch > SBR_LAUNCH_EQUIDISTANT_OCTA)
+        return fail(c, SBR_E_INVALID_ARG, "n, launch or max_order out of range");
+    int64_t N = num_rays(launch, n);
     if (first < 0 || count < 0 || first + count > N)
         return fail(c, SBR_E_INVALID_ARG, "ray range outside 0..%lld", (long long)N);
     HIPCHK(c, hipSetDevice(c->device));
@@ -971,6 +985,7 @@ sbr_status sbr_trace_rays(sbr_scene* s, const double tx[3], int32_t n, int32_t K
     sbr_trace_params p{};
     p.max_order = K;
     p.division_n = n;
+    p.launch = launch;
     p.iterations = 0;
     p.subrays = 6;
     p.freq_hz = 1.0;
@@ -1117,7 +1132,7 @@ sbr_status sbr_trace_batch(sbr_context* c, sbr_scene* const* scenes, int32_t n_s
     HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
     for (int32_t j = 0; j < n_jobs; ++j) {
         const sbr_job& J = jobs[j];
-        int64_t N = 10 * (int64_t)J.params.division_n * J.params.division_n + 2;
+        int64_t N = num_rays(J.params.launch, J.params.division_n);
         sbr_status r = add_job(c, call, J.scene, J.tx, J.rx_first, J.n_rx, &J.params, 0, N);
         if (r) return r;
     }

@@ -67,12 +67,20 @@ struct LdsPlan {
 // in `budget` bytes: everything when the scene fits, else a node prefix.
 LdsPlan make_lds_plan(int64_t n_nodes, int64_t n_tris, int block, int depth, int budget);
 
-// Launch-grid tables for one division n (device, FP64 SoA).
+// Launch-grid tables for one launch method and division n (device, FP64 SoA).
 struct GridDev {
     double* dir;       // [3][N]: x, y, z
     int64_t N;
     int32_t n;
+    int32_t launch;    // SBR_LAUNCH_*
 };
+
+// Rays of a launch method at division n: 10 n^2 + 2 on the icosahedron,
+// 4 n^2 + 2 on the octahedron.
+inline int64_t num_rays(int32_t launch, int32_t n)
+{
+    return (launch == SBR_LAUNCH_EQUIDISTANT_OCTA ? 4 : 10) * (int64_t)n * n + 2;
+}
 
 // Ball-tree node over receivers (48 B), in depth-first preorder: the ball
 // (centre c, radius rho) holds every receiver below.  count > 0: a leaf of

@@ -1,7 +1,9 @@
 // launch.hip -- equiangular icosahedral launch directions (Sec. II.B) for
 // gfx950: ring corners of the 20 faces layer by layer, then one thread per
 // ray.  Every value is bit-identical to the correctly rounded FP64 grid (see
-// geom.h for the double-double trigonometry).
+// geom.h for the double-double trigonometry).  The equidistant icosahedral
+// and octahedral grids of Sec. II.A, which the paper compares against, are
+// launch methods too.
 #include <math.h>
 
 #include "geom.h"
@@ -21,6 +23,7 @@ struct GridHdr {
     d3 V[12];
     int32_t e[30][2];
     int32_t f[20][3];
+    int32_t nv, ne, nf;
 };
 
 __host__ __device__ static inline int64_t ring_cap(int32_t n) { return n / 3 + 2; }
@@ -37,6 +40,9 @@ __device__ static void ico_build(GridHdr* H)
                                {1, phi, 0},  {-1, phi, 0},  {1, -phi, 0},  {-1, -phi, 0},
                                {phi, 0, 1},  {phi, 0, -1},  {-phi, 0, 1},  {-phi, 0, -1}};
     for (int i = 0; i < 12; ++i) H->V[i] = normalize(ld3(raw[i]));
+    H->nv = 12;
+    H->ne = 30;
+    H->nf = 20;
     int ne = 0, nf = 0;
     for (int i = 0; i < 12; ++i)
         for (int j = i + 1; j < 12; ++j)
@@ -195,8 +201,109 @@ __global__ void k_grid_dirs(int32_t n, int64_t N, const char* __restrict__ scrat
     dir[2 * N + i] = r.z;
 }
 
+// ===========================================================================
+// Equidistant division (Sec. II.A), the comparison grids: points at equal
+// spacing on the flat faces of a regular polyhedron, projected onto the
+// sphere.
+// ===========================================================================
+// Octahedron: vertices +x, -x, +y, -y, +z, -z in this order; edges are the
+// 12 non-antipodal pairs i < j, lexicographically; faces are the 8 mutually
+// adjacent triples i < j < k, lexicographically, wound counter-clockwise
+// seen from outside (the same rules as the icosahedron's).
+__device__ static void octa_build(GridHdr* H)
+{
+    const double raw[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+    for (int i = 0; i < 6; ++i) H->V[i] = ld3(raw[i]);
+    H->nv = 6;
+    int ne = 0, nf = 0;
+    for (int i = 0; i < 6; ++i)
+        for (int j = i + 1; j < 6; ++j)
+            if (dot(H->V[i], H->V[j]) > -0.5) {
+                H->e[ne][0] = i;
+                H->e[ne][1] = j;
+                ++ne;
+            }
+    for (int i = 0; i < 6; ++i)
+        for (int j = i + 1; j < 6; ++j)
+            for (int k = j + 1; k < 6; ++k) {
+                bool a = dot(H->V[i], H->V[j]) > -0.5, b = dot(H->V[j], H->V[k]) > -0.5,
+                     c = dot(H->V[i], H->V[k]) > -0.5;
+                if (a && b && c) {
+                    double sg = dot(H->V[i], cross(H->V[j], H->V[k]));
+                    H->f[nf][0] = i;
+                    H->f[nf][1] = sg > 0.0 ? j : k;
+                    H->f[nf][2] = sg > 0.0 ? k : j;
+                    ++nf;
+                }
+            }
+    H->ne = ne;
+    H->nf = nf;
+}
+
+__global__ void k_poly_setup(int32_t launch, char* scratch)
+{
+    if (threadIdx.x != 0) return;
+    GridHdr* H = (GridHdr*)scratch;
+    GridHdr h;
+    if (launch == SBR_LAUNCH_EQUIDISTANT_OCTA)
+        octa_build(&h);
+    else
+        ico_build(&h);
+    *H = h;
+}
+
+// Ray order: the vertex rays; edge interiors edge by edge, k = 1..n-1 from
+// the lower vertex, at (n-k) V_i + k V_j; face interiors face by face, rows
+// i = 1..n-2 and j = 1..n-1-i, at (n-i-j) A + i B + j C for the face's
+// corners A, B, C in winding order; each normalized.
+__global__ void k_grid_equidistant(int32_t n, int64_t N, const char* __restrict__ scratch,
+                                   double* __restrict__ dir)
+{
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= N) return;
+    const GridHdr* H = (const GridHdr*)scratch;
+    const int64_t i0 = idx;
+    d3 r;
+    if (idx < H->nv) {
+        r = H->V[idx];
+    } else {
+        idx -= H->nv;
+        if (idx < (int64_t)H->ne * (n - 1)) {
+            int64_t e = idx / (n - 1), k = idx % (n - 1) + 1;
+            r = normalize(add(scl((double)(n - k), H->V[H->e[e][0]]),
+                              scl((double)k, H->V[H->e[e][1]])));
+        } else {
+            idx -= (int64_t)H->ne * (n - 1);
+            const int64_t per_face = (int64_t)(n - 1) * (n - 2) / 2;
+            const int64_t f = idx / per_face, q = idx % per_face;
+            // row i holds n-1-i points; rows before i hold (i-1)(2n-2-i)/2.
+            // Estimate i from the quadratic, then settle it exactly.
+            const double nn = (double)(2 * n - 3);
+            int64_t i = (int64_t)((nn - sqrt(nn * nn - 8.0 * (double)q)) * 0.5) + 1;
+            if (i < 1) i = 1;
+            if (i > n - 2) i = n - 2;
+            while (i > 1 && (i - 1) * (2 * (int64_t)n - 2 - i) / 2 > q) --i;
+            while (i < n - 2 && i * (2 * (int64_t)n - 3 - i) / 2 <= q) ++i;
+            const int64_t j = q - (i - 1) * (2 * (int64_t)n - 2 - i) / 2 + 1;
+            const int64_t a = n - i - j;
+            const d3 A = H->V[H->f[f][0]], B = H->V[H->f[f][1]], C = H->V[H->f[f][2]];
+            r = normalize(add(add(scl((double)a, A), scl((double)i, B)), scl((double)j, C)));
+        }
+    }
+    dir[i0] = r.x;
+    dir[N + i0] = r.y;
+    dir[2 * N + i0] = r.z;
+}
+
 hipError_t launch_grid(GridDev g, hipStream_t s, void* scratch)
 {
+    if (g.launch != SBR_LAUNCH_EQUIANGULAR) {
+        hipLaunchKernelGGL(k_poly_setup, dim3(1), dim3(64), 0, s, g.launch, (char*)scratch);
+        int64_t blocks = (g.N + 255) / 256;
+        hipLaunchKernelGGL(k_grid_equidistant, dim3((unsigned)blocks), dim3(256), 0, s, g.n, g.N,
+                           (const char*)scratch, g.dir);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(128), 0, s, g.n, (char*)scratch);
     int64_t blocks = (g.N + 255) / 256;
     hipLaunchKernelGGL(k_grid_dirs, dim3((unsigned)blocks), dim3(256), 0, s, g.n, g.N,

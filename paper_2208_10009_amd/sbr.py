@@ -54,7 +54,7 @@ class TraceParams(C.Structure):
         ("freq_hz", C.c_double),
         ("tx_power_dbm", C.c_double),
         ("flags", C.c_uint32),
-        ("reserved", C.c_int32),
+        ("launch", C.c_int32),
     ]
 
 
@@ -158,8 +158,9 @@ def lib(load_torch: bool = True):
                             C.POINTER(TraceStats)]
     L.sbr_candidates.argtypes = [vp, dp, dp, C.c_int32, C.POINTER(TraceParams), vp, C.c_int64,
                                  lp]
-    L.sbr_launch_grid.argtypes = [vp, C.c_int32, C.c_int64, C.c_int64, dp]
-    L.sbr_trace_rays.argtypes = [vp, dp, C.c_int32, C.c_int32, C.c_int64, C.c_int64, ip, dp]
+    L.sbr_launch_grid.argtypes = [vp, C.c_int32, C.c_int32, C.c_int64, C.c_int64, dp]
+    L.sbr_trace_rays.argtypes = [vp, dp, C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_int64,
+                                 ip, dp]
     L.sbr_trace_counters.argtypes = [vp, dp, dp, C.c_int32, C.POINTER(TraceParams), lp]
     L.sbr_context_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
     L.sbr_context_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
@@ -181,11 +182,20 @@ def _i(a):
     return a.ctypes.data_as(C.POINTER(C.c_int32))
 
 
+EQUIANGULAR, EQUIDISTANT_ICOSA, EQUIDISTANT_OCTA = 0, 1, 2
+
+
+def num_rays(n: int, launch: int = EQUIANGULAR) -> int:
+    """Launch rays of division n: 10 n^2 + 2 (icosahedron), 4 n^2 + 2 (octahedron)."""
+    return (4 if launch == EQUIDISTANT_OCTA else 10) * n * n + 2
+
+
 def make_params(max_order=3, division_n=20, iterations=3, subrays=6, target_err_deg=0.0,
-                freq_hz=28e9, tx_power_dbm=0.0, keep_invalid=False, fresh_grid=False):
+                freq_hz=28e9, tx_power_dbm=0.0, keep_invalid=False, fresh_grid=False,
+                launch=EQUIANGULAR):
     flags = (FLAG_KEEP_INVALID if keep_invalid else 0) | (FLAG_FRESH_GRID if fresh_grid else 0)
     return TraceParams(max_order, division_n, iterations, subrays, target_err_deg, freq_hz,
-                       tx_power_dbm, flags, 0)
+                       tx_power_dbm, flags, launch)
 
 
 class Context:
@@ -212,12 +222,13 @@ class Context:
         if st != OK:
             raise SbrError(st, lib().sbr_last_error(self.h).decode())
 
-    def launch_grid(self, n: int, first: int = 0, count: int | None = None) -> np.ndarray:
-        N = 10 * n * n + 2
+    def launch_grid(self, n: int, first: int = 0, count: int | None = None,
+                    launch: int = EQUIANGULAR) -> np.ndarray:
+        N = num_rays(n, launch)
         if count is None:
             count = N - first
         out = np.empty((count, 3), np.float64)
-        self._check(lib().sbr_launch_grid(self.h, n, first, count, _d(out)))
+        self._check(lib().sbr_launch_grid(self.h, launch, n, first, count, _d(out)))
         return out
 
     def tuning(self) -> dict:
@@ -331,15 +342,16 @@ class Scene:
             self.ctx._check(st)
             return out[: n.value].copy()
 
-    def trace_rays(self, tx, n: int, max_order: int, first: int = 0, count: int | None = None):
+    def trace_rays(self, tx, n: int, max_order: int, first: int = 0, count: int | None = None,
+                   launch: int = EQUIANGULAR):
         """sbr_trace_rays: (tri [count, K+1] input indices, t [count, K+1])."""
-        N = 10 * n * n + 2
+        N = num_rays(n, launch)
         if count is None:
             count = N - first
         txa = np.ascontiguousarray(tx, np.float64).reshape(3)
         ot = np.empty((count, max_order + 1), np.int32)
         oT = np.empty((count, max_order + 1), np.float64)
-        self.ctx._check(lib().sbr_trace_rays(self.h, _d(txa), n, max_order, first, count,
+        self.ctx._check(lib().sbr_trace_rays(self.h, _d(txa), launch, n, max_order, first, count,
                                              _i(ot), _d(oT)))
         return ot, oT
 
