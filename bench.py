@@ -246,6 +246,39 @@ def large_city_leg(ctx, scenes, torch, steps=5):
     }
 
 
+def launch_variants(ctx, scenes, torch, steps=3):
+    """Sec. II / Sec. IV comparison on the Manhattan workload at about 400k
+    rays per grid: the paper's equiangular icosahedral grid and the
+    equidistant icosahedral and octahedral grids it is compared with, each
+    traced as traditional SBR (no iterations) and with the precise algorithm
+    to 0.01 deg: time, paths, and AOD/AOA error against the exact solve."""
+    cfg = scenes.manhattan_config(0)
+    sc = ctx.scene(cfg["scene"])
+    out = []
+    for name, launch, n in (("equiangular_icosa", 0, 200), ("equidistant_icosa", 1, 200),
+                            ("equidistant_octa", 2, 316)):
+        for mode, kw in (("traditional", dict(iterations=0)),
+                         ("precise_0.01deg", dict(iterations=30, target_err_deg=0.01))):
+            prm = dict(cfg["params"], division_n=n, launch=launch, **kw)
+            sc.trace(cfg["tx"], cfg["rx"], **prm)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                p, _ = sc.trace(cfg["tx"], cfg["rx"], **prm)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / steps
+            ea = angle_deg(p["aod"], p["exact_aod"]) if len(p) else np.zeros(0)
+            eo = angle_deg(p["aoa"], p["exact_aoa"]) if len(p) else np.zeros(0)
+            out.append({"grid": name, "n": n, "rays": 10 * n * n + 2 if launch < 2 else 4 * n * n + 2,
+                        "mode": mode, "ms": round(ms, 4), "paths": int(len(p)),
+                        "aod_err_deg_mean": float(ea.mean()) if len(p) else None,
+                        "aod_err_deg_max": float(ea.max()) if len(p) else None,
+                        "aoa_err_deg_mean": float(eo.mean()) if len(p) else None,
+                        "within_0.01deg": int(accurate_mask(p).sum())})
+    sc.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -257,6 +290,8 @@ def main():
                     help="skip the batched-vs-plain comparison on the 256-pair workload")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the large-city (500k triangles, 10M rays, 1024 Rx) leg")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the launch-grid / traditional-vs-precise comparison")
     ap.add_argument("--large-only", action="store_true",
                     help="run only the large-city leg and print its JSON object (profiling)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -393,6 +428,8 @@ def main():
     if not args.no_large:
         out["large_city"] = large_city_leg(ctx, scenes, torch)
         log("large city", json.dumps(out["large_city"]))
+    if not args.no_variants:
+        out["launch_variants"] = launch_variants(ctx, scenes, torch)
     if not args.no_batch:
         out["batched"] = batch_vs_plain(ctx, scenes, torch)
     ctx.close()

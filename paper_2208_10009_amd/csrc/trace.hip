@@ -15,6 +15,8 @@ namespace sbr {
 
 // Per-lane state of the ray a lane is tracing: its current segment starts at
 // o with direction d after j reflections on faces[0..j), unfolded length D.
+// The faces are only ever indexed by unrolled constant indices, so the whole
+// state stays in registers.
 struct RayState {
     d3 o, d;
     double D;
@@ -27,12 +29,19 @@ __device__ static inline void start_ray(const JobDev& J, int64_t r, RayState& R)
 {
     R.r = r;
     R.o = mk(J.tx[0], J.tx[1], J.tx[2]);
-    R.d = mk(J.dir[r], J.dir[J.N + r], J.dir[2 * J.N + r]);
+    R.d = mk(gld(J.dir + r), gld(J.dir + J.N + r), gld(J.dir + 2 * J.N + r));
     R.D = 0.0;
     R.prev = -1;
     R.j = 0;
 #pragma unroll
     for (int q = 0; q < SBR_MAX_ORDER; ++q) R.faces[q] = -1;
+}
+
+// faces[j] = f without a dynamic index.
+__device__ static inline void set_face(RayState& R, int32_t j, int32_t f)
+{
+#pragma unroll
+    for (int q = 0; q < SBR_MAX_ORDER; ++q) R.faces[q] = q == j ? f : R.faces[q];
 }
 
 // Append the reception event of receiver gx on the lane's current segment
@@ -44,7 +53,7 @@ __device__ static inline void receive(const JobDev& J, const double* __restrict_
                                       bool count)
 {
     double tn;
-    d3 rx = mk(rx_all[3 * gx], rx_all[3 * gx + 1], rx_all[3 * gx + 2]);
+    d3 rx = mk(gld(rx_all + 3 * gx), gld(rx_all + 3 * gx + 1), gld(rx_all + 3 * gx + 2));
     if (!capture(R.o, R.d, R.D, t, rx, J.thl, &tn)) return;
     if (count) *events += 1;
     unsigned long long pos = atomicAdd(ccount, 1ull);
@@ -135,7 +144,17 @@ __global__ __launch_bounds__(256) void k_trace(CallDev call, LdsPlan L, SceneDev
             int32_t nd = J.rx_root;
             const int32_t end = call.rx_nodes[nd].skip;
             while (nd != end) {
-                const RxNode N = call.rx_nodes[nd];
+                const double2* q = (const double2*)(call.rx_nodes + nd);
+                const double2 c01 = gld(q), c2r = gld(q + 1), m = gld(q + 2);
+                RxNode N;
+                N.c[0] = c01.x;
+                N.c[1] = c01.y;
+                N.c[2] = c2r.x;
+                N.rho = c2r.y;
+                const long long w0 = __double_as_longlong(m.x), w1 = __double_as_longlong(m.y);
+                N.first = (int32_t)(w0 & 0xffffffffll);
+                N.count = (int32_t)(w0 >> 32);
+                N.skip = (int32_t)(w1 & 0xffffffffll);
                 if (!rx_ball_may_capture(R.o, R.d, R.D, t, mk(N.c[0], N.c[1], N.c[2]), N.rho,
                                          J.thl)) {
                     nd = N.skip;
@@ -143,8 +162,8 @@ __global__ __launch_bounds__(256) void k_trace(CallDev call, LdsPlan L, SceneDev
                     nd = nd + 1;
                 } else {
                     for (int q = 0; q < N.count; ++q)
-                        receive(J, call.rx, R, t, call.rx_perm[N.first + q], cand, cap, ccount,
-                                &events, COUNT);
+                        receive(J, call.rx, R, t, gld(call.rx_perm + N.first + q), cand, cap,
+                                ccount, &events, COUNT);
                     nd = N.skip;
                 }
             }
@@ -168,7 +187,7 @@ __global__ __launch_bounds__(256) void k_trace(CallDev call, LdsPlan L, SceneDev
         R.D = R.D + t;
         R.o = on;
         R.prev = f;
-        R.faces[R.j] = f;
+        set_face(R, R.j, f);
         R.j += 1;
     }
     if (COUNT) {

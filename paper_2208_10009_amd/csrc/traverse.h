@@ -63,17 +63,44 @@ __device__ static inline bool mt_hit(const TriD& T, d3 o, d3 d, double t_lo, dou
     return false;
 }
 
-__device__ static inline TriD unpack_tri(float4 fa, float4 fb, float4 fc, float4 fd, float4 fe)
+// Loads through the global address space: the scene arrays are global
+// memory, and telling the compiler so turns generic (flat) loads, which also
+// count against the LDS wait counter, into global loads.
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float4 gld(const float4* p)
 {
-    double2 a = __builtin_bit_cast(double2, fa), b = __builtin_bit_cast(double2, fb),
-            c = __builtin_bit_cast(double2, fc), d = __builtin_bit_cast(double2, fd),
-            e = __builtin_bit_cast(double2, fe);
+    const f4v v = *(const __attribute__((address_space(1))) f4v*)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ double2 gld(const double2* p)
+{
+    const d2v v = *(const __attribute__((address_space(1))) d2v*)p;
+    return make_double2(v.x, v.y);
+}
+
+__device__ __forceinline__ double gld(const double* p)
+{
+    return *(const __attribute__((address_space(1))) double*)p;
+}
+
+__device__ __forceinline__ int32_t gld(const int32_t* p)
+{
+    return *(const __attribute__((address_space(1))) int32_t*)p;
+}
+
+// A triangle record from five 16-byte pieces (v0, e1, e2 as doubles; the
+// last 8 bytes hold the face id and the input index).
+__device__ static inline TriD make_tri(double2 a, double2 b, double2 c, double2 d, double2 e)
+{
     TriD T;
     T.v0x = a.x; T.v0y = a.y; T.v0z = b.x; T.e1x = b.y; T.e1y = c.x;
     T.e1z = c.y; T.e2x = d.x; T.e2y = d.y; T.e2z = e.x;
-    int2 fi = __builtin_bit_cast(int2, e.y);
-    T.face = fi.x;
-    T.orig = fi.y;
+    const long long w = __double_as_longlong(e.y);
+    T.face = (int32_t)(w & 0xffffffffll);
+    T.orig = (int32_t)(w >> 32);
     return T;
 }
 
@@ -82,11 +109,11 @@ template <bool LDS>
 __device__ static inline TriD tri_at(const SceneDev& S, const LdsPlan& L, int32_t i)
 {
     if (LDS && i < L.n_tris) {
-        const float4* q = g_smem4 + 4 * L.n_nodes + 5 * i;
-        return unpack_tri(q[0], q[1], q[2], q[3], q[4]);
+        const double2* q = (const double2*)(g_smem4 + 4 * L.n_nodes + 5 * i);
+        return make_tri(q[0], q[1], q[2], q[3], q[4]);
     }
-    const float4* q = (const float4*)(S.tris + i);
-    return unpack_tri(q[0], q[1], q[2], q[3], q[4]);
+    const double2* q = (const double2*)(S.tris + i);
+    return make_tri(gld(q), gld(q + 1), gld(q + 2), gld(q + 3), gld(q + 4));
 }
 
 struct HitRec {
@@ -98,11 +125,13 @@ struct Tally {
     uint32_t nodes, tris;
 };
 
+constexpr int kShortStack = 16;  // LDS stack entries per lane without an LDS plan
+
 // Closest hit (ANY = false: smallest t; equal t -> lower face id -> lower
 // input index) or any hit (ANY = true) of the ray o + t d, t_lo < t < t_hi,
 // ignoring triangles of faces xa and xb.  Returns the leaf-order position of
-// the hit or -1.  LDS = false reads everything from global memory and keeps
-// the stack in private memory (no LDS plan needed).
+// the hit or -1.  LDS = false reads everything from global memory (no LDS
+// plan needed) and keeps the top of the stack in a static LDS array.
 template <bool ANY, bool COUNT, bool LDS>
 __device__ static int32_t traverse(const SceneDev& S, const LdsPlan& L, d3 o, d3 d, int32_t xa,
                                    int32_t xb, double t_lo, double t_hi, float delta, HitRec* h,
@@ -125,9 +154,21 @@ __device__ static int32_t traverse(const SceneDev& S, const LdsPlan& L, d3 o, d3
     h->orig = 0x7fffffff;
     float tb = isinf(t_hi) ? INFINITY : (float)t_hi * slack;
 
-    int32_t* lst = LDS ? (int32_t*)(g_smem4) + (L.stack_off >> 2) + threadIdx.x : nullptr;
-    const int bd = blockDim.x;
-    const int ldepth = LDS ? L.depth : 0;
+    // The first stack entries live in LDS: the plan's stack (LDS instances)
+    // or a fixed short stack of kShortStack entries per lane (workgroups of
+    // at most 256 lanes); deeper entries go to the private array.
+    int32_t* lst;
+    int bd, ldepth;
+    if constexpr (LDS) {
+        lst = (int32_t*)(g_smem4) + (L.stack_off >> 2) + threadIdx.x;
+        bd = blockDim.x;
+        ldepth = L.depth;
+    } else {
+        __shared__ int32_t s_stack[kShortStack * 256];
+        lst = s_stack + threadIdx.x;
+        bd = 256;
+        ldepth = kShortStack;
+    }
     int32_t ost[kTraceStack];
     int sp = 0;
     int32_t node = 0;
@@ -138,7 +179,7 @@ __device__ static int32_t traverse(const SceneDev& S, const LdsPlan& L, d3 o, d3
             a = np[0]; b = np[1]; c = np[2]; mf = np[3];
         } else {
             const float4* np = (const float4*)(S.nodes + node);
-            a = np[0]; b = np[1]; c = np[2]; mf = np[3];
+            a = gld(np); b = gld(np + 1); c = gld(np + 2); mf = gld(np + 3);
         }
         const int4 m = __builtin_bit_cast(int4, mf);
         if (COUNT) tally->nodes += 1;
@@ -196,7 +237,7 @@ __device__ static int32_t traverse(const SceneDev& S, const LdsPlan& L, d3 o, d3
                 atomicOr(err, 1);
                 return h->pos;
             }
-            if (LDS && sp < ldepth) lst[sp * bd] = farc;
+            if (sp < ldepth) lst[sp * bd] = farc;
             else ost[sp - ldepth] = farc;
             ++sp;
             node = nearc;
@@ -207,7 +248,7 @@ __device__ static int32_t traverse(const SceneDev& S, const LdsPlan& L, d3 o, d3
         } else {
             if (sp == 0) break;
             --sp;
-            node = (LDS && sp < ldepth) ? lst[sp * bd] : ost[sp - ldepth];
+            node = sp < ldepth ? lst[sp * bd] : ost[sp - ldepth];
         }
     }
     return h->pos;
