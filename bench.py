@@ -1,11 +1,13 @@
 """Benchmark of the SBR hot path on one MI355X.
 
-One step = one sbr_trace call over the whole path: equiangular launch
-(recomputed every step), BVH traversal with specular bounces and cone
+One step = one sbr_trace_device call over the whole path: equiangular
+launch (recomputed every step), BVH traversal with specular bounces and cone
 reception, path test 1, the precise algorithm, image solve / path test 2 /
 power, and the canonical emit.  The scene (BVH) is uploaded once before the
-timed region; Tx/Rx positions (64 x 24 B) and the path list travel with
-every call.
+timed region and the receivers are a device tensor, so the inputs are
+resident in HBM; the paths are written to a device buffer.  The rate of the
+host-array entry point (sbr_trace, receivers and paths over PCIe each call)
+is reported beside it.
 
 Workload: the Manhattan grid (8 x 8 box buildings on a 40 m pitch plus
 ground, 770 triangles), Tx at 25 m, 64 Rx at 1.5 m on street centrelines,
@@ -197,23 +199,28 @@ def large_city_leg(ctx, scenes, torch, steps=5):
     counts = sc.trace_counters(cfg["tx"], cfg["rx"], **prm)
     from paper_2208_10009_amd import autotune
     entry_tuning = ctx.tuning()
+    rx_tune = torch.as_tensor(cfg["rx"], device="cuda")
     best, _ = autotune.autotune(
-        ctx, lambda: sc.trace(cfg["tx"], cfg["rx"], **prm),
+        ctx, lambda: sc.trace_device(cfg["tx"], rx_tune, **prm),
         space={"trace_chunk": [1, 2], "persist_blocks": [1024, 2048, 4096],
                "rx_tree_min": [16, 1 << 30], "lds_budget": [0, 24 * 4 * 256],
                "stack_depth": [24]}, warmup=1, steps=2)
     log("large city tuning", best)
 
+    from paper_2208_10009_amd import sbr
+    rx_dev = torch.as_tensor(cfg["rx"], device="cuda")
+
     def run(kw):
-        sc.trace(cfg["tx"], cfg["rx"], **kw)
+        sc.trace_device(cfg["tx"], rx_dev, **kw)
         torch.cuda.synchronize()
         stats = []
         t0 = time.perf_counter()
         for _ in range(steps):
-            paths, st = sc.trace(cfg["tx"], cfg["rx"], **kw)
+            got, st = sc.trace_device(cfg["tx"], rx_dev, **kw)
             stats.append(st)
         torch.cuda.synchronize()
         ms = 1e3 * (time.perf_counter() - t0) / steps
+        paths = got.cpu().numpy().reshape(-1).view(sbr.PATH_DTYPE)
         stage = {k: round(float(np.mean([x[k] for x in stats])), 4)
                  for k in ("ms_launch", "ms_trace", "ms_dedup", "ms_refine", "ms_solve",
                            "ms_emit", "ms_total")}
@@ -330,24 +337,40 @@ def main():
     counts = sc.trace_counters(cfg["tx"], cfg["rx"], **prm)
     log("counts", counts)
     from paper_2208_10009_amd import autotune
+    rx_tune = torch.as_tensor(cfg["rx"], device="cuda")
     best, _ = autotune.autotune(
-        ctx, lambda: sc.trace(cfg["tx"], cfg["rx"], **prm),
+        ctx, lambda: sc.trace_device(cfg["tx"], rx_tune, **prm),
         space={"trace_chunk": [1, 2], "persist_blocks": [1024, 2048, 4096],
                "lds_budget": [0, 24 * 4 * 256], "stack_depth": [24],
                "lookahead_max_paths": [4096], "rx_tree_min": [16, 1 << 30]}, warmup=1, steps=5)
     log("tuning", best)
 
-    def timed(steps, warmup, **kw):
+    # Inputs resident in HBM: the receivers are a device tensor and the paths
+    # are written to a device buffer (sbr_trace_device); the transmitter and
+    # the parameters are call arguments.
+    rx_dev = torch.as_tensor(cfg["rx"], device="cuda")
+    out_buf = torch.empty((4096, sbr.PATH_DTYPE.itemsize), dtype=torch.uint8, device="cuda")
+
+    def run_dev(**kw):
+        got, st = sc.trace_device(cfg["tx"], rx_dev, out=out_buf, **kw)
+        return got, st
+
+    def timed(steps, warmup, host_api=False, **kw):
+        call = (lambda: sc.trace(cfg["tx"], cfg["rx"], **kw)) if host_api else \
+            (lambda: run_dev(**kw))
         for _ in range(warmup):
-            sc.trace(cfg["tx"], cfg["rx"], **kw)
+            call()
         stats = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            paths, st = sc.trace(cfg["tx"], cfg["rx"], **kw)
+            paths, st = call()
             stats.append(st)
         torch.cuda.synchronize()
-        return paths, stats, time.perf_counter() - t0
+        wall = time.perf_counter() - t0
+        if not host_api:
+            paths = paths.cpu().numpy().reshape(-1).view(sbr.PATH_DTYPE)
+        return paths, stats, wall
 
     # (1) the configuration as stated: I = 5 iterations, launch grid recomputed every step
     paths, stats, wall = timed(args.steps, args.warmup, fresh_grid=True, **prm)
@@ -360,6 +383,9 @@ def main():
     # (2) steady state of a tracer serving many calls at one division n: the
     # launch directions stay cached in the context
     _, _, wall_c = timed(args.steps, 1, **prm)
+    # (2b) the host-array entry point (sbr_trace): receivers and paths cross
+    # PCIe every call
+    _, _, wall_h = timed(args.steps, 1, host_api=True, fresh_grid=True, **prm)
     # (3) refined paths at <= 0.01 deg: iterate each path until its AOD (and,
     # through the L_last / L_total scaling, its AOA) error is below 0.01 deg
     tprm = dict(prm, iterations=30, target_err_deg=0.01)
@@ -417,6 +443,7 @@ def main():
         "fixed_i5": {"paths": int(len(paths)), "within_0.01deg": good,
                      "refined_paths_per_s": good / (ms_step * 1e-3)},
         "value_cached_grid": n_rays * args.steps / wall_c,
+        "value_host_arrays_pcie": n_rays * args.steps / wall_h,
         "trace_rays_per_s": n_rays / (stage["ms_trace"] * 1e-3),
         "stage_ms": {k: round(v, 5) for k, v in stage.items()},
         "counts": counts,

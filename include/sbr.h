@@ -193,6 +193,18 @@ sbr_status sbr_trace(sbr_scene* scene, const double tx[3], const double* rx, int
                      const sbr_trace_params* params, sbr_path* out, int64_t capacity,
                      int64_t* n_out, sbr_trace_stats* stats);
 
+/* sbr_trace with the receivers and the output in device memory (for example
+ * torch tensors on the context's device): rx [n_rx][3] and out [capacity]
+ * are device pointers, tx and params stay on the host.  The work is queued on
+ * the context's stream after everything already queued there, and the call
+ * returns when out and *n_out (host) are complete.  When n_rx reaches the
+ * context's rx_tree_min the receivers are read back once to build the
+ * receiver tree on the host.  Receivers are not validated: non-finite ones
+ * are never captured.  Errors as sbr_trace. */
+sbr_status sbr_trace_device(sbr_scene* scene, const double tx[3], const double* rx, int32_t n_rx,
+                            const sbr_trace_params* params, sbr_path* out, int64_t capacity,
+                            int64_t* n_out, sbr_trace_stats* stats);
+
 /* One job of a batched trace: transmitter tx on scenes[scene], its receivers
  * rx[rx_first .. rx_first + n_rx) of the batch's receiver array (a receiver
  * belongs to at most one job), and its own trace parameters. */

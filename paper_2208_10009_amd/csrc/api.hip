@@ -250,7 +250,8 @@ struct Call {
     std::vector<int32_t> rx_job;
     std::vector<RxNode> rx_nodes;  // receiver trees of the jobs that have one
     std::vector<int32_t> rx_perm;  // receiver indices in tree-leaf order
-    const double* rx = nullptr;  // host [n_rx][3]
+    const double* rx = nullptr;      // host [n_rx][3] (NULL with only device receivers)
+    const double* rx_dev = nullptr;  // device [n_rx][3] when the caller passed device memory
     int32_t n_rx = 0;
     int64_t n_rays = 0, n_packets = 0;
     int32_t chunk = 1;
@@ -373,8 +374,12 @@ sbr_status upload_call(sbr_context* c, Call& call)
         HIPCHK(c, hipMemcpyAsync(c->d_scenes.p, sd.data(), sizeof(SceneDev) * sd.size(),
                                  hipMemcpyHostToDevice, st));
     if (call.n_rx > 0) {
-        HIPCHK(c, hipMemcpyAsync(c->rx.p, call.rx, sizeof(double) * 3 * (size_t)call.n_rx,
-                                 hipMemcpyHostToDevice, st));
+        if (call.rx_dev)
+            HIPCHK(c, hipMemcpyAsync(c->rx.p, call.rx_dev, sizeof(double) * 3 * (size_t)call.n_rx,
+                                     hipMemcpyDeviceToDevice, st));
+        else
+            HIPCHK(c, hipMemcpyAsync(c->rx.p, call.rx, sizeof(double) * 3 * (size_t)call.n_rx,
+                                     hipMemcpyHostToDevice, st));
         HIPCHK(c, hipMemcpyAsync(c->d_rxjob.p, call.rx_job.data(), sizeof(int32_t) * call.rx_job.size(),
                                  hipMemcpyHostToDevice, st));
     }
@@ -501,7 +506,7 @@ sbr_status ensure_host_paths(sbr_context* c, int64_t n)
 // The back half: precise algorithm, path quantities / path test 2 / power,
 // and the canonical emit into out.
 sbr_status run_paths(sbr_context* c, Call& call, sbr_path* out, int64_t capacity, int64_t* n_out,
-                     sbr_trace_stats* stats)
+                     sbr_trace_stats* stats, bool out_on_device = false)
 {
     hipStream_t st = c->stream;
     Counters* hc = c->host_ctr;
@@ -541,7 +546,7 @@ sbr_status run_paths(sbr_context* c, Call& call, sbr_path* out, int64_t capacity
                                     c->outp.as<sbr_path>(), &dc->n_paths, st));
         r = ensure_host_paths(c, (int64_t)U1);
         if (r) return r;
-        if (Umax > 0)
+        if (Umax > 0 && !out_on_device)
             HIPCHK(c, hipMemcpyAsync(c->host_paths, c->outp.p, sizeof(sbr_path) * (size_t)Umax,
                                      hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipMemcpyAsync(hc, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
@@ -554,7 +559,13 @@ sbr_status run_paths(sbr_context* c, Call& call, sbr_path* out, int64_t capacity
         if (P > capacity)
             return fail(c, SBR_E_CAPACITY, "%lld paths, capacity %lld", (long long)P,
                         (long long)capacity);
-        if (P > 0) memcpy(out, c->host_paths, sizeof(sbr_path) * (size_t)P);
+        if (P > 0 && out_on_device) {
+            HIPCHK(c, hipMemcpyAsync(out, c->outp.p, sizeof(sbr_path) * (size_t)P,
+                                     hipMemcpyDeviceToDevice, st));
+            HIPCHK(c, hipStreamSynchronize(st));
+        } else if (P > 0) {
+            memcpy(out, c->host_paths, sizeof(sbr_path) * (size_t)P);
+        }
     } else {
         HIPCHK(c, launch_scan(c->keep.as<int32_t>(), c->offs.as<int32_t>(), U, &dc->n_paths,
                               c->scan.p, st));
@@ -571,7 +582,9 @@ sbr_status run_paths(sbr_context* c, Call& call, sbr_path* out, int64_t capacity
                                        c->offs.as<int32_t>(), U, c->outp.as<sbr_path>(), st));
         if (P > 0)
             HIPCHK(c, hipMemcpyAsync(out, c->outp.p, sizeof(sbr_path) * (size_t)P,
-                                     hipMemcpyDeviceToHost, st));
+                                     out_on_device ? hipMemcpyDeviceToDevice
+                                                   : hipMemcpyDeviceToHost,
+                                     st));
         HIPCHK(c, hipEventRecord(c->ev[6], st));
         HIPCHK(c, hipEventSynchronize(c->ev[6]));
     }
@@ -1087,6 +1100,33 @@ sbr_status sbr_trace(sbr_scene* s, const double tx[3], const double* rx, int32_t
     r = run_front(c, call, true, nullptr, nullptr, nullptr);
     if (r) return r;
     return run_paths(c, call, out, capacity, n_out, stats);
+}
+
+sbr_status sbr_trace_device(sbr_scene* s, const double tx[3], const double* rx, int32_t n_rx,
+                            const sbr_trace_params* p, sbr_path* out, int64_t capacity,
+                            int64_t* n_out, sbr_trace_stats* stats)
+{
+    sbr_status r = check_trace_inputs(s, tx, nullptr, 0, p, capacity, out, n_out);
+    if (r) return r;
+    sbr_context* c = s->ctx;
+    if (n_rx < 0 || (n_rx > 0 && !rx)) return fail(c, SBR_E_INVALID_ARG, "bad rx array");
+    HIPCHK(c, hipSetDevice(c->device));
+    // The receiver tree is built on the host: read the receivers back once
+    // when the job is large enough to use it.
+    std::vector<double> rx_host;
+    if (n_rx > 0 && n_rx >= c->rx_tree_min) {
+        rx_host.resize(3 * (size_t)n_rx);
+        HIPCHK(c, hipMemcpyAsync(rx_host.data(), rx, sizeof(double) * rx_host.size(),
+                                 hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    Call call;
+    call.rx_dev = rx;
+    r = single_call(s, call, tx, rx_host.empty() ? nullptr : rx_host.data(), n_rx, p, 0, -1);
+    if (r) return r;
+    r = run_front(c, call, true, nullptr, nullptr, nullptr);
+    if (r) return r;
+    return run_paths(c, call, out, capacity, n_out, stats, true);
 }
 
 sbr_status sbr_trace_batch(sbr_context* c, sbr_scene* const* scenes, int32_t n_scenes,

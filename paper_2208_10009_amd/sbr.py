@@ -38,7 +38,8 @@ PATH_TARGET_MET = 4
 # every function declared in include/sbr.h
 EXPORTS = (
     "sbr_context_create", "sbr_context_destroy", "sbr_scene_upload", "sbr_bvh_build",
-    "sbr_scene_destroy", "sbr_trace", "sbr_candidates", "sbr_launch_grid", "sbr_trace_rays",
+    "sbr_scene_destroy", "sbr_trace", "sbr_trace_device", "sbr_candidates", "sbr_launch_grid",
+    "sbr_trace_rays",
     "sbr_trace_counters", "sbr_trace_batch", "sbr_context_get_tuning", "sbr_context_set_tuning",
     "sbr_path_gradients", "sbr_status_string", "sbr_last_error",
 )
@@ -156,6 +157,8 @@ def lib(load_torch: bool = True):
     L.sbr_scene_destroy.argtypes = [vp]
     L.sbr_trace.argtypes = [vp, dp, dp, C.c_int32, C.POINTER(TraceParams), vp, C.c_int64, lp,
                             C.POINTER(TraceStats)]
+    L.sbr_trace_device.argtypes = [vp, dp, vp, C.c_int32, C.POINTER(TraceParams), vp, C.c_int64,
+                                   lp, C.POINTER(TraceStats)]
     L.sbr_candidates.argtypes = [vp, dp, dp, C.c_int32, C.POINTER(TraceParams), vp, C.c_int64,
                                  lp]
     L.sbr_launch_grid.argtypes = [vp, C.c_int32, C.c_int32, C.c_int64, C.c_int64, dp]
@@ -324,6 +327,31 @@ class Scene:
                 continue
             self.ctx._check(st)
             return out[: n.value].copy(), stats.as_dict()
+
+    def trace_device(self, tx, rx, out=None, **params):
+        """sbr_trace_device: rx is a float64 [n_rx, 3] tensor on the context's
+        device; returns (paths as a uint8 [n, record] device tensor, stats).
+        `out` (a uint8 device tensor of whole records) is reused when large
+        enough; otherwise, or on SBR_E_CAPACITY, a larger one is allocated."""
+        import torch
+        txa = np.ascontiguousarray(tx, np.float64).reshape(3)
+        assert rx.dtype == torch.float64 and rx.is_cuda and rx.dim() == 2 and rx.shape[1] == 3
+        rx = rx.contiguous()
+        prm = make_params(**params)
+        rec = PATH_DTYPE.itemsize
+        if out is None:
+            out = torch.empty((4096, rec), dtype=torch.uint8, device=rx.device)
+        while True:
+            n = C.c_int64()
+            stats = TraceStats()
+            st = lib().sbr_trace_device(self.h, _d(txa), C.c_void_p(rx.data_ptr()), rx.shape[0],
+                                        C.byref(prm), C.c_void_p(out.data_ptr()), out.shape[0],
+                                        C.byref(n), C.byref(stats))
+            if st == E_CAPACITY:
+                out = torch.empty((n.value, rec), dtype=torch.uint8, device=rx.device)
+                continue
+            self.ctx._check(st)
+            return out[: n.value], stats.as_dict()
 
     def candidates(self, tx, rx, capacity: int | None = None, **params):
         """sbr_candidates: reception events before path test 1, sorted."""

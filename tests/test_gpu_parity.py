@@ -429,3 +429,34 @@ def test_tuning_roundtrip_and_invariance(gpu):
     finally:
         gpu.set_tuning(**base)
         sc.close()
+
+
+# --------------------------------------------------- device-memory variant --
+def test_trace_device_matches_host_api(gpu):
+    """sbr_trace_device (receivers and paths in device memory) returns the
+    same records as sbr_trace: small and large receiver sets (the latter
+    through the receiver tree), a too-small output buffer (two-call sizing
+    inside the binding) and no receivers."""
+    import torch
+    from paper_2208_10009_amd import sbr
+    base = gpu.tuning()
+    for cfg, prm, tree in ((scenes.manhattan_config(0), {}, None),
+                           (scenes.manhattan_config(5, n_rx=300), dict(division_n=80), 16)):
+        p = dict(cfg["params"], **prm)
+        sc = gpu.scene(cfg["scene"])
+        try:
+            if tree:
+                gpu.set_tuning(rx_tree_min=tree)
+            ref, st = sc.trace(cfg["tx"], cfg["rx"], **p)
+            rx = torch.as_tensor(cfg["rx"], device="cuda")
+            got, st2 = sc.trace_device(cfg["tx"], rx, **p)
+            small = torch.empty((3, sbr.PATH_DTYPE.itemsize), dtype=torch.uint8, device="cuda")
+            got2, _ = sc.trace_device(cfg["tx"], rx, out=small, **p)
+            none, _ = sc.trace_device(cfg["tx"], rx[:0], **p)
+        finally:
+            gpu.set_tuning(**base)
+            sc.close()
+        g = got.cpu().numpy().reshape(-1).view(sbr.PATH_DTYPE)
+        assert len(ref) > 3 and g.tobytes() == ref.tobytes()
+        assert got2.cpu().numpy().tobytes() == ref.tobytes()
+        assert none.shape[0] == 0 and st2["n_paths"] == st["n_paths"]
