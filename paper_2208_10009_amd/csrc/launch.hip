@@ -28,9 +28,18 @@ struct GridHdr {
 
 __host__ __device__ static inline int64_t ring_cap(int32_t n) { return n / 3 + 2; }
 
+// Scratch layout: the header; ring corners [20][cap][3] (d3); the angle each
+// ring side subtends, [20][cap][3] (double); the angle of each icosahedron
+// edge, [30] (double).
 size_t grid_scratch_bytes(int32_t n)
 {
-    return sizeof(GridHdr) + sizeof(d3) * 3 * 20 * (size_t)ring_cap(n);
+    return sizeof(GridHdr) + (sizeof(d3) + sizeof(double)) * 3 * 20 * (size_t)ring_cap(n) +
+           sizeof(double) * 30;
+}
+
+__host__ __device__ static inline double* side_angles(char* scratch, int32_t n)
+{
+    return (double*)(scratch + sizeof(GridHdr) + sizeof(d3) * 3 * 20 * (size_t)ring_cap(n));
 }
 
 __device__ static void ico_build(GridHdr* H)
@@ -66,18 +75,6 @@ __device__ static void ico_build(GridHdr* H)
             }
 }
 
-// Point k of m equal-angle steps from P to Q along their great circle: the
-// angles subtended at the centre by consecutive points are equal (eq. (1)).
-// Direction sin((m-k) th/m) P + sin(k th/m) Q, normalized.
-__device__ static d3 arc_point(d3 P, d3 Q, int64_t k, int64_t m)
-{
-    double th = acos_cr(dot(P, Q));
-    double a = ((double)k * th) / (double)m;
-    double b = ((double)(m - k) * th) / (double)m;
-    double sa = sin_cr(a), sb = sin_cr(b);
-    return normalize(add(scl(sb, P), scl(sa, Q)));
-}
-
 // Central projection onto the plane x.g = 1 parallel to the face.
 __device__ static d3 proj_face(d3 p, d3 g)
 {
@@ -92,21 +89,31 @@ __device__ static d3 proj_face(d3 p, d3 g)
 // construction of Fig. 3b), and the new side has three steps fewer.  Side 0
 // is the single face-centre ray; negative sides end the face (the three
 // innermost cases).  The layers depend on each other, so one block walks
-// them in order: 120 threads compute the 20 x 3 x 2 neighbour points of a
-// layer, then 60 threads form the next corners.
+// them in order.  Per layer each of the 60 ring sides (20 faces x 3) has two
+// lanes: the side's angle th = acos_cr(P.Q) needs the double-double sine and
+// cosine of the library's acos (one lane each), the two neighbour points
+// need sin(th/m) and sin((m-1)th/m) (one lane each: the first step from one
+// corner and the last step into the next corner use the same two sines,
+// swapped).  The arithmetic is that of arc_point and acos_cr, term by term.
+// The side angles are kept for k_grid_dirs, which would otherwise recompute
+// them for every ray.
 __global__ __launch_bounds__(128) void k_grid_setup(int32_t n, char* scratch)
 {
     GridHdr* H = (GridHdr*)scratch;
     d3* rings = (d3*)(scratch + sizeof(GridHdr));
+    double* ths = side_angles(scratch, n);
     __shared__ GridHdr sh;
     __shared__ d3 W[20][3];
     __shared__ d3 P[20][3][2];
+    __shared__ dd SC[60][2];
+    __shared__ double SN[60][2];
     const int t = threadIdx.x;
     if (t == 0) {
         ico_build(&sh);
         *H = sh;
     }
     __syncthreads();
+    if (t < 30) ths[3 * 20 * ring_cap(n) + t] = acos_cr(dot(sh.V[sh.e[t][0]], sh.V[sh.e[t][1]]));
     const int f60 = t / 3, s60 = t % 3;
     if (t < 60) W[f60][s60] = sh.V[sh.f[f60][s60]];
     __syncthreads();
@@ -115,10 +122,32 @@ __global__ __launch_bounds__(128) void k_grid_setup(int32_t n, char* scratch)
         d3 A = sh.V[sh.f[f60][0]], B = sh.V[sh.f[f60][1]], C = sh.V[sh.f[f60][2]];
         g = add(add(A, B), C);
     }
+    const int side = t >> 1, role = t & 1;
+    const int fs = side / 3, ss = side % 3;
     const size_t cap3 = 3 * (size_t)ring_cap(n);
     int64_t m = n;
     for (int a = 0;; ++a) {
-        int64_t mp = m - 3;
+        // m >= 1 is the side of ring a (ring 0 is the face boundary); its
+        // corners are W.  First the angle of each of its sides.
+        d3 Pa = mk(0.0, 0.0, 0.0), Pb = Pa;
+        double x = 0.0, y0 = 0.0, th = 0.0;
+        if (t < 120) {
+            Pa = W[fs][ss];
+            Pb = W[fs][(ss + 1) % 3];
+            x = dot(Pa, Pb);
+            y0 = acos(x);
+            const dd yy = dd{y0, 0.0};
+            const dd tt = dd_mul(yy, yy);
+            SC[side][role] = role == 0 ? dd_mul(yy, dd_poly_alt(1, tt)) : dd_poly_alt(0, tt);
+        }
+        __syncthreads();
+        if (t < 120) {
+            // th = acos_cr(x): one Newton step y + (cos y - x) / sin y
+            const dd y = dd_add(dd{y0, 0.0}, dd_div(dd_sub(SC[side][1], dd{x, 0.0}), SC[side][0]));
+            th = y.hi + y.lo;
+            if (role == 0 && a > 0) ths[(size_t)fs * cap3 + 3 * (a - 1) + ss] = th;
+        }
+        const int64_t mp = m - 3;
         if (mp < 0) break;
         if (mp == 0) {
             if (t < 20) {
@@ -132,12 +161,19 @@ __global__ __launch_bounds__(128) void k_grid_setup(int32_t n, char* scratch)
             break;
         }
         if (t < 120) {
-            // w = 0: first step from corner s toward s+1; w = 1: last step
-            // from corner s-1 toward s (the two ring neighbours of corner s)
-            int f = t / 6, s = (t % 6) >> 1, w = t & 1;
-            d3 Pa = w == 0 ? W[f][s] : W[f][(s + 2) % 3];
-            d3 Pb = w == 0 ? W[f][(s + 1) % 3] : W[f][s];
-            P[f][s][w] = arc_point(Pa, Pb, w == 0 ? 1 : m - 1, m);
+            const double a1 = ((double)1 * th) / (double)m;
+            const double b1 = ((double)(m - 1) * th) / (double)m;
+            SN[side][role] = sin_cr(role == 0 ? a1 : b1);
+        }
+        __syncthreads();
+        if (t < 120) {
+            const double sa = SN[side][0], sb = SN[side][1];
+            // role 0: step 1 from corner ss toward ss+1; role 1: step m-1 of
+            // the same side, the last step into corner ss+1
+            if (role == 0)
+                P[fs][ss][0] = normalize(add(scl(sb, Pa), scl(sa, Pb)));
+            else
+                P[fs][(ss + 1) % 3][1] = normalize(add(scl(sa, Pa), scl(sb, Pb)));
         }
         __syncthreads();
         d3 Wn = mk(0.0, 0.0, 0.0);
@@ -154,6 +190,18 @@ __global__ __launch_bounds__(128) void k_grid_setup(int32_t n, char* scratch)
     }
 }
 
+// Point k of m equal-angle steps from P to Q along their great circle, th
+// being the angle P and Q subtend (acos_cr(P.Q)): the angles subtended at
+// the centre by consecutive points are equal (eq. (1)).  Direction
+// sin((m-k) th/m) P + sin(k th/m) Q, normalized.
+__device__ static d3 arc_point_th(d3 P, d3 Q, double th, int64_t k, int64_t m)
+{
+    double a = ((double)k * th) / (double)m;
+    double b = ((double)(m - k) * th) / (double)m;
+    double sa = sin_cr(a), sb = sin_cr(b);
+    return normalize(add(scl(sb, P), scl(sa, Q)));
+}
+
 // Ray order: the 12 vertex rays; then edge interiors, edge by edge, steps
 // 1..n-1 from the lower to the higher vertex index; then face interiors, face
 // by face, layer by layer, each ring starting at the corner that descends
@@ -165,6 +213,7 @@ __global__ void k_grid_dirs(int32_t n, int64_t N, const char* __restrict__ scrat
     if (i >= N) return;
     const GridHdr* H = (const GridHdr*)scratch;
     const d3* rings = (const d3*)(scratch + sizeof(GridHdr));
+    const double* ths = side_angles((char*)scratch, n);
     d3 r;
     int64_t idx = i;
     if (idx < 12) {
@@ -173,7 +222,8 @@ __global__ void k_grid_dirs(int32_t n, int64_t N, const char* __restrict__ scrat
         idx -= 12;
         if (idx < 30 * (int64_t)(n - 1)) {
             int64_t e = idx / (n - 1), k = idx % (n - 1) + 1;
-            r = arc_point(H->V[H->e[e][0]], H->V[H->e[e][1]], k, n);
+            r = arc_point_th(H->V[H->e[e][0]], H->V[H->e[e][1]], ths[3 * 20 * ring_cap(n) + e], k,
+                             n);
         } else {
             idx -= 30 * (int64_t)(n - 1);
             int64_t per_face = (int64_t)(n - 1) * (n - 2) / 2;
@@ -192,7 +242,9 @@ __global__ void k_grid_dirs(int32_t n, int64_t N, const char* __restrict__ scrat
                 r = W[0];
             } else {
                 int64_t s = q / m, k = q % m;
-                r = k == 0 ? W[s] : arc_point(W[s], W[(s + 1) % 3], k, m);
+                r = k == 0 ? W[s]
+                           : arc_point_th(W[s], W[(s + 1) % 3],
+                                          ths[(size_t)f * 3 * ring_cap(n) + 3 * a + s], k, m);
             }
         }
     }
