@@ -139,8 +139,10 @@ typedef struct {
  * per workgroup (a budget of just 4 * stack_depth * trace_block bytes keeps
  * only the stack there); 0 traverses from global memory with a private stack
  * (256 lanes per workgroup).
- * The refinement resolves two iterations per step with one wave per path
- * when there are at most lookahead_max_paths paths.  A job with at least
+ * With at most lookahead_max_paths paths the refinement resolves
+ * lookahead_depth iterations per traversal step (3: a 512-lane workgroup per
+ * path, used without an LDS plan; 2: one wave per path); otherwise, or with
+ * depth 1, one iteration per step with eight lanes per path.  A job with at least
  * rx_tree_min receivers tests reception through a ball tree over its
  * receivers (a conservative cull before the exact test of eq. (3)) instead of
  * testing every receiver on every segment. */
@@ -152,6 +154,8 @@ typedef struct {
     int32_t lds_budget;          /* bytes, 0..device limit per workgroup    */
     int32_t rx_tree_min;         /* >= 1                                    */
     int64_t lookahead_max_paths; /* >= 0                                    */
+    int32_t lookahead_depth;     /* 1..3                                    */
+    int32_t reserved;            /* must be 0                               */
 } sbr_tuning;
 
 sbr_status sbr_context_get_tuning(const sbr_context* ctx, sbr_tuning* out);

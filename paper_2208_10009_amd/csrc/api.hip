@@ -80,6 +80,7 @@ struct sbr_context {
     // (SBR_TRACE_CHUNK, SBR_TRACE_BLOCKS)
     int32_t trace_chunk = 1, persist_blocks = 2048;
     int32_t rx_tree_min = 64;
+    int32_t lookahead_depth = 3;
 };
 
 struct sbr_scene {
@@ -521,9 +522,9 @@ sbr_status run_paths(sbr_context* c, Call& call, sbr_path* out, int64_t capacity
     HIPCHK(c, ensure(c->geom, sizeof(PathGeom) * U1));
     LdsPlan lp256 = call.scenes.size() == 1 ? plan_for(call.scenes[0], 256) : LdsPlan{};
     lp256.block = 256;
-    const bool lookahead = Umax <= c->lookahead_max_paths;
+    const int depth = Umax <= c->lookahead_max_paths ? c->lookahead_depth : 1;
     HIPCHK(c, launch_refine(call.dev, lp256, call.s0, c->uniq.as<sbr_candidate>(), Umax, ndev,
-                            lookahead, c->refine.as<RefineOut>(), c->geom.as<PathGeom>(),
+                            depth, c->refine.as<RefineOut>(), c->geom.as<PathGeom>(),
                             &dc->err, st));
     HIPCHK(c, hipEventRecord(c->ev[4], st));
 
@@ -725,6 +726,7 @@ sbr_status sbr_context_create(int32_t device, void* hip_stream, sbr_context** ou
         c->trace_chunk = env_int("SBR_TRACE_CHUNK", 1, 1, 64);
         c->persist_blocks = env_int("SBR_TRACE_BLOCKS", 2048, 1, 1 << 20);
         c->rx_tree_min = env_int("SBR_RX_TREE_MIN", 64, 1, 0x7fffffff);
+        c->lookahead_depth = env_int("SBR_LOOKAHEAD_DEPTH", 3, 1, 3);
     }
     if (e != hipSuccess) {
         g_create_err = std::string("context setup: ") + hipGetErrorString(e);
@@ -747,6 +749,8 @@ sbr_status sbr_context_get_tuning(const sbr_context* c, sbr_tuning* t)
     t->lds_budget = c->lds_budget;
     t->rx_tree_min = c->rx_tree_min;
     t->lookahead_max_paths = c->lookahead_max_paths;
+    t->lookahead_depth = c->lookahead_depth;
+    t->reserved = 0;
     return SBR_OK;
 }
 
@@ -758,7 +762,8 @@ sbr_status sbr_context_set_tuning(sbr_context* c, const sbr_tuning* t)
     if (t->trace_chunk < 1 || t->trace_chunk > 64 || t->persist_blocks < 1 ||
         t->trace_block < 64 || t->trace_block > 256 || t->trace_block % 64 != 0 ||
         t->stack_depth < 0 || t->stack_depth > kTraceStack || t->lds_budget < 0 ||
-        t->lds_budget > c->lds_max || t->rx_tree_min < 1 || t->lookahead_max_paths < 0)
+        t->lds_budget > c->lds_max || t->rx_tree_min < 1 || t->lookahead_max_paths < 0 ||
+        t->lookahead_depth < 1 || t->lookahead_depth > 3 || t->reserved != 0)
         return fail(c, SBR_E_INVALID_ARG, "tuning field out of range");
     c->trace_chunk = t->trace_chunk;
     c->persist_blocks = t->persist_blocks;
@@ -767,6 +772,7 @@ sbr_status sbr_context_set_tuning(sbr_context* c, const sbr_tuning* t)
     c->lds_budget = t->lds_budget;
     c->rx_tree_min = t->rx_tree_min;
     c->lookahead_max_paths = t->lookahead_max_paths;
+    c->lookahead_depth = t->lookahead_depth;
     return SBR_OK;
 }
 

@@ -180,12 +180,13 @@ struct RefineOut {
     uint32_t flags;
 };
 
-// U_max paths (the first min(U_max, *n_dev) when n_dev is non-NULL).  With
-// lookahead, one wave per path resolves two iterations per step; otherwise
-// eight lanes per path take one iteration per step.
+// U_max paths (the first min(U_max, *n_dev) when n_dev is non-NULL).  Depth
+// 3 (without an LDS plan): one 512-lane workgroup per path resolves three
+// iterations per step; depth 2: one wave per path, two iterations per step;
+// depth 1: eight lanes per path, one iteration per step.
 hipError_t launch_refine(const CallDev& call, const LdsPlan& L, const SceneDev& s0,
                          const sbr_candidate* uniq, int64_t U_max, const int32_t* n_dev,
-                         bool lookahead, RefineOut* out, PathGeom* geom, int32_t* err,
+                         int depth, RefineOut* out, PathGeom* geom, int32_t* err,
                          hipStream_t s);
 
 hipError_t launch_solve(const CallDev& call, const LdsPlan& L, const SceneDev& s0,

@@ -74,7 +74,7 @@ __device__ static inline void store_geom(PathGeom* g, int k, const d3* pts, cons
 // target no replay is needed; with a target the replay gives the unfolded
 // lengths of the stop rule.  Returns false if the replay does not reproduce
 // the path.
-template <bool LDS>
+template <bool LDS, int BLK = 256>
 __device__ static inline bool start_path(const SceneDev& S, const LdsPlan& L, double tan_tgt,
                                          const sbr_candidate& c, d3 tx, d3 rx, d3 axis,
                                          float delta, int32_t* err, double* tan, bool* met)
@@ -85,7 +85,7 @@ __device__ static inline bool start_path(const SceneDev& S, const LdsPlan& L, do
         return true;
     }
     Follow F0;
-    if (!follow<LDS>(S, L, tx, axis, rx, c.order, c.face, delta, &F0, nullptr, nullptr, err))
+    if (!follow<LDS, BLK>(S, L, tx, axis, rx, c.order, c.face, delta, &F0, nullptr, nullptr, err))
         return false;
     *tan = F0.tan_err;
     *met = target_met(F0.tan_err, tan_tgt, F0.D, F0.Llast);
@@ -314,12 +314,185 @@ __global__ __launch_bounds__(256) void k_refine_la(CallDev call, LdsPlan L, Scen
     }
 }
 
+// One workgroup of 512 lanes per path, three iterations per step.  Lane
+// (s1, s2, s3) = (t >> 6, (t >> 3) & 7, t & 7) traces the sub-ray that the
+// sub-ray choices s1, then s2, then s3 would give; index 7 marks a level the
+// lane does not reach, so lanes (s1, 7, 7) are the first level, (s1, s2, 7)
+// the second and (s1, s2, s3) the third.  The winners are picked level by
+// level through LDS; as in k_refine_la every sub-ray is computed with the
+// arithmetic of the one-iteration-at-a-time order, so the result is the same
+// bit for bit and three iterations take the latency of one.
+template <bool LDS>
+__global__ __launch_bounds__(512) void k_refine_la3(CallDev call, LdsPlan L, SceneDev s0,
+                                                    const sbr_candidate* __restrict__ uniq,
+                                                    int64_t U_max,
+                                                    const int32_t* __restrict__ n_dev,
+                                                    RefineOut* __restrict__ out,
+                                                    PathGeom* __restrict__ geom,
+                                                    int32_t* __restrict__ err)
+{
+    if (LDS) stage_scene(s0, L);
+    __shared__ double sk[8], sD[8], sL[8];
+    const int64_t p = blockIdx.x;
+    const int t = threadIdx.x;
+    const int s1 = t >> 6, s2 = (t >> 3) & 7, s3 = t & 7;
+    const int64_t U = n_dev ? min(U_max, (int64_t)*n_dev) : U_max;
+    if (p >= U) return;  // uniform over the workgroup
+    const sbr_candidate c = uniq[p];
+    const int jb = call.rx_job[c.rx];
+    const JobDev J = call.jobs[jb];
+    const SceneDev S = LDS ? s0 : call.scenes[J.scene];
+    const d3 tx = mk(J.tx[0], J.tx[1], J.tx[2]);
+    const d3 rx = mk(call.rx[3 * c.rx], call.rx[3 * c.rx + 1], call.rx[3 * c.rx + 2]);
+    d3 axis = mk(J.dir[c.ray], J.dir[J.N + c.ray], J.dir[2 * J.N + c.ray]);
+    double tan;
+    bool met;
+    if (!start_path<LDS, 512>(S, L, J.tan_tgt, c, tx, rx, axis, J.delta, err, &tan, &met)) {
+        if (t == 0) out[p] = stalled_at_start(axis);
+        return;
+    }
+    const int S_ = J.subrays;
+    uint32_t flags = met ? SBR_PATH_TARGET_MET : 0u;
+    int32_t iters = 0;
+    double rho = J.thl;
+    // the smallest of the 8 slots (ties: lower index); 8 when all are empty
+    auto argmin8 = [&](double* k) {
+        int b = 8;
+        double kb = INFINITY;
+        for (int q = 0; q < 8; ++q)
+            if (k[q] < kb) {
+                kb = k[q];
+                b = q;
+            }
+        return b;
+    };
+    for (int i = 1; i <= J.iterations && !met; i += 3) {
+        const double rho1 = rho / sqrt(3.0);
+        const double rho2 = rho1 / sqrt(3.0);
+        const double rho3 = rho2 / sqrt(3.0);
+        const int levels = min(3, J.iterations - i + 1);
+        d3 u, v;
+        basis(axis, &u, &v);
+        const bool lvl1 = s2 == 7 && s3 == 7 && s1 < S_;
+        const bool lvl2 = levels >= 2 && s3 == 7 && s1 < S_ && s2 < S_;
+        const bool lvl3 = levels >= 3 && s1 < S_ && s2 < S_ && s3 < S_;
+        Follow F;
+        bool ok = false;
+        d3 gp[SBR_MAX_ORDER], gd[SBR_MAX_ORDER];
+        if (lvl1 || lvl2 || lvl3) {
+            d3 dt = subray(axis, u, v, rho1, s1);
+            if (lvl2 || lvl3) {
+                d3 u2, v2;
+                basis(dt, &u2, &v2);
+                dt = subray(dt, u2, v2, rho2, s2);
+            }
+            if (lvl3) {
+                d3 u3, v3;
+                basis(dt, &u3, &v3);
+                dt = subray(dt, u3, v3, rho3, s3);
+            }
+            ok = follow<LDS, 512>(S, L, tx, dt, rx, c.order, c.face, J.delta, &F, gp, gd, err);
+        }
+        // first level: lanes (s1, 7, 7)
+        if (s2 == 7 && s3 == 7) {
+            sk[s1] = (lvl1 && ok) ? F.tan_err : INFINITY;
+            sD[s1] = (lvl1 && ok) ? F.D : 0.0;
+            sL[s1] = (lvl1 && ok) ? F.Llast : 0.0;
+        }
+        __syncthreads();
+        const int b1 = argmin8(sk);
+        const double k1 = b1 < 8 ? sk[b1] : INFINITY, w1D = b1 < 8 ? sD[b1] : 0.0,
+                     w1L = b1 < 8 ? sL[b1] : 0.0;
+        __syncthreads();
+        if (b1 >= 8) {
+            flags |= SBR_PATH_STALLED;
+            break;
+        }
+        if (s1 == b1 && s2 == 7 && s3 == 7) store_geom(geom + p, c.order, gp, gd);
+        axis = subray(axis, u, v, rho1, b1);
+        tan = k1;
+        iters = i;
+        rho = rho1;
+        if (J.tan_tgt > 0.0 && target_met(k1, J.tan_tgt, w1D, w1L)) {
+            flags |= SBR_PATH_TARGET_MET;
+            break;
+        }
+        if (levels < 2) break;
+        // second level: lanes (b1, s2, 7)
+        if (s1 == b1 && s3 == 7) {
+            sk[s2] = (lvl2 && ok) ? F.tan_err : INFINITY;
+            sD[s2] = (lvl2 && ok) ? F.D : 0.0;
+            sL[s2] = (lvl2 && ok) ? F.Llast : 0.0;
+        }
+        __threadfence_block();
+        __syncthreads();
+        const int b2 = argmin8(sk);
+        const double k2 = b2 < 8 ? sk[b2] : INFINITY, w2D = b2 < 8 ? sD[b2] : 0.0,
+                     w2L = b2 < 8 ? sL[b2] : 0.0;
+        __syncthreads();
+        if (b2 >= 8) {
+            flags |= SBR_PATH_STALLED;
+            break;
+        }
+        if (s1 == b1 && s2 == b2 && s3 == 7) store_geom(geom + p, c.order, gp, gd);
+        basis(axis, &u, &v);
+        axis = subray(axis, u, v, rho2, b2);
+        tan = k2;
+        iters = i + 1;
+        rho = rho2;
+        if (J.tan_tgt > 0.0 && target_met(k2, J.tan_tgt, w2D, w2L)) {
+            flags |= SBR_PATH_TARGET_MET;
+            break;
+        }
+        if (levels < 3) break;
+        // third level: lanes (b1, b2, s3)
+        if (s1 == b1 && s2 == b2) {
+            sk[s3] = (lvl3 && ok) ? F.tan_err : INFINITY;
+            sD[s3] = (lvl3 && ok) ? F.D : 0.0;
+            sL[s3] = (lvl3 && ok) ? F.Llast : 0.0;
+        }
+        __threadfence_block();
+        __syncthreads();
+        const int b3 = argmin8(sk);
+        const double k3 = b3 < 8 ? sk[b3] : INFINITY, w3D = b3 < 8 ? sD[b3] : 0.0,
+                     w3L = b3 < 8 ? sL[b3] : 0.0;
+        __syncthreads();
+        if (b3 >= 8) {
+            flags |= SBR_PATH_STALLED;
+            break;
+        }
+        if (s1 == b1 && s2 == b2 && s3 == b3) store_geom(geom + p, c.order, gp, gd);
+        basis(axis, &u, &v);
+        axis = subray(axis, u, v, rho3, b3);
+        tan = k3;
+        iters = i + 2;
+        rho = rho3;
+        if (J.tan_tgt > 0.0 && target_met(k3, J.tan_tgt, w3D, w3L)) {
+            flags |= SBR_PATH_TARGET_MET;
+            break;
+        }
+    }
+    if (t == 0) {
+        RefineOut o;
+        st3(o.axis, axis);
+        o.tan_err = tan;
+        o.iters = iters;
+        o.flags = flags;
+        out[p] = o;
+    }
+}
+
 hipError_t launch_refine(const CallDev& call, const LdsPlan& L, const SceneDev& s0,
-                         const sbr_candidate* uniq, int64_t U, const int32_t* n_dev,
-                         bool lookahead, RefineOut* out, PathGeom* geom, int32_t* err,
-                         hipStream_t s)
+                         const sbr_candidate* uniq, int64_t U, const int32_t* n_dev, int depth,
+                         RefineOut* out, PathGeom* geom, int32_t* err, hipStream_t s)
 {
     if (U <= 0) return hipSuccess;
+    if (depth >= 3 && L.bytes == 0) {
+        hipLaunchKernelGGL(k_refine_la3<false>, dim3((unsigned)U), dim3(512), 0, s, call, L, s0,
+                           uniq, U, n_dev, out, geom, err);
+        return hipGetLastError();
+    }
+    const bool lookahead = depth >= 2;
     int64_t threads = U * (lookahead ? 64 : 8);
     dim3 grid((unsigned)((threads + L.block - 1) / L.block));
     if (lookahead && L.bytes > 0)

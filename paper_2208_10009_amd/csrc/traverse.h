@@ -132,7 +132,7 @@ constexpr int kShortStack = 16;  // LDS stack entries per lane without an LDS pl
 // ignoring triangles of faces xa and xb.  Returns the leaf-order position of
 // the hit or -1.  LDS = false reads everything from global memory (no LDS
 // plan needed) and keeps the top of the stack in a static LDS array.
-template <bool ANY, bool COUNT, bool LDS>
+template <bool ANY, bool COUNT, bool LDS, int BLK = 256>
 __device__ static int32_t traverse(const SceneDev& S, const LdsPlan& L, d3 o, d3 d, int32_t xa,
                                    int32_t xb, double t_lo, double t_hi, float delta, HitRec* h,
                                    int32_t* err, Tally* tally = nullptr)
@@ -156,7 +156,7 @@ __device__ static int32_t traverse(const SceneDev& S, const LdsPlan& L, d3 o, d3
 
     // The first stack entries live in LDS: the plan's stack (LDS instances)
     // or a fixed short stack of kShortStack entries per lane (workgroups of
-    // at most 256 lanes); deeper entries go to the private array.
+    // at most BLK lanes); deeper entries go to the private array.
     int32_t* lst;
     int bd, ldepth;
     if constexpr (LDS) {
@@ -164,10 +164,12 @@ __device__ static int32_t traverse(const SceneDev& S, const LdsPlan& L, d3 o, d3
         bd = blockDim.x;
         ldepth = L.depth;
     } else {
-        __shared__ int32_t s_stack[kShortStack * 256];
+        __shared__ int32_t s_stack[kShortStack * BLK];
         lst = s_stack + threadIdx.x;
-        bd = 256;
-        ldepth = kShortStack;
+        bd = BLK;
+        // a lane beyond BLK (a caller instantiated for a smaller workgroup)
+        // keeps its whole stack in private memory instead of past the array
+        ldepth = threadIdx.x < BLK ? kShortStack : 0;
     }
     int32_t ost[kTraceStack];
     int sp = 0;
@@ -321,7 +323,7 @@ struct Follow {
 // order and Rx lies ahead on its last segment before the next obstacle.
 // With pts/din non-NULL the reflection points and incoming directions are
 // stored.
-template <bool LDS>
+template <bool LDS, int BLK = 256>
 __device__ static bool follow(const SceneDev& S, const LdsPlan& L, d3 tx, d3 d0, d3 rx, int k,
                               const int32_t* faces, float delta, Follow* F, d3* pts, d3* din,
                               int32_t* err)
@@ -332,7 +334,8 @@ __device__ static bool follow(const SceneDev& S, const LdsPlan& L, d3 tx, d3 d0,
     for (int j = 0;; ++j) {
         HitRec h;
         int32_t hit =
-            traverse<false, false, LDS>(S, L, o, d, prev, prev, S.t_eps, INFINITY, delta, &h, err);
+            traverse<false, false, LDS, BLK>(S, L, o, d, prev, prev, S.t_eps, INFINITY, delta, &h,
+                                             err);
         if (j == k) {
             double t = hit < 0 ? INFINITY : h.t;
             double tn;

@@ -68,10 +68,11 @@ class Tuning(C.Structure):
     _fields_ = [("trace_chunk", C.c_int32), ("persist_blocks", C.c_int32),
                 ("trace_block", C.c_int32), ("stack_depth", C.c_int32),
                 ("lds_budget", C.c_int32), ("rx_tree_min", C.c_int32),
-                ("lookahead_max_paths", C.c_int64)]
+                ("lookahead_max_paths", C.c_int64), ("lookahead_depth", C.c_int32),
+                ("reserved", C.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class Complex(C.Structure):

@@ -277,16 +277,19 @@ def _trace_with_env(env, cfg, **prm):
 
 
 @pytest.mark.parametrize("prm", [dict(iterations=5, subrays=7), dict(iterations=4, subrays=6),
-                                 dict(iterations=9, subrays=7, target_err_deg=0.01)])
+                                 dict(iterations=9, subrays=7, target_err_deg=0.01),
+                                 dict(iterations=7, subrays=6, target_err_deg=0.003),
+                                 dict(iterations=1, subrays=7), dict(iterations=2, subrays=6)])
 def test_refine_lookahead_matches_single_step(gpu, orc, prm):
-    """The two-iteration lookahead kernel (64 lanes per path) and the
-    one-iteration kernel (8 lanes per path) give byte-identical paths, and
-    both match the oracle."""
+    """The three-iteration (512 lanes per path) and two-iteration (64 lanes)
+    lookahead kernels and the one-iteration kernel (8 lanes per path) give
+    byte-identical paths, and all match the oracle."""
     cfg = scenes.manhattan_config(2, n_rx=24)
     full = dict(cfg["params"], division_n=80, **prm)
     a = _trace_with_env({"SBR_LOOKAHEAD_PATHS": "0"}, cfg, **full)
-    b = _trace_with_env({"SBR_LOOKAHEAD_PATHS": "100000"}, cfg, **full)
-    assert a.tobytes() == b.tobytes()
+    b = _trace_with_env({"SBR_LOOKAHEAD_PATHS": "100000", "SBR_LOOKAHEAD_DEPTH": "2"}, cfg, **full)
+    c = _trace_with_env({"SBR_LOOKAHEAD_PATHS": "100000", "SBR_LOOKAHEAD_DEPTH": "3"}, cfg, **full)
+    assert a.tobytes() == b.tobytes() == c.tobytes()
     o = orc.run(cfg["scene"], cfg["tx"], cfg["rx"], **full)["paths"]
     _compare_paths(a, o)
 
@@ -417,7 +420,8 @@ def test_tuning_roundtrip_and_invariance(gpu):
         for t in (dict(trace_chunk=3, persist_blocks=7), dict(persist_blocks=1),
                   dict(lds_budget=65536, stack_depth=8, trace_block=128),
                   dict(lds_budget=24 * 4 * 256, stack_depth=24),
-                  dict(lookahead_max_paths=0, trace_chunk=64), dict(rx_tree_min=1)):
+                  dict(lookahead_max_paths=0, trace_chunk=64), dict(rx_tree_min=1),
+                  dict(lookahead_depth=2), dict(lookahead_depth=1)):
             gpu.set_tuning(**dict(base, **t))
             assert gpu.tuning()["trace_chunk"] == dict(base, **t)["trace_chunk"]
             got, _ = sc.trace(cfg["tx"], cfg["rx"], **prm)
@@ -426,6 +430,8 @@ def test_tuning_roundtrip_and_invariance(gpu):
             gpu.set_tuning(trace_block=100)
         with pytest.raises(sbr.SbrError):
             gpu.set_tuning(rx_tree_min=0)
+        with pytest.raises(sbr.SbrError):
+            gpu.set_tuning(lookahead_depth=4)
     finally:
         gpu.set_tuning(**base)
         sc.close()
