@@ -36,7 +36,7 @@ if ROOT not in sys.path:
 
 METRIC = "rays/s + refined paths/s at ≤0.01° AOA/AOD error; batched vs plain, 1 GPU"
 HBM_PEAK_GBS = 8000.0
-NODE_BYTES = 64     # BVH2 node: two FP32 child boxes + child references
+NODE_BYTES = 128    # BVH4 node: four FP32 child boxes + child references
 TRI_BYTES = 80      # FP64 triangle record (v0, e1, e2, face, index)
 RAY_BYTES = 24      # FP64 launch direction read per ray
 EVENT_BYTES = 56    # reception event record written

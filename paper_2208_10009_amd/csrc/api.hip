@@ -161,7 +161,7 @@ sbr_status get_grid(sbr_context* c, int32_t launch, int32_t n, GridDev* g, bool*
 SceneDev scene_dev(const sbr_scene* s)
 {
     SceneDev S;
-    S.nodes = s->nodes.as<const BvhNode>();
+    S.nodes = s->nodes.as<const Bvh4Node>();
     S.tris = s->tris.as<const TriD>();
     S.fplane = s->d_fplane.as<const double>();
     S.fmat = s->d_fmat.as<const int32_t>();
@@ -643,14 +643,14 @@ LdsPlan make_lds_plan(int64_t NN, int64_t T, int block, int depth, int budget)
     depth = (int)std::min<int64_t>(depth, std::max<int64_t>(0, budget / per_entry));
     L.depth = depth;
     int64_t avail = (int64_t)budget - per_entry * depth;
-    if (NN * (int64_t)sizeof(BvhNode) + T * (int64_t)sizeof(TriD) <= avail) {
+    if (NN * (int64_t)sizeof(Bvh4Node) + T * (int64_t)sizeof(TriD) <= avail) {
         L.n_nodes = (int32_t)NN;
         L.n_tris = (int32_t)T;
     } else {
-        L.n_nodes = (int32_t)std::min<int64_t>(NN, avail / (int64_t)sizeof(BvhNode));
+        L.n_nodes = (int32_t)std::min<int64_t>(NN, avail / (int64_t)sizeof(Bvh4Node));
         L.n_tris = 0;
     }
-    L.stack_off = (int32_t)(L.n_nodes * (int64_t)sizeof(BvhNode) + L.n_tris * (int64_t)sizeof(TriD));
+    L.stack_off = (int32_t)(L.n_nodes * (int64_t)sizeof(Bvh4Node) + L.n_tris * (int64_t)sizeof(TriD));
     L.bytes = (int32_t)(L.stack_off + per_entry * depth);
     return L;
 }
@@ -899,11 +899,11 @@ sbr_status sbr_bvh_build(sbr_scene* s, const sbr_bvh_params* bp)
     int leaf = bp ? bp->max_leaf_size : 4, bins = bp ? bp->sah_bins : 16;
     if (leaf < 1 || leaf > 16 || bins < 4 || bins > 64)
         return fail(c, SBR_E_INVALID_ARG, "bvh params out of range");
-    std::vector<BvhNode> nodes;
+    std::vector<Bvh4Node> nodes;
     std::vector<int32_t> perm;
     s->bvh_depth = build_bvh(s->tri_v.data(), s->T, leaf, bins, c->lds_budget > 0, nodes, perm);
     s->n_nodes = (int64_t)nodes.size();
-    if (s->bvh_depth >= kTraceStack) return fail(c, SBR_E_INTERNAL, "BVH too deep");
+    if (3 * s->bvh_depth >= kTraceStack) return fail(c, SBR_E_INTERNAL, "BVH too deep");
     std::vector<TriD> tris((size_t)s->T);
     std::vector<int32_t> pos_of((size_t)s->T);
     for (int64_t q = 0; q < s->T; ++q) {
@@ -925,14 +925,14 @@ sbr_status sbr_bvh_build(sbr_scene* s, const sbr_bvh_params* bp)
     for (int64_t t = 0; t < s->T; ++t) ftris[fill[s->face[t]]++] = pos_of[t];
 
     HIPCHK(c, hipSetDevice(c->device));
-    HIPCHK(c, ensure(s->nodes, sizeof(BvhNode) * nodes.size()));
+    HIPCHK(c, ensure(s->nodes, sizeof(Bvh4Node) * nodes.size()));
     HIPCHK(c, ensure(s->tris, sizeof(TriD) * tris.size()));
     HIPCHK(c, ensure(s->d_fplane, sizeof(double) * s->fplane.size()));
     HIPCHK(c, ensure(s->d_fmat, sizeof(int32_t) * s->fmat.size()));
     HIPCHK(c, ensure(s->fstart, sizeof(int32_t) * fstart.size()));
     HIPCHK(c, ensure(s->ftris, sizeof(int32_t) * ftris.size()));
     HIPCHK(c, ensure(s->d_eps, sizeof(double) * s->eps.size()));
-    HIPCHK(c, hipMemcpy(s->nodes.p, nodes.data(), sizeof(BvhNode) * nodes.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(s->nodes.p, nodes.data(), sizeof(Bvh4Node) * nodes.size(), hipMemcpyHostToDevice));
     if (!tris.empty())
         HIPCHK(c, hipMemcpy(s->tris.p, tris.data(), sizeof(TriD) * tris.size(), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(s->d_fplane.p, s->fplane.data(), sizeof(double) * s->fplane.size(), hipMemcpyHostToDevice));

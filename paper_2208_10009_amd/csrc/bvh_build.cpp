@@ -1,4 +1,4 @@
-// bvh_build.cpp -- host-side binned-SAH BVH2 builder.
+// bvh_build.cpp -- host-side binned-SAH BVH2 builder, collapsed to a BVH4.
 //
 // The paper leaves the acceleration of SBR open (Sec. I mentions acceleration
 // work only); this BVH is the build's own choice.  Boxes are computed in FP64
@@ -205,8 +205,70 @@ struct Builder {
 
 }  // namespace
 
+namespace {
+
+// One child slot of a BVH4 node under construction.
+struct Slot {
+    float lo[3], hi[3];
+    int32_t index, count;
+    double area() const
+    {
+        double dx = (double)hi[0] - lo[0], dy = (double)hi[1] - lo[1], dz = (double)hi[2] - lo[2];
+        return 2.0 * (dx * dy + dy * dz + dz * dx);
+    }
+};
+
+void bvh2_children(const BvhNode& nd, Slot* s)
+{
+    s[0] = Slot{{nd.a[0], nd.a[1], nd.a[2]}, {nd.a[3], nd.b[0], nd.b[1]}, nd.m[0], nd.m[2]};
+    s[1] = Slot{{nd.b[2], nd.b[3], nd.c[0]}, {nd.c[1], nd.c[2], nd.c[3]}, nd.m[1], nd.m[3]};
+}
+
+// Collapse the BVH2 subtree at n2 into a BVH4 node (depth-first preorder):
+// start from n2's two children and open the inner child of largest surface
+// area until there are four children or only leaves.  Returns the depth.
+int collapse(const std::vector<BvhNode>& n2, int32_t r, std::vector<Bvh4Node>& n4, int32_t at)
+{
+    Slot s[4];
+    int ns = 2;
+    bvh2_children(n2[r], s);
+    while (ns < 4) {
+        int best = -1;
+        for (int k = 0; k < ns; ++k)
+            if (s[k].count == 0 && (best < 0 || s[k].area() > s[best].area())) best = k;
+        if (best < 0) break;
+        Slot two[2];
+        bvh2_children(n2[s[best].index], two);
+        s[best] = two[0];
+        s[ns++] = two[1];
+    }
+    int depth = 1;
+    for (int k = 0; k < ns; ++k)
+        if (s[k].count == 0) {
+            const int32_t child = (int32_t)n4.size();
+            n4.push_back(Bvh4Node{});
+            depth = std::max(depth, 1 + collapse(n2, s[k].index, n4, child));
+            s[k].index = child;
+        }
+    Bvh4Node& nd = n4[at];
+    for (int k = 0; k < 4; ++k) {
+        const bool used = k < ns && s[k].count >= 0;
+        nd.lox[k] = used ? s[k].lo[0] : 0.0f;
+        nd.loy[k] = used ? s[k].lo[1] : 0.0f;
+        nd.loz[k] = used ? s[k].lo[2] : 0.0f;
+        nd.hix[k] = used ? s[k].hi[0] : 0.0f;
+        nd.hiy[k] = used ? s[k].hi[1] : 0.0f;
+        nd.hiz[k] = used ? s[k].hi[2] : 0.0f;
+        nd.idx[k] = used ? s[k].index : 0;
+        nd.cnt[k] = used ? s[k].count : -1;
+    }
+    return depth;
+}
+
+}  // namespace
+
 int build_bvh(const double* tri_v, int64_t T, int max_leaf, int bins, bool bfs,
-              std::vector<BvhNode>& nodes, std::vector<int32_t>& perm)
+              std::vector<Bvh4Node>& nodes, std::vector<int32_t>& perm)
 {
     Builder B;
     B.tv = tri_v;
@@ -244,38 +306,40 @@ int build_bvh(const double* tri_v, int64_t T, int max_leaf, int bins, bool bfs,
         }
     }
     B.emit(0, L, R);
+    // BVH4 in depth-first preorder: the first child usually follows its
+    // parent in memory
+    std::vector<Bvh4Node> n4;
+    n4.push_back(Bvh4Node{});
+    const int depth = collapse(B.nodes, 0, n4, 0);
+    perm.swap(B.idx);
     if (!bfs) {
-        // depth-first order: the near child usually follows its parent in memory
-        nodes.swap(B.nodes);
-        perm.swap(B.idx);
-        return B.depth_reached;
+        nodes.swap(n4);
+        return depth;
     }
-    // Renumber the inner nodes breadth-first, so that the top levels of the
-    // tree form a prefix of the node array (the part staged in LDS).
-    const size_t NN = B.nodes.size();
+    // Renumber breadth-first, so that the top levels of the tree form a
+    // prefix of the node array (the part staged in LDS).
+    const size_t NN = n4.size();
     std::vector<int32_t> order;
     order.reserve(NN);
     std::vector<int32_t> new_id(NN, -1);
     order.push_back(0);
     new_id[0] = 0;
     for (size_t q = 0; q < order.size(); ++q) {
-        const BvhNode& nd = B.nodes[order[q]];
-        for (int c = 0; c < 2; ++c) {
-            if (nd.m[2 + c] != 0) continue;  // leaf or empty child
-            int32_t ch = nd.m[c];
-            new_id[ch] = (int32_t)order.size();
-            order.push_back(ch);
+        const Bvh4Node& nd = n4[order[q]];
+        for (int k = 0; k < 4; ++k) {
+            if (nd.cnt[k] != 0) continue;  // leaf or empty child
+            new_id[nd.idx[k]] = (int32_t)order.size();
+            order.push_back(nd.idx[k]);
         }
     }
     nodes.resize(order.size());
     for (size_t q = 0; q < order.size(); ++q) {
-        BvhNode nd = B.nodes[order[q]];
-        for (int c = 0; c < 2; ++c)
-            if (nd.m[2 + c] == 0) nd.m[c] = new_id[nd.m[c]];
+        Bvh4Node nd = n4[order[q]];
+        for (int k = 0; k < 4; ++k)
+            if (nd.cnt[k] == 0) nd.idx[k] = new_id[nd.idx[k]];
         nodes[q] = nd;
     }
-    perm.swap(B.idx);
-    return B.depth_reached;
+    return depth;
 }
 
 }  // namespace sbr

@@ -22,27 +22,38 @@ static_assert(sizeof(TriD) == 80, "TriD layout");
 // BVH2 node, 64 bytes: the FP32 boxes of both children (rounded outward)
 // and, per child, (index, count): count > 0 is a leaf of `count` triangles
 // starting at `index` in leaf order, count == 0 an inner node, count < 0 an
-// empty child.  Packed as 4 x 16 B for aligned vector loads:
+// empty child.  Packed as 4 x 16 B:
 //   a = lo0.xyz hi0.x | b = hi0.yz lo1.xy | c = lo1.z hi1.xyz | m = c0 c1 n0 n1
+// The builder's intermediate form; the device traverses the BVH4 below.
 struct BvhNode {
     float a[4], b[4], c[4];
     int32_t m[4];
 };
 static_assert(sizeof(BvhNode) == 64, "BvhNode layout");
 
-constexpr int kMaxBvhDepth = 48;   // builder cap; traversal stack bound (< kTraceStack)
-constexpr int kTraceStack = 64;
+// BVH4 node, 128 bytes (8 x 16 B): the FP32 boxes of four children in SoA
+// (lo x, lo y, lo z, hi x, hi y, hi z, four children each), then per child
+// (index, count) with the BvhNode meaning.  Collapsed from the BVH2, whose
+// outward-rounded child boxes it keeps unchanged.
+struct Bvh4Node {
+    float lox[4], loy[4], loz[4], hix[4], hiy[4], hiz[4];
+    int32_t idx[4], cnt[4];
+};
+static_assert(sizeof(Bvh4Node) == 128, "Bvh4Node layout");
 
-// Host-side BVH build (binned SAH).  tri_v is [T][9] FP64 vertices.  Inner
-// nodes are numbered depth-first, or breadth-first with bfs (so that the top
-// levels form a prefix for LDS staging).  perm receives the leaf order
-// (input indices); returns the depth reached.
+constexpr int kMaxBvhDepth = 48;  // builder cap on the BVH2 depth
+constexpr int kTraceStack = 96;   // traversal stack; a BVH4 level pushes at most 3
+
+// Host-side BVH build (binned SAH BVH2, collapsed to BVH4).  tri_v is [T][9]
+// FP64 vertices.  Nodes are numbered depth-first, or breadth-first with bfs
+// (so that the top levels form a prefix for LDS staging).  perm receives the
+// leaf order (input indices); returns the BVH4 depth.
 int build_bvh(const double* tri_v, int64_t T, int max_leaf, int bins, bool bfs,
-              std::vector<BvhNode>& nodes, std::vector<int32_t>& perm);
+              std::vector<Bvh4Node>& nodes, std::vector<int32_t>& perm);
 
 // Device view of a scene.
 struct SceneDev {
-    const BvhNode* nodes;
+    const Bvh4Node* nodes;
     const TriD* tris;       // leaf order
     const double* fplane;   // [F][4]: unit normal, offset n.v0
     const int32_t* fmat;    // [F]

@@ -1,7 +1,8 @@
 // traverse.h -- BVH traversal with FP64 ray-triangle decisions, shared by the
 // trace, refinement and solve kernels.
 //
-// Memory plan per workgroup (dynamic LDS, see LdsPlan): the first n_nodes BVH
+// The scene is a BVH4 (128-byte nodes with four FP32 child boxes).  Memory
+// plan per workgroup (dynamic LDS, see LdsPlan): the first n_nodes BVH
 // nodes (the top levels: nodes are numbered breadth-first), all triangles
 // when they fit, and a per-lane traversal stack of `depth` entries.  Deeper
 // nodes are read from global memory, and stack entries beyond `depth` spill
@@ -31,9 +32,9 @@ extern __shared__ float4 g_smem4[];
 __device__ static inline void stage_scene(const SceneDev& S, const LdsPlan& L)
 {
     const float4* sn = (const float4*)S.nodes;
-    for (int i = threadIdx.x; i < 4 * L.n_nodes; i += blockDim.x) g_smem4[i] = sn[i];
+    for (int i = threadIdx.x; i < 8 * L.n_nodes; i += blockDim.x) g_smem4[i] = sn[i];
     const float4* st = (const float4*)S.tris;
-    float4* dt = g_smem4 + 4 * L.n_nodes;
+    float4* dt = g_smem4 + 8 * L.n_nodes;
     for (int i = threadIdx.x; i < 5 * L.n_tris; i += blockDim.x) dt[i] = st[i];
     __syncthreads();
 }
@@ -109,7 +110,7 @@ template <bool LDS>
 __device__ static inline TriD tri_at(const SceneDev& S, const LdsPlan& L, int32_t i)
 {
     if (LDS && i < L.n_tris) {
-        const double2* q = (const double2*)(g_smem4 + 4 * L.n_nodes + 5 * i);
+        const double2* q = (const double2*)(g_smem4 + 8 * L.n_nodes + 5 * i);
         return make_tri(q[0], q[1], q[2], q[3], q[4]);
     }
     const double2* q = (const double2*)(S.tris + i);
@@ -175,36 +176,49 @@ __device__ static int32_t traverse(const SceneDev& S, const LdsPlan& L, d3 o, d3
     int sp = 0;
     int32_t node = 0;
     for (;;) {
-        float4 a, b, c, mf;
+        float4 q0, q1, q2, q3, q4, q5, q6, q7;
         if (LDS && node < L.n_nodes) {
-            const float4* np = g_smem4 + 4 * node;
-            a = np[0]; b = np[1]; c = np[2]; mf = np[3];
+            const float4* np = g_smem4 + 8 * node;
+            q0 = np[0]; q1 = np[1]; q2 = np[2]; q3 = np[3];
+            q4 = np[4]; q5 = np[5]; q6 = np[6]; q7 = np[7];
         } else {
             const float4* np = (const float4*)(S.nodes + node);
-            a = gld(np); b = gld(np + 1); c = gld(np + 2); mf = gld(np + 3);
+            q0 = gld(np); q1 = gld(np + 1); q2 = gld(np + 2); q3 = gld(np + 3);
+            q4 = gld(np + 4); q5 = gld(np + 5); q6 = gld(np + 6); q7 = gld(np + 7);
         }
-        const int4 m = __builtin_bit_cast(int4, mf);
+        const int4 cidx = __builtin_bit_cast(int4, q6), ccnt = __builtin_bit_cast(int4, q7);
         if (COUNT) tally->nodes += 1;
-        // child 0: lo (a.x a.y a.z) hi (a.w b.x b.y); child 1: lo (b.z b.w c.x) hi (c.y c.z c.w)
-        float t0x = (a.x - lx) * ix, t1x = (a.w - hx) * ix;
-        float t0y = (a.y - ly) * iy, t1y = (b.x - hy) * iy;
-        float t0z = (a.z - lz) * iz, t1z = (b.y - hz) * iz;
-        float tn0 = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fminf(t0z, t1z));
-        float tf0 = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)) * slack;
-        float u0x = (b.z - lx) * ix, u1x = (c.y - hx) * ix;
-        float u0y = (b.w - ly) * iy, u1y = (c.z - hy) * iy;
-        float u0z = (c.x - lz) * iz, u1z = (c.w - hz) * iz;
-        float tn1 = fmaxf(fmaxf(fminf(u0x, u1x), fminf(u0y, u1y)), fminf(u0z, u1z));
-        float tf1 = fminf(fminf(fmaxf(u0x, u1x), fmaxf(u0y, u1y)), fmaxf(u0z, u1z)) * slack;
-        bool hit0 = m.z >= 0 && tn0 <= tf0 && tf0 >= 0.0f && tn0 <= tb;
-        bool hit1 = m.w >= 0 && tn1 <= tf1 && tf1 >= 0.0f && tn1 <= tb;
+        // child k: lo (q0[k], q1[k], q2[k]), hi (q3[k], q4[k], q5[k])
+        float tn[4];
+        bool hit[4];
+        int32_t first[4], cnt[4];
 #pragma unroll
-        for (int side = 0; side < 2; ++side) {
-            bool hl = side == 0 ? (hit0 && m.z > 0) : (hit1 && m.w > 0);
-            if (!hl) continue;
-            int32_t first = side == 0 ? m.x : m.y;
-            int32_t cnt = side == 0 ? m.z : m.w;
-            for (int32_t i = first; i < first + cnt; ++i) {
+        for (int k = 0; k < 4; ++k) {
+            const float lox = k == 0 ? q0.x : k == 1 ? q0.y : k == 2 ? q0.z : q0.w;
+            const float loy = k == 0 ? q1.x : k == 1 ? q1.y : k == 2 ? q1.z : q1.w;
+            const float loz = k == 0 ? q2.x : k == 1 ? q2.y : k == 2 ? q2.z : q2.w;
+            const float hix = k == 0 ? q3.x : k == 1 ? q3.y : k == 2 ? q3.z : q3.w;
+            const float hiy = k == 0 ? q4.x : k == 1 ? q4.y : k == 2 ? q4.z : q4.w;
+            const float hiz = k == 0 ? q5.x : k == 1 ? q5.y : k == 2 ? q5.z : q5.w;
+            first[k] = k == 0 ? cidx.x : k == 1 ? cidx.y : k == 2 ? cidx.z : cidx.w;
+            cnt[k] = k == 0 ? ccnt.x : k == 1 ? ccnt.y : k == 2 ? ccnt.z : ccnt.w;
+            const float t0x = (lox - lx) * ix, t1x = (hix - hx) * ix;
+            const float t0y = (loy - ly) * iy, t1y = (hiy - hy) * iy;
+            const float t0z = (loz - lz) * iz, t1z = (hiz - hz) * iz;
+            tn[k] = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fminf(t0z, t1z));
+            const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)) * slack;
+            hit[k] = cnt[k] >= 0 && tn[k] <= tf && tf >= 0.0f && tn[k] <= tb;
+        }
+        // leaf children first: their hits can only shrink the pruning bound
+        uint32_t leaves = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) leaves |= (hit[k] && cnt[k] > 0) ? (1u << k) : 0u;
+        while (leaves) {
+            const int k = __builtin_ctz(leaves);
+            leaves &= leaves - 1;
+            const int32_t lf = k == 0 ? first[0] : k == 1 ? first[1] : k == 2 ? first[2] : first[3];
+            const int32_t lc = k == 0 ? cnt[0] : k == 1 ? cnt[1] : k == 2 ? cnt[2] : cnt[3];
+            for (int32_t i = lf; i < lf + lc; ++i) {
                 TriD T = tri_at<LDS>(S, L, i);
                 if (COUNT) tally->tris += 1;
                 if (T.face == xa || T.face == xb) continue;
@@ -230,28 +244,56 @@ __device__ static int32_t traverse(const SceneDev& S, const LdsPlan& L, d3 o, d3
                 }
             }
         }
-        bool go0 = hit0 && m.z == 0 && tn0 <= tb;
-        bool go1 = hit1 && m.w == 0 && tn1 <= tb;
-        if (go0 && go1) {
-            bool first0 = tn0 <= tn1;
-            int32_t nearc = first0 ? m.x : m.y, farc = first0 ? m.y : m.x;
-            if (sp >= kTraceStack) {
-                atomicOr(err, 1);
-                return h->pos;
+        // inner children still within the bound, nearest first: a sorting
+        // network on (entry distance, node); empty entries sort last
+        float k0 = (hit[0] && cnt[0] == 0 && tn[0] <= tb) ? tn[0] : INFINITY;
+        float k1 = (hit[1] && cnt[1] == 0 && tn[1] <= tb) ? tn[1] : INFINITY;
+        float k2 = (hit[2] && cnt[2] == 0 && tn[2] <= tb) ? tn[2] : INFINITY;
+        float k3 = (hit[3] && cnt[3] == 0 && tn[3] <= tb) ? tn[3] : INFINITY;
+        int32_t n0 = first[0], n1 = first[1], n2 = first[2], n3 = first[3];
+        auto cswap = [](float& ka, int32_t& na, float& kb, int32_t& nb) {
+            if (kb < ka) {
+                const float tk = ka;
+                ka = kb;
+                kb = tk;
+                const int32_t tnn = na;
+                na = nb;
+                nb = tnn;
             }
-            if (sp < ldepth) lst[sp * bd] = farc;
-            else ost[sp - ldepth] = farc;
-            ++sp;
-            node = nearc;
-        } else if (go0) {
-            node = m.x;
-        } else if (go1) {
-            node = m.y;
-        } else {
+        };
+        cswap(k0, n0, k1, n1);
+        cswap(k2, n2, k3, n3);
+        cswap(k0, n0, k2, n2);
+        cswap(k1, n1, k3, n3);
+        cswap(k1, n1, k2, n2);
+        if (k0 == INFINITY) {
             if (sp == 0) break;
             --sp;
             node = sp < ldepth ? lst[sp * bd] : ost[sp - ldepth];
+            continue;
         }
+        // push the farther ones, farthest first, and descend into the nearest
+        const int npush = (k1 < INFINITY) + (k2 < INFINITY) + (k3 < INFINITY);
+        if (sp + npush > kTraceStack) {
+            atomicOr(err, 1);
+            return h->pos;
+        }
+        if (k3 < INFINITY) {
+            if (sp < ldepth) lst[sp * bd] = n3;
+            else ost[sp - ldepth] = n3;
+            ++sp;
+        }
+        if (k2 < INFINITY) {
+            if (sp < ldepth) lst[sp * bd] = n2;
+            else ost[sp - ldepth] = n2;
+            ++sp;
+        }
+        if (k1 < INFINITY) {
+            if (sp < ldepth) lst[sp * bd] = n1;
+            else ost[sp - ldepth] = n1;
+            ++sp;
+        }
+        node = n0;
     }
     return h->pos;
 }
