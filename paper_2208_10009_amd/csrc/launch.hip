@@ -89,15 +89,24 @@ __device__ static d3 proj_face(d3 p, d3 g)
 // construction of Fig. 3b), and the new side has three steps fewer.  Side 0
 // is the single face-centre ray; negative sides end the face (the three
 // innermost cases).  The layers depend on each other, so one block walks
-// them in order.  Per layer each of the 60 ring sides (20 faces x 3) has two
-// lanes: the side's angle th = acos_cr(P.Q) needs the double-double sine and
-// cosine of the library's acos (one lane each), the two neighbour points
-// need sin(th/m) and sin((m-1)th/m) (one lane each: the first step from one
-// corner and the last step into the next corner use the same two sines,
-// swapped).  The arithmetic is that of arc_point and acos_cr, term by term.
-// The side angles are kept for k_grid_dirs, which would otherwise recompute
-// them for every ray.
-__global__ __launch_bounds__(128) void k_grid_setup(int32_t n, char* scratch)
+// them in order.
+//
+// Each layer needs, per ring side (20 faces x 3), the side's angle
+// th = acos(P.Q) and the sines of a = th/m and b = (m-1) th/m, all correctly
+// rounded (the first step from one corner and the last step into the next
+// corner use the same two sines, swapped).  To keep the chain short, three
+// lanes per side start from the library's y0 = acos(P.Q) at once:
+//   lane 0: cos y0 in double-double and sin y0 from the library; one Newton
+//           step th = y0 + (cos y0 - P.Q) / sin y0 is accurate to ~1e-31
+//           (the correction is ~1e-16, so a 1e-16 relative sine suffices);
+//   lanes 1, 2: sin b0, sin a0 in double-double for b0, a0 formed from y0,
+//           and cos b0, cos a0 from the library.
+// Then sin a = sin a0 + cos a0 (a - a0) - sin a0 (a - a0)^2 / 2 with
+// a - a0 ~ 1e-16 (exact in binary64), likewise for b; the neglected terms are
+// below 1e-31 relative, so each value rounds as the exact one does (the
+// results are checked bit for bit against the correctly rounded grid).
+// The side angles are kept for k_grid_dirs.
+__global__ __launch_bounds__(192) void k_grid_setup(int32_t n, char* scratch)
 {
     GridHdr* H = (GridHdr*)scratch;
     d3* rings = (d3*)(scratch + sizeof(GridHdr));
@@ -105,8 +114,9 @@ __global__ __launch_bounds__(128) void k_grid_setup(int32_t n, char* scratch)
     __shared__ GridHdr sh;
     __shared__ d3 W[20][3];
     __shared__ d3 P[20][3][2];
-    __shared__ dd SC[60][2];
-    __shared__ double SN[60][2];
+    __shared__ dd SV[60][3];    // lane 0: cos y0; lane 1: sin b0; lane 2: sin a0
+    __shared__ double CV[60][3];  // lane 0: sin y0; lane 1: cos b0; lane 2: cos a0
+    __shared__ double SN[60][2];  // sin a, sin b
     const int t = threadIdx.x;
     if (t == 0) {
         ico_build(&sh);
@@ -122,28 +132,33 @@ __global__ __launch_bounds__(128) void k_grid_setup(int32_t n, char* scratch)
         d3 A = sh.V[sh.f[f60][0]], B = sh.V[sh.f[f60][1]], C = sh.V[sh.f[f60][2]];
         g = add(add(A, B), C);
     }
-    const int side = t >> 1, role = t & 1;
+    const int side = t / 3, role = t % 3;
     const int fs = side / 3, ss = side % 3;
     const size_t cap3 = 3 * (size_t)ring_cap(n);
     int64_t m = n;
     for (int a = 0;; ++a) {
         // m >= 1 is the side of ring a (ring 0 is the face boundary); its
-        // corners are W.  First the angle of each of its sides.
+        // corners are W.
         d3 Pa = mk(0.0, 0.0, 0.0), Pb = Pa;
-        double x = 0.0, y0 = 0.0, th = 0.0;
-        if (t < 120) {
+        double x = 0.0, y0 = 0.0, a0 = 0.0, b0 = 0.0;
+        if (t < 180) {
             Pa = W[fs][ss];
             Pb = W[fs][(ss + 1) % 3];
             x = dot(Pa, Pb);
             y0 = acos(x);
-            const dd yy = dd{y0, 0.0};
-            const dd tt = dd_mul(yy, yy);
-            SC[side][role] = role == 0 ? dd_mul(yy, dd_poly_alt(1, tt)) : dd_poly_alt(0, tt);
+            a0 = ((double)1 * y0) / (double)m;
+            b0 = ((double)(m - 1) * y0) / (double)m;
+            const double arg = role == 0 ? y0 : role == 1 ? b0 : a0;
+            const dd aa = dd{arg, 0.0};
+            const dd tt = dd_mul(aa, aa);
+            SV[side][role] = role == 0 ? dd_poly_alt(0, tt) : dd_mul(aa, dd_poly_alt(1, tt));
+            CV[side][role] = role == 0 ? sin(arg) : cos(arg);
         }
         __syncthreads();
-        if (t < 120) {
-            // th = acos_cr(x): one Newton step y + (cos y - x) / sin y
-            const dd y = dd_add(dd{y0, 0.0}, dd_div(dd_sub(SC[side][1], dd{x, 0.0}), SC[side][0]));
+        double th = 0.0;
+        if (t < 180) {
+            const dd r = dd_sub(SV[side][0], dd{x, 0.0});
+            const dd y = dd_add(dd{y0, 0.0}, dd{r.hi / CV[side][0], 0.0});
             th = y.hi + y.lo;
             if (role == 0 && a > 0) ths[(size_t)fs * cap3 + 3 * (a - 1) + ss] = th;
         }
@@ -160,13 +175,18 @@ __global__ __launch_bounds__(128) void k_grid_setup(int32_t n, char* scratch)
             }
             break;
         }
-        if (t < 120) {
-            const double a1 = ((double)1 * th) / (double)m;
-            const double b1 = ((double)(m - 1) * th) / (double)m;
-            SN[side][role] = sin_cr(role == 0 ? a1 : b1);
+        if (t < 180 && role > 0) {
+            // role 1: sin b with b = (m-1) th / m; role 2: sin a with a = th / m
+            const double v = role == 1 ? ((double)(m - 1) * th) / (double)m
+                                       : ((double)1 * th) / (double)m;
+            const double dv = v - (role == 1 ? b0 : a0);
+            const dd s0 = SV[side][role];
+            dd r = dd_add(s0, two_prod(CV[side][role], dv));
+            r = dd_add(r, dd{-(s0.hi * dv * dv * 0.5), 0.0});
+            SN[side][role == 2 ? 0 : 1] = r.hi + r.lo;
         }
         __syncthreads();
-        if (t < 120) {
+        if (t < 180 && role < 2) {
             const double sa = SN[side][0], sb = SN[side][1];
             // role 0: step 1 from corner ss toward ss+1; role 1: step m-1 of
             // the same side, the last step into corner ss+1
@@ -356,7 +376,7 @@ hipError_t launch_grid(GridDev g, hipStream_t s, void* scratch)
                            (const char*)scratch, g.dir);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(128), 0, s, g.n, (char*)scratch);
+    hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(192), 0, s, g.n, (char*)scratch);
     int64_t blocks = (g.N + 255) / 256;
     hipLaunchKernelGGL(k_grid_dirs, dim3((unsigned)blocks), dim3(256), 0, s, g.n, g.N,
                        (const char*)scratch, g.dir);
