@@ -386,6 +386,10 @@ def main():
     # (2b) the host-array entry point (sbr_trace): receivers and paths cross
     # PCIe every call
     _, _, wall_h = timed(args.steps, 1, host_api=True, fresh_grid=True, **prm)
+    # (2c) the stated configuration replayed from a captured HIP graph
+    gpaths, gstats, wall_g = timed(args.steps, 2, fresh_grid=True, graph=True, **prm)
+    graph_replays = sum(1 for st in gstats if st["ms_trace"] == 0.0)
+    assert gpaths.tobytes() == paths.tobytes(), "graph replay differs from the eager call"
     # (3) refined paths at <= 0.01 deg: iterate each path until its AOD (and,
     # through the L_last / L_total scaling, its AOA) error is below 0.01 deg
     tprm = dict(prm, iterations=30, target_err_deg=0.01)
@@ -444,6 +448,8 @@ def main():
                      "refined_paths_per_s": good / (ms_step * 1e-3)},
         "value_cached_grid": n_rays * args.steps / wall_c,
         "value_host_arrays_pcie": n_rays * args.steps / wall_h,
+        "value_graph_replay": n_rays * args.steps / wall_g,
+        "graph_replays": graph_replays,
         "trace_rays_per_s": n_rays / (stage["ms_trace"] * 1e-3),
         "stage_ms": {k: round(v, 5) for k, v in stage.items()},
         "counts": counts,

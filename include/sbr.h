@@ -84,6 +84,8 @@ typedef struct {
 
 #define SBR_FLAG_KEEP_INVALID 1u /* keep paths that fail path test 2 (flag INVALID) */
 #define SBR_FLAG_FRESH_GRID 2u   /* recompute the launch directions even when cached */
+#define SBR_FLAG_GRAPH 4u        /* sbr_trace_device: capture the call as a HIP graph and
+                                    replay it on later calls of the same shape */
 
 /* Path flags (sbr_path.flags). */
 #define SBR_PATH_STALLED 1u    /* an iteration found no sub-ray with the same faces  */
@@ -204,7 +206,16 @@ sbr_status sbr_trace(sbr_scene* scene, const double tx[3], const double* rx, int
  * returns when out and *n_out (host) are complete.  When n_rx reaches the
  * context's rx_tree_min the receivers are read back once to build the
  * receiver tree on the host.  Receivers are not validated: non-finite ones
- * are never captured.  Errors as sbr_trace. */
+ * are never captured.
+ * With SBR_FLAG_GRAPH (and fewer than rx_tree_min receivers) a call that
+ * ends with at most 4096 reception events captures its launch sequence as a
+ * HIP graph; a later call with the same scene, rx and out pointers, n_rx,
+ * capacity, params (flags included) and tuning replays it, reading the
+ * transmitter from this call and the receivers from rx.  A replay whose
+ * counts exceed what was captured (more than 4096 events, or more than twice
+ * the capturing call's unique paths) is redone as a normal call.  Results
+ * are identical either way; with a replay only the count and ms_total fields
+ * of stats are set.  Errors as sbr_trace. */
 sbr_status sbr_trace_device(sbr_scene* scene, const double tx[3], const double* rx, int32_t n_rx,
                             const sbr_trace_params* params, sbr_path* out, int64_t capacity,
                             int64_t* n_out, sbr_trace_stats* stats);

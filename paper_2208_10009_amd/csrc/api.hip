@@ -26,10 +26,15 @@ struct DevBuf {
     T* as() const { return (T*)p; }
 };
 
+// Bumped whenever a device buffer is (re)allocated or released: a captured
+// graph is only replayed while the buffers it was captured with still exist.
+uint64_t g_alloc_epoch = 1;
+
 hipError_t ensure(DevBuf& b, size_t bytes)
 {
     if (bytes == 0) bytes = 256;
     if (b.cap >= bytes) return hipSuccess;
+    ++g_alloc_epoch;
     if (b.p) (void)hipFree(b.p);
     b.p = nullptr;
     b.cap = 0;
@@ -40,6 +45,7 @@ hipError_t ensure(DevBuf& b, size_t bytes)
 
 void release(DevBuf& b)
 {
+    ++g_alloc_epoch;
     if (b.p) (void)hipFree(b.p);
     b.p = nullptr;
     b.cap = 0;
@@ -81,10 +87,28 @@ struct sbr_context {
     int32_t trace_chunk = 1, persist_blocks = 2048;
     int32_t rx_tree_min = 64;
     int32_t lookahead_depth = 3;
+    // one captured graph of a sbr_trace_device call (SBR_FLAG_GRAPH)
+    struct Graph {
+        bool valid = false;
+        uint64_t epoch = 0, scene_id = 0;
+        const double* rx = nullptr;
+        int32_t n_rx = 0;
+        sbr_path* out = nullptr;
+        int64_t capacity = 0, u_cap = 0, n_rays = 0;
+        sbr_trace_params params{};
+        sbr_tuning tuning{};
+        hipGraphExec_t exec = nullptr;
+        hipStream_t cap_stream = nullptr;
+        JobDev* h_job = nullptr;      // pinned staging read by the graph
+        SceneDev* h_scene = nullptr;  // pinned
+        int32_t* h_rxjob = nullptr;   // pinned [n_rx]
+        int32_t h_rxjob_cap = 0;
+    } graph;
 };
 
 struct sbr_scene {
     sbr_context* ctx = nullptr;
+    uint64_t id = 0;  // unique per upload (keys captured graphs)
     int64_t T = 0;
     int32_t F = 0, M = 0;
     std::vector<double> tri_v;  // [T][9]
@@ -100,6 +124,13 @@ struct sbr_scene {
 };
 
 namespace {
+
+void drop_graph(sbr_context* c)
+{
+    if (c->graph.exec) (void)hipGraphExecDestroy(c->graph.exec);
+    c->graph.exec = nullptr;
+    c->graph.valid = false;
+}
 
 sbr_status fail(sbr_context* c, sbr_status st, const char* fmt, ...)
     __attribute__((format(printf, 3, 4)));
@@ -229,7 +260,7 @@ sbr_status check_params(sbr_context* c, const sbr_trace_params* p)
         return fail(c, SBR_E_INVALID_ARG, "freq_hz must be finite and > 0");
     if (!isfinite(p->tx_power_dbm) || !isfinite(p->target_err_deg) || p->target_err_deg >= 45.0)
         return fail(c, SBR_E_INVALID_ARG, "tx_power_dbm / target_err_deg out of range");
-    if (p->flags & ~(SBR_FLAG_KEEP_INVALID | SBR_FLAG_FRESH_GRID))
+    if (p->flags & ~(SBR_FLAG_KEEP_INVALID | SBR_FLAG_FRESH_GRID | SBR_FLAG_GRAPH))
         return fail(c, SBR_E_INVALID_ARG, "unknown flags");
     if (p->launch < SBR_LAUNCH_EQUIANGULAR || p->launch > SBR_LAUNCH_EQUIDISTANT_OCTA)
         return fail(c, SBR_E_INVALID_ARG, "unknown launch method %d", p->launch);
@@ -544,7 +575,7 @@ sbr_status run_paths(sbr_context* c, Call& call, sbr_path* out, int64_t capacity
         // counts come back in one round trip
         HIPCHK(c, ensure(c->outp, sizeof(sbr_path) * U1));
         HIPCHK(c, launch_emit_small(c->paths.as<sbr_path>(), c->keep.as<int32_t>(), Umax, ndev,
-                                    c->outp.as<sbr_path>(), &dc->n_paths, st));
+                                    c->outp.as<sbr_path>(), (int64_t)U1, &dc->n_paths, st));
         r = ensure_host_paths(c, (int64_t)U1);
         if (r) return r;
         if (Umax > 0 && !out_on_device)
@@ -793,6 +824,11 @@ sbr_status sbr_context_destroy(sbr_context* c)
         if (ev) (void)hipEventDestroy(ev);
     if (c->host_ctr) (void)hipHostFree(c->host_ctr);
     if (c->host_paths) (void)hipHostFree(c->host_paths);
+    drop_graph(c);
+    if (c->graph.cap_stream) (void)hipStreamDestroy(c->graph.cap_stream);
+    if (c->graph.h_job) (void)hipHostFree(c->graph.h_job);
+    if (c->graph.h_scene) (void)hipHostFree(c->graph.h_scene);
+    if (c->graph.h_rxjob) (void)hipHostFree(c->graph.h_rxjob);
     delete c;
     return SBR_OK;
 }
@@ -814,8 +850,10 @@ sbr_status sbr_scene_upload(sbr_context* c, const double* xyz, int64_t nv, const
     for (int32_t m = 0; m < M; ++m)
         if (!isfinite(eps_r[m].re) || !isfinite(eps_r[m].im))
             return fail(c, SBR_E_INVALID_ARG, "eps_r[%d] not finite", m);
+    static uint64_t next_scene_id = 0;
     sbr_scene* s = new sbr_scene();
     s->ctx = c;
+    s->id = ++next_scene_id;
     s->T = T;
     s->M = M;
     s->tri_v.resize((size_t)T * 9);
@@ -1108,6 +1146,202 @@ sbr_status sbr_trace(sbr_scene* s, const double tx[3], const double* rx, int32_t
     return run_paths(c, call, out, capacity, n_out, stats);
 }
 
+// ---------------------------------------------------------------------------
+// Captured graphs of sbr_trace_device calls (SBR_FLAG_GRAPH).  A call whose
+// scene, receiver and output buffers, parameters and tuning match the
+// captured one replays the graph: the job table (the transmitter and what
+// depends on it) is written to pinned staging that the graph copies to the
+// device, everything else is fixed at capture.  The graph holds the one-
+// workgroup path test 1 and emit, sized by the capturing call; a replay whose
+// counts exceed those sizes is detected from the counters and redone as a
+// normal call.  Memory is cleared by kernels, not memset nodes.
+// ---------------------------------------------------------------------------
+namespace {
+
+bool same_tuning(const sbr_context* c, const sbr_tuning& t)
+{
+    sbr_tuning now;
+    (void)sbr_context_get_tuning(c, &now);
+    return memcmp(&now, &t, sizeof(now)) == 0;
+}
+
+bool graph_matches(const sbr_context* c, const sbr_scene* s, const double* rx, int32_t n_rx,
+                   const sbr_trace_params* p, const sbr_path* out, int64_t capacity)
+{
+    const auto& G = c->graph;
+    return G.valid && G.epoch == g_alloc_epoch && G.scene_id == s->id && G.rx == rx &&
+           G.n_rx == n_rx && G.out == out && G.capacity == capacity &&
+           memcmp(&G.params, p, sizeof(*p)) == 0 && same_tuning(c, G.tuning);
+}
+
+// Build the job of a call without launching anything (the launch grid
+// already exists: the capturing call created it).
+sbr_status graph_job(sbr_context* c, sbr_scene* s, const double* tx, int32_t n_rx,
+                     const sbr_trace_params* p, Call& call)
+{
+    sbr_trace_params q = *p;
+    q.flags &= ~(SBR_FLAG_FRESH_GRID | SBR_FLAG_GRAPH);
+    call.scenes.push_back(s);
+    call.rx = nullptr;
+    call.n_rx = n_rx;
+    call.rx_job.assign((size_t)n_rx, 0);
+    call.chunk = c->trace_chunk;
+    return add_job(c, call, 0, tx, 0, n_rx, &q, 0, num_rays(p->launch, p->division_n));
+}
+
+// Capture the whole pipeline of the call described by `call` (one job, no
+// receiver tree) into c->graph.  Buffers are sized first: nothing is
+// allocated while capturing.
+sbr_status capture_graph(sbr_context* c, sbr_scene* s, Call& call, const double* rx_dev,
+                         const sbr_trace_params* p, sbr_path* out, int64_t capacity,
+                         int64_t u_cap)
+{
+    auto& G = c->graph;
+    const int32_t n_rx = call.n_rx;
+    if (!G.cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&G.cap_stream, hipStreamNonBlocking));
+    if (!G.h_job) HIPCHK(c, hipHostMalloc((void**)&G.h_job, sizeof(JobDev), 0));
+    if (!G.h_scene) HIPCHK(c, hipHostMalloc((void**)&G.h_scene, sizeof(SceneDev), 0));
+    if (G.h_rxjob_cap < std::max(n_rx, 1)) {
+        if (G.h_rxjob) (void)hipHostFree(G.h_rxjob);
+        G.h_rxjob = nullptr;
+        G.h_rxjob_cap = 0;
+        HIPCHK(c, hipHostMalloc((void**)&G.h_rxjob, sizeof(int32_t) * (size_t)std::max(n_rx, 1), 0));
+        G.h_rxjob_cap = std::max(n_rx, 1);
+    }
+    *G.h_job = call.jobs[0];
+    *G.h_scene = scene_dev(s);
+    for (int32_t x = 0; x < n_rx; ++x) G.h_rxjob[x] = 0;
+    const size_t U1 = (size_t)u_cap;
+    HIPCHK(c, ensure(c->d_jobs, sizeof(JobDev)));
+    HIPCHK(c, ensure(c->d_scenes, sizeof(SceneDev)));
+    HIPCHK(c, ensure(c->rx, sizeof(double) * 3 * (size_t)std::max(n_rx, 1)));
+    HIPCHK(c, ensure(c->d_rxjob, sizeof(int32_t) * (size_t)std::max(n_rx, 1)));
+    HIPCHK(c, ensure(c->counters, sizeof(Counters)));
+    HIPCHK(c, ensure(c->cand, sizeof(sbr_candidate) * (size_t)kSmallEvents));
+    HIPCHK(c, ensure(c->uniq, sizeof(sbr_candidate) * (size_t)kSmallEvents));
+    HIPCHK(c, ensure(c->refine, sizeof(RefineOut) * U1));
+    HIPCHK(c, ensure(c->geom, sizeof(PathGeom) * U1));
+    HIPCHK(c, ensure(c->paths, sizeof(sbr_path) * U1));
+    HIPCHK(c, ensure(c->keep, sizeof(int32_t) * U1));
+    GridDev g;
+    bool built = false;
+    sbr_status r = get_grid(c, p->launch, p->division_n, &g, &built);
+    if (r) return r;
+    if (p->flags & SBR_FLAG_FRESH_GRID) HIPCHK(c, ensure(c->grid_scratch, grid_scratch_bytes(p->division_n)));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+
+    call.dev.jobs = c->d_jobs.as<const JobDev>();
+    call.dev.scenes = c->d_scenes.as<const SceneDev>();
+    call.dev.rx = c->rx.as<const double>();
+    call.dev.rx_job = c->d_rxjob.as<const int32_t>();
+    call.dev.rx_nodes = nullptr;
+    call.dev.rx_perm = nullptr;
+    call.dev.n_jobs = 1;
+    call.dev.chunk = call.chunk;
+    call.dev.n_packets = call.n_packets;
+    call.s0 = *G.h_scene;
+    call.lp = plan_for(s, c->trace_block);
+    LdsPlan lp256 = plan_for(s, 256);
+    lp256.block = 256;
+    Counters* dc = c->counters.as<Counters>();
+    const hipStream_t st = G.cap_stream;
+    const int depth = u_cap <= c->lookahead_max_paths ? c->lookahead_depth : 1;
+
+    HIPCHK(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    auto step = [&](hipError_t x) {
+        if (e == hipSuccess) e = x;
+    };
+    step(hipMemcpyAsync(c->d_jobs.p, G.h_job, sizeof(JobDev), hipMemcpyHostToDevice, st));
+    step(hipMemcpyAsync(c->d_scenes.p, G.h_scene, sizeof(SceneDev), hipMemcpyHostToDevice, st));
+    if (n_rx > 0) {
+        step(hipMemcpyAsync(c->rx.p, rx_dev, sizeof(double) * 3 * (size_t)n_rx,
+                            hipMemcpyDeviceToDevice, st));
+        step(hipMemcpyAsync(c->d_rxjob.p, G.h_rxjob, sizeof(int32_t) * (size_t)n_rx,
+                            hipMemcpyHostToDevice, st));
+    }
+    step(launch_zero(c->counters.p, sizeof(Counters), st));
+    if (p->flags & SBR_FLAG_FRESH_GRID) step(launch_grid(g, st, c->grid_scratch.p));
+    step(launch_trace(call.dev, call.lp, call.s0, trace_blocks(c, call), &dc->queue,
+                      c->cand.as<sbr_candidate>(), kSmallEvents, &dc->cand, nullptr, nullptr,
+                      &dc->err, st));
+    step(launch_dedup_small(c->cand.as<sbr_candidate>(), kSmallEvents, c->uniq.as<sbr_candidate>(),
+                            &dc->n_unique, st, &dc->cand));
+    step(launch_refine(call.dev, lp256, call.s0, c->uniq.as<sbr_candidate>(), u_cap, &dc->n_unique,
+                       depth, c->refine.as<RefineOut>(), c->geom.as<PathGeom>(), &dc->err, st));
+    step(launch_solve(call.dev, lp256, call.s0, c->uniq.as<sbr_candidate>(),
+                      c->refine.as<RefineOut>(), c->geom.as<const PathGeom>(), u_cap, &dc->n_unique,
+                      c->paths.as<sbr_path>(), c->keep.as<int32_t>(), &dc->err, st));
+    step(launch_emit_small(c->paths.as<sbr_path>(), c->keep.as<int32_t>(), u_cap, &dc->n_unique,
+                           out, capacity, &dc->n_paths, st));
+    step(hipMemcpyAsync(c->host_ctr, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(st, &graph);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        G.exec = nullptr;
+        return fail(c, SBR_E_DEVICE, "graph capture: %s", hipGetErrorString(e));
+    }
+    G.valid = true;
+    G.epoch = g_alloc_epoch;
+    G.scene_id = s->id;
+    G.rx = rx_dev;
+    G.n_rx = n_rx;
+    G.out = out;
+    G.capacity = capacity;
+    G.u_cap = u_cap;
+    G.n_rays = call.n_rays;
+    G.params = *p;
+    (void)sbr_context_get_tuning(c, &G.tuning);
+    return SBR_OK;
+}
+
+// Replay the captured graph for transmitter tx.  Returns SBR_OK with
+// *replayed false when the counts overflowed the captured sizes (the caller
+// then runs the call normally).
+sbr_status replay_graph(sbr_context* c, sbr_scene* s, const double* tx, int32_t n_rx,
+                        const sbr_trace_params* p, int64_t capacity, int64_t* n_out,
+                        sbr_trace_stats* stats, bool* replayed)
+{
+    auto& G = c->graph;
+    *replayed = false;
+    Call call;
+    sbr_status r = graph_job(c, s, tx, n_rx, p, call);
+    if (r) return r;
+    *G.h_job = call.jobs[0];
+    HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
+    HIPCHK(c, hipGraphLaunch(G.exec, c->stream));
+    HIPCHK(c, hipEventRecord(c->ev[6], c->stream));
+    HIPCHK(c, hipEventSynchronize(c->ev[6]));
+    const Counters* hc = c->host_ctr;
+    if (hc->err) return fail(c, SBR_E_INTERNAL, "traversal stack overflow");
+    if (hc->cand > (unsigned long long)kSmallEvents || hc->n_unique > G.u_cap) {
+        drop_graph(c);
+        return SBR_OK;
+    }
+    *replayed = true;
+    *n_out = hc->n_paths;
+    if (stats) {
+        memset(stats, 0, sizeof(*stats));
+        stats->n_rays = G.n_rays;
+        stats->n_candidates = (int64_t)hc->cand;
+        stats->n_unique = hc->n_unique;
+        stats->n_paths = hc->n_paths;
+        float tot = 0;
+        (void)hipEventElapsedTime(&tot, c->ev[0], c->ev[6]);
+        stats->ms_total = tot;
+        stats->lds_max = c->lds_max;
+    }
+    if (hc->n_paths > capacity)
+        return fail(c, SBR_E_CAPACITY, "%d paths, capacity %lld", hc->n_paths,
+                    (long long)capacity);
+    return SBR_OK;
+}
+
+}  // namespace
+
 sbr_status sbr_trace_device(sbr_scene* s, const double tx[3], const double* rx, int32_t n_rx,
                             const sbr_trace_params* p, sbr_path* out, int64_t capacity,
                             int64_t* n_out, sbr_trace_stats* stats)
@@ -1117,6 +1351,12 @@ sbr_status sbr_trace_device(sbr_scene* s, const double tx[3], const double* rx, 
     sbr_context* c = s->ctx;
     if (n_rx < 0 || (n_rx > 0 && !rx)) return fail(c, SBR_E_INVALID_ARG, "bad rx array");
     HIPCHK(c, hipSetDevice(c->device));
+    const bool want_graph = (p->flags & SBR_FLAG_GRAPH) != 0 && n_rx < c->rx_tree_min;
+    if (want_graph && graph_matches(c, s, rx, n_rx, p, out, capacity)) {
+        bool replayed = false;
+        r = replay_graph(c, s, tx, n_rx, p, capacity, n_out, stats, &replayed);
+        if (r || replayed) return r;
+    }
     // The receiver tree is built on the host: read the receivers back once
     // when the job is large enough to use it.
     std::vector<double> rx_host;
@@ -1132,7 +1372,17 @@ sbr_status sbr_trace_device(sbr_scene* s, const double tx[3], const double* rx, 
     if (r) return r;
     r = run_front(c, call, true, nullptr, nullptr, nullptr);
     if (r) return r;
-    return run_paths(c, call, out, capacity, n_out, stats, true);
+    r = run_paths(c, call, out, capacity, n_out, stats, true);
+    if (r || !want_graph || !call.small) return r;
+    // capture for the next calls of this shape, with room for twice this
+    // call's paths
+    drop_graph(c);
+    const int64_t u_cap =
+        std::min<int64_t>(kSmallEvents, std::max<int64_t>(64, 2 * (int64_t)c->host_ctr->n_unique));
+    Call cap;
+    r = graph_job(c, s, tx, n_rx, p, cap);
+    if (r) return r;
+    return capture_graph(c, s, cap, rx, p, out, capacity, u_cap);
 }
 
 sbr_status sbr_trace_batch(sbr_context* c, sbr_scene* const* scenes, int32_t n_scenes,

@@ -214,10 +214,15 @@ hipError_t launch_gather_sorted(const sbr_candidate* cand, const uint32_t* idx, 
 // Up to kSmallEvents reception events, path test 1 and the final compaction
 // run in one workgroup each and leave their counts on the device.
 constexpr int kSmallEvents = 4096;
+// With n_dev the event count is min(n, *n_dev), read on the device.
 hipError_t launch_dedup_small(const sbr_candidate* C, int64_t n, sbr_candidate* U,
-                              int32_t* n_unique, hipStream_t s);
+                              int32_t* n_unique, hipStream_t s,
+                              const unsigned long long* n_dev = nullptr);
 hipError_t launch_emit_small(const sbr_path* paths, const int32_t* keep, int64_t U_max,
-                             const int32_t* n_dev, sbr_path* out, int32_t* n_paths, hipStream_t s);
+                             const int32_t* n_dev, sbr_path* out, int64_t capacity,
+                             int32_t* n_paths, hipStream_t s);
+// Zero `bytes` (a multiple of 4) with a kernel.
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 
 // Differentiable path quantities (grad.hip); all pointers are device memory.
 struct GradArgs {

@@ -274,12 +274,15 @@ namespace sbr {
 // the winners, in sorted order; writes the number of unique paths to
 // *n_unique.
 __global__ __launch_bounds__(1024) void k_dedup_small(const sbr_candidate* __restrict__ C,
-                                                      int32_t n, sbr_candidate* __restrict__ U,
+                                                      int32_t n_max,
+                                                      const unsigned long long* __restrict__ n_dev,
+                                                      sbr_candidate* __restrict__ U,
                                                       int32_t* __restrict__ n_unique)
 {
     __shared__ uint32_t idx[kSmallEvents];
     __shared__ int32_t part[1024];
     const int t = threadIdx.x;
+    const int n = n_dev ? (int)min((unsigned long long)n_max, *n_dev) : n_max;
     int P = 1;
     while (P < n) P <<= 1;
     for (int i = t; i < P; i += 1024) idx[i] = i < n ? (uint32_t)i : 0xffffffffu;
@@ -323,18 +326,19 @@ __global__ __launch_bounds__(1024) void k_dedup_small(const sbr_candidate* __res
 }
 
 hipError_t launch_dedup_small(const sbr_candidate* C, int64_t n, sbr_candidate* U,
-                              int32_t* n_unique, hipStream_t s)
+                              int32_t* n_unique, hipStream_t s, const unsigned long long* n_dev)
 {
-    hipLaunchKernelGGL(k_dedup_small, dim3(1), dim3(1024), 0, s, C, (int32_t)n, U, n_unique);
+    hipLaunchKernelGGL(k_dedup_small, dim3(1), dim3(1024), 0, s, C, (int32_t)n, n_dev, U, n_unique);
     return hipGetLastError();
 }
 
 // Stable compaction of the kept paths (path test 2) of the first
-// min(U_max, *n_dev) records; writes the count to *n_paths.
+// min(U_max, *n_dev) records; writes the count to *n_paths, and the records
+// to out only when they fit in its capacity.
 __global__ __launch_bounds__(1024) void k_emit_small(const sbr_path* __restrict__ paths,
                                                      const int32_t* __restrict__ keep,
                                                      int32_t U_max, const int32_t* __restrict__ n_dev,
-                                                     sbr_path* __restrict__ out,
+                                                     sbr_path* __restrict__ out, int64_t capacity,
                                                      int32_t* __restrict__ n_paths)
 {
     __shared__ int32_t part[1024];
@@ -356,17 +360,35 @@ __global__ __launch_bounds__(1024) void k_emit_small(const sbr_path* __restrict_
         __syncthreads();
     }
     int run = part[t] - sum;
+    if ((int64_t)part[1023] <= capacity) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-        if (h[q]) out[run++] = paths[4 * t + q];
+        for (int q = 0; q < 4; ++q)
+            if (h[q]) out[run++] = paths[4 * t + q];
+    }
     if (t == 1023) *n_paths = part[1023];
 }
 
 hipError_t launch_emit_small(const sbr_path* paths, const int32_t* keep, int64_t U_max,
-                             const int32_t* n_dev, sbr_path* out, int32_t* n_paths, hipStream_t s)
+                             const int32_t* n_dev, sbr_path* out, int64_t capacity,
+                             int32_t* n_paths, hipStream_t s)
 {
     hipLaunchKernelGGL(k_emit_small, dim3(1), dim3(1024), 0, s, paths, keep, (int32_t)U_max, n_dev,
-                       out, n_paths);
+                       out, capacity, n_paths);
+    return hipGetLastError();
+}
+
+// Zero n 32-bit words (a kernel, so that it can sit in a captured graph).
+__global__ void k_zero(uint32_t* __restrict__ p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s)
+{
+    const int64_t n = (int64_t)(bytes / 4);
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (uint32_t*)p, n);
     return hipGetLastError();
 }
 

@@ -31,6 +31,7 @@ E_INTERNAL = -7
 
 FLAG_KEEP_INVALID = 1
 FLAG_FRESH_GRID = 2
+FLAG_GRAPH = 4
 PATH_STALLED = 1
 PATH_INVALID = 2
 PATH_TARGET_MET = 4
@@ -196,8 +197,9 @@ def num_rays(n: int, launch: int = EQUIANGULAR) -> int:
 
 def make_params(max_order=3, division_n=20, iterations=3, subrays=6, target_err_deg=0.0,
                 freq_hz=28e9, tx_power_dbm=0.0, keep_invalid=False, fresh_grid=False,
-                launch=EQUIANGULAR):
-    flags = (FLAG_KEEP_INVALID if keep_invalid else 0) | (FLAG_FRESH_GRID if fresh_grid else 0)
+                launch=EQUIANGULAR, graph=False):
+    flags = (FLAG_KEEP_INVALID if keep_invalid else 0) | (FLAG_FRESH_GRID if fresh_grid else 0) | \
+        (FLAG_GRAPH if graph else 0)
     return TraceParams(max_order, division_n, iterations, subrays, target_err_deg, freq_hz,
                        tx_power_dbm, flags, launch)
 
