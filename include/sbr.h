@@ -143,21 +143,22 @@ typedef struct {
  * (256 lanes per workgroup).
  * With at most lookahead_max_paths paths the refinement resolves
  * lookahead_depth iterations per traversal step (3: a 512-lane workgroup per
- * path, used without an LDS plan; 2: one wave per path); otherwise, or with
- * depth 1, one iteration per step with eight lanes per path.  A job with at least
- * rx_tree_min receivers tests reception through a ball tree over its
- * receivers (a conservative cull before the exact test of eq. (3)) instead of
- * testing every receiver on every segment. */
+ * path, used without an LDS plan and for at most lookahead3_max_paths paths,
+ * since it traces 399 sub-rays per path and step; 2: one wave per path);
+ * otherwise, or with depth 1, one iteration per step with eight lanes per
+ * path.  A job with at least rx_tree_min receivers tests reception through
+ * a ball tree over its receivers (a conservative cull before the exact test
+ * of eq. (3)) instead of testing every receiver on every segment. */
 typedef struct {
     int32_t trace_chunk;         /* 1..64                                   */
     int32_t persist_blocks;      /* >= 1                                    */
     int32_t trace_block;         /* 64..256, multiple of 64 (LDS staging)   */
-    int32_t stack_depth;         /* 0..64                                   */
+    int32_t stack_depth;         /* 0..96                                   */
     int32_t lds_budget;          /* bytes, 0..device limit per workgroup    */
     int32_t rx_tree_min;         /* >= 1                                    */
     int64_t lookahead_max_paths; /* >= 0                                    */
     int32_t lookahead_depth;     /* 1..3                                    */
-    int32_t reserved;            /* must be 0                               */
+    int32_t lookahead3_max_paths; /* >= 0                                   */
 } sbr_tuning;
 
 sbr_status sbr_context_get_tuning(const sbr_context* ctx, sbr_tuning* out);

@@ -87,6 +87,7 @@ struct sbr_context {
     int32_t trace_chunk = 1, persist_blocks = 2048;
     int32_t rx_tree_min = 64;
     int32_t lookahead_depth = 3;
+    int32_t lookahead3_max_paths = 256;
     // one captured graph of a sbr_trace_device call (SBR_FLAG_GRAPH)
     struct Graph {
         bool valid = false;
@@ -453,6 +454,15 @@ int trace_blocks(const sbr_context* c, const Call& call)
     return (int)std::max<int64_t>(1, std::min<int64_t>(want, c->persist_blocks));
 }
 
+// Iterations per refinement step for U paths: three only for few paths
+// (latency-bound), two up to lookahead_max_paths, else one.
+int refine_depth(const sbr_context* c, int64_t U)
+{
+    if (U > c->lookahead_max_paths) return 1;
+    if (c->lookahead_depth >= 3 && U > c->lookahead3_max_paths) return 2;
+    return c->lookahead_depth;
+}
+
 // Launch, trace and reception, then path test 1.  On return the context
 // holds cand (n_cand events) and, with need_unique, uniq (the path-test-1
 // winners, n_uniq or -- small -- a count on the device).  Without
@@ -553,7 +563,7 @@ sbr_status run_paths(sbr_context* c, Call& call, sbr_path* out, int64_t capacity
     HIPCHK(c, ensure(c->geom, sizeof(PathGeom) * U1));
     LdsPlan lp256 = call.scenes.size() == 1 ? plan_for(call.scenes[0], 256) : LdsPlan{};
     lp256.block = 256;
-    const int depth = Umax <= c->lookahead_max_paths ? c->lookahead_depth : 1;
+    const int depth = refine_depth(c, Umax);
     HIPCHK(c, launch_refine(call.dev, lp256, call.s0, c->uniq.as<sbr_candidate>(), Umax, ndev,
                             depth, c->refine.as<RefineOut>(), c->geom.as<PathGeom>(),
                             &dc->err, st));
@@ -758,6 +768,7 @@ sbr_status sbr_context_create(int32_t device, void* hip_stream, sbr_context** ou
         c->persist_blocks = env_int("SBR_TRACE_BLOCKS", 2048, 1, 1 << 20);
         c->rx_tree_min = env_int("SBR_RX_TREE_MIN", 64, 1, 0x7fffffff);
         c->lookahead_depth = env_int("SBR_LOOKAHEAD_DEPTH", 3, 1, 3);
+        c->lookahead3_max_paths = env_int("SBR_LOOKAHEAD3_PATHS", 256, 0, 1 << 30);
     }
     if (e != hipSuccess) {
         g_create_err = std::string("context setup: ") + hipGetErrorString(e);
@@ -781,7 +792,7 @@ sbr_status sbr_context_get_tuning(const sbr_context* c, sbr_tuning* t)
     t->rx_tree_min = c->rx_tree_min;
     t->lookahead_max_paths = c->lookahead_max_paths;
     t->lookahead_depth = c->lookahead_depth;
-    t->reserved = 0;
+    t->lookahead3_max_paths = c->lookahead3_max_paths;
     return SBR_OK;
 }
 
@@ -794,7 +805,7 @@ sbr_status sbr_context_set_tuning(sbr_context* c, const sbr_tuning* t)
         t->trace_block < 64 || t->trace_block > 256 || t->trace_block % 64 != 0 ||
         t->stack_depth < 0 || t->stack_depth > kTraceStack || t->lds_budget < 0 ||
         t->lds_budget > c->lds_max || t->rx_tree_min < 1 || t->lookahead_max_paths < 0 ||
-        t->lookahead_depth < 1 || t->lookahead_depth > 3 || t->reserved != 0)
+        t->lookahead_depth < 1 || t->lookahead_depth > 3 || t->lookahead3_max_paths < 0)
         return fail(c, SBR_E_INVALID_ARG, "tuning field out of range");
     c->trace_chunk = t->trace_chunk;
     c->persist_blocks = t->persist_blocks;
@@ -804,6 +815,7 @@ sbr_status sbr_context_set_tuning(sbr_context* c, const sbr_tuning* t)
     c->rx_tree_min = t->rx_tree_min;
     c->lookahead_max_paths = t->lookahead_max_paths;
     c->lookahead_depth = t->lookahead_depth;
+    c->lookahead3_max_paths = t->lookahead3_max_paths;
     return SBR_OK;
 }
 
@@ -1245,7 +1257,7 @@ sbr_status capture_graph(sbr_context* c, sbr_scene* s, Call& call, const double*
     lp256.block = 256;
     Counters* dc = c->counters.as<Counters>();
     const hipStream_t st = G.cap_stream;
-    const int depth = u_cap <= c->lookahead_max_paths ? c->lookahead_depth : 1;
+    const int depth = refine_depth(c, u_cap);
 
     HIPCHK(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;

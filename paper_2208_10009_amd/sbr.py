@@ -70,10 +70,10 @@ class Tuning(C.Structure):
                 ("trace_block", C.c_int32), ("stack_depth", C.c_int32),
                 ("lds_budget", C.c_int32), ("rx_tree_min", C.c_int32),
                 ("lookahead_max_paths", C.c_int64), ("lookahead_depth", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("lookahead3_max_paths", C.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class Complex(C.Structure):

@@ -288,7 +288,8 @@ def test_refine_lookahead_matches_single_step(gpu, orc, prm):
     full = dict(cfg["params"], division_n=80, **prm)
     a = _trace_with_env({"SBR_LOOKAHEAD_PATHS": "0"}, cfg, **full)
     b = _trace_with_env({"SBR_LOOKAHEAD_PATHS": "100000", "SBR_LOOKAHEAD_DEPTH": "2"}, cfg, **full)
-    c = _trace_with_env({"SBR_LOOKAHEAD_PATHS": "100000", "SBR_LOOKAHEAD_DEPTH": "3"}, cfg, **full)
+    c = _trace_with_env({"SBR_LOOKAHEAD_PATHS": "100000", "SBR_LOOKAHEAD_DEPTH": "3",
+                         "SBR_LOOKAHEAD3_PATHS": "100000"}, cfg, **full)
     assert a.tobytes() == b.tobytes() == c.tobytes()
     o = orc.run(cfg["scene"], cfg["tx"], cfg["rx"], **full)["paths"]
     _compare_paths(a, o)
