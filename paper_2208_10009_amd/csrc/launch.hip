@@ -105,6 +105,8 @@ __device__ static d3 proj_face(d3 p, d3 g)
 // a - a0 ~ 1e-16 (exact in binary64), likewise for b; the neglected terms are
 // below 1e-31 relative, so each value rounds as the exact one does (the
 // results are checked bit for bit against the correctly rounded grid).
+// The role is the wave index (lane = side, 60 of 64 lanes busy), so no wave
+// runs the cosine and the sine series one after the other.
 // The side angles are kept for k_grid_dirs.
 __global__ __launch_bounds__(192) void k_grid_setup(int32_t n, char* scratch)
 {
@@ -132,7 +134,8 @@ __global__ __launch_bounds__(192) void k_grid_setup(int32_t n, char* scratch)
         d3 A = sh.V[sh.f[f60][0]], B = sh.V[sh.f[f60][1]], C = sh.V[sh.f[f60][2]];
         g = add(add(A, B), C);
     }
-    const int side = t / 3, role = t % 3;
+    const int side = t & 63, role = t >> 6;
+    const bool act = side < 60;
     const int fs = side / 3, ss = side % 3;
     const size_t cap3 = 3 * (size_t)ring_cap(n);
     int64_t m = n;
@@ -141,7 +144,7 @@ __global__ __launch_bounds__(192) void k_grid_setup(int32_t n, char* scratch)
         // corners are W.
         d3 Pa = mk(0.0, 0.0, 0.0), Pb = Pa;
         double x = 0.0, y0 = 0.0, a0 = 0.0, b0 = 0.0;
-        if (t < 180) {
+        if (act) {
             Pa = W[fs][ss];
             Pb = W[fs][(ss + 1) % 3];
             x = dot(Pa, Pb);
@@ -156,7 +159,7 @@ __global__ __launch_bounds__(192) void k_grid_setup(int32_t n, char* scratch)
         }
         __syncthreads();
         double th = 0.0;
-        if (t < 180) {
+        if (act) {
             const dd r = dd_sub(SV[side][0], dd{x, 0.0});
             const dd y = dd_add(dd{y0, 0.0}, dd{r.hi / CV[side][0], 0.0});
             th = y.hi + y.lo;
@@ -175,7 +178,7 @@ __global__ __launch_bounds__(192) void k_grid_setup(int32_t n, char* scratch)
             }
             break;
         }
-        if (t < 180 && role > 0) {
+        if (act && role > 0) {
             // role 1: sin b with b = (m-1) th / m; role 2: sin a with a = th / m
             const double v = role == 1 ? ((double)(m - 1) * th) / (double)m
                                        : ((double)1 * th) / (double)m;
@@ -186,7 +189,7 @@ __global__ __launch_bounds__(192) void k_grid_setup(int32_t n, char* scratch)
             SN[side][role == 2 ? 0 : 1] = r.hi + r.lo;
         }
         __syncthreads();
-        if (t < 180 && role < 2) {
+        if (act && role < 2) {
             const double sa = SN[side][0], sb = SN[side][1];
             // role 0: step 1 from corner ss toward ss+1; role 1: step m-1 of
             // the same side, the last step into corner ss+1
