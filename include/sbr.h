@@ -148,7 +148,11 @@ typedef struct {
  * otherwise, or with depth 1, one iteration per step with eight lanes per
  * path.  A job with at least rx_tree_min receivers tests reception through
  * a ball tree over its receivers (a conservative cull before the exact test
- * of eq. (3)) instead of testing every receiver on every segment. */
+ * of eq. (3)) instead of testing every receiver on every segment.  The
+ * equiangular grid's setup takes a value from short series when its error
+ * bound, scaled by 2^grid_check_log2, proves the rounding, and otherwise
+ * recomputes that layer with the full series (same grid; larger values only
+ * send more layers through the full series). */
 typedef struct {
     int32_t trace_chunk;         /* 1..64                                   */
     int32_t persist_blocks;      /* >= 1                                    */
@@ -159,6 +163,7 @@ typedef struct {
     int64_t lookahead_max_paths; /* >= 0                                    */
     int32_t lookahead_depth;     /* 1..3                                    */
     int32_t lookahead3_max_paths; /* >= 0                                   */
+    int32_t grid_check_log2;     /* 0..200                                  */
 } sbr_tuning;
 
 sbr_status sbr_context_get_tuning(const sbr_context* ctx, sbr_tuning* out);

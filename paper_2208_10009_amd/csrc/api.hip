@@ -88,6 +88,7 @@ struct sbr_context {
     int32_t rx_tree_min = 64;
     int32_t lookahead_depth = 3;
     int32_t lookahead3_max_paths = 256;
+    int32_t grid_check_log2 = 0;
     // one captured graph of a sbr_trace_device call (SBR_FLAG_GRAPH)
     struct Graph {
         bool valid = false;
@@ -170,7 +171,7 @@ sbr_status get_grid(sbr_context* c, int32_t launch, int32_t n, GridDev* g, bool*
     if (it != c->grids.end() && fresh) {
         HIPCHK(c, ensure(c->grid_scratch, grid_scratch_bytes(n)));
         GridDev gd{it->second.as<double>(), N, n, launch};
-        HIPCHK(c, launch_grid(gd, c->stream, c->grid_scratch.p));
+        HIPCHK(c, launch_grid(gd, c->stream, c->grid_scratch.p, c->grid_check_log2));
         *built = true;
     }
     if (it == c->grids.end()) {
@@ -178,7 +179,7 @@ sbr_status get_grid(sbr_context* c, int32_t launch, int32_t n, GridDev* g, bool*
         HIPCHK(c, ensure(b, sizeof(double) * 3 * (size_t)N));
         HIPCHK(c, ensure(c->grid_scratch, grid_scratch_bytes(n)));
         GridDev gd{b.as<double>(), N, n, launch};
-        hipError_t e = launch_grid(gd, c->stream, c->grid_scratch.p);
+        hipError_t e = launch_grid(gd, c->stream, c->grid_scratch.p, c->grid_check_log2);
         if (e != hipSuccess) {
             release(b);
             return fail(c, SBR_E_DEVICE, "launch grid: %s", hipGetErrorString(e));
@@ -793,6 +794,7 @@ sbr_status sbr_context_get_tuning(const sbr_context* c, sbr_tuning* t)
     t->lookahead_max_paths = c->lookahead_max_paths;
     t->lookahead_depth = c->lookahead_depth;
     t->lookahead3_max_paths = c->lookahead3_max_paths;
+    t->grid_check_log2 = c->grid_check_log2;
     return SBR_OK;
 }
 
@@ -805,8 +807,15 @@ sbr_status sbr_context_set_tuning(sbr_context* c, const sbr_tuning* t)
         t->trace_block < 64 || t->trace_block > 256 || t->trace_block % 64 != 0 ||
         t->stack_depth < 0 || t->stack_depth > kTraceStack || t->lds_budget < 0 ||
         t->lds_budget > c->lds_max || t->rx_tree_min < 1 || t->lookahead_max_paths < 0 ||
-        t->lookahead_depth < 1 || t->lookahead_depth > 3 || t->lookahead3_max_paths < 0)
+        t->lookahead_depth < 1 || t->lookahead_depth > 3 || t->lookahead3_max_paths < 0 ||
+        t->grid_check_log2 < 0 || t->grid_check_log2 > 200)
         return fail(c, SBR_E_INVALID_ARG, "tuning field out of range");
+    if (t->grid_check_log2 != c->grid_check_log2) {
+        // cached grids were made under the old setting (they are the same
+        // values; dropping them lets the next call exercise the new one)
+        for (auto& kv : c->grids) release(kv.second);
+        c->grids.clear();
+    }
     c->trace_chunk = t->trace_chunk;
     c->persist_blocks = t->persist_blocks;
     c->trace_block = t->trace_block;
@@ -816,6 +825,7 @@ sbr_status sbr_context_set_tuning(sbr_context* c, const sbr_tuning* t)
     c->lookahead_max_paths = t->lookahead_max_paths;
     c->lookahead_depth = t->lookahead_depth;
     c->lookahead3_max_paths = t->lookahead3_max_paths;
+    c->grid_check_log2 = t->grid_check_log2;
     return SBR_OK;
 }
 
@@ -1273,7 +1283,8 @@ sbr_status capture_graph(sbr_context* c, sbr_scene* s, Call& call, const double*
                             hipMemcpyHostToDevice, st));
     }
     step(launch_zero(c->counters.p, sizeof(Counters), st));
-    if (p->flags & SBR_FLAG_FRESH_GRID) step(launch_grid(g, st, c->grid_scratch.p));
+    if (p->flags & SBR_FLAG_FRESH_GRID)
+        step(launch_grid(g, st, c->grid_scratch.p, c->grid_check_log2));
     step(launch_trace(call.dev, call.lp, call.s0, trace_blocks(c, call), &dc->queue,
                       c->cand.as<sbr_candidate>(), kSmallEvents, &dc->cand, nullptr, nullptr,
                       &dc->err, st));

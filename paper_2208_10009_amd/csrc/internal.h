@@ -139,7 +139,8 @@ struct CallDev {
 };
 
 // ---- launchers -----------------------------------------------------------
-hipError_t launch_grid(GridDev g, hipStream_t s, void* scratch);
+// check_log2 scales the error bounds of the equiangular grid's fast pass.
+hipError_t launch_grid(GridDev g, hipStream_t s, void* scratch, int32_t check_log2 = 0);
 size_t grid_scratch_bytes(int32_t n);
 
 // Persistent trace + reception over all packets of the call.  Reception

@@ -96,29 +96,110 @@ __device__ static d3 proj_face(d3 p, d3 g)
 // rounded (the first step from one corner and the last step into the next
 // corner use the same two sines, swapped).  To keep the chain short, three
 // lanes per side start from the library's y0 = acos(P.Q) at once:
-//   lane 0: cos y0 in double-double and sin y0 from the library; one Newton
-//           step th = y0 + (cos y0 - P.Q) / sin y0 is accurate to ~1e-31
-//           (the correction is ~1e-16, so a 1e-16 relative sine suffices);
+//   lane 0: cos y0 in double-double and sin y0 in double; one Newton step
+//           th = y0 + (cos y0 - P.Q) / sin y0 (the correction is ~1e-16, so
+//           a 1e-16 relative sine suffices);
 //   lanes 1, 2: sin b0, sin a0 in double-double for b0, a0 formed from y0,
-//           and cos b0, cos a0 from the library.
+//           and cos b0, cos a0 in double.
 // Then sin a = sin a0 + cos a0 (a - a0) - sin a0 (a - a0)^2 / 2 with
-// a - a0 ~ 1e-16 (exact in binary64), likewise for b; the neglected terms are
-// below 1e-31 relative, so each value rounds as the exact one does (the
-// results are checked bit for bit against the correctly rounded grid).
+// a - a0 ~ 1e-16 (exact in binary64), likewise for b.
+//
+// Two passes per layer.  The first evaluates the series with only their
+// leading terms in double-double (series_fast) and carries a rigorous
+// bound on the error of every value; a value is accepted when rounding both
+// ends of its error interval gives the same double (rounding is monotone, so
+// the exact value rounds to it too).  When any value of the layer fails that
+// test (about one layer in a hundred), the layer is recomputed with the full
+// 18-term double-double series, whose error (~1e-31 relative) leaves each
+// value rounding as the exact one does; the results are checked bit for bit
+// against the correctly rounded grid either way.  2^check_log2 scales every
+// bound (a larger value only sends more layers through the second pass).
+//
 // The role is the wave index (lane = side, 60 of 64 lanes busy), so no wave
-// runs the cosine and the sine series one after the other.
-// The side angles are kept for k_grid_dirs.
-__global__ __launch_bounds__(192) void k_grid_setup(int32_t n, char* scratch)
+// runs the cosine and the sine series one after the other.  The lanes that
+// form the two step points next to a corner also project them onto the face
+// plane, and the third wave projects the corners, so the new corners need one
+// more step only.  The side angles are kept for k_grid_dirs.
+
+// Accept v (a normalized double-double, |v - exact| <= e) when both ends of
+// [v - 2e, v + 2e] round to v.hi + v.lo.  The factor 2 covers the rounding of
+// v.lo +- 2e, given e >= 2^-100 |v|.
+__device__ static inline bool rounds_safely(dd v, double e)
+{
+    const double r = v.hi + v.lo, e2 = 2.0 * e;
+    return v.hi + (v.lo + e2) == r && v.hi + (v.lo - e2) == r;
+}
+
+// Coefficients of one lane's series, chosen once per lane: the double-double
+// series of cos (role 0) or sin (roles 1, 2), and the double series of the
+// other function.
+struct LaneSeries {
+    dd head[5];       // 1/k! for the first five terms of the double-double series
+    double tail[9];   // 1/k! for the next nine terms
+    double e_tail, e_trunc;  // 1/k! of the first tail term and of the first omitted term
+    double other[11]; // 1/k! of the double series
+    bool cosine;
+};
+
+__device__ static LaneSeries lane_series(bool cosine)
+{
+    const int o = cosine ? 0 : 1;
+    LaneSeries L;
+    L.cosine = cosine;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) L.head[k] = cosine ? kInvFact[2 * k] : kInvFact[2 * k + 1];
+#pragma unroll
+    for (int j = 0; j < 9; ++j)
+        L.tail[j] = cosine ? kInvFact[2 * j + 10].hi : kInvFact[2 * j + 11].hi;
+    L.e_tail = kInvFact[10 + o].hi;
+    L.e_trunc = kInvFact[28 + o].hi;
+#pragma unroll
+    for (int k = 0; k < 11; ++k)
+        L.other[k] = cosine ? kInvFact[2 * k + 1].hi : kInvFact[2 * k].hi;
+    return L;
+}
+
+// Short series for 0 <= y <= 1.2: cos y (cosine lanes) or sin y with the terms up to y^8/8! (y^9/9!) in double-double (Horner's
+// rule in t = y^2, exact as two_prod(y, y)) and the next nine terms in
+// double, folded into the innermost coefficient.  *err bounds the error: the
+// double-double steps (< 2^-100 relative to values below 1), the double tail
+// (relative error below 5 ulp; 2^-47 t^5/10! (/11!) is 16 times that), and
+// the omitted terms (alternating and decreasing: below t^14/28! (y t^14/29!)).
+// *other is the other function in double (Taylor series to y^20/20!
+// (y^21/21!), about 1e-16 relative).
+__device__ static dd series_fast(const LaneSeries& L, double y, double* err, double* other)
+{
+    const double ym = L.cosine ? 1.0 : y;
+    const dd t = two_prod(y, y);
+    const double td = t.hi;
+    double q = L.tail[8];
+#pragma unroll
+    for (int j = 7; j >= 0; --j) q = fma(-td, q, L.tail[j]);
+    dd h = dd_sub(L.head[4], dd{td * q, 0.0});
+#pragma unroll
+    for (int k = 3; k >= 0; --k) h = dd_sub(L.head[k], dd_mul(t, h));
+    const double t2 = td * td, t4 = t2 * t2, t5 = t4 * td, t14 = t4 * t4 * t4 * t2;
+    *err = ym * (0x1p-96 + 0x1p-47 * t5 * L.e_tail + t14 * L.e_trunc);
+    double p = L.other[10];
+#pragma unroll
+    for (int k = 9; k >= 0; --k) p = fma(-td, p, L.other[k]);
+    *other = L.cosine ? y * p : p;
+    return dd_mul(dd{ym, 0.0}, h);
+}
+
+__global__ __launch_bounds__(192) void k_grid_setup(int32_t n, char* scratch, int32_t check_log2)
 {
     GridHdr* H = (GridHdr*)scratch;
     d3* rings = (d3*)(scratch + sizeof(GridHdr));
     double* ths = side_angles(scratch, n);
     __shared__ GridHdr sh;
     __shared__ d3 W[20][3];
-    __shared__ d3 P[20][3][2];
-    __shared__ dd SV[60][3];    // lane 0: cos y0; lane 1: sin b0; lane 2: sin a0
-    __shared__ double CV[60][3];  // lane 0: sin y0; lane 1: cos b0; lane 2: cos a0
+    __shared__ d3 PP[20][3][2];   // the two step points next to each corner, projected
+    __shared__ d3 PW[20][3];      // the corners, projected
+    __shared__ dd SV[60][3];      // lane 0: cos y0; lane 1: sin b0; lane 2: sin a0
+    __shared__ double CV[60][3];  // lane 0: 1 / sin y0; lane 1: cos b0; lane 2: cos a0
     __shared__ double SN[60][2];  // sin a, sin b
+    __shared__ int wave_bad[3];   // a value of the wave failed its rounding test
     const int t = threadIdx.x;
     if (t == 0) {
         ico_build(&sh);
@@ -126,46 +207,86 @@ __global__ __launch_bounds__(192) void k_grid_setup(int32_t n, char* scratch)
     }
     __syncthreads();
     if (t < 30) ths[3 * 20 * ring_cap(n) + t] = acos_cr(dot(sh.V[sh.e[t][0]], sh.V[sh.e[t][1]]));
-    const int f60 = t / 3, s60 = t % 3;
-    if (t < 60) W[f60][s60] = sh.V[sh.f[f60][s60]];
+    if (t < 60) W[t / 3][t % 3] = sh.V[sh.f[t / 3][t % 3]];
     __syncthreads();
-    d3 g = mk(0.0, 0.0, 0.0);
-    if (t < 60) {
-        d3 A = sh.V[sh.f[f60][0]], B = sh.V[sh.f[f60][1]], C = sh.V[sh.f[f60][2]];
-        g = add(add(A, B), C);
-    }
     const int side = t & 63, role = t >> 6;
     const bool act = side < 60;
-    const int fs = side / 3, ss = side % 3;
+    const int fs = act ? side / 3 : 0, ss = side % 3;
+    d3 g = mk(0.0, 0.0, 0.0);  // face normal direction (sum of the face's vertices)
+    if (act) {
+        d3 A = sh.V[sh.f[fs][0]], B = sh.V[sh.f[fs][1]], C = sh.V[sh.f[fs][2]];
+        g = add(add(A, B), C);
+    }
+    const double scale = ldexp(1.0, check_log2);
+    const LaneSeries L = lane_series(role == 0);
     const size_t cap3 = 3 * (size_t)ring_cap(n);
     int64_t m = n;
     for (int a = 0;; ++a) {
         // m >= 1 is the side of ring a (ring 0 is the face boundary); its
         // corners are W.
+        const int64_t mp = m - 3;
+        const double rm = 1.0 / (double)m;
         d3 Pa = mk(0.0, 0.0, 0.0), Pb = Pa;
-        double x = 0.0, y0 = 0.0, a0 = 0.0, b0 = 0.0;
+        double x = 0.0, y0 = 0.0, a0 = 0.0, b0 = 0.0, th = 0.0;
         if (act) {
             Pa = W[fs][ss];
             Pb = W[fs][(ss + 1) % 3];
             x = dot(Pa, Pb);
             y0 = acos(x);
-            a0 = ((double)1 * y0) / (double)m;
-            b0 = ((double)(m - 1) * y0) / (double)m;
-            const double arg = role == 0 ? y0 : role == 1 ? b0 : a0;
-            const dd aa = dd{arg, 0.0};
-            const dd tt = dd_mul(aa, aa);
-            SV[side][role] = role == 0 ? dd_poly_alt(0, tt) : dd_mul(aa, dd_poly_alt(1, tt));
-            CV[side][role] = role == 0 ? sin(arg) : cos(arg);
+            a0 = y0 * rm;  // any value within a few ulp of a serves
+            b0 = ((double)(m - 1) * y0) * rm;
         }
-        __syncthreads();
-        double th = 0.0;
-        if (act) {
-            const dd r = dd_sub(SV[side][0], dd{x, 0.0});
-            const dd y = dd_add(dd{y0, 0.0}, dd{r.hi / CV[side][0], 0.0});
-            th = y.hi + y.lo;
-            if (role == 0 && a > 0) ths[(size_t)fs * cap3 + 3 * (a - 1) + ss] = th;
+        const double arg = role == 0 ? y0 : role == 1 ? b0 : a0;
+        for (int full = 0; full < 2; ++full) {
+            double err = 0.0;
+            if (act) {
+                if (full) {
+                    const dd aa = dd{arg, 0.0};
+                    const dd tt = dd_mul(aa, aa);
+                    SV[side][role] = role == 0 ? dd_poly_alt(0, tt) : dd_mul(aa, dd_poly_alt(1, tt));
+                } else {
+                    double other;  // sin y0 (role 0), cos b0, cos a0
+                    SV[side][role] = series_fast(L, arg, &err, &other);
+                    CV[side][role] = role == 0 ? 1.0 / other : other;
+                }
+            }
+            __syncthreads();
+            bool bad = false;
+            if (act) {
+                // Newton step: th - y0 = (cos y0 - x) / sin y0 up to a term
+                // (th - y0)^2 cot(y0) / 2.
+                const dd r = dd_sub(SV[side][0], dd{x, 0.0});
+                const double rs = CV[side][0];
+                const double q = r.hi * rs;
+                const dd y = two_sum(y0, q);
+                th = y.hi + y.lo;
+                if (!full && role == 0) {
+                    const double e_th = err * rs + 2.0 * q * q * rs + 0x1p-38 * fabs(q) +
+                                        0x1p-100 * y0;
+                    bad = !(y0 <= 1.2) || !(fabs(q) <= 0x1p-30 * y0) ||
+                          !rounds_safely(y, e_th * scale);
+                }
+                if (mp > 0 && role > 0) {
+                    // role 1: sin b with b = (m-1) th / m; role 2: sin a with a = th / m
+                    const double v = role == 1 ? ((double)(m - 1) * th) / (double)m
+                                               : ((double)1 * th) / (double)m;
+                    const double dv = v - arg;
+                    const dd s0 = SV[side][role];
+                    dd rr = dd_add(s0, two_prod(CV[side][role], dv));
+                    rr = dd_add(rr, dd{-(s0.hi * dv * dv * 0.5), 0.0});
+                    SN[side][role == 2 ? 0 : 1] = rr.hi + rr.lo;
+                    if (!full) {
+                        const double e_s = err + 0x1p-40 * fabs(dv) + 0x1p-98 * fabs(rr.hi);
+                        bad = bad || !(arg <= 1.2) || !rounds_safely(rr, e_s * scale);
+                    }
+                }
+            }
+            const bool wb = __any(bad);
+            if (side == 0) wave_bad[role] = wb;
+            __syncthreads();
+            if (!(wave_bad[0] | wave_bad[1] | wave_bad[2])) break;
         }
-        const int64_t mp = m - 3;
+        if (act && role == 0 && a > 0) ths[(size_t)fs * cap3 + 3 * (a - 1) + ss] = th;
         if (mp < 0) break;
         if (mp == 0) {
             if (t < 20) {
@@ -178,96 +299,103 @@ __global__ __launch_bounds__(192) void k_grid_setup(int32_t n, char* scratch)
             }
             break;
         }
-        if (act && role > 0) {
-            // role 1: sin b with b = (m-1) th / m; role 2: sin a with a = th / m
-            const double v = role == 1 ? ((double)(m - 1) * th) / (double)m
-                                       : ((double)1 * th) / (double)m;
-            const double dv = v - (role == 1 ? b0 : a0);
-            const dd s0 = SV[side][role];
-            dd r = dd_add(s0, two_prod(CV[side][role], dv));
-            r = dd_add(r, dd{-(s0.hi * dv * dv * 0.5), 0.0});
-            SN[side][role == 2 ? 0 : 1] = r.hi + r.lo;
-        }
-        __syncthreads();
-        if (act && role < 2) {
+        if (act) {
             const double sa = SN[side][0], sb = SN[side][1];
             // role 0: step 1 from corner ss toward ss+1; role 1: step m-1 of
-            // the same side, the last step into corner ss+1
+            // the same side, the last step into corner ss+1; role 2: corner ss
             if (role == 0)
-                P[fs][ss][0] = normalize(add(scl(sb, Pa), scl(sa, Pb)));
+                PP[fs][ss][0] = proj_face(normalize(add(scl(sb, Pa), scl(sa, Pb))), g);
+            else if (role == 1)
+                PP[fs][(ss + 1) % 3][1] = proj_face(normalize(add(scl(sa, Pa), scl(sb, Pb))), g);
             else
-                P[fs][(ss + 1) % 3][1] = normalize(add(scl(sa, Pa), scl(sb, Pb)));
+                PW[fs][ss] = proj_face(Pa, g);
         }
         __syncthreads();
-        d3 Wn = mk(0.0, 0.0, 0.0);
         if (t < 60) {
-            d3 X = sub(add(proj_face(P[f60][s60][0], g), proj_face(P[f60][s60][1], g)),
-                       proj_face(W[f60][s60], g));
-            Wn = normalize(X);
-            rings[(size_t)f60 * cap3 + 3 * a + s60] = Wn;
+            const d3 Wn = normalize(sub(add(PP[fs][ss][0], PP[fs][ss][1]), PW[fs][ss]));
+            rings[(size_t)fs * cap3 + 3 * a + ss] = Wn;
+            W[fs][ss] = Wn;
         }
-        __syncthreads();
-        if (t < 60) W[f60][s60] = Wn;
         __syncthreads();
         m = mp;
     }
+}
+
+// Correctly rounded sin y for 0 <= y <= 1.2: the short series of the grid
+// setup when its error bound (times scale >= 1) proves the rounding (all but
+// about two values in a million), else the full double-double series.
+__device__ static double sin_rounded(double y, double scale)
+{
+    const LaneSeries L = lane_series(false);
+    double err, c;
+    const dd s = series_fast(L, y, &err, &c);
+    if (y <= 1.2 && rounds_safely(s, err * scale)) return s.hi + s.lo;
+    return sin_cr(y);
 }
 
 // Point k of m equal-angle steps from P to Q along their great circle, th
 // being the angle P and Q subtend (acos_cr(P.Q)): the angles subtended at
 // the centre by consecutive points are equal (eq. (1)).  Direction
 // sin((m-k) th/m) P + sin(k th/m) Q, normalized.
-__device__ static d3 arc_point_th(d3 P, d3 Q, double th, int64_t k, int64_t m)
+__device__ static d3 arc_point_th(d3 P, d3 Q, double th, int64_t k, int64_t m, double scale)
 {
     double a = ((double)k * th) / (double)m;
     double b = ((double)(m - k) * th) / (double)m;
-    double sa = sin_cr(a), sb = sin_cr(b);
+    double sa = sin_rounded(a, scale), sb = sin_rounded(b, scale);
     return normalize(add(scl(sb, P), scl(sa, Q)));
 }
 
 // Ray order: the 12 vertex rays; then edge interiors, edge by edge, steps
 // 1..n-1 from the lower to the higher vertex index; then face interiors, face
 // by face, layer by layer, each ring starting at the corner that descends
-// from the face's first vertex and following the winding.
+// from the face's first vertex and following the winding.  n <= 10000, so
+// every index fits in 32 bits.
 __global__ void k_grid_dirs(int32_t n, int64_t N, const char* __restrict__ scratch,
-                            double* __restrict__ dir)
+                            double* __restrict__ dir, int32_t check_log2)
 {
+    const double scale = ldexp(1.0, check_log2);
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const GridHdr* H = (const GridHdr*)scratch;
     const d3* rings = (const d3*)(scratch + sizeof(GridHdr));
     const double* ths = side_angles((char*)scratch, n);
+    const uint32_t un = (uint32_t)n;
     d3 r;
-    int64_t idx = i;
+    uint32_t idx = (uint32_t)i;
     if (idx < 12) {
         r = H->V[idx];
     } else {
         idx -= 12;
-        if (idx < 30 * (int64_t)(n - 1)) {
-            int64_t e = idx / (n - 1), k = idx % (n - 1) + 1;
+        if (idx < 30 * (un - 1)) {
+            const uint32_t e = idx / (un - 1), k = idx % (un - 1) + 1;
             r = arc_point_th(H->V[H->e[e][0]], H->V[H->e[e][1]], ths[3 * 20 * ring_cap(n) + e], k,
-                             n);
+                             n, scale);
         } else {
-            idx -= 30 * (int64_t)(n - 1);
-            int64_t per_face = (int64_t)(n - 1) * (n - 2) / 2;
-            int64_t f = idx / per_face, q = idx % per_face;
-            int a = 0;
-            int64_t m = n - 3;
-            for (;;) {
-                int64_t sz = m > 0 ? 3 * m : 1;
-                if (q < sz) break;
-                q -= sz;
-                ++a;
-                m -= 3;
-            }
+            idx -= 30 * (un - 1);
+            const uint32_t per_face = (un - 1) * (un - 2) / 2;
+            const uint32_t f = idx / per_face;
+            const int64_t q = idx % per_face;
+            // Ring a starts at S(a) = 3a(n-3) - 9a(a-1)/2 (the rings before it
+            // have sides n-3, n-6, ... > 0); the last ring, of side 0, is the
+            // face centre.  Estimate a from the quadratic, then settle it.
+            const int64_t c1 = 3 * (int64_t)(n - 3);
+            const double hb = (double)c1 + 4.5;
+            const double disc = hb * hb - 18.0 * (double)q;
+            int64_t a = (int64_t)((hb - sqrt(disc > 0.0 ? disc : 0.0)) / 9.0);
+            if (a < 0) a = 0;
+            while (a > 0 && a * c1 - 9 * a * (a - 1) / 2 > q) --a;
+            while (n - 3 - 3 * (a + 1) >= 0 && (a + 1) * c1 - 9 * (a + 1) * a / 2 <= q) ++a;
+            const int64_t m = n - 3 - 3 * a;
+            const uint32_t qq = (uint32_t)(q - (a * c1 - 9 * a * (a - 1) / 2));
             const d3* W = rings + (size_t)f * 3 * ring_cap(n) + 3 * a;
             if (m == 0) {
                 r = W[0];
             } else {
-                int64_t s = q / m, k = q % m;
+                const uint32_t s = qq / (uint32_t)m, k = qq % (uint32_t)m;
                 r = k == 0 ? W[s]
                            : arc_point_th(W[s], W[(s + 1) % 3],
-                                          ths[(size_t)f * 3 * ring_cap(n) + 3 * a + s], k, m);
+                                          ths[(size_t)f * 3 * ring_cap(n) + 3 * a + s], k, m,
+                                          scale);
             }
         }
     }
@@ -370,7 +498,7 @@ __global__ void k_grid_equidistant(int32_t n, int64_t N, const char* __restrict_
     dir[2 * N + i0] = r.z;
 }
 
-hipError_t launch_grid(GridDev g, hipStream_t s, void* scratch)
+hipError_t launch_grid(GridDev g, hipStream_t s, void* scratch, int32_t check_log2)
 {
     if (g.launch != SBR_LAUNCH_EQUIANGULAR) {
         hipLaunchKernelGGL(k_poly_setup, dim3(1), dim3(64), 0, s, g.launch, (char*)scratch);
@@ -379,10 +507,10 @@ hipError_t launch_grid(GridDev g, hipStream_t s, void* scratch)
                            (const char*)scratch, g.dir);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(192), 0, s, g.n, (char*)scratch);
+    hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(192), 0, s, g.n, (char*)scratch, check_log2);
     int64_t blocks = (g.N + 255) / 256;
     hipLaunchKernelGGL(k_grid_dirs, dim3((unsigned)blocks), dim3(256), 0, s, g.n, g.N,
-                       (const char*)scratch, g.dir);
+                       (const char*)scratch, g.dir, check_log2);
     return hipGetLastError();
 }
 

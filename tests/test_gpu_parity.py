@@ -45,6 +45,28 @@ def test_launch_grid_large_n_sampled(gpu, orc):
     assert np.array_equal(bits(g[ids]), bits(o))
 
 
+@pytest.mark.parametrize("check_log2", [200, 0])
+def test_launch_grid_full_series_pass(gpu, orc, check_log2):
+    """The grid setup accepts short-series values only when their error bound
+    proves the rounding; with the bounds scaled by 2^200 every layer takes the
+    full-series pass instead.  Both give the correctly rounded grid."""
+    from paper_2208_10009_amd import sbr
+    base = gpu.tuning()
+    try:
+        gpu.set_tuning(**dict(base, grid_check_log2=check_log2))
+        assert gpu.tuning()["grid_check_log2"] == check_log2
+        for n in (4, 7, 21, 200):
+            assert np.array_equal(bits(gpu.launch_grid(n)), bits(orc.launch_dirs(n))), n
+        n = 1000
+        N = 10 * n * n + 2
+        ids = np.unique(np.random.default_rng(8).integers(0, N, 3000))
+        assert np.array_equal(bits(gpu.launch_grid(n)[ids]), bits(orc.launch_dirs(n, ids)))
+        with pytest.raises(sbr.SbrError):
+            gpu.set_tuning(grid_check_log2=201)
+    finally:
+        gpu.set_tuning(**base)
+
+
 # ------------------------------------------------------- per-ray tracing --
 def _compare_rays(gpu, orc, cfg, n, K, first=0, count=None):
     sc = gpu.scene(cfg["scene"])
