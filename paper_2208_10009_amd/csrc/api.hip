@@ -89,6 +89,7 @@ struct sbr_context {
     int32_t lookahead_depth = 3;
     int32_t lookahead3_max_paths = 256;
     int32_t grid_check_log2 = 0;
+    bool la3_lds = true;  // stage the scene in LDS for the three-level refinement
     // one captured graph of a sbr_trace_device call (SBR_FLAG_GRAPH)
     struct Graph {
         bool valid = false;
@@ -226,6 +227,20 @@ int env_int(const char* name, int dflt, int lo, int hi)
     if (!v || !*v) return dflt;
     long x = strtol(v, nullptr, 10);
     return (int)std::min<long>(hi, std::max<long>(lo, x));
+}
+
+// Plan of the three-level refinement (512 lanes, a 16-entry LDS stack per
+// lane): the whole scene in LDS when it fits next to the stacks and the
+// kernel's static LDS, else none (global memory).
+LdsPlan plan_la3(const sbr_scene* s)
+{
+    const sbr_context* c = s->ctx;
+    LdsPlan L = make_lds_plan(s->n_nodes, s->T, 512, 16, c->lds_max - 1024);
+    if (!c->la3_lds || L.n_tris != s->T || L.depth != 16) {
+        L = LdsPlan{};
+        L.block = 512;
+    }
+    return L;
 }
 
 LdsPlan plan_for(const sbr_scene* s, int block)
@@ -565,8 +580,9 @@ sbr_status run_paths(sbr_context* c, Call& call, sbr_path* out, int64_t capacity
     LdsPlan lp256 = call.scenes.size() == 1 ? plan_for(call.scenes[0], 256) : LdsPlan{};
     lp256.block = 256;
     const int depth = refine_depth(c, Umax);
-    HIPCHK(c, launch_refine(call.dev, lp256, call.s0, c->uniq.as<sbr_candidate>(), Umax, ndev,
-                            depth, c->refine.as<RefineOut>(), c->geom.as<PathGeom>(),
+    LdsPlan lp3 = call.scenes.size() == 1 ? plan_la3(call.scenes[0]) : LdsPlan{};
+    HIPCHK(c, launch_refine(call.dev, lp256, lp3, call.s0, c->uniq.as<sbr_candidate>(), Umax,
+                            ndev, depth, c->refine.as<RefineOut>(), c->geom.as<PathGeom>(),
                             &dc->err, st));
     HIPCHK(c, hipEventRecord(c->ev[4], st));
 
@@ -770,6 +786,11 @@ sbr_status sbr_context_create(int32_t device, void* hip_stream, sbr_context** ou
         c->rx_tree_min = env_int("SBR_RX_TREE_MIN", 64, 1, 0x7fffffff);
         c->lookahead_depth = env_int("SBR_LOOKAHEAD_DEPTH", 3, 1, 3);
         c->lookahead3_max_paths = env_int("SBR_LOOKAHEAD3_PATHS", 256, 0, 1 << 30);
+        c->la3_lds = env_int("SBR_LA3_LDS", 1, 0, 1) != 0;
+        if (refine_la3_set_lds_limit(c->lds_max - 1024) != hipSuccess) {
+            (void)hipGetLastError();
+            c->la3_lds = false;
+        }
     }
     if (e != hipSuccess) {
         g_create_err = std::string("context setup: ") + hipGetErrorString(e);
@@ -1180,11 +1201,18 @@ sbr_status sbr_trace(sbr_scene* s, const double tx[3], const double* rx, int32_t
 // ---------------------------------------------------------------------------
 namespace {
 
+// Field by field: the struct has tail padding, which memcmp would compare.
 bool same_tuning(const sbr_context* c, const sbr_tuning& t)
 {
     sbr_tuning now;
     (void)sbr_context_get_tuning(c, &now);
-    return memcmp(&now, &t, sizeof(now)) == 0;
+    return now.trace_chunk == t.trace_chunk && now.persist_blocks == t.persist_blocks &&
+           now.trace_block == t.trace_block && now.stack_depth == t.stack_depth &&
+           now.lds_budget == t.lds_budget && now.rx_tree_min == t.rx_tree_min &&
+           now.lookahead_max_paths == t.lookahead_max_paths &&
+           now.lookahead_depth == t.lookahead_depth &&
+           now.lookahead3_max_paths == t.lookahead3_max_paths &&
+           now.grid_check_log2 == t.grid_check_log2;
 }
 
 bool graph_matches(const sbr_context* c, const sbr_scene* s, const double* rx, int32_t n_rx,
@@ -1290,8 +1318,9 @@ sbr_status capture_graph(sbr_context* c, sbr_scene* s, Call& call, const double*
                       &dc->err, st));
     step(launch_dedup_small(c->cand.as<sbr_candidate>(), kSmallEvents, c->uniq.as<sbr_candidate>(),
                             &dc->n_unique, st, &dc->cand));
-    step(launch_refine(call.dev, lp256, call.s0, c->uniq.as<sbr_candidate>(), u_cap, &dc->n_unique,
-                       depth, c->refine.as<RefineOut>(), c->geom.as<PathGeom>(), &dc->err, st));
+    step(launch_refine(call.dev, lp256, plan_la3(s), call.s0, c->uniq.as<sbr_candidate>(), u_cap,
+                       &dc->n_unique, depth, c->refine.as<RefineOut>(), c->geom.as<PathGeom>(),
+                       &dc->err, st));
     step(launch_solve(call.dev, lp256, call.s0, c->uniq.as<sbr_candidate>(),
                       c->refine.as<RefineOut>(), c->geom.as<const PathGeom>(), u_cap, &dc->n_unique,
                       c->paths.as<sbr_path>(), c->keep.as<int32_t>(), &dc->err, st));

@@ -155,6 +155,7 @@ hipError_t launch_trace(const CallDev& call, const LdsPlan& L, const SceneDev& s
                         int32_t* err_flag, hipStream_t s, unsigned long long* tallies = nullptr);
 hipError_t trace_set_lds_limit(int bytes);
 hipError_t refine_set_lds_limit(int bytes);
+hipError_t refine_la3_set_lds_limit(int bytes);
 
 // Sort candidates (sbr_candidate records) by (rx, order, faces, tan, ray);
 // idx (pow2_at_least(n) entries) receives the permutation.
@@ -196,10 +197,12 @@ struct RefineOut {
 // 3 (without an LDS plan): one 512-lane workgroup per path resolves three
 // iterations per step; depth 2: one wave per path, two iterations per step;
 // depth 1: eight lanes per path, one iteration per step.
-hipError_t launch_refine(const CallDev& call, const LdsPlan& L, const SceneDev& s0,
-                         const sbr_candidate* uniq, int64_t U_max, const int32_t* n_dev,
-                         int depth, RefineOut* out, PathGeom* geom, int32_t* err,
-                         hipStream_t s);
+// L3 is the plan of the three-level kernel (512 lanes; bytes == 0: global
+// memory), used when depth >= 3 and L has no LDS.
+hipError_t launch_refine(const CallDev& call, const LdsPlan& L, const LdsPlan& L3,
+                         const SceneDev& s0, const sbr_candidate* uniq, int64_t U_max,
+                         const int32_t* n_dev, int depth, RefineOut* out, PathGeom* geom,
+                         int32_t* err, hipStream_t s);
 
 hipError_t launch_solve(const CallDev& call, const LdsPlan& L, const SceneDev& s0,
                         const sbr_candidate* uniq, const RefineOut* rf, const PathGeom* geom,

@@ -482,14 +482,19 @@ __global__ __launch_bounds__(512) void k_refine_la3(CallDev call, LdsPlan L, Sce
     }
 }
 
-hipError_t launch_refine(const CallDev& call, const LdsPlan& L, const SceneDev& s0,
-                         const sbr_candidate* uniq, int64_t U, const int32_t* n_dev, int depth,
-                         RefineOut* out, PathGeom* geom, int32_t* err, hipStream_t s)
+hipError_t launch_refine(const CallDev& call, const LdsPlan& L, const LdsPlan& L3,
+                         const SceneDev& s0, const sbr_candidate* uniq, int64_t U,
+                         const int32_t* n_dev, int depth, RefineOut* out, PathGeom* geom,
+                         int32_t* err, hipStream_t s)
 {
     if (U <= 0) return hipSuccess;
     if (depth >= 3 && L.bytes == 0) {
-        hipLaunchKernelGGL(k_refine_la3<false>, dim3((unsigned)U), dim3(512), 0, s, call, L, s0,
-                           uniq, U, n_dev, out, geom, err);
+        if (L3.bytes > 0)
+            hipLaunchKernelGGL(k_refine_la3<true>, dim3((unsigned)U), dim3(512), L3.bytes, s, call,
+                               L3, s0, uniq, U, n_dev, out, geom, err);
+        else
+            hipLaunchKernelGGL(k_refine_la3<false>, dim3((unsigned)U), dim3(512), 0, s, call, L,
+                               s0, uniq, U, n_dev, out, geom, err);
         return hipGetLastError();
     }
     const bool lookahead = depth >= 2;
@@ -772,6 +777,14 @@ hipError_t launch_solve(const CallDev& call, const LdsPlan& L, const SceneDev& s
     return hipGetLastError();
 }
 
+// The three-level kernel also has 192 bytes of static LDS: its dynamic
+// limit is set separately, to what the caller's plans for it may use.
+hipError_t refine_la3_set_lds_limit(int bytes)
+{
+    return hipFuncSetAttribute((const void*)k_refine_la3<true>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
 hipError_t refine_set_lds_limit(int bytes)
 {
     hipError_t e = hipFuncSetAttribute((const void*)k_refine<true>,
@@ -780,6 +793,7 @@ hipError_t refine_set_lds_limit(int bytes)
     e = hipFuncSetAttribute((const void*)k_refine_la<true>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
+
     return hipFuncSetAttribute((const void*)k_solve<true>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }

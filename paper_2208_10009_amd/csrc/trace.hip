@@ -44,16 +44,14 @@ __device__ static inline void set_face(RayState& R, int32_t j, int32_t f)
     for (int q = 0; q < SBR_MAX_ORDER; ++q) R.faces[q] = q == j ? f : R.faces[q];
 }
 
-// Append the reception event of receiver gx on the lane's current segment
-// (closed by the hit at t) when it passes the cone test of eq. (3).
-__device__ static inline void receive(const JobDev& J, const double* __restrict__ rx_all,
-                                      const RayState& R, double t, int32_t gx,
-                                      sbr_candidate* __restrict__ cand, int64_t cap,
-                                      unsigned long long* __restrict__ ccount, uint32_t* events,
-                                      bool count)
+// Append the reception event of receiver gx at rx on the lane's current
+// segment (closed by the hit at t) when it passes the cone test of eq. (3).
+__device__ static inline void receive_at(const JobDev& J, const RayState& R, double t, int32_t gx,
+                                         d3 rx, sbr_candidate* __restrict__ cand, int64_t cap,
+                                         unsigned long long* __restrict__ ccount,
+                                         uint32_t* events, bool count)
 {
     double tn;
-    d3 rx = mk(gld(rx_all + 3 * gx), gld(rx_all + 3 * gx + 1), gld(rx_all + 3 * gx + 2));
     if (!capture(R.o, R.d, R.D, t, rx, J.thl, &tn)) return;
     if (count) *events += 1;
     unsigned long long pos = atomicAdd(ccount, 1ull);
@@ -67,6 +65,16 @@ __device__ static inline void receive(const JobDev& J, const double* __restrict_
         c.tan_err = tn;
         cand[pos] = c;
     }
+}
+
+__device__ static inline void receive(const JobDev& J, const double* __restrict__ rx_all,
+                                      const RayState& R, double t, int32_t gx,
+                                      sbr_candidate* __restrict__ cand, int64_t cap,
+                                      unsigned long long* __restrict__ ccount, uint32_t* events,
+                                      bool count)
+{
+    d3 rx = mk(gld(rx_all + 3 * gx), gld(rx_all + 3 * gx + 1), gld(rx_all + 3 * gx + 2));
+    receive_at(J, R, t, gx, rx, cand, cap, ccount, events, count);
 }
 
 // Persistent trace.  A wave takes a packet of 64 x chunk consecutive launch
@@ -137,7 +145,20 @@ __global__ __launch_bounds__(256) void k_trace(CallDev call, LdsPlan L, SceneDev
         if (out_t) out_t[ro + R.j] = t;
         // reception on the segment
         if (J.rx_root < 0) {
-            for (int x = 0; x < J.n_rx; ++x)
+            // four receivers per batch: their coordinates (wave-uniform,
+            // scalar loads) are loaded together before the four tests
+            const double* rxp = call.rx + 3 * (int64_t)J.rx_first;
+            int x = 0;
+            for (; x + 4 <= J.n_rx; x += 4) {
+                double c[12];
+#pragma unroll
+                for (int u = 0; u < 12; ++u) c[u] = cld(rxp + 3 * x + u);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    receive_at(J, R, t, J.rx_first + x + u, mk(c[3 * u], c[3 * u + 1], c[3 * u + 2]),
+                               cand, cap, ccount, &events, COUNT);
+            }
+            for (; x < J.n_rx; ++x)
                 receive(J, call.rx, R, t, J.rx_first + x, cand, cap, ccount, &events, COUNT);
         } else {
             // stackless preorder walk of the job's receiver tree

@@ -92,6 +92,14 @@ __device__ __forceinline__ int32_t gld(const int32_t* p)
     return *(const __attribute__((address_space(1))) int32_t*)p;
 }
 
+// Loads through the constant address space, for arrays that no kernel
+// writes while it reads them (the receivers): at a wave-uniform address the
+// compiler then issues scalar loads.
+__device__ __forceinline__ double cld(const double* p)
+{
+    return *(const __attribute__((address_space(4))) double*)p;
+}
+
 // A triangle record from five 16-byte pieces (v0, e1, e2 as doubles; the
 // last 8 bytes hold the face id and the input index).
 __device__ static inline TriD make_tri(double2 a, double2 b, double2 c, double2 d, double2 e)
@@ -269,11 +277,26 @@ __device__ static int32_t traverse(const SceneDev& S, const LdsPlan& L, d3 o, d3
         if (k0 == INFINITY) {
             if (sp == 0) break;
             --sp;
-            node = sp < ldepth ? lst[sp * bd] : ost[sp - ldepth];
+            if (sp < ldepth)
+                node = lst[sp * bd];
+            else
+                node = ost[sp - ldepth];
             continue;
         }
         // push the farther ones, farthest first, and descend into the nearest
-        const int npush = (k1 < INFINITY) + (k2 < INFINITY) + (k3 < INFINITY);
+        const int c1 = k1 < INFINITY, c2 = k2 < INFINITY, c3 = k3 < INFINITY;
+        const int npush = c1 + c2 + c3;
+        if (sp + 3 <= ldepth) {
+            // all in the LDS part: three unconditional writes at the slots
+            // the finite keys take (the finite ones form a prefix, so a slot
+            // an infinite key writes is either overwritten or above the top)
+            lst[sp * bd] = n3;
+            lst[(sp + c3) * bd] = n2;
+            lst[(sp + c3 + c2) * bd] = n1;
+            sp += npush;
+            node = n0;
+            continue;
+        }
         if (sp + npush > kTraceStack) {
             atomicOr(err, 1);
             return h->pos;
@@ -359,6 +382,18 @@ struct Follow {
     double tan_err, D, Llast;
 };
 
+// faces[j] of a face sequence without a dynamic index, which would place the
+// caller's list in private memory.
+__device__ static inline int32_t face_at(const int32_t* faces, int j)
+{
+    // every load has a constant index; selecting values (not addresses)
+    // lets the list stay in registers
+    int32_t f = 0;
+#pragma unroll
+    for (int q = 0; q < SBR_MAX_ORDER; ++q) f |= q == j ? faces[q] : 0;
+    return f;
+}
+
 // Trace direction d0 from Tx through exactly the faces of a path of order k
 // and report the error angle of Rx on the last segment (no cone condition).
 // A sub-ray is a usable path only if it meets the same faces in the same
@@ -387,7 +422,7 @@ __device__ static bool follow(const SceneDev& S, const LdsPlan& L, d3 tx, d3 d0,
             F->Llast = norm(sub(rx, o));
             return true;
         }
-        if (hit < 0 || h.face != faces[j]) return false;
+        if (hit < 0 || h.face != face_at(faces, j)) return false;
         d3 nf = face_normal(S, h.face);
         d3 on = add(o, scl(h.t, d));
         if (din) din[j] = d;

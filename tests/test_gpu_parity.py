@@ -317,6 +317,20 @@ def test_refine_lookahead_matches_single_step(gpu, orc, prm):
     _compare_paths(a, o)
 
 
+@pytest.mark.parametrize("seed,order", [(2, 6), (5, 3)])
+def test_refine_three_level_lds_matches_global(gpu, orc, seed, order):
+    """The three-level refinement with the scene staged in LDS and reading
+    global memory give byte-identical paths, equal to the oracle's."""
+    cfg = scenes.manhattan_config(seed, n_rx=20)
+    full = dict(cfg["params"], division_n=70, max_order=order, iterations=7)
+    env = {"SBR_LOOKAHEAD_PATHS": "100000", "SBR_LOOKAHEAD_DEPTH": "3",
+           "SBR_LOOKAHEAD3_PATHS": "100000"}
+    a = _trace_with_env(dict(env, SBR_LA3_LDS="1"), cfg, **full)
+    b = _trace_with_env(dict(env, SBR_LA3_LDS="0"), cfg, **full)
+    assert a.tobytes() == b.tobytes() and len(a) > 20
+    _compare_paths(a, orc.run(cfg["scene"], cfg["tx"], cfg["rx"], **full)["paths"])
+
+
 def test_lds_staged_traversal_matches(gpu, orc):
     """LDS-staged traversal (node prefix, triangles and stack in LDS, or the
     stack alone) gives the same paths as global-memory traversal."""
