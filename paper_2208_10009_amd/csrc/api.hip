@@ -68,7 +68,7 @@ struct sbr_context {
     std::string err;
     int32_t n_scenes = 0;
     std::map<int32_t, DevBuf> grids;  // division n -> [3][N] FP64 directions
-    DevBuf grid_scratch, rx, cand, idx, flags, offs, scan, uniq, refine, paths, keep, outp,
+    DevBuf grid_scratch, rx, rx32, cand, idx, flags, offs, scan, uniq, refine, paths, keep, outp,
         counters, rays_tri, rays_t, tally, geom, d_jobs, d_scenes, d_rxjob, d_rxnodes, d_rxperm;
     Counters* host_ctr = nullptr;  // pinned
     sbr_path* host_paths = nullptr;  // pinned staging of the path list
@@ -415,6 +415,7 @@ sbr_status upload_call(sbr_context* c, Call& call)
     HIPCHK(c, ensure(c->d_jobs, sizeof(JobDev) * std::max<size_t>(call.jobs.size(), 1)));
     HIPCHK(c, ensure(c->d_scenes, sizeof(SceneDev) * std::max<size_t>(sd.size(), 1)));
     HIPCHK(c, ensure(c->rx, sizeof(double) * 3 * (size_t)std::max(call.n_rx, 1)));
+    HIPCHK(c, ensure(c->rx32, sizeof(float4) * (size_t)std::max(call.n_rx, 1)));
     HIPCHK(c, ensure(c->d_rxjob, sizeof(int32_t) * (size_t)std::max(call.n_rx, 1)));
     if (!call.jobs.empty())
         HIPCHK(c, hipMemcpyAsync(c->d_jobs.p, call.jobs.data(), sizeof(JobDev) * call.jobs.size(),
@@ -431,10 +432,12 @@ sbr_status upload_call(sbr_context* c, Call& call)
                                      hipMemcpyHostToDevice, st));
         HIPCHK(c, hipMemcpyAsync(c->d_rxjob.p, call.rx_job.data(), sizeof(int32_t) * call.rx_job.size(),
                                  hipMemcpyHostToDevice, st));
+        HIPCHK(c, launch_rx32(c->rx.as<const double>(), call.n_rx, c->rx32.as<float4>(), st));
     }
     call.dev.jobs = c->d_jobs.as<const JobDev>();
     call.dev.scenes = c->d_scenes.as<const SceneDev>();
     call.dev.rx = c->rx.as<const double>();
+    call.dev.rx32 = c->rx32.as<const float4>();
     call.dev.rx_job = c->d_rxjob.as<const int32_t>();
     call.dev.rx_nodes = nullptr;
     call.dev.rx_perm = nullptr;
@@ -857,7 +860,7 @@ sbr_status sbr_context_destroy(sbr_context* c)
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     for (auto& kv : c->grids) release(kv.second);
-    DevBuf* bufs[] = {&c->grid_scratch, &c->rx,    &c->cand,  &c->idx,  &c->flags,
+    DevBuf* bufs[] = {&c->grid_scratch, &c->rx,    &c->rx32,  &c->cand,  &c->idx,  &c->flags,
                       &c->offs,         &c->scan,  &c->uniq,  &c->refine, &c->paths,
                       &c->keep,         &c->outp,  &c->counters, &c->rays_tri, &c->rays_t, &c->tally,
                       &c->geom,         &c->d_jobs, &c->d_scenes, &c->d_rxjob,
@@ -1265,6 +1268,7 @@ sbr_status capture_graph(sbr_context* c, sbr_scene* s, Call& call, const double*
     HIPCHK(c, ensure(c->d_jobs, sizeof(JobDev)));
     HIPCHK(c, ensure(c->d_scenes, sizeof(SceneDev)));
     HIPCHK(c, ensure(c->rx, sizeof(double) * 3 * (size_t)std::max(n_rx, 1)));
+    HIPCHK(c, ensure(c->rx32, sizeof(float4) * (size_t)std::max(n_rx, 1)));
     HIPCHK(c, ensure(c->d_rxjob, sizeof(int32_t) * (size_t)std::max(n_rx, 1)));
     HIPCHK(c, ensure(c->counters, sizeof(Counters)));
     HIPCHK(c, ensure(c->cand, sizeof(sbr_candidate) * (size_t)kSmallEvents));
@@ -1283,6 +1287,7 @@ sbr_status capture_graph(sbr_context* c, sbr_scene* s, Call& call, const double*
     call.dev.jobs = c->d_jobs.as<const JobDev>();
     call.dev.scenes = c->d_scenes.as<const SceneDev>();
     call.dev.rx = c->rx.as<const double>();
+    call.dev.rx32 = c->rx32.as<const float4>();
     call.dev.rx_job = c->d_rxjob.as<const int32_t>();
     call.dev.rx_nodes = nullptr;
     call.dev.rx_perm = nullptr;
@@ -1309,6 +1314,7 @@ sbr_status capture_graph(sbr_context* c, sbr_scene* s, Call& call, const double*
                             hipMemcpyDeviceToDevice, st));
         step(hipMemcpyAsync(c->d_rxjob.p, G.h_rxjob, sizeof(int32_t) * (size_t)n_rx,
                             hipMemcpyHostToDevice, st));
+        step(launch_rx32(c->rx.as<const double>(), n_rx, c->rx32.as<float4>(), st));
     }
     step(launch_zero(c->counters.p, sizeof(Counters), st));
     if (p->flags & SBR_FLAG_FRESH_GRID)

@@ -133,12 +133,16 @@ struct CallDev {
     const int32_t* rx_job;  // job of each receiver
     const RxNode* rx_nodes; // receiver trees of the jobs that have one
     const int32_t* rx_perm; // receiver indices in tree-leaf order
+    const float4* rx32;     // [n_rx_total]: receivers in FP32 and max |coordinate|
     int32_t n_jobs;
     int32_t chunk;          // 64-ray groups per packet
     int64_t n_packets;
 };
 
 // ---- launchers -----------------------------------------------------------
+// FP32 copies of n receivers for the reception pre-test: (x, y, z, m) with m
+// at least max(|x|, |y|, |z|) of the FP64 receiver.
+hipError_t launch_rx32(const double* rx, int64_t n, float4* out, hipStream_t s);
 // check_log2 scales the error bounds of the equiangular grid's fast pass.
 hipError_t launch_grid(GridDev g, hipStream_t s, void* scratch, int32_t check_log2 = 0);
 size_t grid_scratch_bytes(int32_t n);

@@ -270,26 +270,20 @@ namespace sbr {
 // Single-workgroup variants for up to kSmallEvents events: one launch each,
 // no host round trip in between (the counts stay on the device).
 // ===========================================================================
-// Sort (bitonic, in LDS), path test 1 (heads of equal keys) and compaction of
-// the winners, in sorted order; writes the number of unique paths to
-// *n_unique.
-__global__ __launch_bounds__(1024) void k_dedup_small(const sbr_candidate* __restrict__ C,
-                                                      int32_t n_max,
-                                                      const unsigned long long* __restrict__ n_dev,
-                                                      sbr_candidate* __restrict__ U,
-                                                      int32_t* __restrict__ n_unique)
+// Threads of the one-workgroup path test 1 and the events each handles in
+// the scan (256 threads measured slower: the head tests then run 16 deep).
+constexpr int kDedupThreads = 1024;
+constexpr int kDedupPer = kSmallEvents / kDedupThreads;
+static_assert(kDedupPer <= 32, "head bits of one thread must fit a 32-bit mask");
+
+// Bitonic sort of the index list idx[0..P) of the n events in C (P = the
+// power of two >= n; empty slots hold 0xffffffff and sort last).
+__device__ static void bitonic_block(const sbr_candidate* C, uint32_t* idx, int P)
 {
-    __shared__ uint32_t idx[kSmallEvents];
-    __shared__ int32_t part[1024];
     const int t = threadIdx.x;
-    const int n = n_dev ? (int)min((unsigned long long)n_max, *n_dev) : n_max;
-    int P = 1;
-    while (P < n) P <<= 1;
-    for (int i = t; i < P; i += 1024) idx[i] = i < n ? (uint32_t)i : 0xffffffffu;
-    __syncthreads();
     for (int k = 2; k <= P; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int q = t; q < P / 2; q += 1024) {
+            for (int q = t; q < P / 2; q += kDedupThreads) {
                 int i = 2 * q - (q & (j - 1));
                 int l = i + j;
                 bool asc = (i & k) == 0;
@@ -303,32 +297,135 @@ __global__ __launch_bounds__(1024) void k_dedup_small(const sbr_candidate* __res
             __syncthreads();
         }
     }
-    int h[4], sum = 0;
+}
+
+// The sort key of an event as 16 unsigned words whose lexicographic order is
+// the canonical order (rx, order, face sequence, then the smaller error
+// angle, then the lower ray): signed fields are offset by 2^31, tan_err >= 0
+// and ray >= 0 compare as their bit patterns; the last two words are zero.
+__device__ static inline void pack_key(const sbr_candidate& c, uint4* K)
+{
+    const uint32_t o = 0x80000000u;
+    const unsigned long long tb = (unsigned long long)__double_as_longlong(c.tan_err);
+    const unsigned long long rb = (unsigned long long)c.ray;
+    K[0] = make_uint4((uint32_t)c.rx ^ o, (uint32_t)c.order ^ o, (uint32_t)c.face[0] ^ o,
+                      (uint32_t)c.face[1] ^ o);
+    K[1] = make_uint4((uint32_t)c.face[2] ^ o, (uint32_t)c.face[3] ^ o, (uint32_t)c.face[4] ^ o,
+                      (uint32_t)c.face[5] ^ o);
+    K[2] = make_uint4((uint32_t)c.face[6] ^ o, (uint32_t)c.face[7] ^ o, (uint32_t)(tb >> 32),
+                      (uint32_t)tb);
+    K[3] = make_uint4((uint32_t)(rb >> 32), (uint32_t)rb, 0u, 0u);
+}
+
+__device__ static inline void unpack16(const uint4* K, uint32_t* w)
+{
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        int i = 4 * t + q;
-        h[q] = (i < n && (i == 0 || key_cmp(C[idx[i]], C[idx[i - 1]]) != 0)) ? 1 : 0;
-        sum += h[q];
+        const uint4 v = K[q];
+        w[4 * q] = v.x;
+        w[4 * q + 1] = v.y;
+        w[4 * q + 2] = v.z;
+        w[4 * q + 3] = v.w;
     }
+}
+
+// Is the key of event ia before that of ib (empty slots last)?  Compares
+// words 0..nw-1, branch-free from the last word up.
+__device__ static inline bool key_less16(const uint4* K, uint32_t ia, uint32_t ib, int nw)
+{
+    if (ia == 0xffffffffu) return false;
+    if (ib == 0xffffffffu) return true;
+    uint32_t a[16], b[16];
+    unpack16(K + 4 * (size_t)ia, a);
+    unpack16(K + 4 * (size_t)ib, b);
+    bool lt = false;
+#pragma unroll
+    for (int q = 15; q >= 0; --q)
+        if (q < nw) lt = a[q] < b[q] || (a[q] == b[q] && lt);
+    return lt;
+}
+
+// Events staged in LDS (as packed keys) for the sort when there are at most
+// this many.
+constexpr int kDedupLds = 2048;
+
+// Sort (bitonic, in LDS), path test 1 (heads of equal keys) and compaction of
+// the winners, in sorted order; writes the number of unique paths to
+// *n_unique.  Up to kDedupLds events are first packed into LDS keys, so that
+// each comparison is four LDS reads and a branch-free word compare.
+__global__ __launch_bounds__(kDedupThreads) void k_dedup_small(const sbr_candidate* __restrict__ C,
+                                                      int32_t n_max,
+                                                      const unsigned long long* __restrict__ n_dev,
+                                                      sbr_candidate* __restrict__ U,
+                                                      int32_t* __restrict__ n_unique)
+{
+    __shared__ uint32_t idx[kSmallEvents];
+    __shared__ int32_t part[kDedupThreads];
+    __shared__ uint4 sK[4 * kDedupLds];
+    const int t = threadIdx.x;
+    const int n = n_dev ? (int)min((unsigned long long)n_max, *n_dev) : n_max;
+    int P = 1;
+    while (P < n) P <<= 1;
+    for (int i = t; i < P; i += kDedupThreads) idx[i] = i < n ? (uint32_t)i : 0xffffffffu;
+    const bool staged = n <= kDedupLds;  // uniform over the workgroup
+    if (staged)
+        for (int i = t; i < n; i += kDedupThreads) pack_key(C[i], sK + 4 * i);
+    __syncthreads();
+    if (staged) {
+        for (int k = 2; k <= P; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int q = t; q < P / 2; q += kDedupThreads) {
+                    int i = 2 * q - (q & (j - 1));
+                    int l = i + j;
+                    bool asc = (i & k) == 0;
+                    uint32_t a = idx[i], b = idx[l];
+                    bool swap = asc ? key_less16(sK, b, a, 14) : key_less16(sK, a, b, 14);
+                    if (swap) {
+                        idx[i] = b;
+                        idx[l] = a;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    } else {
+        bitonic_block(C, idx, P);
+    }
+    uint32_t hm = 0;  // bit q: event kDedupPer t + q heads its key
+#pragma unroll
+    for (int q = 0; q < kDedupPer; ++q) {
+        int i = kDedupPer * t + q;
+        bool head = false;
+        if (i < n) {
+            if (i == 0)
+                head = true;
+            else if (staged)  // keys differ in (rx, order, face sequence): words 0..9
+                head = key_less16(sK, idx[i - 1], idx[i], 10);
+            else
+                head = key_cmp(C[idx[i]], C[idx[i - 1]]) != 0;
+        }
+        hm |= head ? 1u << q : 0u;
+    }
+    const int sum = __popc(hm);
     part[t] = sum;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
+    for (int off = 1; off < kDedupThreads; off <<= 1) {
         int v = t >= off ? part[t - off] : 0;
         __syncthreads();
         part[t] += v;
         __syncthreads();
     }
     int run = part[t] - sum;
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-        if (h[q]) U[run++] = C[idx[4 * t + q]];
-    if (t == 1023) *n_unique = part[1023];
+    for (int q = 0; q < kDedupPer; ++q)
+        if (hm >> q & 1u) U[run++] = C[idx[kDedupPer * t + q]];
+    if (t == kDedupThreads - 1) *n_unique = part[kDedupThreads - 1];
 }
 
 hipError_t launch_dedup_small(const sbr_candidate* C, int64_t n, sbr_candidate* U,
                               int32_t* n_unique, hipStream_t s, const unsigned long long* n_dev)
 {
-    hipLaunchKernelGGL(k_dedup_small, dim3(1), dim3(1024), 0, s, C, (int32_t)n, n_dev, U, n_unique);
+    hipLaunchKernelGGL(k_dedup_small, dim3(1), dim3(kDedupThreads), 0, s, C, (int32_t)n, n_dev, U,
+                       n_unique);
     return hipGetLastError();
 }
 

@@ -44,6 +44,67 @@ __device__ static inline void set_face(RayState& R, int32_t j, int32_t f)
     for (int q = 0; q < SBR_MAX_ORDER; ++q) R.faces[q] = q == j ? f : R.faces[q];
 }
 
+// ---------------------------------------------------------------------------
+// FP32 pre-test of reception.  capture() decides in FP64; this cheaper test
+// only rejects receivers that capture() would reject too.  With u = 2^-24,
+// M = max(|o|inf, |rx|inf) and v = rx - o, the FP32 foot parameter tc is
+// within 24 u M of the exact one and the FP32 perpendicular within 38 u M of
+// the exact distance, so a capture needs
+//   tc > -dl,   tc - dl <= t,   |w|^2 <= (thl (D + tc + dl) + dl)^2 (1 + small)
+// with dl = 2^-18 (M + D) = 64 u (M + D); the thresholds below carry factors
+// 1 + 2^-20 (t, thl) and 1 + 2^-18 (the squared bound) for their own
+// roundings, and every comparison is written so that NaN never rejects.
+struct Seg32 {
+    float ox, oy, oz, dx, dy, dz, D, t, thl, dl;
+};
+
+__device__ static inline Seg32 seg32(const RayState& R, double t, double thl)
+{
+    Seg32 g;
+    g.ox = (float)R.o.x;
+    g.oy = (float)R.o.y;
+    g.oz = (float)R.o.z;
+    g.dx = (float)R.d.x;
+    g.dy = (float)R.d.y;
+    g.dz = (float)R.d.z;
+    g.D = (float)R.D;
+    const float up = 1.0f + 0x1p-20f;
+    g.t = (float)t * up;
+    g.thl = (float)thl * up;
+    g.dl = 0x1p-18f * (fmaxf(fmaxf(fabsf(g.ox), fabsf(g.oy)), fabsf(g.oz)) + g.D);
+    return g;
+}
+
+__device__ static inline bool rx_may_capture32(const Seg32& g, float4 r)
+{
+    const float vx = r.x - g.ox, vy = r.y - g.oy, vz = r.z - g.oz;
+    const float tc = fmaf(vz, g.dz, fmaf(vy, g.dy, vx * g.dx));
+    const float dl = fmaf(0x1p-18f, r.w, g.dl);
+    if (tc + dl <= 0.0f) return false;
+    if (tc - dl > g.t) return false;
+    const float wx = fmaf(-tc, g.dx, vx), wy = fmaf(-tc, g.dy, vy), wz = fmaf(-tc, g.dz, vz);
+    const float ww = fmaf(wz, wz, fmaf(wy, wy, wx * wx));
+    const float A = fmaf(g.thl, (g.D + tc) + dl, dl);
+    return !(ww > (A * A) * (1.0f + 0x1p-18f));
+}
+
+__global__ void k_rx32(const double* __restrict__ rx, int64_t n, float4* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float x = (float)rx[3 * i], y = (float)rx[3 * i + 1], z = (float)rx[3 * i + 2];
+    // rounding to FP32 may lower a magnitude by 2^-24 relative; the bound
+    // dl keeps a factor 1.6 of slack for that
+    out[i] = make_float4(x, y, z, fmaxf(fmaxf(fabsf(x), fabsf(y)), fabsf(z)));
+}
+
+hipError_t launch_rx32(const double* rx, int64_t n, float4* out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rx32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, rx, n, out);
+    return hipGetLastError();
+}
+
 // Append the reception event of receiver gx at rx on the lane's current
 // segment (closed by the hit at t) when it passes the cone test of eq. (3).
 __device__ static inline void receive_at(const JobDev& J, const RayState& R, double t, int32_t gx,
@@ -144,22 +205,15 @@ __global__ __launch_bounds__(256) void k_trace(CallDev call, LdsPlan L, SceneDev
         if (out_tri) out_tri[ro + R.j] = hit < 0 ? -1 : h.orig;
         if (out_t) out_t[ro + R.j] = t;
         // reception on the segment
+        const Seg32 g32 = seg32(R, t, J.thl);
         if (J.rx_root < 0) {
-            // four receivers per batch: their coordinates (wave-uniform,
-            // scalar loads) are loaded together before the four tests
-            const double* rxp = call.rx + 3 * (int64_t)J.rx_first;
-            int x = 0;
-            for (; x + 4 <= J.n_rx; x += 4) {
-                double c[12];
-#pragma unroll
-                for (int u = 0; u < 12; ++u) c[u] = cld(rxp + 3 * x + u);
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    receive_at(J, R, t, J.rx_first + x + u, mk(c[3 * u], c[3 * u + 1], c[3 * u + 2]),
-                               cand, cap, ccount, &events, COUNT);
+            // FP32 pre-test of every receiver (wave-uniform, scalar loads),
+            // the FP64 test for the few it lets through
+            for (int x = 0; x < J.n_rx; ++x) {
+                const int32_t gx = J.rx_first + x;
+                if (rx_may_capture32(g32, cld4(call.rx32 + gx)))
+                    receive(J, call.rx, R, t, gx, cand, cap, ccount, &events, COUNT);
             }
-            for (; x < J.n_rx; ++x)
-                receive(J, call.rx, R, t, J.rx_first + x, cand, cap, ccount, &events, COUNT);
         } else {
             // stackless preorder walk of the job's receiver tree
             int32_t nd = J.rx_root;
@@ -182,9 +236,11 @@ __global__ __launch_bounds__(256) void k_trace(CallDev call, LdsPlan L, SceneDev
                 } else if (N.count == 0) {
                     nd = nd + 1;
                 } else {
-                    for (int q = 0; q < N.count; ++q)
-                        receive(J, call.rx, R, t, gld(call.rx_perm + N.first + q), cand, cap,
-                                ccount, &events, COUNT);
+                    for (int q = 0; q < N.count; ++q) {
+                        const int32_t gx = gld(call.rx_perm + N.first + q);
+                        if (rx_may_capture32(g32, gld(call.rx32 + gx)))
+                            receive(J, call.rx, R, t, gx, cand, cap, ccount, &events, COUNT);
+                    }
                     nd = N.skip;
                 }
             }

@@ -100,6 +100,12 @@ __device__ __forceinline__ double cld(const double* p)
     return *(const __attribute__((address_space(4))) double*)p;
 }
 
+__device__ __forceinline__ float4 cld4(const float4* p)
+{
+    const f4v v = *(const __attribute__((address_space(4))) f4v*)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
 // A triangle record from five 16-byte pieces (v0, e1, e2 as doubles; the
 // last 8 bytes hold the face id and the input index).
 __device__ static inline TriD make_tri(double2 a, double2 b, double2 c, double2 d, double2 e)
@@ -153,9 +159,14 @@ __device__ static int32_t traverse(const SceneDev& S, const LdsPlan& L, d3 o, d3
     dy = dy >= 0.0f ? fmaxf(dy, 1e-20f) : fminf(dy, -1e-20f);
     dz = dz >= 0.0f ? fmaxf(dz, 1e-20f) : fminf(dz, -1e-20f);
     const float ix = 1.0f / dx, iy = 1.0f / dy, iz = 1.0f / dz;
-    // lo - delta - o = lo - (o + delta);  hi + delta - o = hi - (o - delta)
+    // lo - delta - o = lo - (o + delta);  hi + delta - o = hi - (o - delta).
+    // A slab parameter (lo - l) i is formed as fma(lo, i, -(l i)): the one
+    // rounding of l i moves the plane by at most 2^-24 |l|, less than the
+    // rounding of the subtraction it replaces, inside the widening delta.
     const float lx = ox + delta, ly = oy + delta, lz = oz + delta;
     const float hx = ox - delta, hy = oy - delta, hz = oz - delta;
+    const float nlx = -(lx * ix), nly = -(ly * iy), nlz = -(lz * iz);
+    const float nhx = -(hx * ix), nhy = -(hy * iy), nhz = -(hz * iz);
 
     h->pos = -1;
     h->t = INFINITY;
@@ -210,9 +221,9 @@ __device__ static int32_t traverse(const SceneDev& S, const LdsPlan& L, d3 o, d3
             const float hiz = k == 0 ? q5.x : k == 1 ? q5.y : k == 2 ? q5.z : q5.w;
             first[k] = k == 0 ? cidx.x : k == 1 ? cidx.y : k == 2 ? cidx.z : cidx.w;
             cnt[k] = k == 0 ? ccnt.x : k == 1 ? ccnt.y : k == 2 ? ccnt.z : ccnt.w;
-            const float t0x = (lox - lx) * ix, t1x = (hix - hx) * ix;
-            const float t0y = (loy - ly) * iy, t1y = (hiy - hy) * iy;
-            const float t0z = (loz - lz) * iz, t1z = (hiz - hz) * iz;
+            const float t0x = fmaf(lox, ix, nlx), t1x = fmaf(hix, ix, nhx);
+            const float t0y = fmaf(loy, iy, nly), t1y = fmaf(hiy, iy, nhy);
+            const float t0z = fmaf(loz, iz, nlz), t1z = fmaf(hiz, iz, nhz);
             tn[k] = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fminf(t0z, t1z));
             const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)) * slack;
             hit[k] = cnt[k] >= 0 && tn[k] <= tf && tf >= 0.0f && tn[k] <= tb;
