@@ -90,6 +90,14 @@ struct sbr_context {
     int32_t lookahead3_max_paths = 256;
     int32_t grid_check_log2 = 0;
     bool la3_lds = true;  // stage the scene in LDS for the three-level refinement
+    // event and path counts of the last device-memory call, which predict
+    // the next one's (-1: no prediction)
+    int64_t spec_events = -1, spec_unique = 0;
+    // bytes of the job, scene and receiver-job tables last copied to the
+    // device, valid while no buffer was (re)allocated since and no graph
+    // wrote those buffers
+    std::vector<char> up_last;
+    uint64_t up_epoch = 0;
     // one captured graph of a sbr_trace_device call (SBR_FLAG_GRAPH)
     struct Graph {
         bool valid = false;
@@ -310,8 +318,18 @@ struct Call {
     int64_t n_cand = 0, n_uniq = 0;
     bool small = false;  // path test 1 ran in one workgroup; n_uniq is on the device
     bool grids_built = false;
+    // speculative call: the event count was not read back after the trace;
+    // n_cand holds the bound the one-workgroup stages were launched for, and
+    // u_pred the path count that picks the refinement kernel
+    bool spec = false;
+    int64_t u_pred = 0;
+    int64_t cap = 0;
     float ms_launch = 0, ms_trace = 0;
 };
+
+// Returned by run_paths when a speculative call found more events than its
+// bound: the caller runs the call again without speculation.
+constexpr sbr_status kSpecMiss = (sbr_status)1000;
 
 // Ball tree over the receivers perm[lo, hi) (global indices into rx), built
 // in preorder by median splits on the widest axis; returns the node index.
@@ -406,7 +424,10 @@ sbr_status add_job(sbr_context* c, Call& call, int32_t scene_idx, const double* 
     return SBR_OK;
 }
 
-// Copy the job, scene and receiver tables to the device.
+// Copy the job, scene and receiver tables to the device (skipped when they
+// equal the last copy), point the kernels at the receivers (device-memory
+// receivers are read in place), and in one launch form the FP32 receivers
+// and zero the call's counters.
 sbr_status upload_call(sbr_context* c, Call& call)
 {
     hipStream_t st = c->stream;
@@ -414,29 +435,38 @@ sbr_status upload_call(sbr_context* c, Call& call)
     for (const sbr_scene* s : call.scenes) sd.push_back(scene_dev(s));
     HIPCHK(c, ensure(c->d_jobs, sizeof(JobDev) * std::max<size_t>(call.jobs.size(), 1)));
     HIPCHK(c, ensure(c->d_scenes, sizeof(SceneDev) * std::max<size_t>(sd.size(), 1)));
-    HIPCHK(c, ensure(c->rx, sizeof(double) * 3 * (size_t)std::max(call.n_rx, 1)));
     HIPCHK(c, ensure(c->rx32, sizeof(float4) * (size_t)std::max(call.n_rx, 1)));
     HIPCHK(c, ensure(c->d_rxjob, sizeof(int32_t) * (size_t)std::max(call.n_rx, 1)));
-    if (!call.jobs.empty())
-        HIPCHK(c, hipMemcpyAsync(c->d_jobs.p, call.jobs.data(), sizeof(JobDev) * call.jobs.size(),
-                                 hipMemcpyHostToDevice, st));
-    if (!sd.empty())
-        HIPCHK(c, hipMemcpyAsync(c->d_scenes.p, sd.data(), sizeof(SceneDev) * sd.size(),
-                                 hipMemcpyHostToDevice, st));
-    if (call.n_rx > 0) {
-        if (call.rx_dev)
-            HIPCHK(c, hipMemcpyAsync(c->rx.p, call.rx_dev, sizeof(double) * 3 * (size_t)call.n_rx,
-                                     hipMemcpyDeviceToDevice, st));
-        else
+    HIPCHK(c, ensure(c->counters, sizeof(Counters)));
+    if (!call.rx_dev) HIPCHK(c, ensure(c->rx, sizeof(double) * 3 * (size_t)std::max(call.n_rx, 1)));
+    const size_t bj = sizeof(JobDev) * call.jobs.size(), bs = sizeof(SceneDev) * sd.size(),
+                 br = sizeof(int32_t) * call.rx_job.size();
+    std::vector<char> now(bj + bs + br);
+    if (bj) memcpy(now.data(), call.jobs.data(), bj);
+    if (bs) memcpy(now.data() + bj, sd.data(), bs);
+    if (br) memcpy(now.data() + bj + bs, call.rx_job.data(), br);
+    if (c->up_epoch != g_alloc_epoch || now != c->up_last) {
+        if (bj)
+            HIPCHK(c, hipMemcpyAsync(c->d_jobs.p, call.jobs.data(), bj, hipMemcpyHostToDevice, st));
+        if (bs)
+            HIPCHK(c, hipMemcpyAsync(c->d_scenes.p, sd.data(), bs, hipMemcpyHostToDevice, st));
+        if (br)
+            HIPCHK(c, hipMemcpyAsync(c->d_rxjob.p, call.rx_job.data(), br, hipMemcpyHostToDevice, st));
+        c->up_last.swap(now);
+        c->up_epoch = g_alloc_epoch;
+    }
+    const double* rx_src = call.rx_dev;
+    if (!rx_src) {
+        if (call.n_rx > 0)
             HIPCHK(c, hipMemcpyAsync(c->rx.p, call.rx, sizeof(double) * 3 * (size_t)call.n_rx,
                                      hipMemcpyHostToDevice, st));
-        HIPCHK(c, hipMemcpyAsync(c->d_rxjob.p, call.rx_job.data(), sizeof(int32_t) * call.rx_job.size(),
-                                 hipMemcpyHostToDevice, st));
-        HIPCHK(c, launch_rx32(c->rx.as<const double>(), call.n_rx, c->rx32.as<float4>(), st));
+        rx_src = c->rx.as<const double>();
     }
+    HIPCHK(c, launch_rx32(rx_src, call.n_rx, c->rx32.as<float4>(), st, c->counters.p,
+                          sizeof(Counters)));
     call.dev.jobs = c->d_jobs.as<const JobDev>();
     call.dev.scenes = c->d_scenes.as<const SceneDev>();
-    call.dev.rx = c->rx.as<const double>();
+    call.dev.rx = rx_src;
     call.dev.rx32 = c->rx32.as<const float4>();
     call.dev.rx_job = c->d_rxjob.as<const int32_t>();
     call.dev.rx_nodes = nullptr;
@@ -487,7 +517,7 @@ int refine_depth(const sbr_context* c, int64_t U)
 // winners, n_uniq or -- small -- a count on the device).  Without
 // need_unique, idx holds the sorted permutation of the events.
 sbr_status run_front(sbr_context* c, Call& call, bool need_unique, int32_t* out_tri,
-                     double* out_t, unsigned long long* tallies)
+                     double* out_t, unsigned long long* tallies, bool speculate = false)
 {
     hipStream_t st = c->stream;
     sbr_status r = upload_call(c, call);
@@ -497,9 +527,34 @@ sbr_status run_front(sbr_context* c, Call& call, bool need_unique, int32_t* out_
     int64_t cap = std::max<int64_t>(65536, (int64_t)(c->cand.cap / sizeof(sbr_candidate)));
     Counters* hc = c->host_ctr;
     Counters* dc = c->counters.as<Counters>();
-    for (;;) {
+    if (speculate && need_unique && !tallies && c->spec_events >= 0 &&
+        c->spec_events <= kSmallEvents / 2) {
+        // The last call had few events: trace and run path test 1 in one
+        // workgroup for up to twice as many, reading the count on the device;
+        // run_paths checks it after its one read-back.
+        const int64_t bound = std::min<int64_t>(kSmallEvents, std::max<int64_t>(256, 2 * c->spec_events));
         HIPCHK(c, ensure(c->cand, sizeof(sbr_candidate) * (size_t)cap));
-        HIPCHK(c, hipMemsetAsync(c->counters.p, 0, sizeof(Counters), st));
+        HIPCHK(c, hipEventRecord(c->ev[7], st));
+        HIPCHK(c, launch_trace(call.dev, call.lp, call.s0, trace_blocks(c, call), &dc->queue,
+                               c->cand.as<sbr_candidate>(), cap, &dc->cand, out_tri, out_t,
+                               &dc->err, st, nullptr));
+        HIPCHK(c, hipEventRecord(c->ev[2], st));
+        HIPCHK(c, ensure(c->uniq, sizeof(sbr_candidate) * (size_t)bound));
+        HIPCHK(c, launch_dedup_small(c->cand.as<sbr_candidate>(), bound, c->uniq.as<sbr_candidate>(),
+                                     &dc->n_unique, st, &dc->cand));
+        HIPCHK(c, hipEventRecord(c->ev[3], st));
+        call.small = true;
+        call.spec = true;
+        call.cap = cap;
+        call.n_cand = bound;
+        call.n_uniq = -1;
+        call.u_pred = c->spec_unique;
+        return SBR_OK;
+    }
+    for (int pass = 0;; ++pass) {
+        HIPCHK(c, ensure(c->cand, sizeof(sbr_candidate) * (size_t)cap));
+        if (pass > 0)  // upload_call zeroed them for the first pass
+            HIPCHK(c, hipMemsetAsync(c->counters.p, 0, sizeof(Counters), st));
         if (tallies) HIPCHK(c, hipMemsetAsync(tallies, 0, 4 * sizeof(unsigned long long), st));
         HIPCHK(c, hipEventRecord(c->ev[7], st));
         HIPCHK(c, launch_trace(call.dev, call.lp, call.s0, trace_blocks(c, call), &dc->queue,
@@ -582,7 +637,7 @@ sbr_status run_paths(sbr_context* c, Call& call, sbr_path* out, int64_t capacity
     HIPCHK(c, ensure(c->geom, sizeof(PathGeom) * U1));
     LdsPlan lp256 = call.scenes.size() == 1 ? plan_for(call.scenes[0], 256) : LdsPlan{};
     lp256.block = 256;
-    const int depth = refine_depth(c, Umax);
+    const int depth = refine_depth(c, call.spec ? call.u_pred : Umax);
     LdsPlan lp3 = call.scenes.size() == 1 ? plan_la3(call.scenes[0]) : LdsPlan{};
     HIPCHK(c, launch_refine(call.dev, lp256, lp3, call.s0, c->uniq.as<sbr_candidate>(), Umax,
                             ndev, depth, c->refine.as<RefineOut>(), c->geom.as<PathGeom>(),
@@ -602,18 +657,31 @@ sbr_status run_paths(sbr_context* c, Call& call, sbr_path* out, int64_t capacity
     int64_t P = 0, U = call.n_uniq;
     if (call.small) {
         // one workgroup compacts; the list (at most Umax records) and the
-        // counts come back in one round trip
-        HIPCHK(c, ensure(c->outp, sizeof(sbr_path) * U1));
-        HIPCHK(c, launch_emit_small(c->paths.as<sbr_path>(), c->keep.as<int32_t>(), Umax, ndev,
-                                    c->outp.as<sbr_path>(), (int64_t)U1, &dc->n_paths, st));
-        r = ensure_host_paths(c, (int64_t)U1);
-        if (r) return r;
-        if (Umax > 0 && !out_on_device)
-            HIPCHK(c, hipMemcpyAsync(c->host_paths, c->outp.p, sizeof(sbr_path) * (size_t)Umax,
-                                     hipMemcpyDeviceToHost, st));
+        // counts come back in one round trip.  Device output is written in
+        // place (only when it fits the capacity).
+        if (out_on_device) {
+            HIPCHK(c, launch_emit_small(c->paths.as<sbr_path>(), c->keep.as<int32_t>(), Umax, ndev,
+                                        out, capacity, &dc->n_paths, st));
+        } else {
+            HIPCHK(c, ensure(c->outp, sizeof(sbr_path) * U1));
+            HIPCHK(c, launch_emit_small(c->paths.as<sbr_path>(), c->keep.as<int32_t>(), Umax, ndev,
+                                        c->outp.as<sbr_path>(), (int64_t)U1, &dc->n_paths, st));
+            r = ensure_host_paths(c, (int64_t)U1);
+            if (r) return r;
+            if (Umax > 0)
+                HIPCHK(c, hipMemcpyAsync(c->host_paths, c->outp.p, sizeof(sbr_path) * (size_t)Umax,
+                                         hipMemcpyDeviceToHost, st));
+        }
         HIPCHK(c, hipMemcpyAsync(hc, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipEventRecord(c->ev[6], st));
         HIPCHK(c, hipEventSynchronize(c->ev[6]));
+        if (call.spec) {
+            if (hc->err || (int64_t)hc->cand > call.n_cand) return kSpecMiss;
+            call.n_cand = (int64_t)hc->cand;
+            HIPCHK(c, hipEventElapsedTime(&call.ms_launch, c->ev[0], c->ev[1]));
+            if (!call.grids_built) call.ms_launch = 0.0f;
+            HIPCHK(c, hipEventElapsedTime(&call.ms_trace, c->ev[7], c->ev[2]));
+        }
         if (hc->err) return fail(c, SBR_E_INTERNAL, "traversal stack overflow");
         P = hc->n_paths;
         U = hc->n_unique;
@@ -621,13 +689,7 @@ sbr_status run_paths(sbr_context* c, Call& call, sbr_path* out, int64_t capacity
         if (P > capacity)
             return fail(c, SBR_E_CAPACITY, "%lld paths, capacity %lld", (long long)P,
                         (long long)capacity);
-        if (P > 0 && out_on_device) {
-            HIPCHK(c, hipMemcpyAsync(out, c->outp.p, sizeof(sbr_path) * (size_t)P,
-                                     hipMemcpyDeviceToDevice, st));
-            HIPCHK(c, hipStreamSynchronize(st));
-        } else if (P > 0) {
-            memcpy(out, c->host_paths, sizeof(sbr_path) * (size_t)P);
-        }
+        if (P > 0 && !out_on_device) memcpy(out, c->host_paths, sizeof(sbr_path) * (size_t)P);
     } else {
         HIPCHK(c, launch_scan(c->keep.as<int32_t>(), c->offs.as<int32_t>(), U, &dc->n_paths,
                               c->scan.p, st));
@@ -1249,6 +1311,7 @@ sbr_status capture_graph(sbr_context* c, sbr_scene* s, Call& call, const double*
                          const sbr_trace_params* p, sbr_path* out, int64_t capacity,
                          int64_t u_cap)
 {
+    c->up_epoch = 0;  // the graph writes the job, scene and receiver-job buffers
     auto& G = c->graph;
     const int32_t n_rx = call.n_rx;
     if (!G.cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&G.cap_stream, hipStreamNonBlocking));
@@ -1286,7 +1349,7 @@ sbr_status capture_graph(sbr_context* c, sbr_scene* s, Call& call, const double*
 
     call.dev.jobs = c->d_jobs.as<const JobDev>();
     call.dev.scenes = c->d_scenes.as<const SceneDev>();
-    call.dev.rx = c->rx.as<const double>();
+    call.dev.rx = rx_dev;
     call.dev.rx32 = c->rx32.as<const float4>();
     call.dev.rx_job = c->d_rxjob.as<const int32_t>();
     call.dev.rx_nodes = nullptr;
@@ -1309,14 +1372,11 @@ sbr_status capture_graph(sbr_context* c, sbr_scene* s, Call& call, const double*
     };
     step(hipMemcpyAsync(c->d_jobs.p, G.h_job, sizeof(JobDev), hipMemcpyHostToDevice, st));
     step(hipMemcpyAsync(c->d_scenes.p, G.h_scene, sizeof(SceneDev), hipMemcpyHostToDevice, st));
-    if (n_rx > 0) {
-        step(hipMemcpyAsync(c->rx.p, rx_dev, sizeof(double) * 3 * (size_t)n_rx,
-                            hipMemcpyDeviceToDevice, st));
+    if (n_rx > 0)
         step(hipMemcpyAsync(c->d_rxjob.p, G.h_rxjob, sizeof(int32_t) * (size_t)n_rx,
                             hipMemcpyHostToDevice, st));
-        step(launch_rx32(c->rx.as<const double>(), n_rx, c->rx32.as<float4>(), st));
-    }
-    step(launch_zero(c->counters.p, sizeof(Counters), st));
+    // the receivers are read in place (a replay requires the same pointer)
+    step(launch_rx32(rx_dev, n_rx, c->rx32.as<float4>(), st, c->counters.p, sizeof(Counters)));
     if (p->flags & SBR_FLAG_FRESH_GRID)
         step(launch_grid(g, st, c->grid_scratch.p, c->grid_check_log2));
     step(launch_trace(call.dev, call.lp, call.s0, trace_blocks(c, call), &dc->queue,
@@ -1363,6 +1423,7 @@ sbr_status replay_graph(sbr_context* c, sbr_scene* s, const double* tx, int32_t 
                         const sbr_trace_params* p, int64_t capacity, int64_t* n_out,
                         sbr_trace_stats* stats, bool* replayed)
 {
+    c->up_epoch = 0;  // the graph writes the job, scene and receiver-job buffers
     auto& G = c->graph;
     *replayed = false;
     Call call;
@@ -1425,12 +1486,23 @@ sbr_status sbr_trace_device(sbr_scene* s, const double tx[3], const double* rx, 
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
     Call call;
-    call.rx_dev = rx;
-    r = single_call(s, call, tx, rx_host.empty() ? nullptr : rx_host.data(), n_rx, p, 0, -1);
-    if (r) return r;
-    r = run_front(c, call, true, nullptr, nullptr, nullptr);
-    if (r) return r;
-    r = run_paths(c, call, out, capacity, n_out, stats, true);
+    for (int attempt = 0;; ++attempt) {
+        call = Call{};
+        call.rx_dev = rx;
+        r = single_call(s, call, tx, rx_host.empty() ? nullptr : rx_host.data(), n_rx, p, 0, -1);
+        if (r) return r;
+        r = run_front(c, call, true, nullptr, nullptr, nullptr, attempt == 0);
+        if (r) return r;
+        r = run_paths(c, call, out, capacity, n_out, stats, true);
+        if (r != kSpecMiss) break;
+        c->spec_events = -1;  // more events than predicted: again, reading the count
+    }
+    if (!r && call.small) {
+        c->spec_events = call.n_cand;
+        c->spec_unique = c->host_ctr->n_unique;
+    } else if (!r) {
+        c->spec_events = call.n_cand;
+    }
     if (r || !want_graph || !call.small) return r;
     // capture for the next calls of this shape, with room for twice this
     // call's paths

@@ -141,8 +141,10 @@ struct CallDev {
 
 // ---- launchers -----------------------------------------------------------
 // FP32 copies of n receivers for the reception pre-test: (x, y, z, m) with m
-// at least max(|x|, |y|, |z|) of the FP64 receiver.
-hipError_t launch_rx32(const double* rx, int64_t n, float4* out, hipStream_t s);
+// at least max(|x|, |y|, |z|) of the FP64 receiver; the same launch zeroes
+// zero_bytes (a multiple of 4) at zero.
+hipError_t launch_rx32(const double* rx, int64_t n, float4* out, hipStream_t s,
+                       void* zero = nullptr, size_t zero_bytes = 0);
 // check_log2 scales the error bounds of the equiangular grid's fast pass.
 hipError_t launch_grid(GridDev g, hipStream_t s, void* scratch, int32_t check_log2 = 0);
 size_t grid_scratch_bytes(int32_t n);

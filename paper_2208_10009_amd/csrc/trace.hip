@@ -9,6 +9,8 @@
 // of uneven length keep the lanes busy.
 #include <math.h>
 
+#include <algorithm>
+
 #include "traverse.h"
 
 namespace sbr {
@@ -88,9 +90,13 @@ __device__ static inline bool rx_may_capture32(const Seg32& g, float4 r)
     return !(ww > (A * A) * (1.0f + 0x1p-18f));
 }
 
-__global__ void k_rx32(const double* __restrict__ rx, int64_t n, float4* __restrict__ out)
+// Per-call preparation in one launch: the FP32 receivers, and zeroing of
+// n_zero 32-bit words (the call's counters).
+__global__ void k_prep(const double* __restrict__ rx, int64_t n, float4* __restrict__ out,
+                       uint32_t* __restrict__ zero, int32_t n_zero)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_zero) zero[i] = 0u;
     if (i >= n) return;
     const float x = (float)rx[3 * i], y = (float)rx[3 * i + 1], z = (float)rx[3 * i + 2];
     // rounding to FP32 may lower a magnitude by 2^-24 relative; the bound
@@ -98,10 +104,14 @@ __global__ void k_rx32(const double* __restrict__ rx, int64_t n, float4* __restr
     out[i] = make_float4(x, y, z, fmaxf(fmaxf(fabsf(x), fabsf(y)), fabsf(z)));
 }
 
-hipError_t launch_rx32(const double* rx, int64_t n, float4* out, hipStream_t s)
+hipError_t launch_rx32(const double* rx, int64_t n, float4* out, hipStream_t s, void* zero,
+                       size_t zero_bytes)
 {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rx32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, rx, n, out);
+    const int32_t nz = (int32_t)(zero_bytes / 4);
+    const int64_t m = std::max<int64_t>(n, nz);
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_prep, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, rx, n, out,
+                       (uint32_t*)zero, nz);
     return hipGetLastError();
 }
 

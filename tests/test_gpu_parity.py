@@ -505,6 +505,35 @@ def test_trace_device_matches_host_api(gpu):
         assert none.shape[0] == 0 and st2["n_paths"] == st["n_paths"]
 
 
+def test_trace_device_event_prediction(gpu):
+    """Device-memory calls predict their event count from the previous call
+    (and skip reading it back after the trace); a call with more events than
+    predicted runs again and still returns sbr_trace's records: few events,
+    then a few hundred, then more than 4096, then few again."""
+    import torch
+    from paper_2208_10009_amd import sbr
+    cfg = scenes.shoebox_config(7)
+    rng = np.random.default_rng(11)
+    rx_many = rng.uniform(0.2, 0.8, size=(160, 3)) * np.array([10.0, 8.0, 3.0])
+    prm = dict(cfg["params"], iterations=2)
+    sc = gpu.scene(cfg["scene"])
+    seen = []
+    try:
+        # a receiver subset with a few hundred events (above the first call's bound)
+        mid = next(rx_many[:k] for k in (4, 8, 16, 32, 64)
+                   if sc.trace(cfg["tx"], rx_many[:k], **prm)[1]["n_candidates"] > 300)
+        for rx_np in (cfg["rx"][:1], mid, rx_many, cfg["rx"][:1], cfg["rx"][:1]):
+            ref, st = sc.trace(cfg["tx"], rx_np, **prm)
+            got, st2 = sc.trace_device(cfg["tx"], torch.as_tensor(rx_np, device="cuda"), **prm)
+            g = got.cpu().numpy().reshape(-1).view(sbr.PATH_DTYPE)
+            assert g.tobytes() == ref.tobytes()
+            assert st2["n_candidates"] == st["n_candidates"] and st2["n_paths"] == st["n_paths"]
+            seen.append(st["n_candidates"])
+    finally:
+        sc.close()
+    assert seen[0] < 128 and 300 < seen[1] <= 4096 and seen[2] > 4096, seen
+
+
 @pytest.mark.parametrize("fresh", [False, True])
 def test_graph_replay_matches_eager(gpu, fresh):
     """SBR_FLAG_GRAPH: the first call captures a HIP graph, later calls with
