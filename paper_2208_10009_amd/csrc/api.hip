@@ -270,6 +270,15 @@ double theta_launch(int32_t launch, int32_t n)
     return th / (sqrt(3.0) * (double)n);
 }
 
+// Make `device` current; hipSetDevice only when another one is (it costs
+// tens of microseconds per call on this runtime).
+hipError_t use_device(int device)
+{
+    int cur = -1;
+    if (hipGetDevice(&cur) == hipSuccess && cur == device) return hipSuccess;
+    return hipSetDevice(device);
+}
+
 sbr_status check_params(sbr_context* c, const sbr_trace_params* p)
 {
     if (!p) return fail(c, SBR_E_INVALID_ARG, "params is NULL");
@@ -919,7 +928,7 @@ sbr_status sbr_context_destroy(sbr_context* c)
 {
     if (!c) return SBR_E_INVALID_ARG;
     if (c->n_scenes > 0) return fail(c, SBR_E_INVALID_ARG, "%d scene(s) still alive", c->n_scenes);
-    (void)hipSetDevice(c->device);
+    (void)use_device(c->device);
     (void)hipStreamSynchronize(c->stream);
     for (auto& kv : c->grids) release(kv.second);
     DevBuf* bufs[] = {&c->grid_scratch, &c->rx,    &c->rx32,  &c->cand,  &c->idx,  &c->flags,
@@ -1070,7 +1079,7 @@ sbr_status sbr_bvh_build(sbr_scene* s, const sbr_bvh_params* bp)
     std::vector<int32_t> fill(fstart.begin(), fstart.end() - 1);
     for (int64_t t = 0; t < s->T; ++t) ftris[fill[s->face[t]]++] = pos_of[t];
 
-    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, use_device(c->device));
     HIPCHK(c, ensure(s->nodes, sizeof(Bvh4Node) * nodes.size()));
     HIPCHK(c, ensure(s->tris, sizeof(TriD) * tris.size()));
     HIPCHK(c, ensure(s->d_fplane, sizeof(double) * s->fplane.size()));
@@ -1094,7 +1103,7 @@ sbr_status sbr_bvh_build(sbr_scene* s, const sbr_bvh_params* bp)
 sbr_status sbr_scene_destroy(sbr_scene* s)
 {
     if (!s || !s->ctx) return SBR_E_NO_SCENE;
-    (void)hipSetDevice(s->ctx->device);
+    (void)use_device(s->ctx->device);
     (void)hipStreamSynchronize(s->ctx->stream);
     DevBuf* bufs[] = {&s->nodes, &s->tris, &s->d_fplane, &s->d_fmat, &s->fstart, &s->ftris, &s->d_eps};
     for (DevBuf* b : bufs) release(*b);
@@ -1115,7 +1124,7 @@ sbr_status sbr_launch_grid(sbr_context* c, int32_t launch, int32_t n, int64_t fi
     int64_t N = num_rays(launch, n);
     if (first < 0 || count < 0 || first + count > N || (count > 0 && !out))
         return fail(c, SBR_E_INVALID_ARG, "ray range outside 0..%lld", (long long)N);
-    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, use_device(c->device));
     GridDev g;
     bool built;
     sbr_status r = get_grid(c, launch, n, &g, &built);
@@ -1145,7 +1154,7 @@ sbr_status sbr_trace_rays(sbr_scene* s, const double tx[3], int32_t launch, int3
     int64_t N = num_rays(launch, n);
     if (first < 0 || count < 0 || first + count > N)
         return fail(c, SBR_E_INVALID_ARG, "ray range outside 0..%lld", (long long)N);
-    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, use_device(c->device));
     if (count == 0) return SBR_OK;
     sbr_trace_params p{};
     p.max_order = K;
@@ -1197,7 +1206,7 @@ sbr_status sbr_candidates(sbr_scene* s, const double tx[3], const double* rx, in
     sbr_status r = check_trace_inputs(s, tx, rx, n_rx, p, capacity, out, n_out);
     if (r) return r;
     sbr_context* c = s->ctx;
-    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, use_device(c->device));
     Call call;
     r = single_call(s, call, tx, rx, n_rx, p, 0, -1);
     if (r) return r;
@@ -1225,7 +1234,7 @@ sbr_status sbr_trace_counters(sbr_scene* s, const double tx[3], const double* rx
     if (r) return r;
     sbr_context* c = s->ctx;
     if (!counts) return fail(c, SBR_E_INVALID_ARG, "counts is NULL");
-    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, use_device(c->device));
     HIPCHK(c, ensure(c->tally, 4 * sizeof(unsigned long long)));
     Call call;
     r = single_call(s, call, tx, rx, n_rx, p, 0, -1);
@@ -1245,7 +1254,7 @@ sbr_status sbr_trace(sbr_scene* s, const double tx[3], const double* rx, int32_t
     sbr_status r = check_trace_inputs(s, tx, rx, n_rx, p, capacity, out, n_out);
     if (r) return r;
     sbr_context* c = s->ctx;
-    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, use_device(c->device));
     Call call;
     r = single_call(s, call, tx, rx, n_rx, p, 0, -1);
     if (r) return r;
@@ -1469,7 +1478,7 @@ sbr_status sbr_trace_device(sbr_scene* s, const double tx[3], const double* rx, 
     if (r) return r;
     sbr_context* c = s->ctx;
     if (n_rx < 0 || (n_rx > 0 && !rx)) return fail(c, SBR_E_INVALID_ARG, "bad rx array");
-    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, use_device(c->device));
     const bool want_graph = (p->flags & SBR_FLAG_GRAPH) != 0 && n_rx < c->rx_tree_min;
     if (want_graph && graph_matches(c, s, rx, n_rx, p, out, capacity)) {
         bool replayed = false;
@@ -1548,7 +1557,7 @@ sbr_status sbr_trace_batch(sbr_context* c, sbr_scene* const* scenes, int32_t n_s
         sbr_status r = check_params(c, &J.params);
         if (r) return r;
     }
-    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, use_device(c->device));
     Call call;
     for (int32_t i = 0; i < n_scenes; ++i) call.scenes.push_back(scenes[i]);
     call.rx = rx;
@@ -1584,7 +1593,7 @@ sbr_status sbr_path_gradients(sbr_scene* s, int64_t n_paths, const double* tx, c
     if (upstream && (!grad_tx || !grad_rx || !grad_eps))
         return fail(c, SBR_E_INVALID_ARG, "upstream gradients given but no gradient outputs");
     if (n_paths == 0) return SBR_OK;
-    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, use_device(c->device));
     GradArgs A;
     A.tx = tx;
     A.rx = rx;

@@ -373,31 +373,38 @@ __global__ __launch_bounds__(512) void k_refine_la3(CallDev call, LdsPlan L, Sce
         const int levels = min(3, J.iterations - i + 1);
         d3 u, v;
         basis(axis, &u, &v);
-        const bool lvl1 = s2 == 7 && s3 == 7 && s1 < S_;
-        const bool lvl2 = levels >= 2 && s3 == 7 && s1 < S_ && s2 < S_;
-        const bool lvl3 = levels >= 3 && s1 < S_ && s2 < S_ && s3 < S_;
+        // A step of one or two levels (the last one, when I is not a
+        // multiple of 3) packs its 7 + 49 sub-rays into the first wave,
+        // lanes (a1, a2) = (t / 8, t % 8), so that this wave has its SIMD to
+        // itself; the sub-rays are the same as with the full layout.
+        const bool packed = levels < 3;
+        const bool on = !packed || t < 64;
+        const int a1 = packed ? (t >> 3) & 7 : s1, a2 = packed ? t & 7 : s2, a3 = packed ? 7 : s3;
+        const bool lvl1 = on && a2 == 7 && a3 == 7 && a1 < S_;
+        const bool lvl2 = on && levels >= 2 && a3 == 7 && a1 < S_ && a2 < S_;
+        const bool lvl3 = on && levels >= 3 && a1 < S_ && a2 < S_ && a3 < S_;
         Follow F;
         bool ok = false;
         d3 gp[SBR_MAX_ORDER], gd[SBR_MAX_ORDER];
         if (lvl1 || lvl2 || lvl3) {
-            d3 dt = subray(axis, u, v, rho1, s1);
+            d3 dt = subray(axis, u, v, rho1, a1);
             if (lvl2 || lvl3) {
                 d3 u2, v2;
                 basis(dt, &u2, &v2);
-                dt = subray(dt, u2, v2, rho2, s2);
+                dt = subray(dt, u2, v2, rho2, a2);
             }
             if (lvl3) {
                 d3 u3, v3;
                 basis(dt, &u3, &v3);
-                dt = subray(dt, u3, v3, rho3, s3);
+                dt = subray(dt, u3, v3, rho3, a3);
             }
             ok = follow<LDS, 512>(S, L, tx, dt, rx, c.order, c.face, J.delta, &F, gp, gd, err);
         }
-        // first level: lanes (s1, 7, 7)
-        if (s2 == 7 && s3 == 7) {
-            sk[s1] = (lvl1 && ok) ? F.tan_err : INFINITY;
-            sD[s1] = (lvl1 && ok) ? F.D : 0.0;
-            sL[s1] = (lvl1 && ok) ? F.Llast : 0.0;
+        // first level: lanes (a1, 7, 7)
+        if (on && a2 == 7 && a3 == 7) {
+            sk[a1] = (lvl1 && ok) ? F.tan_err : INFINITY;
+            sD[a1] = (lvl1 && ok) ? F.D : 0.0;
+            sL[a1] = (lvl1 && ok) ? F.Llast : 0.0;
         }
         __syncthreads();
         const int b1 = argmin8(sk);
@@ -408,7 +415,7 @@ __global__ __launch_bounds__(512) void k_refine_la3(CallDev call, LdsPlan L, Sce
             flags |= SBR_PATH_STALLED;
             break;
         }
-        if (s1 == b1 && s2 == 7 && s3 == 7) store_geom(geom + p, c.order, gp, gd);
+        if (on && a1 == b1 && a2 == 7 && a3 == 7) store_geom(geom + p, c.order, gp, gd);
         axis = subray(axis, u, v, rho1, b1);
         tan = k1;
         iters = i;
@@ -418,11 +425,11 @@ __global__ __launch_bounds__(512) void k_refine_la3(CallDev call, LdsPlan L, Sce
             break;
         }
         if (levels < 2) break;
-        // second level: lanes (b1, s2, 7)
-        if (s1 == b1 && s3 == 7) {
-            sk[s2] = (lvl2 && ok) ? F.tan_err : INFINITY;
-            sD[s2] = (lvl2 && ok) ? F.D : 0.0;
-            sL[s2] = (lvl2 && ok) ? F.Llast : 0.0;
+        // second level: lanes (b1, a2, 7)
+        if (on && a1 == b1 && a3 == 7) {
+            sk[a2] = (lvl2 && ok) ? F.tan_err : INFINITY;
+            sD[a2] = (lvl2 && ok) ? F.D : 0.0;
+            sL[a2] = (lvl2 && ok) ? F.Llast : 0.0;
         }
         __threadfence_block();
         __syncthreads();
@@ -434,7 +441,7 @@ __global__ __launch_bounds__(512) void k_refine_la3(CallDev call, LdsPlan L, Sce
             flags |= SBR_PATH_STALLED;
             break;
         }
-        if (s1 == b1 && s2 == b2 && s3 == 7) store_geom(geom + p, c.order, gp, gd);
+        if (on && a1 == b1 && a2 == b2 && a3 == 7) store_geom(geom + p, c.order, gp, gd);
         basis(axis, &u, &v);
         axis = subray(axis, u, v, rho2, b2);
         tan = k2;
@@ -445,11 +452,11 @@ __global__ __launch_bounds__(512) void k_refine_la3(CallDev call, LdsPlan L, Sce
             break;
         }
         if (levels < 3) break;
-        // third level: lanes (b1, b2, s3)
-        if (s1 == b1 && s2 == b2) {
-            sk[s3] = (lvl3 && ok) ? F.tan_err : INFINITY;
-            sD[s3] = (lvl3 && ok) ? F.D : 0.0;
-            sL[s3] = (lvl3 && ok) ? F.Llast : 0.0;
+        // third level (full layout): lanes (b1, b2, a3)
+        if (a1 == b1 && a2 == b2) {
+            sk[a3] = (lvl3 && ok) ? F.tan_err : INFINITY;
+            sD[a3] = (lvl3 && ok) ? F.D : 0.0;
+            sL[a3] = (lvl3 && ok) ? F.Llast : 0.0;
         }
         __threadfence_block();
         __syncthreads();
@@ -461,7 +468,7 @@ __global__ __launch_bounds__(512) void k_refine_la3(CallDev call, LdsPlan L, Sce
             flags |= SBR_PATH_STALLED;
             break;
         }
-        if (s1 == b1 && s2 == b2 && s3 == b3) store_geom(geom + p, c.order, gp, gd);
+        if (a1 == b1 && a2 == b2 && a3 == b3) store_geom(geom + p, c.order, gp, gd);
         basis(axis, &u, &v);
         axis = subray(axis, u, v, rho3, b3);
         tan = k3;
