@@ -270,8 +270,7 @@ double theta_launch(int32_t launch, int32_t n)
     return th / (sqrt(3.0) * (double)n);
 }
 
-// Make `device` current; hipSetDevice only when another one is (it costs
-// tens of microseconds per call on this runtime).
+// Make `device` current, calling hipSetDevice only when another device is.
 hipError_t use_device(int device)
 {
     int cur = -1;
