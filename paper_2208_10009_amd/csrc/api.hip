@@ -657,7 +657,7 @@ sbr_status run_paths(sbr_context* c, Call& call, sbr_path* out, int64_t capacity
     HIPCHK(c, ensure(c->offs, sizeof(int32_t) * U1));
     HIPCHK(c, ensure(c->scan, scan_scratch_bytes(Umax)));
     HIPCHK(c, launch_solve(call.dev, lp256, call.s0, c->uniq.as<sbr_candidate>(),
-                           c->refine.as<RefineOut>(), c->geom.as<const PathGeom>(), Umax, ndev,
+                           c->refine.as<RefineOut>(), c->geom.as<PathGeom>(), Umax, ndev,
                            c->paths.as<sbr_path>(), c->keep.as<int32_t>(), &dc->err, st));
     HIPCHK(c, hipEventRecord(c->ev[5], st));
 
@@ -1396,7 +1396,7 @@ sbr_status capture_graph(sbr_context* c, sbr_scene* s, Call& call, const double*
                        &dc->n_unique, depth, c->refine.as<RefineOut>(), c->geom.as<PathGeom>(),
                        &dc->err, st));
     step(launch_solve(call.dev, lp256, call.s0, c->uniq.as<sbr_candidate>(),
-                      c->refine.as<RefineOut>(), c->geom.as<const PathGeom>(), u_cap, &dc->n_unique,
+                      c->refine.as<RefineOut>(), c->geom.as<PathGeom>(), u_cap, &dc->n_unique,
                       c->paths.as<sbr_path>(), c->keep.as<int32_t>(), &dc->err, st));
     step(launch_emit_small(c->paths.as<sbr_path>(), c->keep.as<int32_t>(), u_cap, &dc->n_unique,
                            out, capacity, &dc->n_paths, st));

@@ -211,7 +211,7 @@ hipError_t launch_refine(const CallDev& call, const LdsPlan& L, const LdsPlan& L
                          int32_t* err, hipStream_t s);
 
 hipError_t launch_solve(const CallDev& call, const LdsPlan& L, const SceneDev& s0,
-                        const sbr_candidate* uniq, const RefineOut* rf, const PathGeom* geom,
+                        const sbr_candidate* uniq, const RefineOut* rf, PathGeom* geom,
                         int64_t U_max, const int32_t* n_dev, sbr_path* paths, int32_t* keep,
                         int32_t* err, hipStream_t s);
 

@@ -579,7 +579,10 @@ __device__ static inline double path_power(double ptx, double freq, double L, co
 {
     double lambda = kC0 / freq;
     double p = ptx + 20.0 * log10(lambda / (4.0 * kPi * L));
-    for (int j = 0; j < k; ++j) p += 10.0 * log10(refl[j]);
+    // unrolled with a guard, so that a register array stays in registers
+#pragma unroll
+    for (int j = 0; j < SBR_MAX_ORDER; ++j)
+        if (j < k) p += 10.0 * log10(refl[j]);
     return p;
 }
 
@@ -624,52 +627,74 @@ __device__ static bool blocked(const SceneDev& S, const LdsPlan& L, d3 A, d3 B, 
 __device__ static bool image_points(const SceneDev& S, d3 tx, d3 rx, int k, const int32_t* faces,
                                     d3* pts)
 {
+    // loops unrolled with guards: every index is a constant, so the arrays
+    // stay in registers
     d3 img[SBR_MAX_ORDER + 1];
     img[0] = tx;
-    for (int j = 0; j < k; ++j) {
-        int32_t f = faces[j];
-        d3 n = face_normal(S, f);
-        double c = S.fplane[4 * (size_t)f + 3];
-        double dd = dot(n, img[j]) - c;
-        img[j + 1] = sub(img[j], scl(2.0 * dd, n));
+#pragma unroll
+    for (int j = 0; j < SBR_MAX_ORDER; ++j) {
+        img[j + 1] = img[j];
+        if (j < k) {
+            int32_t f = faces[j];
+            d3 n = face_normal(S, f);
+            double c = S.fplane[4 * (size_t)f + 3];
+            double dd = dot(n, img[j]) - c;
+            img[j + 1] = sub(img[j], scl(2.0 * dd, n));
+        }
     }
     bool ok = true;
     d3 X = rx;
-    for (int j = k - 1; j >= 0; --j) {
-        int32_t f = faces[j];
-        d3 n = face_normal(S, f);
-        double c = S.fplane[4 * (size_t)f + 3];
-        d3 dir = sub(img[j + 1], X);
-        double den = dot(n, dir);
-        double s = (c - dot(n, X)) / den;
-        if (!(s > 0.0 && s < 1.0)) ok = false;
-        pts[j] = add(X, scl(s, dir));
-        X = pts[j];
+#pragma unroll
+    for (int j = SBR_MAX_ORDER - 1; j >= 0; --j) {
+        pts[j] = mk(0.0, 0.0, 0.0);
+        if (j < k) {
+            int32_t f = faces[j];
+            d3 n = face_normal(S, f);
+            double c = S.fplane[4 * (size_t)f + 3];
+            d3 dir = sub(img[j + 1], X);
+            double den = dot(n, dir);
+            double s = (c - dot(n, X)) / den;
+            if (!(s > 0.0 && s < 1.0)) ok = false;
+            pts[j] = add(X, scl(s, dir));
+            X = pts[j];
+        }
     }
     return ok;
+}
+
+// a[j] of an 8-entry point list by value (no dynamic index)
+__device__ static inline d3 pick8(const d3* a, int j)
+{
+    d3 r = a[0];
+#pragma unroll
+    for (int q = 1; q < SBR_MAX_ORDER; ++q)
+        if (q == j) r = a[q];
+    return r;
 }
 
 __device__ static inline double poly_length(d3 tx, const d3* p, int k, d3 rx)
 {
     double L = 0.0;
     d3 prev = tx;
-    for (int j = 0; j < k; ++j) {
-        L = L + norm(sub(p[j], prev));
-        prev = p[j];
-    }
+#pragma unroll
+    for (int j = 0; j < SBR_MAX_ORDER; ++j)
+        if (j < k) {
+            L = L + norm(sub(p[j], prev));
+            prev = p[j];
+        }
     L = L + norm(sub(rx, prev));
     return L;
 }
 
-// Sixteen lanes per path.  Lane 0 replays the refined ray and forms the
-// refined quantities; lane 1 + j checks segment j of the image-method path
-// (reflection point j inside its face, segment j unobstructed), so path
-// test 2 costs one traversal of latency instead of k + 1.
+// Sixteen lanes per path.  Lane 1 + j checks segment j of the image-method
+// path (reflection point j inside its face, segment j unobstructed), so path
+// test 2 costs one traversal of latency instead of k + 1; then lanes 0 and 1
+// form the refined and the exact path quantities side by side.
 template <bool LDS>
 __global__ __launch_bounds__(256) void k_solve(CallDev call, LdsPlan L, SceneDev s0,
                                                const sbr_candidate* __restrict__ uniq,
                                                const RefineOut* __restrict__ rf,
-                                               const PathGeom* __restrict__ geom, int64_t U_max,
+                                               PathGeom* __restrict__ geom, int64_t U_max,
                                                const int32_t* __restrict__ n_dev,
                                                sbr_path* __restrict__ paths,
                                                int32_t* __restrict__ keep,
@@ -692,39 +717,70 @@ __global__ __launch_bounds__(256) void k_solve(CallDev call, LdsPlan L, SceneDev
     const bool geo_ok = image_points(S, tx, rx, k, c.face, ep);
     bool bad = false;
     if (geo_ok && lane >= 1 && lane <= k + 1) {
-        int j = lane - 1;
-        if (j < k && !inside_face<LDS>(S, L, c.face[j], ep[j])) {
+        // by value from the register lists (a dynamic index would move
+        // them to private memory)
+        const int j = lane - 1;
+        const d3 ej = pick8(ep, j), ejm = pick8(ep, j - 1);
+        const int32_t fj = face_at(c.face, j), fjm = face_at(c.face, j - 1);
+        if (j < k && !inside_face<LDS>(S, L, fj, ej)) {
             bad = true;
         } else {
-            d3 Pa = j == 0 ? tx : ep[j - 1];
-            d3 Pb = j < k ? ep[j] : rx;
-            int32_t fa = j == 0 ? -1 : c.face[j - 1];
-            int32_t fb = j < k ? c.face[j] : -1;
+            d3 Pa = j == 0 ? tx : ejm;
+            d3 Pb = j < k ? ej : rx;
+            int32_t fa = j == 0 ? -1 : fjm;
+            int32_t fb = j < k ? fj : -1;
             bad = blocked<LDS>(S, L, Pa, Pb, fa, fb, delta, err);
         }
     }
     unsigned long long mask = __ballot(bad);
     const int base = (int)(threadIdx.x & 63) & ~15;
     const bool any_bad = ((mask >> base) & 0xffffull) != 0;
-    if (lane != 0) return;
+    if (lane > 1) return;
 
     const RefineOut R = rf[p];
-    d3 axis = ld3(R.axis);
-    d3 pts[SBR_MAX_ORDER], din[SBR_MAX_ORDER];
-    for (int j = 0; j < SBR_MAX_ORDER; ++j) {
-        pts[j] = mk(0.0, 0.0, 0.0);
-        din[j] = mk(0.0, 0.0, 0.0);
-    }
-    if (R.iters > 0) {
-        // the refinement stored the geometry of its final winning sub-ray
-        for (int j = 0; j < k; ++j) {
-            pts[j] = geom[p].pts[j];
-            din[j] = geom[p].din[j];
+    const d3 axis = ld3(R.axis);
+    // The refinement stored the geometry of its final winning sub-ray in
+    // geom[p]; without iterations the launch ray is replayed into it.
+    PathGeom* gm = geom + p;
+    if (lane == 0 && R.iters == 0) {
+        for (int j = 0; j < SBR_MAX_ORDER; ++j) {
+            gm->pts[j] = mk(0.0, 0.0, 0.0);
+            gm->din[j] = mk(0.0, 0.0, 0.0);
         }
-    } else {
         Follow F;
-        follow<LDS>(S, L, tx, axis, rx, k, c.face, delta, &F, pts, din, err);
+        follow<LDS>(S, L, tx, axis, rx, k, c.face, delta, &F, gm->pts, gm->din, err);
     }
+    // Lanes 0 and 1 form the same quantities side by side: lane 0 of the
+    // refined path (the final ray's reflection points and incoming
+    // directions), lane 1 of the exact path (the image points; incoming
+    // direction = point minus the previous point).
+    const bool ex = lane == 1;
+    d3 P[SBR_MAX_ORDER], Din[SBR_MAX_ORDER];
+    d3 prev = tx;
+#pragma unroll
+    for (int j = 0; j < SBR_MAX_ORDER; ++j) {
+        const d3 gp = gm->pts[j], gd = gm->din[j];
+        P[j] = ex ? ep[j] : gp;
+        Din[j] = ex ? sub(ep[j], prev) : gd;
+        prev = ep[j];
+    }
+    // Tx -> reflection points -> Rx
+    const double Lq = poly_length(tx, P, k, rx);
+    const double delay = Lq / kC0;
+    const d3 firstq = k > 0 ? P[0] : rx;
+    const d3 aod = ex ? normalize(sub(firstq, tx)) : axis;
+    const d3 lastq = k > 0 ? pick8(P, k - 1) : tx;
+    const d3 aoa = normalize(sub(lastq, rx));
+    double refl[SBR_MAX_ORDER];
+#pragma unroll
+    for (int j = 0; j < SBR_MAX_ORDER; ++j) refl[j] = j < k ? refl_at(S, c.face[j], Din[j]) : 1.0;
+    const double pw = path_power(J.tx_power_dbm, J.freq_hz, Lq, refl, k);
+    // the exact path's values to lane 0
+    const int src = base + 1;
+    const double EL = __shfl(Lq, src), Edelay = __shfl(delay, src), Epw = __shfl(pw, src);
+    const d3 Eaod = mk(__shfl(aod.x, src), __shfl(aod.y, src), __shfl(aod.z, src));
+    const d3 Eaoa = mk(__shfl(aoa.x, src), __shfl(aoa.y, src), __shfl(aoa.z, src));
+    if (ex) return;
 
     sbr_path o;
     o.rx = c.rx;
@@ -736,39 +792,25 @@ __global__ __launch_bounds__(256) void k_solve(CallDev call, LdsPlan L, SceneDev
     o.init_tan_err = c.tan_err;
     o.tan_err = R.tan_err;
     st3(o.axis, axis);
-    // refined path: Tx -> reflection points of the final ray -> Rx
-    double Lr = poly_length(tx, pts, k, rx);
-    o.length_m = Lr;
-    o.delay_s = Lr / kC0;
-    st3(o.aod, axis);
-    d3 last = k > 0 ? pts[k - 1] : tx;
-    st3(o.aoa, normalize(sub(last, rx)));
-    double refl[SBR_MAX_ORDER];
-    for (int j = 0; j < k; ++j) refl[j] = refl_at(S, c.face[j], din[j]);
-    o.power_dbm = path_power(J.tx_power_dbm, J.freq_hz, Lr, refl, k);
+    o.length_m = Lq;
+    o.delay_s = delay;
+    st3(o.aod, aod);
+    st3(o.aoa, aoa);
+    o.power_dbm = pw;
     o.err_angle_deg = atan(R.tan_err) * (180.0 / kPi);
-    // exact path of the same faces
     const bool ok = geo_ok && !any_bad;
-    double EL = poly_length(tx, ep, k, rx);
     o.exact_length_m = EL;
-    o.exact_delay_s = EL / kC0;
-    d3 firstp = k > 0 ? ep[0] : rx;
-    st3(o.exact_aod, normalize(sub(firstp, tx)));
-    d3 elast = k > 0 ? ep[k - 1] : tx;
-    st3(o.exact_aoa, normalize(sub(elast, rx)));
-    d3 prev = tx;
-    for (int j = 0; j < k; ++j) {
-        refl[j] = refl_at(S, c.face[j], sub(ep[j], prev));
-        prev = ep[j];
-    }
-    o.exact_power_dbm = path_power(J.tx_power_dbm, J.freq_hz, EL, refl, k);
+    o.exact_delay_s = Edelay;
+    st3(o.exact_aod, Eaod);
+    st3(o.exact_aoa, Eaoa);
+    o.exact_power_dbm = Epw;
     if (!ok) o.flags |= SBR_PATH_INVALID;
     paths[p] = o;
     keep[p] = (ok || J.keep_invalid) ? 1 : 0;
 }
 
 hipError_t launch_solve(const CallDev& call, const LdsPlan& L, const SceneDev& s0,
-                        const sbr_candidate* uniq, const RefineOut* rf, const PathGeom* geom,
+                        const sbr_candidate* uniq, const RefineOut* rf, PathGeom* geom,
                         int64_t U, const int32_t* n_dev, sbr_path* paths, int32_t* keep,
                         int32_t* err, hipStream_t s)
 {
