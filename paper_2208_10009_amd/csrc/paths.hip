@@ -338,11 +338,22 @@ __device__ static inline bool key_less16(const uint4* K, uint32_t ia, uint32_t i
     uint32_t a[16], b[16];
     unpack16(K + 4 * (size_t)ia, a);
     unpack16(K + 4 * (size_t)ib, b);
-    bool lt = false;
+    // (less, equal) per word, merged pairwise in a tree: the first word
+    // decides unless equal, then the second
+    bool lt[16], eq[16];
 #pragma unroll
-    for (int q = 15; q >= 0; --q)
-        if (q < nw) lt = a[q] < b[q] || (a[q] == b[q] && lt);
-    return lt;
+    for (int q = 0; q < 16; ++q) {
+        lt[q] = q < nw && a[q] < b[q];
+        eq[q] = q >= nw || a[q] == b[q];
+    }
+#pragma unroll
+    for (int w = 1; w < 16; w <<= 1)
+#pragma unroll
+        for (int q = 0; q + w < 16; q += 2 * w) {
+            lt[q] = lt[q] || (eq[q] && lt[q + w]);
+            eq[q] = eq[q] && eq[q + w];
+        }
+    return lt[0];
 }
 
 // Events staged in LDS (as packed keys) for the sort when there are at most
@@ -379,7 +390,11 @@ __global__ __launch_bounds__(kDedupThreads) void k_dedup_small(const sbr_candida
                     int l = i + j;
                     bool asc = (i & k) == 0;
                     uint32_t a = idx[i], b = idx[l];
-                    bool swap = asc ? key_less16(sK, b, a, 14) : key_less16(sK, a, b, 14);
+                    // keys are distinct (one event per ray, order and
+                    // receiver), so b < a is !(a < b) but for two empty
+                    // slots, whose swap changes nothing
+                    const bool ab = key_less16(sK, a, b, 14);
+                    bool swap = asc ? !ab : ab;
                     if (swap) {
                         idx[i] = b;
                         idx[l] = a;
