@@ -150,7 +150,7 @@ constexpr int kShortStack = 16;  // LDS stack entries per lane without an LDS pl
 template <bool ANY, bool COUNT, bool LDS, int BLK = 256>
 __device__ static int32_t traverse(const SceneDev& S, const LdsPlan& L, d3 o, d3 d, int32_t xa,
                                    int32_t xb, double t_lo, double t_hi, float delta, HitRec* h,
-                                   int32_t* err, Tally* tally = nullptr)
+                                   int32_t* err, Tally* tally = nullptr, bool seeded = false)
 {
     const float slack = 1.0f + 9.5367431640625e-07f;  // 1 + 2^-20
     float ox = (float)o.x, oy = (float)o.y, oz = (float)o.z;
@@ -168,11 +168,20 @@ __device__ static int32_t traverse(const SceneDev& S, const LdsPlan& L, d3 o, d3
     const float nlx = -(lx * ix), nly = -(ly * iy), nlz = -(lz * iz);
     const float nhx = -(hx * ix), nhy = -(hy * iy), nhz = -(hz * iz);
 
-    h->pos = -1;
-    h->t = INFINITY;
-    h->face = 0x7fffffff;
-    h->orig = 0x7fffffff;
     float tb = isinf(t_hi) ? INFINITY : (float)t_hi * slack;
+    if (seeded && h->pos >= 0) {
+        // closest-hit search seeded with a hit the caller found (one of the
+        // triangles this search would test, with the same arithmetic): the
+        // pruning bound starts at it, and the result is the same
+        float ts = (float)h->t * slack;
+        if ((double)ts < h->t) ts = nextafterf(ts, INFINITY);
+        tb = fminf(tb, ts);
+    } else {
+        h->pos = -1;
+        h->t = INFINITY;
+        h->face = 0x7fffffff;
+        h->orig = 0x7fffffff;
+    }
 
     // The first stack entries live in LDS: the plan's stack (LDS instances)
     // or a fixed short stack of kShortStack entries per lane (workgroups of
@@ -421,9 +430,32 @@ __device__ static bool follow(const SceneDev& S, const LdsPlan& L, d3 tx, d3 d0,
     int32_t prev = -1;
     for (int j = 0;; ++j) {
         HitRec h;
+        h.pos = -1;
+        h.t = INFINITY;
+        h.face = 0x7fffffff;
+        h.orig = 0x7fffffff;
+        if (j < k) {
+            // seed with the closest hit on the face the path expects next:
+            // it bounds the search from the start
+            const int32_t fe = face_at(faces, j);
+            if (fe != prev)
+                for (int32_t q = S.fstart[fe]; q < S.fstart[fe + 1]; ++q) {
+                    const int32_t i = S.ftris[q];
+                    const TriD T = tri_at<LDS>(S, L, i);
+                    double t;
+                    if (!mt_hit(T, o, d, S.t_eps, INFINITY, &t)) continue;
+                    if (h.pos < 0 || t < h.t ||
+                        (t == h.t && (T.face < h.face || (T.face == h.face && T.orig < h.orig)))) {
+                        h.pos = i;
+                        h.t = t;
+                        h.face = T.face;
+                        h.orig = T.orig;
+                    }
+                }
+        }
         int32_t hit =
             traverse<false, false, LDS, BLK>(S, L, o, d, prev, prev, S.t_eps, INFINITY, delta, &h,
-                                             err);
+                                             err, nullptr, j < k);
         if (j == k) {
             double t = hit < 0 ? INFINITY : h.t;
             double tn;
