@@ -1314,10 +1314,12 @@ sbr_status graph_job(sbr_context* c, sbr_scene* s, const double* tx, int32_t n_r
 
 // Capture the whole pipeline of the call described by `call` (one job, no
 // receiver tree) into c->graph.  Buffers are sized first: nothing is
-// allocated while capturing.
+// allocated while capturing.  u_cap bounds the paths a replay may hold;
+// u_pred (the capturing call's path count) picks the refinement kernel, as
+// for an eager call (every choice gives the same bytes).
 sbr_status capture_graph(sbr_context* c, sbr_scene* s, Call& call, const double* rx_dev,
                          const sbr_trace_params* p, sbr_path* out, int64_t capacity,
-                         int64_t u_cap)
+                         int64_t u_cap, int64_t u_pred)
 {
     c->up_epoch = 0;  // the graph writes the job, scene and receiver-job buffers
     auto& G = c->graph;
@@ -1371,7 +1373,7 @@ sbr_status capture_graph(sbr_context* c, sbr_scene* s, Call& call, const double*
     lp256.block = 256;
     Counters* dc = c->counters.as<Counters>();
     const hipStream_t st = G.cap_stream;
-    const int depth = refine_depth(c, u_cap);
+    const int depth = refine_depth(c, u_pred);
 
     HIPCHK(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
@@ -1515,12 +1517,12 @@ sbr_status sbr_trace_device(sbr_scene* s, const double tx[3], const double* rx, 
     // capture for the next calls of this shape, with room for twice this
     // call's paths
     drop_graph(c);
-    const int64_t u_cap =
-        std::min<int64_t>(kSmallEvents, std::max<int64_t>(64, 2 * (int64_t)c->host_ctr->n_unique));
+    const int64_t u_now = c->host_ctr->n_unique;
+    const int64_t u_cap = std::min<int64_t>(kSmallEvents, std::max<int64_t>(64, 2 * u_now));
     Call cap;
     r = graph_job(c, s, tx, n_rx, p, cap);
     if (r) return r;
-    return capture_graph(c, s, cap, rx, p, out, capacity, u_cap);
+    return capture_graph(c, s, cap, rx, p, out, capacity, u_cap, u_now);
 }
 
 sbr_status sbr_trace_batch(sbr_context* c, sbr_scene* const* scenes, int32_t n_scenes,
