@@ -152,7 +152,11 @@ typedef struct {
  * equiangular grid's setup takes a value from short series when its error
  * bound, scaled by 2^grid_check_log2, proves the rounding, and otherwise
  * recomputes that layer with the full series (same grid; larger values only
- * send more layers through the full series). */
+ * send more layers through the full series).  With ray_order = 1 a job that
+ * traces every ray of its grid hands its rays to the waves sorted by
+ * direction (cube-map cells in Z order, the order made once per grid), so
+ * the 64 rays of a wave leave in nearby directions and traverse the same BVH
+ * nodes; 0 hands them out by index (same results). */
 typedef struct {
     int32_t trace_chunk;         /* 1..64                                   */
     int32_t persist_blocks;      /* >= 1                                    */
@@ -164,6 +168,7 @@ typedef struct {
     int32_t lookahead_depth;     /* 1..3                                    */
     int32_t lookahead3_max_paths; /* >= 0                                   */
     int32_t grid_check_log2;     /* 0..200                                  */
+    int32_t ray_order;           /* 0 or 1                                  */
 } sbr_tuning;
 
 sbr_status sbr_context_get_tuning(const sbr_context* ctx, sbr_tuning* out);

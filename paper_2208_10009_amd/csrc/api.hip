@@ -68,6 +68,10 @@ struct sbr_context {
     std::string err;
     int32_t n_scenes = 0;
     std::map<int32_t, DevBuf> grids;  // division n -> [3][N] FP64 directions
+    // whole-grid jobs hand their rays out by direction cell (get_order), the
+    // order cached per grid
+    std::map<int32_t, DevBuf> orders;
+    int32_t ray_order = 1;
     DevBuf grid_scratch, rx, rx32, cand, idx, flags, offs, scan, uniq, refine, paths, keep, outp,
         counters, rays_tri, rays_t, tally, geom, d_jobs, d_scenes, d_rxjob, d_rxnodes, d_rxperm;
     Counters* host_ctr = nullptr;  // pinned
@@ -197,6 +201,63 @@ sbr_status get_grid(sbr_context* c, int32_t launch, int32_t n, GridDev* g, bool*
         *built = true;
     }
     *g = GridDev{it->second.as<double>(), N, n, launch};
+    return SBR_OK;
+}
+
+// A hand-out order of a grid's rays that keeps each wave's rays close in
+// direction: rays sorted by their cube-map cell (about one ray per cell, cells
+// in Z order per cube face; launch_ray_cells), by index within a cell
+// (stable two-pass radix sort of the 32-bit cells on the host).  Made once per
+// grid; it changes the order rays are traced in, not the results.
+sbr_status get_order(sbr_context* c, int32_t launch, int32_t n, const GridDev& g,
+                     const uint32_t** out)
+{
+    const int32_t key = launch * 100000 + n;
+    auto it = c->orders.find(key);
+    if (it == c->orders.end()) {
+        const int64_t N = g.N;
+        int32_t R = 1;
+        while (R < 8192 && (int64_t)R * R * 6 < N) R *= 2;
+        DevBuf b;
+        HIPCHK(c, ensure(b, sizeof(uint32_t) * (size_t)N));
+        std::vector<uint32_t> cell((size_t)N), ord((size_t)N), tmp((size_t)N);
+        hipError_t e = launch_ray_cells(g.dir, N, R, b.as<uint32_t>(), c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(cell.data(), b.p, sizeof(uint32_t) * (size_t)N,
+                               hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            release(b);
+            return fail(c, SBR_E_DEVICE, "ray order: %s", hipGetErrorString(e));
+        }
+        for (int64_t i = 0; i < N; ++i) ord[(size_t)i] = (uint32_t)i;
+        std::vector<int64_t> cnt(1 << 16);
+        for (int pass = 0; pass < 2; ++pass) {
+            const int sh = 16 * pass;
+            std::fill(cnt.begin(), cnt.end(), 0);
+            for (int64_t i = 0; i < N; ++i) ++cnt[(cell[ord[(size_t)i]] >> sh) & 0xffff];
+            int64_t run = 0;
+            for (auto& x : cnt) {
+                const int64_t k = x;
+                x = run;
+                run += k;
+            }
+            for (int64_t i = 0; i < N; ++i) {
+                const uint32_t r = ord[(size_t)i];
+                tmp[(size_t)cnt[(cell[r] >> sh) & 0xffff]++] = r;
+            }
+            ord.swap(tmp);
+        }
+        e = hipMemcpyAsync(b.p, ord.data(), sizeof(uint32_t) * (size_t)N, hipMemcpyHostToDevice,
+                           c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            release(b);
+            return fail(c, SBR_E_DEVICE, "ray order: %s", hipGetErrorString(e));
+        }
+        it = c->orders.emplace(key, b).first;
+    }
+    *out = it->second.as<const uint32_t>();
     return SBR_OK;
 }
 
@@ -405,6 +466,11 @@ sbr_status add_job(sbr_context* c, Call& call, int32_t scene_idx, const double* 
     J.tx_power_dbm = p->tx_power_dbm;
     J.dir = g.dir;
     J.N = g.N;
+    J.order = nullptr;
+    if (c->ray_order && ray_begin == 0 && ray_count == g.N) {
+        r = get_order(c, p->launch, p->division_n, g, &J.order);
+        if (r) return r;
+    }
     J.ray_begin = ray_begin;
     J.ray_count = ray_count;
     J.packet_first = call.n_packets;
@@ -860,6 +926,7 @@ sbr_status sbr_context_create(int32_t device, void* hip_stream, sbr_context** ou
         c->lookahead_depth = env_int("SBR_LOOKAHEAD_DEPTH", 3, 1, 3);
         c->lookahead3_max_paths = env_int("SBR_LOOKAHEAD3_PATHS", 256, 0, 1 << 30);
         c->la3_lds = env_int("SBR_LA3_LDS", 1, 0, 1) != 0;
+        c->ray_order = env_int("SBR_RAY_ORDER", 1, 0, 1);
         if (refine_la3_set_lds_limit(c->lds_max - 1024) != hipSuccess) {
             (void)hipGetLastError();
             c->la3_lds = false;
@@ -889,6 +956,7 @@ sbr_status sbr_context_get_tuning(const sbr_context* c, sbr_tuning* t)
     t->lookahead_depth = c->lookahead_depth;
     t->lookahead3_max_paths = c->lookahead3_max_paths;
     t->grid_check_log2 = c->grid_check_log2;
+    t->ray_order = c->ray_order;
     return SBR_OK;
 }
 
@@ -902,7 +970,8 @@ sbr_status sbr_context_set_tuning(sbr_context* c, const sbr_tuning* t)
         t->stack_depth < 0 || t->stack_depth > kTraceStack || t->lds_budget < 0 ||
         t->lds_budget > c->lds_max || t->rx_tree_min < 1 || t->lookahead_max_paths < 0 ||
         t->lookahead_depth < 1 || t->lookahead_depth > 3 || t->lookahead3_max_paths < 0 ||
-        t->grid_check_log2 < 0 || t->grid_check_log2 > 200)
+        t->grid_check_log2 < 0 || t->grid_check_log2 > 200 || t->ray_order < 0 ||
+        t->ray_order > 1)
         return fail(c, SBR_E_INVALID_ARG, "tuning field out of range");
     if (t->grid_check_log2 != c->grid_check_log2) {
         // cached grids were made under the old setting (they are the same
@@ -920,6 +989,7 @@ sbr_status sbr_context_set_tuning(sbr_context* c, const sbr_tuning* t)
     c->lookahead_depth = t->lookahead_depth;
     c->lookahead3_max_paths = t->lookahead3_max_paths;
     c->grid_check_log2 = t->grid_check_log2;
+    c->ray_order = t->ray_order;
     return SBR_OK;
 }
 
@@ -930,6 +1000,7 @@ sbr_status sbr_context_destroy(sbr_context* c)
     (void)use_device(c->device);
     (void)hipStreamSynchronize(c->stream);
     for (auto& kv : c->grids) release(kv.second);
+    for (auto& kv : c->orders) release(kv.second);
     DevBuf* bufs[] = {&c->grid_scratch, &c->rx,    &c->rx32,  &c->cand,  &c->idx,  &c->flags,
                       &c->offs,         &c->scan,  &c->uniq,  &c->refine, &c->paths,
                       &c->keep,         &c->outp,  &c->counters, &c->rays_tri, &c->rays_t, &c->tally,
@@ -1285,7 +1356,7 @@ bool same_tuning(const sbr_context* c, const sbr_tuning& t)
            now.lookahead_max_paths == t.lookahead_max_paths &&
            now.lookahead_depth == t.lookahead_depth &&
            now.lookahead3_max_paths == t.lookahead3_max_paths &&
-           now.grid_check_log2 == t.grid_check_log2;
+           now.grid_check_log2 == t.grid_check_log2 && now.ray_order == t.ray_order;
 }
 
 bool graph_matches(const sbr_context* c, const sbr_scene* s, const double* rx, int32_t n_rx,

@@ -123,6 +123,7 @@ struct JobDev {
     int32_t iterations, subrays, keep_invalid;
     float delta;           // box inflation (m) making FP32 traversal conservative
     int32_t rx_root;       // root of the job's receiver tree; -1: test every receiver
+    const uint32_t* order; // whole-grid jobs: the order rays are handed out in (NULL: by index)
 };
 
 // Everything the kernels of one call see.
@@ -148,6 +149,10 @@ hipError_t launch_rx32(const double* rx, int64_t n, float4* out, hipStream_t s,
 // check_log2 scales the error bounds of the equiangular grid's fast pass.
 hipError_t launch_grid(GridDev g, hipStream_t s, void* scratch, int32_t check_log2 = 0);
 size_t grid_scratch_bytes(int32_t n);
+// cell[i] = the cube-map cell (R x R per cube face, Z order) of ray i's
+// direction, R a power of two <= 8192.
+hipError_t launch_ray_cells(const double* dir, int64_t N, int32_t R, uint32_t* cell,
+                            hipStream_t s);
 
 // Persistent trace + reception over all packets of the call.  Reception
 // events are appended to cand (up to cap; *cand_count counts all); queue is a

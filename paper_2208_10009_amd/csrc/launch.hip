@@ -498,6 +498,42 @@ __global__ void k_grid_equidistant(int32_t n, int64_t N, const char* __restrict_
     dir[2 * N + i0] = r.z;
 }
 
+// ===========================================================================
+// Hand-out order of a grid's rays
+// ===========================================================================
+// The cell of each ray on a cube map over the sphere: the face of the largest
+// coordinate (2 axis + sign), then the Z-order index of the other two
+// coordinates over that one, quantized to R x R (R a power of two).  Sorted
+// by cell, rays next to each other in the order are close in direction.
+__global__ void k_ray_cells(const double* __restrict__ dir, int64_t N, int32_t R,
+                            uint32_t* __restrict__ cell)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double v[3] = {dir[i], dir[N + i], dir[2 * N + i]};
+    int ax = 0;
+    if (fabs(v[1]) > fabs(v[ax])) ax = 1;
+    if (fabs(v[2]) > fabs(v[ax])) ax = 2;
+    const double m = fabs(v[ax]);
+    const double u = v[(ax + 1) % 3] / m, w = v[(ax + 2) % 3] / m;
+    const int iu = min(R - 1, max(0, (int)((u + 1.0) * 0.5 * (double)R)));
+    const int iw = min(R - 1, max(0, (int)((w + 1.0) * 0.5 * (double)R)));
+    uint32_t z = 0;
+    for (int b = 0; (1 << b) < R; ++b)
+        z |= (uint32_t)((iu >> b) & 1) << (2 * b) | (uint32_t)((iw >> b) & 1) << (2 * b + 1);
+    const uint32_t face = (uint32_t)(2 * ax + (v[ax] < 0.0 ? 1 : 0));
+    cell[i] = face * (uint32_t)R * (uint32_t)R + z;
+}
+
+hipError_t launch_ray_cells(const double* dir, int64_t N, int32_t R, uint32_t* cell,
+                            hipStream_t s)
+{
+    if (N <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ray_cells, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, dir, N, R,
+                       cell);
+    return hipGetLastError();
+}
+
 hipError_t launch_grid(GridDev g, hipStream_t s, void* scratch, int32_t check_log2)
 {
     if (g.launch != SBR_LAUNCH_EQUIANGULAR) {

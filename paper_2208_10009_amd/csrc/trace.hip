@@ -27,8 +27,9 @@ struct RayState {
     int32_t faces[SBR_MAX_ORDER];
 };
 
-__device__ static inline void start_ray(const JobDev& J, int64_t r, RayState& R)
+__device__ static inline void start_ray(const JobDev& J, int64_t i, RayState& R)
 {
+    const int64_t r = J.order ? (int64_t)gld((const int32_t*)J.order + i) : i;
     R.r = r;
     R.o = mk(J.tx[0], J.tx[1], J.tx[2]);
     R.d = mk(gld(J.dir + r), gld(J.dir + J.N + r), gld(J.dir + 2 * J.N + r));

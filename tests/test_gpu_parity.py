@@ -458,7 +458,8 @@ def test_tuning_roundtrip_and_invariance(gpu):
                   dict(lds_budget=65536, stack_depth=8, trace_block=128),
                   dict(lds_budget=24 * 4 * 256, stack_depth=24),
                   dict(lookahead_max_paths=0, trace_chunk=64), dict(rx_tree_min=1),
-                  dict(lookahead_depth=2), dict(lookahead_depth=1)):
+                  dict(lookahead_depth=2), dict(lookahead_depth=1), dict(ray_order=0),
+                  dict(ray_order=0, trace_chunk=2, lds_budget=24 * 4 * 256)):
             gpu.set_tuning(**dict(base, **t))
             assert gpu.tuning()["trace_chunk"] == dict(base, **t)["trace_chunk"]
             got, _ = sc.trace(cfg["tx"], cfg["rx"], **prm)
@@ -469,9 +470,43 @@ def test_tuning_roundtrip_and_invariance(gpu):
             gpu.set_tuning(rx_tree_min=0)
         with pytest.raises(sbr.SbrError):
             gpu.set_tuning(lookahead_depth=4)
+        with pytest.raises(sbr.SbrError):
+            gpu.set_tuning(ray_order=2)
     finally:
         gpu.set_tuning(**base)
         sc.close()
+
+
+def test_ray_order_full_size(gpu, orc):
+    """Whole-grid jobs hand their rays out sorted by direction cell
+    (ray_order = 1, the default) or by index (0): at the benchmark's full size
+    (n = 200, 6 reflections, 64 Rx) and at n = 1000 the path records and the
+    per-ray traces are byte-identical, and match the oracle."""
+    base = gpu.tuning()
+    assert base["ray_order"] == 1
+    cfg = scenes.manhattan_config(0)
+    sc = gpu.scene(cfg["scene"])
+    try:
+        got = {}
+        for o in (1, 0):
+            gpu.set_tuning(**dict(base, ray_order=o))
+            g, st = sc.trace(cfg["tx"], cfg["rx"], **cfg["params"])
+            t, T = sc.trace_rays(cfg["tx"], 200, 6)
+            g2, _ = sc.trace(cfg["tx"], cfg["rx"][:8], **dict(cfg["params"], division_n=1000,
+                                                                 max_order=2, iterations=1))
+            got[o] = (g, t, T, g2)
+    finally:
+        gpu.set_tuning(**base)
+        sc.close()
+    for a, b in zip(got[0], got[1]):
+        assert a.tobytes() == b.tobytes()
+    g, t, T, g2 = got[1]
+    assert len(g) > 100 and len(g2) > 0 and t.shape == (400002, 7)
+    o = orc.run(cfg["scene"], cfg["tx"], cfg["rx"], **cfg["params"])["paths"]
+    _compare_paths(g, o)
+    ids = np.unique(np.random.default_rng(12).integers(0, 400002, 3000))
+    ot, _, oT = orc.trace_rays(cfg["scene"], cfg["tx"], 200, 6, ids=ids)
+    assert np.array_equal(t[ids], ot) and np.array_equal(bits(T[ids]), bits(oT))
 
 
 # --------------------------------------------------- device-memory variant --
