@@ -154,9 +154,9 @@ typedef struct {
  * recomputes that layer with the full series (same grid; larger values only
  * send more layers through the full series).  With ray_order = 1 a job that
  * traces every ray of its grid hands its rays to the waves sorted by
- * direction (cube-map cells in Z order, the order made once per grid), so
- * the 64 rays of a wave leave in nearby directions and traverse the same BVH
- * nodes; 0 hands them out by index (same results). */
+ * direction (cube-map cells in Z order, the order made once per grid of at
+ * most 2^27 rays), so the 64 rays of a wave leave in nearby directions and
+ * traverse the same BVH nodes; 0 hands them out by index (same results). */
 typedef struct {
     int32_t trace_chunk;         /* 1..64                                   */
     int32_t persist_blocks;      /* >= 1                                    */

@@ -204,6 +204,11 @@ sbr_status get_grid(sbr_context* c, int32_t launch, int32_t n, GridDev* g, bool*
     return SBR_OK;
 }
 
+// Grids up to this many rays (n = 3663 on the icosahedron) get a hand-out
+// order; larger ones, whose order would take seconds and gigabytes of host
+// memory to make, are traced by index.
+constexpr int64_t kOrderMaxRays = int64_t(1) << 27;
+
 // A hand-out order of a grid's rays that keeps each wave's rays close in
 // direction: rays sorted by their cube-map cell (about one ray per cell, cells
 // in Z order per cube face; launch_ray_cells), by index within a cell
@@ -467,7 +472,7 @@ sbr_status add_job(sbr_context* c, Call& call, int32_t scene_idx, const double* 
     J.dir = g.dir;
     J.N = g.N;
     J.order = nullptr;
-    if (c->ray_order && ray_begin == 0 && ray_count == g.N) {
+    if (c->ray_order && ray_begin == 0 && ray_count == g.N && g.N <= kOrderMaxRays) {
         r = get_order(c, p->launch, p->division_n, g, &J.order);
         if (r) return r;
     }
