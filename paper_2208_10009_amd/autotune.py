@@ -12,7 +12,9 @@ import time
 
 DEFAULT_SPACE = {
     "trace_chunk": [1, 2, 4],
-    "persist_blocks": [1024, 2048, 4096],
+    # four workgroups per CU fill the machine; a small scene's trace runs
+    # faster with fewer (its BVH then shares each CU's L1 among fewer waves)
+    "persist_blocks": [1024, 2048, 640, 768],
     "lds_budget": [0, 65536],
     "stack_depth": [16],
     "trace_block": [256],
