@@ -196,6 +196,21 @@ def test_paths_shoebox_target_and_invalid(gpu, orc, S):
     assert (g["flags"] & 4).any()  # the target stop is taken
 
 
+@pytest.mark.parametrize("K,iters", [(0, 3), (0, 0), (8, 3), (8, 0)])
+def test_paths_order_extremes(gpu, orc, K, iters):
+    """No reflections (direct paths only) and the most the records hold
+    (SBR_MAX_ORDER = 8), with and without refinement, in the closed shoebox
+    and the Manhattan scene: every record field against the oracle."""
+    for cfg, n in ((scenes.shoebox_config(4), 20), (scenes.manhattan_config(3, n_rx=8), 30)):
+        prm = dict(cfg["params"], max_order=K, division_n=n, iterations=iters)
+        g, o, st = _run_both(gpu, orc, cfg, **prm)
+        _compare_paths(g, o)
+        assert len(g) > 0 and (g["order"] <= K).all()
+        if K == 0:
+            assert (g["order"] == 0).all()
+        assert st["n_rays"] == 10 * n * n + 2
+
+
 def test_paths_traditional_sbr(gpu, orc):
     cfg = scenes.shoebox_config(2)
     prm = dict(cfg["params"], iterations=0)
