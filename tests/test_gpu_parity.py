@@ -211,6 +211,25 @@ def test_paths_order_extremes(gpu, orc, K, iters):
         assert st["n_rays"] == 10 * n * n + 2
 
 
+def test_degenerate_receivers(gpu, orc):
+    """Receivers at the transmitter, 1e-9 m from it, on a wall, in a room
+    corner, and a repeated receiver: the same records as the oracle, and the
+    repeated receiver gets the same paths as its twin."""
+    cfg = scenes.shoebox_config(1)
+    tx = cfg["tx"]
+    rx = np.array([tx, tx + np.array([1e-9, 0.0, 0.0]), [0.0, 4.0, 1.5], [10.0, 8.0, 3.0],
+                   [6.5, 2.25, 0.75], [6.5, 2.25, 0.75], [5.0, 4.0, 0.0]])
+    cfg = dict(cfg, rx=rx)
+    prm = dict(cfg["params"], max_order=3, division_n=30, iterations=3)
+    g, o, _ = _run_both(gpu, orc, cfg, **prm)
+    _compare_paths(g, o)
+    a, b = g[g["rx"] == 4], g[g["rx"] == 5]
+    assert len(a) > 0 and len(a) == len(b)
+    for f in a.dtype.names:
+        if f != "rx":
+            assert a[f].tobytes() == b[f].tobytes(), f
+
+
 def test_paths_traditional_sbr(gpu, orc):
     cfg = scenes.shoebox_config(2)
     prm = dict(cfg["params"], iterations=0)
