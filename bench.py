@@ -203,7 +203,7 @@ def large_city_leg(ctx, scenes, torch, steps=5):
     best, _ = autotune.autotune(
         ctx, lambda: sc.trace_device(cfg["tx"], rx_tune, **prm),
         space={"trace_chunk": [1, 2], "persist_blocks": [1024, 2048, 640, 768],
-               "rx_tree_min": [16, 1 << 30], "lds_budget": [0, 24 * 4 * 256],
+               "rx_tree_min": [16, 1 << 30], "lds_budget": [65536, 0, 24 * 4 * 256],
                "stack_depth": [24]}, warmup=1, steps=2)
     log("large city tuning", best)
 
@@ -340,8 +340,8 @@ def main():
     rx_tune = torch.as_tensor(cfg["rx"], device="cuda")
     best, _ = autotune.autotune(
         ctx, lambda: sc.trace_device(cfg["tx"], rx_tune, **prm),
-        space={"trace_chunk": [1, 2], "persist_blocks": [1024, 2048, 640, 704, 768],
-               "lds_budget": [0, 24 * 4 * 256], "stack_depth": [24],
+        space={"trace_chunk": [1, 2], "persist_blocks": [640, 704, 768, 1024, 2048],
+               "lds_budget": [65536, 0, 24 * 4 * 256], "stack_depth": [24],
                "lookahead_max_paths": [4096], "rx_tree_min": [16, 1 << 30]}, warmup=1, steps=5)
     log("tuning", best)
 

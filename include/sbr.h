@@ -143,7 +143,7 @@ typedef struct {
  * (256 lanes per workgroup).
  * With at most lookahead_max_paths paths the refinement resolves
  * lookahead_depth iterations per traversal step (3: a 512-lane workgroup per
- * path, used without an LDS plan and for at most lookahead3_max_paths paths,
+ * path, with its own LDS plan, for at most lookahead3_max_paths paths,
  * since it traces 399 sub-rays per path and step; 2: one wave per path);
  * otherwise, or with depth 1, one iteration per step with eight lanes per
  * path.  A job with at least rx_tree_min receivers tests reception through

@@ -209,7 +209,7 @@ struct RefineOut {
 // iterations per step; depth 2: one wave per path, two iterations per step;
 // depth 1: eight lanes per path, one iteration per step.
 // L3 is the plan of the three-level kernel (512 lanes; bytes == 0: global
-// memory), used when depth >= 3 and L has no LDS.
+// memory), used when depth >= 3 whatever L is.
 hipError_t launch_refine(const CallDev& call, const LdsPlan& L, const LdsPlan& L3,
                          const SceneDev& s0, const sbr_candidate* uniq, int64_t U_max,
                          const int32_t* n_dev, int depth, RefineOut* out, PathGeom* geom,

@@ -495,13 +495,14 @@ hipError_t launch_refine(const CallDev& call, const LdsPlan& L, const LdsPlan& L
                          int32_t* err, hipStream_t s)
 {
     if (U <= 0) return hipSuccess;
-    if (depth >= 3 && L.bytes == 0) {
+    // the three-level kernel has its own LDS plan (L3), whatever the trace's
+    if (depth >= 3) {
         if (L3.bytes > 0)
             hipLaunchKernelGGL(k_refine_la3<true>, dim3((unsigned)U), dim3(512), L3.bytes, s, call,
                                L3, s0, uniq, U, n_dev, out, geom, err);
         else
-            hipLaunchKernelGGL(k_refine_la3<false>, dim3((unsigned)U), dim3(512), 0, s, call, L,
-                               s0, uniq, U, n_dev, out, geom, err);
+            hipLaunchKernelGGL(k_refine_la3<false>, dim3((unsigned)U), dim3(512), 0, s, call,
+                               LdsPlan{}, s0, uniq, U, n_dev, out, geom, err);
         return hipGetLastError();
     }
     const bool lookahead = depth >= 2;
