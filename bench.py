@@ -185,7 +185,7 @@ def batch_vs_plain(ctx, scenes, torch, seed=0, steps=2):
     }
 
 
-def large_city_leg(ctx, scenes, torch, steps=5):
+def large_city_leg(ctx, scenes, torch, steps=5, tuning=None):
     """The large procedural city (about 500k triangles, 1024 Rx on a 32 x 32
     grid, n = 1000: 10,000,002 rays, K = 8, I = 5, S = 6), one sbr_trace call
     per step with the launch grid recomputed: rays/s, stage times, the trace
@@ -200,11 +200,15 @@ def large_city_leg(ctx, scenes, torch, steps=5):
     from paper_2208_10009_amd import autotune
     entry_tuning = ctx.tuning()
     rx_tune = torch.as_tensor(cfg["rx"], device="cuda")
-    best, _ = autotune.autotune(
-        ctx, lambda: sc.trace_device(cfg["tx"], rx_tune, **prm),
-        space={"trace_chunk": [1, 2], "persist_blocks": [1024, 2048, 640, 768],
-               "rx_tree_min": [16, 1 << 30], "lds_budget": [65536, 0, 24 * 4 * 256],
-               "stack_depth": [24]}, warmup=1, steps=2)
+    if tuning:
+        ctx.set_tuning(**dict(entry_tuning, **tuning))
+        best = tuning
+    else:
+        best, _ = autotune.autotune(
+            ctx, lambda: sc.trace_device(cfg["tx"], rx_tune, **prm),
+            space={"trace_chunk": [1, 2], "persist_blocks": [1024, 2048, 640, 768],
+                   "rx_tree_min": [16, 1 << 30], "lds_budget": [65536, 0, 24 * 4 * 256],
+                   "stack_depth": [24]}, warmup=1, steps=2)
     log("large city tuning", best)
 
     from paper_2208_10009_amd import sbr
@@ -301,6 +305,11 @@ def main():
                     help="skip the launch-grid / traditional-vs-precise comparison")
     ap.add_argument("--large-only", action="store_true",
                     help="run only the large-city leg and print its JSON object (profiling)")
+    ap.add_argument("--tuning", type=json.loads, default=None, metavar="JSON",
+                    help="tuning fields for the stated configuration instead of autotuning "
+                         "(profiling runs pin what an earlier run chose)")
+    ap.add_argument("--large-tuning", type=json.loads, default=None, metavar="JSON",
+                    help="the same for the large-city leg")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 5 times (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -325,7 +334,7 @@ def main():
         return
     if args.large_only:
         ctx = sbr.Context(0)
-        print(json.dumps(large_city_leg(ctx, scenes, torch)), flush=True)
+        print(json.dumps(large_city_leg(ctx, scenes, torch, tuning=args.large_tuning)), flush=True)
         ctx.close()
         return
     cfg = scenes.manhattan_config(args.seed)
@@ -338,11 +347,16 @@ def main():
     log("counts", counts)
     from paper_2208_10009_amd import autotune
     rx_tune = torch.as_tensor(cfg["rx"], device="cuda")
-    best, _ = autotune.autotune(
-        ctx, lambda: sc.trace_device(cfg["tx"], rx_tune, **prm),
-        space={"trace_chunk": [1, 2], "persist_blocks": [640, 704, 768, 1024, 2048],
-               "lds_budget": [65536, 0, 24 * 4 * 256], "stack_depth": [24],
-               "lookahead_max_paths": [4096], "rx_tree_min": [16, 1 << 30]}, warmup=1, steps=5)
+    if args.tuning:
+        ctx.set_tuning(**dict(ctx.tuning(), **args.tuning))
+        best = args.tuning
+    else:
+        best, _ = autotune.autotune(
+            ctx, lambda: sc.trace_device(cfg["tx"], rx_tune, **prm),
+            space={"trace_chunk": [1, 2], "persist_blocks": [640, 704, 768, 1024, 2048],
+                   "lds_budget": [65536, 0, 24 * 4 * 256], "stack_depth": [24],
+                   "lookahead_max_paths": [4096], "rx_tree_min": [16, 1 << 30]}, warmup=1,
+            steps=5)
     log("tuning", best)
 
     # Inputs resident in HBM: the receivers are a device tensor and the paths
@@ -459,7 +473,7 @@ def main():
     }
     sc.close()
     if not args.no_large:
-        out["large_city"] = large_city_leg(ctx, scenes, torch)
+        out["large_city"] = large_city_leg(ctx, scenes, torch, tuning=args.large_tuning)
         log("large city", json.dumps(out["large_city"]))
     if not args.no_variants:
         out["launch_variants"] = launch_variants(ctx, scenes, torch)
