@@ -91,6 +91,75 @@ __device__ static inline bool rx_may_capture32(const Seg32& g, float4 r)
     return !(ww > (A * A) * (1.0f + 0x1p-18f));
 }
 
+// Bounding box of a job's FP32 receivers and the largest of their max
+// |coordinate|, reduced over the wave (all 64 lanes take part).
+struct RxBox {
+    float lo[3], hi[3], w;
+};
+
+__device__ static RxBox rx_box(const float4* __restrict__ rx32, int32_t first, int32_t n)
+{
+    RxBox b;
+    for (int a = 0; a < 3; ++a) {
+        b.lo[a] = INFINITY;
+        b.hi[a] = -INFINITY;
+    }
+    b.w = 0.0f;
+    for (int32_t x = (int32_t)(threadIdx.x & 63); x < n; x += 64) {
+        const float4 r = gld(rx32 + first + x);
+        b.lo[0] = fminf(b.lo[0], r.x);
+        b.lo[1] = fminf(b.lo[1], r.y);
+        b.lo[2] = fminf(b.lo[2], r.z);
+        b.hi[0] = fmaxf(b.hi[0], r.x);
+        b.hi[1] = fmaxf(b.hi[1], r.y);
+        b.hi[2] = fmaxf(b.hi[2], r.z);
+        b.w = fmaxf(b.w, r.w);
+    }
+    for (int off = 32; off >= 1; off >>= 1)
+        for (int a = 0; a < 3; ++a) {
+            b.lo[a] = fminf(b.lo[a], __shfl_xor(b.lo[a], off));
+            b.hi[a] = fmaxf(b.hi[a], __shfl_xor(b.hi[a], off));
+        }
+    for (int off = 32; off >= 1; off >>= 1) b.w = fmaxf(b.w, __shfl_xor(b.w, off));
+    // wave-uniform: held in scalar registers
+    auto uni = [](float v) {
+        return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+    };
+    for (int a = 0; a < 3; ++a) {
+        b.lo[a] = uni(b.lo[a]);
+        b.hi[a] = uni(b.hi[a]);
+    }
+    b.w = uni(b.w);
+    return b;
+}
+
+// Whether any receiver in box b can pass rx_may_capture32 on segment g.  A
+// receiver that passes is r = o + tc d + w with -dl < tc <= t + dl and
+// |w| <= A(tc) = c0 + thl tc up to factors 1 + 2^-19 (c0 = thl (D + dl) + dl),
+// so along each axis r lies between the linear functions
+// o + tc (d -+ thl) -+ c0 of tc, whose extremes over that range are at its
+// ends (infinite for an escaping segment on the side it heads to).  A margin
+// of 0.1% of the coordinates, the unfolded length and the segment covers the
+// roundings of this bound and of the pre-test.
+__device__ static inline bool rx_box_may(const Seg32& g, const RxBox& b)
+{
+    const float dl = fmaf(0x1p-18f, b.w, g.dl);
+    const float c0 = fmaf(g.thl, g.D + dl, dl);
+    const float T = g.t + dl;
+    const float M = fmaxf(fmaxf(fabsf(g.ox), fabsf(g.oy)), fabsf(g.oz)) + g.D;
+    const float m = 1e-3f * (1.0f + M + (T < INFINITY ? T : 0.0f));
+    const float o[3] = {g.ox, g.oy, g.oz}, d[3] = {g.dx, g.dy, g.dz};
+    bool may = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float dm = d[a] - g.thl, dp = d[a] + g.thl;
+        const float lo = o[a] + (dm >= 0.0f ? -dl * dm : T * dm) - c0 - m;
+        const float hi = o[a] + (dp <= 0.0f ? -dl * dp : T * dp) + c0 + m;
+        may = may && !(lo > b.hi[a]) && !(hi < b.lo[a]);
+    }
+    return may;
+}
+
 // Per-call preparation in one launch: the FP32 receivers, and zeroing of
 // n_zero 32-bit words (the call's counters).
 __global__ void k_prep(const double* __restrict__ rx, int64_t n, float4* __restrict__ out,
@@ -174,6 +243,7 @@ __global__ __launch_bounds__(256) void k_trace(CallDev call, LdsPlan L, SceneDev
     uint32_t segs = 0, events = 0;
     JobDev J{};
     SceneDev S = s0;
+    RxBox box{};  // the current job's receivers (linear reception test)
     int64_t next = 0, pend = 0;  // rays of the current packet not yet handed out
     RayState R;
     R.r = -1;
@@ -200,6 +270,7 @@ __global__ __launch_bounds__(256) void k_trace(CallDev call, LdsPlan L, SceneDev
             }
             J = call.jobs[lo];
             if (!LDS) S = call.scenes[J.scene];
+            if (J.rx_root < 0) box = rx_box(call.rx32, J.rx_first, J.n_rx);
             next = J.ray_begin + ((int64_t)pk - J.packet_first) * 64 * call.chunk;
             pend = min(next + 64 * (int64_t)call.chunk, J.ray_begin + J.ray_count);
             continue;
@@ -219,12 +290,14 @@ __global__ __launch_bounds__(256) void k_trace(CallDev call, LdsPlan L, SceneDev
         const Seg32 g32 = seg32(R, t, J.thl);
         if (J.rx_root < 0) {
             // FP32 pre-test of every receiver (wave-uniform, scalar loads),
-            // the FP64 test for the few it lets through
-            for (int x = 0; x < J.n_rx; ++x) {
-                const int32_t gx = J.rx_first + x;
-                if (rx_may_capture32(g32, cld4(call.rx32 + gx)))
-                    receive(J, call.rx, R, t, gx, cand, cap, ccount, &events, COUNT);
-            }
+            // the FP64 test for the few it lets through; skipped when no
+            // busy lane's segment can reach the receivers' box
+            if (__ballot(rx_box_may(g32, box)) != 0)
+                for (int x = 0; x < J.n_rx; ++x) {
+                    const int32_t gx = J.rx_first + x;
+                    if (rx_may_capture32(g32, cld4(call.rx32 + gx)))
+                        receive(J, call.rx, R, t, gx, cand, cap, ccount, &events, COUNT);
+                }
         } else {
             // stackless preorder walk of the job's receiver tree
             int32_t nd = J.rx_root;
