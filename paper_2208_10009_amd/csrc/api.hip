@@ -727,7 +727,11 @@ sbr_status run_paths(sbr_context* c, Call& call, sbr_path* out, int64_t capacity
     HIPCHK(c, ensure(c->keep, sizeof(int32_t) * U1));
     HIPCHK(c, ensure(c->offs, sizeof(int32_t) * U1));
     HIPCHK(c, ensure(c->scan, scan_scratch_bytes(Umax)));
-    HIPCHK(c, launch_solve(call.dev, lp256, call.s0, c->uniq.as<sbr_candidate>(),
+    // the solve traverses from global memory (one traversal per lane: staging
+    // the scene in LDS costs more than it saves)
+    LdsPlan lps{};
+    lps.block = 256;
+    HIPCHK(c, launch_solve(call.dev, lps, call.s0, c->uniq.as<sbr_candidate>(),
                            c->refine.as<RefineOut>(), c->geom.as<PathGeom>(), Umax, ndev,
                            c->paths.as<sbr_path>(), c->keep.as<int32_t>(), &dc->err, st));
     HIPCHK(c, hipEventRecord(c->ev[5], st));
@@ -1473,7 +1477,9 @@ sbr_status capture_graph(sbr_context* c, sbr_scene* s, Call& call, const double*
     step(launch_refine(call.dev, lp256, plan_la3(s), call.s0, c->uniq.as<sbr_candidate>(), u_cap,
                        &dc->n_unique, depth, c->refine.as<RefineOut>(), c->geom.as<PathGeom>(),
                        &dc->err, st));
-    step(launch_solve(call.dev, lp256, call.s0, c->uniq.as<sbr_candidate>(),
+    LdsPlan lps{};
+    lps.block = 256;
+    step(launch_solve(call.dev, lps, call.s0, c->uniq.as<sbr_candidate>(),
                       c->refine.as<RefineOut>(), c->geom.as<PathGeom>(), u_cap, &dc->n_unique,
                       c->paths.as<sbr_path>(), c->keep.as<int32_t>(), &dc->err, st));
     step(launch_emit_small(c->paths.as<sbr_path>(), c->keep.as<int32_t>(), u_cap, &dc->n_unique,
