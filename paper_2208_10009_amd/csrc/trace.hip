@@ -243,7 +243,7 @@ __global__ __launch_bounds__(256) void k_trace(CallDev call, LdsPlan L, SceneDev
     uint32_t segs = 0, events = 0;
     JobDev J{};
     SceneDev S = s0;
-    RxBox box{};  // the current job's receivers (linear reception test)
+    RxBox box{};  // box of the current job's receivers
     int64_t next = 0, pend = 0;  // rays of the current packet not yet handed out
     RayState R;
     R.r = -1;
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(256) void k_trace(CallDev call, LdsPlan L, SceneDev
             }
             J = call.jobs[lo];
             if (!LDS) S = call.scenes[J.scene];
-            if (J.rx_root < 0) box = rx_box(call.rx32, J.rx_first, J.n_rx);
+            box = rx_box(call.rx32, J.rx_first, J.n_rx);
             next = J.ray_begin + ((int64_t)pk - J.packet_first) * 64 * call.chunk;
             pend = min(next + 64 * (int64_t)call.chunk, J.ray_begin + J.ray_count);
             continue;
@@ -298,8 +298,9 @@ __global__ __launch_bounds__(256) void k_trace(CallDev call, LdsPlan L, SceneDev
                     if (rx_may_capture32(g32, cld4(call.rx32 + gx)))
                         receive(J, call.rx, R, t, gx, cand, cap, ccount, &events, COUNT);
                 }
-        } else {
-            // stackless preorder walk of the job's receiver tree
+        } else if (rx_box_may(g32, box)) {
+            // stackless preorder walk of the job's receiver tree (lanes whose
+            // segment cannot reach the receivers' box skip it)
             int32_t nd = J.rx_root;
             const int32_t end = call.rx_nodes[nd].skip;
             while (nd != end) {
