@@ -166,6 +166,28 @@ def test_candidates_manhattan_full(gpu, orc):
     assert len(g) > 50
 
 
+@pytest.mark.parametrize("tree", [False, True])
+def test_candidates_receivers_everywhere(gpu, orc, tree):
+    """Receivers spread through the whole volume (at ground level, between
+    and above the buildings, above the transmitter), tested one by one and
+    through the receiver tree: a wave skips its receivers only where no
+    receiver can be captured, so the events equal the oracle's bit for bit."""
+    rng = np.random.default_rng(21)
+    cfg = scenes.manhattan_config(2)
+    rx = np.column_stack([rng.uniform(-20.0, 340.0, 48), rng.uniform(-20.0, 340.0, 48),
+                          np.concatenate([rng.uniform(0.0, 2.0, 16), rng.uniform(2.0, 70.0, 24),
+                                          rng.uniform(70.0, 200.0, 8)])])
+    cfg = dict(cfg, rx=rx)
+    prm = dict(cfg["params"], division_n=80, max_order=4)
+    base = gpu.tuning()
+    try:
+        gpu.set_tuning(**dict(base, rx_tree_min=1 if tree else 1 << 30))
+        g = _compare_candidates(gpu, orc, cfg, **prm)
+    finally:
+        gpu.set_tuning(**base)
+    assert len(g) > 50 and len(np.unique(g["rx"])) > 20
+
+
 # ------------------------------------------------------------ full paths --
 def _run_both(gpu, orc, cfg, **prm):
     sc = gpu.scene(cfg["scene"])
