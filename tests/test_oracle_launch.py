@@ -396,3 +396,60 @@ def test_trig_correctly_rounded(orc):
         m_lo = (Decimal(lo) + Decimal(t)) / 2
         m_hi = (Decimal(t) + Decimal(hi)) / 2
         assert dcos(m_lo) >= C_ >= dcos(m_hi)
+
+
+def _face_rings(d, n, f_i):
+    """Interior rings of face f_i (oracle ray order: a contiguous block per
+    face, ring after ring, each of 3(n - 3a) points with its corners at
+    positions 0, m, 2m)."""
+    per_face = (n - 1) * (n - 2) // 2
+    base = 12 + 30 * (n - 1) + f_i * per_face
+    rings, off, a = [], 0, 1
+    while n - 3 * a >= 1:
+        m = n - 3 * a
+        rings.append((m, d[base + off: base + off + 3 * m]))
+        off += 3 * m
+        a += 1
+    return rings
+
+
+@pytest.mark.parametrize("n", [4, 7, 10, 20])
+def test_inner_corners_are_flat_face_parallelogram_completions(orc, n):
+    """Eq. (2), Sec. II.B and Fig. 3b: every corner X of ring a+1 completes
+    the parallelogram of its corner P^0 on ring a and the two ring-a points
+    P^1, P^-1 next to it, X = P^1 + P^-1 - P^0, on the flat icosahedron face.
+    The points are taken from the oracle's grid and centrally projected onto
+    the face's plane here; the neighbours are found geometrically (ring 0 is
+    the face's vertices and edge points)."""
+    d = orc.launch_dirs(n)
+    V = d[:12]
+    faces = ico_faces(V)
+    adj = V @ V.T > 0
+    edges = [(i, j) for i in range(12) for j in range(i + 1, 12) if adj[i, j]]
+    worst = 0.0
+    for f_i, f in enumerate(faces):
+        g = V[list(f)].sum(axis=0)
+
+        def proj(p):
+            return p / (p @ g)
+
+        ring0 = [V[v] for v in f]
+        for e_i, (i, j) in enumerate(edges):
+            if i in f and j in f:
+                ring0 += list(d[12 + e_i * (n - 1): 12 + (e_i + 1) * (n - 1)])
+        prev_pts, prev_corners = np.array(ring0), V[list(f)]
+        for m, ring in _face_rings(d, n, f_i):
+            for s in range(3):
+                X = ring[s * m]
+                P0 = prev_corners[np.argmax(prev_corners @ X)]
+                near = np.argsort(-(prev_pts @ P0))
+                assert np.abs(prev_pts[near[0]] - P0).max() == 0.0
+                P1, Pm = prev_pts[near[1]], prev_pts[near[2]]
+                Y = proj(P1) + proj(Pm) - proj(P0)
+                Y /= np.linalg.norm(Y)
+                ang = np.arctan2(np.linalg.norm(np.cross(X, Y)), X @ Y)
+                worst = max(worst, ang)
+            prev_pts, prev_corners = ring, ring[[0, m, 2 * m]]
+    # the same completion on the unit sphere instead of the flat face would
+    # be off by about a tenth of the step angle
+    assert worst < 1e-14, worst

@@ -360,3 +360,300 @@ def test_refined_within_001_deg_of_image_method(orc):
             assert angle_deg(q["aoa"], aoa) <= 0.01
             assert abs(q["length_m"] - L) < 1e-4 * L
         assert len(p) >= 0.85 * len(ims)
+
+
+# --------------------------------------------- reception behind a wall --
+def test_no_reception_behind_the_next_wall(orc):
+    """Reading of eq. (3) with Sec. III.A: a segment receives only up to its
+    next hit (0 < t* <= t).  A receiver just behind a wall that the ray cone
+    meets gets no event; the same receiver in front of the wall, or the wall
+    removed, gets direct-path events."""
+    wall = scenes.SceneBuilder()
+    wall.quad((5, -2, -2), (5, 2, -2), (5, 2, 2), (5, -2, 2), 0)
+    sc = wall.scene([5.0 + 0j])
+    empty = tri_scene(np.zeros((0, 3, 3)), [])
+    tx = np.array([0.0, 0.0, 0.0])
+    # (the decision is on the foot of the perpendicular t*, so receivers within
+    # a few centimetres of the wall plane may fall either way)
+    behind = np.array([[6.0, 0.3, -0.2], [5.5, -0.1, 0.4]])
+    front = np.array([[4.0, 0.3, -0.2], [4.5, -0.1, 0.4]])
+    for K in (0, 2):
+        kw = dict(max_order=K, division_n=15, iterations=0)
+        assert len(orc.run(sc, tx, behind, **kw)["candidates"]) == 0
+        assert len(orc.run(empty, tx, behind, **kw)["candidates"]) > 0
+        c = orc.run(sc, tx, front, **kw)["candidates"]
+        assert set(c["rx"][c["order"] == 0].tolist()) == {0, 1}
+
+
+# ----------------------------------------- refined path quantities --
+def _lattice_cell(tx, axis, k):
+    """Cell of the mirrored-room lattice that the straight line tx + s axis
+    reaches after its k-th wall crossing, and the unfolded length D to that
+    crossing."""
+    ev = unfolded_crossings(tx, axis, BOX, k)
+    D = ev[k - 1][0] if k else 0.0
+    mid = tx + 0.5 * (D + ev[k][0]) * axis
+    return np.floor(mid / BOX).astype(int), D
+
+
+def _image(p, cell):
+    return np.array([cell[a] * BOX[a] + (p[a] if cell[a] % 2 == 0 else BOX[a] - p[a])
+                     for a in range(3)])
+
+
+def _fold(q, cell):
+    return np.array([q[a] - cell[a] * BOX[a] if cell[a] % 2 == 0
+                     else (cell[a] + 1) * BOX[a] - q[a] for a in range(3)])
+
+
+FACE_AXIS = {f: a for (a, _), f in WALL.items()}
+
+
+def _refined_expected(orc, q, tx, rx, eps, freq):
+    """Length, AOA and power of the refined path from its reported departure
+    direction, by unfolding the shoebox into the lattice of mirrored rooms:
+    the ray is the straight line from Tx, its k-th reflection point is at
+    unfolded distance D, the last segment goes to the image of Rx in that
+    cell, and every reflection on a wall normal to axis a has
+    cos(incidence) = |axis_a|."""
+    k = int(q["order"])
+    ax = np.asarray(q["axis"], float)
+    cell, D = _lattice_cell(tx, ax, k)
+    pk = tx + D * ax
+    rxi = _image(rx, cell)
+    L = D + np.linalg.norm(rxi - pk)
+    aoa = _fold(pk, cell) - rx if k else tx - rx
+    aoa /= np.linalg.norm(aoa)
+    lam = C0 / freq
+    P = 20 * math.log10(lam / (4 * math.pi * L))
+    for f in q["face"][:k]:
+        P += 10 * math.log10(orc.fresnel_avg(abs(ax[FACE_AXIS[int(f)]]), eps))
+    return L, aoa, P
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_refined_length_aoa_power_by_unfolding(orc, seed):
+    """The refined path's length, delay, AOA (unit(p_k - Rx), Sec. IV) and
+    power (Friis plus per-reflection Fresnel at the ray's own incidence)
+    for every order-1..3 path of the shoebox, recomputed from the reported
+    axis through the image lattice."""
+    cfg = scenes.shoebox_config(seed)
+    tx, rx = cfg["tx"], cfg["rx"][0]
+    r = orc.run(cfg["scene"], tx, cfg["rx"], **cfg["params"])
+    p = r["paths"]
+    assert (p["order"] >= 2).sum() >= 10
+    for q in p:
+        L, aoa, P = _refined_expected(orc, q, tx, rx, scenes.CONCRETE, 28e9)
+        assert abs(q["length_m"] - L) <= 1e-12 * L
+        assert abs(q["delay_s"] - L / C0) <= 1e-12 * L / C0
+        assert np.abs(q["aoa"] - aoa).max() <= 1e-11
+        assert abs(q["power_dbm"] - P) <= 1e-9
+
+
+def test_refined_length_and_power_converge_at_the_papers_rate(orc):
+    """Sec. III.B after eq. (6) and the conclusion: errors of length and
+    power fall with the iterations like the angle error.  The length error of
+    the refined path is second order in the angle (the exact path is the
+    shortest through its faces, so it is never longer), the power error is
+    first order (Fresnel at a slightly wrong incidence): over 10 iterations
+    the power error falls by about 24 dB and the length error by about
+    twice that."""
+    cfg = scenes.shoebox_config(1)
+    tx = cfg["tx"]
+    errs = {}
+    for it in (0, 10, 20):
+        p = orc.run(cfg["scene"], tx, cfg["rx"], max_order=3, division_n=20, iterations=it,
+                    subrays=7)["paths"]
+        p = p[p["order"] >= 1]
+        dl = p["length_m"] - p["exact_length_m"]
+        assert (dl >= -1e-12 * p["exact_length_m"]).all()
+        errs[it] = (np.abs(dl).mean(), np.abs(p["power_dbm"] - p["exact_power_dbm"]).mean(),
+                    np.radians(p["err_angle_deg"]).mean())
+    for a, b in ((0, 10), (10, 20)):
+        ang = 10 * math.log10(errs[a][2] / errs[b][2])
+        pw = 10 * math.log10(errs[a][1] / errs[b][1])
+        ln = 10 * math.log10(errs[a][0] / errs[b][0])
+        assert 20.0 < ang < 32.0, (a, ang)
+        assert 17.0 < pw < 35.0, (a, pw)
+        assert 38.0 < ln < 64.0, (a, ln)
+
+
+def _wedge_scene():
+    """Two tall walls meeting at 60 degrees along the z axis: wall A in the
+    plane y = 0, wall B in the plane at azimuth 60 degrees."""
+    b = scenes.SceneBuilder()
+    c, s = 0.5, math.sqrt(3.0) / 2
+    b.quad((0, 0, -20), (40, 0, -20), (40, 0, 20), (0, 0, 20), 0)
+    b.quad((0, 0, -20), (40 * c, 40 * s, -20), (40 * c, 40 * s, 20), (0, 0, 20), 1)
+    nA = np.array([0.0, 1.0, 0.0])
+    nB = np.array([s, -c, 0.0])
+    return b.scene([5.3 - 0.4j, 3.8 - 0.1j]), (nA, nB)
+
+
+def _mirror(p, n):
+    return p - 2 * (p @ n) * n      # planes through the origin
+
+
+def test_refined_power_uses_each_reflections_own_incidence(orc):
+    """Two walls at 60 degrees (their normals are not orthogonal, so a
+    reflection on one changes the incidence on the other): for the order-2
+    paths A->B and B->A, the refined power is Friis over the refined length
+    plus the Fresnel loss of each reflection at the incidence of the ray
+    segment arriving there, and it converges to the exact path's power.
+    The points are computed here by intersecting the reported axis ray with
+    the two planes; the exact path by mirror images, checked against the law
+    of reflection."""
+    sc, (nA, nB) = _wedge_scene()
+    eps = sc["eps_r"]
+    tx = np.array([8.0, 3.0, 1.0])
+    rx = np.array([12.0, 4.0, 1.5])
+    freq = 2.4e9
+    p = orc.run(sc, tx, rx[None], max_order=2, division_n=21, iterations=40, subrays=6,
+                target_err_deg=1e-7, freq_hz=freq)["paths"]
+    seqs = {tuple(q["face"][:2]) for q in p if q["order"] == 2}
+    assert seqs == {(0, 1), (1, 0)}
+    lam = C0 / freq
+    for q in p[p["order"] == 2]:
+        f0, f1 = int(q["face"][0]), int(q["face"][1])
+        normals = (nA, nB)
+        # refined path from the reported axis
+        o, d = tx.copy(), np.asarray(q["axis"], float)
+        pts, dins = [], []
+        for f in (f0, f1):
+            n = normals[f]
+            t = -(o @ n) / (d @ n)
+            o = o + t * d
+            pts.append(o)
+            dins.append(d)
+            d = d - 2 * (d @ n) * n
+        L = np.linalg.norm(pts[0] - tx) + np.linalg.norm(pts[1] - pts[0]) + np.linalg.norm(rx - pts[1])
+        P = 20 * math.log10(lam / (4 * math.pi * L))
+        for f, din in zip((f0, f1), dins):
+            P += 10 * math.log10(orc.fresnel_avg(abs(din @ normals[f]) / np.linalg.norm(din), eps[f]))
+        assert abs(q["length_m"] - L) <= 1e-11 * L
+        assert abs(q["power_dbm"] - P) <= 1e-9
+        # exact path by images, then the law of reflection at both points
+        img = _mirror(_mirror(tx, normals[f0]), normals[f1])
+        x1 = rx + (-(rx @ normals[f1]) / ((img - rx) @ normals[f1])) * (img - rx)
+        img0 = _mirror(tx, normals[f0])
+        x0 = x1 + (-(x1 @ normals[f0]) / ((img0 - x1) @ normals[f0])) * (img0 - x1)
+        for X, a, b, n in ((x0, tx, x1, normals[f0]), (x1, x0, rx, normals[f1])):
+            u, w = (X - a) / np.linalg.norm(X - a), (b - X) / np.linalg.norm(b - X)
+            assert np.abs(w - (u - 2 * (u @ n) * n)).max() < 1e-12
+        Le = np.linalg.norm(x0 - tx) + np.linalg.norm(x1 - x0) + np.linalg.norm(rx - x1)
+        Pe = 20 * math.log10(lam / (4 * math.pi * Le))
+        for X, a, n, f in ((x0, tx, normals[f0], f0), (x1, x0, normals[f1], f1)):
+            u = (X - a) / np.linalg.norm(X - a)
+            Pe += 10 * math.log10(orc.fresnel_avg(abs(u @ n), eps[f]))
+        assert abs(q["exact_length_m"] - Le) <= 1e-12 * Le
+        assert abs(q["exact_power_dbm"] - Pe) <= 1e-9
+        assert angle_deg(q["aod"], x0 - tx) <= 1e-7
+        assert abs(q["power_dbm"] - Pe) <= 1e-6
+        assert -1e-13 * Le <= q["length_m"] - Le <= 1e-9 * Le
+
+
+# ------------------------------------------------------------- stalls --
+def test_stalled_path_stops_at_the_launch_ray(orc):
+    """Sec. III.B with reading 11: a sub-ray counts only if it meets the
+    path's faces in order; when none of an iteration's sub-rays does, the
+    path stops there and keeps its axis.  A small hexagonal reflector, 10 m
+    out on one launch ray, subtends half a cone half-angle: the launch ray
+    hits it, the six first-level sub-rays (at 1/sqrt3 of the cone) all miss
+    it, while second-level ones (at 1/3) would hit it."""
+    n, r0 = 10, 287
+    thl = math.atan(2.0) / (math.sqrt(3.0) * n)
+    tx = np.array([0.5, -1.0, 2.0])
+    d0 = orc.launch_dirs(n, [r0])[0]
+    e = np.eye(3)[np.argmin(np.abs(d0))]
+    u = e - (e @ d0) * d0
+    u /= np.linalg.norm(u)
+    nr = -d0 + 0.6 * u
+    nr /= np.linalg.norm(nr)
+    a = np.cross(nr, d0)
+    a /= np.linalg.norm(a)
+    bvec = np.cross(nr, a)
+    c = tx + 10.0 * d0
+    R = 10.0 * math.tan(0.5 * thl)
+    hexv = [c + R * (math.cos(t) * a + math.sin(t) * bvec) for t in np.arange(6) * math.pi / 3]
+    tris = [[c, hexv[i], hexv[(i + 1) % 6]] for i in range(6)]
+    sc = tri_scene(tris, [0] * 6)
+    d1 = d0 - 2 * (d0 @ nr) * nr
+    w = np.cross(d1, a)
+    rx = c + 5.0 * d1 + 0.05 * w
+    kw = dict(max_order=1, division_n=n, subrays=6)
+    p = orc.run(sc, tx, rx[None], iterations=5, **kw)["paths"]
+    p1 = p[p["order"] == 1]
+    assert len(p1) == 1
+    q = p1[0]
+    assert q["launch_ray"] == r0
+    assert q["flags"] & 1 and not q["flags"] & 4
+    assert q["iters_used"] == 0
+    assert np.array_equal(q["axis"], d0)
+    assert q["tan_err"] == q["init_tan_err"] > 0
+    # the geometry is what the test claims: second-level sub-rays around d0
+    # do meet the reflector, first-level ones do not
+    ub, vb = u, np.cross(d0, u)
+    for rho, hits in ((thl / math.sqrt(3.0), 0), (thl / 3.0, 6)):
+        dirs = [d0 + rho * (math.cos(t) * ub + math.sin(t) * vb) for t in np.arange(6) * math.pi / 3]
+        dirs = np.array(dirs) / np.linalg.norm(dirs, axis=1, keepdims=True)
+        _, face, _, _ = orc.trace_dirs(sc, tx, dirs, 0)
+        assert (face[:, 0] == 0).sum() == hits
+
+
+# --------------------------------------------------- tie of path test 1 --
+def test_double_counting_tie_keeps_lower_ray_index(orc):
+    """Reading 9: two launch rays with exactly equal error angles for one
+    receiver and face sequence -- the lower ray index wins path test 1.  The
+    two middle points of the icosahedron edge between (1, phi, 0) and
+    (-1, phi, 0) are exact mirror images in x; a receiver straight along +y
+    from the transmitter sees both at the same error angle, bit for bit."""
+    n = 11
+    d = orc.launch_dirs(n)
+    V = d[:12]
+    adj = V @ V.T > 0
+    edges = [(i, j) for i in range(12) for j in range(i + 1, 12) if adj[i, j]]
+    e = next(q for q, (i, j) in enumerate(edges)
+             if V[i][0] != 0 and V[j][0] == -V[i][0] and V[j][1] == V[i][1] and V[j][2] == V[i][2])
+    k1, k2 = (n - 1) // 2, (n + 1) // 2
+    r1, r2 = 12 + e * (n - 1) + k1 - 1, 12 + e * (n - 1) + k2 - 1
+    assert np.array_equal(d[r1] * [-1, 1, 1], d[r2])
+    empty = tri_scene(np.zeros((0, 3, 3)), [])
+    tx = np.array([0.5, -0.25, 2.0])
+    rx = tx + np.array([0.0, 7.0, 0.0])
+    r = orc.run(empty, tx, rx[None], max_order=0, division_n=n, iterations=0)
+    c = r["candidates"]
+    t1 = c["tan_err"][c["ray"] == r1]
+    t2 = c["tan_err"][c["ray"] == r2]
+    assert len(t1) == len(t2) == 1 and t1[0] == t2[0]
+    assert c["tan_err"].min() == t1[0]
+    assert len(r["unique"]) == 1 and r["unique"]["ray"][0] == min(r1, r2)
+
+
+def test_subray_tie_keeps_lower_subray_index(orc):
+    """Reading 10: of sub-rays with exactly equal error angles the lower
+    index wins.  The launch ray through the icosahedron vertex (0, 1, phi)
+    lies in the plane x = 0, so its sub-rays 1 and 2 (phases 60 and 120
+    degrees, basis u = +x) are exact mirror images in x.  A receiver in that
+    plane, displaced from the axis toward phase 90 degrees, is equally close
+    to both and closer than to the other four: one iteration must end on
+    sub-ray 1 (x > 0), not its mirror."""
+    n = 9
+    thl = math.atan(2.0) / (math.sqrt(3.0) * n)
+    a = orc.launch_dirs(n, [0])[0]
+    assert a[0] == 0.0
+    u = np.array([1.0, 0.0, 0.0])
+    v = np.cross(a, u)
+    empty = tri_scene(np.zeros((0, 3, 3)), [])
+    tx = np.array([0.0, 0.3, 1.0])
+    w = a + 0.3 * thl * v
+    rx = tx + 9.0 * w / np.linalg.norm(w)
+    rx[0] = 0.0
+    rho = thl / math.sqrt(3.0)
+    subs = np.array([a + rho * (math.cos(t) * u + math.sin(t) * v)
+                     for t in np.arange(6) * math.pi / 3])
+    subs /= np.linalg.norm(subs, axis=1, keepdims=True)
+    ang = angle_deg(subs, rx - tx)
+    assert abs(ang[1] - ang[2]) < 1e-12 and ang[1] < np.delete(ang, [1, 2]).min() - 1e-3
+    p = orc.run(empty, tx, rx[None], max_order=0, division_n=n, iterations=1, subrays=6)["paths"]
+    assert len(p) == 1 and p["launch_ray"][0] == 0 and p["iters_used"][0] == 1
+    assert np.abs(p["axis"][0] - subs[1]).max() < 1e-15
