@@ -43,6 +43,8 @@ typedef int32_t sbr_status;
 #define SBR_E_OOM (-5)         /* device or host allocation failed               */
 #define SBR_E_DEVICE (-6)      /* a HIP call failed (message has the HIP error)  */
 #define SBR_E_INTERNAL (-7)    /* internal consistency check failed              */
+#define SBR_E_SCRATCH (-8)     /* sbr_trace_device_noalloc: the call needs more
+                                  than its fixed scratch holds                    */
 
 typedef struct sbr_context sbr_context;
 typedef struct sbr_scene sbr_scene;
@@ -230,6 +232,32 @@ sbr_status sbr_trace(sbr_scene* scene, const double tx[3], const double* rx, int
 sbr_status sbr_trace_device(sbr_scene* scene, const double tx[3], const double* rx, int32_t n_rx,
                             const sbr_trace_params* params, sbr_path* out, int64_t capacity,
                             int64_t* n_out, sbr_trace_stats* stats);
+
+/* sbr_trace_device for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, results and stream semantics as sbr_trace_device, but the
+ * call allocates nothing (no hipMalloc, hipFree or pinned host memory): all of
+ * its working memory -- the launch grid, the FP32 receivers, reception events,
+ * path-test-1 winners, refinement state and path records -- lives in one
+ * fixed 24 MiB array of device memory per GPU, set up when the library's
+ * context is created and held until the process ends.  Limits, checked before
+ * any work is queued unless noted: n_rx <= 4096; the launch grid (24 bytes per
+ * ray) must fit beside the other buffers, which allows up to about 900,000
+ * rays (division n <= 300 on the icosahedron); at most 4096 reception events
+ * (known only after the trace: the call then returns SBR_E_SCRATCH and leaves
+ * out unwritten).  Any limit exceeded gives SBR_E_SCRATCH and a message;
+ * sbr_trace_device has none of these limits.  SBR_FLAG_GRAPH is rejected
+ * (SBR_E_INVALID_ARG).  Rays are handed out by index and every receiver is
+ * tested on every segment (no receiver tree), which gives the same paths.
+ * Every call on one GPU, from any context, shares that GPU's array: calls
+ * that overlap in time on one GPU race and give undefined results.  The array
+ * keeps the last call's launch grid, which a later call with the same launch
+ * method and n reuses (SBR_FLAG_FRESH_GRID recomputes it).  Errors as
+ * sbr_trace_device, plus SBR_E_SCRATCH, and SBR_E_DEVICE when the array's
+ * device address could not be obtained. */
+sbr_status sbr_trace_device_noalloc(sbr_scene* scene, const double tx[3], const double* rx,
+                                    int32_t n_rx, const sbr_trace_params* params, sbr_path* out,
+                                    int64_t capacity, int64_t* n_out, sbr_trace_stats* stats);
 
 /* One job of a batched trace: transmitter tx on scenes[scene], its receivers
  * rx[rx_first .. rx_first + n_rx) of the batch's receiver array (a receiver

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -62,6 +63,52 @@ struct Counters {
 
 }  // namespace
 
+// Device memory of sbr_trace_device_noalloc: everything that entry point needs
+// beyond its inputs and outputs lives in this array (one copy per device,
+// held until the process ends).  Host code never passes `scratch` itself to a
+// kernel or copy: the device address comes from hipGetSymbolAddress, taken
+// once per device (noalloc_scratch_ptr).
+constexpr size_t kNoAllocBytes = size_t(24) << 20;
+constexpr int32_t kNoAllocMaxRx = 4096;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+
+// The device address of `scratch` on `device` (which must be current), looked
+// up on the first call for that device and kept.
+hipError_t noalloc_scratch_ptr(int device, void** out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_done[device]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+        g_scratch_err[device] = e;
+        g_scratch_ptr[device] = e == hipSuccess ? ptr : nullptr;
+        g_scratch_done[device] = true;
+        if (e != hipSuccess) (void)hipGetLastError();
+    }
+    *out = g_scratch_ptr[device];
+    return g_scratch_err[device];
+}
+
+// Which launch grid (launch * 100000 + n, -1: none) the scratch of each device
+// holds at the grid offset for that n, as left by the last completed call.
+int32_t g_scratch_grid[kMaxDevices] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1,
+                                       -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1,
+                                       -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1,
+                                       -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1,
+                                       -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
+
+}  // namespace
+
 struct sbr_context {
     int32_t device = 0;
     hipStream_t stream = nullptr;
@@ -72,6 +119,9 @@ struct sbr_context {
     // order cached per grid
     std::map<int32_t, DevBuf> orders;
     int32_t ray_order = 1;
+    void* scratch = nullptr;  // device address of the no-allocation scratch (NULL: unavailable)
+    hipError_t scratch_err = hipSuccess;
+    int64_t noalloc_unique = -1;  // path count of the last no-allocation call
     DevBuf grid_scratch, rx, rx32, cand, idx, flags, offs, scan, uniq, refine, paths, keep, outp,
         counters, rays_tri, rays_t, tally, geom, d_jobs, d_scenes, d_rxjob, d_rxnodes, d_rxperm;
     Counters* host_ctr = nullptr;  // pinned
@@ -450,6 +500,37 @@ int32_t build_rx_tree(const double* rx, std::vector<int32_t>& perm, int32_t lo, 
     return me;
 }
 
+// The job of transmitter tx with parameters p over launch directions dir
+// [3][N], rays [ray_begin, ray_begin + ray_count) handed out by index, as the
+// only job of a call (first packet 0, scene 0, its receivers the call's
+// first n_rx, no receiver tree).
+JobDev make_job(const sbr_scene* s, const double* tx, const sbr_trace_params* p,
+                const double* dir, int64_t N, int64_t ray_begin, int64_t ray_count)
+{
+    JobDev J{};
+    for (int i = 0; i < 3; ++i) J.tx[i] = tx[i];
+    J.thl = theta_launch(p->launch, p->division_n);
+    J.tan_tgt = p->target_err_deg > 0.0 ? tan_cr((p->target_err_deg * kPi) / 180.0) : 0.0;
+    J.freq_hz = p->freq_hz;
+    J.tx_power_dbm = p->tx_power_dbm;
+    J.dir = dir;
+    J.N = N;
+    J.order = nullptr;
+    J.ray_begin = ray_begin;
+    J.ray_count = ray_count;
+    J.packet_first = 0;
+    J.scene = 0;
+    J.rx_first = 0;
+    J.n_rx = 0;
+    J.K = p->max_order;
+    J.iterations = p->iterations;
+    J.subrays = p->subrays;
+    J.keep_invalid = (p->flags & SBR_FLAG_KEEP_INVALID) ? 1 : 0;
+    J.delta = traversal_delta(s, tx);
+    J.rx_root = -1;
+    return J;
+}
+
 // Add a job: its launch directions (cached per division n), parameters and
 // packets of 64 x chunk rays.
 sbr_status add_job(sbr_context* c, Call& call, int32_t scene_idx, const double* tx,
@@ -463,31 +544,15 @@ sbr_status add_job(sbr_context* c, Call& call, int32_t scene_idx, const double* 
     if (r) return r;
     call.grids_built = call.grids_built || built;
     const sbr_scene* s = call.scenes[scene_idx];
-    JobDev J{};
-    for (int i = 0; i < 3; ++i) J.tx[i] = tx[i];
-    J.thl = theta_launch(p->launch, p->division_n);
-    J.tan_tgt = p->target_err_deg > 0.0 ? tan_cr((p->target_err_deg * kPi) / 180.0) : 0.0;
-    J.freq_hz = p->freq_hz;
-    J.tx_power_dbm = p->tx_power_dbm;
-    J.dir = g.dir;
-    J.N = g.N;
-    J.order = nullptr;
+    JobDev J = make_job(s, tx, p, g.dir, g.N, ray_begin, ray_count);
     if (c->ray_order && ray_begin == 0 && ray_count == g.N && g.N <= kOrderMaxRays) {
         r = get_order(c, p->launch, p->division_n, g, &J.order);
         if (r) return r;
     }
-    J.ray_begin = ray_begin;
-    J.ray_count = ray_count;
     J.packet_first = call.n_packets;
     J.scene = scene_idx;
     J.rx_first = rx_first;
     J.n_rx = n_rx;
-    J.K = p->max_order;
-    J.iterations = p->iterations;
-    J.subrays = p->subrays;
-    J.keep_invalid = (p->flags & SBR_FLAG_KEEP_INVALID) ? 1 : 0;
-    J.delta = traversal_delta(s, tx);
-    J.rx_root = -1;
     if (n_rx > 0 && n_rx >= c->rx_tree_min) {
         if (call.rx_perm.size() != (size_t)call.n_rx) {
             call.rx_perm.resize((size_t)call.n_rx);
@@ -875,6 +940,7 @@ const char* sbr_status_string(sbr_status s)
         case SBR_E_OOM: return "out of memory";
         case SBR_E_DEVICE: return "HIP device error";
         case SBR_E_INTERNAL: return "internal error";
+        case SBR_E_SCRATCH: return "exceeds the fixed scratch of the no-allocation entry point";
         default: return "unknown status";
     }
 }
@@ -940,6 +1006,8 @@ sbr_status sbr_context_create(int32_t device, void* hip_stream, sbr_context** ou
             (void)hipGetLastError();
             c->la3_lds = false;
         }
+        // the no-allocation entry point's scratch (a failure only disables it)
+        c->scratch_err = noalloc_scratch_ptr(device, &c->scratch);
     }
     if (e != hipSuccess) {
         g_create_err = std::string("context setup: ") + hipGetErrorString(e);
@@ -1605,6 +1673,182 @@ sbr_status sbr_trace_device(sbr_scene* s, const double tx[3], const double* rx, 
     r = graph_job(c, s, tx, n_rx, p, cap);
     if (r) return r;
     return capture_graph(c, s, cap, rx, p, out, capacity, u_cap, u_now);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Where sbr_trace_device_noalloc keeps its buffers in the scratch (byte
+// offsets, 256-aligned).  The counters and the receivers' job indices come
+// first, so that one kernel zeroes both; the launch grid comes last, at an
+// offset that depends only on n, so that the grid of the last call can be
+// reused in place.
+struct NoAllocLayout {
+    size_t counters, rxjob, job, scene, rx32, cand, uniq, refine, geom, paths, keep, gscr, grid,
+        end;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+NoAllocLayout noalloc_layout(int32_t n, int64_t N)
+{
+    NoAllocLayout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    L.counters = take(sizeof(Counters));
+    L.rxjob = take(sizeof(int32_t) * kNoAllocMaxRx);
+    L.job = take(sizeof(JobDev));
+    L.scene = take(sizeof(SceneDev));
+    L.rx32 = take(sizeof(float4) * kNoAllocMaxRx);
+    L.cand = take(sizeof(sbr_candidate) * kSmallEvents);
+    L.uniq = take(sizeof(sbr_candidate) * kSmallEvents);
+    L.refine = take(sizeof(RefineOut) * kSmallEvents);
+    L.geom = take(sizeof(PathGeom) * kSmallEvents);
+    L.paths = take(sizeof(sbr_path) * kSmallEvents);
+    L.keep = take(sizeof(int32_t) * kSmallEvents);
+    L.gscr = take(grid_scratch_bytes(n));
+    L.grid = take(sizeof(double) * 3 * (size_t)N);
+    L.end = o;
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+sbr_status sbr_trace_device_noalloc(sbr_scene* s, const double tx[3], const double* rx,
+                                    int32_t n_rx, const sbr_trace_params* p, sbr_path* out,
+                                    int64_t capacity, int64_t* n_out, sbr_trace_stats* stats)
+{
+    sbr_status r = check_trace_inputs(s, tx, nullptr, 0, p, capacity, out, n_out);
+    if (r) return r;
+    sbr_context* c = s->ctx;
+    if (n_rx < 0 || (n_rx > 0 && !rx)) return fail(c, SBR_E_INVALID_ARG, "bad rx array");
+    if (p->flags & SBR_FLAG_GRAPH)
+        return fail(c, SBR_E_INVALID_ARG, "SBR_FLAG_GRAPH needs allocation; capture the call instead");
+    if (!c->scratch)
+        return fail(c, SBR_E_DEVICE, "no-allocation scratch unavailable: %s",
+                    hipGetErrorString(c->scratch_err));
+    if (n_rx > kNoAllocMaxRx)
+        return fail(c, SBR_E_SCRATCH, "%d receivers; the no-allocation scratch holds at most %d",
+                    n_rx, kNoAllocMaxRx);
+    const int64_t N = num_rays(p->launch, p->division_n);
+    const NoAllocLayout L = noalloc_layout(p->division_n, N);
+    if (L.end > kNoAllocBytes)
+        return fail(c, SBR_E_SCRATCH,
+                    "%lld launch rays need %zu bytes of scratch; the no-allocation scratch has %zu",
+                    (long long)N, L.end, kNoAllocBytes);
+    HIPCHK(c, use_device(c->device));
+    const hipStream_t st = c->stream;
+    char* base = (char*)c->scratch;
+    double* dir = (double*)(base + L.grid);
+    JobDev J = make_job(s, tx, p, dir, N, 0, N);
+    J.n_rx = n_rx;
+    const SceneDev S0 = scene_dev(s);
+    Counters* dc = (Counters*)(base + L.counters);
+    sbr_candidate* cand = (sbr_candidate*)(base + L.cand);
+    sbr_candidate* uniq = (sbr_candidate*)(base + L.uniq);
+    RefineOut* rf = (RefineOut*)(base + L.refine);
+    PathGeom* geom = (PathGeom*)(base + L.geom);
+    sbr_path* paths = (sbr_path*)(base + L.paths);
+    int32_t* keep = (int32_t*)(base + L.keep);
+
+    HIPCHK(c, hipEventRecord(c->ev[0], st));
+    HIPCHK(c, hipMemcpyAsync(base + L.job, &J, sizeof J, hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(base + L.scene, &S0, sizeof S0, hipMemcpyHostToDevice, st));
+    // FP32 receivers; the counters and the receivers' job (all 0) zeroed
+    HIPCHK(c, launch_rx32(rx, n_rx, (float4*)(base + L.rx32), st, base,
+                          L.rxjob + sizeof(int32_t) * (size_t)n_rx));
+    const int32_t dev = c->device;
+    const int32_t key = p->launch * 100000 + p->division_n;
+    const bool grid_fresh = (p->flags & SBR_FLAG_FRESH_GRID) || g_scratch_grid[dev] != key;
+    g_scratch_grid[dev] = -1;  // until this call has completed
+    if (grid_fresh)
+        HIPCHK(c, launch_grid(GridDev{dir, N, p->division_n, p->launch}, st, base + L.gscr,
+                              c->grid_check_log2));
+    HIPCHK(c, hipEventRecord(c->ev[1], st));
+
+    CallDev D{};
+    D.jobs = (const JobDev*)(base + L.job);
+    D.scenes = (const SceneDev*)(base + L.scene);
+    D.rx = rx;
+    D.rx_job = (const int32_t*)(base + L.rxjob);
+    D.rx_nodes = nullptr;
+    D.rx_perm = nullptr;
+    D.rx32 = (const float4*)(base + L.rx32);
+    D.n_jobs = 1;
+    D.chunk = c->trace_chunk;
+    const int64_t per = 64 * (int64_t)D.chunk;
+    D.n_packets = (N + per - 1) / per;
+    const LdsPlan lp = plan_for(s, c->trace_block);
+    const int64_t per_block = std::max<int64_t>(1, lp.block / 64);
+    const int blocks = (int)std::max<int64_t>(
+        1, std::min<int64_t>((D.n_packets + per_block - 1) / per_block, c->persist_blocks));
+    HIPCHK(c, hipEventRecord(c->ev[7], st));
+    HIPCHK(c, launch_trace(D, lp, S0, blocks, &dc->queue, cand, kSmallEvents, &dc->cand, nullptr,
+                           nullptr, &dc->err, st));
+    HIPCHK(c, hipEventRecord(c->ev[2], st));
+    HIPCHK(c, launch_dedup_small(cand, kSmallEvents, uniq, &dc->n_unique, st, &dc->cand));
+    HIPCHK(c, hipEventRecord(c->ev[3], st));
+    LdsPlan lp256 = plan_for(s, 256);
+    lp256.block = 256;
+    const int depth = refine_depth(c, c->noalloc_unique >= 0 ? c->noalloc_unique : 256);
+    HIPCHK(c, launch_refine(D, lp256, plan_la3(s), S0, uniq, kSmallEvents, &dc->n_unique, depth,
+                            rf, geom, &dc->err, st));
+    HIPCHK(c, hipEventRecord(c->ev[4], st));
+    LdsPlan lps{};
+    lps.block = 256;
+    HIPCHK(c, launch_solve(D, lps, S0, uniq, rf, geom, kSmallEvents, &dc->n_unique, paths, keep,
+                           &dc->err, st));
+    HIPCHK(c, hipEventRecord(c->ev[5], st));
+    HIPCHK(c, launch_emit_small(paths, keep, kSmallEvents, &dc->n_unique, out, capacity,
+                                &dc->n_paths, st));
+    HIPCHK(c, hipMemcpyAsync(c->host_ctr, dc, sizeof(Counters), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipEventRecord(c->ev[6], st));
+    HIPCHK(c, hipEventSynchronize(c->ev[6]));
+    const Counters* hc = c->host_ctr;
+    if (hc->err) return fail(c, SBR_E_INTERNAL, "traversal stack overflow");
+    g_scratch_grid[dev] = key;
+    if (hc->cand > (unsigned long long)kSmallEvents)
+        return fail(c, SBR_E_SCRATCH,
+                    "%llu reception events; the no-allocation scratch holds at most %d",
+                    hc->cand, kSmallEvents);
+    c->noalloc_unique = hc->n_unique;
+    *n_out = hc->n_paths;
+    if (stats) {
+        memset(stats, 0, sizeof(*stats));
+        stats->n_rays = N;
+        stats->n_candidates = (int64_t)hc->cand;
+        stats->n_unique = hc->n_unique;
+        stats->n_paths = hc->n_paths;
+        float t[7] = {};
+        (void)hipEventElapsedTime(&t[0], c->ev[0], c->ev[1]);
+        (void)hipEventElapsedTime(&t[1], c->ev[7], c->ev[2]);
+        (void)hipEventElapsedTime(&t[2], c->ev[2], c->ev[3]);
+        (void)hipEventElapsedTime(&t[3], c->ev[3], c->ev[4]);
+        (void)hipEventElapsedTime(&t[4], c->ev[4], c->ev[5]);
+        (void)hipEventElapsedTime(&t[5], c->ev[5], c->ev[6]);
+        (void)hipEventElapsedTime(&t[6], c->ev[0], c->ev[6]);
+        stats->ms_launch = grid_fresh ? t[0] : 0.0;
+        stats->ms_trace = t[1];
+        stats->ms_dedup = t[2];
+        stats->ms_refine = t[3];
+        stats->ms_solve = t[4];
+        stats->ms_emit = t[5];
+        stats->ms_total = t[6];
+        stats->lds_bytes = lp.bytes;
+        stats->lds_nodes = lp.n_nodes;
+        stats->lds_tris = lp.n_tris;
+        stats->lds_max = c->lds_max;
+    }
+    if (hc->n_paths > capacity)
+        return fail(c, SBR_E_CAPACITY, "%d paths, capacity %lld", hc->n_paths, (long long)capacity);
+    return SBR_OK;
 }
 
 sbr_status sbr_trace_batch(sbr_context* c, sbr_scene* const* scenes, int32_t n_scenes,

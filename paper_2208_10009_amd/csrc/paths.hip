@@ -363,7 +363,10 @@ constexpr int kDedupLds = 2048;
 // Sort (bitonic, in LDS), path test 1 (heads of equal keys) and compaction of
 // the winners, in sorted order; writes the number of unique paths to
 // *n_unique.  Up to kDedupLds events are first packed into LDS keys, so that
-// each comparison is four LDS reads and a branch-free word compare.
+// each comparison is four LDS reads and a branch-free word compare.  With a
+// device count n_dev above n_max (more events than the call was sized for,
+// a result every caller discards) there are no winners: the later stages
+// then do no work and write no paths.
 __global__ __launch_bounds__(kDedupThreads) void k_dedup_small(const sbr_candidate* __restrict__ C,
                                                       int32_t n_max,
                                                       const unsigned long long* __restrict__ n_dev,
@@ -374,7 +377,7 @@ __global__ __launch_bounds__(kDedupThreads) void k_dedup_small(const sbr_candida
     __shared__ int32_t part[kDedupThreads];
     __shared__ uint4 sK[4 * kDedupLds];
     const int t = threadIdx.x;
-    const int n = n_dev ? (int)min((unsigned long long)n_max, *n_dev) : n_max;
+    const int n = n_dev ? (*n_dev > (unsigned long long)n_max ? 0 : (int)*n_dev) : n_max;
     int P = 1;
     while (P < n) P <<= 1;
     for (int i = t; i < P; i += kDedupThreads) idx[i] = i < n ? (uint32_t)i : 0xffffffffu;

@@ -28,6 +28,7 @@ E_CAPACITY = -4
 E_OOM = -5
 E_DEVICE = -6
 E_INTERNAL = -7
+E_SCRATCH = -8
 
 FLAG_KEEP_INVALID = 1
 FLAG_FRESH_GRID = 2
@@ -42,7 +43,7 @@ EXPORTS = (
     "sbr_scene_destroy", "sbr_trace", "sbr_trace_device", "sbr_candidates", "sbr_launch_grid",
     "sbr_trace_rays",
     "sbr_trace_counters", "sbr_trace_batch", "sbr_context_get_tuning", "sbr_context_set_tuning",
-    "sbr_path_gradients", "sbr_status_string", "sbr_last_error",
+    "sbr_path_gradients", "sbr_status_string", "sbr_last_error", "sbr_trace_device_noalloc",
 )
 
 
@@ -162,6 +163,8 @@ def lib(load_torch: bool = True):
                             C.POINTER(TraceStats)]
     L.sbr_trace_device.argtypes = [vp, dp, vp, C.c_int32, C.POINTER(TraceParams), vp, C.c_int64,
                                    lp, C.POINTER(TraceStats)]
+    L.sbr_trace_device_noalloc.argtypes = [vp, dp, vp, C.c_int32, C.POINTER(TraceParams), vp,
+                                           C.c_int64, lp, C.POINTER(TraceStats)]
     L.sbr_candidates.argtypes = [vp, dp, dp, C.c_int32, C.POINTER(TraceParams), vp, C.c_int64,
                                  lp]
     L.sbr_launch_grid.argtypes = [vp, C.c_int32, C.c_int32, C.c_int64, C.c_int64, dp]
@@ -356,6 +359,26 @@ class Scene:
                 continue
             self.ctx._check(st)
             return out[: n.value], stats.as_dict()
+
+    def trace_device_noalloc(self, tx, rx, out, **params):
+        """sbr_trace_device_noalloc: as trace_device, into the caller's `out`
+        (a uint8 [capacity, record] device tensor); nothing is allocated.
+        Returns (paths view of out, stats); raises SbrError when out is too
+        small or the call exceeds the fixed scratch."""
+        import torch
+        txa = np.ascontiguousarray(tx, np.float64).reshape(3)
+        assert rx.dtype == torch.float64 and rx.is_cuda and rx.dim() == 2 and rx.shape[1] == 3
+        assert rx.is_contiguous(), "rx must be contiguous (nothing is copied)"
+        assert out.dtype == torch.uint8 and out.is_cuda and out.is_contiguous()
+        assert out.dim() == 2 and out.shape[1] == PATH_DTYPE.itemsize
+        prm = make_params(**params)
+        n = C.c_int64()
+        stats = TraceStats()
+        st = lib().sbr_trace_device_noalloc(self.h, _d(txa), C.c_void_p(rx.data_ptr()),
+                                            rx.shape[0], C.byref(prm), C.c_void_p(out.data_ptr()),
+                                            out.shape[0], C.byref(n), C.byref(stats))
+        self.ctx._check(st)
+        return out[: n.value], stats.as_dict()
 
     def candidates(self, tx, rx, capacity: int | None = None, **params):
         """sbr_candidates: reception events before path test 1, sorted."""
