@@ -104,7 +104,9 @@ typedef struct {
     int32_t order;               /* number of reflections k                          */
     int32_t face[SBR_MAX_ORDER]; /* face ids hit in order; -1 beyond order           */
     int64_t launch_ray;          /* launch ray that won path test 1                  */
-    int32_t iters_used;          /* iterations that improved the path                */
+    int32_t iters_used;          /* precise-algorithm iterations whose winning sub-ray
+                                    became the path's axis (upturns included): the
+                                    index of the last such iteration, 0 if none      */
     uint32_t flags;              /* SBR_PATH_*                                       */
     double tan_err;              /* tan of the error angle of the reported ray       */
     double axis[3];              /* reported departure direction                     */
@@ -189,10 +191,12 @@ sbr_status sbr_context_destroy(sbr_context* ctx);
  * tri [n_triangles][3] vertex indices; face_id [n_triangles] >= 0 names the
  * planar polygon ("face") a triangle belongs to -- a face's plane and
  * material are those of its lowest-index triangle and every triangle of a face
- * must lie in that plane (relative 1e-9); mat_id [n_triangles] indexes
- * eps_r [n_materials].  Degenerate triangles are accepted and never hit.
- * Errors: SBR_E_INVALID_ARG (index out of range, non-finite vertex, face not
- * planar), SBR_E_OOM, SBR_E_DEVICE. */
+ * must lie in that plane (within 1e-9 of the scene's bounding-box diagonal);
+ * mat_id [n_triangles] indexes eps_r [n_materials].  Degenerate triangles are
+ * accepted and never hit, except as a face's lowest-index triangle, which
+ * must define the plane.  Errors: SBR_E_INVALID_ARG (index out of range,
+ * non-finite vertex or permittivity, a face's first triangle degenerate, a
+ * triangle off its face's plane), SBR_E_OOM, SBR_E_DEVICE. */
 sbr_status sbr_scene_upload(sbr_context* ctx, const double* xyz, int64_t n_vertices,
                             const int32_t* tri, const int32_t* face_id, const int32_t* mat_id,
                             int64_t n_triangles, const sbr_complex* eps_r, int32_t n_materials,
@@ -332,7 +336,7 @@ sbr_status sbr_path_gradients(sbr_scene* scene, int64_t n_paths, const double* t
 
 /* Work counts of the trace stage of sbr_trace with the same arguments, from
  * an instrumented copy of the trace kernel: counts[0] segments traced
- * (ray-bounces), counts[1] BVH nodes visited (64 B each), counts[2]
+ * (ray-bounces), counts[1] BVH4 nodes visited (128 B each), counts[2]
  * ray-triangle tests (80 B triangle records), counts[3] reception events.
  * They define the algorithmic bytes of the trace kernel for its roofline. */
 sbr_status sbr_trace_counters(sbr_scene* scene, const double tx[3], const double* rx,

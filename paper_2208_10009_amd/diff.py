@@ -22,6 +22,21 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def _check_inputs(tx, rx, eps, order, faces, device):
+    """The C ABI reads raw FP64 / int32 device arrays of these shapes."""
+    P = rx.shape[0]
+    for name, t, dt, shape in (("tx", tx, torch.float64, (P, 3)), ("rx", rx, torch.float64, (P, 3)),
+                               ("eps", eps, torch.float64, (eps.shape[0], 2)),
+                               ("order", order, torch.int32, (P,)),
+                               ("faces", faces, torch.int32, (P, sbr.MAX_ORDER))):
+        if t.dtype != dt:
+            raise TypeError("%s must be %s (got %s)" % (name, dt, t.dtype))
+        if t.device != device:
+            raise ValueError("%s must be on %s (got %s)" % (name, device, t.device))
+        if tuple(t.shape) != shape:
+            raise ValueError("%s must have shape %s (got %s)" % (name, shape, tuple(t.shape)))
+
+
 def _setup():
     L = sbr.lib()
     if not getattr(L, "_grad_ready", False):
@@ -40,7 +55,10 @@ class PathQuantities(torch.autograd.Function):
     @staticmethod
     def forward(ctx, tx, rx, eps, scene, order, faces, freq_hz, tx_power_dbm):
         L = _setup()
+        dev = torch.device("cuda", scene.ctx.device)
+        _check_inputs(tx, rx, eps, order, faces, dev)
         tx, rx, eps = tx.contiguous(), rx.contiguous(), eps.contiguous()
+        order, faces = order.contiguous(), faces.contiguous()
         P = tx.shape[0]
         val = torch.empty((P, 8), dtype=torch.float64, device=tx.device)
         st = L.sbr_path_gradients(scene.h, P, _ptr(tx), _ptr(rx), _ptr(order), _ptr(faces),
@@ -55,7 +73,7 @@ class PathQuantities(torch.autograd.Function):
     def backward(ctx, gval):
         L = _setup()
         tx, rx, eps, order, faces = ctx.saved_tensors
-        gval = gval.contiguous()
+        gval = gval.to(torch.float64).contiguous()
         gtx, grx = torch.empty_like(tx), torch.empty_like(rx)
         geps = torch.zeros_like(eps)
         st = L.sbr_path_gradients(ctx.scene.h, tx.shape[0], _ptr(tx), _ptr(rx), _ptr(order),

@@ -319,6 +319,30 @@ def test_invalid_arguments(gpu):
     bad_scene["mat_id"] = np.full(12, 3, np.int32)
     with pytest.raises(sbr.SbrError):
         gpu.scene(bad_scene)
+    # a face whose second triangle leaves the first one's plane
+    off = scenes.SceneBuilder()
+    off.add(np.array([[0, 0, 0], [4, 0, 0], [4, 4, 0], [0, 4, 0.01]], float),
+            [(0, 1, 2), (0, 2, 3)], [0, 0], 0)
+    with pytest.raises(sbr.SbrError, match="not in the plane") as e:
+        gpu.scene(off.scene([5.0 + 0j]))
+    assert e.value.status == sbr.E_INVALID_ARG
+    # the same quad within the tolerance is accepted
+    flat = scenes.SceneBuilder()
+    flat.add(np.array([[0, 0, 0], [4, 0, 0], [4, 4, 0], [0, 4, 1e-12]], float),
+             [(0, 1, 2), (0, 2, 3)], [0, 0], 0)
+    gpu.scene(flat.scene([5.0 + 0j])).close()
+    # a face whose lowest-index triangle is degenerate (no plane); a later
+    # degenerate triangle of a face is accepted
+    deg = scenes.SceneBuilder()
+    deg.add(np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0], [0, 4, 0]], float),
+            [(0, 1, 2), (0, 1, 3)], [0, 0], 0)
+    with pytest.raises(sbr.SbrError, match="degenerate") as e:
+        gpu.scene(deg.scene([5.0 + 0j]))
+    assert e.value.status == sbr.E_INVALID_ARG
+    ok = scenes.SceneBuilder()
+    ok.add(np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0], [0, 4, 0]], float),
+           [(0, 1, 3), (0, 1, 2)], [0, 0], 0)
+    gpu.scene(ok.scene([5.0 + 0j])).close()
 
 
 def test_deterministic_reruns(gpu):
