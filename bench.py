@@ -1,24 +1,27 @@
 """Benchmark of the SBR hot path on one MI355X.
 
-One step = one sbr_trace_device call over the whole path: equiangular
-launch (recomputed every step), BVH traversal with specular bounces and cone
+One step = one sbr_trace_device call over the whole path: equiangular launch
+(recomputed every step), BVH traversal with specular bounces and cone
 reception, path test 1, the precise algorithm, image solve / path test 2 /
 power, and the canonical emit.  The scene (BVH) is uploaded once before the
 timed region and the receivers are a device tensor, so the inputs are
-resident in HBM; the paths are written to a device buffer.  The rate of the
-host-array entry point (sbr_trace, receivers and paths over PCIe each call)
-is reported beside it.
+resident in HBM; the paths are written to a device buffer.
 
-Workload: the Manhattan grid (8 x 8 box buildings on a 40 m pitch plus
-ground, 770 triangles), Tx at 25 m, 64 Rx at 1.5 m on street centrelines,
-n = 200 (400,002 rays), up to 6 reflections, 5 iterations of 7 sub-rays,
-28 GHz -- seeded synthetic stand-in for the paper's scenes.
+Headline workload: the large procedural city (2000 extruded polygon
+buildings on a terrain mesh, 498,614 triangles), one Tx 30 m above the
+terrain, 1024 Rx on a 32 x 32 grid at 1.5 m, n = 1000 (10,000,002 rays),
+up to 8 reflections, 5 iterations of 6 sub-rays, 28 GHz -- the largest
+single-GPU configuration, seeded synthetic stand-in for the paper's scenes.
+The Manhattan grid (770 triangles, 400,002 rays, 64 Rx), the batched
+workload (256 Tx/Rx pairs on 16 scenes, one call against one call per pair)
+and the launch-grid comparison are reported beside it.
 
-Prints ONE JSON line: value = launched rays per second of whole-step time
-for the configuration as stated (I = 5); refined paths per second counts the
-paths whose refined AOD and AOA are within 0.01 deg of the exact solve, in a
-second timed run that iterates each path to that target; the roofline of the
-trace kernel; the CPU oracle baseline.
+Prints ONE JSON line: value = launched rays per second of whole-step time for
+the headline configuration as stated (I = 5); refined paths per second counts
+the paths whose refined AOD and AOA are within 0.01 deg of the exact solve, in
+a second timed run that iterates each path to that target; the roofline of
+the trace kernel; the CPU oracle baseline on a seeded sample of the same
+workload.
 """
 from __future__ import annotations
 
@@ -40,6 +43,23 @@ NODE_BYTES = 128    # BVH4 node: four FP32 child boxes + child references
 TRI_BYTES = 80      # FP64 triangle record (v0, e1, e2, face, index)
 RAY_BYTES = 24      # FP64 launch direction read per ray
 EVENT_BYTES = 56    # reception event record written
+# The trace kernel is bound by vector-ALU issue.  Its algorithmic work in
+# VALU lane operations (one FP32 or FP64 add, multiply, FMA, min, max or
+# compare on one lane): a BVH4 node visit is four slab tests of 15 (six slab
+# parameters, three entry and three exit minima/maxima, the two three-way
+# combines, the overlap compare); a ray-triangle test is the FP64
+# Moller-Trumbore of 50 (two cross products of 9, four dot products of 5,
+# o - v0, three divisions, six compares and the u + v add); a segment is the
+# specular reflection and the move to the hit point (19).
+NODE_OPS = 60
+TRI_OPS = 50
+SEG_OPS = 19
+# Peak VALU lane operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# (one wave64 instruction per SIMD every 4 cycles, FP32 and FP64 alike; twice
+# this in flops is the published 78.6 TFLOP/s FP64 vector peak).
+VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
+LARGE = "large_city_498614tri_rx1024_n1000_k8_i5_s6"
+MANHATTAN = "manhattan_8x8_770tri_n200_k6_i5_s7_rx64"
 
 
 def log(*a):
@@ -47,7 +67,7 @@ def log(*a):
 
 
 TRACE_SOURCES = ("trace.hip", "traverse.h", "internal.h", "geom.h")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_trace_hbm_traffic.txt")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_trace_counters.txt")
 
 
 def trace_source_hash():
@@ -60,23 +80,51 @@ def trace_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(workload):
-    """HBM bytes per k_trace launch for `workload` from the counter summary
-    (FETCH_SIZE + WRITE_SIZE, calibrated), or None when the summary is
+def measured_counters(workload):
+    """Counter values of the trace kernel for `workload` from the committed
+    rocprofv3 summary (HBM bytes per launch from FETCH_SIZE + WRITE_SIZE,
+    calibrated; VALU busy and lane utilization), or {} when the summary is
     missing or was taken from other kernel sources."""
     try:
-        lines = open(TRAFFIC_FILE).read().split("\n")
+        lines = open(COUNTERS_FILE).read().split("\n")
     except OSError:
-        return None
+        return {}
     kv = {}
     for ln in lines:
         ln = ln.strip()
         if ln and not ln.startswith("#") and "=" in ln:
             k, v = ln.split("=", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("source_sha256") != trace_source_hash() or workload + ".bytes" not in kv:
-        return None
-    return int(kv[workload + ".bytes"])
+    if kv.get("source_sha256") != trace_source_hash():
+        return {}
+    pre = workload + "."
+    return {k[len(pre):]: float(v) for k, v in kv.items() if k.startswith(pre)}
+
+
+def trace_roofline(counts, n_rays, kernel_ms, workload):
+    """Roofline of the trace kernel: algorithmic VALU lane operations per
+    launch over its mean HIP-event time, against the VALU peak; beside it the
+    measured HBM traffic and its fraction of 8 TB/s, the bytes the traversal
+    touches (served from LDS, L1 and L2, not HBM) and the VALU counters."""
+    ops = counts["nodes"] * NODE_OPS + counts["tris"] * TRI_OPS + counts["segments"] * SEG_OPS
+    touched = (counts["nodes"] * NODE_BYTES + counts["tris"] * TRI_BYTES + n_rays * RAY_BYTES
+               + counts["events"] * EVENT_BYTES)
+    sec = kernel_ms * 1e-3
+    ach = ops / sec / 1e9
+    mc = measured_counters(workload)
+    traffic = int(mc["hbm_bytes"]) if "hbm_bytes" in mc else None
+    return {
+        "kernel": "k_trace", "bound": "alu", "achieved": round(ach, 1),
+        "peak": VALU_PEAK_GOPS, "unit": "Gop/s", "frac": round(ach / VALU_PEAK_GOPS, 5),
+        "traffic": traffic,
+        "ops_per_launch": int(ops),
+        "ops_per_unit": {"node_visit": NODE_OPS, "triangle_test": TRI_OPS, "segment": SEG_OPS},
+        "kernel_ms": round(kernel_ms, 5),
+        "hbm": {"achieved_gbs": round(traffic / sec / 1e9, 1) if traffic else None,
+                "frac": round(traffic / sec / 1e9 / HBM_PEAK_GBS, 5) if traffic else None},
+        "bytes_touched_on_chip_gbs": round(touched / sec / 1e9, 1),
+        "valu_busy": mc.get("valu_busy"), "valu_lane_util": mc.get("valu_util"),
+    }
 
 
 def angle_deg(a, b):
@@ -89,10 +137,28 @@ def accurate_mask(p, tol_deg=0.01):
         (angle_deg(p["aoa"], p["exact_aoa"]) <= tol_deg) & ((p["flags"] & 2) == 0)
 
 
-def cpu_baseline(cfg, budget_s=10.0, max_runs=20):
-    """The FP64 CPU oracle, as it stands, on the same workload: whole runs of
-    the configuration as stated, repeated until about budget_s of wall time
-    (rays/s), plus one run in the 0.01 deg target mode (refined paths/s)."""
+def cpu_info():
+    """Host threads available to this process and the CPU model."""
+    try:
+        cores = int(os.environ["OMP_NUM_THREADS"])
+    except (KeyError, ValueError):
+        cores = len(os.sched_getaffinity(0))
+    model = None
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return cores, model
+
+
+def cpu_baseline_manhattan(cfg, budget_s=8.0, max_runs=20):
+    """The FP64 CPU oracle, as it stands, on the Manhattan workload: whole
+    runs of the configuration as stated, repeated until about budget_s of
+    wall time (rays/s), plus one run in the 0.01 deg target mode (refined
+    paths/s)."""
     from oracle import oracle as orc
     orc.build()
     n_rays = 10 * cfg["params"]["division_n"] ** 2 + 2
@@ -105,27 +171,82 @@ def cpu_baseline(cfg, budget_s=10.0, max_runs=20):
     t1 = time.perf_counter()
     tpaths = orc.run(cfg["scene"], cfg["tx"], cfg["rx"], **tprm)["paths"]
     tdt = time.perf_counter() - t1
-    try:
-        cores = int(os.environ["OMP_NUM_THREADS"])
-    except (KeyError, ValueError):
-        cores = len(os.sched_getaffinity(0))
+    cores, model = cpu_info()
     return {
-        "value": n_rays * runs / dt,
-        "unit": "rays/s",
-        "cores": cores,
+        "value": n_rays * runs / dt, "unit": "rays/s", "cores": cores, "cpu_model": model,
         "kind": "oracle",
-        "sample": "%d full run(s) of the same workload (%d rays, %d Rx), %.1f s; refined paths "
-                  "from one 0.01 deg target run, %.2f s" % (runs, n_rays, len(cfg["rx"]), dt, tdt),
+        "sample": "%d full run(s) of the Manhattan workload (%d rays, %d Rx), %.1f s; refined "
+                  "paths from one 0.01 deg target run, %.2f s" % (runs, n_rays, len(cfg["rx"]), dt,
+                                                                 tdt),
         "refined_paths_per_s": float(accurate_mask(tpaths).sum()) / tdt,
     }
+
+
+def cpu_baseline_large(cfg, stride=1000):
+    """The FP64 CPU oracle, as it stands, on a seeded sample of the headline
+    workload: every stride-th launch ray of the large city (brute force over
+    all 498,614 triangles, all 1024 receivers, up to 8 reflections), timed
+    and scaled to rays/s (the whole 10,000,002-ray run would take stride
+    times as long); then path test 1 over the sample's reception events and
+    the precise algorithm, solve and power of its winners in the 0.01 deg
+    target mode (refined paths/s)."""
+    from oracle import oracle as orc
+    orc.build()
+    prm = cfg["params"]
+    n, K = prm["division_n"], prm["max_order"]
+    N = 10 * n * n + 2
+    ids = np.arange(0, N, stride, dtype=np.int64)
+    t0 = time.perf_counter()
+    ev = orc.ray_events(cfg["scene"], cfg["tx"], cfg["rx"], n, K, ids)
+    dt = time.perf_counter() - t0
+    win = orc.path_test1(ev)
+    tprm = dict(prm, iterations=30, target_err_deg=0.01)
+    t1 = time.perf_counter()
+    rec = orc.path_records(cfg["scene"], cfg["tx"], cfg["rx"], win, **tprm) if len(win) else []
+    tdt = time.perf_counter() - t1
+    good = int(accurate_mask(rec).sum()) if len(win) else 0
+    cores, model = cpu_info()
+    return {
+        "value": len(ids) / dt, "unit": "rays/s", "cores": cores, "cpu_model": model,
+        "kind": "oracle",
+        "sample": "every %dth launch ray of the large city (%d of %d rays, seeded ray indices "
+                  "0, %d, ...), all 1024 Rx, K = 8: %.1f s, extrapolated (a whole run is %d times "
+                  "longer); refined paths: the sample's %d path-test-1 winners iterated to 0.01 "
+                  "deg, %.2f s" % (stride, len(ids), N, stride, dt, stride, len(win), tdt),
+        "refined_paths_per_s": good / tdt if len(win) and tdt > 0 else None,
+        "sample_events": int(len(ev)), "sample_paths_within_0.01deg": good,
+    }
+
+
+def miss_breakdown(p):
+    """Why paths end outside 0.01 deg: counts by outcome, with the largest
+    AOD and AOA errors of each."""
+    ea = angle_deg(p["aod"], p["exact_aod"])
+    eo = angle_deg(p["aoa"], p["exact_aoa"])
+    ok = accurate_mask(p)
+    st = (p["flags"] & 1) != 0
+    inv = (p["flags"] & 2) != 0
+    met = (p["flags"] & 4) != 0
+    out = {}
+    for name, m in (("stalled", st & ~inv), ("invalid", inv),
+                    ("target_met_aoa_over", met & ~st & ~inv & ~ok),
+                    ("iteration_cap", ~met & ~st & ~inv & ~ok)):
+        m = m & ~ok
+        out[name] = {"paths": int(m.sum()),
+                     "max_aod_err_deg": float(ea[m].max()) if m.any() else None,
+                     "max_aoa_err_deg": float(eo[m].max()) if m.any() else None,
+                     "orders": sorted(set(int(x) for x in p["order"][m]))}
+    return out
 
 
 def batch_vs_plain(ctx, scenes, torch, seed=0, steps=2):
     """The batched workload (16 box-building cities of 200-50k triangles,
     256 Tx/Rx pairs spread unevenly over them, n in 50-400, K in 3-8), each
     pair refined to 0.01 deg: one sbr_trace_batch call (persistent trace
-    over all jobs) against one sbr_trace call per pair.  Launch grids are
-    cached (both sides), the scenes' BVHs are built beforehand."""
+    over all jobs) against one sbr_trace call per pair, each side autotuned
+    over the same space.  Launch grids are cached (both sides), the scenes'
+    BVHs are built beforehand.  The per-pair results, renumbered to the
+    batch's receivers, must equal the batch's byte for byte."""
     from paper_2208_10009_amd import autotune
     b = scenes.batch_config(seed)
     jobs = [dict(j, iterations=30, target_err_deg=0.01) for j in b["jobs"]]
@@ -135,10 +256,10 @@ def batch_vs_plain(ctx, scenes, torch, seed=0, steps=2):
     build_s = time.perf_counter() - t0
     ctx.trace_batch(scs, jobs, b["rx"])  # warm-up: launch grids of every n
     base = ctx.tuning()
-    best, trials = autotune.autotune(
-        ctx, lambda: ctx.trace_batch(scs, jobs, b["rx"]),
-        space={"trace_chunk": [1, 2, 4], "persist_blocks": [1024, 2048, 4096, 8192],
-               "lookahead_max_paths": [0, 4096]}, warmup=0, steps=1)
+    space = {"trace_chunk": [1, 2, 4], "persist_blocks": [1024, 2048, 4096, 8192],
+             "lookahead_max_paths": [0, 4096]}
+    best, trials = autotune.autotune(ctx, lambda: ctx.trace_batch(scs, jobs, b["rx"]),
+                                     space=space, warmup=0, steps=1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -152,11 +273,12 @@ def batch_vs_plain(ctx, scenes, torch, seed=0, steps=2):
             prm = {k: v for k, v in j.items() if k not in ("scene", "tx", "rx_first", "n_rx")}
             rx = b["rx"][j["rx_first"]:j["rx_first"] + j["n_rx"]]
             p, _ = scs[j["scene"]].trace(j["tx"], rx, **prm)
+            p["rx"] += j["rx_first"]
             got.append(p)
         return np.concatenate(got)
 
-    ctx.set_tuning(**base)  # one call per pair: the default tuning
-    plain_pass()
+    ctx.set_tuning(**base)
+    best_p, _ = autotune.autotune(ctx, plain_pass, space=space, warmup=0, steps=1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -166,30 +288,57 @@ def batch_vs_plain(ctx, scenes, torch, seed=0, steps=2):
     for sc in scs:
         sc.close()
     ctx.set_tuning(**base)
+    pp = pp[np.argsort(pp["rx"], kind="stable")]
+    assert pp.tobytes() == pb.tobytes(), "batched paths differ from one call per pair"
     gb, gp = int(accurate_mask(pb).sum()), int(accurate_mask(pp).sum())
     return {
         "workload": "batch_16scenes_200-50k_tri_256pairs_n50-400_k3-8_target0.01deg",
         "triangles": [int(len(s["tri"])) for s in b["scenes"]], "pairs": len(jobs),
         "rays": int(n_rays), "bvh_build_s": round(build_s, 3),
-        "tuning": best, "tuning_trials": len(trials),
+        "same_bytes_as_one_call_per_pair": True,
         "batched": {"ms": round(1e3 * tb, 3), "rays_per_s": n_rays / tb,
                     "paths": int(len(pb)), "within_0.01deg": gb,
-                    "refined_paths_per_s": gb / tb,
+                    "refined_paths_per_s": gb / tb, "tuning": best,
+                    "tuning_trials": len(trials),
                     "stage_ms": {k: round(float(stb[k]), 4) for k in
                                  ("ms_launch", "ms_trace", "ms_dedup", "ms_refine", "ms_solve",
                                   "ms_emit", "ms_total")}},
         "plain": {"ms": round(1e3 * tp, 3), "rays_per_s": n_rays / tp, "paths": int(len(pp)),
-                  "tuning": base,
-                  "within_0.01deg": gp, "refined_paths_per_s": gp / tp},
+                  "tuning": best_p, "within_0.01deg": gp, "refined_paths_per_s": gp / tp},
         "speedup": tp / tb,
     }
 
 
-def large_city_leg(ctx, scenes, torch, steps=5, tuning=None):
-    """The large procedural city (about 500k triangles, 1024 Rx on a 32 x 32
-    grid, n = 1000: 10,000,002 rays, K = 8, I = 5, S = 6), one sbr_trace call
-    per step with the launch grid recomputed: rays/s, stage times, the trace
-    kernel's roofline, and refined paths/s in the 0.01 deg target mode."""
+STAGES = ("ms_launch", "ms_trace", "ms_dedup", "ms_refine", "ms_solve", "ms_emit", "ms_total")
+
+
+def timed_device(sc, cfg, torch, steps, warmup, out_buf, **kw):
+    """steps timed sbr_trace_device calls (after warmup ones): paths of the
+    last call, wall seconds, mean stage milliseconds (HIP events)."""
+    from paper_2208_10009_amd import sbr
+    rx_dev = torch.as_tensor(cfg["rx"], device="cuda")
+    for _ in range(warmup):
+        sc.trace_device(cfg["tx"], rx_dev, out=out_buf, **kw)
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        got, st = sc.trace_device(cfg["tx"], rx_dev, out=out_buf, **kw)
+        stats.append(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    paths = got.cpu().numpy().reshape(-1).view(sbr.PATH_DTYPE)
+    stage = {k: float(np.mean([x[k] for x in stats])) for k in STAGES}
+    return paths, wall, stage, stats
+
+
+def large_city_leg(ctx, scenes, torch, steps, warmup, tuning=None):
+    """The headline: the large procedural city (498,614 triangles, 1024 Rx on
+    a 32 x 32 grid, n = 1000: 10,000,002 rays, K = 8, I = 5, S = 6), one
+    sbr_trace_device call per step with the launch grid recomputed: rays/s,
+    stage times, the trace kernel's roofline, refined paths/s in the 0.01 deg
+    target mode and why paths miss it."""
+    from paper_2208_10009_amd import autotune, sbr
     cfg = scenes.large_city_config(0)
     prm = cfg["params"]
     n_rays = 10 * prm["division_n"] ** 2 + 2
@@ -197,11 +346,10 @@ def large_city_leg(ctx, scenes, torch, steps=5, tuning=None):
     sc = ctx.scene(cfg["scene"])
     build_s = time.perf_counter() - t0
     counts = sc.trace_counters(cfg["tx"], cfg["rx"], **prm)
-    from paper_2208_10009_amd import autotune
-    entry_tuning = ctx.tuning()
+    log("large city counts", counts)
     rx_tune = torch.as_tensor(cfg["rx"], device="cuda")
     if tuning:
-        ctx.set_tuning(**dict(entry_tuning, **tuning))
+        ctx.set_tuning(**dict(ctx.tuning(), **tuning))
         best = tuning
     else:
         best, _ = autotune.autotune(
@@ -210,50 +358,108 @@ def large_city_leg(ctx, scenes, torch, steps=5, tuning=None):
                    "rx_tree_min": [16, 1 << 30], "lds_budget": [65536, 0, 24 * 4 * 256],
                    "stack_depth": [24]}, warmup=1, steps=2)
     log("large city tuning", best)
-
-    from paper_2208_10009_amd import sbr
-    rx_dev = torch.as_tensor(cfg["rx"], device="cuda")
-
-    def run(kw):
-        sc.trace_device(cfg["tx"], rx_dev, **kw)
-        torch.cuda.synchronize()
-        stats = []
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            got, st = sc.trace_device(cfg["tx"], rx_dev, **kw)
-            stats.append(st)
-        torch.cuda.synchronize()
-        ms = 1e3 * (time.perf_counter() - t0) / steps
-        paths = got.cpu().numpy().reshape(-1).view(sbr.PATH_DTYPE)
-        stage = {k: round(float(np.mean([x[k] for x in stats])), 4)
-                 for k in ("ms_launch", "ms_trace", "ms_dedup", "ms_refine", "ms_solve",
-                           "ms_emit", "ms_total")}
-        return paths, ms, stage
-
-    paths, ms, stage = run(dict(prm, fresh_grid=True))
-    tpaths, tms, tstage = run(dict(prm, iterations=30, target_err_deg=0.01, fresh_grid=True))
+    out_buf = torch.empty((8192, sbr.PATH_DTYPE.itemsize), dtype=torch.uint8, device="cuda")
+    paths, wall, stage, stats = timed_device(sc, cfg, torch, steps, warmup, out_buf,
+                                             fresh_grid=True, **prm)
+    ms = 1e3 * wall / steps
+    log("large city stages (mean ms):", json.dumps(stage))
+    tpaths, twall, tstage, _ = timed_device(sc, cfg, torch, steps, 1, out_buf, fresh_grid=True,
+                                            **dict(prm, iterations=30, target_err_deg=0.01))
+    tms = 1e3 * twall / steps
     sc.close()
-    tuning = ctx.tuning()
-    ctx.set_tuning(**entry_tuning)
-    alg = (counts["nodes"] * NODE_BYTES + counts["tris"] * TRI_BYTES + n_rays * RAY_BYTES
-           + counts["events"] * EVENT_BYTES)
-    ach = alg / (stage["ms_trace"] * 1e-3) / 1e9
     tgood = int(accurate_mask(tpaths).sum())
-    return {
-        "workload": cfg["name"] + "_i5_s6",
+    t_paths_ms = tstage["ms_dedup"] + tstage["ms_refine"] + tstage["ms_solve"] + tstage["ms_emit"]
+    return cfg, {
+        "value": n_rays * steps / wall, "ms_per_step": ms,
         "triangles": int(len(cfg["scene"]["tri"])), "rx": int(len(cfg["rx"])), "rays": n_rays,
         "bvh_build_s": round(build_s, 3),
-        "ms_per_step": round(ms, 4), "rays_per_s": n_rays / (ms * 1e-3),
         "trace_rays_per_s": n_rays / (stage["ms_trace"] * 1e-3),
-        "paths": int(len(paths)), "stage_ms": stage, "counts": counts,
+        "paths": int(len(paths)), "stage_ms": {k: round(v, 4) for k, v in stage.items()},
+        "counts": counts, "tuning": ctx.tuning(),
+        "lds": {k: int(stats[-1][k]) for k in ("lds_bytes", "lds_nodes", "lds_tris", "lds_max")},
+        "roofline": trace_roofline(counts, n_rays, stage["ms_trace"], LARGE),
+        "refined_paths_per_s": tgood / (tms * 1e-3),
+        "refined_paths": {
+            "mode": "target 0.01 deg (AOD, AOA via L_last/L_total), at most 30 iterations",
+            "paths": int(len(tpaths)), "within_0.01deg": tgood, "ms_per_step": round(tms, 4),
+            "per_s_paths_stages": tgood / (t_paths_ms * 1e-3),
+            "mean_iterations": float(np.mean(tpaths["iters_used"])) if len(tpaths) else 0.0,
+            "stage_ms": {k: round(v, 4) for k, v in tstage.items()},
+            "misses": miss_breakdown(tpaths)},
+        "fixed_i5": {"paths": int(len(paths)), "within_0.01deg": int(accurate_mask(paths).sum())},
+    }
+
+
+def manhattan_leg(ctx, scenes, torch, args):
+    """The Manhattan grid (8 x 8 box buildings plus ground, 770 triangles),
+    Tx at 25 m, 64 Rx at 1.5 m on street centrelines, n = 200 (400,002
+    rays), K = 6, I = 5, S = 7: rays/s as stated, with cached launch
+    directions, through the host-array entry point and replayed from a
+    captured HIP graph; refined paths/s; the trace kernel's roofline."""
+    from paper_2208_10009_amd import autotune, sbr
+    cfg = scenes.manhattan_config(args.seed)
+    prm = cfg["params"]
+    sc = ctx.scene(cfg["scene"])
+    n_rays = 10 * prm["division_n"] ** 2 + 2
+    counts = sc.trace_counters(cfg["tx"], cfg["rx"], **prm)
+    rx_tune = torch.as_tensor(cfg["rx"], device="cuda")
+    entry = ctx.tuning()
+    if args.tuning:
+        ctx.set_tuning(**dict(entry, **args.tuning))
+        best = args.tuning
+    else:
+        best, _ = autotune.autotune(
+            ctx, lambda: sc.trace_device(cfg["tx"], rx_tune, **prm),
+            space={"trace_chunk": [1, 2], "persist_blocks": [640, 704, 768, 1024, 2048],
+                   "lds_budget": [65536, 0, 24 * 4 * 256], "stack_depth": [24],
+                   "lookahead_max_paths": [4096], "rx_tree_min": [16, 1 << 30]}, warmup=1,
+            steps=5)
+    log("manhattan tuning", best)
+    out_buf = torch.empty((4096, sbr.PATH_DTYPE.itemsize), dtype=torch.uint8, device="cuda")
+    steps, warmup = args.steps, args.warmup
+    paths, wall, stage, stats = timed_device(sc, cfg, torch, steps, warmup, out_buf,
+                                             fresh_grid=True, **prm)
+    # launch directions cached in the context (a tracer serving many calls at one n)
+    _, wall_c, _, _ = timed_device(sc, cfg, torch, steps, 1, out_buf, **prm)
+    # the host-array entry point: receivers and paths cross PCIe every call
+    for _ in range(1):
+        sc.trace(cfg["tx"], cfg["rx"], fresh_grid=True, **prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sc.trace(cfg["tx"], cfg["rx"], fresh_grid=True, **prm)
+    torch.cuda.synchronize()
+    wall_h = time.perf_counter() - t0
+    # replayed from a captured HIP graph
+    gpaths, wall_g, _, gstats = timed_device(sc, cfg, torch, steps, 2, out_buf, fresh_grid=True,
+                                             graph=True, **prm)
+    graph_replays = sum(1 for st in gstats if st["ms_trace"] == 0.0)
+    assert gpaths.tobytes() == paths.tobytes(), "graph replay differs from the eager call"
+    tpaths, twall, tstage, _ = timed_device(sc, cfg, torch, steps, 1, out_buf, fresh_grid=True,
+                                            **dict(prm, iterations=30, target_err_deg=0.01))
+    tms = 1e3 * twall / steps
+    tgood = int(accurate_mask(tpaths).sum())
+    sc.close()
+    tuning = ctx.tuning()
+    ctx.set_tuning(**entry)
+    return cfg, {
+        "workload": MANHATTAN, "triangles": len(cfg["scene"]["tri"]), "rays": n_rays,
+        "rx": len(cfg["rx"]), "value": n_rays * steps / wall, "ms_per_step": 1e3 * wall / steps,
+        "value_cached_grid": n_rays * steps / wall_c,
+        "value_host_arrays_pcie": n_rays * steps / wall_h,
+        "value_graph_replay": n_rays * steps / wall_g, "graph_replays": graph_replays,
+        "trace_rays_per_s": n_rays / (stage["ms_trace"] * 1e-3),
+        "stage_ms": {k: round(v, 5) for k, v in stage.items()}, "counts": counts,
+        "lds": {k: int(stats[-1][k]) for k in ("lds_bytes", "lds_nodes", "lds_tris", "lds_max")},
         "tuning": tuning,
-        "roofline": {"kernel": "k_trace", "bound": "hbm", "achieved": round(ach, 2),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5),
-                     "traffic": measured_traffic(cfg["name"] + "_i5_s6"),
-                     "algorithmic_bytes_per_launch": int(alg)},
+        "roofline": trace_roofline(counts, n_rays, stage["ms_trace"], MANHATTAN),
         "refined_paths_per_s": tgood / (tms * 1e-3),
         "refined_paths": {"paths": int(len(tpaths)), "within_0.01deg": tgood,
-                          "ms_per_step": round(tms, 4), "stage_ms": tstage},
+                          "ms_per_step": round(tms, 4),
+                          "mean_iterations": float(np.mean(tpaths["iters_used"])),
+                          "stage_ms": {k: round(v, 5) for k, v in tstage.items()},
+                          "misses": miss_breakdown(tpaths)},
+        "fixed_i5": {"paths": int(len(paths)), "within_0.01deg": int(accurate_mask(paths).sum())},
     }
 
 
@@ -299,14 +505,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-vs-plain comparison on the 256-pair workload")
-    ap.add_argument("--no-large", action="store_true",
-                    help="skip the large-city (500k triangles, 10M rays, 1024 Rx) leg")
+    ap.add_argument("--no-manhattan", action="store_true",
+                    help="skip the Manhattan (770 triangles, 400k rays, 64 Rx) leg")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the launch-grid / traditional-vs-precise comparison")
     ap.add_argument("--large-only", action="store_true",
-                    help="run only the large-city leg and print its JSON object (profiling)")
+                    help="run only the headline large-city leg and print its JSON object "
+                         "(profiling)")
+    ap.add_argument("--manhattan-only", action="store_true",
+                    help="run only the Manhattan leg and print its JSON object (profiling)")
     ap.add_argument("--tuning", type=json.loads, default=None, metavar="JSON",
-                    help="tuning fields for the stated configuration instead of autotuning "
+                    help="tuning fields for the Manhattan leg instead of autotuning "
                          "(profiling runs pin what an earlier run chose)")
     ap.add_argument("--large-tuning", type=json.loads, default=None, metavar="JSON",
                     help="the same for the large-city leg")
@@ -332,156 +541,54 @@ def main():
         torch.cuda.synchronize()
         log("copy probe: 5 x %d bytes" % (x.numel() * 4))
         return
-    if args.large_only:
-        ctx = sbr.Context(0)
-        print(json.dumps(large_city_leg(ctx, scenes, torch, tuning=args.large_tuning)), flush=True)
+    ctx = sbr.Context(0)
+    if args.manhattan_only:
+        print(json.dumps(manhattan_leg(ctx, scenes, torch, args)[1]), flush=True)
         ctx.close()
         return
-    cfg = scenes.manhattan_config(args.seed)
-    prm = cfg["params"]
-    ctx = sbr.Context(0)
-    sc = ctx.scene(cfg["scene"])
-    n_rays = 10 * prm["division_n"] ** 2 + 2
-
-    counts = sc.trace_counters(cfg["tx"], cfg["rx"], **prm)
-    log("counts", counts)
-    from paper_2208_10009_amd import autotune
-    rx_tune = torch.as_tensor(cfg["rx"], device="cuda")
-    if args.tuning:
-        ctx.set_tuning(**dict(ctx.tuning(), **args.tuning))
-        best = args.tuning
-    else:
-        best, _ = autotune.autotune(
-            ctx, lambda: sc.trace_device(cfg["tx"], rx_tune, **prm),
-            space={"trace_chunk": [1, 2], "persist_blocks": [640, 704, 768, 1024, 2048],
-                   "lds_budget": [65536, 0, 24 * 4 * 256], "stack_depth": [24],
-                   "lookahead_max_paths": [4096], "rx_tree_min": [16, 1 << 30]}, warmup=1,
-            steps=5)
-    log("tuning", best)
-
-    # Inputs resident in HBM: the receivers are a device tensor and the paths
-    # are written to a device buffer (sbr_trace_device); the transmitter and
-    # the parameters are call arguments.
-    rx_dev = torch.as_tensor(cfg["rx"], device="cuda")
-    out_buf = torch.empty((4096, sbr.PATH_DTYPE.itemsize), dtype=torch.uint8, device="cuda")
-
-    def run_dev(**kw):
-        got, st = sc.trace_device(cfg["tx"], rx_dev, out=out_buf, **kw)
-        return got, st
-
-    def timed(steps, warmup, host_api=False, **kw):
-        call = (lambda: sc.trace(cfg["tx"], cfg["rx"], **kw)) if host_api else \
-            (lambda: run_dev(**kw))
-        for _ in range(warmup):
-            call()
-        stats = []
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            paths, st = call()
-            stats.append(st)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        if not host_api:
-            paths = paths.cpu().numpy().reshape(-1).view(sbr.PATH_DTYPE)
-        return paths, stats, wall
-
-    # (1) the configuration as stated: I = 5 iterations, launch grid recomputed every step
-    paths, stats, wall = timed(args.steps, args.warmup, fresh_grid=True, **prm)
-    ms_step = 1e3 * wall / args.steps
-    good = int(accurate_mask(paths).sum())
-    stage = {k: float(np.mean([s[k] for s in stats]))
-             for k in ("ms_launch", "ms_trace", "ms_dedup", "ms_refine", "ms_solve", "ms_emit",
-                       "ms_total")}
-    log("stages (mean ms):", json.dumps(stage))
-    # (2) steady state of a tracer serving many calls at one division n: the
-    # launch directions stay cached in the context
-    _, _, wall_c = timed(args.steps, 1, **prm)
-    # (2b) the host-array entry point (sbr_trace): receivers and paths cross
-    # PCIe every call
-    _, _, wall_h = timed(args.steps, 1, host_api=True, fresh_grid=True, **prm)
-    # (2c) the stated configuration replayed from a captured HIP graph
-    gpaths, gstats, wall_g = timed(args.steps, 2, fresh_grid=True, graph=True, **prm)
-    graph_replays = sum(1 for st in gstats if st["ms_trace"] == 0.0)
-    assert gpaths.tobytes() == paths.tobytes(), "graph replay differs from the eager call"
-    # (3) refined paths at <= 0.01 deg: iterate each path until its AOD (and,
-    # through the L_last / L_total scaling, its AOA) error is below 0.01 deg
-    tprm = dict(prm, iterations=30, target_err_deg=0.01)
-    tpaths, tstats, twall = timed(args.steps, 1, fresh_grid=True, **tprm)
-    tms = 1e3 * twall / args.steps
-    tgood = int(accurate_mask(tpaths).sum())
-    tstage = {k: float(np.mean([s[k] for s in tstats]))
-              for k in ("ms_launch", "ms_trace", "ms_dedup", "ms_refine", "ms_solve", "ms_emit")}
-    t_paths_ms = tstage["ms_dedup"] + tstage["ms_refine"] + tstage["ms_solve"] + tstage["ms_emit"]
-
-    alg_bytes = (counts["nodes"] * NODE_BYTES + counts["tris"] * TRI_BYTES + n_rays * RAY_BYTES
-                 + counts["events"] * EVENT_BYTES)
-    achieved = alg_bytes / (stage["ms_trace"] * 1e-3) / 1e9
-    dominant = max(("ms_launch", "ms_trace", "ms_dedup", "ms_refine", "ms_solve", "ms_emit"),
-                   key=lambda k: stage[k])
-    roofline = {
-        "kernel": "k_trace",
-        "bound": "hbm",
-        "achieved": round(achieved, 2),
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 5),
-        "traffic": measured_traffic("manhattan_8x8_770tri_n200_k6_i5_s7_rx64"),
-        "algorithmic_bytes_per_launch": int(alg_bytes),
-        "kernel_ms": round(stage["ms_trace"], 5),
-        "dominant_stage": dominant,
-    }
+    lcfg, lc = large_city_leg(ctx, scenes, torch, args.steps, args.warmup,
+                              tuning=args.large_tuning)
+    if args.large_only:
+        print(json.dumps(lc), flush=True)
+        ctx.close()
+        return
+    prm = lcfg["params"]
     out = {
         "metric": METRIC,
-        "value": n_rays * args.steps / wall,
+        "value": lc.pop("value"),
         "unit": "rays/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": lc.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "manhattan_8x8_770tri_n200_k6_i5_s7_rx64",
-            "triangles": len(cfg["scene"]["tri"]), "rays": n_rays, "rx": len(cfg["rx"]),
+            "workload": LARGE, "triangles": lc["triangles"], "rays": lc["rays"], "rx": lc["rx"],
             "max_order": prm["max_order"], "iterations": prm["iterations"],
             "subrays": prm["subrays"], "freq_hz": prm["freq_hz"], "mode": "plain",
         },
-        "refined_paths_per_s": tgood / (tms * 1e-3),
-        "refined_paths": {
-            "mode": "target 0.01 deg (AOD, AOA via L_last/L_total), at most 30 iterations",
-            "paths": int(len(tpaths)), "within_0.01deg": tgood, "ms_per_step": round(tms, 4),
-            "per_s_paths_stages": tgood / (t_paths_ms * 1e-3),
-            "mean_iterations": float(np.mean(tpaths["iters_used"])) if len(tpaths) else 0.0,
-            "stage_ms": {k: round(v, 5) for k, v in tstage.items()},
-        },
-        "fixed_i5": {"paths": int(len(paths)), "within_0.01deg": good,
-                     "refined_paths_per_s": good / (ms_step * 1e-3)},
-        "value_cached_grid": n_rays * args.steps / wall_c,
-        "value_host_arrays_pcie": n_rays * args.steps / wall_h,
-        "value_graph_replay": n_rays * args.steps / wall_g,
-        "graph_replays": graph_replays,
-        "trace_rays_per_s": n_rays / (stage["ms_trace"] * 1e-3),
-        "stage_ms": {k: round(v, 5) for k, v in stage.items()},
-        "counts": counts,
-        "lds": {k: int(stats[-1][k]) for k in ("lds_bytes", "lds_nodes", "lds_tris", "lds_max")},
-        "tuning": ctx.tuning(),
-        "roofline": roofline,
+        "refined_paths_per_s": lc.pop("refined_paths_per_s"),
+        "roofline": lc.pop("roofline"),
     }
-    sc.close()
-    if not args.no_large:
-        out["large_city"] = large_city_leg(ctx, scenes, torch, tuning=args.large_tuning)
-        log("large city", json.dumps(out["large_city"]))
+    out.update(lc)
+    mcfg = None
+    if not args.no_manhattan:
+        mcfg, out["manhattan"] = manhattan_leg(ctx, scenes, torch, args)
+        log("manhattan", json.dumps(out["manhattan"]))
     if not args.no_variants:
         out["launch_variants"] = launch_variants(ctx, scenes, torch)
     if not args.no_batch:
         out["batched"] = batch_vs_plain(ctx, scenes, torch)
     ctx.close()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg)
+        out["cpu_baseline"] = cpu_baseline_large(lcfg)
+        log("cpu baseline", json.dumps(out["cpu_baseline"]))
+        if mcfg is not None:
+            out["manhattan"]["cpu_baseline"] = cpu_baseline_manhattan(mcfg)
     print(json.dumps(out), flush=True)
 
 

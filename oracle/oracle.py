@@ -147,6 +147,7 @@ def lib():
         L.orc_ray_events.argtypes = [dp, ip, C.c_int64, dp, C.c_int32, C.c_int32, C.c_int32, dp,
                                      C.c_int32, lp, C.c_int64, C.c_int32,
                                      C.POINTER(C.POINTER(_Cand)), lp]
+        L.orc_path_test1.argtypes = [C.c_void_p, C.c_int64, C.POINTER(C.POINTER(_Cand)), lp]
         L.orc_path_records.argtypes = [dp, ip, ip, C.c_int64, dp, dp, C.c_int32, dp, dp,
                                        C.c_int32, C.POINTER(Params), C.c_void_p, C.c_int64,
                                        C.c_void_p]
@@ -302,6 +303,18 @@ def ray_events(scene, tx, rx, n, max_order, ids, threads=0, launch=EQUIANGULAR):
     if rc:
         raise ValueError("orc_ray_events failed (%d)" % rc)
     return _take(cp, nc.value, CAND_DTYPE)
+
+
+def path_test1(events):
+    """Path test 1 over reception events (a CAND_DTYPE array): one winner per
+    (rx, order, face sequence), sorted by that key."""
+    ev = np.ascontiguousarray(events, dtype=CAND_DTYPE)
+    up = C.POINTER(_Cand)()
+    nu = C.c_int64()
+    rc = lib().orc_path_test1(ev.ctypes.data_as(C.c_void_p), len(ev), C.byref(up), C.byref(nu))
+    if rc:
+        raise ValueError("orc_path_test1 failed (%d)" % rc)
+    return _take(up, nu.value, CAND_DTYPE)
 
 
 def path_records(scene, tx, rx, winners, **kw):

@@ -1117,6 +1117,21 @@ int orc_ray_events(const double* tri_v, const int32_t* face_id, int64_t T, const
     return 0;
 }
 
+int orc_path_test1(const orc_candidate* in, int64_t n, orc_candidate** out, int64_t* n_out)
+{
+    if (n < 0 || (n > 0 && !in) || !out || !n_out) return -1;
+    orc_candidate* srt = (orc_candidate*)malloc(sizeof(orc_candidate) * (size_t)(n > 0 ? n : 1));
+    if (!srt) return -2;
+    if (n) memcpy(srt, in, sizeof(orc_candidate) * (size_t)n);
+    qsort(srt, (size_t)n, sizeof(orc_candidate), cand_cmp);
+    int64_t nu = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (i == 0 || key_cmp(&srt[i], &srt[nu - 1]) != 0) srt[nu++] = srt[i];
+    *out = srt;
+    *n_out = nu;
+    return 0;
+}
+
 int orc_path_records(const double* tri_v, const int32_t* face_id, const int32_t* mat_id,
                      int64_t T, const double* eps_re, const double* eps_im, int32_t n_mat,
                      const double tx[3], const double* rx, int32_t n_rx, const orc_params* P,

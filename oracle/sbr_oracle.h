@@ -106,6 +106,11 @@ int orc_ray_events(const double* tri_v, const int32_t* face_id, int64_t n_tri,
                    int32_t n_rx, const int64_t* ids, int64_t m, int32_t n_threads,
                    orc_candidate** out, int64_t* n_out);
 
+/* Path test 1 alone: of the events in[0..n-1], one per (rx, order, face
+ * sequence), the smallest tan_err (ties: lowest ray), sorted by that key;
+ * returned in a malloc'd array. */
+int orc_path_test1(const orc_candidate* in, int64_t n, orc_candidate** out, int64_t* n_out);
+
 /* Steps 3-4 alone for given path-test-1 winners win[0..m-1] (rx, order,
  * faces, launch ray, tan_err): out[i] is the record orc_run produces for
  * that winner, with the INVALID flag set but nothing dropped. */

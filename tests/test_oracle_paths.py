@@ -657,3 +657,12 @@ def test_subray_tie_keeps_lower_subray_index(orc):
     p = orc.run(empty, tx, rx[None], max_order=0, division_n=n, iterations=1, subrays=6)["paths"]
     assert len(p) == 1 and p["launch_ray"][0] == 0 and p["iters_used"][0] == 1
     assert np.abs(p["axis"][0] - subs[1]).max() < 1e-15
+
+
+def test_path_test1_alone_equals_the_whole_method(orc):
+    """orc_path_test1 over the events of orc_run gives orc_run's winners."""
+    cfg = scenes.shoebox_config(2)
+    r = orc.run(cfg["scene"], cfg["tx"], cfg["rx"], **cfg["params"])
+    u = orc.path_test1(r["candidates"][::-1].copy())
+    assert u.tobytes() == r["unique"].tobytes()
+    assert len(orc.path_test1(r["candidates"][:0])) == 0
