@@ -94,6 +94,30 @@ class _Path(C.Structure):
     ]
 
 
+class _DPath(C.Structure):
+    _fields_ = [
+        ("rx", C.c_int32),
+        ("wedge", C.c_int32),
+        ("launch_ray", C.c_int64),
+        ("iters_used", C.c_int32),
+        ("flags", C.c_uint32),
+        ("tan_err", C.c_double),
+        ("axis", C.c_double * 3),
+        ("point", C.c_double * 3),
+        ("delay_s", C.c_double),
+        ("aod", C.c_double * 3),
+        ("aoa", C.c_double * 3),
+        ("err_angle_deg", C.c_double),
+        ("length_m", C.c_double),
+        ("exact_point", C.c_double * 3),
+        ("exact_delay_s", C.c_double),
+        ("exact_aod", C.c_double * 3),
+        ("exact_aoa", C.c_double * 3),
+        ("exact_length_m", C.c_double),
+        ("init_tan_err", C.c_double),
+    ]
+
+
 def _np_dtype(struct):
     fields = []
     for name, ct in struct._fields_:
@@ -108,6 +132,7 @@ def _np_dtype(struct):
 
 CAND_DTYPE = _np_dtype(_Cand)
 PATH_DTYPE = _np_dtype(_Path)
+DPATH_DTYPE = _np_dtype(_DPath)
 
 _lib = None
 
@@ -151,6 +176,14 @@ def lib():
         L.orc_path_records.argtypes = [dp, ip, ip, C.c_int64, dp, dp, C.c_int32, dp, dp,
                                        C.c_int32, C.POINTER(Params), C.c_void_p, C.c_int64,
                                        C.c_void_p]
+        L.orc_wedges.restype = C.c_int64
+        L.orc_wedges.argtypes = [dp, ip, C.c_int64, dp, C.c_int64]
+        L.orc_diffract.argtypes = [dp, ip, C.c_int64, dp, dp, C.c_int32, C.POINTER(Params),
+                                   C.POINTER(C.POINTER(_Cand)), lp,
+                                   C.POINTER(C.POINTER(_Cand)), lp,
+                                   C.POINTER(C.POINTER(_DPath)), lp]
+        L.orc_diffract_history.argtypes = [dp, ip, C.c_int64, dp, C.POINTER(Params), dp, ip, dp,
+                                           C.c_int64, dp]
         L.orc_exact_path.argtypes = [dp, ip, ip, C.c_int64, dp, dp, dp, dp, C.c_int32, ip,
                                      C.c_double, C.c_double, dp, dp, dp, ip]
     return _lib
@@ -370,3 +403,56 @@ def exact_path(scene, tx, rx, faces, freq_hz=28e9, tx_power_dbm=0.0):
     if rc:
         raise ValueError("orc_exact_path failed (%d)" % rc)
     return pts[:k], L.value, P.value, bool(V.value)
+
+
+def wedges(scene):
+    """Wedges of the scene (order-1 diffraction edges): dict of arrays a, b, e,
+    u0, u1 [W, 3] and faces [W, 2]."""
+    tri_v, face, _, _, _ = _scene_arrays(scene)
+    n = lib().orc_wedges(_d(tri_v), _i(face), len(face), None, 0)
+    if n < 0:
+        raise ValueError("orc_wedges failed")
+    out = np.zeros((max(n, 1), 17), np.float64)
+    lib().orc_wedges(_d(tri_v), _i(face), len(face), _d(out), n)
+    out = out[:n]
+    return {"a": out[:, 0:3], "b": out[:, 3:6], "e": out[:, 6:9], "u0": out[:, 9:12],
+            "u1": out[:, 12:15], "faces": out[:, 15:17].astype(np.int32)}
+
+
+def diffract(scene, tx, rx, **kw):
+    """Order-1 diffraction (events, winners, paths); events and winners are
+    CAND_DTYPE with order 1 and face[0] = wedge index."""
+    tri_v, face, _, _, _ = _scene_arrays(scene)
+    txa = np.ascontiguousarray(tx, dtype=np.float64)
+    rxa = np.ascontiguousarray(np.asarray(rx, dtype=np.float64).reshape(-1, 3))
+    prm = make_params(**kw)
+    cp = C.POINTER(_Cand)()
+    up = C.POINTER(_Cand)()
+    pp = C.POINTER(_DPath)()
+    nc, nu, npth = C.c_int64(), C.c_int64(), C.c_int64()
+    rc = lib().orc_diffract(_d(tri_v), _i(face), len(face), _d(txa), _d(rxa), len(rxa),
+                            C.byref(prm), C.byref(cp), C.byref(nc), C.byref(up), C.byref(nu),
+                            C.byref(pp), C.byref(npth))
+    if rc:
+        raise ValueError("orc_diffract failed (%d)" % rc)
+    return {
+        "candidates": _take(cp, nc.value, CAND_DTYPE),
+        "unique": _take(up, nu.value, CAND_DTYPE),
+        "paths": _take(pp, npth.value, DPATH_DTYPE),
+    }
+
+
+def diffract_history(scene, tx, rx_rows, wedge_ids, axes, **kw):
+    """tan(theta_error) after each iteration for diffraction rows."""
+    tri_v, face, _, _, _ = _scene_arrays(scene)
+    prm = make_params(**kw)
+    rx_rows = np.ascontiguousarray(rx_rows, dtype=np.float64).reshape(-1, 3)
+    wid = np.ascontiguousarray(wedge_ids, dtype=np.int32)
+    axes = np.ascontiguousarray(axes, dtype=np.float64).reshape(-1, 3)
+    hist = np.empty((len(wid), prm.iterations + 1), np.float64)
+    txa = np.ascontiguousarray(tx, dtype=np.float64)
+    rc = lib().orc_diffract_history(_d(tri_v), _i(face), len(face), _d(txa), C.byref(prm),
+                                    _d(rx_rows), _i(wid), _d(axes), len(wid), _d(hist))
+    if rc:
+        raise ValueError("orc_diffract_history failed (%d)" % rc)
+    return hist

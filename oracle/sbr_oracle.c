@@ -681,6 +681,85 @@ static int target_met(double tan_err, double tan_tgt, double D, double Llast)
     return tan_err <= thr;
 }
 
+/* The precise algorithm's loop, shared by reflection and diffraction paths.
+ * follow(ctx, d, ...) decides whether direction d still forms the path (for a
+ * reflection path: meets its faces in order with Rx ahead; for a diffraction
+ * path: passes and reaches its wedge) and gives tan(error angle), the
+ * unfolded length D to the last interaction and the last leg Llast, and the
+ * path's geometry in *g. */
+typedef struct dfollow_s dfollow_t;
+typedef int (*follow_fn)(const void* ctx, v3 d, double* tan_err, double* D, double* Llast,
+                         void* g);
+
+typedef struct {
+    v3 axis;
+    double tan_err;
+    int32_t iters;
+    uint32_t flags;
+} refine_state;
+
+/* Start from the winner of path test 1 (axis a0) and iterate: per iteration
+ * shrink the cone by 1/sqrt3 and launch the sub-rays; the smallest error
+ * angle among those that still form the path becomes the new axis (ties:
+ * lower sub-ray); none: STALLED, stop.  Stop after n_it iterations or once
+ * the target is met.  cur, tmp, win: three geometry buffers of `gsz` bytes;
+ * cur ends with the reported ray's. */
+static void refine_loop(follow_fn follow, const void* ctx, void* cur, void* tmp, void* win,
+                        size_t gsz, v3 a0, int32_t n_it, int32_t Sn, double tan_tgt, double thl,
+                        refine_state* R, double* hist)
+{
+    double tn, D, Ll;
+    R->axis = a0;
+    R->iters = 0;
+    R->flags = 0;
+    if (!follow(ctx, a0, &tn, &D, &Ll, cur)) {
+        /* cannot happen for a captured ray; guarded for external rows */
+        R->tan_err = NAN;
+        R->flags |= 1u;
+        if (hist) hist[0] = NAN;
+        return;
+    }
+    R->tan_err = tn;
+    if (hist) hist[0] = R->tan_err;
+    double rho = thl;
+    int met = tan_tgt > 0.0 && target_met(R->tan_err, tan_tgt, D, Ll);
+    if (met) R->flags |= 4u;
+    for (int32_t i = 1; i <= n_it && !met; ++i) {
+        rho = rho / sqrt(3.0);
+        v3 u, v;
+        basis(R->axis, &u, &v);
+        int bs = -1;
+        double bt = INFINITY, bD = 0.0, bL = 0.0;
+        v3 bd = R->axis;
+        for (int s = 0; s < Sn; ++s) {
+            v3 ds = subray(R->axis, u, v, rho, s);
+            if (!follow(ctx, ds, &tn, &D, &Ll, tmp)) continue;
+            if (tn < bt) {
+                bt = tn;
+                bs = s;
+                bd = ds;
+                bD = D;
+                bL = Ll;
+                memcpy(win, tmp, gsz);
+            }
+        }
+        if (bs < 0) {
+            R->flags |= 1u;   /* STALLED: no sub-ray still forms the path */
+            if (hist) for (int32_t q = i; q <= n_it; ++q) hist[q] = R->tan_err;
+            break;
+        }
+        R->axis = bd;
+        R->tan_err = bt;
+        memcpy(cur, win, gsz);
+        R->iters = i;
+        if (hist) hist[i] = bt;
+        if (tan_tgt > 0.0 && target_met(bt, tan_tgt, bD, bL)) {
+            R->flags |= 4u;
+            met = 1;
+        }
+    }
+}
+
 typedef struct {
     v3 axis;
     double tan_err;
@@ -689,55 +768,38 @@ typedef struct {
     follow_t fw;
 } refine_t;
 
-/* One path: start from the winner of path test 1 and iterate. */
+typedef struct {
+    const scene_t* S;
+    v3 tx, rx;
+    int32_t k;
+    const int32_t* faces;
+} refl_ctx;
+
+static int follow_refl_cb(const void* c, v3 d, double* tn, double* D, double* Ll, void* g)
+{
+    const refl_ctx* x = (const refl_ctx*)c;
+    follow_t* fw = (follow_t*)g;
+    if (!follow_path(x->S, x->tx, d, x->rx, x->k, x->faces, fw)) return 0;
+    *tn = fw->tan_err;
+    *D = fw->D;
+    *Ll = fw->Llast;
+    return 1;
+}
+
+/* One reflection path: the precise algorithm from its path-test-1 winner. */
 static void refine_path(const scene_t* S, v3 tx, v3 rx, int32_t k, const int32_t* faces,
                         v3 a0, int32_t n_it, int32_t Sn, double tan_tgt, double thl,
                         refine_t* R, double* hist)
 {
-    R->axis = a0;
-    R->iters = 0;
-    R->flags = 0;
-    if (!follow_path(S, tx, a0, rx, k, faces, &R->fw)) {
-        /* cannot happen for a captured ray; guarded for external rows */
-        R->tan_err = NAN;
-        R->flags |= 1u;
-        if (hist) hist[0] = NAN;
-        return;
-    }
-    R->tan_err = R->fw.tan_err;
-    if (hist) hist[0] = R->tan_err;
-    double rho = thl;
-    int met = tan_tgt > 0.0 && target_met(R->tan_err, tan_tgt, R->fw.D, R->fw.Llast);
-    if (met) R->flags |= 4u;
-    for (int32_t i = 1; i <= n_it && !met; ++i) {
-        rho = rho / sqrt(3.0);
-        v3 u, v;
-        basis(R->axis, &u, &v);
-        int bs = -1;
-        double bt = INFINITY;
-        v3 bd = R->axis;
-        follow_t bfw;
-        for (int s = 0; s < Sn; ++s) {
-            v3 ds = subray(R->axis, u, v, rho, s);
-            follow_t fw;
-            if (!follow_path(S, tx, ds, rx, k, faces, &fw)) continue;
-            if (fw.tan_err < bt) { bt = fw.tan_err; bs = s; bd = ds; bfw = fw; }
-        }
-        if (bs < 0) {
-            R->flags |= 1u;   /* STALLED: no sub-ray keeps the face sequence */
-            if (hist) for (int32_t q = i; q <= n_it; ++q) hist[q] = R->tan_err;
-            break;
-        }
-        R->axis = bd;
-        R->tan_err = bt;
-        R->fw = bfw;
-        R->iters = i;
-        if (hist) hist[i] = bt;
-        if (tan_tgt > 0.0 && target_met(bt, tan_tgt, bfw.D, bfw.Llast)) {
-            R->flags |= 4u;
-            met = 1;
-        }
-    }
+    refl_ctx x = {S, tx, rx, k, faces};
+    follow_t tmp, win;
+    refine_state st;
+    refine_loop(follow_refl_cb, &x, &R->fw, &tmp, &win, sizeof(follow_t), a0, n_it, Sn, tan_tgt,
+                thl, &st, hist);
+    R->axis = st.axis;
+    R->tan_err = st.tan_err;
+    R->iters = st.iters;
+    R->flags = st.flags;
 }
 
 /* ======================================================================== */
@@ -1190,4 +1252,501 @@ int orc_refine_history(const double* tri_v, const int32_t* face_id, int64_t T,
     }
     scene_free(&S);
     return 0;
+}
+
+/* ======================================================================== */
+/* Order-1 diffraction -- Sec. III.A ("faces or wedges"), Sec. III.B         */
+/* (recorded diffraction directions), Sec. IV (order-1 diffraction paths)    */
+/* ======================================================================== */
+/* Reading: a wedge is a mesh edge (two endpoints with exactly equal
+ * coordinates) shared by triangles of exactly two faces whose planes meet at
+ * an angle of at least 10 degrees (|n0 . n1| <= cos 10 deg).  Its endpoints
+ * are ordered lexicographically (x, then y, then z), a < b; wedges are listed
+ * in that order of (a, b).  e = (b - a) / |b - a|.  For each of its faces
+ * (f0 < f1) u_k is the unit vector in the face's plane, normal to the edge,
+ * pointing into the face (toward the third vertex of the face's
+ * lowest-index triangle on the edge). */
+static const double COS_WEDGE = 0.984807753012208; /* cos(10 deg), nearest double */
+
+typedef struct {
+    v3 a, b, e, u0, u1;
+    double len;
+    int32_t f0, f1;
+} wedge_t;
+
+typedef struct {
+    double lo[3], hi[3];
+    int32_t face;
+    int64_t tri;
+    double c[3];      /* third vertex */
+} edge_rec;
+
+static int lex3(const double* p, const double* q)
+{
+    for (int i = 0; i < 3; ++i)
+        if (p[i] != q[i]) return p[i] < q[i] ? -1 : 1;
+    return 0;
+}
+
+static int edge_cmp(const void* pa, const void* pb)
+{
+    const edge_rec *a = (const edge_rec*)pa, *b = (const edge_rec*)pb;
+    int c = lex3(a->lo, b->lo);
+    if (c) return c;
+    c = lex3(a->hi, b->hi);
+    if (c) return c;
+    if (a->face != b->face) return a->face < b->face ? -1 : 1;
+    if (a->tri != b->tri) return a->tri < b->tri ? -1 : 1;
+    return 0;
+}
+
+static v3 in_face_dir(v3 a, v3 e, v3 c)
+{
+    v3 w = sub(c, a);
+    return normalize(sub(w, scl(dot(w, e), e)));
+}
+
+/* Wedges of the scene; returns their number (malloc'd array in *out). */
+static int64_t wedges_build(const scene_t* S, const double* tri_v, wedge_t** out)
+{
+    int64_t T = S->T, ne = 3 * T;
+    edge_rec* E = (edge_rec*)malloc(sizeof(edge_rec) * (size_t)(ne > 0 ? ne : 1));
+    int64_t m = 0;
+    for (int64_t i = 0; i < T; ++i)
+        for (int k = 0; k < 3; ++k) {
+            const double* p = tri_v + 9 * i + 3 * k;
+            const double* q = tri_v + 9 * i + 3 * ((k + 1) % 3);
+            const double* c = tri_v + 9 * i + 3 * ((k + 2) % 3);
+            int o = lex3(p, q);
+            if (o == 0) continue;
+            edge_rec r;
+            memcpy(r.lo, o < 0 ? p : q, sizeof r.lo);
+            memcpy(r.hi, o < 0 ? q : p, sizeof r.hi);
+            memcpy(r.c, c, sizeof r.c);
+            r.face = S->face[i];
+            r.tri = i;
+            E[m++] = r;
+        }
+    qsort(E, (size_t)m, sizeof(edge_rec), edge_cmp);
+    wedge_t* W = (wedge_t*)malloc(sizeof(wedge_t) * (size_t)(m > 0 ? m : 1));
+    int64_t nw = 0;
+    for (int64_t i = 0; i < m;) {
+        int64_t j = i;
+        while (j < m && lex3(E[j].lo, E[i].lo) == 0 && lex3(E[j].hi, E[i].hi) == 0) ++j;
+        /* records i..j-1 share the edge, sorted by face then triangle */
+        int nf = 0;
+        int64_t first[2] = {-1, -1};
+        for (int64_t q = i; q < j; ++q)
+            if (q == i || E[q].face != E[q - 1].face) {
+                if (nf < 2) first[nf] = q;
+                ++nf;
+            }
+        if (nf == 2) {
+            const edge_rec *r0 = &E[first[0]], *r1 = &E[first[1]];
+            double cs = fabs(dot(S->fn[r0->face], S->fn[r1->face]));
+            if (cs <= COS_WEDGE) {
+                wedge_t w;
+                w.a = ld3(r0->lo);
+                w.b = ld3(r0->hi);
+                v3 d = sub(w.b, w.a);
+                w.len = norm(d);
+                w.e = mk(d.x / w.len, d.y / w.len, d.z / w.len);
+                w.f0 = r0->face;
+                w.f1 = r1->face;
+                w.u0 = in_face_dir(w.a, w.e, ld3(r0->c));
+                w.u1 = in_face_dir(w.a, w.e, ld3(r1->c));
+                W[nw++] = w;
+            }
+        }
+        i = j;
+    }
+    free(E);
+    *out = W;
+    return nw;
+}
+
+int64_t orc_wedges(const double* tri_v, const int32_t* face_id, int64_t T, double* out,
+                   int64_t cap)
+{
+    if (T < 0 || (T > 0 && (!tri_v || !face_id))) return -1;
+    scene_t S;
+    if (scene_init(&S, tri_v, face_id, NULL, T)) { scene_free(&S); return -1; }
+    wedge_t* W;
+    int64_t nw = wedges_build(&S, tri_v, &W);
+    for (int64_t i = 0; i < nw && i < cap && out; ++i) {
+        double* o = out + 17 * i;
+        st3(o, W[i].a); st3(o + 3, W[i].b); st3(o + 6, W[i].e);
+        st3(o + 9, W[i].u0); st3(o + 12, W[i].u1);
+        o[15] = (double)W[i].f0;
+        o[16] = (double)W[i].f1;
+    }
+    free(W);
+    scene_free(&S);
+    return nw;
+}
+
+/* Inside the wedge: strictly between its two faces, in the sector where both
+ * faces lie (the solid side of a convex edge): the part of P - a normal to the
+ * edge is b u0 + c u1 with b > 0 and c > 0. */
+static int wedge_interior(const wedge_t* W, v3 P)
+{
+    v3 v = sub(P, W->a);
+    v3 r = sub(v, scl(dot(v, W->e), W->e));
+    double g = dot(W->u0, W->u1);
+    double r0 = dot(r, W->u0), r1 = dot(r, W->u1);
+    return (r0 - g * r1 > 0.0) && (r1 - g * r0 > 0.0);
+}
+
+/* Closest approach of the ray o + t d and the edge line a + s e:
+ * t (along the ray) and s (along the edge); 0 when the lines are (nearly)
+ * parallel. */
+static int ray_edge(const wedge_t* W, v3 o, v3 d, double* t_out, double* s_out)
+{
+    v3 w0 = sub(o, W->a);
+    double b = dot(d, W->e), dd = dot(d, d), ee = dot(W->e, W->e);
+    double dw = dot(d, w0), ew = dot(W->e, w0);
+    double den = dd * ee - b * b;
+    if (!(den > 1e-12)) return 0;
+    *t_out = (b * ew - ee * dw) / den;
+    *s_out = (dd * ew - b * dw) / den;
+    return 1;
+}
+
+/* The receiver unfolded about the edge: Rx rotated about the edge line into
+ * the half-plane through the edge opposite Tx.  The exact order-1 diffraction
+ * path Tx -> Q -> Rx (equal angles with the edge on both sides, Keller's law)
+ * unfolds into the straight line Tx -> Rx', so the angle between a ray and
+ * Rx' - Tx is that ray's departure-angle error -- the diffraction reading of
+ * eq. (3), as for reflections.  Returns 0 when Tx or Rx lies on the edge
+ * line.  *rho_t, *rho_x, *at, *ax: distances from and positions along the
+ * edge line. */
+static int unfold_rx(const wedge_t* W, v3 tx, v3 rx, v3* rxp, double* at, double* ax,
+                     double* rho_t, double* rho_x)
+{
+    v3 vx = sub(rx, W->a), vt = sub(tx, W->a);
+    *ax = dot(vx, W->e);
+    *at = dot(vt, W->e);
+    v3 rxv = sub(vx, scl(*ax, W->e)), rtv = sub(vt, scl(*at, W->e));
+    *rho_x = norm(rxv);
+    *rho_t = norm(rtv);
+    if (!(*rho_t > 0.0) || !(*rho_x > 0.0)) return 0;
+    double k = *rho_x / *rho_t;
+    *rxp = sub(add(W->a, scl(*ax, W->e)), scl(k, rtv));
+    return 1;
+}
+
+/* One ray from Tx in direction d, taken as diffracted at the wedge W toward
+ * Rx (its unfolded image rxp): the ray must pass the edge segment
+ * (closest approach at t > 0, 0 <= s <= len) and reach it (its first hit is
+ * beyond t, or on one of the wedge's own faces, which it clips at the edge);
+ * then tan(error angle) is that of rxp on the ray, as in eq. (3) with D = 0.
+ * Q is the diffraction point, the edge point nearest the ray. */
+struct dfollow_s {
+    double tan_err, t, s, delta, L1, L2;
+    v3 q;
+};
+
+/* The ray from Tx in direction d passes the edge segment (closest approach
+ * at t > 0, 0 <= s <= len) and reaches it: its first hit (th, on face fh;
+ * fh = -1: none) lies beyond t or on one of the wedge's own faces, which a ray
+ * clipping the edge meets there. */
+static int ray_reaches_edge(const wedge_t* W, v3 tx, v3 d, double th, int32_t fh, double* t,
+                            double* s)
+{
+    if (!ray_edge(W, tx, d, t, s)) return 0;
+    if (!(*t > 0.0) || !(*s >= 0.0) || !(*s <= W->len)) return 0;
+    if (fh >= 0 && !(th >= *t) && fh != W->f0 && fh != W->f1) return 0;
+    return 1;
+}
+
+static int follow_diff(const scene_t* S, const wedge_t* W, v3 tx, v3 d, v3 rx, v3 rxp,
+                       dfollow_t* F)
+{
+    double th, t, s;
+    int64_t hit = closest_hit(S, tx, d, -1, &th);
+    if (!ray_reaches_edge(W, tx, d, th, hit < 0 ? -1 : S->face[hit], &t, &s)) return 0;
+    v3 w = sub(rxp, tx);
+    double ts = dot(w, d);
+    if (!(ts > 0.0)) return 0;
+    v3 f = sub(w, scl(ts, d));
+    double dp = norm(f);
+    v3 p = add(tx, scl(t, d));
+    F->q = add(W->a, scl(s, W->e));
+    F->delta = norm(sub(p, F->q));
+    F->tan_err = dp / ts;
+    F->t = t;
+    F->s = s;
+    F->L1 = norm(sub(F->q, tx));
+    F->L2 = norm(sub(rx, F->q));
+    return 1;
+}
+
+/* Reception of a diffracted ray (the SBR step), for a ray that passes and
+ * reaches the edge (closest approach t, edge point q): the edge crosses the
+ * ray cone there (|p - q| <= theta_launch t), and the receiver's unfolded
+ * image lies inside the ray cone (tan error <= theta_launch: eq. (3) with
+ * D = 0 and the unfolded receiver).  Receivers inside the wedge are skipped
+ * before (they are not unfolded). */
+static int capture_diff(v3 tx, v3 d, v3 rxp, double thl, double* tan_out)
+{
+    v3 w = sub(rxp, tx);
+    double ts = dot(w, d);
+    if (!(ts > 0.0)) return 0;
+    v3 f = sub(w, scl(ts, d));
+    double dp = norm(f);
+    if (!(dp <= thl * ts)) return 0;
+    *tan_out = dp / ts;
+    return 1;
+}
+
+/* Precise algorithm for a diffraction path (Sec. III.B): the sub-ray cones
+ * of the reflection paths, each sub-ray diffracted in the recorded direction
+ * -- at the same wedge, toward the same receiver -- so only rays that pass
+ * that edge and reach it count; the smallest error angle wins. */
+typedef struct {
+    v3 axis;
+    double tan_err;
+    int32_t iters;
+    uint32_t flags;
+    dfollow_t fw;
+} drefine_t;
+
+typedef struct {
+    const scene_t* S;
+    const wedge_t* W;
+    v3 tx, rx, rxp;
+} diff_ctx;
+
+static int follow_diff_cb(const void* c, v3 d, double* tn, double* D, double* Ll, void* g)
+{
+    const diff_ctx* x = (const diff_ctx*)c;
+    dfollow_t* fw = (dfollow_t*)g;
+    if (!follow_diff(x->S, x->W, x->tx, d, x->rx, x->rxp, fw)) return 0;
+    *tn = fw->tan_err;
+    *D = fw->L1;
+    *Ll = fw->L2;
+    return 1;
+}
+
+static void refine_diff(const scene_t* S, const wedge_t* W, v3 tx, v3 rx, v3 a0, int32_t n_it,
+                        int32_t Sn, double tan_tgt, double thl, drefine_t* R, double* hist)
+{
+    diff_ctx x = {S, W, tx, rx, rx};
+    double at, ax, rt, rr;
+    refine_state st;
+    memset(&R->fw, 0, sizeof(R->fw));
+    if (!unfold_rx(W, tx, rx, &x.rxp, &at, &ax, &rt, &rr)) {
+        R->axis = a0;
+        R->tan_err = NAN;
+        R->iters = 0;
+        R->flags = 1u;
+        if (hist) hist[0] = NAN;
+        return;
+    }
+    dfollow_t tmp, win;
+    refine_loop(follow_diff_cb, &x, &R->fw, &tmp, &win, sizeof(dfollow_t), a0, n_it, Sn, tan_tgt,
+                thl, &st, hist);
+    R->axis = st.axis;
+    R->tan_err = st.tan_err;
+    R->iters = st.iters;
+    R->flags = st.flags;
+}
+
+/* Exact order-1 diffraction path (Keller's law: the path makes equal angles
+ * with the edge on both sides): Q = a + s e with
+ * s = at + (ax - at) rho_t / (rho_t + rho_x).  Path test 2: Q on the edge
+ * segment (tolerance 1e-9 of its length), Tx and Rx outside the wedge, both
+ * segments unobstructed by any face but the wedge's two. */
+static int exact_diff(const scene_t* S, const wedge_t* W, v3 tx, v3 rx, v3* q)
+{
+    v3 rxp;
+    double at, ax, rt, rr;
+    if (!unfold_rx(W, tx, rx, &rxp, &at, &ax, &rt, &rr)) {
+        *q = W->a;
+        return 0;
+    }
+    double s = at + (ax - at) * (rt / (rt + rr));
+    *q = add(W->a, scl(s, W->e));
+    const double tol = 1e-9 * W->len;
+    if (!(s >= -tol) || !(s <= W->len + tol)) return 0;
+    if (wedge_interior(W, tx) || wedge_interior(W, rx)) return 0;
+    if (blocked(S, tx, *q, W->f0, W->f1)) return 0;
+    if (blocked(S, *q, rx, W->f0, W->f1)) return 0;
+    return 1;
+}
+
+static void diff_record(const scene_t* S, const wedge_t* W, v3 TX, const grid_t* G,
+                        const double* rx, const orc_candidate* c, const orc_params* P,
+                        double tan_tgt, double thl, orc_dpath* o)
+{
+    v3 R = ld3(rx + 3 * c->rx);
+    drefine_t rf;
+    refine_diff(S, W, TX, R, grid_dir(G, c->ray), P->iterations, P->subrays, tan_tgt, thl, &rf,
+                NULL);
+    memset(o, 0, sizeof(*o));
+    o->rx = c->rx;
+    o->wedge = c->face[0];
+    o->launch_ray = c->ray;
+    o->iters_used = rf.iters;
+    o->flags = rf.flags;
+    o->init_tan_err = c->tan_err;
+    o->tan_err = rf.tan_err;
+    st3(o->axis, rf.axis);
+    /* refined path: Tx -> the edge point nearest the final ray -> Rx */
+    st3(o->point, rf.fw.q);
+    double L = rf.fw.L1 + rf.fw.L2;
+    o->length_m = L;
+    o->delay_s = L / C0;
+    st3(o->aod, rf.axis);
+    st3(o->aoa, normalize(sub(rf.fw.q, R)));
+    o->err_angle_deg = atan_cr(rf.tan_err) * (180.0 / PI_D);
+    v3 q;
+    int ok = exact_diff(S, W, TX, R, &q);
+    st3(o->exact_point, q);
+    double EL = norm(sub(q, TX)) + norm(sub(R, q));
+    o->exact_length_m = EL;
+    o->exact_delay_s = EL / C0;
+    st3(o->exact_aod, normalize(sub(q, TX)));
+    st3(o->exact_aoa, normalize(sub(q, R)));
+    if (!ok) o->flags |= 2u;
+}
+
+int orc_diffract(const double* tri_v, const int32_t* face_id, int64_t T, const double tx[3],
+                 const double* rx, int32_t n_rx, const orc_params* P, orc_candidate** cand_out,
+                 int64_t* n_cand_out, orc_candidate** uniq_out, int64_t* n_uniq_out,
+                 orc_dpath** paths_out, int64_t* n_paths_out)
+{
+    if (!P || P->division_n < 1 || P->iterations < 0 || (P->subrays != 6 && P->subrays != 7) ||
+        n_rx < 0 || T < 0 || P->launch < 0 || P->launch > ORC_LAUNCH_EQUIDISTANT_OCTA)
+        return -1;
+    scene_t S;
+    if (scene_init(&S, tri_v, face_id, NULL, T)) { scene_free(&S); return -1; }
+    wedge_t* W;
+    int64_t nw = wedges_build(&S, tri_v, &W);
+    const int32_t n = P->division_n;
+    const int64_t N = orc_num_rays_m(P->launch, n);
+    const double thl = theta_launch_m(P->launch, n);
+    const v3 TX = ld3(tx);
+    grid_t G;
+    grid_init_m(&G, P->launch, n);
+#ifdef _OPENMP
+    if (P->n_threads > 0) omp_set_num_threads(P->n_threads);
+    int nth = omp_get_max_threads();
+#else
+    int nth = 1;
+#endif
+    /* the receivers' images unfolded about each wedge (receivers inside a
+     * wedge, or on its edge line, receive nothing from it) */
+    v3* rxp = (v3*)malloc(sizeof(v3) * (size_t)(nw * n_rx > 0 ? nw * n_rx : 1));
+    char* rxok = (char*)calloc((size_t)(nw * n_rx > 0 ? nw * n_rx : 1), 1);
+    for (int64_t w = 0; w < nw; ++w)
+        for (int32_t x = 0; x < n_rx; ++x) {
+            double at, ax, rt, rr;
+            v3 R = ld3(rx + 3 * x);
+            rxok[w * n_rx + x] = !wedge_interior(&W[w], R) &&
+                                 unfold_rx(&W[w], TX, R, &rxp[w * n_rx + x], &at, &ax, &rt, &rr);
+        }
+    /* 1. launch; every ray that passes a wedge, reaches it and whose cone
+     * the edge crosses diffracts there toward every receiver its cone
+     * captures */
+    cvec* tv = (cvec*)calloc((size_t)nth, sizeof(cvec));
+#pragma omp parallel
+    {
+#ifdef _OPENMP
+        int me = omp_get_thread_num();
+#else
+        int me = 0;
+#endif
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t r = 0; r < N; ++r) {
+            v3 d = grid_dir(&G, r);
+            double th;
+            int64_t hit = closest_hit(&S, TX, d, -1, &th);
+            int32_t fh = hit < 0 ? -1 : S.face[hit];
+            orc_candidate c;
+            memset(&c, 0, sizeof(c));
+            c.ray = r;
+            c.order = 1;
+            for (int q = 1; q < ORC_MAX_ORDER; ++q) c.face[q] = -1;
+            for (int64_t w = 0; w < nw; ++w) {
+                double t, s;
+                if (!ray_reaches_edge(&W[w], TX, d, th, fh, &t, &s)) continue;
+                v3 p = add(TX, scl(t, d));
+                v3 q = add(W[w].a, scl(s, W[w].e));
+                if (!(norm(sub(p, q)) <= thl * t)) continue;
+                for (int32_t x = 0; x < n_rx; ++x) {
+                    double tn;
+                    if (!rxok[w * n_rx + x]) continue;
+                    if (!capture_diff(TX, d, rxp[w * n_rx + x], thl, &tn)) continue;
+                    c.rx = x;
+                    c.face[0] = (int32_t)w;
+                    c.tan_err = tn;
+                    cpush(&tv[me], &c);
+                }
+            }
+        }
+    }
+    int64_t nc = 0;
+    for (int t = 0; t < nth; ++t) nc += tv[t].n;
+    orc_candidate* cand = (orc_candidate*)malloc(sizeof(orc_candidate) * (size_t)(nc > 0 ? nc : 1));
+    nc = 0;
+    for (int t = 0; t < nth; ++t) {
+        if (tv[t].n) memcpy(cand + nc, tv[t].a, sizeof(orc_candidate) * (size_t)tv[t].n);
+        nc += tv[t].n;
+        free(tv[t].a);
+    }
+    free(tv);
+    qsort(cand, (size_t)nc, sizeof(orc_candidate), ray_order_cmp);
+    /* 2. path test 1: one path per (rx, wedge), the smallest error angle */
+    orc_candidate* srt;
+    int64_t nu;
+    orc_path_test1(cand, nc, &srt, &nu);
+    /* 3. precise algorithm, 4. path quantities and path test 2 */
+    double tan_tgt = 0.0;
+    if (P->target_err_deg > 0.0) tan_tgt = tan_cr((P->target_err_deg * PI_D) / 180.0);
+    orc_dpath* out = (orc_dpath*)calloc((size_t)(nu > 0 ? nu : 1), sizeof(orc_dpath));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < nu; ++i)
+        diff_record(&S, &W[srt[i].face[0]], TX, &G, rx, &srt[i], P, tan_tgt, thl, &out[i]);
+    int64_t np = 0;
+    for (int64_t i = 0; i < nu; ++i)
+        if (!(out[i].flags & 2u) || P->keep_invalid) out[np++] = out[i];
+    free(rxp);
+    free(rxok);
+    free(W);
+    grid_free(&G);
+    scene_free(&S);
+    if (cand_out) *cand_out = cand; else free(cand);
+    if (n_cand_out) *n_cand_out = nc;
+    if (uniq_out) *uniq_out = srt; else free(srt);
+    if (n_uniq_out) *n_uniq_out = nu;
+    if (paths_out) *paths_out = out; else free(out);
+    if (n_paths_out) *n_paths_out = np;
+    return 0;
+}
+
+int orc_diffract_history(const double* tri_v, const int32_t* face_id, int64_t T,
+                         const double tx[3], const orc_params* P, const double* rx,
+                         const int32_t* wedge, const double* axis0, int64_t m, double* hist)
+{
+    if (!P || P->division_n < 1 || (P->subrays != 6 && P->subrays != 7) || P->iterations < 0)
+        return -1;
+    scene_t S;
+    if (scene_init(&S, tri_v, face_id, NULL, T)) { scene_free(&S); return -1; }
+    wedge_t* W;
+    int64_t nw = wedges_build(&S, tri_v, &W);
+    const double thl = theta_launch_m(P->launch, P->division_n);
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
+    for (int64_t i = 0; i < m; ++i) {
+        double* h = hist + i * (P->iterations + 1);
+        for (int32_t q = 0; q <= P->iterations; ++q) h[q] = NAN;
+        if (wedge[i] < 0 || wedge[i] >= nw) { bad = 1; continue; }
+        drefine_t rf;
+        refine_diff(&S, &W[wedge[i]], ld3(tx), ld3(rx + 3 * i), ld3(axis0 + 3 * i),
+                    P->iterations, P->subrays, 0.0, thl, &rf, h);
+    }
+    free(W);
+    scene_free(&S);
+    return bad ? -1 : 0;
 }

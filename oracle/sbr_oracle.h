@@ -136,6 +136,36 @@ int orc_exact_path(const double* tri_v, const int32_t* face_id, const int32_t* m
                    double* points /* [order][3] */, double* length_m,
                    double* power_dbm, int32_t* valid);
 
+/* ---- Order-1 diffraction (Sec. III.A wedges, Sec. III.B, Sec. IV) ---- */
+/* Wedges: out [cap][17] = a[3], b[3], e[3], u0[3], u1[3], f0, f1 (as doubles);
+ * returns the number of wedges (all of them even when cap is smaller). */
+int64_t orc_wedges(const double* tri_v, const int32_t* face_id, int64_t n_tri, double* out,
+                   int64_t cap);
+
+/* One order-1 diffraction path: Tx -> point on the edge of `wedge` -> Rx. */
+typedef struct {
+    int32_t rx, wedge;
+    int64_t launch_ray;
+    int32_t iters_used;
+    uint32_t flags;            /* 1 STALLED, 2 INVALID, 4 TARGET_MET          */
+    double tan_err, axis[3], point[3], delay_s, aod[3], aoa[3], err_angle_deg, length_m;
+    double exact_point[3], exact_delay_s, exact_aod[3], exact_aoa[3], exact_length_m;
+    double init_tan_err;
+} orc_dpath;
+
+/* The whole method for order-1 diffraction paths.  Events and winners use
+ * orc_candidate with order 1 and face[0] = wedge index. */
+int orc_diffract(const double* tri_v, const int32_t* face_id, int64_t n_tri, const double tx[3],
+                 const double* rx, int32_t n_rx, const orc_params* prm,
+                 orc_candidate** cand, int64_t* n_cand, orc_candidate** uniq, int64_t* n_uniq,
+                 orc_dpath** paths, int64_t* n_paths);
+
+/* Precise algorithm of diffraction rows (rx[m][3], wedge[m], start axis);
+ * tan(theta_error) after every iteration in hist[m][iterations + 1]. */
+int orc_diffract_history(const double* tri_v, const int32_t* face_id, int64_t n_tri,
+                         const double tx[3], const orc_params* prm, const double* rx,
+                         const int32_t* wedge, const double* axis0, int64_t m, double* hist);
+
 /* Fresnel average power reflectance 0.5(|G_perp|^2+|G_par|^2) for cos(theta_i). */
 double orc_fresnel_avg(double cos_i, double eps_re, double eps_im);
 

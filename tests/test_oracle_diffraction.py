@@ -1,0 +1,335 @@
+"""Pins of the oracle's order-1 diffraction (Sec. III.A: paths through faces
+or wedges; Sec. III.B: sub-rays diffracted in the recorded direction;
+Sec. IV: order-1 diffraction paths and their AOD/AOA error decay) against
+results fixed independently of it: wedge counts of closed boxes and hand-made
+edges, the exact diffraction point as the shortest path via the edge line
+(Fermat's principle, found here by a root search of the path length's
+derivative; equivalently Keller's law of equal angles with the edge), the
+cone capture set in free space, the eq. (6) bound and the paper's "two
+orders of magnitude in 10 iterations"."""
+import math
+
+import numpy as np
+import pytest
+from scipy.optimize import brentq
+
+from paper_2208_10009_amd import scenes
+
+
+def box_scene(*boxes):
+    b = scenes.SceneBuilder()
+    for lo, hi in boxes:
+        b.box(lo, hi, 0)
+    return b.scene([5.3 - 0.4j])
+
+
+def angle_deg(a, b):
+    a = np.asarray(a, float)
+    b = np.asarray(b, float)
+    return np.degrees(np.arctan2(np.linalg.norm(np.cross(a, b), axis=-1), np.sum(a * b, axis=-1)))
+
+
+def fermat_point(a, b, tx, rx):
+    """The point Q = a + s e (e = unit(b - a)) of the edge line minimizing
+    |Tx - Q| + |Q - Rx|: the root of the length's derivative in s (Keller's
+    law: equal angles with the edge on both sides)."""
+    L = np.linalg.norm(b - a)
+    e = (b - a) / L
+
+    def dlen(s):
+        q = a + s * e
+        return (q - tx) @ e / np.linalg.norm(q - tx) + (q - rx) @ e / np.linalg.norm(q - rx)
+
+    lo, hi = -10 * L - 1e3, 10 * L + 1e3
+    s = brentq(dlen, lo, hi, xtol=1e-14, rtol=1e-15, maxiter=500)
+    return a + s * e, s, L
+
+
+# ----------------------------------------------------------------- wedges --
+def test_box_has_twelve_right_angle_wedges(orc):
+    W = orc.wedges(box_scene(((0, 0, 0), (10, 8, 20))))
+    assert len(W["a"]) == 12
+    edges = np.abs(W["b"] - W["a"])
+    # four edges along each axis, with the box's side lengths
+    for ax, L in enumerate((10, 8, 20)):
+        along = edges[:, ax] > 0
+        assert along.sum() == 4 and np.allclose(edges[along, ax], L)
+    # u0, u1: unit, normal to the edge, each pointing from the edge into its
+    # face (toward the box's interior), at right angles to each other
+    for k in range(12):
+        e, u0, u1 = W["e"][k], W["u0"][k], W["u1"][k]
+        assert abs(np.linalg.norm(u0) - 1) < 1e-15 and abs(e @ u0) < 1e-15
+        assert abs(np.linalg.norm(u1) - 1) < 1e-15 and abs(e @ u1) < 1e-15
+        assert abs(u0 @ u1) < 1e-15
+        mid = 0.5 * (W["a"][k] + W["b"][k])
+        centre = np.array([5.0, 4.0, 10.0])
+        assert (centre - mid) @ u0 > 0 and (centre - mid) @ u1 > 0
+    # wedges listed by (a, b) lexicographically
+    keys = [tuple(W["a"][k]) + tuple(W["b"][k]) for k in range(12)]
+    assert keys == sorted(keys)
+
+
+def test_manhattan_wedges_are_the_building_edges(orc):
+    sc = scenes.manhattan(0)
+    W = orc.wedges(sc)
+    assert len(W["a"]) == 64 * 12      # the ground shares no edge with a building
+
+
+def _hinge(angle_deg_between_normals):
+    """Two unit squares sharing the edge x = 0 (along y), the second turned
+    about it: faces 0 and 1."""
+    t = math.radians(angle_deg_between_normals)
+    b = scenes.SceneBuilder()
+    b.quad((0, 0, 0), (0, 1, 0), (-1, 1, 0), (-1, 0, 0), 0)
+    c, s = math.cos(t), math.sin(t)
+    b.quad((0, 0, 0), (c, 0, s), (c, 1, s), (0, 1, 0), 0)
+    return b.scene([4 + 0j])
+
+
+def test_wedge_needs_ten_degrees_and_two_faces(orc):
+    assert len(orc.wedges(_hinge(5.0))["a"]) == 0
+    assert len(orc.wedges(_hinge(9.99))["a"]) == 0
+    assert len(orc.wedges(_hinge(10.01))["a"]) == 1
+    assert len(orc.wedges(_hinge(60.0))["a"]) == 1
+    # the diagonal of a quad (one face) is no wedge
+    b = scenes.SceneBuilder()
+    b.quad((0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0), 0)
+    assert len(orc.wedges(b.scene([4 + 0j]))["a"]) == 0
+    # three faces on one edge: no wedge
+    b = scenes.SceneBuilder()
+    for t in (0.0, 2.0, 4.0):
+        c, s = math.cos(t), math.sin(t)
+        b.quad((0, 0, 0), (c, 0, s), (c, 1, s), (0, 1, 0), 0)
+    assert len(orc.wedges(b.scene([4 + 0j]))["a"]) == 0
+
+
+# ----------------------------------------------------------- exact paths --
+def _around_box_cases(rng, m):
+    """Tx and Rx on either side of the vertical edge x = y = 0 of the box
+    [0, 10] x [0, 10] x [0, 20], both outside it, seeing each other only
+    around the edge."""
+    out = []
+    while len(out) < m:
+        tx = np.array([rng.uniform(-30, -2), rng.uniform(2, 15), rng.uniform(2, 18)])
+        rx = np.array([rng.uniform(2, 30), rng.uniform(-30, -2), rng.uniform(2, 18)])
+        out.append((tx, rx))
+    return out
+
+
+def test_exact_point_is_the_shortest_path_via_the_edge(orc):
+    sc = box_scene(((0, 0, 0), (10, 10, 20)))
+    rng = np.random.default_rng(4)
+    for tx, rx in _around_box_cases(rng, 12):
+        r = orc.diffract(sc, tx, rx[None], division_n=30, iterations=0, subrays=6,
+                         keep_invalid=True)
+        p = r["paths"]
+        assert len(p) >= 1
+        for q in p:
+            W = orc.wedges(sc)
+            k = q["wedge"]
+            Q, s, L = fermat_point(W["a"][k], W["b"][k], tx, rx)
+            if 0 <= s <= L:
+                assert np.abs(q["exact_point"] - Q).max() < 1e-11
+                Le = np.linalg.norm(Q - tx) + np.linalg.norm(rx - Q)
+                assert abs(q["exact_length_m"] - Le) < 1e-12 * Le
+                assert angle_deg(q["exact_aod"], Q - tx) < 1e-10
+                assert angle_deg(q["exact_aoa"], Q - rx) < 1e-10
+                # Keller's law: equal angles with the edge
+                e = W["e"][k]
+                assert abs(angle_deg(Q - tx, e) - angle_deg(rx - Q, e)) < 1e-9
+        # the path around the edge x = y = 0 exists and is valid
+        k0 = next(k for k in range(12) if np.allclose(orc.wedges(sc)["a"][k][:2], 0)
+                  and np.allclose(orc.wedges(sc)["b"][k][:2], 0))
+        assert any(q["wedge"] == k0 and not q["flags"] & 2 for q in p)
+
+
+def test_error_angle_is_the_departure_angle_error(orc):
+    """The diffraction reading of eq. (3): the error angle of every event and
+    of every refined path is the angle between its ray and the exact path's
+    departure direction."""
+    sc = box_scene(((0, 0, 0), (10, 10, 20)))
+    rng = np.random.default_rng(9)
+    n = 40
+    d = orc.launch_dirs(n)
+    W = orc.wedges(sc)
+    checked = 0
+    for tx, rx in _around_box_cases(rng, 24):
+        r = orc.diffract(sc, tx, rx[None], division_n=n, iterations=4, subrays=6,
+                         keep_invalid=True)
+        for c in r["candidates"]:
+            k = c["face"][0]
+            Q, _, _ = fermat_point(W["a"][k], W["b"][k], tx, rx)
+            ang = angle_deg(d[c["ray"]], Q - tx)
+            assert abs(math.degrees(math.atan(c["tan_err"])) - ang) < 1e-9
+            checked += 1
+        for q in r["paths"]:
+            Q, _, _ = fermat_point(W["a"][q["wedge"]], W["b"][q["wedge"]], tx, rx)
+            assert abs(q["err_angle_deg"] - angle_deg(q["aod"], Q - tx)) < 1e-9
+    assert checked > 20
+
+
+@pytest.mark.parametrize("tx,rx,grazing", [
+    ((-12.0, 6.0, 9.0), (14.0, -9.0, 11.0), False),
+    # nearly along the edge: a ray can point within the cone of Rx's image
+    # while the edge stays outside its cone at the closest approach
+    ((-1.14, 1.87, -38.9), (2.43, -0.68, 57.0), True),
+])
+def test_free_space_capture_set(orc, tx, rx, grazing):
+    """Which launch rays diffract toward Rx at the box's edge: those whose
+    closest approach to the edge line lies on the segment, at t > 0, within
+    the ray cone (distance <= theta_launch t), and whose angle to the exact
+    departure direction has tangent <= theta_launch; Tx and Rx see the edge
+    directly, so every such ray reaches it (rays clipping the box meet one of
+    the wedge's own faces)."""
+    sc = box_scene(((0, 0, 0), (10, 10, 20)))
+    W = orc.wedges(sc)
+    n = 24
+    d = orc.launch_dirs(n)
+    thl = math.atan(2.0) / (math.sqrt(3.0) * n)
+    tx, rx = np.array(tx), np.array(rx)
+    r = orc.diffract(sc, tx, rx[None], division_n=n, iterations=0, subrays=6, keep_invalid=True)
+    k0 = next(k for k in range(len(W["a"])) if np.allclose(W["a"][k][:2], 0)
+              and np.allclose(W["b"][k][:2], 0))
+    a, e = W["a"][k0], W["e"][k0]
+    L = np.linalg.norm(W["b"][k0] - a)
+    Q, _, _ = fermat_point(a, W["b"][k0], tx, rx)
+    w0 = tx - a
+    b_ = d @ e
+    den = np.maximum(1 - b_ ** 2, 1e-300)
+    t = (b_ * (e @ w0) - d @ w0) / den
+    s = ((e @ w0) - b_ * (d @ w0)) / den
+    dist = np.linalg.norm(tx + t[:, None] * d - (a + s[:, None] * e), axis=1)
+    tan = np.tan(np.radians(angle_deg(d, Q - tx)))
+    margin = 1e-9
+    inside = (t > 0) & (s >= 0) & (s <= L) & (dist <= thl * t * (1 - margin)) & \
+        (tan <= thl * (1 - margin))
+    border = (np.abs(dist - thl * t) <= thl * t * margin) | (np.abs(tan - thl) <= thl * margin)
+    got = set(int(x) for x in r["candidates"]["ray"][r["candidates"]["face"][:, 0] == k0])
+    want = set(np.nonzero(inside)[0].tolist())
+    assert (want or grazing) and want <= got
+    assert got <= want | set(np.nonzero(border)[0].tolist())
+    if grazing:
+        # rays that pass every other condition but not the edge-in-cone one
+        only = (t > 0) & (s >= 0) & (s <= L) & (tan <= thl) & (dist > thl * t * (1 + margin))
+        assert only.any() and not (set(np.nonzero(only)[0].tolist()) & got)
+
+
+# ------------------------------------------------------------ validity --
+def test_path_test_2_for_diffraction(orc):
+    sc = box_scene(((0, 0, 0), (10, 10, 20)))
+    W = orc.wedges(sc)
+    k0 = next(k for k in range(12) if np.allclose(W["a"][k][:2], 0) and np.allclose(W["b"][k][:2], 0))
+    kw = dict(division_n=60, iterations=3, subrays=6, keep_invalid=True)
+    # Q beyond the top of the edge (both ends high above the roof): invalid
+    tx, rx = np.array([-12.0, 6.0, 40.0]), np.array([14.0, -9.0, 45.0])
+    Q, s, L = fermat_point(W["a"][k0], W["b"][k0], tx, rx)
+    assert s > L + 5
+    r = orc.diffract(sc, tx, rx[None], **kw)
+    # the rays toward Q pass the edge line beyond the segment: no event
+    assert not (r["candidates"]["face"][:, 0] == k0).any()
+    # a receiver inside the box receives nothing
+    r = orc.diffract(sc, tx, np.array([[5.0, 5.0, 5.0]]), **kw)
+    assert len(r["candidates"]) == 0
+    # a second box between the edge and Rx blocks the path
+    tx, rx = np.array([-12.0, 6.0, 9.0]), np.array([14.0, -9.0, 11.0])
+    p = orc.diffract(sc, tx, rx[None], **kw)["paths"]
+    assert any(q["wedge"] == k0 and not q["flags"] & 2 for q in p)
+    sc2 = box_scene(((0, 0, 0), (10, 10, 20)), ((6, -5, 0), (8, -3, 30)))
+    p2 = orc.diffract(sc2, tx, rx[None], **kw)["paths"]
+    W2 = orc.wedges(sc2)
+    k2 = next(k for k in range(len(W2["a"])) if np.allclose(W2["a"][k][:2], 0)
+              and np.allclose(W2["b"][k][:2], 0))
+    assert all(q["flags"] & 2 for q in p2 if q["wedge"] == k2)
+    # a 2 cm plate on the exact segment Tx -> Q: launch rays pass beside it
+    # and find the path, the exact path is blocked
+    Q, _, _ = fermat_point(W["a"][k0], W["b"][k0], tx, rx)
+    mid = 0.5 * (tx + Q)
+    u = np.cross(Q - tx, [0.0, 0.0, 1.0])
+    u /= np.linalg.norm(u)
+    v = np.cross(u, (Q - tx) / np.linalg.norm(Q - tx))
+    b3 = scenes.SceneBuilder()
+    b3.box((0, 0, 0), (10, 10, 20), 0)
+    c = [mid + 0.01 * (x * u + y * v) for x, y in ((-1, -1), (1, -1), (1, 1), (-1, 1))]
+    b3.quad(*c, 0)
+    sc3 = b3.scene([5.3 - 0.4j])
+    p3 = orc.diffract(sc3, tx, rx[None], **kw)["paths"]
+    W3 = orc.wedges(sc3)
+    k3 = next(k for k in range(len(W3["a"])) if np.allclose(W3["a"][k][:2], 0)
+              and np.allclose(W3["b"][k][:2], 0))
+    mine = [q for q in p3 if q["wedge"] == k3]
+    assert mine and all(q["flags"] & 2 for q in mine)
+    # without keep_invalid the invalid paths are dropped
+    kw2 = dict(kw, keep_invalid=False)
+    assert all(not q["flags"] & 2 for q in orc.diffract(sc2, tx, rx[None], **kw2)["paths"])
+
+
+def test_one_path_per_receiver_and_wedge(orc):
+    sc = scenes.manhattan(0)
+    cfg = scenes.manhattan_config(0, n_rx=6)
+    r = orc.diffract(sc, cfg["tx"], cfg["rx"], division_n=30, iterations=0, subrays=6,
+                     keep_invalid=True)
+    u = r["unique"]
+    keys = list(zip(u["rx"].tolist(), u["face"][:, 0].tolist()))
+    assert len(keys) == len(set(keys)) and len(keys) > 0
+    for x, w in keys:
+        ev = r["candidates"][(r["candidates"]["rx"] == x) & (r["candidates"]["face"][:, 0] == w)]
+        win = u[(u["rx"] == x) & (u["face"][:, 0] == w)][0]
+        assert win["tan_err"] == ev["tan_err"].min()
+        assert win["ray"] == ev["ray"][ev["tan_err"] == ev["tan_err"].min()].min()
+
+
+# ---------------------------------------------------- precise algorithm --
+@pytest.mark.parametrize("S", [6, 7])
+def test_diffraction_error_bound_per_iteration(orc, S):
+    """eq. (6) for diffraction paths: the error angle after iteration i is at
+    most theta_launch / 3^(i/2); the paper's outdoor scene reports two orders
+    of magnitude less AOA error after 10 iterations (Sec. IV, 2.2531 to
+    0.0080 deg) and about 20 dB of AOD error (Fig. 8b)."""
+    sc = box_scene(((0, 0, 0), (10, 10, 20)))
+    rng = np.random.default_rng(5)
+    n = 30
+    rows, wids, axes = [], [], []
+    tx0 = None
+    for tx, rx in _around_box_cases(rng, 10):
+        if tx0 is None:
+            tx0 = tx
+        tx = tx0
+        r = orc.diffract(sc, tx, rx[None], division_n=n, iterations=0, subrays=S)
+        for u in r["unique"]:
+            rows.append(rx)
+            wids.append(u["face"][0])
+            axes.append(orc.launch_dirs(n, [u["ray"]])[0])
+    assert len(rows) >= 8
+    h = orc.diffract_history(sc, tx0, np.array(rows), np.array(wids), np.array(axes),
+                             division_n=n, iterations=30, subrays=S)
+    err = np.degrees(np.arctan(h))
+    thl = math.degrees(math.atan(2.0) / (math.sqrt(3.0) * n))
+    bound = thl / 3 ** (np.arange(31) / 2)
+    assert (err <= bound[None, :] * (1 + 1e-9)).all()
+    drop = 10 * np.log10(err[:, 0].mean() / err[:, 10].mean())
+    assert 20.0 < drop < 32.0
+    # mean AOA error over the paths after 10 iterations: more than two orders
+    # of magnitude below the launch rays'
+    rx_all = np.array(rows)
+    p0 = orc.diffract(sc, tx0, rx_all, division_n=n, iterations=0, subrays=S)["paths"]
+    p10 = orc.diffract(sc, tx0, rx_all, division_n=n, iterations=10, subrays=S)["paths"]
+    assert len(p0) == len(p10) >= 8
+    e0 = angle_deg(p0["aoa"], p0["exact_aoa"]).mean()
+    e10 = angle_deg(p10["aoa"], p10["exact_aoa"]).mean()
+    assert e10 < e0 / 100
+
+
+def test_refined_diffraction_point_converges(orc):
+    """With a 1e-7 degree target the refined diffraction point, delay and
+    angles meet the exact path's."""
+    sc = box_scene(((0, 0, 0), (10, 10, 20)))
+    tx, rx = np.array([-12.0, 6.0, 9.0]), np.array([14.0, -9.0, 11.0])
+    p = orc.diffract(sc, tx, rx[None], division_n=24, iterations=60, subrays=6,
+                     target_err_deg=1e-7)["paths"]
+    assert len(p) >= 1
+    for q in p:
+        assert q["flags"] & 4
+        assert np.abs(q["point"] - q["exact_point"]).max() < 1e-5
+        assert angle_deg(q["aod"], q["exact_aod"]) <= 1e-7
+        assert angle_deg(q["aoa"], q["exact_aoa"]) <= 1e-6
+        assert 0 <= q["length_m"] - q["exact_length_m"] < 1e-12 * q["exact_length_m"] + 1e-12
