@@ -334,6 +334,61 @@ sbr_status sbr_path_gradients(sbr_scene* scene, int64_t n_paths, const double* t
                               const double* upstream, double* values, double* grad_tx,
                               double* grad_rx, double* grad_eps);
 
+/* ---- Order-1 diffraction (Sec. III.A: paths through faces or wedges;
+ * Sec. III.B: sub-rays diffracted in the recorded direction; Sec. IV:
+ * order-1 diffraction paths) ---- */
+
+/* A wedge: a mesh edge (endpoints with exactly equal coordinates) shared by
+ * triangles of exactly two faces whose planes meet at an angle of at least
+ * 10 degrees.  a < b lexicographically (x, then y, then z); face[0] < face[1].
+ * Wedges are numbered in the order of (a, b). */
+typedef struct {
+    double a[3], b[3];
+    int32_t face[2];
+} sbr_wedge;
+
+/* The wedges of a scene (made from its triangles on first use).  out may be
+ * NULL with capacity 0 to query the count.  Errors: SBR_E_CAPACITY. */
+sbr_status sbr_scene_wedges(sbr_scene* scene, sbr_wedge* out, int64_t capacity, int64_t* n_out);
+
+/* One order-1 diffraction path Tx -> point on a wedge's edge -> Rx.  The
+ * refined fields come from the precise algorithm's final ray (point = the edge
+ * point nearest that ray), the exact_ fields from the path that makes equal
+ * angles with the edge on both sides (Keller's law), which also decides path
+ * test 2 (the point on the edge segment, Tx and Rx outside the wedge, both
+ * legs unobstructed).  Angles as in sbr_path.  No power: the paper gives no
+ * diffraction coefficient. */
+typedef struct {
+    int32_t rx, wedge;
+    int64_t launch_ray;
+    int32_t iters_used;          /* as sbr_path.iters_used                          */
+    uint32_t flags;              /* SBR_PATH_*                                      */
+    double tan_err, axis[3], point[3], delay_s, aod[3], aoa[3], err_angle_deg, length_m;
+    double exact_point[3], exact_delay_s, exact_aod[3], exact_aoa[3], exact_length_m;
+    double init_tan_err;
+} sbr_diff_path;
+
+/* Order-1 diffraction paths from tx to rx [n_rx][3] (host FP64): every
+ * launch ray whose closest approach to a wedge's edge lies on the segment, in
+ * front of Tx, inside the ray cone and before the ray's first hit (or on one
+ * of the wedge's faces) diffracts there; it reaches each receiver outside the
+ * wedge whose image, the receiver rotated about the edge into the half-plane
+ * opposite Tx, lies inside the ray cone; the error angle is the angle to that
+ * image (the departure-angle error, eq. (3) unfolded).  Path test 1 keeps one
+ * path per (receiver, wedge); the precise algorithm (params->iterations,
+ * subrays, target_err_deg) refines each; path test 2 drops invalid ones
+ * (unless SBR_FLAG_KEEP_INVALID).  max_order, freq_hz and tx_power_dbm are
+ * checked but not used.  Output sorted by (rx, wedge).  Errors as sbr_trace. */
+sbr_status sbr_diffract(sbr_scene* scene, const double tx[3], const double* rx, int32_t n_rx,
+                        const sbr_trace_params* params, sbr_diff_path* out, int64_t capacity,
+                        int64_t* n_out, sbr_trace_stats* stats);
+
+/* The diffraction events before path test 1 (order 1, face[0] = wedge),
+ * sorted by (rx, wedge, tan_err, ray). */
+sbr_status sbr_diff_candidates(sbr_scene* scene, const double tx[3], const double* rx,
+                               int32_t n_rx, const sbr_trace_params* params, sbr_candidate* out,
+                               int64_t capacity, int64_t* n_out);
+
 /* Work counts of the trace stage of sbr_trace with the same arguments, from
  * an instrumented copy of the trace kernel: counts[0] segments traced
  * (ray-bounces), counts[1] BVH4 nodes visited (128 B each), counts[2]

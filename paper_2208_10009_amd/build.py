@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libsbr.so")
 SOURCES = ["api.hip", "launch.hip", "trace.hip", "paths.hip", "refine.hip", "grad.hip",
-           "bvh_build.cpp"]
+           "diffract.hip", "bvh_build.cpp"]
 ARCH = "gfx950"
 
 

@@ -13,6 +13,7 @@
 #include <string>
 #include <vector>
 
+#include "diffract.h"
 #include "geom.h"
 #include "internal.h"
 
@@ -123,7 +124,8 @@ struct sbr_context {
     hipError_t scratch_err = hipSuccess;
     int64_t noalloc_unique = -1;  // path count of the last no-allocation call
     DevBuf grid_scratch, rx, rx32, cand, idx, flags, offs, scan, uniq, refine, paths, keep, outp,
-        counters, rays_tri, rays_t, tally, geom, d_jobs, d_scenes, d_rxjob, d_rxnodes, d_rxperm;
+        counters, rays_tri, rays_t, tally, geom, d_jobs, d_scenes, d_rxjob, d_rxnodes, d_rxperm,
+        d_rxp, dpaths, dout;
     Counters* host_ctr = nullptr;  // pinned
     sbr_path* host_paths = nullptr;  // pinned staging of the path list
     int64_t host_paths_cap = 0;
@@ -186,6 +188,11 @@ struct sbr_scene {
     int32_t bvh_depth = 0;
     int64_t n_nodes = 0;
     DevBuf nodes, tris, d_fplane, d_fmat, fstart, ftris, d_eps;
+    // wedges for order-1 diffraction, made on first use
+    bool has_wedges = false;
+    std::vector<WedgeDev> wedges;
+    std::vector<double> wedge_b;  // [n][3] second endpoints
+    DevBuf d_wedges;
 };
 
 namespace {
@@ -1082,7 +1089,7 @@ sbr_status sbr_context_destroy(sbr_context* c)
                       &c->offs,         &c->scan,  &c->uniq,  &c->refine, &c->paths,
                       &c->keep,         &c->outp,  &c->counters, &c->rays_tri, &c->rays_t, &c->tally,
                       &c->geom,         &c->d_jobs, &c->d_scenes, &c->d_rxjob,
-                      &c->d_rxnodes,    &c->d_rxperm};
+                      &c->d_rxnodes,    &c->d_rxperm, &c->d_rxp, &c->dpaths, &c->dout};
     for (DevBuf* b : bufs) release(*b);
     for (auto& ev : c->ev)
         if (ev) (void)hipEventDestroy(ev);
@@ -1252,7 +1259,8 @@ sbr_status sbr_scene_destroy(sbr_scene* s)
     if (!s || !s->ctx) return SBR_E_NO_SCENE;
     (void)use_device(s->ctx->device);
     (void)hipStreamSynchronize(s->ctx->stream);
-    DevBuf* bufs[] = {&s->nodes, &s->tris, &s->d_fplane, &s->d_fmat, &s->fstart, &s->ftris, &s->d_eps};
+    DevBuf* bufs[] = {&s->nodes, &s->tris,  &s->d_fplane, &s->d_fmat,
+                      &s->fstart, &s->ftris, &s->d_eps,    &s->d_wedges};
     for (DevBuf* b : bufs) release(*b);
     s->ctx->n_scenes -= 1;
     s->ctx = nullptr;
@@ -1848,6 +1856,255 @@ sbr_status sbr_trace_device_noalloc(sbr_scene* s, const double tx[3], const doub
     }
     if (hc->n_paths > capacity)
         return fail(c, SBR_E_CAPACITY, "%d paths, capacity %lld", hc->n_paths, (long long)capacity);
+    return SBR_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Order-1 diffraction
+// ---------------------------------------------------------------------------
+namespace {
+
+sbr_status ensure_wedges(sbr_scene* s)
+{
+    sbr_context* c = s->ctx;
+    if (s->has_wedges) return SBR_OK;
+    build_wedges(s->tri_v.data(), s->face.data(), s->T, s->fplane.data(), s->wedges, s->wedge_b);
+    if (!s->wedges.empty()) {
+        HIPCHK(c, ensure(s->d_wedges, sizeof(WedgeDev) * s->wedges.size()));
+        HIPCHK(c, hipMemcpy(s->d_wedges.p, s->wedges.data(), sizeof(WedgeDev) * s->wedges.size(),
+                            hipMemcpyHostToDevice));
+    }
+    s->has_wedges = true;
+    return SBR_OK;
+}
+
+// Launch grid, unfolded receivers and the SBR diffraction of every launch
+// ray: the events are left in c->cand (count in *n_cand), A describes the
+// call for the later stages.
+sbr_status diff_front(sbr_scene* s, const double* tx, const double* rx, int32_t n_rx,
+                      const sbr_trace_params* p, DiffArgs* A, int64_t* n_cand, float* ms_launch,
+                      float* ms_trace)
+{
+    sbr_context* c = s->ctx;
+    const hipStream_t st = c->stream;
+    sbr_status r = ensure_wedges(s);
+    if (r) return r;
+    HIPCHK(c, hipEventRecord(c->ev[0], st));
+    GridDev g;
+    bool built = false;
+    r = get_grid(c, p->launch, p->division_n, &g, &built, (p->flags & SBR_FLAG_FRESH_GRID) != 0);
+    if (r) return r;
+    HIPCHK(c, hipEventRecord(c->ev[1], st));
+    const int32_t n_w = (int32_t)s->wedges.size();
+    HIPCHK(c, ensure(c->rx, sizeof(double) * 3 * (size_t)std::max(n_rx, 1)));
+    HIPCHK(c, ensure(c->d_rxp, sizeof(double4) * (size_t)std::max<int64_t>((int64_t)n_w * n_rx, 1)));
+    HIPCHK(c, ensure(c->counters, sizeof(Counters)));
+    if (n_rx > 0)
+        HIPCHK(c, hipMemcpyAsync(c->rx.p, rx, sizeof(double) * 3 * (size_t)n_rx,
+                                 hipMemcpyHostToDevice, st));
+    *A = DiffArgs{};
+    A->dir = g.dir;
+    A->N = g.N;
+    for (int i = 0; i < 3; ++i) A->tx[i] = tx[i];
+    A->thl = theta_launch(p->launch, p->division_n);
+    A->tan_tgt = p->target_err_deg > 0.0 ? tan_cr((p->target_err_deg * kPi) / 180.0) : 0.0;
+    A->delta = traversal_delta(s, tx);
+    A->iterations = p->iterations;
+    A->subrays = p->subrays;
+    A->keep_invalid = (p->flags & SBR_FLAG_KEEP_INVALID) ? 1 : 0;
+    A->w = s->d_wedges.as<const WedgeDev>();
+    A->n_w = n_w;
+    A->rx = c->rx.as<const double>();
+    A->n_rx = n_rx;
+    A->rxp = c->d_rxp.as<double4>();
+    HIPCHK(c, launch_diff_unfold(*A, st));
+    Counters* hc = c->host_ctr;
+    Counters* dc = c->counters.as<Counters>();
+    int64_t cap = std::max<int64_t>(65536, (int64_t)(c->cand.cap / sizeof(sbr_candidate)));
+    for (;;) {
+        HIPCHK(c, ensure(c->cand, sizeof(sbr_candidate) * (size_t)cap));
+        HIPCHK(c, launch_zero(c->counters.p, sizeof(Counters), st));
+        HIPCHK(c, hipEventRecord(c->ev[7], st));
+        if (n_w > 0 && n_rx > 0)
+            HIPCHK(c, launch_diff_trace(scene_dev(s), *A, c->cand.as<sbr_candidate>(), cap,
+                                        &dc->cand, &dc->err, st));
+        HIPCHK(c, hipEventRecord(c->ev[2], st));
+        HIPCHK(c, hipMemcpyAsync(hc, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        if (hc->err) return fail(c, SBR_E_INTERNAL, "traversal stack overflow");
+        if ((int64_t)hc->cand <= cap) break;
+        if (hc->cand >= (1ull << 31))
+            return fail(c, SBR_E_CAPACITY, "%llu diffraction events exceed 2^31", hc->cand);
+        cap = (int64_t)(hc->cand + hc->cand / 4 + 1024);
+    }
+    *n_cand = (int64_t)hc->cand;
+    HIPCHK(c, hipEventElapsedTime(ms_launch, c->ev[0], c->ev[1]));
+    if (!built) *ms_launch = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(ms_trace, c->ev[7], c->ev[2]));
+    return SBR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sbr_status sbr_scene_wedges(sbr_scene* s, sbr_wedge* out, int64_t capacity, int64_t* n_out)
+{
+    if (!s || !s->ctx) return SBR_E_NO_SCENE;
+    sbr_context* c = s->ctx;
+    c->err.clear();
+    if (!n_out) return fail(c, SBR_E_INVALID_ARG, "n_out is NULL");
+    *n_out = 0;
+    if (capacity < 0 || (capacity > 0 && !out)) return fail(c, SBR_E_INVALID_ARG, "bad output array");
+    HIPCHK(c, use_device(c->device));
+    sbr_status r = ensure_wedges(s);
+    if (r) return r;
+    const int64_t n = (int64_t)s->wedges.size();
+    *n_out = n;
+    if (n > capacity)
+        return fail(c, SBR_E_CAPACITY, "%lld wedges, capacity %lld", (long long)n, (long long)capacity);
+    for (int64_t i = 0; i < n; ++i) {
+        for (int q = 0; q < 3; ++q) {
+            out[i].a[q] = s->wedges[(size_t)i].a[q];
+            out[i].b[q] = s->wedge_b[3 * (size_t)i + q];
+        }
+        out[i].face[0] = s->wedges[(size_t)i].f0;
+        out[i].face[1] = s->wedges[(size_t)i].f1;
+    }
+    return SBR_OK;
+}
+
+sbr_status sbr_diff_candidates(sbr_scene* s, const double tx[3], const double* rx, int32_t n_rx,
+                               const sbr_trace_params* p, sbr_candidate* out, int64_t capacity,
+                               int64_t* n_out)
+{
+    sbr_status r = check_trace_inputs(s, tx, rx, n_rx, p, capacity, out, n_out);
+    if (r) return r;
+    sbr_context* c = s->ctx;
+    HIPCHK(c, use_device(c->device));
+    DiffArgs A;
+    int64_t C = 0;
+    float ml = 0, mt = 0;
+    r = diff_front(s, tx, rx, n_rx, p, &A, &C, &ml, &mt);
+    if (r) return r;
+    *n_out = C;
+    if (C > capacity)
+        return fail(c, SBR_E_CAPACITY, "%lld events, capacity %lld", (long long)C, (long long)capacity);
+    if (C == 0) return SBR_OK;
+    HIPCHK(c, ensure(c->idx, sizeof(uint32_t) * (size_t)pow2_at_least(C)));
+    HIPCHK(c, launch_sort_candidates(c->cand.as<sbr_candidate>(), C, c->idx.as<uint32_t>(),
+                                     c->stream));
+    HIPCHK(c, ensure(c->uniq, sizeof(sbr_candidate) * (size_t)C));
+    HIPCHK(c, launch_gather_sorted(c->cand.as<sbr_candidate>(), c->idx.as<uint32_t>(), C,
+                                   c->uniq.as<sbr_candidate>(), c->stream));
+    HIPCHK(c, hipMemcpyAsync(out, c->uniq.p, sizeof(sbr_candidate) * (size_t)C,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SBR_OK;
+}
+
+sbr_status sbr_diffract(sbr_scene* s, const double tx[3], const double* rx, int32_t n_rx,
+                        const sbr_trace_params* p, sbr_diff_path* out, int64_t capacity,
+                        int64_t* n_out, sbr_trace_stats* stats)
+{
+    sbr_status r = check_trace_inputs(s, tx, rx, n_rx, p, capacity, out, n_out);
+    if (r) return r;
+    sbr_context* c = s->ctx;
+    HIPCHK(c, use_device(c->device));
+    const hipStream_t st = c->stream;
+    DiffArgs A;
+    int64_t C = 0;
+    float ms_launch = 0, ms_trace = 0;
+    r = diff_front(s, tx, rx, n_rx, p, &A, &C, &ms_launch, &ms_trace);
+    if (r) return r;
+    Counters* hc = c->host_ctr;
+    Counters* dc = c->counters.as<Counters>();
+    const SceneDev S = scene_dev(s);
+    // path test 1: one path per (receiver, wedge)
+    int64_t U = 0;
+    if (C > 0) {
+        if (C <= kSmallEvents) {
+            HIPCHK(c, ensure(c->uniq, sizeof(sbr_candidate) * (size_t)C));
+            HIPCHK(c, launch_dedup_small(c->cand.as<sbr_candidate>(), C,
+                                         c->uniq.as<sbr_candidate>(), &dc->n_unique, st));
+        } else {
+            HIPCHK(c, ensure(c->idx, sizeof(uint32_t) * (size_t)pow2_at_least(C)));
+            HIPCHK(c, launch_sort_candidates(c->cand.as<sbr_candidate>(), C,
+                                             c->idx.as<uint32_t>(), st));
+            HIPCHK(c, ensure(c->flags, sizeof(int32_t) * (size_t)C));
+            HIPCHK(c, ensure(c->offs, sizeof(int32_t) * (size_t)C));
+            HIPCHK(c, ensure(c->scan, scan_scratch_bytes(C)));
+            HIPCHK(c, launch_heads(c->cand.as<sbr_candidate>(), c->idx.as<uint32_t>(), C,
+                                   c->flags.as<int32_t>(), st));
+            HIPCHK(c, launch_scan(c->flags.as<int32_t>(), c->offs.as<int32_t>(), C,
+                                  &dc->n_unique, c->scan.p, st));
+            HIPCHK(c, ensure(c->uniq, sizeof(sbr_candidate) * (size_t)C));
+            HIPCHK(c, launch_gather_unique(c->cand.as<sbr_candidate>(), c->idx.as<uint32_t>(),
+                                           c->flags.as<int32_t>(), c->offs.as<int32_t>(), C,
+                                           c->uniq.as<sbr_candidate>(), st));
+        }
+        HIPCHK(c, hipMemcpyAsync(hc, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        U = hc->n_unique;
+    }
+    HIPCHK(c, hipEventRecord(c->ev[3], st));
+    const size_t U1 = (size_t)std::max<int64_t>(U, 1);
+    HIPCHK(c, ensure(c->refine, sizeof(RefineOut) * U1));
+    HIPCHK(c, ensure(c->dpaths, sizeof(sbr_diff_path) * U1));
+    HIPCHK(c, ensure(c->keep, sizeof(int32_t) * U1));
+    HIPCHK(c, ensure(c->offs, sizeof(int32_t) * U1));
+    HIPCHK(c, ensure(c->scan, scan_scratch_bytes(U)));
+    HIPCHK(c, launch_diff_refine(S, A, c->uniq.as<sbr_candidate>(), U, c->refine.as<RefineOut>(),
+                                 &dc->err, st));
+    HIPCHK(c, hipEventRecord(c->ev[4], st));
+    HIPCHK(c, launch_diff_solve(S, A, c->uniq.as<sbr_candidate>(), c->refine.as<RefineOut>(), U,
+                                c->dpaths.as<sbr_diff_path>(), c->keep.as<int32_t>(), &dc->err,
+                                st));
+    HIPCHK(c, hipEventRecord(c->ev[5], st));
+    int64_t P = 0;
+    if (U > 0) {
+        HIPCHK(c, launch_scan(c->keep.as<int32_t>(), c->offs.as<int32_t>(), U, &dc->n_paths,
+                              c->scan.p, st));
+        HIPCHK(c, hipMemcpyAsync(hc, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        if (hc->err) return fail(c, SBR_E_INTERNAL, "traversal stack overflow");
+        P = hc->n_paths;
+    }
+    *n_out = P;
+    if (P > capacity)
+        return fail(c, SBR_E_CAPACITY, "%lld paths, capacity %lld", (long long)P, (long long)capacity);
+    if (P > 0) {
+        HIPCHK(c, ensure(c->dout, sizeof(sbr_diff_path) * (size_t)P));
+        HIPCHK(c, launch_compact_dpaths(c->dpaths.as<sbr_diff_path>(), c->keep.as<int32_t>(),
+                                        c->offs.as<int32_t>(), U, c->dout.as<sbr_diff_path>(), st));
+        HIPCHK(c, hipMemcpyAsync(out, c->dout.p, sizeof(sbr_diff_path) * (size_t)P,
+                                 hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(c, hipEventRecord(c->ev[6], st));
+    HIPCHK(c, hipEventSynchronize(c->ev[6]));
+    if (stats) {
+        memset(stats, 0, sizeof(*stats));
+        stats->n_rays = A.N;
+        stats->n_candidates = C;
+        stats->n_unique = U;
+        stats->n_paths = P;
+        float dd = 0, a = 0, b = 0, e = 0, tot = 0;
+        (void)hipEventElapsedTime(&dd, c->ev[2], c->ev[3]);
+        (void)hipEventElapsedTime(&a, c->ev[3], c->ev[4]);
+        (void)hipEventElapsedTime(&b, c->ev[4], c->ev[5]);
+        (void)hipEventElapsedTime(&e, c->ev[5], c->ev[6]);
+        (void)hipEventElapsedTime(&tot, c->ev[0], c->ev[6]);
+        stats->ms_launch = ms_launch;
+        stats->ms_trace = ms_trace;
+        stats->ms_dedup = dd;
+        stats->ms_refine = a;
+        stats->ms_solve = b;
+        stats->ms_emit = e;
+        stats->ms_total = tot;
+        stats->lds_max = c->lds_max;
+    }
     return SBR_OK;
 }
 

@@ -44,6 +44,7 @@ EXPORTS = (
     "sbr_trace_rays",
     "sbr_trace_counters", "sbr_trace_batch", "sbr_context_get_tuning", "sbr_context_set_tuning",
     "sbr_path_gradients", "sbr_status_string", "sbr_last_error", "sbr_trace_device_noalloc",
+    "sbr_scene_wedges", "sbr_diffract", "sbr_diff_candidates",
 )
 
 
@@ -113,6 +114,21 @@ PATH_DTYPE = np.dtype([
 ], align=True)
 assert PATH_DTYPE.itemsize == 248
 
+DPATH_DTYPE = np.dtype([
+    ("rx", np.int32), ("wedge", np.int32), ("launch_ray", np.int64), ("iters_used", np.int32),
+    ("flags", np.uint32), ("tan_err", np.float64), ("axis", np.float64, (3,)),
+    ("point", np.float64, (3,)), ("delay_s", np.float64), ("aod", np.float64, (3,)),
+    ("aoa", np.float64, (3,)), ("err_angle_deg", np.float64), ("length_m", np.float64),
+    ("exact_point", np.float64, (3,)), ("exact_delay_s", np.float64),
+    ("exact_aod", np.float64, (3,)), ("exact_aoa", np.float64, (3,)),
+    ("exact_length_m", np.float64), ("init_tan_err", np.float64),
+], align=True)
+assert DPATH_DTYPE.itemsize == 248
+
+WEDGE_DTYPE = np.dtype([("a", np.float64, (3,)), ("b", np.float64, (3,)), ("face", np.int32, (2,))],
+                       align=True)
+assert WEDGE_DTYPE.itemsize == 56
+
 CAND_DTYPE = np.dtype([
     ("rx", np.int32), ("order", np.int32), ("face", np.int32, (MAX_ORDER,)),
     ("ray", np.int64), ("tan_err", np.float64),
@@ -165,6 +181,11 @@ def lib(load_torch: bool = True):
                                    lp, C.POINTER(TraceStats)]
     L.sbr_trace_device_noalloc.argtypes = [vp, dp, vp, C.c_int32, C.POINTER(TraceParams), vp,
                                            C.c_int64, lp, C.POINTER(TraceStats)]
+    L.sbr_scene_wedges.argtypes = [vp, vp, C.c_int64, lp]
+    L.sbr_diffract.argtypes = [vp, dp, dp, C.c_int32, C.POINTER(TraceParams), vp, C.c_int64, lp,
+                               C.POINTER(TraceStats)]
+    L.sbr_diff_candidates.argtypes = [vp, dp, dp, C.c_int32, C.POINTER(TraceParams), vp,
+                                      C.c_int64, lp]
     L.sbr_candidates.argtypes = [vp, dp, dp, C.c_int32, C.POINTER(TraceParams), vp, C.c_int64,
                                  lp]
     L.sbr_launch_grid.argtypes = [vp, C.c_int32, C.c_int32, C.c_int64, C.c_int64, dp]
@@ -391,6 +412,53 @@ class Scene:
             n = C.c_int64()
             st = lib().sbr_candidates(self.h, _d(txa), _d(rxa), len(rxa), C.byref(prm),
                                       out.ctypes.data_as(C.c_void_p), cap, C.byref(n))
+            if st == E_CAPACITY and capacity is None:
+                cap = n.value
+                continue
+            self.ctx._check(st)
+            return out[: n.value].copy()
+
+    def wedges(self):
+        """sbr_scene_wedges: structured array of (a, b, face)."""
+        n = C.c_int64()
+        st = lib().sbr_scene_wedges(self.h, None, 0, C.byref(n))
+        if st != E_CAPACITY:  # the count query of a scene with wedges
+            self.ctx._check(st)
+        out = np.zeros(max(n.value, 1), WEDGE_DTYPE)
+        self.ctx._check(lib().sbr_scene_wedges(self.h, out.ctypes.data_as(C.c_void_p), n.value,
+                                               C.byref(n)))
+        return out[: n.value]
+
+    def diffract(self, tx, rx, capacity: int | None = None, **params):
+        """sbr_diffract: order-1 diffraction paths (DPATH_DTYPE) and stats."""
+        txa = np.ascontiguousarray(tx, np.float64).reshape(3)
+        rxa = np.ascontiguousarray(rx, np.float64).reshape(-1, 3)
+        prm = make_params(**params)
+        cap = capacity if capacity is not None else 4096
+        while True:
+            out = np.zeros(max(cap, 1), DPATH_DTYPE)
+            n = C.c_int64()
+            stats = TraceStats()
+            st = lib().sbr_diffract(self.h, _d(txa), _d(rxa), len(rxa), C.byref(prm),
+                                    out.ctypes.data_as(C.c_void_p), cap, C.byref(n),
+                                    C.byref(stats))
+            if st == E_CAPACITY and capacity is None:
+                cap = n.value
+                continue
+            self.ctx._check(st)
+            return out[: n.value].copy(), stats.as_dict()
+
+    def diff_candidates(self, tx, rx, capacity: int | None = None, **params):
+        """sbr_diff_candidates: diffraction events before path test 1, sorted."""
+        txa = np.ascontiguousarray(tx, np.float64).reshape(3)
+        rxa = np.ascontiguousarray(rx, np.float64).reshape(-1, 3)
+        prm = make_params(**params)
+        cap = capacity if capacity is not None else 16384
+        while True:
+            out = np.zeros(max(cap, 1), CAND_DTYPE)
+            n = C.c_int64()
+            st = lib().sbr_diff_candidates(self.h, _d(txa), _d(rxa), len(rxa), C.byref(prm),
+                                           out.ctypes.data_as(C.c_void_p), cap, C.byref(n))
             if st == E_CAPACITY and capacity is None:
                 cap = n.value
                 continue

@@ -67,8 +67,10 @@ def _struct_layout_probe():
 #include <stdio.h>
 #include "sbr.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu\n", sizeof(sbr_path), sizeof(sbr_candidate),
-         sizeof(sbr_trace_params), sizeof(sbr_trace_stats), sizeof(sbr_complex));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(sbr_path), sizeof(sbr_candidate),
+         sizeof(sbr_trace_params), sizeof(sbr_trace_stats), sizeof(sbr_complex),
+         sizeof(sbr_diff_path), sizeof(sbr_wedge), offsetof(sbr_diff_path, exact_point),
+         offsetof(sbr_diff_path, init_tan_err));
   printf("%zu %zu %zu %zu %zu %zu\n", offsetof(sbr_path, launch_ray), offsetof(sbr_path, tan_err),
          offsetof(sbr_path, delay_s), offsetof(sbr_path, exact_delay_s),
          offsetof(sbr_path, init_tan_err), offsetof(sbr_candidate, tan_err));
@@ -93,6 +95,9 @@ def test_binding_layouts_match_header():
     assert sizes[2] == C.sizeof(sbr.TraceParams)
     assert sizes[3] == C.sizeof(sbr.TraceStats)
     assert sizes[4] == C.sizeof(sbr.Complex)
+    assert sizes[5] == sbr.DPATH_DTYPE.itemsize and sizes[6] == sbr.WEDGE_DTYPE.itemsize
+    assert sizes[7] == sbr.DPATH_DTYPE.fields["exact_point"][1]
+    assert sizes[8] == sbr.DPATH_DTYPE.fields["init_tan_err"][1]
     P, K = sbr.PATH_DTYPE, sbr.CAND_DTYPE
     assert offs == [P.fields["launch_ray"][1], P.fields["tan_err"][1], P.fields["delay_s"][1],
                     P.fields["exact_delay_s"][1], P.fields["init_tan_err"][1],
