@@ -496,6 +496,52 @@ def launch_variants(ctx, scenes, torch, steps=3):
     return out
 
 
+def diffraction_leg(ctx, scenes, torch, steps=5):
+    """Order-1 diffraction (the paper's second workload, Sec. IV) on the
+    Manhattan grid: 768 wedges, Tx at 25 m, 64 Rx, n = 200 (400,002 rays),
+    10 iterations of 6 sub-rays as in the paper, then the 0.01 deg target
+    mode: one sbr_diffract call per step, rays/s, paths, the AOD and AOA
+    errors against the exact (Keller) paths before and after refinement."""
+    cfg = scenes.manhattan_config(0)
+    prm = dict(division_n=200, iterations=10, subrays=6)
+    sc = ctx.scene(cfg["scene"])
+    n_w = len(sc.wedges())
+    N = 10 * 200 * 200 + 2
+
+    def timed(**kw):
+        sc.diffract(cfg["tx"], cfg["rx"], **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            p, st = sc.diffract(cfg["tx"], cfg["rx"], **kw)
+        torch.cuda.synchronize()
+        return p, st, (time.perf_counter() - t0) / steps
+
+    p0, _, _ = timed(**dict(prm, iterations=0))
+    p10, st10, t10 = timed(**prm)
+    pt, stt, tt = timed(**dict(prm, iterations=30, target_err_deg=0.01))
+    sc.close()
+
+    def errs(p):
+        return (float(angle_deg(p["aod"], p["exact_aod"]).mean()) if len(p) else None,
+                float(angle_deg(p["aoa"], p["exact_aoa"]).mean()) if len(p) else None)
+
+    e0, e10, et = errs(p0), errs(p10), errs(pt)
+    good = int(accurate_mask(pt).sum())
+    return {
+        "workload": "manhattan_8x8_770tri_768wedges_n200_rx64_order1_diffraction",
+        "wedges": n_w, "rays": N, "paths": int(len(p10)),
+        "ms_per_call_i10": round(1e3 * t10, 4), "rays_per_s": N / t10,
+        "stage_ms_i10": {k: round(float(st10[k]), 4) for k in STAGES},
+        "mean_err_deg": {"traditional": {"aod": e0[0], "aoa": e0[1]},
+                         "i10": {"aod": e10[0], "aoa": e10[1]},
+                         "target_0.01deg": {"aod": et[0], "aoa": et[1]}},
+        "refined_paths_per_s": good / tt, "within_0.01deg": good, "target_paths": int(len(pt)),
+        "ms_per_call_target": round(1e3 * tt, 4),
+        "stage_ms_target": {k: round(float(stt[k]), 4) for k in STAGES},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -509,6 +555,8 @@ def main():
                     help="skip the Manhattan (770 triangles, 400k rays, 64 Rx) leg")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the launch-grid / traditional-vs-precise comparison")
+    ap.add_argument("--no-diffraction", action="store_true",
+                    help="skip the order-1 diffraction leg")
     ap.add_argument("--large-only", action="store_true",
                     help="run only the headline large-city leg and print its JSON object "
                          "(profiling)")
@@ -581,6 +629,9 @@ def main():
         log("manhattan", json.dumps(out["manhattan"]))
     if not args.no_variants:
         out["launch_variants"] = launch_variants(ctx, scenes, torch)
+    if not args.no_diffraction:
+        out["diffraction"] = diffraction_leg(ctx, scenes, torch)
+        log("diffraction", json.dumps(out["diffraction"]))
     if not args.no_batch:
         out["batched"] = batch_vs_plain(ctx, scenes, torch)
     ctx.close()
