@@ -256,8 +256,9 @@ def batch_vs_plain(ctx, scenes, torch, seed=0, steps=2):
     build_s = time.perf_counter() - t0
     ctx.trace_batch(scs, jobs, b["rx"])  # warm-up: launch grids of every n
     base = ctx.tuning()
+    # depth 0: the refinement's persistent work queue; 3: the lookahead kernels
     space = {"trace_chunk": [1, 2, 4], "persist_blocks": [1024, 2048, 4096, 8192],
-             "lookahead_max_paths": [0, 4096]}
+             "lookahead_max_paths": [0, 4096], "lookahead_depth": [0, 3]}
     best, trials = autotune.autotune(ctx, lambda: ctx.trace_batch(scs, jobs, b["rx"]),
                                      space=space, warmup=0, steps=1)
     torch.cuda.synchronize()
@@ -562,6 +563,8 @@ def main():
                          "(profiling)")
     ap.add_argument("--manhattan-only", action="store_true",
                     help="run only the Manhattan leg and print its JSON object (profiling)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batched-vs-plain comparison and print its JSON object")
     ap.add_argument("--tuning", type=json.loads, default=None, metavar="JSON",
                     help="tuning fields for the Manhattan leg instead of autotuning "
                          "(profiling runs pin what an earlier run chose)")
@@ -592,6 +595,10 @@ def main():
     ctx = sbr.Context(0)
     if args.manhattan_only:
         print(json.dumps(manhattan_leg(ctx, scenes, torch, args)[1]), flush=True)
+        ctx.close()
+        return
+    if args.batch_only:
+        print(json.dumps(batch_vs_plain(ctx, scenes, torch)), flush=True)
         ctx.close()
         return
     lcfg, lc = large_city_leg(ctx, scenes, torch, args.steps, args.warmup,

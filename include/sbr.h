@@ -150,7 +150,12 @@ typedef struct {
  * path, with its own LDS plan, for at most lookahead3_max_paths paths,
  * since it traces 399 sub-rays per path and step; 2: one wave per path);
  * otherwise, or with depth 1, one iteration per step with eight lanes per
- * path.  A job with at least rx_tree_min receivers tests reception through
+ * path.  Depth 0 (single calls and batches) refines in one persistent
+ * launch whose lanes take sub-rays from a device work queue: the lane that
+ * completes an iteration's last sub-ray picks the winner and queues the next
+ * iteration's sub-rays, so every path runs its own number of iterations
+ * without a relaunch (calls whose queue would exceed 256 MiB use depth 1).
+ * A job with at least rx_tree_min receivers tests reception through
  * a ball tree over its receivers (a conservative cull before the exact test
  * of eq. (3)) instead of testing every receiver on every segment.  The
  * equiangular grid's setup takes a value from short series when its error
@@ -169,7 +174,7 @@ typedef struct {
     int32_t lds_budget;          /* bytes, 0..device limit per workgroup    */
     int32_t rx_tree_min;         /* >= 1                                    */
     int64_t lookahead_max_paths; /* >= 0                                    */
-    int32_t lookahead_depth;     /* 1..3                                    */
+    int32_t lookahead_depth;     /* 0..3                                    */
     int32_t lookahead3_max_paths; /* >= 0                                   */
     int32_t grid_check_log2;     /* 0..200                                  */
     int32_t ray_order;           /* 0 or 1                                  */
@@ -277,8 +282,11 @@ typedef struct {
 
 /* Many transmitter/receiver jobs over several scenes in one pass of the path:
  * one persistent trace launch whose device queue hands out ray packets of all
- * jobs, one path test 1 over all reception events, one refinement and one
- * solve launch over all paths.  Each job's paths are exactly those sbr_trace
+ * jobs, one path test 1 over all reception events, one refinement launch over
+ * all paths (the context's lookahead tuning; with depth 0 a persistent launch
+ * whose device work queue holds every path's sub-rays, each path iterating as
+ * far as its own job's iteration count and target take it), and one solve
+ * launch over all paths.  Each job's paths are exactly those sbr_trace
  * returns for it alone, with sbr_path.rx numbering the batch's receiver
  * array; the list is sorted by (rx, order, face sequence).  rx [n_rx_total][3]
  * host FP64.  All scenes must belong to ctx and have a BVH.  Errors as for

@@ -16,6 +16,7 @@
 #include "diffract.h"
 #include "geom.h"
 #include "internal.h"
+#include "refine_queue.h"
 
 using namespace sbr;
 
@@ -125,7 +126,7 @@ struct sbr_context {
     int64_t noalloc_unique = -1;  // path count of the last no-allocation call
     DevBuf grid_scratch, rx, rx32, cand, idx, flags, offs, scan, uniq, refine, paths, keep, outp,
         counters, rays_tri, rays_t, tally, geom, d_jobs, d_scenes, d_rxjob, d_rxnodes, d_rxperm,
-        d_rxp, dpaths, dout;
+        d_rxp, dpaths, dout, q_state, q_slot, q_items, q_ctr;
     Counters* host_ctr = nullptr;  // pinned
     sbr_path* host_paths = nullptr;  // pinned staging of the path list
     int64_t host_paths_cap = 0;
@@ -655,9 +656,11 @@ int trace_blocks(const sbr_context* c, const Call& call)
 }
 
 // Iterations per refinement step for U paths: three only for few paths
-// (latency-bound), two up to lookahead_max_paths, else one.
+// (latency-bound), two up to lookahead_max_paths, else one; 0 selects the
+// persistent work-queue refinement.
 int refine_depth(const sbr_context* c, int64_t U)
 {
+    if (c->lookahead_depth == 0) return 0;
     if (U > c->lookahead_max_paths) return 1;
     if (c->lookahead_depth >= 3 && U > c->lookahead3_max_paths) return 2;
     return c->lookahead_depth;
@@ -770,6 +773,44 @@ sbr_status ensure_host_paths(sbr_context* c, int64_t n)
     return SBR_OK;
 }
 
+// Items beyond this many bytes send the refinement to the lookahead kernels.
+constexpr int64_t kQueueMaxBytes = int64_t(256) << 20;
+
+// The precise algorithm through the persistent work queue (refine_queue.h):
+// buffers for Umax paths of the call's jobs, zeroed items and counters.
+sbr_status refine_by_queue(sbr_context* c, Call& call, int64_t Umax, const int32_t* ndev,
+                           int32_t* err)
+{
+    hipStream_t st = c->stream;
+    int32_t max_it = 1;
+    for (const JobDev& J : call.jobs) max_it = std::max(max_it, J.iterations);
+    RefineQueue Q;
+    Q.cap = refine_queue_cap(std::max<int64_t>(Umax, 1), max_it);
+    const size_t U1 = (size_t)std::max<int64_t>(Umax, 1);
+    HIPCHK(c, ensure(c->q_state, sizeof(QState) * U1));
+    HIPCHK(c, ensure(c->q_slot, sizeof(QSlot) * 8 * U1));
+    HIPCHK(c, ensure(c->q_items, sizeof(unsigned long long) * (size_t)Q.cap));
+    HIPCHK(c, ensure(c->q_ctr, 16));
+    HIPCHK(c, launch_zero(c->q_items.p, sizeof(unsigned long long) * (size_t)Q.cap, st));
+    HIPCHK(c, launch_zero(c->q_ctr.p, 16, st));
+    Q.state = c->q_state.as<QState>();
+    Q.slot = c->q_slot.as<QSlot>();
+    Q.items = c->q_items.as<unsigned long long>();
+    Q.ctr = c->q_ctr.as<uint32_t>();
+    const int blocks = (int)std::max<int64_t>(
+        1, std::min<int64_t>((Umax * 7 + 255) / 256, c->persist_blocks));
+    HIPCHK(c, launch_refine_queue(call.dev, c->uniq.as<sbr_candidate>(), Umax, ndev, Q, blocks,
+                                  c->refine.as<RefineOut>(), err, st));
+    return SBR_OK;
+}
+
+bool queue_fits(const Call& call, int64_t Umax)
+{
+    int32_t max_it = 1;
+    for (const JobDev& J : call.jobs) max_it = std::max(max_it, J.iterations);
+    return refine_queue_cap(std::max<int64_t>(Umax, 1), max_it) * 8 <= kQueueMaxBytes;
+}
+
 // The back half: precise algorithm, path quantities / path test 2 / power,
 // and the canonical emit into out.
 sbr_status run_paths(sbr_context* c, Call& call, sbr_path* out, int64_t capacity, int64_t* n_out,
@@ -788,11 +829,17 @@ sbr_status run_paths(sbr_context* c, Call& call, sbr_path* out, int64_t capacity
     HIPCHK(c, ensure(c->geom, sizeof(PathGeom) * U1));
     LdsPlan lp256 = call.scenes.size() == 1 ? plan_for(call.scenes[0], 256) : LdsPlan{};
     lp256.block = 256;
-    const int depth = refine_depth(c, call.spec ? call.u_pred : Umax);
+    int depth = refine_depth(c, call.spec ? call.u_pred : Umax);
+    if (depth == 0 && !queue_fits(call, Umax)) depth = 1;
     LdsPlan lp3 = call.scenes.size() == 1 ? plan_la3(call.scenes[0]) : LdsPlan{};
-    HIPCHK(c, launch_refine(call.dev, lp256, lp3, call.s0, c->uniq.as<sbr_candidate>(), Umax,
-                            ndev, depth, c->refine.as<RefineOut>(), c->geom.as<PathGeom>(),
-                            &dc->err, st));
+    if (depth == 0) {
+        r = refine_by_queue(c, call, Umax, ndev, &dc->err);
+        if (r) return r;
+    } else {
+        HIPCHK(c, launch_refine(call.dev, lp256, lp3, call.s0, c->uniq.as<sbr_candidate>(), Umax,
+                                ndev, depth, c->refine.as<RefineOut>(), c->geom.as<PathGeom>(),
+                                &dc->err, st));
+    }
     HIPCHK(c, hipEventRecord(c->ev[4], st));
 
     HIPCHK(c, ensure(c->paths, sizeof(sbr_path) * U1));
@@ -805,7 +852,8 @@ sbr_status run_paths(sbr_context* c, Call& call, sbr_path* out, int64_t capacity
     lps.block = 256;
     HIPCHK(c, launch_solve(call.dev, lps, call.s0, c->uniq.as<sbr_candidate>(),
                            c->refine.as<RefineOut>(), c->geom.as<PathGeom>(), Umax, ndev,
-                           c->paths.as<sbr_path>(), c->keep.as<int32_t>(), &dc->err, st));
+                           c->paths.as<sbr_path>(), c->keep.as<int32_t>(), &dc->err, st,
+                           depth == 0));
     HIPCHK(c, hipEventRecord(c->ev[5], st));
 
     // emit: stable compaction of kept paths (already in canonical order)
@@ -831,13 +879,17 @@ sbr_status run_paths(sbr_context* c, Call& call, sbr_path* out, int64_t capacity
         HIPCHK(c, hipEventRecord(c->ev[6], st));
         HIPCHK(c, hipEventSynchronize(c->ev[6]));
         if (call.spec) {
+            if ((hc->err & 2) != 0)
+                return fail(c, SBR_E_INTERNAL, "refinement work queue did not drain");
             if (hc->err || (int64_t)hc->cand > call.n_cand) return kSpecMiss;
             call.n_cand = (int64_t)hc->cand;
             HIPCHK(c, hipEventElapsedTime(&call.ms_launch, c->ev[0], c->ev[1]));
             if (!call.grids_built) call.ms_launch = 0.0f;
             HIPCHK(c, hipEventElapsedTime(&call.ms_trace, c->ev[7], c->ev[2]));
         }
-        if (hc->err) return fail(c, SBR_E_INTERNAL, "traversal stack overflow");
+        if (hc->err)
+            return fail(c, SBR_E_INTERNAL, (hc->err & 2) ? "refinement work queue did not drain"
+                                                          : "traversal stack overflow");
         P = hc->n_paths;
         U = hc->n_unique;
         *n_out = P;
@@ -850,7 +902,9 @@ sbr_status run_paths(sbr_context* c, Call& call, sbr_path* out, int64_t capacity
                               c->scan.p, st));
         HIPCHK(c, hipMemcpyAsync(hc, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipStreamSynchronize(st));
-        if (hc->err) return fail(c, SBR_E_INTERNAL, "traversal stack overflow");
+        if (hc->err)
+            return fail(c, SBR_E_INTERNAL, (hc->err & 2) ? "refinement work queue did not drain"
+                                                          : "traversal stack overflow");
         P = hc->n_paths;
         *n_out = P;
         if (P > capacity)
@@ -1005,7 +1059,7 @@ sbr_status sbr_context_create(int32_t device, void* hip_stream, sbr_context** ou
         c->trace_chunk = env_int("SBR_TRACE_CHUNK", 1, 1, 64);
         c->persist_blocks = env_int("SBR_TRACE_BLOCKS", 2048, 1, 1 << 20);
         c->rx_tree_min = env_int("SBR_RX_TREE_MIN", 64, 1, 0x7fffffff);
-        c->lookahead_depth = env_int("SBR_LOOKAHEAD_DEPTH", 3, 1, 3);
+        c->lookahead_depth = env_int("SBR_LOOKAHEAD_DEPTH", 3, 0, 3);
         c->lookahead3_max_paths = env_int("SBR_LOOKAHEAD3_PATHS", 256, 0, 1 << 30);
         c->la3_lds = env_int("SBR_LA3_LDS", 1, 0, 1) != 0;
         c->ray_order = env_int("SBR_RAY_ORDER", 1, 0, 1);
@@ -1053,7 +1107,7 @@ sbr_status sbr_context_set_tuning(sbr_context* c, const sbr_tuning* t)
         t->trace_block < 64 || t->trace_block > 256 || t->trace_block % 64 != 0 ||
         t->stack_depth < 0 || t->stack_depth > kTraceStack || t->lds_budget < 0 ||
         t->lds_budget > c->lds_max || t->rx_tree_min < 1 || t->lookahead_max_paths < 0 ||
-        t->lookahead_depth < 1 || t->lookahead_depth > 3 || t->lookahead3_max_paths < 0 ||
+        t->lookahead_depth < 0 || t->lookahead_depth > 3 || t->lookahead3_max_paths < 0 ||
         t->grid_check_log2 < 0 || t->grid_check_log2 > 200 || t->ray_order < 0 ||
         t->ray_order > 1)
         return fail(c, SBR_E_INVALID_ARG, "tuning field out of range");
@@ -1089,7 +1143,8 @@ sbr_status sbr_context_destroy(sbr_context* c)
                       &c->offs,         &c->scan,  &c->uniq,  &c->refine, &c->paths,
                       &c->keep,         &c->outp,  &c->counters, &c->rays_tri, &c->rays_t, &c->tally,
                       &c->geom,         &c->d_jobs, &c->d_scenes, &c->d_rxjob,
-                      &c->d_rxnodes,    &c->d_rxperm, &c->d_rxp, &c->dpaths, &c->dout};
+                      &c->d_rxnodes,    &c->d_rxperm, &c->d_rxp, &c->dpaths, &c->dout,
+                      &c->q_state,      &c->q_slot,  &c->q_items, &c->q_ctr};
     for (DevBuf* b : bufs) release(*b);
     for (auto& ev : c->ev)
         if (ev) (void)hipEventDestroy(ev);
@@ -1529,7 +1584,8 @@ sbr_status capture_graph(sbr_context* c, sbr_scene* s, Call& call, const double*
     lp256.block = 256;
     Counters* dc = c->counters.as<Counters>();
     const hipStream_t st = G.cap_stream;
-    const int depth = refine_depth(c, u_pred);
+    // the graph holds the lookahead kernels (the queue is for batches)
+    const int depth = std::max(1, refine_depth(c, u_pred));
 
     HIPCHK(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
@@ -1805,7 +1861,7 @@ sbr_status sbr_trace_device_noalloc(sbr_scene* s, const double tx[3], const doub
     HIPCHK(c, hipEventRecord(c->ev[3], st));
     LdsPlan lp256 = plan_for(s, 256);
     lp256.block = 256;
-    const int depth = refine_depth(c, c->noalloc_unique >= 0 ? c->noalloc_unique : 256);
+    const int depth = std::max(1, refine_depth(c, c->noalloc_unique >= 0 ? c->noalloc_unique : 256));
     HIPCHK(c, launch_refine(D, lp256, plan_la3(s), S0, uniq, kSmallEvents, &dc->n_unique, depth,
                             rf, geom, &dc->err, st));
     HIPCHK(c, hipEventRecord(c->ev[4], st));

@@ -218,7 +218,7 @@ hipError_t launch_refine(const CallDev& call, const LdsPlan& L, const LdsPlan& L
 hipError_t launch_solve(const CallDev& call, const LdsPlan& L, const SceneDev& s0,
                         const sbr_candidate* uniq, const RefineOut* rf, PathGeom* geom,
                         int64_t U_max, const int32_t* n_dev, sbr_path* paths, int32_t* keep,
-                        int32_t* err, hipStream_t s);
+                        int32_t* err, hipStream_t s, bool replay = false);
 
 hipError_t launch_compact_paths(const sbr_path* paths, const int32_t* keep, const int32_t* offs,
                                 int64_t U, sbr_path* out, hipStream_t s);

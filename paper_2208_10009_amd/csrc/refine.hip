@@ -2,7 +2,10 @@
 // quantities, path test 2 and power (Sec. III.A, Sec. IV).
 #include <math.h>
 
+#include <algorithm>
+
 #include "cone.h"
+#include "refine_queue.h"
 #include "traverse.h"
 
 namespace sbr {
@@ -440,6 +443,248 @@ __global__ __launch_bounds__(512) void k_refine_la3(CallDev call, LdsPlan L, Sce
     }
 }
 
+// ---------------------------------------------------------------------------
+// The precise algorithm fed by a device work queue of sub-rays: one
+// persistent launch refines every path of a call (of every job of a batch),
+// whatever its order and iteration count.  A work item is one sub-ray of one
+// path's current iteration.  Lanes take items in the order they were pushed;
+// the lane that finishes the last sub-ray of an iteration (the path's pending
+// count reaching zero) picks the winner (smallest error, ties: lower sub-ray)
+// and either ends the path or pushes the next iteration's sub-rays.  Every
+// sub-ray is traced with the arithmetic of k_refine, so the results are the
+// same; the winner's geometry is not kept (the solve traces the final axis).
+//
+// Memory order.  Data one lane hands to another (the path state, the
+// sub-ray slots, the items) is written and read only with device-scope
+// atomic loads and stores, which are coherent across the chip's L2 caches
+// on their own; every handoff is published by a release operation (items
+// after the state, the pending count after the slot) and read through a
+// value the reader has already loaded (the item names the path; the pending
+// count tells the last lane to read the slots).  No acquire is used: on this
+// chip an acquire at device scope invalidates the L2 cache, which would
+// evict the scene that every lane is traversing.
+// A lane leaves when every path is done, when its item index lies beyond the
+// last item any path can push, or -- never in a correct run -- after a
+// bounded wait (error flag 2).
+// ---------------------------------------------------------------------------
+constexpr int kQueueBlock = 256;
+
+__device__ static inline unsigned long long q_item(int64_t p, int s)
+{
+    return ((unsigned long long)p << 3 | (unsigned long long)s) + 1ull;
+}
+
+template <int W>
+__device__ static inline void q_store_words(void* dst, const void* src)
+{
+    unsigned long long* d = (unsigned long long*)dst;
+    const unsigned long long* v = (const unsigned long long*)src;
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+        __hip_atomic_store(d + k, v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int W>
+__device__ static inline void q_load_words(void* dst, const void* src)
+{
+    unsigned long long* d = (unsigned long long*)dst;
+    const unsigned long long* v = (const unsigned long long*)src;
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+        d[k] = __hip_atomic_load(v + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The state of path p, then (after a release fence) its sub-rays 0..S-1 of
+// the state's iteration.
+__device__ static inline void q_push(const RefineQueue& Q, int64_t p, const QState& q, int S)
+{
+    q_store_words<sizeof(QState) / 8>(Q.state + p, &q);
+    const unsigned int base = atomicAdd(&Q.ctr[1], (unsigned int)S);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    for (int s = 0; s < S; ++s)
+        if ((int64_t)base + s < Q.cap)
+            __hip_atomic_store(&Q.items[base + s], q_item(p, s), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ static inline void q_finish(const RefineQueue& Q, RefineOut* out, int64_t p, d3 axis,
+                                       double tan, int32_t iters, uint32_t flags)
+{
+    RefineOut o;
+    st3(o.axis, axis);
+    o.tan_err = tan;
+    o.iters = iters;
+    o.flags = flags;
+    out[p] = o;
+    __hip_atomic_fetch_add(&Q.ctr[2], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(256) void k_queue_init(CallDev call,
+                                                    const sbr_candidate* __restrict__ uniq,
+                                                    int64_t U_max, const int32_t* __restrict__ n_dev,
+                                                    RefineQueue Q, RefineOut* __restrict__ out,
+                                                    int32_t* __restrict__ err)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t U = n_dev ? min(U_max, (int64_t)*n_dev) : U_max;
+    if (p >= U) return;
+    const sbr_candidate c = uniq[p];
+    const JobDev J = call.jobs[call.rx_job[c.rx]];
+    const SceneDev S = call.scenes[J.scene];
+    const d3 tx = mk(J.tx[0], J.tx[1], J.tx[2]);
+    const d3 rx = mk(call.rx[3 * c.rx], call.rx[3 * c.rx + 1], call.rx[3 * c.rx + 2]);
+    const d3 axis = mk(J.dir[c.ray], J.dir[J.N + c.ray], J.dir[2 * J.N + c.ray]);
+    LdsPlan L0{};
+    L0.block = 256;
+    double tan;
+    bool met;
+    if (!start_path<false>(S, L0, J.tan_tgt, c, tx, rx, axis, J.delta, err, &tan, &met)) {
+        q_finish(Q, out, p, axis, NAN, 0, SBR_PATH_STALLED);
+        return;
+    }
+    if (met || J.iterations == 0) {
+        q_finish(Q, out, p, axis, tan, 0, met ? SBR_PATH_TARGET_MET : 0u);
+        return;
+    }
+    QState q;
+    st3(q.axis, axis);
+    q.rho = J.thl / sqrt(3.0);
+    q.tan = tan;
+    q.i = 1;
+    q.iters = 0;
+    q.flags = 0u;
+    q.pending = J.subrays;
+    q_push(Q, p, q, J.subrays);
+}
+
+// One work item v: trace its sub-ray, record it, and if it was the
+// iteration's last, pick the winner and end the path or queue the next
+// iteration's sub-rays.
+__device__ static inline void q_process(const CallDev& call, const sbr_candidate* uniq,
+                                        const RefineQueue& Q, unsigned long long v,
+                                        RefineOut* out, int32_t* err)
+{
+    LdsPlan L0{};
+    L0.block = kQueueBlock;
+    const int64_t p = (int64_t)((v - 1ull) >> 3);
+    const int s = (int)((v - 1ull) & 7ull);
+    const sbr_candidate c = uniq[p];
+    const JobDev J = call.jobs[call.rx_job[c.rx]];
+    const SceneDev S = call.scenes[J.scene];
+    const d3 tx = mk(J.tx[0], J.tx[1], J.tx[2]);
+    const d3 rx = mk(call.rx[3 * c.rx], call.rx[3 * c.rx + 1], call.rx[3 * c.rx + 2]);
+    QState q;
+    q_load_words<sizeof(QState) / 8>(&q, Q.state + p);
+    const d3 axis = ld3(q.axis);
+    d3 u, w;
+    basis(axis, &u, &w);
+    Follow F;
+    const bool ok = follow<false, kQueueBlock>(S, L0, tx, subray(axis, u, w, q.rho, s), rx,
+                                               c.order, c.face, J.delta, &F, nullptr, nullptr,
+                                               err);
+    QSlot sl;
+    sl.tan = ok ? F.tan_err : INFINITY;
+    sl.D = ok ? F.D : 0.0;
+    sl.Llast = ok ? F.Llast : 0.0;
+    sl.ok = ok ? 1 : 0;
+    sl.pad = 0;
+    q_store_words<sizeof(QSlot) / 8>(Q.slot + 8 * p + s, &sl);
+    const int32_t left = __hip_atomic_fetch_add(&Q.state[p].pending, -1, __ATOMIC_RELEASE,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+    if (left != 1) return;
+    // the iteration's last sub-ray: its winner, then the next iteration
+    double bt = INFINITY;
+    int bs = 8;
+    QSlot win;
+    for (int k = 0; k < J.subrays; ++k) {
+        QSlot o;
+        if (k == s)
+            o = sl;
+        else
+            q_load_words<sizeof(QSlot) / 8>(&o, Q.slot + 8 * p + k);
+        if (o.ok && o.tan < bt) {
+            bt = o.tan;
+            bs = k;
+            win = o;
+        }
+    }
+    if (bs >= 8) {
+        q_finish(Q, out, p, axis, q.tan, q.iters, q.flags | SBR_PATH_STALLED);
+        return;
+    }
+    const d3 naxis = subray(axis, u, w, q.rho, bs);
+    uint32_t flags = q.flags;
+    const bool met = J.tan_tgt > 0.0 && target_met(bt, J.tan_tgt, win.D, win.Llast);
+    if (met) flags |= SBR_PATH_TARGET_MET;
+    if (met || q.i >= J.iterations) {
+        q_finish(Q, out, p, naxis, bt, q.i, flags);
+        return;
+    }
+    QState nq;
+    st3(nq.axis, naxis);
+    nq.rho = q.rho / sqrt(3.0);
+    nq.tan = bt;
+    nq.i = q.i + 1;
+    nq.iters = q.i;
+    nq.flags = flags;
+    nq.pending = J.subrays;
+    q_push(Q, p, nq, J.subrays);
+}
+
+// The lanes of a wave wait for their items independently, and a lane whose
+// item is there traces it in the same pass of the loop, so a lane never waits
+// for a lane of its own wave.  The loop therefore has a single back edge: the
+// empty asm hides the item index's value from the optimiser, which would
+// otherwise thread the waiting path straight back to the item load and so
+// make the wait an inner loop that the whole wave must leave together.
+__global__ __launch_bounds__(kQueueBlock) void k_refine_queue(
+    CallDev call, const sbr_candidate* __restrict__ uniq, int64_t U_max,
+    const int32_t* __restrict__ n_dev, RefineQueue Q, RefineOut* __restrict__ out,
+    int32_t* __restrict__ err)
+{
+    const uint32_t U = (uint32_t)(n_dev ? min(U_max, (int64_t)*n_dev) : U_max);
+    int32_t idx = -1;
+    uint32_t spins = 0;
+    for (;;) {
+        asm volatile("" : "+v"(idx));
+        if (idx < 0) {
+            idx = (int32_t)atomicAdd(&Q.ctr[0], 1u);
+            spins = 0;
+        }
+        bool leave = (int64_t)(uint32_t)idx >= Q.cap;
+        unsigned long long v = 0ull;
+        if (!leave)
+            v = __hip_atomic_load(&Q.items[(uint32_t)idx], __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+        if (v != 0ull) {
+            q_process(call, uniq, Q, v, out, err);
+            idx = -1;
+        } else if (!leave) {
+            if (__hip_atomic_load(&Q.ctr[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= U) {
+                leave = true;
+            } else if (++spins > (1u << 22)) {
+                atomicOr(err, 2);
+                leave = true;
+            } else {
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        if (leave) break;
+    }
+}
+
+hipError_t launch_refine_queue(const CallDev& call, const sbr_candidate* uniq, int64_t U_max,
+                               const int32_t* n_dev, const RefineQueue& Q, int blocks,
+                               RefineOut* out, int32_t* err, hipStream_t s)
+{
+    if (U_max <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_queue_init, dim3((unsigned)((U_max + 255) / 256)), dim3(256), 0, s, call,
+                       uniq, U_max, n_dev, Q, out, err);
+    hipLaunchKernelGGL(k_refine_queue, dim3((unsigned)std::max(blocks, 1)), dim3(kQueueBlock), 0, s,
+                       call, uniq, U_max, n_dev, Q, out, err);
+    return hipGetLastError();
+}
+
 hipError_t launch_refine(const CallDev& call, const LdsPlan& L, const LdsPlan& L3,
                          const SceneDev& s0, const sbr_candidate* uniq, int64_t U,
                          const int32_t* n_dev, int depth, RefineOut* out, PathGeom* geom,
@@ -650,7 +895,7 @@ __global__ __launch_bounds__(256) void k_solve(CallDev call, LdsPlan L, SceneDev
                                                const int32_t* __restrict__ n_dev,
                                                sbr_path* __restrict__ paths,
                                                int32_t* __restrict__ keep,
-                                               int32_t* __restrict__ err)
+                                               int32_t* __restrict__ err, int replay)
 {
     if (LDS) stage_scene(s0, L);
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -692,9 +937,11 @@ __global__ __launch_bounds__(256) void k_solve(CallDev call, LdsPlan L, SceneDev
     const RefineOut R = rf[p];
     const d3 axis = ld3(R.axis);
     // The refinement stored the geometry of its final winning sub-ray in
-    // geom[p]; without iterations the launch ray is replayed into it.
+    // geom[p]; without iterations, or when the refinement stored none
+    // (replay), the final axis is traced into it (the same arithmetic as the
+    // winning sub-ray's trace, so the same geometry).
     PathGeom* gm = geom + p;
-    if (lane == 0 && R.iters == 0) {
+    if (lane == 0 && (R.iters == 0 || replay)) {
         for (int j = 0; j < SBR_MAX_ORDER; ++j) {
             gm->pts[j] = mk(0.0, 0.0, 0.0);
             gm->din[j] = mk(0.0, 0.0, 0.0);
@@ -764,17 +1011,17 @@ __global__ __launch_bounds__(256) void k_solve(CallDev call, LdsPlan L, SceneDev
 hipError_t launch_solve(const CallDev& call, const LdsPlan& L, const SceneDev& s0,
                         const sbr_candidate* uniq, const RefineOut* rf, PathGeom* geom,
                         int64_t U, const int32_t* n_dev, sbr_path* paths, int32_t* keep,
-                        int32_t* err, hipStream_t s)
+                        int32_t* err, hipStream_t s, bool replay)
 {
     if (U <= 0) return hipSuccess;
     int64_t threads = U * 16;
     dim3 grid((unsigned)((threads + L.block - 1) / L.block));
     if (L.bytes > 0)
         hipLaunchKernelGGL(k_solve<true>, grid, dim3(L.block), L.bytes, s, call, L, s0, uniq, rf,
-                           geom, U, n_dev, paths, keep, err);
+                           geom, U, n_dev, paths, keep, err, replay ? 1 : 0);
     else
         hipLaunchKernelGGL(k_solve<false>, grid, dim3(L.block), 0, s, call, L, s0, uniq, rf, geom,
-                           U, n_dev, paths, keep, err);
+                           U, n_dev, paths, keep, err, replay ? 1 : 0);
     return hipGetLastError();
 }
 

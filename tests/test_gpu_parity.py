@@ -381,18 +381,22 @@ def _trace_with_env(env, cfg, **prm):
 @pytest.mark.parametrize("prm", [dict(iterations=5, subrays=7), dict(iterations=4, subrays=6),
                                  dict(iterations=9, subrays=7, target_err_deg=0.01),
                                  dict(iterations=7, subrays=6, target_err_deg=0.003),
-                                 dict(iterations=1, subrays=7), dict(iterations=2, subrays=6)])
+                                 dict(iterations=1, subrays=7), dict(iterations=2, subrays=6),
+                                 dict(iterations=0, subrays=7),
+                                 dict(iterations=0, subrays=6, target_err_deg=0.5)])
 def test_refine_lookahead_matches_single_step(gpu, orc, prm):
     """The three-iteration (512 lanes per path) and two-iteration (64 lanes)
-    lookahead kernels and the one-iteration kernel (8 lanes per path) give
-    byte-identical paths, and all match the oracle."""
+    lookahead kernels, the one-iteration kernel (8 lanes per path) and the
+    persistent work-queue refinement (depth 0) give byte-identical paths, and
+    all match the oracle."""
     cfg = scenes.manhattan_config(2, n_rx=24)
     full = dict(cfg["params"], division_n=80, **prm)
     a = _trace_with_env({"SBR_LOOKAHEAD_PATHS": "0"}, cfg, **full)
     b = _trace_with_env({"SBR_LOOKAHEAD_PATHS": "100000", "SBR_LOOKAHEAD_DEPTH": "2"}, cfg, **full)
     c = _trace_with_env({"SBR_LOOKAHEAD_PATHS": "100000", "SBR_LOOKAHEAD_DEPTH": "3",
                          "SBR_LOOKAHEAD3_PATHS": "100000"}, cfg, **full)
-    assert a.tobytes() == b.tobytes() == c.tobytes()
+    q = _trace_with_env({"SBR_LOOKAHEAD_DEPTH": "0"}, cfg, **full)
+    assert a.tobytes() == b.tobytes() == c.tobytes() == q.tobytes()
     o = orc.run(cfg["scene"], cfg["tx"], cfg["rx"], **full)["paths"]
     _compare_paths(a, o)
 
@@ -487,6 +491,44 @@ def test_batch_equals_individual_traces(gpu):
     assert got.tobytes() == ref.tobytes()
 
 
+def _mixed_batch(seed):
+    """A batch whose jobs differ in iteration count, sub-rays and target, so
+    that paths leave the refinement queue at different iterations."""
+    b = scenes.batch_config(seed, n_scenes=3, n_pairs=40, tri_min=100, tri_max=3000,
+                            n_range=(40, 90), order_range=(2, 6), iterations=4)
+    rng = np.random.default_rng(seed + 77)
+    for j in b["jobs"]:
+        j["iterations"] = int(rng.integers(0, 12))
+        j["subrays"] = int(rng.choice([6, 7]))
+        j["target_err_deg"] = float(rng.choice([0.0, 0.0, 0.05, 0.005]))
+    return b
+
+
+@pytest.mark.parametrize("seed", [11, 12])
+def test_batch_queue_mixed_iterations(gpu, seed):
+    """Jobs of one batch with their own iteration counts (0 to 11), sub-ray
+    counts and targets share the persistent refinement queue (depth 0): every
+    job's paths are byte for byte those of its own single call with the
+    lookahead kernels, and of the batch and the single calls refined the
+    other way round."""
+    b = _mixed_batch(seed)
+    ref = _individual(gpu, b)
+    scs = [gpu.scene(s) for s in b["scenes"]]
+    base = gpu.tuning()
+    try:
+        got_la, _ = gpu.trace_batch(scs, b["jobs"], b["rx"])
+        gpu.set_tuning(**dict(base, lookahead_depth=0))
+        got, _ = gpu.trace_batch(scs, b["jobs"], b["rx"])
+        ref_q = _individual(gpu, b)
+    finally:
+        gpu.set_tuning(**base)
+        for s in scs:
+            s.close()
+    assert len(ref) > 15
+    assert got.tobytes() == ref.tobytes() == ref_q.tobytes() == got_la.tobytes()
+    assert len(np.unique(got["iters_used"])) > 2
+
+
 def test_batch_job_matches_oracle(gpu, orc):
     b = _small_batch(5)
     scs = [gpu.scene(s) for s in b["scenes"]]
@@ -538,7 +580,8 @@ def test_tuning_roundtrip_and_invariance(gpu):
                   dict(lds_budget=65536, stack_depth=8, trace_block=128),
                   dict(lds_budget=24 * 4 * 256, stack_depth=24),
                   dict(lookahead_max_paths=0, trace_chunk=64), dict(rx_tree_min=1),
-                  dict(lookahead_depth=2), dict(lookahead_depth=1), dict(ray_order=0),
+                  dict(lookahead_depth=2), dict(lookahead_depth=1), dict(lookahead_depth=0),
+                  dict(ray_order=0),
                   dict(ray_order=0, trace_chunk=2, lds_budget=24 * 4 * 256)):
             gpu.set_tuning(**dict(base, **t))
             assert gpu.tuning()["trace_chunk"] == dict(base, **t)["trace_chunk"]
@@ -550,6 +593,8 @@ def test_tuning_roundtrip_and_invariance(gpu):
             gpu.set_tuning(rx_tree_min=0)
         with pytest.raises(sbr.SbrError):
             gpu.set_tuning(lookahead_depth=4)
+        with pytest.raises(sbr.SbrError):
+            gpu.set_tuning(lookahead_depth=-1)
         with pytest.raises(sbr.SbrError):
             gpu.set_tuning(ray_order=2)
     finally:
