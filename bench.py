@@ -124,6 +124,16 @@ def trace_roofline(counts, n_rays, kernel_ms, workload):
                 "frac": round(traffic / sec / 1e9 / HBM_PEAK_GBS, 5) if traffic else None},
         "bytes_touched_on_chip_gbs": round(touched / sec / 1e9, 1),
         "valu_busy": mc.get("valu_busy"), "valu_lane_util": mc.get("valu_util"),
+        # share of the wave's lanes busy in the traversal's node and triangle
+        # loops and the segment loop (instrumented copy of the kernel)
+        "node_loop_lanes": round(counts["nodes"] / (64 * counts["wave_node_steps"]), 4)
+        if counts.get("wave_node_steps") else None,
+        "tri_loop_lanes": round(counts["tris"] / (64 * counts["wave_tri_steps"]), 4)
+        if counts.get("wave_tri_steps") else None,
+        "segment_loop_lanes": round(counts["segments"] / (64 * counts["wave_seg_steps"]), 4)
+        if counts.get("wave_seg_steps") else None,
+        "wave_steps": {k: counts.get(k) for k in ("wave_node_steps", "wave_tri_steps",
+                                                   "wave_seg_steps", "wave_rx_steps")},
     }
 
 

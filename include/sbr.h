@@ -131,10 +131,17 @@ typedef struct {
     int64_t lds_bytes, lds_nodes, lds_tris, lds_max;
 } sbr_trace_stats;
 
-/* BVH build options; NULL means defaults (leaf size 4, 16 SAH bins). */
+/* BVH build options; NULL means defaults (leaf size 4, 32 SAH bins, no
+ * split references).  With split_pct > 0 a triangle whose box is large next
+ * to the scene's median triangle box may enter the hierarchy as several
+ * references, each bounding the part of the triangle in one cell of a
+ * midpoint subdivision of its box, up to split_pct percent extra references
+ * in all (largest boxes first).  The hierarchy only decides which nodes a ray
+ * visits: paths do not depend on these options. */
 typedef struct {
     int32_t max_leaf_size; /* 1..16 */
     int32_t sah_bins;      /* 4..64 */
+    int32_t split_pct;     /* 0..400; 0: one reference per triangle */
 } sbr_bvh_params;
 
 /* Launch tuning of a context (the results never depend on it).  The trace
@@ -400,10 +407,16 @@ sbr_status sbr_diff_candidates(sbr_scene* scene, const double tx[3], const doubl
 /* Work counts of the trace stage of sbr_trace with the same arguments, from
  * an instrumented copy of the trace kernel: counts[0] segments traced
  * (ray-bounces), counts[1] BVH4 nodes visited (128 B each), counts[2]
- * ray-triangle tests (80 B triangle records), counts[3] reception events.
- * They define the algorithmic bytes of the trace kernel for its roofline. */
+ * ray-triangle tests, counts[3] reception events, counts[4] triangle tests
+ * run (not skipped as lying on the face the segment leaves), counts[5],
+ * counts[6], counts[7] and counts[8] the passes of the wave-wide node loop,
+ * triangle loop, segment loop and receiver loops (one per wave and pass in
+ * which any lane visits a node, tests a triangle, traces a segment, tests a
+ * receiver or receiver-tree node), so that counts[1] / (64 counts[5]) is the
+ * share of lanes busy in the node loop; counts[9] is 0.  counts[0..3]
+ * define the algorithmic work of the trace kernel for its roofline. */
 sbr_status sbr_trace_counters(sbr_scene* scene, const double tx[3], const double* rx,
-                              int32_t n_rx, const sbr_trace_params* params, int64_t counts[4]);
+                              int32_t n_rx, const sbr_trace_params* params, int64_t counts[10]);
 
 const char* sbr_status_string(sbr_status status);
 /* Message of the last failing call on ctx (empty if none); valid until the

@@ -70,6 +70,10 @@ struct Counters {
 // held until the process ends).  Host code never passes `scratch` itself to a
 // kernel or copy: the device address comes from hipGetSymbolAddress, taken
 // once per device (noalloc_scratch_ptr).
+// BVH defaults when sbr_bvh_build gets no parameters.
+constexpr int kDefaultSahBins = 32;
+constexpr int kDefaultSplitPct = 0;
+
 constexpr size_t kNoAllocBytes = size_t(24) << 20;
 constexpr int32_t kNoAllocMaxRx = 4096;
 static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
@@ -178,6 +182,7 @@ struct sbr_scene {
     sbr_context* ctx = nullptr;
     uint64_t id = 0;  // unique per upload (keys captured graphs)
     int64_t T = 0;
+    int64_t R = 0;  // triangle records in leaf order (references; >= T)
     int32_t F = 0, M = 0;
     std::vector<double> tri_v;  // [T][9]
     std::vector<int32_t> face, mat;
@@ -334,7 +339,7 @@ SceneDev scene_dev(const sbr_scene* s)
     S.fstart = s->fstart.as<const int32_t>();
     S.ftris = s->ftris.as<const int32_t>();
     S.eps = s->d_eps.as<const double>();
-    S.n_tri = (int32_t)s->T;
+    S.n_tri = (int32_t)s->R;
     S.n_face = s->F;
     S.n_node = (int32_t)s->n_nodes;
     S.t_eps = s->t_eps;
@@ -367,8 +372,8 @@ int env_int(const char* name, int dflt, int lo, int hi)
 LdsPlan plan_la3(const sbr_scene* s)
 {
     const sbr_context* c = s->ctx;
-    LdsPlan L = make_lds_plan(s->n_nodes, s->T, 512, 16, c->lds_max - 1024);
-    if (!c->la3_lds || L.n_tris != s->T || L.depth != 16) {
+    LdsPlan L = make_lds_plan(s->n_nodes, s->R, 512, 16, c->lds_max - 1024);
+    if (!c->la3_lds || L.n_tris != s->R || L.depth != 16) {
         L = LdsPlan{};
         L.block = 512;
     }
@@ -383,7 +388,7 @@ LdsPlan plan_for(const sbr_scene* s, int block)
         L.block = 256;
         return L;
     }
-    return make_lds_plan(s->n_nodes, s->T, block, c->stack_depth, c->lds_budget);
+    return make_lds_plan(s->n_nodes, s->R, block, c->stack_depth, c->lds_budget);
 }
 
 // theta_launch = theta_0 / (sqrt(3) n), eq. (4); the equidistant grids use
@@ -709,7 +714,7 @@ sbr_status run_front(sbr_context* c, Call& call, bool need_unique, int32_t* out_
         HIPCHK(c, ensure(c->cand, sizeof(sbr_candidate) * (size_t)cap));
         if (pass > 0)  // upload_call zeroed them for the first pass
             HIPCHK(c, hipMemsetAsync(c->counters.p, 0, sizeof(Counters), st));
-        if (tallies) HIPCHK(c, hipMemsetAsync(tallies, 0, 4 * sizeof(unsigned long long), st));
+        if (tallies) HIPCHK(c, hipMemsetAsync(tallies, 0, 10 * sizeof(unsigned long long), st));
         HIPCHK(c, hipEventRecord(c->ev[7], st));
         HIPCHK(c, launch_trace(call.dev, call.lp, call.s0, trace_blocks(c, call), &dc->queue,
                                c->cand.as<sbr_candidate>(), cap, &dc->cand, out_tri, out_t,
@@ -1260,17 +1265,21 @@ sbr_status sbr_bvh_build(sbr_scene* s, const sbr_bvh_params* bp)
     if (!s || !s->ctx) return SBR_E_NO_SCENE;
     sbr_context* c = s->ctx;
     c->err.clear();
-    int leaf = bp ? bp->max_leaf_size : 4, bins = bp ? bp->sah_bins : 16;
-    if (leaf < 1 || leaf > 16 || bins < 4 || bins > 64)
+    int leaf = bp ? bp->max_leaf_size : 4, bins = bp ? bp->sah_bins : kDefaultSahBins;
+    int split = bp ? bp->split_pct : kDefaultSplitPct;
+    if (leaf < 1 || leaf > 16 || bins < 4 || bins > 64 || split < 0 || split > 400)
         return fail(c, SBR_E_INVALID_ARG, "bvh params out of range");
     std::vector<Bvh4Node> nodes;
     std::vector<int32_t> perm;
-    s->bvh_depth = build_bvh(s->tri_v.data(), s->T, leaf, bins, c->lds_budget > 0, nodes, perm);
+    s->bvh_depth =
+        build_bvh(s->tri_v.data(), s->T, leaf, bins, split, c->lds_budget > 0, nodes, perm);
     s->n_nodes = (int64_t)nodes.size();
     if (3 * s->bvh_depth >= kTraceStack) return fail(c, SBR_E_INTERNAL, "BVH too deep");
-    std::vector<TriD> tris((size_t)s->T);
-    std::vector<int32_t> pos_of((size_t)s->T);
-    for (int64_t q = 0; q < s->T; ++q) {
+    // triangle records in leaf order, one per reference
+    s->R = (int64_t)perm.size();
+    std::vector<TriD> tris((size_t)s->R);
+    std::vector<int32_t> pos_of((size_t)s->T, -1);
+    for (int64_t q = 0; q < s->R; ++q) {
         int32_t t = perm[q];
         const double* V = &s->tri_v[9 * (size_t)t];
         TriD& d = tris[q];
@@ -1279,7 +1288,7 @@ sbr_status sbr_bvh_build(sbr_scene* s, const sbr_bvh_params* bp)
         d.e2x = V[6] - V[0]; d.e2y = V[7] - V[1]; d.e2z = V[8] - V[2];
         d.face = s->face[t];
         d.orig = t;
-        pos_of[t] = (int32_t)q;
+        if (pos_of[t] < 0) pos_of[t] = (int32_t)q;
     }
     // CSR of triangles per face (positions in leaf order, input order within a face)
     std::vector<int32_t> fstart((size_t)s->F + 1, 0), ftris((size_t)s->T);
@@ -1437,7 +1446,7 @@ sbr_status sbr_candidates(sbr_scene* s, const double tx[3], const double* rx, in
 }
 
 sbr_status sbr_trace_counters(sbr_scene* s, const double tx[3], const double* rx, int32_t n_rx,
-                              const sbr_trace_params* p, int64_t counts[4])
+                              const sbr_trace_params* p, int64_t counts[10])
 {
     int64_t dummy;
     sbr_status r = check_trace_inputs(s, tx, rx, n_rx, p, 0, nullptr, &dummy);
@@ -1445,15 +1454,15 @@ sbr_status sbr_trace_counters(sbr_scene* s, const double tx[3], const double* rx
     sbr_context* c = s->ctx;
     if (!counts) return fail(c, SBR_E_INVALID_ARG, "counts is NULL");
     HIPCHK(c, use_device(c->device));
-    HIPCHK(c, ensure(c->tally, 4 * sizeof(unsigned long long)));
+    HIPCHK(c, ensure(c->tally, 10 * sizeof(unsigned long long)));
     Call call;
     r = single_call(s, call, tx, rx, n_rx, p, 0, -1);
     if (r) return r;
     r = run_front(c, call, false, nullptr, nullptr, c->tally.as<unsigned long long>());
     if (r) return r;
-    unsigned long long h[4];
+    unsigned long long h[10];
     HIPCHK(c, hipMemcpy(h, c->tally.p, sizeof h, hipMemcpyDeviceToHost));
-    for (int i = 0; i < 4; ++i) counts[i] = (int64_t)h[i];
+    for (int i = 0; i < 10; ++i) counts[i] = (int64_t)h[i];
     return SBR_OK;
 }
 

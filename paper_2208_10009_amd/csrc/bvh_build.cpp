@@ -9,6 +9,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <queue>
 #include <vector>
 
 #include "internal.h"
@@ -203,6 +204,146 @@ struct Builder {
     }
 };
 
+// ---------------------------------------------------------------------------
+// Reference splitting.  A triangle whose box is large next to the scene's
+// typical triangle enters the hierarchy as several references, each with the
+// box of the part of the triangle inside one cell of a recursive midpoint
+// subdivision of its box (largest boxes first, until the budget of extra
+// references is spent or every box is below twice the median triangle box
+// area).  Every reference names the same triangle record, so traversal
+// results do not change; only which nodes a ray visits does.
+// Conservativeness: a cell's part of the triangle is clipped (Sutherland-
+// Hodgman) against the cell enlarged by pad = 1e-12 (max |vertex coordinate|
+// + 1) on every side, and its box is widened by pad again.  Vertex
+// classification against a plane is exact; a crossing point has the plane's
+// coordinate exactly and the others within a few ulps (far below pad), so
+// every point of the exact triangle inside the exact cell lies in the padded
+// box.  The boxes are then rounded outward to FP32 like any other.
+struct P3 {
+    double x[3];
+};
+
+void clip_plane(const std::vector<P3>& in, int ax, double m, bool keep_le, std::vector<P3>& out)
+{
+    out.clear();
+    const size_t n = in.size();
+    for (size_t i = 0; i < n; ++i) {
+        const P3& P = in[i];
+        const P3& Q = in[(i + 1) % n];
+        const bool inP = keep_le ? P.x[ax] <= m : P.x[ax] >= m;
+        const bool inQ = keep_le ? Q.x[ax] <= m : Q.x[ax] >= m;
+        if (inP) out.push_back(P);
+        if (inP != inQ) {
+            const double t = (m - P.x[ax]) / (Q.x[ax] - P.x[ax]);
+            P3 X;
+            for (int k = 0; k < 3; ++k) X.x[k] = P.x[k] + t * (Q.x[k] - P.x[k]);
+            X.x[ax] = m;
+            out.push_back(X);
+        }
+    }
+}
+
+// Box of triangle t's part inside cell (false: the triangle misses the cell).
+bool clipped_box(const double* V, const Box& tbox, const Box& cell, Box* out)
+{
+    double mx = 0.0;
+    for (int k = 0; k < 9; ++k) mx = std::max(mx, fabs(V[k]));
+    const double pad = 1e-12 * (mx + 1.0);
+    std::vector<P3> a(3), b;
+    for (int v = 0; v < 3; ++v)
+        for (int k = 0; k < 3; ++k) a[v].x[k] = V[3 * v + k];
+    for (int ax = 0; ax < 3 && !a.empty(); ++ax) {
+        clip_plane(a, ax, cell.lo[ax] - pad, false, b);
+        clip_plane(b, ax, cell.hi[ax] + pad, true, a);
+    }
+    if (a.empty()) return false;
+    Box r;
+    r.reset();
+    for (const P3& p : a) r.grow(p.x);
+    for (int k = 0; k < 3; ++k) {
+        r.lo[k] = std::max(r.lo[k] - pad, tbox.lo[k]);
+        r.hi[k] = std::min(r.hi[k] + pad, tbox.hi[k]);
+    }
+    *out = r;
+    return true;
+}
+
+struct SplitRef {
+    int32_t tri;
+    Box cell, box;
+    int depth;
+};
+
+// References of all triangles: rtri[r] (the triangle), rbox[r] (its box),
+// rsplit[r] (whether the box is a clipped part).  Unsplit triangles keep
+// their own box.
+void make_refs(const double* tri_v, int64_t T, const std::vector<Box>& tb, int split_pct,
+               std::vector<int32_t>& rtri, std::vector<Box>& rbox, std::vector<char>& rsplit)
+{
+    std::vector<SplitRef> refs((size_t)T);
+    std::vector<double> areas((size_t)T);
+    for (int64_t t = 0; t < T; ++t) {
+        refs[t] = SplitRef{(int32_t)t, tb[t], tb[t], 0};
+        areas[t] = tb[t].area();
+    }
+    const int64_t budget = split_pct > 0 ? T * (int64_t)split_pct / 100 : 0;
+    if (budget > 0 && T > 0) {
+        std::vector<double> sorted = areas;
+        std::nth_element(sorted.begin(), sorted.begin() + T / 2, sorted.end());
+        const double thresh = 2.0 * sorted[T / 2];
+        typedef std::pair<double, int32_t> Item;
+        std::priority_queue<Item> heap;
+        for (int64_t t = 0; t < T; ++t)
+            if (areas[t] > thresh) heap.push(Item(areas[t], (int32_t)t));
+        int64_t extra = 0;
+        while (!heap.empty() && extra < budget) {
+            const int32_t r = heap.top().second;
+            heap.pop();
+            SplitRef& R = refs[r];
+            const Box bx = R.box;
+            int ax = 0;
+            for (int k = 1; k < 3; ++k)
+                if (bx.hi[k] - bx.lo[k] > bx.hi[ax] - bx.lo[ax]) ax = k;
+            const double m = 0.5 * (bx.lo[ax] + bx.hi[ax]);
+            if (!(m > bx.lo[ax] && m < bx.hi[ax]) || R.depth >= 24) continue;
+            Box cl = R.cell, cr = R.cell;
+            cl.hi[ax] = m;
+            cr.lo[ax] = m;
+            const double* V = tri_v + 9 * (size_t)R.tri;
+            Box bl, br;
+            const bool hl = clipped_box(V, tb[R.tri], cl, &bl);
+            const bool hr = clipped_box(V, tb[R.tri], cr, &br);
+            if (hl && hr) {
+                const SplitRef right{R.tri, cr, br, R.depth + 1};
+                R.cell = cl;
+                R.box = bl;
+                R.depth += 1;
+                refs.push_back(right);
+                extra += 1;
+                const int32_t nr = (int32_t)refs.size() - 1;
+                if (refs[r].box.area() > thresh) heap.push(Item(refs[r].box.area(), r));
+                if (refs[nr].box.area() > thresh) heap.push(Item(refs[nr].box.area(), nr));
+            } else if (hl || hr) {
+                // the triangle lies in one half: a tighter cell, same reference
+                R.cell = hl ? cl : cr;
+                const Box nb = hl ? bl : br;
+                const bool shrank = nb.area() < R.box.area();
+                R.box = nb;
+                R.depth += 1;
+                if (shrank && R.box.area() > thresh) heap.push(Item(R.box.area(), r));
+            }
+        }
+    }
+    rtri.resize(refs.size());
+    rbox.resize(refs.size());
+    rsplit.resize(refs.size());
+    for (size_t r = 0; r < refs.size(); ++r) {
+        rtri[r] = refs[r].tri;
+        rbox[r] = refs[r].box;
+        rsplit[r] = refs[r].depth > 0;
+    }
+}
+
 }  // namespace
 
 namespace {
@@ -267,22 +408,32 @@ int collapse(const std::vector<BvhNode>& n2, int32_t r, std::vector<Bvh4Node>& n
 
 }  // namespace
 
-int build_bvh(const double* tri_v, int64_t T, int max_leaf, int bins, bool bfs,
+int build_bvh(const double* tri_v, int64_t T0, int max_leaf, int bins, int split_pct, bool bfs,
               std::vector<Bvh4Node>& nodes, std::vector<int32_t>& perm)
 {
     Builder B;
     B.tv = tri_v;
     B.max_leaf = max_leaf;
     B.bins = bins;
-    B.tb.resize((size_t)T);
+    std::vector<Box> tbox((size_t)T0);
+    for (int64_t t = 0; t < T0; ++t) {
+        tbox[t].reset();
+        for (int v = 0; v < 3; ++v) tbox[t].grow(tri_v + 9 * t + 3 * v);
+    }
+    // the hierarchy is built over references (several per split triangle)
+    std::vector<int32_t> rtri;
+    std::vector<char> rsplit;
+    make_refs(tri_v, T0, tbox, split_pct, rtri, B.tb, rsplit);
+    const int64_t T = (int64_t)rtri.size();
     B.cen.resize((size_t)T * 3);
     B.idx.resize((size_t)T);
-    for (int64_t t = 0; t < T; ++t) {
-        B.tb[t].reset();
-        for (int v = 0; v < 3; ++v) B.tb[t].grow(tri_v + 9 * t + 3 * v);
+    for (int64_t r = 0; r < T; ++r) {
+        const int64_t t = rtri[r];
         for (int i = 0; i < 3; ++i)
-            B.cen[3 * t + i] = (tri_v[9 * t + i] + tri_v[9 * t + 3 + i] + tri_v[9 * t + 6 + i]) / 3.0;
-        B.idx[t] = (int32_t)t;
+            B.cen[3 * r + i] =
+                rsplit[r] ? 0.5 * (B.tb[r].lo[i] + B.tb[r].hi[i])
+                          : (tri_v[9 * t + i] + tri_v[9 * t + 3 + i] + tri_v[9 * t + 6 + i]) / 3.0;
+        B.idx[r] = (int32_t)r;
     }
     // The root is always an inner node so that traversal starts uniformly.
     B.nodes.push_back(BvhNode{});
@@ -311,7 +462,8 @@ int build_bvh(const double* tri_v, int64_t T, int max_leaf, int bins, bool bfs,
     std::vector<Bvh4Node> n4;
     n4.push_back(Bvh4Node{});
     const int depth = collapse(B.nodes, 0, n4, 0);
-    perm.swap(B.idx);
+    perm.resize((size_t)T);
+    for (int64_t q = 0; q < T; ++q) perm[q] = rtri[B.idx[q]];
     if (!bfs) {
         nodes.swap(n4);
         return depth;

@@ -44,11 +44,14 @@ static_assert(sizeof(Bvh4Node) == 128, "Bvh4Node layout");
 constexpr int kMaxBvhDepth = 48;  // builder cap on the BVH2 depth
 constexpr int kTraceStack = 96;   // traversal stack; a BVH4 level pushes at most 3
 
-// Host-side BVH build (binned SAH BVH2, collapsed to BVH4).  tri_v is [T][9]
-// FP64 vertices.  Nodes are numbered depth-first, or breadth-first with bfs
-// (so that the top levels form a prefix for LDS staging).  perm receives the
-// leaf order (input indices); returns the BVH4 depth.
-int build_bvh(const double* tri_v, int64_t T, int max_leaf, int bins, bool bfs,
+// Host-side BVH build (binned SAH BVH2, collapsed to BVH4) over triangle
+// references: large triangles may be split into up to T split_pct / 100
+// extra references with clipped boxes.  tri_v is [T][9] FP64 vertices.
+// Nodes are numbered depth-first, or breadth-first with bfs (so that the top
+// levels form a prefix for LDS staging).  perm receives the leaf order (the
+// input index of each reference's triangle; a split triangle appears once
+// per reference); returns the BVH4 depth.
+int build_bvh(const double* tri_v, int64_t T, int max_leaf, int bins, int split_pct, bool bfs,
               std::vector<Bvh4Node>& nodes, std::vector<int32_t>& perm);
 
 // Device view of a scene.

@@ -239,7 +239,7 @@ __global__ __launch_bounds__(256) void k_trace(CallDev call, LdsPlan L, SceneDev
     if (LDS) stage_scene(s0, L);
     const int lane = threadIdx.x & 63;
     const uint64_t below = (1ull << lane) - 1ull;
-    Tally tl{0u, 0u};
+    Tally tl{0u, 0u, 0u, 0u, 0u, 0u, 0u};
     uint32_t segs = 0, events = 0;
     JobDev J{};
     SceneDev S = s0;
@@ -276,6 +276,7 @@ __global__ __launch_bounds__(256) void k_trace(CallDev call, LdsPlan L, SceneDev
             continue;
         }
         if (R.r < 0) continue;
+        if (COUNT && first_active_lane()) tl.wave_segs += 1;
         // one segment: closest hit, excluding the face just reflected on
         const int K = J.K;
         HitRec h;
@@ -292,18 +293,21 @@ __global__ __launch_bounds__(256) void k_trace(CallDev call, LdsPlan L, SceneDev
             // FP32 pre-test of every receiver (wave-uniform, scalar loads),
             // the FP64 test for the few it lets through; skipped when no
             // busy lane's segment can reach the receivers' box
-            if (__ballot(rx_box_may(g32, box)) != 0)
+            if (__ballot(rx_box_may(g32, box)) != 0) {
+                if (COUNT && first_active_lane()) tl.wave_rx += (uint32_t)J.n_rx;
                 for (int x = 0; x < J.n_rx; ++x) {
                     const int32_t gx = J.rx_first + x;
                     if (rx_may_capture32(g32, cld4(call.rx32 + gx)))
                         receive(J, call.rx, R, t, gx, cand, cap, ccount, &events, COUNT);
                 }
+            }
         } else if (rx_box_may(g32, box)) {
             // stackless preorder walk of the job's receiver tree (lanes whose
             // segment cannot reach the receivers' box skip it)
             int32_t nd = J.rx_root;
             const int32_t end = call.rx_nodes[nd].skip;
             while (nd != end) {
+                if (COUNT && first_active_lane()) tl.wave_rx += 1;
                 const double2* q = (const double2*)(call.rx_nodes + nd);
                 const double2 c01 = gld(q), c2r = gld(q + 1), m = gld(q + 2);
                 RxNode N;
@@ -322,6 +326,7 @@ __global__ __launch_bounds__(256) void k_trace(CallDev call, LdsPlan L, SceneDev
                     nd = nd + 1;
                 } else {
                     for (int q = 0; q < N.count; ++q) {
+                        if (COUNT && first_active_lane()) tl.wave_rx += 1;
                         const int32_t gx = gld(call.rx_perm + N.first + q);
                         if (rx_may_capture32(g32, gld(call.rx32 + gx)))
                             receive(J, call.rx, R, t, gx, cand, cap, ccount, &events, COUNT);
@@ -357,6 +362,11 @@ __global__ __launch_bounds__(256) void k_trace(CallDev call, LdsPlan L, SceneDev
         atomicAdd(&tallies[1], (unsigned long long)tl.nodes);
         atomicAdd(&tallies[2], (unsigned long long)tl.tris);
         atomicAdd(&tallies[3], (unsigned long long)events);
+        atomicAdd(&tallies[4], (unsigned long long)tl.fp64_tris);
+        atomicAdd(&tallies[5], (unsigned long long)tl.wave_nodes);
+        atomicAdd(&tallies[6], (unsigned long long)tl.wave_tris);
+        atomicAdd(&tallies[7], (unsigned long long)tl.wave_segs);
+        atomicAdd(&tallies[8], (unsigned long long)tl.wave_rx);
     }
 }
 

@@ -136,9 +136,21 @@ struct HitRec {
     int32_t pos, face, orig;
 };
 
+// Work counts of the instrumented trace kernel: node visits and triangle
+// tests per lane, the tests not skipped as the face just left, and the steps
+// of the wave (loop passes in which at least one lane visits a node, tests a
+// triangle, traces a segment or tests receivers; 64 lanes per wave, so nodes
+// / (64 wave_nodes) is the share of lanes busy in the node loop).
 struct Tally {
-    uint32_t nodes, tris;
+    uint32_t nodes, tris, fp64_tris, wave_nodes, wave_tris, wave_segs, wave_rx;
 };
+
+// Whether this lane is the lowest active lane of its wave (counts once per
+// wave and pass).
+__device__ static inline bool first_active_lane()
+{
+    return (int)__lane_id() == __builtin_ctzll(__ballot(1));
+}
 
 constexpr int kShortStack = 16;  // LDS stack entries per lane without an LDS plan
 
@@ -215,7 +227,10 @@ __device__ static int32_t traverse(const SceneDev& S, const LdsPlan& L, d3 o, d3
             q4 = gld(np + 4); q5 = gld(np + 5); q6 = gld(np + 6); q7 = gld(np + 7);
         }
         const int4 cidx = __builtin_bit_cast(int4, q6), ccnt = __builtin_bit_cast(int4, q7);
-        if (COUNT) tally->nodes += 1;
+        if (COUNT) {
+            tally->nodes += 1;
+            if (first_active_lane()) tally->wave_nodes += 1;
+        }
         // child k: lo (q0[k], q1[k], q2[k]), hi (q3[k], q4[k], q5[k])
         float tn[4];
         bool hit[4];
@@ -248,8 +263,12 @@ __device__ static int32_t traverse(const SceneDev& S, const LdsPlan& L, d3 o, d3
             const int32_t lc = k == 0 ? cnt[0] : k == 1 ? cnt[1] : k == 2 ? cnt[2] : cnt[3];
             for (int32_t i = lf; i < lf + lc; ++i) {
                 TriD T = tri_at<LDS>(S, L, i);
-                if (COUNT) tally->tris += 1;
+                if (COUNT) {
+                    tally->tris += 1;
+                    if (first_active_lane()) tally->wave_tris += 1;
+                }
                 if (T.face == xa || T.face == xb) continue;
+                if (COUNT) tally->fp64_tris += 1;
                 double t;
                 if (!mt_hit(T, o, d, t_lo, t_hi, &t)) continue;
                 if (ANY) {

@@ -84,7 +84,7 @@ class Complex(C.Structure):
 
 
 class BvhParams(C.Structure):
-    _fields_ = [("max_leaf_size", C.c_int32), ("sah_bins", C.c_int32)]
+    _fields_ = [("max_leaf_size", C.c_int32), ("sah_bins", C.c_int32), ("split_pct", C.c_int32)]
 
 
 class TraceStats(C.Structure):
@@ -275,8 +275,9 @@ class Context:
         t = Tuning(**cur)
         self._check(lib().sbr_context_set_tuning(self.h, C.byref(t)))
 
-    def scene(self, scene: dict, max_leaf_size: int = 4, sah_bins: int = 16) -> "Scene":
-        return Scene(self, scene, max_leaf_size, sah_bins)
+    def scene(self, scene: dict, max_leaf_size: int = 4, sah_bins: int = 32,
+              split_pct: int = 0) -> "Scene":
+        return Scene(self, scene, max_leaf_size, sah_bins, split_pct)
 
     def trace_batch(self, scenes, jobs, rx, capacity: int | None = None):
         """sbr_trace_batch.  scenes: list of Scene; jobs: list of dicts with
@@ -320,7 +321,7 @@ class Context:
 class Scene:
     """sbr_scene_upload + sbr_bvh_build of a scene dict (see scenes.py)."""
 
-    def __init__(self, ctx: Context, scene: dict, max_leaf_size=4, sah_bins=16):
+    def __init__(self, ctx: Context, scene: dict, max_leaf_size=4, sah_bins=32, split_pct=0):
         self.ctx = ctx
         xyz = np.ascontiguousarray(scene["xyz"], np.float64).reshape(-1, 3)
         tri = np.ascontiguousarray(scene["tri"], np.int32).reshape(-1, 3)
@@ -333,7 +334,7 @@ class Scene:
                                           len(tri), ce, len(eps), C.byref(h)))
         self.h = h
         ctx.scenes.append(self)
-        bp = BvhParams(max_leaf_size, sah_bins)
+        bp = BvhParams(max_leaf_size, sah_bins, split_pct)
         ctx._check(lib().sbr_bvh_build(self.h, C.byref(bp)))
         self.n_tri = len(tri)
 
@@ -479,14 +480,18 @@ class Scene:
         return ot, oT
 
     def trace_counters(self, tx, rx, **params):
-        """sbr_trace_counters: dict of segments, nodes, tris, events."""
+        """sbr_trace_counters: dict of segments, nodes, tris, events,
+        tris_run, wave_node_steps, wave_tri_steps, wave_seg_steps,
+        wave_rx_steps."""
         txa = np.ascontiguousarray(tx, np.float64).reshape(3)
         rxa = np.ascontiguousarray(rx, np.float64).reshape(-1, 3)
         prm = make_params(**params)
-        out = np.zeros(4, np.int64)
+        out = np.zeros(10, np.int64)
         self.ctx._check(lib().sbr_trace_counters(self.h, _d(txa), _d(rxa), len(rxa), C.byref(prm),
                                                  out.ctypes.data_as(C.POINTER(C.c_int64))))
-        return dict(zip(("segments", "nodes", "tris", "events"), (int(v) for v in out)))
+        return dict(zip(("segments", "nodes", "tris", "events", "tris_run", "wave_node_steps",
+                         "wave_tri_steps", "wave_seg_steps", "wave_rx_steps"),
+                        (int(v) for v in out)))
 
     def close(self):
         if self.h:

@@ -74,6 +74,9 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu\n", offsetof(sbr_path, launch_ray), offsetof(sbr_path, tan_err),
          offsetof(sbr_path, delay_s), offsetof(sbr_path, exact_delay_s),
          offsetof(sbr_path, init_tan_err), offsetof(sbr_candidate, tan_err));
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(sbr_tuning), offsetof(sbr_tuning, lookahead_max_paths),
+         offsetof(sbr_tuning, ray_order), sizeof(sbr_bvh_params),
+         offsetof(sbr_bvh_params, split_pct), sizeof(sbr_job));
   return 0;
 }
 """
@@ -84,12 +87,13 @@ int main(void) {
     exe = os.path.join(d, "probe")
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
     lines = subprocess.check_output([exe], text=True).split("\n")
-    return [int(x) for x in lines[0].split()], [int(x) for x in lines[1].split()]
+    return ([int(x) for x in lines[0].split()], [int(x) for x in lines[1].split()],
+            [int(x) for x in lines[2].split()])
 
 
 def test_binding_layouts_match_header():
     from paper_2208_10009_amd import sbr
-    sizes, offs = _struct_layout_probe()
+    sizes, offs, more = _struct_layout_probe()
     assert sizes[0] == sbr.PATH_DTYPE.itemsize
     assert sizes[1] == sbr.CAND_DTYPE.itemsize
     assert sizes[2] == C.sizeof(sbr.TraceParams)
@@ -102,6 +106,9 @@ def test_binding_layouts_match_header():
     assert offs == [P.fields["launch_ray"][1], P.fields["tan_err"][1], P.fields["delay_s"][1],
                     P.fields["exact_delay_s"][1], P.fields["init_tan_err"][1],
                     K.fields["tan_err"][1]]
+    assert more == [C.sizeof(sbr.Tuning), sbr.Tuning.lookahead_max_paths.offset,
+                    sbr.Tuning.ray_order.offset, C.sizeof(sbr.BvhParams),
+                    sbr.BvhParams.split_pct.offset, C.sizeof(sbr.Job)]
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

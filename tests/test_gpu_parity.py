@@ -415,6 +415,55 @@ def test_refine_three_level_lds_matches_global(gpu, orc, seed, order):
     _compare_paths(a, orc.run(cfg["scene"], cfg["tx"], cfg["rx"], **full)["paths"])
 
 
+def test_bvh_options_do_not_change_paths(gpu, orc):
+    """The hierarchy (leaf size, SAH bins, split references with clipped
+    boxes) only decides which nodes a ray visits: paths and per-ray traces are
+    byte-identical across builds, and match the oracle."""
+    cfg = scenes.manhattan_config(4, n_rx=24)
+    prm = dict(cfg["params"], division_n=90)
+    ref_p = ref_t = None
+    for opt in (dict(), dict(max_leaf_size=1, sah_bins=16), dict(sah_bins=64, split_pct=100),
+                dict(max_leaf_size=8, split_pct=400), dict(split_pct=50)):
+        sc = gpu.scene(cfg["scene"], **opt)
+        try:
+            p, _ = sc.trace(cfg["tx"], cfg["rx"], **prm)
+            tri, t = sc.trace_rays(cfg["tx"], prm["division_n"], prm["max_order"], 0, 20000)
+        finally:
+            sc.close()
+        if ref_p is None:
+            ref_p, ref_t = p, (tri, t)
+            _compare_paths(p, orc.run(cfg["scene"], cfg["tx"], cfg["rx"], **prm)["paths"])
+        else:
+            assert p.tobytes() == ref_p.tobytes(), opt
+            assert np.array_equal(tri, ref_t[0]) and np.array_equal(t, ref_t[1]), opt
+
+
+def test_trace_counters_are_consistent(gpu):
+    """The instrumented trace kernel's counts: a wave pass serves 1 to 64
+    lanes, every segment traces at least the root node, and the counts do not
+    depend on the launch tuning that leaves packets whole."""
+    cfg = scenes.manhattan_config(1, n_rx=32)
+    prm = dict(cfg["params"], division_n=120)
+    sc = gpu.scene(cfg["scene"])
+    try:
+        c = sc.trace_counters(cfg["tx"], cfg["rx"], **prm)
+        base = gpu.tuning()
+        gpu.set_tuning(**dict(base, persist_blocks=37))
+        c2 = sc.trace_counters(cfg["tx"], cfg["rx"], **prm)
+        gpu.set_tuning(**base)
+    finally:
+        sc.close()
+    n_rays = 10 * prm["division_n"] ** 2 + 2
+    assert n_rays <= c["segments"] <= n_rays * (prm["max_order"] + 1)
+    assert c["nodes"] >= c["segments"]
+    for lanes, steps in (("nodes", "wave_node_steps"), ("tris", "wave_tri_steps"),
+                         ("segments", "wave_seg_steps")):
+        assert c[steps] <= c[lanes] <= 64 * c[steps], (lanes, c)
+    assert c["tris_run"] <= c["tris"] and c["wave_rx_steps"] > 0
+    for k in ("segments", "nodes", "tris", "events", "tris_run"):
+        assert c2[k] == c[k], k
+
+
 def test_lds_staged_traversal_matches(gpu, orc):
     """LDS-staged traversal (node prefix, triangles and stack in LDS, or the
     stack alone) gives the same paths as global-memory traversal."""
