@@ -86,8 +86,9 @@ typedef struct {
 
 #define SBR_FLAG_KEEP_INVALID 1u /* keep paths that fail path test 2 (flag INVALID) */
 #define SBR_FLAG_FRESH_GRID 2u   /* recompute the launch directions even when cached */
-#define SBR_FLAG_GRAPH 4u        /* sbr_trace_device: capture the call as a HIP graph and
-                                    replay it on later calls of the same shape */
+#define SBR_FLAG_GRAPH 4u        /* sbr_trace_device, sbr_trace_batch: capture the call as
+                                    a HIP graph and replay it on later calls of the same
+                                    shape */
 
 /* Path flags (sbr_path.flags). */
 #define SBR_PATH_STALLED 1u    /* an iteration found no sub-ray with the same faces  */
@@ -296,9 +297,19 @@ typedef struct {
  * launch over all paths.  Each job's paths are exactly those sbr_trace
  * returns for it alone, with sbr_path.rx numbering the batch's receiver
  * array; the list is sorted by (rx, order, face sequence).  rx [n_rx_total][3]
- * host FP64.  All scenes must belong to ctx and have a BVH.  Errors as for
- * sbr_trace, plus SBR_E_INVALID_ARG for a job whose scene index, receiver
- * slice or parameters are out of range. */
+ * host FP64.  All scenes must belong to ctx and have a BVH.
+ * When every job has SBR_FLAG_GRAPH (none SBR_FLAG_FRESH_GRID, none with
+ * rx_tree_min or more receivers) and the call ends with at most 4096
+ * reception events, its launch sequence is captured as a HIP graph; a later
+ * call with the same scenes, the same jobs apart from their transmitters
+ * and the same receiver count replays it with this call's transmitters and
+ * receivers (the job table and the receivers go through pinned staging, the
+ * paths through a device buffer sized by the capture).  A replay whose counts
+ * exceed the captured sizes (more than 4096 events, or more than twice the
+ * capturing call's unique paths) is redone as a normal call.  Results are
+ * identical either way; with a replay only the count and ms_total fields of
+ * stats are set.  Errors as for sbr_trace, plus SBR_E_INVALID_ARG for a job
+ * whose scene index, receiver slice or parameters are out of range. */
 sbr_status sbr_trace_batch(sbr_context* ctx, sbr_scene* const* scenes, int32_t n_scenes,
                            const sbr_job* jobs, int32_t n_jobs, const double* rx,
                            int32_t n_rx_total, sbr_path* out, int64_t capacity, int64_t* n_out,

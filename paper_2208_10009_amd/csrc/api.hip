@@ -176,6 +176,24 @@ struct sbr_context {
         int32_t* h_rxjob = nullptr;   // pinned [n_rx]
         int32_t h_rxjob_cap = 0;
     } graph;
+    // one captured graph of a sbr_trace_batch call (every job SBR_FLAG_GRAPH)
+    struct BatchGraph {
+        bool valid = false;
+        uint64_t epoch = 0;
+        std::vector<uint64_t> scene_ids;
+        std::vector<sbr_job> jobs;  // the key (tx not compared)
+        int32_t n_rx = 0;
+        int64_t u_cap = 0, n_rays = 0;
+        sbr_tuning tuning{};
+        hipGraphExec_t exec = nullptr;
+        hipStream_t cap_stream = nullptr;
+        // pinned staging read by the graph
+        JobDev* h_jobs = nullptr;
+        SceneDev* h_scenes = nullptr;
+        int32_t* h_rxjob = nullptr;
+        double* h_rx = nullptr;
+        int64_t jobs_cap = 0, scenes_cap = 0, rxjob_cap = 0, rx_cap = 0;
+    } bgraph;
 };
 
 struct sbr_scene {
@@ -208,6 +226,13 @@ void drop_graph(sbr_context* c)
     if (c->graph.exec) (void)hipGraphExecDestroy(c->graph.exec);
     c->graph.exec = nullptr;
     c->graph.valid = false;
+}
+
+void drop_bgraph(sbr_context* c)
+{
+    if (c->bgraph.exec) (void)hipGraphExecDestroy(c->bgraph.exec);
+    c->bgraph.exec = nullptr;
+    c->bgraph.valid = false;
 }
 
 sbr_status fail(sbr_context* c, sbr_status st, const char* fmt, ...)
@@ -1160,6 +1185,12 @@ sbr_status sbr_context_destroy(sbr_context* c)
     if (c->graph.h_job) (void)hipHostFree(c->graph.h_job);
     if (c->graph.h_scene) (void)hipHostFree(c->graph.h_scene);
     if (c->graph.h_rxjob) (void)hipHostFree(c->graph.h_rxjob);
+    drop_bgraph(c);
+    auto& B = c->bgraph;
+    if (B.cap_stream) (void)hipStreamDestroy(B.cap_stream);
+    void* pinned[] = {B.h_jobs, B.h_scenes, B.h_rxjob, B.h_rx};
+    for (void* q : pinned)
+        if (q) (void)hipHostFree(q);
     delete c;
     return SBR_OK;
 }
@@ -1692,6 +1723,239 @@ sbr_status replay_graph(sbr_context* c, sbr_scene* s, const double* tx, int32_t 
     return SBR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Captured sbr_trace_batch calls: every job carries SBR_FLAG_GRAPH (and not
+// SBR_FLAG_FRESH_GRID), no job is large enough for a receiver tree, and the
+// capturing call ended with at most kSmallEvents reception events.  A later
+// call with the same scenes, the same jobs apart from their transmitters and
+// the same number of receivers replays the graph: the job table and the
+// receivers go to pinned staging that the graph copies to the device; the
+// paths land in a device buffer sized by the capture, of which the host
+// copies the ones produced.  Counts beyond the captured sizes are detected
+// from the counters and the call is redone normally.
+// ---------------------------------------------------------------------------
+// Pinned host buffer *p of at least n elements of `elem` bytes.
+sbr_status grow_pinned(sbr_context* c, void** p, int64_t* cap, int64_t n, size_t elem)
+{
+    n = std::max<int64_t>(n, 1);
+    if (*cap >= n) return SBR_OK;
+    if (*p) (void)hipHostFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    HIPCHK(c, hipHostMalloc(p, elem * (size_t)n, 0));
+    *cap = n;
+    return SBR_OK;
+}
+
+// The call of a batch (job table, receiver-job map), launching nothing:
+// every launch grid and ray order it names already exists or is made here.
+sbr_status batch_call(sbr_context* c, sbr_scene* const* scenes, int32_t n_scenes,
+                      const sbr_job* jobs, int32_t n_jobs, const double* rx, int32_t n_rx,
+                      Call& call)
+{
+    for (int32_t i = 0; i < n_scenes; ++i) call.scenes.push_back(scenes[i]);
+    call.rx = rx;
+    call.n_rx = n_rx;
+    call.rx_job.assign((size_t)n_rx, 0);
+    call.chunk = c->trace_chunk;
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        const sbr_job& J = jobs[j];
+        const int64_t N = num_rays(J.params.launch, J.params.division_n);
+        sbr_status r = add_job(c, call, J.scene, J.tx, J.rx_first, J.n_rx, &J.params, 0, N);
+        if (r) return r;
+    }
+    return SBR_OK;
+}
+
+bool batch_wants_graph(const sbr_context* c, const sbr_job* jobs, int32_t n_jobs)
+{
+    if (n_jobs < 1) return false;
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        const sbr_job& J = jobs[j];
+        if (!(J.params.flags & SBR_FLAG_GRAPH) || (J.params.flags & SBR_FLAG_FRESH_GRID) ||
+            (J.n_rx > 0 && J.n_rx >= c->rx_tree_min))
+            return false;
+    }
+    return true;
+}
+
+bool bgraph_matches(const sbr_context* c, sbr_scene* const* scenes, int32_t n_scenes,
+                    const sbr_job* jobs, int32_t n_jobs, int32_t n_rx)
+{
+    const auto& B = c->bgraph;
+    if (!B.valid || B.epoch != g_alloc_epoch || (int32_t)B.scene_ids.size() != n_scenes ||
+        (int32_t)B.jobs.size() != n_jobs || B.n_rx != n_rx || !same_tuning(c, B.tuning))
+        return false;
+    for (int32_t i = 0; i < n_scenes; ++i)
+        if (scenes[i]->id != B.scene_ids[i]) return false;
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        const sbr_job &a = jobs[j], &b = B.jobs[j];
+        if (a.scene != b.scene || a.rx_first != b.rx_first || a.n_rx != b.n_rx ||
+            memcmp(&a.params, &b.params, sizeof(a.params)) != 0)
+            return false;
+    }
+    return true;
+}
+
+sbr_status capture_bgraph(sbr_context* c, Call& call, const sbr_job* jobs, int32_t n_jobs,
+                          int64_t u_cap, int64_t u_pred)
+{
+    c->up_epoch = 0;  // the graph writes the job, scene and receiver-job buffers
+    auto& B = c->bgraph;
+    const int32_t n_rx = call.n_rx, nj = (int32_t)call.jobs.size();
+    const int32_t ns = (int32_t)call.scenes.size();
+    if (!B.cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&B.cap_stream, hipStreamNonBlocking));
+    sbr_status r;
+    if ((r = grow_pinned(c, (void**)&B.h_jobs, &B.jobs_cap, nj, sizeof(JobDev)))) return r;
+    if ((r = grow_pinned(c, (void**)&B.h_scenes, &B.scenes_cap, ns, sizeof(SceneDev)))) return r;
+    if ((r = grow_pinned(c, (void**)&B.h_rxjob, &B.rxjob_cap, n_rx, sizeof(int32_t)))) return r;
+    if ((r = grow_pinned(c, (void**)&B.h_rx, &B.rx_cap, n_rx, 3 * sizeof(double)))) return r;
+    for (int32_t j = 0; j < nj; ++j) B.h_jobs[j] = call.jobs[j];
+    for (int32_t i = 0; i < ns; ++i) B.h_scenes[i] = scene_dev(call.scenes[i]);
+    for (int32_t x = 0; x < n_rx; ++x) B.h_rxjob[x] = call.rx_job[x];
+    if (n_rx > 0) memcpy(B.h_rx, call.rx, sizeof(double) * 3 * (size_t)n_rx);
+    const size_t U1 = (size_t)u_cap;
+    HIPCHK(c, ensure(c->d_jobs, sizeof(JobDev) * (size_t)std::max(nj, 1)));
+    HIPCHK(c, ensure(c->d_scenes, sizeof(SceneDev) * (size_t)std::max(ns, 1)));
+    HIPCHK(c, ensure(c->rx, sizeof(double) * 3 * (size_t)std::max(n_rx, 1)));
+    HIPCHK(c, ensure(c->rx32, sizeof(float4) * (size_t)std::max(n_rx, 1)));
+    HIPCHK(c, ensure(c->d_rxjob, sizeof(int32_t) * (size_t)std::max(n_rx, 1)));
+    HIPCHK(c, ensure(c->counters, sizeof(Counters)));
+    HIPCHK(c, ensure(c->cand, sizeof(sbr_candidate) * (size_t)kSmallEvents));
+    HIPCHK(c, ensure(c->uniq, sizeof(sbr_candidate) * (size_t)kSmallEvents));
+    HIPCHK(c, ensure(c->refine, sizeof(RefineOut) * U1));
+    HIPCHK(c, ensure(c->geom, sizeof(PathGeom) * U1));
+    HIPCHK(c, ensure(c->paths, sizeof(sbr_path) * U1));
+    HIPCHK(c, ensure(c->keep, sizeof(int32_t) * U1));
+    HIPCHK(c, ensure(c->dout, sizeof(sbr_path) * U1));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+
+    call.dev.jobs = c->d_jobs.as<const JobDev>();
+    call.dev.scenes = c->d_scenes.as<const SceneDev>();
+    call.dev.rx = c->rx.as<const double>();
+    call.dev.rx32 = c->rx32.as<const float4>();
+    call.dev.rx_job = c->d_rxjob.as<const int32_t>();
+    call.dev.rx_nodes = nullptr;
+    call.dev.rx_perm = nullptr;
+    call.dev.n_jobs = nj;
+    call.dev.chunk = call.chunk;
+    call.dev.n_packets = call.n_packets;
+    const bool one = ns == 1;
+    call.s0 = scene_dev(call.scenes[0]);
+    if (one) {
+        call.lp = plan_for(call.scenes[0], c->trace_block);
+    } else {
+        call.lp = LdsPlan{};
+        call.lp.block = 256;
+    }
+    LdsPlan lp256 = one ? plan_for(call.scenes[0], 256) : LdsPlan{};
+    lp256.block = 256;
+    const LdsPlan lp3 = one ? plan_la3(call.scenes[0]) : LdsPlan{};
+    Counters* dc = c->counters.as<Counters>();
+    const hipStream_t st = B.cap_stream;
+    // the graph holds the lookahead kernels (the work queue allocates)
+    const int depth = std::max(1, refine_depth(c, u_pred));
+
+    HIPCHK(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    auto step = [&](hipError_t x) {
+        if (e == hipSuccess) e = x;
+    };
+    step(hipMemcpyAsync(c->d_jobs.p, B.h_jobs, sizeof(JobDev) * (size_t)nj,
+                        hipMemcpyHostToDevice, st));
+    step(hipMemcpyAsync(c->d_scenes.p, B.h_scenes, sizeof(SceneDev) * (size_t)ns,
+                        hipMemcpyHostToDevice, st));
+    if (n_rx > 0) {
+        step(hipMemcpyAsync(c->d_rxjob.p, B.h_rxjob, sizeof(int32_t) * (size_t)n_rx,
+                            hipMemcpyHostToDevice, st));
+        step(hipMemcpyAsync(c->rx.p, B.h_rx, sizeof(double) * 3 * (size_t)n_rx,
+                            hipMemcpyHostToDevice, st));
+    }
+    step(launch_rx32(c->rx.as<const double>(), n_rx, c->rx32.as<float4>(), st, c->counters.p,
+                     sizeof(Counters)));
+    step(launch_trace(call.dev, call.lp, call.s0, trace_blocks(c, call), &dc->queue,
+                      c->cand.as<sbr_candidate>(), kSmallEvents, &dc->cand, nullptr, nullptr,
+                      &dc->err, st));
+    step(launch_dedup_small(c->cand.as<sbr_candidate>(), kSmallEvents, c->uniq.as<sbr_candidate>(),
+                            &dc->n_unique, st, &dc->cand));
+    step(launch_refine(call.dev, lp256, lp3, call.s0, c->uniq.as<sbr_candidate>(), u_cap,
+                       &dc->n_unique, depth, c->refine.as<RefineOut>(), c->geom.as<PathGeom>(),
+                       &dc->err, st));
+    LdsPlan lps{};
+    lps.block = 256;
+    step(launch_solve(call.dev, lps, call.s0, c->uniq.as<sbr_candidate>(),
+                      c->refine.as<RefineOut>(), c->geom.as<PathGeom>(), u_cap, &dc->n_unique,
+                      c->paths.as<sbr_path>(), c->keep.as<int32_t>(), &dc->err, st));
+    step(launch_emit_small(c->paths.as<sbr_path>(), c->keep.as<int32_t>(), u_cap, &dc->n_unique,
+                           c->dout.as<sbr_path>(), u_cap, &dc->n_paths, st));
+    step(hipMemcpyAsync(c->host_ctr, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(st, &graph);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&B.exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        B.exec = nullptr;
+        return fail(c, SBR_E_DEVICE, "batch graph capture: %s", hipGetErrorString(e));
+    }
+    B.valid = true;
+    B.epoch = g_alloc_epoch;
+    B.scene_ids.clear();
+    for (const sbr_scene* sc : call.scenes) B.scene_ids.push_back(sc->id);
+    B.jobs.assign(jobs, jobs + n_jobs);
+    B.n_rx = n_rx;
+    B.u_cap = u_cap;
+    B.n_rays = call.n_rays;
+    (void)sbr_context_get_tuning(c, &B.tuning);
+    return SBR_OK;
+}
+
+// Replay for the job table and receivers of `call`.  *replayed false: the
+// counts overflowed the captured sizes (the caller runs the call normally).
+sbr_status replay_bgraph(sbr_context* c, const Call& call, sbr_path* out, int64_t capacity,
+                         int64_t* n_out, sbr_trace_stats* stats, bool* replayed)
+{
+    c->up_epoch = 0;
+    auto& B = c->bgraph;
+    *replayed = false;
+    if (B.epoch != g_alloc_epoch) {  // making the job table reallocated a buffer
+        drop_bgraph(c);
+        return SBR_OK;
+    }
+    for (size_t j = 0; j < call.jobs.size(); ++j) B.h_jobs[j] = call.jobs[j];
+    if (call.n_rx > 0) memcpy(B.h_rx, call.rx, sizeof(double) * 3 * (size_t)call.n_rx);
+    HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
+    HIPCHK(c, hipGraphLaunch(B.exec, c->stream));
+    HIPCHK(c, hipEventRecord(c->ev[6], c->stream));
+    HIPCHK(c, hipEventSynchronize(c->ev[6]));
+    const Counters* hc = c->host_ctr;
+    if (hc->err) return fail(c, SBR_E_INTERNAL, "traversal stack overflow");
+    if (hc->cand > (unsigned long long)kSmallEvents || hc->n_unique > B.u_cap) {
+        drop_bgraph(c);
+        return SBR_OK;
+    }
+    *replayed = true;
+    *n_out = hc->n_paths;
+    if (stats) {
+        memset(stats, 0, sizeof(*stats));
+        stats->n_rays = B.n_rays;
+        stats->n_candidates = (int64_t)hc->cand;
+        stats->n_unique = hc->n_unique;
+        stats->n_paths = hc->n_paths;
+        float tot = 0;
+        (void)hipEventElapsedTime(&tot, c->ev[0], c->ev[6]);
+        stats->ms_total = tot;
+        stats->lds_max = c->lds_max;
+    }
+    if (hc->n_paths > capacity)
+        return fail(c, SBR_E_CAPACITY, "%d paths, capacity %lld", hc->n_paths,
+                    (long long)capacity);
+    if (hc->n_paths > 0)
+        HIPCHK(c, hipMemcpy(out, c->dout.p, sizeof(sbr_path) * (size_t)hc->n_paths,
+                            hipMemcpyDeviceToHost));
+    return SBR_OK;
+}
+
 }  // namespace
 
 sbr_status sbr_trace_device(sbr_scene* s, const double tx[3], const double* rx, int32_t n_rx,
@@ -2207,22 +2471,32 @@ sbr_status sbr_trace_batch(sbr_context* c, sbr_scene* const* scenes, int32_t n_s
         if (r) return r;
     }
     HIPCHK(c, use_device(c->device));
-    Call call;
-    for (int32_t i = 0; i < n_scenes; ++i) call.scenes.push_back(scenes[i]);
-    call.rx = rx;
-    call.n_rx = n_rx_total;
-    call.rx_job.assign((size_t)n_rx_total, 0);
-    call.chunk = c->trace_chunk;
-    HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
-    for (int32_t j = 0; j < n_jobs; ++j) {
-        const sbr_job& J = jobs[j];
-        int64_t N = num_rays(J.params.launch, J.params.division_n);
-        sbr_status r = add_job(c, call, J.scene, J.tx, J.rx_first, J.n_rx, &J.params, 0, N);
+    const bool want_graph = batch_wants_graph(c, jobs, n_jobs);
+    if (want_graph && bgraph_matches(c, scenes, n_scenes, jobs, n_jobs, n_rx_total)) {
+        Call rc;
+        sbr_status r = batch_call(c, scenes, n_scenes, jobs, n_jobs, rx, n_rx_total, rc);
         if (r) return r;
+        bool replayed = false;
+        r = replay_bgraph(c, rc, out, capacity, n_out, stats, &replayed);
+        if (r || replayed) return r;
     }
-    sbr_status r = run_front(c, call, true, nullptr, nullptr, nullptr);
+    Call call;
+    HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
+    sbr_status r = batch_call(c, scenes, n_scenes, jobs, n_jobs, rx, n_rx_total, call);
     if (r) return r;
-    return run_paths(c, call, out, capacity, n_out, stats);
+    r = run_front(c, call, true, nullptr, nullptr, nullptr);
+    if (r) return r;
+    r = run_paths(c, call, out, capacity, n_out, stats);
+    if (r || !want_graph || !call.small) return r;
+    // capture for the next calls of this shape, with room for twice this
+    // call's paths
+    drop_bgraph(c);
+    const int64_t u_now = c->host_ctr->n_unique;
+    const int64_t u_cap = std::min<int64_t>(kSmallEvents, std::max<int64_t>(64, 2 * u_now));
+    Call cap;
+    r = batch_call(c, scenes, n_scenes, jobs, n_jobs, rx, n_rx_total, cap);
+    if (r) return r;
+    return capture_bgraph(c, cap, jobs, n_jobs, u_cap, u_now);
 }
 
 sbr_status sbr_path_gradients(sbr_scene* s, int64_t n_paths, const double* tx, const double* rx,

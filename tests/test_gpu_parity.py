@@ -578,6 +578,46 @@ def test_batch_queue_mixed_iterations(gpu, seed):
     assert len(np.unique(got["iters_used"])) > 2
 
 
+def test_batch_graph_replay_matches_eager(gpu):
+    """SBR_FLAG_GRAPH on every job of a batch: the first call captures a HIP
+    graph, later calls with other transmitters and receiver positions replay
+    it.  Every replay, with eager batches and synchronizations between the
+    replays, gives the same bytes as the batch without the graph; a replay
+    that outgrows the captured sizes is redone as a normal call, and a batch
+    of another shape is not replayed."""
+    import torch
+    b = _small_batch(7)
+    scs = [gpu.scene(s) for s in b["scenes"]]
+    rng = np.random.default_rng(4)
+    try:
+        replays = 0
+        for i in range(6):
+            jobs = [dict(j, tx=np.asarray(j["tx"]) + (rng.uniform(-2, 2, 3) if i else 0.0))
+                    for j in b["jobs"]]
+            rx = b["rx"] + (np.array([1.0, -1.0, 0.0]) if i >= 3 else 0.0)
+            got, st = gpu.trace_batch(scs, [dict(j, graph=True) for j in jobs], rx)
+            replays += i > 0 and st["ms_trace"] == 0.0  # a replay reports no stage times
+            ref, _ = gpu.trace_batch(scs, jobs, rx)  # eager work between replays
+            torch.cuda.synchronize()
+            assert got.tobytes() == ref.tobytes(), i
+            assert st["n_paths"] == len(got)
+        assert replays >= 3, replays
+        # captured with few paths (transmitters 400 m up), replayed with many
+        high = [dict(j, tx=np.asarray(j["tx"]) + np.array([0.0, 0.0, 400.0]), graph=True)
+                for j in b["jobs"]]
+        gpu.trace_batch(scs, high, b["rx"])
+        got, _ = gpu.trace_batch(scs, [dict(j, graph=True) for j in b["jobs"]], b["rx"])
+        ref, _ = gpu.trace_batch(scs, b["jobs"], b["rx"])
+        assert got.tobytes() == ref.tobytes()
+        # another shape (one job fewer) after a capture: a normal call
+        got, _ = gpu.trace_batch(scs, [dict(j, graph=True) for j in b["jobs"][1:]], b["rx"])
+        ref, _ = gpu.trace_batch(scs, b["jobs"][1:], b["rx"])
+        assert got.tobytes() == ref.tobytes()
+    finally:
+        for s in scs:
+            s.close()
+
+
 def test_batch_job_matches_oracle(gpu, orc):
     b = _small_batch(5)
     scs = [gpu.scene(s) for s in b["scenes"]]
