@@ -277,6 +277,16 @@ def batch_vs_plain(ctx, scenes, torch, seed=0, steps=2):
         pb, stb = ctx.trace_batch(scs, jobs, b["rx"])
     torch.cuda.synchronize()
     tb = (time.perf_counter() - t0) / steps
+    # the same batch captured as a HIP graph (first call) and replayed
+    gjobs = [dict(j, graph=True) for j in jobs]
+    ctx.trace_batch(scs, gjobs, b["rx"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pg, stg = ctx.trace_batch(scs, gjobs, b["rx"])
+    torch.cuda.synchronize()
+    tg = (time.perf_counter() - t0) / steps
+    assert pg.tobytes() == pb.tobytes(), "graph replay differs from the batch"
 
     def plain_pass():
         got = []
@@ -314,6 +324,9 @@ def batch_vs_plain(ctx, scenes, torch, seed=0, steps=2):
                     "stage_ms": {k: round(float(stb[k]), 4) for k in
                                  ("ms_launch", "ms_trace", "ms_dedup", "ms_refine", "ms_solve",
                                   "ms_emit", "ms_total")}},
+        "graph_replay": {"ms": round(1e3 * tg, 3), "rays_per_s": n_rays / tg,
+                         "replayed": bool(stg["ms_trace"] == 0.0),
+                         "same_bytes_as_batch": True},
         "plain": {"ms": round(1e3 * tp, 3), "rays_per_s": n_rays / tp, "paths": int(len(pp)),
                   "tuning": best_p, "within_0.01deg": gp, "refined_paths_per_s": gp / tp},
         "speedup": tp / tb,
