@@ -130,11 +130,15 @@ struct sbr_context {
     int64_t noalloc_unique = -1;  // path count of the last no-allocation call
     DevBuf grid_scratch, rx, rx32, cand, idx, flags, offs, scan, uniq, refine, paths, keep, outp,
         counters, rays_tri, rays_t, tally, geom, d_jobs, d_scenes, d_rxjob, d_rxnodes, d_rxperm,
-        d_rxp, dpaths, dout, q_state, q_slot, q_items, q_ctr;
+        d_rxp, dpaths, dout, q_state, q_slot, q_items, q_ctr, geom0;
     Counters* host_ctr = nullptr;  // pinned
     sbr_path* host_paths = nullptr;  // pinned staging of the path list
     int64_t host_paths_cap = 0;
     hipEvent_t ev[8] = {};
+    // second stream (default priority) for the exact solve beside the
+    // refinement, and the events that fork to it and join back
+    hipStream_t stream2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // LDS staging of the traversal kernels: budget per block (0 = traverse
     // from global memory with a private stack), lanes per block of the trace
     // kernel, LDS stack entries per lane.  Defaults can be overridden with
@@ -857,33 +861,44 @@ sbr_status run_paths(sbr_context* c, Call& call, sbr_path* out, int64_t capacity
     const size_t U1 = (size_t)std::max<int64_t>(Umax, 1);
     HIPCHK(c, ensure(c->refine, sizeof(RefineOut) * U1));
     HIPCHK(c, ensure(c->geom, sizeof(PathGeom) * U1));
+    HIPCHK(c, ensure(c->geom0, sizeof(PathGeom) * U1));
+    HIPCHK(c, ensure(c->paths, sizeof(sbr_path) * U1));
+    HIPCHK(c, ensure(c->keep, sizeof(int32_t) * U1));
+    HIPCHK(c, ensure(c->offs, sizeof(int32_t) * U1));
+    HIPCHK(c, ensure(c->scan, scan_scratch_bytes(Umax)));
     LdsPlan lp256 = call.scenes.size() == 1 ? plan_for(call.scenes[0], 256) : LdsPlan{};
     lp256.block = 256;
     int depth = refine_depth(c, call.spec ? call.u_pred : Umax);
     if (depth == 0 && !queue_fits(call, Umax)) depth = 1;
     LdsPlan lp3 = call.scenes.size() == 1 ? plan_la3(call.scenes[0]) : LdsPlan{};
     if (depth == 0) {
+        // the work queue allocates as it goes: its launches stay on one stream
+        HIPCHK(c, launch_solve_exact(call.dev, c->uniq.as<sbr_candidate>(), Umax, ndev,
+                                     c->paths.as<sbr_path>(), c->keep.as<int32_t>(),
+                                     c->geom0.as<PathGeom>(), &dc->err, st));
         r = refine_by_queue(c, call, Umax, ndev, &dc->err);
         if (r) return r;
+        HIPCHK(c, hipEventRecord(c->ev[4], st));
     } else {
+        // path test 2 and the exact path need no refinement result: they run
+        // on the second stream beside the refinement, which leaves most of the
+        // machine idle
+        HIPCHK(c, hipEventRecord(c->ev_fork, st));
+        HIPCHK(c, hipStreamWaitEvent(c->stream2, c->ev_fork, 0));
+        HIPCHK(c, launch_solve_exact(call.dev, c->uniq.as<sbr_candidate>(), Umax, ndev,
+                                     c->paths.as<sbr_path>(), c->keep.as<int32_t>(),
+                                     c->geom0.as<PathGeom>(), &dc->err, c->stream2));
+        HIPCHK(c, hipEventRecord(c->ev_join, c->stream2));
         HIPCHK(c, launch_refine(call.dev, lp256, lp3, call.s0, c->uniq.as<sbr_candidate>(), Umax,
                                 ndev, depth, c->refine.as<RefineOut>(), c->geom.as<PathGeom>(),
                                 &dc->err, st));
+        HIPCHK(c, hipEventRecord(c->ev[4], st));
+        HIPCHK(c, hipStreamWaitEvent(st, c->ev_join, 0));
     }
-    HIPCHK(c, hipEventRecord(c->ev[4], st));
-
-    HIPCHK(c, ensure(c->paths, sizeof(sbr_path) * U1));
-    HIPCHK(c, ensure(c->keep, sizeof(int32_t) * U1));
-    HIPCHK(c, ensure(c->offs, sizeof(int32_t) * U1));
-    HIPCHK(c, ensure(c->scan, scan_scratch_bytes(Umax)));
-    // the solve traverses from global memory (one traversal per lane: staging
-    // the scene in LDS costs more than it saves)
-    LdsPlan lps{};
-    lps.block = 256;
-    HIPCHK(c, launch_solve(call.dev, lps, call.s0, c->uniq.as<sbr_candidate>(),
-                           c->refine.as<RefineOut>(), c->geom.as<PathGeom>(), Umax, ndev,
-                           c->paths.as<sbr_path>(), c->keep.as<int32_t>(), &dc->err, st,
-                           depth == 0));
+    HIPCHK(c, launch_solve_refined(call.dev, c->uniq.as<sbr_candidate>(),
+                                   c->refine.as<RefineOut>(), c->geom.as<PathGeom>(),
+                                   c->geom0.as<PathGeom>(), Umax, ndev, c->paths.as<sbr_path>(),
+                                   &dc->err, st, depth == 0));
     HIPCHK(c, hipEventRecord(c->ev[5], st));
 
     // emit: stable compaction of kept paths (already in canonical order)
@@ -1071,6 +1086,9 @@ sbr_status sbr_context_create(int32_t device, void* hip_stream, sbr_context** ou
         e = hipEventCreate(&ev);
         if (e != hipSuccess) break;
     }
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->host_ctr, sizeof(Counters), 0);
     if (e == hipSuccess) {
         int v = 0;
@@ -1104,6 +1122,9 @@ sbr_status sbr_context_create(int32_t device, void* hip_stream, sbr_context** ou
         g_create_err = std::string("context setup: ") + hipGetErrorString(e);
         for (auto& ev : c->ev)
             if (ev) (void)hipEventDestroy(ev);
+        if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+        if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+        if (c->stream2) (void)hipStreamDestroy(c->stream2);
         delete c;
         return SBR_E_DEVICE;
     }
@@ -1174,10 +1195,13 @@ sbr_status sbr_context_destroy(sbr_context* c)
                       &c->keep,         &c->outp,  &c->counters, &c->rays_tri, &c->rays_t, &c->tally,
                       &c->geom,         &c->d_jobs, &c->d_scenes, &c->d_rxjob,
                       &c->d_rxnodes,    &c->d_rxperm, &c->d_rxp, &c->dpaths, &c->dout,
-                      &c->q_state,      &c->q_slot,  &c->q_items, &c->q_ctr};
+                      &c->q_state,      &c->q_slot,  &c->q_items, &c->q_ctr, &c->geom0};
     for (DevBuf* b : bufs) release(*b);
     for (auto& ev : c->ev)
         if (ev) (void)hipEventDestroy(ev);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->stream2) (void)hipStreamDestroy(c->stream2);
     if (c->host_ctr) (void)hipHostFree(c->host_ctr);
     if (c->host_paths) (void)hipHostFree(c->host_paths);
     drop_graph(c);
@@ -1649,11 +1673,9 @@ sbr_status capture_graph(sbr_context* c, sbr_scene* s, Call& call, const double*
     step(launch_refine(call.dev, lp256, plan_la3(s), call.s0, c->uniq.as<sbr_candidate>(), u_cap,
                        &dc->n_unique, depth, c->refine.as<RefineOut>(), c->geom.as<PathGeom>(),
                        &dc->err, st));
-    LdsPlan lps{};
-    lps.block = 256;
-    step(launch_solve(call.dev, lps, call.s0, c->uniq.as<sbr_candidate>(),
-                      c->refine.as<RefineOut>(), c->geom.as<PathGeom>(), u_cap, &dc->n_unique,
-                      c->paths.as<sbr_path>(), c->keep.as<int32_t>(), &dc->err, st));
+    step(launch_solve(call.dev, c->uniq.as<sbr_candidate>(), c->refine.as<RefineOut>(),
+                      c->geom.as<PathGeom>(), u_cap, &dc->n_unique, c->paths.as<sbr_path>(),
+                      c->keep.as<int32_t>(), &dc->err, st));
     step(launch_emit_small(c->paths.as<sbr_path>(), c->keep.as<int32_t>(), u_cap, &dc->n_unique,
                            out, capacity, &dc->n_paths, st));
     step(hipMemcpyAsync(c->host_ctr, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
@@ -1881,11 +1903,9 @@ sbr_status capture_bgraph(sbr_context* c, Call& call, const sbr_job* jobs, int32
     step(launch_refine(call.dev, lp256, lp3, call.s0, c->uniq.as<sbr_candidate>(), u_cap,
                        &dc->n_unique, depth, c->refine.as<RefineOut>(), c->geom.as<PathGeom>(),
                        &dc->err, st));
-    LdsPlan lps{};
-    lps.block = 256;
-    step(launch_solve(call.dev, lps, call.s0, c->uniq.as<sbr_candidate>(),
-                      c->refine.as<RefineOut>(), c->geom.as<PathGeom>(), u_cap, &dc->n_unique,
-                      c->paths.as<sbr_path>(), c->keep.as<int32_t>(), &dc->err, st));
+    step(launch_solve(call.dev, c->uniq.as<sbr_candidate>(), c->refine.as<RefineOut>(),
+                      c->geom.as<PathGeom>(), u_cap, &dc->n_unique, c->paths.as<sbr_path>(),
+                      c->keep.as<int32_t>(), &dc->err, st));
     step(launch_emit_small(c->paths.as<sbr_path>(), c->keep.as<int32_t>(), u_cap, &dc->n_unique,
                            c->dout.as<sbr_path>(), u_cap, &dc->n_paths, st));
     step(hipMemcpyAsync(c->host_ctr, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
@@ -2138,9 +2158,7 @@ sbr_status sbr_trace_device_noalloc(sbr_scene* s, const double tx[3], const doub
     HIPCHK(c, launch_refine(D, lp256, plan_la3(s), S0, uniq, kSmallEvents, &dc->n_unique, depth,
                             rf, geom, &dc->err, st));
     HIPCHK(c, hipEventRecord(c->ev[4], st));
-    LdsPlan lps{};
-    lps.block = 256;
-    HIPCHK(c, launch_solve(D, lps, S0, uniq, rf, geom, kSmallEvents, &dc->n_unique, paths, keep,
+    HIPCHK(c, launch_solve(D, uniq, rf, geom, kSmallEvents, &dc->n_unique, paths, keep,
                            &dc->err, st));
     HIPCHK(c, hipEventRecord(c->ev[5], st));
     HIPCHK(c, launch_emit_small(paths, keep, kSmallEvents, &dc->n_unique, out, capacity,

@@ -218,10 +218,24 @@ hipError_t launch_refine(const CallDev& call, const LdsPlan& L, const LdsPlan& L
                          const int32_t* n_dev, int depth, RefineOut* out, PathGeom* geom,
                          int32_t* err, hipStream_t s);
 
-hipError_t launch_solve(const CallDev& call, const LdsPlan& L, const SceneDev& s0,
-                        const sbr_candidate* uniq, const RefineOut* rf, PathGeom* geom,
-                        int64_t U_max, const int32_t* n_dev, sbr_path* paths, int32_t* keep,
-                        int32_t* err, hipStream_t s, bool replay = false);
+// Path test 2, path quantities and power (Sec. III.A, Sec. IV) in two
+// launches: the exact (image-method) path and its validity, which need no
+// refinement result and may run beside the refinement, then the refined
+// path's quantities and the refinement's flags.  geom0 (optional): the
+// launch rays' geometry, traced by the first launch for the paths the
+// refinement ends without an iteration.  replay: the refinement stored no
+// geometry (the work queue), so the final axis is traced.
+hipError_t launch_solve_exact(const CallDev& call, const sbr_candidate* uniq, int64_t U_max,
+                              const int32_t* n_dev, sbr_path* paths, int32_t* keep,
+                              PathGeom* geom0, int32_t* err, hipStream_t s);
+hipError_t launch_solve_refined(const CallDev& call, const sbr_candidate* uniq,
+                                const RefineOut* rf, PathGeom* geom, const PathGeom* geom0,
+                                int64_t U_max, const int32_t* n_dev, sbr_path* paths,
+                                int32_t* err, hipStream_t s, bool replay = false);
+// Both, in order on one stream.
+hipError_t launch_solve(const CallDev& call, const sbr_candidate* uniq, const RefineOut* rf,
+                        PathGeom* geom, int64_t U_max, const int32_t* n_dev, sbr_path* paths,
+                        int32_t* keep, int32_t* err, hipStream_t s, bool replay = false);
 
 hipError_t launch_compact_paths(const sbr_path* paths, const int32_t* keep, const int32_t* offs,
                                 int64_t U, sbr_path* out, hipStream_t s);

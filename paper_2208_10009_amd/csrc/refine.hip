@@ -883,21 +883,53 @@ __device__ static inline double poly_length(d3 tx, const d3* p, int k, d3 rx)
     return L;
 }
 
-// Sixteen lanes per path.  Lane 1 + j checks segment j of the image-method
-// path (reflection point j inside its face, segment j unobstructed), so path
-// test 2 costs one traversal of latency instead of k + 1; then lanes 0 and 1
-// form the refined and the exact path quantities side by side.
-template <bool LDS>
-__global__ __launch_bounds__(256) void k_solve(CallDev call, LdsPlan L, SceneDev s0,
-                                               const sbr_candidate* __restrict__ uniq,
-                                               const RefineOut* __restrict__ rf,
-                                               PathGeom* __restrict__ geom, int64_t U_max,
-                                               const int32_t* __restrict__ n_dev,
-                                               sbr_path* __restrict__ paths,
-                                               int32_t* __restrict__ keep,
-                                               int32_t* __restrict__ err, int replay)
+// Path quantities of one path from its reflection points P[0..k) and the
+// incoming directions Din (the refined path: the final ray's; the exact
+// path: the image points), the departure direction aod given.
+struct PathQ {
+    double L, delay, pw;
+    d3 aod, aoa;
+};
+
+__device__ static inline PathQ path_quantities(const SceneDev& S, const JobDev& J,
+                                               const sbr_candidate& c, d3 tx, d3 rx, d3 aod,
+                                               const d3* P, const d3* Din)
 {
-    if (LDS) stage_scene(s0, L);
+    const int k = c.order;
+    PathQ q;
+    // Tx -> reflection points -> Rx
+    q.L = poly_length(tx, P, k, rx);
+    q.delay = q.L / kC0;
+    q.aod = aod;
+    const d3 lastq = k > 0 ? pick8(P, k - 1) : tx;
+    q.aoa = normalize(sub(lastq, rx));
+    double refl[SBR_MAX_ORDER];
+#pragma unroll
+    for (int j = 0; j < SBR_MAX_ORDER; ++j) refl[j] = j < k ? refl_at(S, c.face[j], Din[j]) : 1.0;
+    q.pw = path_power(J.tx_power_dbm, J.freq_hz, q.L, refl, k);
+    return q;
+}
+
+// Path test 2 and the exact path, sixteen lanes per path.  Lane 1 + j checks
+// segment j of the image-method path (reflection point j inside its face,
+// segment j unobstructed), so the test costs one traversal of latency
+// instead of k + 1; lane 1 then forms the exact path's quantities.  With
+// geom0, lane 0 meanwhile traces the path's launch ray into geom0[p], the
+// geometry of a path that the refinement ends without an iteration.  None of
+// this needs a refinement result, so it runs beside the refinement.  Writes
+// the record's identity, the exact_* fields, the INVALID flag (as the whole
+// flags field) and keep.
+__global__ __launch_bounds__(256) void k_solve_exact(CallDev call,
+                                                     const sbr_candidate* __restrict__ uniq,
+                                                     int64_t U_max,
+                                                     const int32_t* __restrict__ n_dev,
+                                                     sbr_path* __restrict__ paths,
+                                                     int32_t* __restrict__ keep,
+                                                     PathGeom* __restrict__ geom0,
+                                                     int32_t* __restrict__ err)
+{
+    LdsPlan L{};
+    L.block = 256;
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t p = gid >> 4;
     int lane = (int)(gid & 15);
@@ -905,7 +937,7 @@ __global__ __launch_bounds__(256) void k_solve(CallDev call, LdsPlan L, SceneDev
     if (p >= U) return;
     const sbr_candidate c = uniq[p];
     const JobDev J = call.jobs[call.rx_job[c.rx]];
-    const SceneDev S = LDS ? s0 : call.scenes[J.scene];
+    const SceneDev S = call.scenes[J.scene];
     const float delta = J.delta;
     const int k = c.order;
     const d3 tx = mk(J.tx[0], J.tx[1], J.tx[2]);
@@ -919,110 +951,148 @@ __global__ __launch_bounds__(256) void k_solve(CallDev call, LdsPlan L, SceneDev
         const int j = lane - 1;
         const d3 ej = pick8(ep, j), ejm = pick8(ep, j - 1);
         const int32_t fj = face_at(c.face, j), fjm = face_at(c.face, j - 1);
-        if (j < k && !inside_face<LDS>(S, L, fj, ej)) {
+        if (j < k && !inside_face<false>(S, L, fj, ej)) {
             bad = true;
         } else {
             d3 Pa = j == 0 ? tx : ejm;
             d3 Pb = j < k ? ej : rx;
             int32_t fa = j == 0 ? -1 : fjm;
             int32_t fb = j < k ? fj : -1;
-            bad = blocked<LDS>(S, L, Pa, Pb, fa, fb, delta, err);
+            bad = blocked<false>(S, L, Pa, Pb, fa, fb, delta, err);
         }
     }
     unsigned long long mask = __ballot(bad);
     const int base = (int)(threadIdx.x & 63) & ~15;
     const bool any_bad = ((mask >> base) & 0xffffull) != 0;
-    if (lane > 1) return;
+    if (lane == 0 && geom0) {
+        PathGeom* gm = geom0 + p;
+        for (int j = 0; j < SBR_MAX_ORDER; ++j) {
+            gm->pts[j] = mk(0.0, 0.0, 0.0);
+            gm->din[j] = mk(0.0, 0.0, 0.0);
+        }
+        const d3 axis0 = mk(J.dir[c.ray], J.dir[J.N + c.ray], J.dir[2 * J.N + c.ray]);
+        Follow F;
+        follow<false>(S, L, tx, axis0, rx, k, c.face, delta, &F, gm->pts, gm->din, err);
+    }
+    if (lane != 1) return;
+    // the exact path: the image points; incoming direction = point minus
+    // the previous point
+    d3 Din[SBR_MAX_ORDER];
+    d3 prev = tx;
+#pragma unroll
+    for (int j = 0; j < SBR_MAX_ORDER; ++j) {
+        Din[j] = sub(ep[j], prev);
+        prev = ep[j];
+    }
+    const d3 firstq = k > 0 ? ep[0] : rx;
+    const PathQ E = path_quantities(S, J, c, tx, rx, normalize(sub(firstq, tx)), ep, Din);
+    sbr_path* o = paths + p;
+    o->rx = c.rx;
+    o->order = k;
+    for (int q = 0; q < SBR_MAX_ORDER; ++q) o->face[q] = c.face[q];
+    o->launch_ray = c.ray;
+    o->init_tan_err = c.tan_err;
+    o->exact_length_m = E.L;
+    o->exact_delay_s = E.delay;
+    st3(o->exact_aod, E.aod);
+    st3(o->exact_aoa, E.aoa);
+    o->exact_power_dbm = E.pw;
+    const bool ok = geo_ok && !any_bad;
+    o->flags = ok ? 0u : SBR_PATH_INVALID;
+    keep[p] = (ok || J.keep_invalid) ? 1 : 0;
+}
 
+// The refined path, one lane per path, after the refinement and
+// k_solve_exact: its quantities from the final ray's reflection points and
+// incoming directions, and the refinement's flags.  The refinement stored
+// the final ray's geometry in geom[p]; a path without iterations has the
+// launch ray's, traced by k_solve_exact into geom0[p]; without geom0, or
+// when the refinement stored none (replay), the final axis is traced here.
+// Every trace of an axis uses the arithmetic of the winning sub-ray's, so
+// the geometry is the same whichever kernel forms it.
+__global__ __launch_bounds__(64) void k_solve_refined(CallDev call,
+                                                      const sbr_candidate* __restrict__ uniq,
+                                                      const RefineOut* __restrict__ rf,
+                                                      PathGeom* __restrict__ geom,
+                                                      const PathGeom* __restrict__ geom0,
+                                                      int64_t U_max,
+                                                      const int32_t* __restrict__ n_dev,
+                                                      sbr_path* __restrict__ paths,
+                                                      int32_t* __restrict__ err, int replay)
+{
+    LdsPlan L{};
+    L.block = 64;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t U = n_dev ? min(U_max, (int64_t)*n_dev) : U_max;
+    if (p >= U) return;
+    const sbr_candidate c = uniq[p];
+    const JobDev J = call.jobs[call.rx_job[c.rx]];
+    const SceneDev S = call.scenes[J.scene];
+    const int k = c.order;
+    const d3 tx = mk(J.tx[0], J.tx[1], J.tx[2]);
+    const d3 rx = mk(call.rx[3 * c.rx], call.rx[3 * c.rx + 1], call.rx[3 * c.rx + 2]);
     const RefineOut R = rf[p];
     const d3 axis = ld3(R.axis);
-    // The refinement stored the geometry of its final winning sub-ray in
-    // geom[p]; without iterations, or when the refinement stored none
-    // (replay), the final axis is traced into it (the same arithmetic as the
-    // winning sub-ray's trace, so the same geometry).
+    const bool from0 = R.iters == 0 && geom0;
     PathGeom* gm = geom + p;
-    if (lane == 0 && (R.iters == 0 || replay)) {
+    if (!from0 && (R.iters == 0 || replay)) {
         for (int j = 0; j < SBR_MAX_ORDER; ++j) {
             gm->pts[j] = mk(0.0, 0.0, 0.0);
             gm->din[j] = mk(0.0, 0.0, 0.0);
         }
         Follow F;
-        follow<LDS>(S, L, tx, axis, rx, k, c.face, delta, &F, gm->pts, gm->din, err);
+        follow<false, 64>(S, L, tx, axis, rx, k, c.face, J.delta, &F, gm->pts, gm->din, err);
     }
-    // Lanes 0 and 1 form the same quantities side by side: lane 0 of the
-    // refined path (the final ray's reflection points and incoming
-    // directions), lane 1 of the exact path (the image points; incoming
-    // direction = point minus the previous point).
-    const bool ex = lane == 1;
+    const PathGeom* g = from0 ? geom0 + p : gm;
     d3 P[SBR_MAX_ORDER], Din[SBR_MAX_ORDER];
-    d3 prev = tx;
 #pragma unroll
     for (int j = 0; j < SBR_MAX_ORDER; ++j) {
-        const d3 gp = gm->pts[j], gd = gm->din[j];
-        P[j] = ex ? ep[j] : gp;
-        Din[j] = ex ? sub(ep[j], prev) : gd;
-        prev = ep[j];
+        P[j] = g->pts[j];
+        Din[j] = g->din[j];
     }
-    // Tx -> reflection points -> Rx
-    const double Lq = poly_length(tx, P, k, rx);
-    const double delay = Lq / kC0;
-    const d3 firstq = k > 0 ? P[0] : rx;
-    const d3 aod = ex ? normalize(sub(firstq, tx)) : axis;
-    const d3 lastq = k > 0 ? pick8(P, k - 1) : tx;
-    const d3 aoa = normalize(sub(lastq, rx));
-    double refl[SBR_MAX_ORDER];
-#pragma unroll
-    for (int j = 0; j < SBR_MAX_ORDER; ++j) refl[j] = j < k ? refl_at(S, c.face[j], Din[j]) : 1.0;
-    const double pw = path_power(J.tx_power_dbm, J.freq_hz, Lq, refl, k);
-    // the exact path's values to lane 0
-    const int src = base + 1;
-    const double EL = __shfl(Lq, src), Edelay = __shfl(delay, src), Epw = __shfl(pw, src);
-    const d3 Eaod = mk(__shfl(aod.x, src), __shfl(aod.y, src), __shfl(aod.z, src));
-    const d3 Eaoa = mk(__shfl(aoa.x, src), __shfl(aoa.y, src), __shfl(aoa.z, src));
-    if (ex) return;
-
-    sbr_path o;
-    o.rx = c.rx;
-    o.order = k;
-    for (int q = 0; q < SBR_MAX_ORDER; ++q) o.face[q] = c.face[q];
-    o.launch_ray = c.ray;
-    o.iters_used = R.iters;
-    o.flags = R.flags;
-    o.init_tan_err = c.tan_err;
-    o.tan_err = R.tan_err;
-    st3(o.axis, axis);
-    o.length_m = Lq;
-    o.delay_s = delay;
-    st3(o.aod, aod);
-    st3(o.aoa, aoa);
-    o.power_dbm = pw;
-    o.err_angle_deg = atan(R.tan_err) * (180.0 / kPi);
-    const bool ok = geo_ok && !any_bad;
-    o.exact_length_m = EL;
-    o.exact_delay_s = Edelay;
-    st3(o.exact_aod, Eaod);
-    st3(o.exact_aoa, Eaoa);
-    o.exact_power_dbm = Epw;
-    if (!ok) o.flags |= SBR_PATH_INVALID;
-    paths[p] = o;
-    keep[p] = (ok || J.keep_invalid) ? 1 : 0;
+    const PathQ Q = path_quantities(S, J, c, tx, rx, axis, P, Din);
+    sbr_path* o = paths + p;
+    o->iters_used = R.iters;
+    o->flags |= R.flags;
+    o->tan_err = R.tan_err;
+    st3(o->axis, axis);
+    o->length_m = Q.L;
+    o->delay_s = Q.delay;
+    st3(o->aod, Q.aod);
+    st3(o->aoa, Q.aoa);
+    o->power_dbm = Q.pw;
+    o->err_angle_deg = atan(R.tan_err) * (180.0 / kPi);
 }
 
-hipError_t launch_solve(const CallDev& call, const LdsPlan& L, const SceneDev& s0,
-                        const sbr_candidate* uniq, const RefineOut* rf, PathGeom* geom,
-                        int64_t U, const int32_t* n_dev, sbr_path* paths, int32_t* keep,
-                        int32_t* err, hipStream_t s, bool replay)
+hipError_t launch_solve_exact(const CallDev& call, const sbr_candidate* uniq, int64_t U,
+                              const int32_t* n_dev, sbr_path* paths, int32_t* keep,
+                              PathGeom* geom0, int32_t* err, hipStream_t s)
 {
     if (U <= 0) return hipSuccess;
-    int64_t threads = U * 16;
-    dim3 grid((unsigned)((threads + L.block - 1) / L.block));
-    if (L.bytes > 0)
-        hipLaunchKernelGGL(k_solve<true>, grid, dim3(L.block), L.bytes, s, call, L, s0, uniq, rf,
-                           geom, U, n_dev, paths, keep, err, replay ? 1 : 0);
-    else
-        hipLaunchKernelGGL(k_solve<false>, grid, dim3(L.block), 0, s, call, L, s0, uniq, rf, geom,
-                           U, n_dev, paths, keep, err, replay ? 1 : 0);
+    const int64_t threads = U * 16;
+    hipLaunchKernelGGL(k_solve_exact, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
+                       call, uniq, U, n_dev, paths, keep, geom0, err);
     return hipGetLastError();
+}
+
+hipError_t launch_solve_refined(const CallDev& call, const sbr_candidate* uniq,
+                                const RefineOut* rf, PathGeom* geom, const PathGeom* geom0,
+                                int64_t U, const int32_t* n_dev, sbr_path* paths, int32_t* err,
+                                hipStream_t s, bool replay)
+{
+    if (U <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_solve_refined, dim3((unsigned)((U + 63) / 64)), dim3(64), 0, s, call,
+                       uniq, rf, geom, geom0, U, n_dev, paths, err, replay ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve(const CallDev& call, const sbr_candidate* uniq, const RefineOut* rf,
+                        PathGeom* geom, int64_t U, const int32_t* n_dev, sbr_path* paths,
+                        int32_t* keep, int32_t* err, hipStream_t s, bool replay)
+{
+    hipError_t e = launch_solve_exact(call, uniq, U, n_dev, paths, keep, nullptr, err, s);
+    if (e != hipSuccess) return e;
+    return launch_solve_refined(call, uniq, rf, geom, nullptr, U, n_dev, paths, err, s, replay);
 }
 
 // The three-level kernel also has 192 bytes of static LDS: its dynamic
@@ -1038,11 +1108,7 @@ hipError_t refine_set_lds_limit(int bytes)
     hipError_t e = hipFuncSetAttribute((const void*)k_refine<true>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)k_refine_la<true>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e != hipSuccess) return e;
-
-    return hipFuncSetAttribute((const void*)k_solve<true>,
+    return hipFuncSetAttribute((const void*)k_refine_la<true>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
