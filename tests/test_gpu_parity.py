@@ -383,7 +383,9 @@ def _trace_with_env(env, cfg, **prm):
                                  dict(iterations=7, subrays=6, target_err_deg=0.003),
                                  dict(iterations=1, subrays=7), dict(iterations=2, subrays=6),
                                  dict(iterations=0, subrays=7),
-                                 dict(iterations=0, subrays=6, target_err_deg=0.5)])
+                                 dict(iterations=0, subrays=6, target_err_deg=0.5),
+                                 dict(iterations=20, subrays=7, target_err_deg=0.0002),
+                                 dict(iterations=13, subrays=6)])
 def test_refine_lookahead_matches_single_step(gpu, orc, prm):
     """The three-iteration (512 lanes per path) and two-iteration (64 lanes)
     lookahead kernels, the one-iteration kernel (8 lanes per path) and the
@@ -391,7 +393,7 @@ def test_refine_lookahead_matches_single_step(gpu, orc, prm):
     all match the oracle."""
     cfg = scenes.manhattan_config(2, n_rx=24)
     full = dict(cfg["params"], division_n=80, **prm)
-    a = _trace_with_env({"SBR_LOOKAHEAD_PATHS": "0"}, cfg, **full)
+    a = _trace_with_env({"SBR_LOOKAHEAD_PATHS": "0", "SBR_LOOKAHEAD_DEPTH": "1"}, cfg, **full)
     b = _trace_with_env({"SBR_LOOKAHEAD_PATHS": "100000", "SBR_LOOKAHEAD_DEPTH": "2"}, cfg, **full)
     c = _trace_with_env({"SBR_LOOKAHEAD_PATHS": "100000", "SBR_LOOKAHEAD_DEPTH": "3",
                          "SBR_LOOKAHEAD3_PATHS": "100000"}, cfg, **full)
