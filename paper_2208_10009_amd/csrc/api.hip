@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -31,7 +32,9 @@ struct DevBuf {
 
 // Bumped whenever a device buffer is (re)allocated or released: a captured
 // graph is only replayed while the buffers it was captured with still exist.
-uint64_t g_alloc_epoch = 1;
+// Atomic because contexts may run on different threads; a bump by another
+// context only costs this one a recapture.
+std::atomic<uint64_t> g_alloc_epoch{1};
 
 hipError_t ensure(DevBuf& b, size_t bytes)
 {
@@ -65,15 +68,15 @@ struct Counters {
 
 }  // namespace
 
+// BVH defaults when sbr_bvh_build gets no parameters.
+constexpr int kDefaultSahBins = 32;
+constexpr int kDefaultSplitPct = 0;
+
 // Device memory of sbr_trace_device_noalloc: everything that entry point needs
 // beyond its inputs and outputs lives in this array (one copy per device,
 // held until the process ends).  Host code never passes `scratch` itself to a
 // kernel or copy: the device address comes from hipGetSymbolAddress, taken
 // once per device (noalloc_scratch_ptr).
-// BVH defaults when sbr_bvh_build gets no parameters.
-constexpr int kDefaultSahBins = 32;
-constexpr int kDefaultSplitPct = 0;
-
 constexpr size_t kNoAllocBytes = size_t(24) << 20;
 constexpr int32_t kNoAllocMaxRx = 4096;
 static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
