@@ -294,9 +294,11 @@ def batch_vs_plain(ctx, scenes, torch, seed=0, steps=2):
     build_s = time.perf_counter() - t0
     ctx.trace_batch(scs, jobs, b["rx"])  # warm-up: launch grids of every n
     base = ctx.tuning()
-    # depth 0: the refinement's persistent work queue; 3: the lookahead kernels
-    space = {"trace_chunk": [1, 2, 4], "persist_blocks": [1024, 2048, 4096, 8192],
-             "lookahead_max_paths": [0, 4096], "lookahead_depth": [0, 3]}
+    # depth 0: the refinement's persistent work queue; 3: the lookahead
+    # kernels, or with refine_segments the segment-parallel kernel
+    space = {"trace_chunk": [1, 2, 4], "persist_blocks": [1024, 2048, 4096],
+             "lookahead_max_paths": [0, 4096], "lookahead_depth": [0, 3],
+             "refine_segments": [1, 0]}
     best, trials = autotune.autotune(ctx, lambda: ctx.trace_batch(scs, jobs, b["rx"]),
                                      space=space, warmup=0, steps=1)
     torch.cuda.synchronize()

@@ -173,7 +173,13 @@ typedef struct {
  * traces every ray of its grid hands its rays to the waves sorted by
  * direction (cube-map cells in Z order, the order made once per grid of at
  * most 2^27 rays), so the 64 rays of a wave leave in nearby directions and
- * traverse the same BVH nodes; 0 hands them out by index (same results). */
+ * traverse the same BVH nodes; 0 hands them out by index (same results).
+ * With refine_segments = 1 (and a depth other than 0), up to
+ * lookahead_max_paths paths are refined one iteration per step by one wave
+ * per path whose lanes trace the k + 1 segments of every sub-ray at once:
+ * lane (s, j) starts segment j where the chain of closest hits on the
+ * expected faces puts it, so a step waits for the slowest segment instead of
+ * the k + 1 segments in a row (same results). */
 typedef struct {
     int32_t trace_chunk;         /* 1..64                                   */
     int32_t persist_blocks;      /* >= 1                                    */
@@ -186,6 +192,7 @@ typedef struct {
     int32_t lookahead3_max_paths; /* >= 0                                   */
     int32_t grid_check_log2;     /* 0..200                                  */
     int32_t ray_order;           /* 0 or 1                                  */
+    int32_t refine_segments;     /* 0 or 1                                  */
 } sbr_tuning;
 
 sbr_status sbr_context_get_tuning(const sbr_context* ctx, sbr_tuning* out);
@@ -215,7 +222,10 @@ sbr_status sbr_scene_upload(sbr_context* ctx, const double* xyz, int64_t n_verti
                             int64_t n_triangles, const sbr_complex* eps_r, int32_t n_materials,
                             sbr_scene** out);
 /* Build the acceleration structure (binned SAH BVH with conservative FP32
- * boxes; not part of the paper's method, which leaves acceleration open). */
+ * boxes; not part of the paper's method, which leaves acceleration open).
+ * Errors: SBR_E_INVALID_ARG (a parameter out of range, or a hierarchy of more
+ * than 2^25 nodes, 4 GiB: about 100 M triangles), SBR_E_INTERNAL (hierarchy
+ * deeper than the traversal stack), SBR_E_OOM, SBR_E_DEVICE. */
 sbr_status sbr_bvh_build(sbr_scene* scene, const sbr_bvh_params* params);
 sbr_status sbr_scene_destroy(sbr_scene* scene);
 

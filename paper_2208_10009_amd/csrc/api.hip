@@ -156,6 +156,7 @@ struct sbr_context {
     int32_t rx_tree_min = 64;
     int32_t lookahead_depth = 3;
     int32_t lookahead3_max_paths = 256;
+    int32_t refine_segments = 1;
     int32_t grid_check_log2 = 0;
     bool la3_lds = true;  // stage the scene in LDS for the three-level refinement
     // event and path counts of the last device-memory call, which predict
@@ -699,6 +700,7 @@ int refine_depth(const sbr_context* c, int64_t U)
 {
     if (c->lookahead_depth == 0) return 0;
     if (U > c->lookahead_max_paths) return 1;
+    if (c->refine_segments) return kRefineSegments;
     if (c->lookahead_depth >= 3 && U > c->lookahead3_max_paths) return 2;
     return c->lookahead_depth;
 }
@@ -1112,6 +1114,7 @@ sbr_status sbr_context_create(int32_t device, void* hip_stream, sbr_context** ou
         c->rx_tree_min = env_int("SBR_RX_TREE_MIN", 64, 1, 0x7fffffff);
         c->lookahead_depth = env_int("SBR_LOOKAHEAD_DEPTH", 3, 0, 3);
         c->lookahead3_max_paths = env_int("SBR_LOOKAHEAD3_PATHS", 256, 0, 1 << 30);
+        c->refine_segments = env_int("SBR_REFINE_SEGMENTS", 1, 0, 1);
         c->la3_lds = env_int("SBR_LA3_LDS", 1, 0, 1) != 0;
         c->ray_order = env_int("SBR_RAY_ORDER", 1, 0, 1);
         if (refine_la3_set_lds_limit(c->lds_max - 1024) != hipSuccess) {
@@ -1149,6 +1152,7 @@ sbr_status sbr_context_get_tuning(const sbr_context* c, sbr_tuning* t)
     t->lookahead3_max_paths = c->lookahead3_max_paths;
     t->grid_check_log2 = c->grid_check_log2;
     t->ray_order = c->ray_order;
+    t->refine_segments = c->refine_segments;
     return SBR_OK;
 }
 
@@ -1163,7 +1167,7 @@ sbr_status sbr_context_set_tuning(sbr_context* c, const sbr_tuning* t)
         t->lds_budget > c->lds_max || t->rx_tree_min < 1 || t->lookahead_max_paths < 0 ||
         t->lookahead_depth < 0 || t->lookahead_depth > 3 || t->lookahead3_max_paths < 0 ||
         t->grid_check_log2 < 0 || t->grid_check_log2 > 200 || t->ray_order < 0 ||
-        t->ray_order > 1)
+        t->ray_order > 1 || t->refine_segments < 0 || t->refine_segments > 1)
         return fail(c, SBR_E_INVALID_ARG, "tuning field out of range");
     if (t->grid_check_log2 != c->grid_check_log2) {
         // cached grids were made under the old setting (they are the same
@@ -1182,6 +1186,7 @@ sbr_status sbr_context_set_tuning(sbr_context* c, const sbr_tuning* t)
     c->lookahead3_max_paths = t->lookahead3_max_paths;
     c->grid_check_log2 = t->grid_check_log2;
     c->ray_order = t->ray_order;
+    c->refine_segments = t->refine_segments;
     return SBR_OK;
 }
 
@@ -1332,6 +1337,10 @@ sbr_status sbr_bvh_build(sbr_scene* s, const sbr_bvh_params* bp)
     s->bvh_depth =
         build_bvh(s->tri_v.data(), s->T, leaf, bins, split, c->lds_budget > 0, nodes, perm);
     s->n_nodes = (int64_t)nodes.size();
+    // the traversal addresses a node by a 32-bit byte offset
+    if (s->n_nodes > kMaxBvhNodes)
+        return fail(c, SBR_E_INVALID_ARG, "BVH of %lld nodes: at most %lld", (long long)s->n_nodes,
+                    (long long)kMaxBvhNodes);
     if (3 * s->bvh_depth >= kTraceStack) return fail(c, SBR_E_INTERNAL, "BVH too deep");
     // triangle records in leaf order, one per reference
     s->R = (int64_t)perm.size();
@@ -1563,7 +1572,8 @@ bool same_tuning(const sbr_context* c, const sbr_tuning& t)
            now.lookahead_max_paths == t.lookahead_max_paths &&
            now.lookahead_depth == t.lookahead_depth &&
            now.lookahead3_max_paths == t.lookahead3_max_paths &&
-           now.grid_check_log2 == t.grid_check_log2 && now.ray_order == t.ray_order;
+           now.grid_check_log2 == t.grid_check_log2 && now.ray_order == t.ray_order &&
+           now.refine_segments == t.refine_segments;
 }
 
 bool graph_matches(const sbr_context* c, const sbr_scene* s, const double* rx, int32_t n_rx,

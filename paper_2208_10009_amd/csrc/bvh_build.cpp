@@ -393,13 +393,16 @@ int collapse(const std::vector<BvhNode>& n2, int32_t r, std::vector<Bvh4Node>& n
         }
     Bvh4Node& nd = n4[at];
     for (int k = 0; k < 4; ++k) {
+        // an empty slot gets the inverted box (lo = +inf, hi = -inf): its
+        // entry parameter is +inf and its exit -inf on every axis, whatever
+        // the sign of the direction, so no ray enters it
         const bool used = k < ns && s[k].count >= 0;
-        nd.lox[k] = used ? s[k].lo[0] : 0.0f;
-        nd.loy[k] = used ? s[k].lo[1] : 0.0f;
-        nd.loz[k] = used ? s[k].lo[2] : 0.0f;
-        nd.hix[k] = used ? s[k].hi[0] : 0.0f;
-        nd.hiy[k] = used ? s[k].hi[1] : 0.0f;
-        nd.hiz[k] = used ? s[k].hi[2] : 0.0f;
+        nd.lox[k] = used ? s[k].lo[0] : INFINITY;
+        nd.loy[k] = used ? s[k].lo[1] : INFINITY;
+        nd.loz[k] = used ? s[k].lo[2] : INFINITY;
+        nd.hix[k] = used ? s[k].hi[0] : -INFINITY;
+        nd.hiy[k] = used ? s[k].hi[1] : -INFINITY;
+        nd.hiz[k] = used ? s[k].hi[2] : -INFINITY;
         nd.idx[k] = used ? s[k].index : 0;
         nd.cnt[k] = used ? s[k].count : -1;
     }

@@ -32,16 +32,22 @@ struct BvhNode {
 static_assert(sizeof(BvhNode) == 64, "BvhNode layout");
 
 // BVH4 node, 128 bytes (8 x 16 B): the FP32 boxes of four children in SoA
-// (lo x, lo y, lo z, hi x, hi y, hi z, four children each), then per child
-// (index, count) with the BvhNode meaning.  Collapsed from the BVH2, whose
-// outward-rounded child boxes it keeps unchanged.
+// rows of four (lo x, lo y, lo z at bytes 0, 16, 32; hi x, hi y, hi z at 64,
+// 80, 96: each axis's lo and hi rows 64 bytes apart, so a traversal lane
+// finds the far row of an axis by flipping bit 6 of the near row's offset),
+// and per child (index, count) at 48 and 112 with the BvhNode meaning; an
+// empty child has the inverted box lo = +inf, hi = -inf, which no ray enters.
+// Collapsed from the BVH2, whose outward-rounded child boxes it keeps.
 struct Bvh4Node {
-    float lox[4], loy[4], loz[4], hix[4], hiy[4], hiz[4];
-    int32_t idx[4], cnt[4];
+    float lox[4], loy[4], loz[4];
+    int32_t idx[4];
+    float hix[4], hiy[4], hiz[4];
+    int32_t cnt[4];
 };
 static_assert(sizeof(Bvh4Node) == 128, "Bvh4Node layout");
 
 constexpr int kMaxBvhDepth = 48;  // builder cap on the BVH2 depth
+constexpr int64_t kMaxBvhNodes = int64_t(1) << 25;  // node byte offsets fit 32 bits
 constexpr int kTraceStack = 96;   // traversal stack; a BVH4 level pushes at most 3
 
 // Host-side BVH build (binned SAH BVH2, collapsed to BVH4) over triangle
@@ -210,9 +216,12 @@ struct RefineOut {
 // U_max paths (the first min(U_max, *n_dev) when n_dev is non-NULL).  Depth
 // 3 (without an LDS plan): one 512-lane workgroup per path resolves three
 // iterations per step; depth 2: one wave per path, two iterations per step;
-// depth 1: eight lanes per path, one iteration per step.
+// depth 1: eight lanes per path, one iteration per step; depth
+// kRefineSegments: one wave per path, one iteration per step, the segments
+// of every sub-ray traced in parallel lanes.
 // L3 is the plan of the three-level kernel (512 lanes; bytes == 0: global
-// memory), used when depth >= 3 whatever L is.
+// memory), used when depth is 3 whatever L is.
+constexpr int kRefineSegments = 4;
 hipError_t launch_refine(const CallDev& call, const LdsPlan& L, const LdsPlan& L3,
                          const SceneDev& s0, const sbr_candidate* uniq, int64_t U_max,
                          const int32_t* n_dev, int depth, RefineOut* out, PathGeom* geom,

@@ -443,6 +443,116 @@ __global__ __launch_bounds__(512) void k_refine_la3(CallDev call, LdsPlan L, Sce
     }
 }
 
+// One wave per path, one iteration per step, every sub-ray's segments traced
+// at once: lane (s, j) = (lane / (k + 1), lane % (k + 1)), s < subrays,
+// checks segment j of sub-ray s (seg_lane), so a step waits for the slowest
+// single segment (plus the short chain of expected-face hits that places
+// it) instead of k + 1 traversals in a row.  A sub-ray is kept when none of
+// its lanes failed; its error angle is on lane (s, k).  Winner, ties, stop
+// rules and stored geometry are those of k_refine, so the result is the same
+// bit for bit.  6 or 7 sub-rays of at most 9 segments fill at most 63 lanes.
+template <bool LDS>
+__global__ __launch_bounds__(256) void k_refine_seg(CallDev call, LdsPlan L, SceneDev s0,
+                                                    const sbr_candidate* __restrict__ uniq,
+                                                    int64_t U_max,
+                                                    const int32_t* __restrict__ n_dev,
+                                                    RefineOut* __restrict__ out,
+                                                    PathGeom* __restrict__ geom,
+                                                    int32_t* __restrict__ err)
+{
+    if (LDS) stage_scene(s0, L);
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t p = gid >> 6;
+    const int lane = (int)(gid & 63);
+    const int64_t U = n_dev ? min(U_max, (int64_t)*n_dev) : U_max;
+    if (p >= U) return;  // uniform over the wave
+    const sbr_candidate c = uniq[p];
+    const int jb = __builtin_amdgcn_readfirstlane(call.rx_job[c.rx]);  // one path per wave
+    const JobDev J = call.jobs[jb];
+    const SceneDev S = LDS ? s0 : call.scenes[J.scene];
+    const d3 tx = mk(J.tx[0], J.tx[1], J.tx[2]);
+    const d3 rx = mk(call.rx[3 * c.rx], call.rx[3 * c.rx + 1], call.rx[3 * c.rx + 2]);
+    d3 axis = mk(J.dir[c.ray], J.dir[J.N + c.ray], J.dir[2 * J.N + c.ray]);
+    const int k = __builtin_amdgcn_readfirstlane(c.order);
+    int32_t faces[SBR_MAX_ORDER];
+#pragma unroll
+    for (int q = 0; q < SBR_MAX_ORDER; ++q) faces[q] = __builtin_amdgcn_readfirstlane(c.face[q]);
+    const int K1 = k + 1;
+    int s = 0, j = lane;
+    while (j >= K1) {
+        j -= K1;
+        ++s;
+    }
+    Follow F{0.0, 0.0, 0.0};
+    d3 pt = mk(0.0, 0.0, 0.0), din = pt;
+    // start (start_path): with a target, the launch ray is replayed by lanes (0, j)
+    double tan = c.tan_err;
+    bool met = false;
+    if (J.tan_tgt > 0.0) {
+        bool ok = false;
+        if (s == 0) ok = seg_lane<LDS>(S, L, tx, axis, rx, k, j, faces, J.delta, &F, &pt, &din, err);
+        if (__ballot(s == 0 && !ok)) {
+            if (lane == 0) out[p] = stalled_at_start(axis);
+            return;
+        }
+        tan = __shfl(F.tan_err, k);
+        met = target_met(tan, J.tan_tgt, __shfl(F.D, k), __shfl(F.Llast, k));
+    }
+    const bool act = s < J.subrays;
+    const unsigned long long segs = ((1ull << K1) - 1) << (act ? s * K1 : 0);
+    uint32_t flags = met ? SBR_PATH_TARGET_MET : 0u;
+    int32_t iters = 0;
+    double rho = J.thl;
+    for (int i = 1; i <= J.iterations && !met; ++i) {
+        rho = rho / sqrt(3.0);
+        d3 u, v;
+        basis(axis, &u, &v);
+        bool ok = false;
+        if (act)
+            ok = seg_lane<LDS>(S, L, tx, subray(axis, u, v, rho, s), rx, k, j, faces, J.delta, &F,
+                               &pt, &din, err);
+        const unsigned long long bad = __ballot(act && !ok);
+        const bool keep = act && j == k && (bad & segs) == 0;
+        double bt = keep ? F.tan_err : INFINITY;
+        int bs = keep ? s : 8;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            double ot = __shfl_xor(bt, off);
+            int os = __shfl_xor(bs, off);
+            if (ot < bt || (ot == bt && os < bs)) {
+                bt = ot;
+                bs = os;
+            }
+        }
+        if (bs >= 8) {
+            flags |= SBR_PATH_STALLED;
+            break;
+        }
+        const int wl = bs * K1 + k;
+        const double wD = __shfl(F.D, wl), wL = __shfl(F.Llast, wl);
+        if (act && s == bs && j < k) {
+            geom[p].pts[j] = pt;
+            geom[p].din[j] = din;
+        }
+        __threadfence_block();
+        axis = subray(axis, u, v, rho, bs);
+        tan = bt;
+        iters = i;
+        if (J.tan_tgt > 0.0 && target_met(bt, J.tan_tgt, wD, wL)) {
+            flags |= SBR_PATH_TARGET_MET;
+            met = true;
+        }
+    }
+    if (lane == 0) {
+        RefineOut o;
+        st3(o.axis, axis);
+        o.tan_err = tan;
+        o.iters = iters;
+        o.flags = flags;
+        out[p] = o;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // The precise algorithm fed by a device work queue of sub-rays: one
 // persistent launch refines every path of a call (of every job of a batch),
@@ -691,6 +801,16 @@ hipError_t launch_refine(const CallDev& call, const LdsPlan& L, const LdsPlan& L
                          int32_t* err, hipStream_t s)
 {
     if (U <= 0) return hipSuccess;
+    if (depth == kRefineSegments) {
+        dim3 grid((unsigned)((U * 64 + L.block - 1) / L.block));
+        if (L.bytes > 0)
+            hipLaunchKernelGGL(k_refine_seg<true>, grid, dim3(L.block), L.bytes, s, call, L, s0,
+                               uniq, U, n_dev, out, geom, err);
+        else
+            hipLaunchKernelGGL(k_refine_seg<false>, grid, dim3(L.block), 0, s, call, L, s0, uniq,
+                               U, n_dev, out, geom, err);
+        return hipGetLastError();
+    }
     // the three-level kernel has its own LDS plan (L3), whatever the trace's
     if (depth >= 3) {
         if (L3.bytes > 0)

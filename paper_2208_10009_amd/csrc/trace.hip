@@ -227,7 +227,8 @@ __device__ static inline void receive(const JobDev& J, const double* __restrict_
 // takes a new packet only when all its lanes are idle, so the job and its
 // scene stay uniform across the wave.
 template <bool COUNT, bool LDS>
-__global__ __launch_bounds__(256) void k_trace(CallDev call, LdsPlan L, SceneDev s0,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+void k_trace(CallDev call, LdsPlan L, SceneDev s0,
                                                uint32_t* __restrict__ queue,
                                                sbr_candidate* __restrict__ cand, int64_t cap,
                                                unsigned long long* __restrict__ ccount,

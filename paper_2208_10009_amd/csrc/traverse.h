@@ -179,6 +179,18 @@ __device__ static int32_t traverse(const SceneDev& S, const LdsPlan& L, d3 o, d3
     const float hx = ox - delta, hy = oy - delta, hz = oz - delta;
     const float nlx = -(lx * ix), nly = -(ly * iy), nlz = -(lz * iz);
     const float nhx = -(hx * ix), nhy = -(hy * iy), nhz = -(hz * iz);
+    // Near and far planes per axis by the sign of the direction: for i > 0,
+    // lo < hi and nl <= nh give fma(lo, i, nl) <= fma(hi, i, nh) (products,
+    // sums and roundings are monotonic), and the reverse for i < 0, so the
+    // near plane's parameter is exactly the minimum of the two and the far
+    // one's the maximum.  The lane loads the rows it needs instead of taking
+    // minima and maxima: the near row of an axis at node + s (s = 0 for lo,
+    // 64 for hi, plus the axis's row offset) and the far row at (node + s) ^ 64.
+    const uint32_t sx = ix > 0.0f ? 0u : 64u, sy = iy > 0.0f ? 0u : 64u;
+    const uint32_t sz = iz > 0.0f ? 0u : 64u;
+    const float cnx = ix > 0.0f ? nlx : nhx, cfx = ix > 0.0f ? nhx : nlx;
+    const float cny = iy > 0.0f ? nly : nhy, cfy = iy > 0.0f ? nhy : nly;
+    const float cnz = iz > 0.0f ? nlz : nhz, cfz = iz > 0.0f ? nhz : nlz;
 
     float tb = isinf(t_hi) ? INFINITY : (float)t_hi * slack;
     if (seeded && h->pos >= 0) {
@@ -216,41 +228,54 @@ __device__ static int32_t traverse(const SceneDev& S, const LdsPlan& L, d3 o, d3
     int sp = 0;
     int32_t node = 0;
     for (;;) {
-        float4 q0, q1, q2, q3, q4, q5, q6, q7;
+        // near and far plane rows (x, y, z) and the child index and count rows
+        float4 nx4, ny4, nz4, fx4, fy4, fz4, q6, q7;
+        const uint32_t nb = (uint32_t)node << 7;
+        const uint32_t ax = nb + sx, ay = nb + sy, az = nb + sz;
         if (LDS && node < L.n_nodes) {
-            const float4* np = g_smem4 + 8 * node;
-            q0 = np[0]; q1 = np[1]; q2 = np[2]; q3 = np[3];
-            q4 = np[4]; q5 = np[5]; q6 = np[6]; q7 = np[7];
+            const char* np = (const char*)g_smem4;
+            nx4 = *(const float4*)(np + ax);
+            fx4 = *(const float4*)(np + (ax ^ 64u));
+            ny4 = *(const float4*)(np + ay + 16);
+            fy4 = *(const float4*)(np + (ay ^ 64u) + 16);
+            nz4 = *(const float4*)(np + az + 32);
+            fz4 = *(const float4*)(np + (az ^ 64u) + 32);
+            q6 = *(const float4*)(np + nb + 48);
+            q7 = *(const float4*)(np + nb + 112);
         } else {
-            const float4* np = (const float4*)(S.nodes + node);
-            q0 = gld(np); q1 = gld(np + 1); q2 = gld(np + 2); q3 = gld(np + 3);
-            q4 = gld(np + 4); q5 = gld(np + 5); q6 = gld(np + 6); q7 = gld(np + 7);
+            const char* np = (const char*)S.nodes;
+            nx4 = gld((const float4*)(np + ax));
+            fx4 = gld((const float4*)(np + (ax ^ 64u)));
+            ny4 = gld((const float4*)(np + ay + 16));
+            fy4 = gld((const float4*)(np + (ay ^ 64u) + 16));
+            nz4 = gld((const float4*)(np + az + 32));
+            fz4 = gld((const float4*)(np + (az ^ 64u) + 32));
+            q6 = gld((const float4*)(np + nb + 48));
+            q7 = gld((const float4*)(np + nb + 112));
         }
         const int4 cidx = __builtin_bit_cast(int4, q6), ccnt = __builtin_bit_cast(int4, q7);
         if (COUNT) {
             tally->nodes += 1;
             if (first_active_lane()) tally->wave_nodes += 1;
         }
-        // child k: lo (q0[k], q1[k], q2[k]), hi (q3[k], q4[k], q5[k])
         float tn[4];
         bool hit[4];
         int32_t first[4], cnt[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const float lox = k == 0 ? q0.x : k == 1 ? q0.y : k == 2 ? q0.z : q0.w;
-            const float loy = k == 0 ? q1.x : k == 1 ? q1.y : k == 2 ? q1.z : q1.w;
-            const float loz = k == 0 ? q2.x : k == 1 ? q2.y : k == 2 ? q2.z : q2.w;
-            const float hix = k == 0 ? q3.x : k == 1 ? q3.y : k == 2 ? q3.z : q3.w;
-            const float hiy = k == 0 ? q4.x : k == 1 ? q4.y : k == 2 ? q4.z : q4.w;
-            const float hiz = k == 0 ? q5.x : k == 1 ? q5.y : k == 2 ? q5.z : q5.w;
+            const float nx = k == 0 ? nx4.x : k == 1 ? nx4.y : k == 2 ? nx4.z : nx4.w;
+            const float ny = k == 0 ? ny4.x : k == 1 ? ny4.y : k == 2 ? ny4.z : ny4.w;
+            const float nz = k == 0 ? nz4.x : k == 1 ? nz4.y : k == 2 ? nz4.z : nz4.w;
+            const float fx = k == 0 ? fx4.x : k == 1 ? fx4.y : k == 2 ? fx4.z : fx4.w;
+            const float fy = k == 0 ? fy4.x : k == 1 ? fy4.y : k == 2 ? fy4.z : fy4.w;
+            const float fz = k == 0 ? fz4.x : k == 1 ? fz4.y : k == 2 ? fz4.z : fz4.w;
             first[k] = k == 0 ? cidx.x : k == 1 ? cidx.y : k == 2 ? cidx.z : cidx.w;
             cnt[k] = k == 0 ? ccnt.x : k == 1 ? ccnt.y : k == 2 ? ccnt.z : ccnt.w;
-            const float t0x = fmaf(lox, ix, nlx), t1x = fmaf(hix, ix, nhx);
-            const float t0y = fmaf(loy, iy, nly), t1y = fmaf(hiy, iy, nhy);
-            const float t0z = fmaf(loz, iz, nlz), t1z = fmaf(hiz, iz, nhz);
-            tn[k] = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fminf(t0z, t1z));
-            const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)) * slack;
-            hit[k] = cnt[k] >= 0 && tn[k] <= tf && tf >= 0.0f && tn[k] <= tb;
+            tn[k] = fmaxf(fmaxf(fmaf(nx, ix, cnx), fmaf(ny, iy, cny)), fmaf(nz, iz, cnz));
+            const float tf =
+                fminf(fminf(fmaf(fx, ix, cfx), fmaf(fy, iy, cfy)), fmaf(fz, iz, cfz)) * slack;
+            // an empty slot (cnt < 0) has the inverted box: tn = +inf, tf = -inf
+            hit[k] = tn[k] <= tf && tf >= 0.0f && tn[k] <= tb;
         }
         // leaf children first: their hits can only shrink the pruning bound
         uint32_t leaves = 0;
@@ -495,6 +520,103 @@ __device__ static bool follow(const SceneDev& S, const LdsPlan& L, d3 tx, d3 d0,
         if (pts) pts[j] = on;
         prev = h.face;
     }
+}
+
+// Triangle i read at a wave-uniform index: from LDS when staged, else
+// through the constant address space, so that the compiler issues scalar
+// loads (the scene is never written while a kernel reads it).
+template <bool LDS>
+__device__ static inline TriD tri_uniform(const SceneDev& S, const LdsPlan& L, int32_t i)
+{
+    if (LDS && i < L.n_tris) return tri_at<LDS>(S, L, i);
+    typedef const __attribute__((address_space(4))) d2v* cp;
+    const cp q = (cp)(S.tris + i);
+    auto g = [](d2v v) { return make_double2(v.x, v.y); };
+    return make_tri(g(q[0]), g(q[1]), g(q[2]), g(q[3]), g(q[4]));
+}
+
+__device__ static inline int32_t ild_uniform(const int32_t* p)
+{
+    return *(const __attribute__((address_space(4))) int32_t*)p;
+}
+
+// One lane's share of follow() with the segments of a sub-ray spread over
+// lanes: lane j (0 <= j <= k) checks segment j only.  The segments before it
+// are stepped through with the closest hit on each expected face, which is
+// the hit follow() seeds its search with and, whenever that segment passes,
+// the hit it then reflects at; so lane j starts segment j exactly where
+// follow() would and runs the same search.  Segment j < k passes when its
+// search ends on the expected face (the reflection point and incoming
+// direction go to pt and din), segment k when Rx is captured before the next
+// obstacle (F as follow()).  follow() succeeds exactly when every lane of the
+// sub-ray does, with the same F and geometry.  faces and k must be uniform
+// over the wave (the face data are then read with scalar loads).
+template <bool LDS, int BLK = 256>
+__device__ static bool seg_lane(const SceneDev& S, const LdsPlan& L, d3 tx, d3 d0, d3 rx, int k,
+                                int j, const int32_t* faces, float delta, Follow* F, d3* pt,
+                                d3* din, int32_t* err)
+{
+    d3 o = tx, d = d0;
+    double D = 0.0;
+    int32_t prev = -1;
+    HitRec h;
+    h.pos = -1;
+    h.t = INFINITY;
+    h.face = 0x7fffffff;
+    h.orig = 0x7fffffff;
+    for (int jj = 0; jj < k; ++jj) {
+        // closest hit on the face expected at segment jj
+        const int32_t fe = face_at(faces, jj);
+        if (fe == prev) return false;  // follow() cannot meet fe there
+        h.pos = -1;
+        h.t = INFINITY;
+        h.face = 0x7fffffff;
+        h.orig = 0x7fffffff;
+        const int32_t q1 = ild_uniform(S.fstart + fe + 1);
+        for (int32_t q = ild_uniform(S.fstart + fe); q < q1; ++q) {
+            const int32_t i = ild_uniform(S.ftris + q);
+            const TriD T = tri_uniform<LDS>(S, L, i);
+            double t;
+            if (!mt_hit(T, o, d, S.t_eps, INFINITY, &t)) continue;
+            if (h.pos < 0 || t < h.t ||
+                (t == h.t && (T.face < h.face || (T.face == h.face && T.orig < h.orig)))) {
+                h.pos = i;
+                h.t = t;
+                h.face = T.face;
+                h.orig = T.orig;
+            }
+        }
+        if (h.pos < 0) return false;  // no triangle of fe ahead: follow() fails
+        if (jj == j) break;
+        d3 nf = face_normal(S, fe);
+        d3 on = add(o, scl(h.t, d));
+        double k2 = 2.0 * dot(d, nf);
+        d = sub(d, scl(k2, nf));
+        D = D + h.t;
+        o = on;
+        prev = fe;
+    }
+    if (j == k) {
+        h.pos = -1;
+        h.t = INFINITY;
+        h.face = 0x7fffffff;
+        h.orig = 0x7fffffff;
+    }
+    int32_t hit = traverse<false, false, LDS, BLK>(S, L, o, d, prev, prev, S.t_eps, INFINITY,
+                                                   delta, &h, err, nullptr, j < k);
+    if (j == k) {
+        double t = hit < 0 ? INFINITY : h.t;
+        double tn;
+        if (!capture(o, d, D, t, rx, -1.0, &tn)) return false;
+        F->tan_err = tn;
+        F->D = D;
+        F->Llast = norm(sub(rx, o));
+        return true;
+    }
+    if (hit < 0 || h.face != face_at(faces, j)) return false;
+    *pt = add(o, scl(h.t, d));
+    *din = d;
+    return true;
 }
 
 }  // namespace sbr

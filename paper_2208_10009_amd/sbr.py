@@ -73,7 +73,7 @@ class Tuning(C.Structure):
                 ("lds_budget", C.c_int32), ("rx_tree_min", C.c_int32),
                 ("lookahead_max_paths", C.c_int64), ("lookahead_depth", C.c_int32),
                 ("lookahead3_max_paths", C.c_int32), ("grid_check_log2", C.c_int32),
-                ("ray_order", C.c_int32)]
+                ("ray_order", C.c_int32), ("refine_segments", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

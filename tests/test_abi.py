@@ -74,8 +74,9 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu\n", offsetof(sbr_path, launch_ray), offsetof(sbr_path, tan_err),
          offsetof(sbr_path, delay_s), offsetof(sbr_path, exact_delay_s),
          offsetof(sbr_path, init_tan_err), offsetof(sbr_candidate, tan_err));
-  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(sbr_tuning), offsetof(sbr_tuning, lookahead_max_paths),
-         offsetof(sbr_tuning, ray_order), sizeof(sbr_bvh_params),
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(sbr_tuning),
+         offsetof(sbr_tuning, lookahead_max_paths), offsetof(sbr_tuning, ray_order),
+         offsetof(sbr_tuning, refine_segments), sizeof(sbr_bvh_params),
          offsetof(sbr_bvh_params, split_pct), sizeof(sbr_job));
   return 0;
 }
@@ -107,8 +108,8 @@ def test_binding_layouts_match_header():
                     P.fields["exact_delay_s"][1], P.fields["init_tan_err"][1],
                     K.fields["tan_err"][1]]
     assert more == [C.sizeof(sbr.Tuning), sbr.Tuning.lookahead_max_paths.offset,
-                    sbr.Tuning.ray_order.offset, C.sizeof(sbr.BvhParams),
-                    sbr.BvhParams.split_pct.offset, C.sizeof(sbr.Job)]
+                    sbr.Tuning.ray_order.offset, sbr.Tuning.refine_segments.offset,
+                    C.sizeof(sbr.BvhParams), sbr.BvhParams.split_pct.offset, C.sizeof(sbr.Job)]
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

@@ -134,6 +134,28 @@ def test_large_city_paths_sampled(city, city_run, orc):
         assert key_of(p) + (int(p["launch_ray"]), int(bits(p["init_tan_err"])[0])) in have
 
 
+def test_large_city_refinement_kernels_agree(gpu, city, city_run):
+    """At full size, in the stated configuration and in the 0.01 deg target
+    mode (up to 30 iterations, long paths with grazing terrain bounces), the
+    segment-parallel refinement (a lane per sub-ray segment), the two-level
+    lookahead kernel and the work queue give byte-identical paths."""
+    cfg, sc = city
+    base = gpu.tuning()
+    try:
+        for prm in (cfg["params"], dict(cfg["params"], iterations=30, target_err_deg=0.01)):
+            got = {}
+            for name, t in (("segments", dict(refine_segments=1)),
+                            ("two-level", dict(refine_segments=0, lookahead_depth=2)),
+                            ("queue", dict(lookahead_depth=0))):
+                gpu.set_tuning(**dict(base, lookahead_max_paths=4096, **t))
+                got[name] = sc.trace(cfg["tx"], cfg["rx"], keep_invalid=True, **prm)[0]
+            assert len(got["segments"]) == len(city_run[1])
+            assert got["segments"].tobytes() == got["two-level"].tobytes() == \
+                got["queue"].tobytes()
+    finally:
+        gpu.set_tuning(**base)
+
+
 def test_rx_tree_matches_linear_and_oracle(gpu, orc):
     """1024 receivers on the Manhattan grid: reception through the receiver
     ball tree and by testing every receiver give byte-identical events and

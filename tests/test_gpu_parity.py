@@ -388,17 +388,22 @@ def _trace_with_env(env, cfg, **prm):
                                  dict(iterations=13, subrays=6)])
 def test_refine_lookahead_matches_single_step(gpu, orc, prm):
     """The three-iteration (512 lanes per path) and two-iteration (64 lanes)
-    lookahead kernels, the one-iteration kernel (8 lanes per path) and the
-    persistent work-queue refinement (depth 0) give byte-identical paths, and
-    all match the oracle."""
+    lookahead kernels, the one-iteration kernel (8 lanes per path), the
+    segment-parallel kernel (a wave per path, a lane per sub-ray segment) and
+    the persistent work-queue refinement (depth 0) give byte-identical paths,
+    and all match the oracle."""
     cfg = scenes.manhattan_config(2, n_rx=24)
     full = dict(cfg["params"], division_n=80, **prm)
     a = _trace_with_env({"SBR_LOOKAHEAD_PATHS": "0", "SBR_LOOKAHEAD_DEPTH": "1"}, cfg, **full)
-    b = _trace_with_env({"SBR_LOOKAHEAD_PATHS": "100000", "SBR_LOOKAHEAD_DEPTH": "2"}, cfg, **full)
+    b = _trace_with_env({"SBR_LOOKAHEAD_PATHS": "100000", "SBR_LOOKAHEAD_DEPTH": "2",
+                         "SBR_REFINE_SEGMENTS": "0"}, cfg, **full)
     c = _trace_with_env({"SBR_LOOKAHEAD_PATHS": "100000", "SBR_LOOKAHEAD_DEPTH": "3",
-                         "SBR_LOOKAHEAD3_PATHS": "100000"}, cfg, **full)
+                         "SBR_LOOKAHEAD3_PATHS": "100000", "SBR_REFINE_SEGMENTS": "0"}, cfg,
+                        **full)
     q = _trace_with_env({"SBR_LOOKAHEAD_DEPTH": "0"}, cfg, **full)
-    assert a.tobytes() == b.tobytes() == c.tobytes() == q.tobytes()
+    g = _trace_with_env({"SBR_LOOKAHEAD_PATHS": "100000", "SBR_REFINE_SEGMENTS": "1"}, cfg,
+                        **full)
+    assert a.tobytes() == b.tobytes() == c.tobytes() == q.tobytes() == g.tobytes()
     o = orc.run(cfg["scene"], cfg["tx"], cfg["rx"], **full)["paths"]
     _compare_paths(a, o)
 
@@ -410,7 +415,7 @@ def test_refine_three_level_lds_matches_global(gpu, orc, seed, order):
     cfg = scenes.manhattan_config(seed, n_rx=20)
     full = dict(cfg["params"], division_n=70, max_order=order, iterations=7)
     env = {"SBR_LOOKAHEAD_PATHS": "100000", "SBR_LOOKAHEAD_DEPTH": "3",
-           "SBR_LOOKAHEAD3_PATHS": "100000"}
+           "SBR_LOOKAHEAD3_PATHS": "100000", "SBR_REFINE_SEGMENTS": "0"}
     a = _trace_with_env(dict(env, SBR_LA3_LDS="1"), cfg, **full)
     b = _trace_with_env(dict(env, SBR_LA3_LDS="0"), cfg, **full)
     assert a.tobytes() == b.tobytes() and len(a) > 20
@@ -560,13 +565,15 @@ def test_batch_queue_mixed_iterations(gpu, seed):
     """Jobs of one batch with their own iteration counts (0 to 11), sub-ray
     counts and targets share the persistent refinement queue (depth 0): every
     job's paths are byte for byte those of its own single call with the
-    lookahead kernels, and of the batch and the single calls refined the
-    other way round."""
+    segment-parallel kernel (the default), and of the batch and the single
+    calls refined the other ways (queue, lookahead kernels)."""
     b = _mixed_batch(seed)
     ref = _individual(gpu, b)
     scs = [gpu.scene(s) for s in b["scenes"]]
     base = gpu.tuning()
     try:
+        got_seg, _ = gpu.trace_batch(scs, b["jobs"], b["rx"])
+        gpu.set_tuning(**dict(base, refine_segments=0))
         got_la, _ = gpu.trace_batch(scs, b["jobs"], b["rx"])
         gpu.set_tuning(**dict(base, lookahead_depth=0))
         got, _ = gpu.trace_batch(scs, b["jobs"], b["rx"])
@@ -576,7 +583,8 @@ def test_batch_queue_mixed_iterations(gpu, seed):
         for s in scs:
             s.close()
     assert len(ref) > 15
-    assert got.tobytes() == ref.tobytes() == ref_q.tobytes() == got_la.tobytes()
+    assert got.tobytes() == ref.tobytes() == ref_q.tobytes() == got_la.tobytes() == \
+        got_seg.tobytes()
     assert len(np.unique(got["iters_used"])) > 2
 
 
@@ -671,8 +679,10 @@ def test_tuning_roundtrip_and_invariance(gpu):
                   dict(lds_budget=65536, stack_depth=8, trace_block=128),
                   dict(lds_budget=24 * 4 * 256, stack_depth=24),
                   dict(lookahead_max_paths=0, trace_chunk=64), dict(rx_tree_min=1),
-                  dict(lookahead_depth=2), dict(lookahead_depth=1), dict(lookahead_depth=0),
-                  dict(ray_order=0),
+                  dict(lookahead_depth=2, refine_segments=0), dict(lookahead_depth=1),
+                  dict(lookahead_depth=0), dict(lookahead_depth=3, refine_segments=0),
+                  dict(ray_order=0), dict(refine_segments=0),
+                  dict(refine_segments=1, lds_budget=65536, stack_depth=8),
                   dict(ray_order=0, trace_chunk=2, lds_budget=24 * 4 * 256)):
             gpu.set_tuning(**dict(base, **t))
             assert gpu.tuning()["trace_chunk"] == dict(base, **t)["trace_chunk"]
@@ -688,6 +698,8 @@ def test_tuning_roundtrip_and_invariance(gpu):
             gpu.set_tuning(lookahead_depth=-1)
         with pytest.raises(sbr.SbrError):
             gpu.set_tuning(ray_order=2)
+        with pytest.raises(sbr.SbrError):
+            gpu.set_tuning(refine_segments=2)
     finally:
         gpu.set_tuning(**base)
         sc.close()
