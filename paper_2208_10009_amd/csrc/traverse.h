@@ -458,6 +458,30 @@ __device__ static inline int32_t face_at(const int32_t* faces, int j)
     return f;
 }
 
+// The last segment of a sub-ray (origin o after the path's reflections):
+// Rx is captured when its foot t* = (Rx - o).d satisfies 0 < t* <= t for the
+// segment's closest hit t.  That holds exactly when no triangle is hit in
+// (t_eps, t*): the closest hit is then at t* or beyond (a hit exactly at t*
+// lies outside the open range and passes, as t* <= t does), and a hit inside
+// the range makes the closest one fall short.  So the last segment's search
+// is bounded by t* instead of running along the whole ray, and the capture
+// test then takes t = infinity.  last_bound gives t* (false: Rx is behind).
+__device__ static inline bool last_bound(d3 o, d3 d, d3 rx, double* ts)
+{
+    *ts = dot(sub(rx, o), d);
+    return *ts > 0.0;
+}
+
+__device__ static inline bool last_capture(d3 o, d3 d, double D, d3 rx, Follow* F)
+{
+    double tn;
+    if (!capture(o, d, D, INFINITY, rx, -1.0, &tn)) return false;
+    F->tan_err = tn;
+    F->D = D;
+    F->Llast = norm(sub(rx, o));
+    return true;
+}
+
 // Trace direction d0 from Tx through exactly the faces of a path of order k
 // and report the error angle of Rx on the last segment (no cone condition).
 // A sub-ray is a usable path only if it meets the same faces in the same
@@ -497,18 +521,11 @@ __device__ static bool follow(const SceneDev& S, const LdsPlan& L, d3 tx, d3 d0,
                     }
                 }
         }
-        int32_t hit =
-            traverse<false, false, LDS, BLK>(S, L, o, d, prev, prev, S.t_eps, INFINITY, delta, &h,
-                                             err, nullptr, j < k);
-        if (j == k) {
-            double t = hit < 0 ? INFINITY : h.t;
-            double tn;
-            if (!capture(o, d, D, t, rx, -1.0, &tn)) return false;
-            F->tan_err = tn;
-            F->D = D;
-            F->Llast = norm(sub(rx, o));
-            return true;
-        }
+        double thi = INFINITY;
+        if (j == k && !last_bound(o, d, rx, &thi)) return false;
+        int32_t hit = traverse<false, false, LDS, BLK>(S, L, o, d, prev, prev, S.t_eps, thi,
+                                                       delta, &h, err, nullptr, j < k);
+        if (j == k) return hit < 0 && last_capture(o, d, D, rx, F);
         if (hit < 0 || h.face != face_at(faces, j)) return false;
         d3 nf = face_normal(S, h.face);
         d3 on = add(o, scl(h.t, d));
@@ -596,23 +613,17 @@ __device__ static bool seg_lane(const SceneDev& S, const LdsPlan& L, d3 tx, d3 d
         o = on;
         prev = fe;
     }
+    double thi = INFINITY;
     if (j == k) {
+        if (!last_bound(o, d, rx, &thi)) return false;
         h.pos = -1;
         h.t = INFINITY;
         h.face = 0x7fffffff;
         h.orig = 0x7fffffff;
     }
-    int32_t hit = traverse<false, false, LDS, BLK>(S, L, o, d, prev, prev, S.t_eps, INFINITY,
-                                                   delta, &h, err, nullptr, j < k);
-    if (j == k) {
-        double t = hit < 0 ? INFINITY : h.t;
-        double tn;
-        if (!capture(o, d, D, t, rx, -1.0, &tn)) return false;
-        F->tan_err = tn;
-        F->D = D;
-        F->Llast = norm(sub(rx, o));
-        return true;
-    }
+    const int32_t hit = traverse<false, false, LDS, BLK>(S, L, o, d, prev, prev, S.t_eps, thi,
+                                                         delta, &h, err, nullptr, j < k);
+    if (j == k) return hit < 0 && last_capture(o, d, D, rx, F);
     if (hit < 0 || h.face != face_at(faces, j)) return false;
     *pt = add(o, scl(h.t, d));
     *din = d;
