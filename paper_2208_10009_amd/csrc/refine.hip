@@ -485,33 +485,37 @@ __global__ __launch_bounds__(256) void k_refine_seg(CallDev call, LdsPlan L, Sce
     }
     Follow F{0.0, 0.0, 0.0};
     d3 pt = mk(0.0, 0.0, 0.0), din = pt;
-    // start (start_path): with a target, the launch ray is replayed by lanes (0, j)
-    double tan = c.tan_err;
-    bool met = false;
-    if (J.tan_tgt > 0.0) {
-        bool ok = false;
-        if (s == 0) ok = seg_lane<LDS>(S, L, tx, axis, rx, k, j, faces, J.delta, &F, &pt, &din, err);
-        if (__ballot(s == 0 && !ok)) {
-            if (lane == 0) out[p] = stalled_at_start(axis);
-            return;
-        }
-        tan = __shfl(F.tan_err, k);
-        met = target_met(tan, J.tan_tgt, __shfl(F.D, k), __shfl(F.Llast, k));
-    }
     const bool act = s < J.subrays;
     const unsigned long long segs = ((1ull << K1) - 1) << (act ? s * K1 : 0);
-    uint32_t flags = met ? SBR_PATH_TARGET_MET : 0u;
+    double tan = c.tan_err;
+    bool met = false;
+    uint32_t flags = 0u;
     int32_t iters = 0;
     double rho = J.thl;
-    for (int i = 1; i <= J.iterations && !met; ++i) {
-        rho = rho / sqrt(3.0);
-        d3 u, v;
-        basis(axis, &u, &v);
+    // Step 0 (with a target only) replays the launch ray on lanes (0, j), as
+    // start_path does; steps 1.. are the iterations.  One loop, so that the
+    // kernel holds a single copy of the segment search.
+    for (int i = J.tan_tgt > 0.0 ? 0 : 1; i <= J.iterations && !met; ++i) {
+        d3 u, v, dt = axis;
+        if (i > 0) {
+            rho = rho / sqrt(3.0);
+            basis(axis, &u, &v);
+            dt = subray(axis, u, v, rho, s);
+        }
+        const bool on = i > 0 ? act : s == 0;
         bool ok = false;
-        if (act)
-            ok = seg_lane<LDS>(S, L, tx, subray(axis, u, v, rho, s), rx, k, j, faces, J.delta, &F,
-                               &pt, &din, err);
-        const unsigned long long bad = __ballot(act && !ok);
+        if (on) ok = seg_lane<LDS>(S, L, tx, dt, rx, k, j, faces, J.delta, &F, &pt, &din, err);
+        const unsigned long long bad = __ballot(on && !ok);
+        if (i == 0) {
+            if (bad) {
+                if (lane == 0) out[p] = stalled_at_start(axis);
+                return;
+            }
+            tan = __shfl(F.tan_err, k);
+            met = target_met(tan, J.tan_tgt, __shfl(F.D, k), __shfl(F.Llast, k));
+            if (met) flags = SBR_PATH_TARGET_MET;
+            continue;
+        }
         const bool keep = act && j == k && (bad & segs) == 0;
         double bt = keep ? F.tan_err : INFINITY;
         int bs = keep ? s : 8;
