@@ -67,7 +67,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-TRACE_SOURCES = ("trace.hip", "traverse.h", "internal.h", "geom.h")
+TRACE_SOURCES = ("trace.hip", "traverse.h", "layout.h", "geom.h")
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_trace_counters.txt")
 
 

@@ -175,11 +175,14 @@ typedef struct {
  * most 2^27 rays), so the 64 rays of a wave leave in nearby directions and
  * traverse the same BVH nodes; 0 hands them out by index (same results).
  * With refine_segments = 1 (and a depth other than 0), up to
- * lookahead_max_paths paths are refined one iteration per step by one wave
- * per path whose lanes trace the k + 1 segments of every sub-ray at once:
- * lane (s, j) starts segment j where the chain of closest hits on the
- * expected faces puts it, so a step waits for the slowest segment instead of
- * the k + 1 segments in a row (same results). */
+ * lookahead_max_paths paths are refined with the k + 1 segments of every
+ * sub-ray traced at once by separate lanes: a lane starts its segment where
+ * the chain of closest hits on the expected faces puts it, so a step waits
+ * for the slowest segment instead of the k + 1 segments in a row (same
+ * results).  Up to lookahead3_max_paths paths get a 512-lane workgroup each
+ * and two iterations per step; more get one wave each and one iteration per
+ * step, and those still running after ten iterations continue two per step
+ * on 512-lane workgroups. */
 typedef struct {
     int32_t trace_chunk;         /* 1..64                                   */
     int32_t persist_blocks;      /* >= 1                                    */

@@ -157,6 +157,10 @@ struct sbr_context {
     int32_t lookahead_depth = 3;
     int32_t lookahead3_max_paths = 256;
     int32_t refine_segments = 1;
+    // segment-parallel refinement of many paths: iterations on one wave per
+    // path before the paths still running move to 512-lane workgroups
+    // (SBR_SEG_TAIL; 0: never)
+    int32_t seg_tail = 10;
     int32_t grid_check_log2 = 0;
     bool la3_lds = true;  // stage the scene in LDS for the three-level refinement
     // event and path counts of the last device-memory call, which predict
@@ -405,7 +409,8 @@ int env_int(const char* name, int dflt, int lo, int hi)
 LdsPlan plan_la3(const sbr_scene* s)
 {
     const sbr_context* c = s->ctx;
-    LdsPlan L = make_lds_plan(s->n_nodes, s->R, 512, 16, c->lds_max - 1024);
+    // 2 KB left for the kernels' static LDS
+    LdsPlan L = make_lds_plan(s->n_nodes, s->R, 512, 16, c->lds_max - 2048);
     if (!c->la3_lds || L.n_tris != s->R || L.depth != 16) {
         L = LdsPlan{};
         L.block = 512;
@@ -696,11 +701,18 @@ int trace_blocks(const sbr_context* c, const Call& call)
 // Iterations per refinement step for U paths: three only for few paths
 // (latency-bound), two up to lookahead_max_paths, else one; 0 selects the
 // persistent work-queue refinement.
+int32_t max_iterations(const Call& call)
+{
+    int32_t m = 0;
+    for (const JobDev& J : call.jobs) m = std::max(m, J.iterations);
+    return m;
+}
+
 int refine_depth(const sbr_context* c, int64_t U)
 {
     if (c->lookahead_depth == 0) return 0;
     if (U > c->lookahead_max_paths) return 1;
-    if (c->refine_segments) return kRefineSegments;
+    if (c->refine_segments) return U > c->lookahead3_max_paths ? kRefineSegments : kRefineSegments2;
     if (c->lookahead_depth >= 3 && U > c->lookahead3_max_paths) return 2;
     return c->lookahead_depth;
 }
@@ -896,7 +908,7 @@ sbr_status run_paths(sbr_context* c, Call& call, sbr_path* out, int64_t capacity
         HIPCHK(c, hipEventRecord(c->ev_join, c->stream2));
         HIPCHK(c, launch_refine(call.dev, lp256, lp3, call.s0, c->uniq.as<sbr_candidate>(), Umax,
                                 ndev, depth, c->refine.as<RefineOut>(), c->geom.as<PathGeom>(),
-                                &dc->err, st));
+                                &dc->err, st, max_iterations(call), c->seg_tail));
         HIPCHK(c, hipEventRecord(c->ev[4], st));
         HIPCHK(c, hipStreamWaitEvent(st, c->ev_join, 0));
     }
@@ -1115,9 +1127,10 @@ sbr_status sbr_context_create(int32_t device, void* hip_stream, sbr_context** ou
         c->lookahead_depth = env_int("SBR_LOOKAHEAD_DEPTH", 3, 0, 3);
         c->lookahead3_max_paths = env_int("SBR_LOOKAHEAD3_PATHS", 256, 0, 1 << 30);
         c->refine_segments = env_int("SBR_REFINE_SEGMENTS", 1, 0, 1);
+        c->seg_tail = env_int("SBR_SEG_TAIL", 10, 0, 200);
         c->la3_lds = env_int("SBR_LA3_LDS", 1, 0, 1) != 0;
         c->ray_order = env_int("SBR_RAY_ORDER", 1, 0, 1);
-        if (refine_la3_set_lds_limit(c->lds_max - 1024) != hipSuccess) {
+        if (refine_la3_set_lds_limit(c->lds_max - 2048) != hipSuccess) {
             (void)hipGetLastError();
             c->la3_lds = false;
         }
@@ -1685,7 +1698,7 @@ sbr_status capture_graph(sbr_context* c, sbr_scene* s, Call& call, const double*
                             &dc->n_unique, st, &dc->cand));
     step(launch_refine(call.dev, lp256, plan_la3(s), call.s0, c->uniq.as<sbr_candidate>(), u_cap,
                        &dc->n_unique, depth, c->refine.as<RefineOut>(), c->geom.as<PathGeom>(),
-                       &dc->err, st));
+                       &dc->err, st, max_iterations(call), c->seg_tail));
     step(launch_solve(call.dev, c->uniq.as<sbr_candidate>(), c->refine.as<RefineOut>(),
                       c->geom.as<PathGeom>(), u_cap, &dc->n_unique, c->paths.as<sbr_path>(),
                       c->keep.as<int32_t>(), &dc->err, st));
@@ -1915,7 +1928,7 @@ sbr_status capture_bgraph(sbr_context* c, Call& call, const sbr_job* jobs, int32
                             &dc->n_unique, st, &dc->cand));
     step(launch_refine(call.dev, lp256, lp3, call.s0, c->uniq.as<sbr_candidate>(), u_cap,
                        &dc->n_unique, depth, c->refine.as<RefineOut>(), c->geom.as<PathGeom>(),
-                       &dc->err, st));
+                       &dc->err, st, max_iterations(call), c->seg_tail));
     step(launch_solve(call.dev, c->uniq.as<sbr_candidate>(), c->refine.as<RefineOut>(),
                       c->geom.as<PathGeom>(), u_cap, &dc->n_unique, c->paths.as<sbr_path>(),
                       c->keep.as<int32_t>(), &dc->err, st));
@@ -2169,7 +2182,7 @@ sbr_status sbr_trace_device_noalloc(sbr_scene* s, const double tx[3], const doub
     lp256.block = 256;
     const int depth = std::max(1, refine_depth(c, c->noalloc_unique >= 0 ? c->noalloc_unique : 256));
     HIPCHK(c, launch_refine(D, lp256, plan_la3(s), S0, uniq, kSmallEvents, &dc->n_unique, depth,
-                            rf, geom, &dc->err, st));
+                            rf, geom, &dc->err, st, p->iterations, c->seg_tail));
     HIPCHK(c, hipEventRecord(c->ev[4], st));
     HIPCHK(c, launch_solve(D, uniq, rf, geom, kSmallEvents, &dc->n_unique, paths, keep,
                            &dc->err, st));

@@ -5,8 +5,8 @@
 #include <algorithm>
 
 #include "cone.h"
+#include "follow.h"
 #include "refine_queue.h"
-#include "traverse.h"
 
 namespace sbr {
 
@@ -268,6 +268,186 @@ __global__ __launch_bounds__(256) void k_refine_la(CallDev call, LdsPlan L, Scen
     }
 }
 
+// One workgroup of 512 lanes per path, two iterations per step, every
+// sub-ray's segments traced at once: lane t = sub (k + 1) + j checks segment j
+// of sub-ray sub = 8 s1 + s2, where s2 = 7 marks first-level sub-ray s1 and
+// s2 < subrays the second-level sub-ray s2 of the cone that s1 would open
+// (as k_refine_la); at most 56 sub-rays of 9 segments fill 504 lanes.  A
+// sub-ray's lanes may lie in different waves, so failures and error angles
+// meet in LDS; the winners are picked level by level with the ties, stop
+// rules and geometry of k_refine, so the result is the same bit for bit.
+// resume = 0 starts every path (step 0 replays the launch ray with a
+// target); resume = 1 continues the paths k_refine_seg left unfinished at
+// its iteration limit (neither stalled nor at the target, iterations left),
+// from their recorded axis, error, flags and iteration count (the cone
+// radius rebuilt by the same successive divisions), and leaves the others.
+template <bool LDS>
+__global__ __launch_bounds__(512) void k_refine_seg2(CallDev call, LdsPlan L, SceneDev s0,
+                                                     const sbr_candidate* __restrict__ uniq,
+                                                     int64_t U_max,
+                                                     const int32_t* __restrict__ n_dev,
+                                                     RefineOut* __restrict__ out,
+                                                     PathGeom* __restrict__ geom,
+                                                     int32_t* __restrict__ err, int32_t resume)
+{
+    if (LDS) stage_scene(s0, L);
+    __shared__ double sk[64], sD[64], sL[64];
+    __shared__ int32_t sbad[64];
+    const int64_t p = blockIdx.x;
+    const int t = threadIdx.x;
+    const int64_t U = n_dev ? min(U_max, (int64_t)*n_dev) : U_max;
+    if (p >= U) return;  // uniform over the workgroup
+    const sbr_candidate c = uniq[p];
+    const JobDev J = call.jobs[call.rx_job[c.rx]];
+    const SceneDev S = LDS ? s0 : call.scenes[J.scene];
+    const d3 tx = mk(J.tx[0], J.tx[1], J.tx[2]);
+    const d3 rx = mk(call.rx[3 * c.rx], call.rx[3 * c.rx + 1], call.rx[3 * c.rx + 2]);
+    d3 axis = mk(J.dir[c.ray], J.dir[J.N + c.ray], J.dir[2 * J.N + c.ray]);
+    const int k = __builtin_amdgcn_readfirstlane(c.order);
+    int32_t faces[SBR_MAX_ORDER];
+#pragma unroll
+    for (int q = 0; q < SBR_MAX_ORDER; ++q) faces[q] = __builtin_amdgcn_readfirstlane(c.face[q]);
+    const int K1 = k + 1;
+    const int sub = t / K1, j = t - sub * K1;
+    const int s1 = sub >> 3, s2 = sub & 7;
+    const int S_ = J.subrays;
+    double tan = c.tan_err;
+    uint32_t flags = 0u;
+    int32_t iters = 0;
+    double rho = J.thl;
+    int first = J.tan_tgt > 0.0 ? 0 : 1;
+    if (resume) {
+        const RefineOut o = out[p];
+        if ((o.flags & (SBR_PATH_STALLED | SBR_PATH_TARGET_MET)) || o.iters >= J.iterations)
+            return;  // uniform over the workgroup
+        axis = mk(o.axis[0], o.axis[1], o.axis[2]);
+        tan = o.tan_err;
+        flags = o.flags;
+        iters = o.iters;
+        for (int q = 0; q < iters; ++q) rho = rho / sqrt(3.0);
+        first = iters + 1;
+    }
+    Follow F{0.0, 0.0, 0.0};
+    d3 pt = mk(0.0, 0.0, 0.0), din = pt;
+    // the smallest error among slots base + q step, q < S_ (ties: lower q;
+    // a slot whose sub-ray failed counts as infinite); 8 when none is finite
+    auto argmin = [&](int base, int step, double* kb) {
+        int b = 8;
+        *kb = INFINITY;
+        for (int q = 0; q < S_; ++q) {
+            const int x = base + q * step;
+            const double v = sbad[x] ? INFINITY : sk[x];
+            if (v < *kb) {
+                *kb = v;
+                b = q;
+            }
+        }
+        return b;
+    };
+    for (int i = first; i <= J.iterations; i += 2) {
+        // step 0: lanes of sub-ray 0 replay the launch ray (start_path)
+        const bool replay = i == 0;
+        const double rho1 = rho / sqrt(3.0), rho2 = rho1 / sqrt(3.0);
+        d3 u, v;
+        basis(axis, &u, &v);
+        const bool two = !replay && i + 1 <= J.iterations;
+        const bool lvl1 = !replay && s2 == 7 && s1 < S_;
+        const bool lvl2 = two && s1 < S_ && s2 < S_;
+        const bool on = replay ? sub == 0 : (lvl1 || lvl2);
+        if (t < 64) sbad[t] = 0;
+        __syncthreads();
+        bool ok = false;
+        if (on) {
+            d3 dt = axis;
+            if (!replay) {
+                dt = subray(axis, u, v, rho1, s1);
+                if (lvl2) {
+                    d3 u2, v2;
+                    basis(dt, &u2, &v2);
+                    dt = subray(dt, u2, v2, rho2, s2);
+                }
+            }
+            ok = seg_lane<LDS, 512>(S, L, tx, dt, rx, k, j, faces, J.delta, &F, &pt, &din, err);
+            if (!ok) sbad[sub] = 1;
+            if (j == k) {
+                sk[sub] = ok ? F.tan_err : INFINITY;
+                sD[sub] = ok ? F.D : 0.0;
+                sL[sub] = ok ? F.Llast : 0.0;
+            }
+        }
+        if (!on && j == k && sub < 64) sk[sub] = INFINITY;
+        __syncthreads();
+        if (replay) {
+            if (sbad[0]) {
+                if (t == 0) out[p] = stalled_at_start(axis);
+                return;
+            }
+            tan = sk[0];
+            const bool met = target_met(tan, J.tan_tgt, sD[0], sL[0]);
+            __syncthreads();
+            if (met) {
+                flags = SBR_PATH_TARGET_MET;
+                break;
+            }
+            i = -1;  // the iterations start at 1
+            continue;
+        }
+        // first level: slots (s1, 7)
+        double k1;
+        const int b1 = argmin(7, 8, &k1);
+        if (b1 >= 8) {
+            flags |= SBR_PATH_STALLED;
+            break;
+        }
+        const double w1D = sD[b1 * 8 + 7], w1L = sL[b1 * 8 + 7];
+        if (on && sub == b1 * 8 + 7 && j < k) {
+            geom[p].pts[j] = pt;
+            geom[p].din[j] = din;
+        }
+        axis = subray(axis, u, v, rho1, b1);
+        tan = k1;
+        iters = i;
+        rho = rho1;
+        if (J.tan_tgt > 0.0 && target_met(k1, J.tan_tgt, w1D, w1L)) {
+            flags |= SBR_PATH_TARGET_MET;
+            break;
+        }
+        if (!two) break;
+        // second level: slots (b1, s2)
+        double k2;
+        const int b2 = argmin(b1 * 8, 1, &k2);
+        if (b2 >= 8) {
+            flags |= SBR_PATH_STALLED;
+            break;
+        }
+        const double w2D = sD[b1 * 8 + b2], w2L = sL[b1 * 8 + b2];
+        __threadfence_block();
+        __syncthreads();  // the first level's geometry is written
+        if (on && sub == b1 * 8 + b2 && j < k) {
+            geom[p].pts[j] = pt;
+            geom[p].din[j] = din;
+        }
+        basis(axis, &u, &v);
+        axis = subray(axis, u, v, rho2, b2);
+        tan = k2;
+        iters = i + 1;
+        rho = rho2;
+        if (J.tan_tgt > 0.0 && target_met(k2, J.tan_tgt, w2D, w2L)) {
+            flags |= SBR_PATH_TARGET_MET;
+            break;
+        }
+        __syncthreads();  // every lane has read the slots of this step
+    }
+    if (t == 0) {
+        RefineOut o;
+        st3(o.axis, axis);
+        o.tan_err = tan;
+        o.iters = iters;
+        o.flags = flags;
+        out[p] = o;
+    }
+}
+
 // One workgroup of 512 lanes per path, three iterations per step.  Lane
 // (s1, s2, s3) = (t >> 6, (t >> 3) & 7, t & 7) traces the sub-ray that the
 // sub-ray choices s1, then s2, then s3 would give; index 7 marks a level the
@@ -458,7 +638,7 @@ __global__ __launch_bounds__(256) void k_refine_seg(CallDev call, LdsPlan L, Sce
                                                     const int32_t* __restrict__ n_dev,
                                                     RefineOut* __restrict__ out,
                                                     PathGeom* __restrict__ geom,
-                                                    int32_t* __restrict__ err)
+                                                    int32_t* __restrict__ err, int32_t it_limit)
 {
     if (LDS) stage_scene(s0, L);
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -494,8 +674,10 @@ __global__ __launch_bounds__(256) void k_refine_seg(CallDev call, LdsPlan L, Sce
     double rho = J.thl;
     // Step 0 (with a target only) replays the launch ray on lanes (0, j), as
     // start_path does; steps 1.. are the iterations.  One loop, so that the
-    // kernel holds a single copy of the segment search.
-    for (int i = J.tan_tgt > 0.0 ? 0 : 1; i <= J.iterations && !met; ++i) {
+    // kernel holds a single copy of the segment search.  With it_limit > 0
+    // the kernel stops after that many iterations; k_refine_seg2 resumes.
+    const int32_t last = it_limit > 0 ? min(J.iterations, it_limit) : J.iterations;
+    for (int i = J.tan_tgt > 0.0 ? 0 : 1; i <= last && !met; ++i) {
         d3 u, v, dt = axis;
         if (i > 0) {
             rho = rho / sqrt(3.0);
@@ -802,17 +984,32 @@ hipError_t launch_refine_queue(const CallDev& call, const sbr_candidate* uniq, i
 hipError_t launch_refine(const CallDev& call, const LdsPlan& L, const LdsPlan& L3,
                          const SceneDev& s0, const sbr_candidate* uniq, int64_t U,
                          const int32_t* n_dev, int depth, RefineOut* out, PathGeom* geom,
-                         int32_t* err, hipStream_t s)
+                         int32_t* err, hipStream_t s, int32_t max_iters, int32_t tail_after)
 {
     if (U <= 0) return hipSuccess;
-    if (depth == kRefineSegments) {
-        dim3 grid((unsigned)((U * 64 + L.block - 1) / L.block));
-        if (L.bytes > 0)
-            hipLaunchKernelGGL(k_refine_seg<true>, grid, dim3(L.block), L.bytes, s, call, L, s0,
-                               uniq, U, n_dev, out, geom, err);
+    if (depth == kRefineSegments || depth == kRefineSegments2) {
+        int32_t resume = 0;
+        if (depth == kRefineSegments) {
+            // one wave per path; with a tail, it stops after tail_after
+            // iterations and the paths still running continue below
+            const int32_t lim = tail_after > 0 && max_iters > tail_after ? tail_after : 0;
+            dim3 grid((unsigned)((U * 64 + L.block - 1) / L.block));
+            if (L.bytes > 0)
+                hipLaunchKernelGGL(k_refine_seg<true>, grid, dim3(L.block), L.bytes, s, call, L,
+                                   s0, uniq, U, n_dev, out, geom, err, lim);
+            else
+                hipLaunchKernelGGL(k_refine_seg<false>, grid, dim3(L.block), 0, s, call, L, s0,
+                                   uniq, U, n_dev, out, geom, err, lim);
+            if (lim == 0) return hipGetLastError();
+            resume = 1;
+        }
+        // 512 lanes per path, two iterations per step (its own LDS plan, L3)
+        if (L3.bytes > 0)
+            hipLaunchKernelGGL(k_refine_seg2<true>, dim3((unsigned)U), dim3(512), L3.bytes, s,
+                               call, L3, s0, uniq, U, n_dev, out, geom, err, resume);
         else
-            hipLaunchKernelGGL(k_refine_seg<false>, grid, dim3(L.block), 0, s, call, L, s0, uniq,
-                               U, n_dev, out, geom, err);
+            hipLaunchKernelGGL(k_refine_seg2<false>, dim3((unsigned)U), dim3(512), 0, s, call,
+                               LdsPlan{}, s0, uniq, U, n_dev, out, geom, err, resume);
         return hipGetLastError();
     }
     // the three-level kernel has its own LDS plan (L3), whatever the trace's
@@ -1034,15 +1231,18 @@ __device__ static inline PathQ path_quantities(const SceneDev& S, const JobDev& 
     return q;
 }
 
-// Path test 2 and the exact path, sixteen lanes per path.  Lane 1 + j checks
+// Path test 2 and the exact path, one wave per path.  Lane 1 + j checks
 // segment j of the image-method path (reflection point j inside its face,
 // segment j unobstructed), so the test costs one traversal of latency
 // instead of k + 1; lane 1 then forms the exact path's quantities.  With
-// geom0, lane 0 meanwhile traces the path's launch ray into geom0[p], the
-// geometry of a path that the refinement ends without an iteration.  None of
-// this needs a refinement result, so it runs beside the refinement.  Writes
-// the record's identity, the exact_* fields, the INVALID flag (as the whole
-// flags field) and keep.
+// geom0, lanes 32 + j trace segment j of the path's launch ray (seg_lane)
+// into geom0[p], the geometry of a path that the refinement ends without an
+// iteration: as follow() writes it, a segment's reflection point and
+// incoming direction when it and every segment before it meet the expected
+// faces, zeros from the first that does not.  None of this needs a
+// refinement result, so it runs beside the refinement.  Writes the record's
+// identity, the exact_* fields, the INVALID flag (as the whole flags field)
+// and keep.
 __global__ __launch_bounds__(256) void k_solve_exact(CallDev call,
                                                      const sbr_candidate* __restrict__ uniq,
                                                      int64_t U_max,
@@ -1054,27 +1254,47 @@ __global__ __launch_bounds__(256) void k_solve_exact(CallDev call,
 {
     LdsPlan L{};
     L.block = 256;
-    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t p = gid >> 4;
-    int lane = (int)(gid & 15);
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t p = gid >> 6;
+    const int lane = (int)(gid & 63);
     const int64_t U = n_dev ? min(U_max, (int64_t)*n_dev) : U_max;
-    if (p >= U) return;
+    if (p >= U) return;  // uniform over the wave
     const sbr_candidate c = uniq[p];
-    const JobDev J = call.jobs[call.rx_job[c.rx]];
+    const JobDev J = call.jobs[__builtin_amdgcn_readfirstlane(call.rx_job[c.rx])];
     const SceneDev S = call.scenes[J.scene];
     const float delta = J.delta;
-    const int k = c.order;
+    const int k = __builtin_amdgcn_readfirstlane(c.order);
+    int32_t faces[SBR_MAX_ORDER];
+#pragma unroll
+    for (int q = 0; q < SBR_MAX_ORDER; ++q) faces[q] = __builtin_amdgcn_readfirstlane(c.face[q]);
     const d3 tx = mk(J.tx[0], J.tx[1], J.tx[2]);
     const d3 rx = mk(call.rx[3 * c.rx], call.rx[3 * c.rx + 1], call.rx[3 * c.rx + 2]);
+    // the launch ray's segments (geom0)
+    const int jg = lane - 32;
+    bool gok = false;
+    d3 gpt = mk(0.0, 0.0, 0.0), gdin = gpt;
+    if (geom0 && jg >= 0 && jg < k) {
+        const d3 axis0 = mk(J.dir[c.ray], J.dir[J.N + c.ray], J.dir[2 * J.N + c.ray]);
+        Follow F;
+        gok = seg_lane<false>(S, L, tx, axis0, rx, k, jg, faces, delta, &F, &gpt, &gdin, err);
+    }
+    const unsigned long long gfail = __ballot(geom0 && jg >= 0 && jg < k && !gok);
+    if (geom0 && jg >= 0 && jg < SBR_MAX_ORDER) {
+        // written when segments 0 .. jg all meet their faces
+        const bool w = jg < k && (gfail & (((2ull << jg) - 1) << 32)) == 0;
+        PathGeom* gm = geom0 + p;
+        gm->pts[jg] = w ? gpt : mk(0.0, 0.0, 0.0);
+        gm->din[jg] = w ? gdin : mk(0.0, 0.0, 0.0);
+    }
     d3 ep[SBR_MAX_ORDER];
-    const bool geo_ok = image_points(S, tx, rx, k, c.face, ep);
+    const bool geo_ok = image_points(S, tx, rx, k, faces, ep);
     bool bad = false;
     if (geo_ok && lane >= 1 && lane <= k + 1) {
         // by value from the register lists (a dynamic index would move
         // them to private memory)
         const int j = lane - 1;
         const d3 ej = pick8(ep, j), ejm = pick8(ep, j - 1);
-        const int32_t fj = face_at(c.face, j), fjm = face_at(c.face, j - 1);
+        const int32_t fj = face_at(faces, j), fjm = face_at(faces, j - 1);
         if (j < k && !inside_face<false>(S, L, fj, ej)) {
             bad = true;
         } else {
@@ -1085,19 +1305,7 @@ __global__ __launch_bounds__(256) void k_solve_exact(CallDev call,
             bad = blocked<false>(S, L, Pa, Pb, fa, fb, delta, err);
         }
     }
-    unsigned long long mask = __ballot(bad);
-    const int base = (int)(threadIdx.x & 63) & ~15;
-    const bool any_bad = ((mask >> base) & 0xffffull) != 0;
-    if (lane == 0 && geom0) {
-        PathGeom* gm = geom0 + p;
-        for (int j = 0; j < SBR_MAX_ORDER; ++j) {
-            gm->pts[j] = mk(0.0, 0.0, 0.0);
-            gm->din[j] = mk(0.0, 0.0, 0.0);
-        }
-        const d3 axis0 = mk(J.dir[c.ray], J.dir[J.N + c.ray], J.dir[2 * J.N + c.ray]);
-        Follow F;
-        follow<false>(S, L, tx, axis0, rx, k, c.face, delta, &F, gm->pts, gm->din, err);
-    }
+    const bool any_bad = __ballot(bad) != 0;
     if (lane != 1) return;
     // the exact path: the image points; incoming direction = point minus
     // the previous point
@@ -1193,7 +1401,7 @@ hipError_t launch_solve_exact(const CallDev& call, const sbr_candidate* uniq, in
                               PathGeom* geom0, int32_t* err, hipStream_t s)
 {
     if (U <= 0) return hipSuccess;
-    const int64_t threads = U * 16;
+    const int64_t threads = U * 64;
     hipLaunchKernelGGL(k_solve_exact, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
                        call, uniq, U, n_dev, paths, keep, geom0, err);
     return hipGetLastError();
@@ -1223,7 +1431,10 @@ hipError_t launch_solve(const CallDev& call, const sbr_candidate* uniq, const Re
 // limit is set separately, to what the caller's plans for it may use.
 hipError_t refine_la3_set_lds_limit(int bytes)
 {
-    return hipFuncSetAttribute((const void*)k_refine_la3<true>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_refine_la3<true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_refine_seg2<true>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
@@ -1232,7 +1443,10 @@ hipError_t refine_set_lds_limit(int bytes)
     hipError_t e = hipFuncSetAttribute((const void*)k_refine<true>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)k_refine_la<true>,
+    e = hipFuncSetAttribute((const void*)k_refine_la<true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_refine_seg<true>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 

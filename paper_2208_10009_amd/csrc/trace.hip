@@ -11,6 +11,7 @@
 
 #include <algorithm>
 
+#include "internal.h"
 #include "traverse.h"
 
 namespace sbr {

@@ -389,9 +389,10 @@ def _trace_with_env(env, cfg, **prm):
 def test_refine_lookahead_matches_single_step(gpu, orc, prm):
     """The three-iteration (512 lanes per path) and two-iteration (64 lanes)
     lookahead kernels, the one-iteration kernel (8 lanes per path), the
-    segment-parallel kernel (a wave per path, a lane per sub-ray segment) and
-    the persistent work-queue refinement (depth 0) give byte-identical paths,
-    and all match the oracle."""
+    segment-parallel kernels (a lane per sub-ray segment: a wave per path, a
+    512-lane workgroup per path, and the hand-over from the first to the
+    second) and the persistent work-queue refinement (depth 0) give
+    byte-identical paths, and all match the oracle."""
     cfg = scenes.manhattan_config(2, n_rx=24)
     full = dict(cfg["params"], division_n=80, **prm)
     a = _trace_with_env({"SBR_LOOKAHEAD_PATHS": "0", "SBR_LOOKAHEAD_DEPTH": "1"}, cfg, **full)
@@ -401,9 +402,18 @@ def test_refine_lookahead_matches_single_step(gpu, orc, prm):
                          "SBR_LOOKAHEAD3_PATHS": "100000", "SBR_REFINE_SEGMENTS": "0"}, cfg,
                         **full)
     q = _trace_with_env({"SBR_LOOKAHEAD_DEPTH": "0"}, cfg, **full)
-    g = _trace_with_env({"SBR_LOOKAHEAD_PATHS": "100000", "SBR_REFINE_SEGMENTS": "1"}, cfg,
-                        **full)
-    assert a.tobytes() == b.tobytes() == c.tobytes() == q.tobytes() == g.tobytes()
+    assert a.tobytes() == b.tobytes() == c.tobytes() == q.tobytes()
+    # segments in parallel lanes: one wave per path only; 512 lanes per path
+    # (two iterations per step) from the start; one wave per path handing the
+    # paths still running to 512-lane workgroups after 1 and after 2
+    # iterations (odd and even splits)
+    for env in ({"SBR_LOOKAHEAD3_PATHS": "0", "SBR_SEG_TAIL": "0"},
+                {"SBR_LOOKAHEAD3_PATHS": "100000"},
+                {"SBR_LOOKAHEAD3_PATHS": "0", "SBR_SEG_TAIL": "1"},
+                {"SBR_LOOKAHEAD3_PATHS": "0", "SBR_SEG_TAIL": "2"}):
+        g = _trace_with_env(dict(env, SBR_LOOKAHEAD_PATHS="100000", SBR_REFINE_SEGMENTS="1"), cfg,
+                            **full)
+        assert g.tobytes() == a.tobytes(), env
     o = orc.run(cfg["scene"], cfg["tx"], cfg["rx"], **full)["paths"]
     _compare_paths(a, o)
 
