@@ -333,3 +333,56 @@ def test_refined_diffraction_point_converges(orc):
         assert angle_deg(q["aod"], q["exact_aod"]) <= 1e-7
         assert angle_deg(q["aoa"], q["exact_aoa"]) <= 1e-6
         assert 0 <= q["length_m"] - q["exact_length_m"] < 1e-12 * q["exact_length_m"] + 1e-12
+
+
+# ------------------------------------------- the wedge's solid side, reach --
+def _hinge_long(angle_deg_between_normals, L=4.0):
+    t = math.radians(angle_deg_between_normals)
+    b = scenes.SceneBuilder()
+    b.quad((0, 0, 0), (0, L, 0), (-L, L, 0), (-L, 0, 0), 0)
+    c, s = math.cos(t), math.sin(t)
+    b.quad((0, 0, 0), (L * c, 0, L * s), (L * c, L, L * s), (0, L, 0), 0)
+    return b.scene([4 + 0j])
+
+
+@pytest.mark.parametrize("normals_deg", [60.0, 120.0])
+def test_receivers_inside_the_wedge_get_no_diffraction(orc, normals_deg):
+    """Sec. III.A: a diffracted ray leaves the edge into the space outside
+    the wedge.  Two plates meet at the edge x = z = 0 (along y); in the xz
+    plane face 0 points to 180 degrees and face 1 to normals_deg degrees, so
+    the solid sector is the angles between them.  Receivers at
+    6 m from the edge, 5 degrees off every multiple of 10 degrees: those
+    strictly inside the sector get no event, every other one gets one.  With
+    an obtuse (120 degree) or acute (60 degree) opening, the sector is not
+    the set of points in front of both faces."""
+    sc = _hinge_long(normals_deg)
+    lo, hi = normals_deg, 180.0
+    tx = np.array([1.0, 2.0, -3.0])
+    for ang in np.arange(5.0, 360.0, 10.0):
+        a = math.radians(ang)
+        rx = np.array([6 * math.cos(a), 2.2, 6 * math.sin(a)])
+        r = orc.diffract(sc, tx, rx[None], division_n=24, iterations=0, subrays=6,
+                         keep_invalid=True)
+        inside = lo < ang < hi
+        assert (len(r["candidates"]) == 0) == inside, (ang, len(r["candidates"]))
+
+
+def test_diffraction_needs_the_ray_to_reach_the_edge(orc):
+    """SBR step of Sec. III.A: a launch ray diffracts at an edge only if
+    nothing stops it before the edge.  A wall between Tx and the box's
+    vertical edge x = y = 0 removes every event at that edge."""
+    tx, rx = np.array([-12.0, 6.0, 9.0]), np.array([14.0, -9.0, 11.0])
+    b = scenes.SceneBuilder()
+    b.box((0, 0, 0), (10, 10, 20), 0)
+    counts = []
+    for wall in (False, True):
+        if wall:
+            b.quad((-6, 0, 0), (-6, 12, 0), (-6, 12, 25), (-6, 0, 25), 0)
+        sc = b.scene([5.3 - 0.4j])
+        W = orc.wedges(sc)
+        k0 = next(k for k in range(len(W["a"])) if np.allclose(W["a"][k][:2], 0)
+                  and np.allclose(W["b"][k][:2], 0))
+        r = orc.diffract(sc, tx, rx[None], division_n=40, iterations=0, subrays=6,
+                         keep_invalid=True)
+        counts.append(int((r["candidates"]["face"][:, 0] == k0).sum()))
+    assert counts[0] > 0 and counts[1] == 0, counts

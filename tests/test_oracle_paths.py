@@ -666,3 +666,47 @@ def test_path_test1_alone_equals_the_whole_method(orc):
     u = orc.path_test1(r["candidates"][::-1].copy())
     assert u.tobytes() == r["unique"].tobytes()
     assert len(orc.path_test1(r["candidates"][:0])) == 0
+
+
+# ------------------------------------------- sub-rays keep the path's faces --
+def test_refined_axis_stays_on_the_paths_face(orc):
+    """Sec. III.B: a sub-ray is kept only if it reflects off the same faces as
+    the path it refines.  The ground is split at x = 0 into two coplanar faces
+    (0: x <= 0, 1: x >= 0); the specular point of Tx and Rx lies on face 1 at
+    x = 0.35.  With n = 2 a launch ray that hits face 0 also captures Rx, so a
+    path of face 0 exists: its exact solve leaves the face (invalid) and its
+    refinement may only move the axis toward the shared edge, never across
+    it, where sub-rays over face 1 would reach the specular point."""
+    b = scenes.SceneBuilder()
+    b.quad((-20, -20, 0), (0, -20, 0), (0, 20, 0), (-20, 20, 0), 0)
+    b.quad((0, -20, 0), (20, -20, 0), (20, 20, 0), (0, 20, 0), 0)
+    sc = b.scene([5.0 + 0j])
+    tx = np.array([-0.3, 0.0, 3.0])
+    rx = np.array([1.0, 0.2, 3.0])
+    spec_x = (tx[0] * rx[2] + rx[0] * tx[2]) / (tx[2] + rx[2])
+    seen = set()
+    for n in (2, 3, 4, 6):
+        p = orc.run(sc, tx, rx[None], max_order=1, division_n=n, iterations=8, subrays=6,
+                    keep_invalid=1)["paths"]
+        for q in p[p["order"] == 1]:
+            f = int(q["face"][0])
+            seen.add((n, f, int(q["flags"]) & 2))
+            a = q["axis"]
+            hit = tx + (-tx[2] / a[2]) * a
+            assert (hit[0] <= 0.0) if f == 0 else (hit[0] >= 0.0), (n, f, hit)
+            if f == 0:
+                # cannot get closer to the specular point than the edge allows
+                assert spec_x - hit[0] > 0.9 * spec_x
+    assert (2, 0, 2) in seen and (3, 1, 0) in seen, seen
+
+
+def test_validity_tolerance_is_tight(orc):
+    """Path test 2: a reflection point 0.1 mm outside its face is invalid, one
+    0.1 mm inside is valid (the face test's tolerance is far below the
+    geometry's scale)."""
+    tx, rx = [0, 0, 2], [10, 0, 2]     # specular point at (5, 0, 0)
+    for edge, ok in ((5.0 - 1e-4, False), (5.0 + 1e-4, True)):
+        b = scenes.SceneBuilder()
+        b.quad((-10, -10, 0), (edge, -10, 0), (edge, 10, 0), (-10, 10, 0), 0)
+        _, _, _, v = orc.exact_path(b.scene([4 + 0j]), tx, rx, [0])
+        assert bool(v) == ok, (edge, v)
