@@ -277,6 +277,33 @@ def miss_breakdown(p):
     return out
 
 
+def error_histogram(p):
+    """Refined against exact (image-method) quantities of the valid paths,
+    per reflection order: counts of AOD and AOA errors per decade of degrees
+    (bins [0, 1e-6), [1e-6, 1e-5), ..., [1, inf)), the median and largest
+    angle errors, the largest relative length error and the largest power
+    error in dB."""
+    edges = [0.0] + [10.0 ** e for e in range(-6, 1)] + [np.inf]
+    labels = ["<1e-6"] + ["%g-%g" % (edges[i], edges[i + 1]) for i in range(1, len(edges) - 2)] \
+        + [">=1"]
+    v = p[(p["flags"] & 2) == 0]
+    ea = angle_deg(v["aod"], v["exact_aod"])
+    eo = angle_deg(v["aoa"], v["exact_aoa"])
+    el = np.abs(v["length_m"] - v["exact_length_m"]) / v["exact_length_m"]
+    ep = np.abs(v["power_dbm"] - v["exact_power_dbm"])
+    out = {"bins_deg": labels}
+    for k in sorted(set(int(x) for x in v["order"])):
+        m = v["order"] == k
+        out[str(k)] = {
+            "paths": int(m.sum()),
+            "aod_hist": np.histogram(ea[m], edges)[0].tolist(),
+            "aoa_hist": np.histogram(eo[m], edges)[0].tolist(),
+            "aod_median_deg": float(np.median(ea[m])), "aod_max_deg": float(ea[m].max()),
+            "aoa_median_deg": float(np.median(eo[m])), "aoa_max_deg": float(eo[m].max()),
+            "length_max_rel": float(el[m].max()), "power_max_db": float(ep[m].max())}
+    return out
+
+
 def batch_vs_plain(ctx, scenes, torch, seed=0, steps=2):
     """The batched workload (16 box-building cities of 200-50k triangles,
     256 Tx/Rx pairs spread unevenly over them, n in 50-400, K in 3-8), each
@@ -439,8 +466,9 @@ def large_city_leg(ctx, scenes, torch, steps, warmup, tuning=None):
             "per_s_paths_stages": tgood / (t_paths_ms * 1e-3),
             "mean_iterations": float(np.mean(tpaths["iters_used"])) if len(tpaths) else 0.0,
             "stage_ms": {k: round(v, 4) for k, v in tstage.items()},
-            "misses": miss_breakdown(tpaths)},
-        "fixed_i5": {"paths": int(len(paths)), "within_0.01deg": int(accurate_mask(paths).sum())},
+            "misses": miss_breakdown(tpaths), "errors_by_order": error_histogram(tpaths)},
+        "fixed_i5": {"paths": int(len(paths)), "within_0.01deg": int(accurate_mask(paths).sum()),
+                     "errors_by_order": error_histogram(paths)},
     }
 
 
@@ -512,8 +540,9 @@ def manhattan_leg(ctx, scenes, torch, args):
                           "ms_per_step": round(tms, 4),
                           "mean_iterations": float(np.mean(tpaths["iters_used"])),
                           "stage_ms": {k: round(v, 5) for k, v in tstage.items()},
-                          "misses": miss_breakdown(tpaths)},
-        "fixed_i5": {"paths": int(len(paths)), "within_0.01deg": int(accurate_mask(paths).sum())},
+                          "misses": miss_breakdown(tpaths), "errors_by_order": error_histogram(tpaths)},
+        "fixed_i5": {"paths": int(len(paths)), "within_0.01deg": int(accurate_mask(paths).sum()),
+                     "errors_by_order": error_histogram(paths)},
     }
 
 

@@ -170,3 +170,56 @@ def test_diffraction_edge_cases(gpu, orc):
         assert e.value.status == sbr.E_CAPACITY
     finally:
         s.close()
+
+
+def _hinge_long(normals_deg, L=4.0):
+    t = math.radians(normals_deg)
+    b = scenes.SceneBuilder()
+    b.quad((0, 0, 0), (0, L, 0), (-L, L, 0), (-L, 0, 0), 0)
+    c, s_ = math.cos(t), math.sin(t)
+    b.quad((0, 0, 0), (L * c, 0, L * s_), (L * c, L, L * s_), (0, L, 0), 0)
+    return b.scene([4 + 0j])
+
+
+@pytest.mark.parametrize("normals_deg", [60.0, 120.0])
+def test_diffraction_hinge_solid_side(gpu, orc, normals_deg):
+    """An obtuse and an acute hinge (the wedge's solid side is not the set of
+    points in front of both faces): receivers all around the edge, events and
+    paths equal to the oracle's."""
+    sc = _hinge_long(normals_deg)
+    tx = (1.0, 2.0, -3.0)
+    ang = np.radians(np.arange(5.0, 360.0, 10.0))
+    rx = np.stack([6 * np.cos(ang), np.full(len(ang), 2.2), 6 * np.sin(ang)], axis=1)
+    prm = dict(division_n=24, iterations=6, subrays=6, keep_invalid=True)
+    s = gpu.scene(sc)
+    try:
+        ev = s.diff_candidates(tx, rx, **prm)
+        got, _ = s.diffract(tx, rx, **prm)
+    finally:
+        s.close()
+    o = orc.diffract(sc, tx, rx, **prm)
+    oc = sort_events(o["candidates"])
+    assert len(ev) == len(oc) > 0
+    assert ev.tobytes() == oc.tobytes()
+    compare_dpaths(got, o["paths"])
+    # receivers strictly inside the solid sector get nothing
+    inside = (np.degrees(ang) > normals_deg) & (np.degrees(ang) < 180.0)
+    assert not np.isin(np.nonzero(inside)[0], ev["rx"]).any()
+
+
+def test_diffraction_blocked_before_the_edge(gpu, orc):
+    b = scenes.SceneBuilder()
+    b.box((0, 0, 0), (10, 10, 20), 0)
+    b.quad((-6, 0, 0), (-6, 12, 0), (-6, 12, 25), (-6, 0, 25), 0)
+    sc = b.scene([5.3 - 0.4j])
+    tx, rx = (-12.0, 6.0, 9.0), np.array([[14.0, -9.0, 11.0], [20.0, -8.0, 4.0]])
+    prm = dict(division_n=40, iterations=4, subrays=6, keep_invalid=True)
+    s = gpu.scene(sc)
+    try:
+        ev = s.diff_candidates(tx, rx, **prm)
+        got, _ = s.diffract(tx, rx, **prm)
+    finally:
+        s.close()
+    o = orc.diffract(sc, tx, rx, **prm)
+    assert ev.tobytes() == sort_events(o["candidates"]).tobytes()
+    compare_dpaths(got, o["paths"])

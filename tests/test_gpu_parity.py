@@ -233,6 +233,22 @@ def test_paths_order_extremes(gpu, orc, K, iters):
         assert st["n_rays"] == 10 * n * n + 2
 
 
+def test_paths_coplanar_split_ground(gpu, orc):
+    """Two coplanar ground faces meeting at x = 0: the paths of the face
+    that does not hold the specular point (kept invalid) refine toward the
+    shared edge only; every record equals the oracle's."""
+    b = scenes.SceneBuilder()
+    b.quad((-20, -20, 0), (0, -20, 0), (0, 20, 0), (-20, 20, 0), 0)
+    b.quad((0, -20, 0), (20, -20, 0), (20, 20, 0), (0, 20, 0), 0)
+    cfg = {"scene": b.scene([5.0 + 0j]), "tx": np.array([-0.3, 0.0, 3.0]),
+           "rx": np.array([[1.0, 0.2, 3.0], [0.5, -0.4, 2.0], [-2.0, 1.0, 1.0]])}
+    for n in (2, 3, 4, 6):
+        prm = dict(max_order=1, division_n=n, iterations=8, subrays=6, keep_invalid=True)
+        g, o, _ = _run_both(gpu, orc, cfg, **prm)
+        _compare_paths(g, o)
+        assert len(g) > 0
+
+
 def test_degenerate_receivers(gpu, orc):
     """Receivers at the transmitter, 1e-9 m from it, on a wall, in a room
     corner, and a repeated receiver: the same records as the oracle, and the
