@@ -16,6 +16,7 @@
 
 #include "diffract.h"
 #include "geom.h"
+#include "grid_layout.h"
 #include "internal.h"
 #include "refine_queue.h"
 
@@ -138,6 +139,26 @@ struct sbr_context {
     sbr_path* host_paths = nullptr;  // pinned staging of the path list
     int64_t host_paths_cap = 0;
     hipEvent_t ev[8] = {};
+    // streamed launch grids: a fresh equiangular grid whose ray orders exist
+    // can have its ring setup run on grid_stream (default priority) beside
+    // the trace, which forms the directions itself; gprog holds the setup's
+    // published progress, grid_epoch numbers the setups
+    // the ray order of a streamed grid (stream_order; SBR_GRID_ORDER,
+    // SBR_GRID_PREFIX; 0: the cell order, no separate order)
+    int32_t grid_order = 2, grid_prefix = 35;
+    std::map<int32_t, DevBuf> orders_stream;
+    // the launch-grid and trace times (ms) of the last fresh call of each
+    // grid that formed its grid first and made no order: with
+    // grid_stream_mode 1 a grid is streamed when its trace took at least
+    // three times as long as the grid (the setup then finishes well inside
+    // the trace, and the directions the trace forms cost less than the grid
+    // saved); 2 streams whenever possible, 0 never (SBR_GRID_STREAM)
+    std::map<int32_t, std::pair<float, float>> grid_times;
+    int32_t grid_stream_mode = 1;
+    hipStream_t grid_stream = nullptr;
+    hipEvent_t ev_grid_fork = nullptr, ev_grid_join = nullptr;
+    DevBuf gprog;
+    uint32_t grid_epoch = 0;
     // second stream (default priority) for the exact solve beside the
     // refinement, and the events that fork to it and join back
     hipStream_t stream2 = nullptr;
@@ -309,21 +330,75 @@ sbr_status get_grid(sbr_context* c, int32_t launch, int32_t n, GridDev* g, bool*
 // memory to make, are traced by index.
 constexpr int64_t kOrderMaxRays = int64_t(1) << 27;
 
+// The order of a streamed grid's rays (see sbr_context::grid_order): groups
+// of 64 consecutive rays of the cell order, the groups first whose rays need
+// the least of the grid setup's progress (grid_need), by the power-of-two
+// bucket of that need, then the others in cell order.  Bucket b holds about
+// 2^b layers' rays, whose tracing takes far longer than the setup needs for
+// the layers of bucket b + 1, so the packets taken while the setup runs find
+// their layers published; the buckets first hold grid_prefix percent of the
+// rays, which the trace takes longer to work through than the setup needs to
+// finish (mode 2), or every bucket is (mode 1).  The packets keep their
+// rays, so each still traces nearby directions.
+std::vector<uint32_t> stream_order(const sbr_context* c, int32_t n, const std::vector<uint32_t>& ord)
+{
+    const int64_t N = (int64_t)ord.size();
+    const int64_t G = (N + 63) / 64;
+    std::vector<uint32_t> gb((size_t)G, 0);
+    for (int64_t i = 0; i < N; ++i) {
+        uint32_t& x = gb[(size_t)(i / 64)];
+        x = std::max(x, grid_need(n, ord[(size_t)i]));
+    }
+    uint32_t top = 0;
+    for (auto& x : gb) {
+        uint32_t b = 0;
+        while ((2u << b) <= x) ++b;  // floor(log2(need)), need >= 1
+        x = b;
+        top = std::max(top, b);
+    }
+    uint32_t cut = top;
+    if (c->grid_order == 2) {
+        std::vector<int64_t> rays((size_t)top + 1, 0);
+        for (int64_t g = 0; g < G; ++g) rays[gb[(size_t)g]] += std::min<int64_t>(64, N - 64 * g);
+        int64_t acc = 0;
+        for (cut = 0; cut < top; ++cut) {
+            acc += rays[cut];
+            if (100 * acc >= (int64_t)c->grid_prefix * N) break;
+        }
+    }
+    auto key = [&](int64_t g) { return gb[(size_t)g] <= cut ? gb[(size_t)g] : cut + 1; };
+    std::vector<int64_t> start((size_t)top + 3, 0);
+    for (int64_t g = 0; g < G; ++g) ++start[key(g) + 1];
+    for (size_t k = 1; k < start.size(); ++k) start[k] += start[k - 1];
+    std::vector<int64_t> gorder((size_t)G);
+    for (int64_t g = 0; g < G; ++g) gorder[(size_t)start[key(g)]++] = g;
+    std::vector<uint32_t> out((size_t)N);
+    int64_t o = 0;
+    for (int64_t g : gorder)
+        for (int64_t i = 64 * g; i < std::min<int64_t>(N, 64 * g + 64); ++i)
+            out[(size_t)o++] = ord[(size_t)i];
+    return out;
+}
+
 // A hand-out order of a grid's rays that keeps each wave's rays close in
 // direction: rays sorted by their cube-map cell (about one ray per cell, cells
 // in Z order per cube face; launch_ray_cells), by index within a cell
 // (stable two-pass radix sort of the 32-bit cells on the host).  Made once per
-// grid; it changes the order rays are traced in, not the results.
+// grid, with the order of a streamed grid beside it (equiangular grids,
+// stream_order); it changes the order rays are traced in, not the results.
+// *built: this call made them.
 sbr_status get_order(sbr_context* c, int32_t launch, int32_t n, const GridDev& g,
-                     const uint32_t** out)
+                     const uint32_t** out, bool streamed, bool* built)
 {
     const int32_t key = launch * 100000 + n;
+    *built = false;
     auto it = c->orders.find(key);
     if (it == c->orders.end()) {
+        *built = true;
         const int64_t N = g.N;
         int32_t R = 1;
         while (R < 8192 && (int64_t)R * R * 6 < N) R *= 2;
-        DevBuf b;
+        DevBuf b, bs;
         HIPCHK(c, ensure(b, sizeof(uint32_t) * (size_t)N));
         std::vector<uint32_t> cell((size_t)N), ord((size_t)N), tmp((size_t)N);
         hipError_t e = launch_ray_cells(g.dir, N, R, b.as<uint32_t>(), c->stream);
@@ -355,14 +430,30 @@ sbr_status get_order(sbr_context* c, int32_t launch, int32_t n, const GridDev& g
         }
         e = hipMemcpyAsync(b.p, ord.data(), sizeof(uint32_t) * (size_t)N, hipMemcpyHostToDevice,
                            c->stream);
+        std::vector<uint32_t> so;
+        if (e == hipSuccess && launch == SBR_LAUNCH_EQUIANGULAR && c->grid_order > 0) {
+            so = stream_order(c, n, ord);
+            e = ensure(bs, sizeof(uint32_t) * (size_t)N);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(bs.p, so.data(), sizeof(uint32_t) * (size_t)N,
+                                   hipMemcpyHostToDevice, c->stream);
+        }
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) {
             release(b);
+            release(bs);
             return fail(c, SBR_E_DEVICE, "ray order: %s", hipGetErrorString(e));
         }
         it = c->orders.emplace(key, b).first;
+        if (bs.p) c->orders_stream.emplace(key, bs);
     }
-    *out = it->second.as<const uint32_t>();
+    if (streamed) {
+        auto is = c->orders_stream.find(key);
+        *out = is != c->orders_stream.end() ? is->second.as<const uint32_t>()
+                                            : it->second.as<const uint32_t>();
+    } else {
+        *out = it->second.as<const uint32_t>();
+    }
     return SBR_OK;
 }
 
@@ -493,6 +584,12 @@ struct Call {
     int64_t n_cand = 0, n_uniq = 0;
     bool small = false;  // path test 1 ran in one workgroup; n_uniq is on the device
     bool grids_built = false;
+    // the job's launch grid is streamed (see sbr_context::grid_stream_mode):
+    // its ring setup is launched beside the trace of the first pass
+    bool stream_grid = false;
+    int32_t stream_n = 0;
+    bool order_built = false;  // a ray order was made for this call
+    bool streamed = false;     // the trace formed the directions (stream_grid was set)
     // speculative call: the event count was not read back after the trace;
     // n_cand holds the bound the one-workgroup stages were launched for, and
     // u_pred the path count that picks the refinement kernel
@@ -590,15 +687,34 @@ sbr_status add_job(sbr_context* c, Call& call, int32_t scene_idx, const double* 
 {
     GridDev g;
     bool built = false;
+    const int32_t key = p->launch * 100000 + p->division_n;
+    const int64_t N = num_rays(p->launch, p->division_n);
+    // a fresh grid of a single whole-grid job whose grid and ray order exist
+    // is streamed: nothing is launched for it here
+    bool stream = (p->flags & SBR_FLAG_FRESH_GRID) != 0 && c->grid_stream_mode > 0 &&
+                  c->ray_order && p->launch == SBR_LAUNCH_EQUIANGULAR && call.jobs.empty() &&
+                  ray_begin == 0 && ray_count == N && N <= kOrderMaxRays &&
+                  c->grids.count(key) && c->orders_stream.count(key);
+    if (stream && c->grid_stream_mode == 1) {
+        auto t = c->grid_times.find(key);
+        stream = t != c->grid_times.end() && t->second.second >= 3.0f * t->second.first;
+    }
     sbr_status r = get_grid(c, p->launch, p->division_n, &g, &built,
-                            (p->flags & SBR_FLAG_FRESH_GRID) != 0);
+                            (p->flags & SBR_FLAG_FRESH_GRID) != 0 && !stream);
     if (r) return r;
     call.grids_built = call.grids_built || built;
+    if (stream) {
+        HIPCHK(c, ensure(c->grid_scratch, grid_scratch_bytes(p->division_n)));
+        call.stream_grid = true;
+        call.stream_n = p->division_n;
+    }
     const sbr_scene* s = call.scenes[scene_idx];
     JobDev J = make_job(s, tx, p, g.dir, g.N, ray_begin, ray_count);
     if (c->ray_order && ray_begin == 0 && ray_count == g.N && g.N <= kOrderMaxRays) {
-        r = get_order(c, p->launch, p->division_n, g, &J.order);
+        bool made = false;
+        r = get_order(c, p->launch, p->division_n, g, &J.order, stream, &made);
         if (r) return r;
+        call.order_built = call.order_built || made;
     }
     J.packet_first = call.n_packets;
     J.scene = scene_idx;
@@ -717,6 +833,72 @@ int refine_depth(const sbr_context* c, int64_t U)
     return c->lookahead_depth;
 }
 
+// The call's trace.  With a streamed grid (first pass only), the ring setup
+// goes to the grid stream once the main stream has reached this point (so
+// the previous call's trace has finished reading the setup's scratch); a
+// one-lane kernel then waits until the setup has started, so that the
+// persistent trace cannot take the slot it needs, and the main stream joins
+// the setup after the trace.  A streamed counting call forms its grid first.
+sbr_status trace_launch(sbr_context* c, Call& call, int64_t cap, int32_t* out_tri,
+                        double* out_t, unsigned long long* tallies)
+{
+    hipStream_t st = c->stream;
+    Counters* dc = c->counters.as<Counters>();
+    call.dev.gscr = nullptr;
+    call.dev.gprog = nullptr;
+    if (call.stream_grid && tallies) {
+        const JobDev& J = call.jobs[0];
+        HIPCHK(c, launch_grid(GridDev{(double*)J.dir, J.N, call.stream_n, SBR_LAUNCH_EQUIANGULAR},
+                              st, c->grid_scratch.p, c->grid_check_log2));
+        call.stream_grid = false;
+    }
+    if (call.stream_grid) {
+        call.streamed = true;
+        if (!c->grid_stream)
+            HIPCHK(c, hipStreamCreateWithFlags(&c->grid_stream, hipStreamNonBlocking));
+        if (!c->ev_grid_fork)
+            HIPCHK(c, hipEventCreateWithFlags(&c->ev_grid_fork, hipEventDisableTiming));
+        if (!c->ev_grid_join)
+            HIPCHK(c, hipEventCreateWithFlags(&c->ev_grid_join, hipEventDisableTiming));
+        HIPCHK(c, ensure(c->gprog, sizeof(unsigned long long)));
+        if (++c->grid_epoch == 0) c->grid_epoch = 1;
+        unsigned long long* prog = c->gprog.as<unsigned long long>();
+        HIPCHK(c, hipEventRecord(c->ev_grid_fork, st));
+        HIPCHK(c, hipStreamWaitEvent(c->grid_stream, c->ev_grid_fork, 0));
+        HIPCHK(c, launch_grid_setup_streamed(call.stream_n, c->grid_scratch.p, c->grid_check_log2,
+                                             prog, c->grid_epoch, c->grid_stream));
+        HIPCHK(c, hipEventRecord(c->ev_grid_join, c->grid_stream));
+        HIPCHK(c, launch_grid_wait_started(prog, c->grid_epoch, &dc->err, st));
+        call.dev.gscr = (const char*)c->grid_scratch.p;
+        call.dev.gprog = prog;
+        call.dev.gepoch = c->grid_epoch;
+        call.dev.gn = call.stream_n;
+        call.dev.gcheck = c->grid_check_log2;
+    }
+    HIPCHK(c, hipEventRecord(c->ev[7], st));
+    HIPCHK(c, launch_trace(call.dev, call.lp, call.s0, trace_blocks(c, call), &dc->queue,
+                           c->cand.as<sbr_candidate>(), cap, &dc->cand, out_tri, out_t, &dc->err,
+                           st, tallies));
+    HIPCHK(c, hipEventRecord(c->ev[2], st));
+    if (call.stream_grid) {
+        HIPCHK(c, hipStreamWaitEvent(st, c->ev_grid_join, 0));
+        // a later pass finds the directions in place
+        call.stream_grid = false;
+        call.dev.gscr = nullptr;
+        call.dev.gprog = nullptr;
+    }
+    return SBR_OK;
+}
+
+// What a nonzero error word of the device counters means.
+const char* device_error(int32_t err)
+{
+    if (err & 1) return "traversal stack overflow";
+    if (err & 2) return "refinement work queue did not drain";
+    if (err & 12) return "streamed launch grid: the ring setup did not publish in time";
+    return "device error";
+}
+
 // Launch, trace and reception, then path test 1.  On return the context
 // holds cand (n_cand events) and, with need_unique, uniq (the path-test-1
 // winners, n_uniq or -- small -- a count on the device).  Without
@@ -739,11 +921,8 @@ sbr_status run_front(sbr_context* c, Call& call, bool need_unique, int32_t* out_
         // run_paths checks it after its one read-back.
         const int64_t bound = std::min<int64_t>(kSmallEvents, std::max<int64_t>(256, 2 * c->spec_events));
         HIPCHK(c, ensure(c->cand, sizeof(sbr_candidate) * (size_t)cap));
-        HIPCHK(c, hipEventRecord(c->ev[7], st));
-        HIPCHK(c, launch_trace(call.dev, call.lp, call.s0, trace_blocks(c, call), &dc->queue,
-                               c->cand.as<sbr_candidate>(), cap, &dc->cand, out_tri, out_t,
-                               &dc->err, st, nullptr));
-        HIPCHK(c, hipEventRecord(c->ev[2], st));
+        sbr_status r2 = trace_launch(c, call, cap, out_tri, out_t, nullptr);
+        if (r2) return r2;
         HIPCHK(c, ensure(c->uniq, sizeof(sbr_candidate) * (size_t)bound));
         HIPCHK(c, launch_dedup_small(c->cand.as<sbr_candidate>(), bound, c->uniq.as<sbr_candidate>(),
                                      &dc->n_unique, st, &dc->cand));
@@ -761,14 +940,11 @@ sbr_status run_front(sbr_context* c, Call& call, bool need_unique, int32_t* out_
         if (pass > 0)  // upload_call zeroed them for the first pass
             HIPCHK(c, hipMemsetAsync(c->counters.p, 0, sizeof(Counters), st));
         if (tallies) HIPCHK(c, hipMemsetAsync(tallies, 0, 10 * sizeof(unsigned long long), st));
-        HIPCHK(c, hipEventRecord(c->ev[7], st));
-        HIPCHK(c, launch_trace(call.dev, call.lp, call.s0, trace_blocks(c, call), &dc->queue,
-                               c->cand.as<sbr_candidate>(), cap, &dc->cand, out_tri, out_t,
-                               &dc->err, st, tallies));
-        HIPCHK(c, hipEventRecord(c->ev[2], st));
+        sbr_status r2 = trace_launch(c, call, cap, out_tri, out_t, tallies);
+        if (r2) return r2;
         HIPCHK(c, hipMemcpyAsync(hc, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipStreamSynchronize(st));
-        if (hc->err) return fail(c, SBR_E_INTERNAL, "traversal stack overflow");
+        if (hc->err) return fail(c, SBR_E_INTERNAL, "%s", device_error(hc->err));
         if ((int64_t)hc->cand <= cap) break;
         if (hc->cand >= (1ull << 31))
             return fail(c, SBR_E_CAPACITY, "%llu reception events exceed 2^31", hc->cand);
@@ -949,9 +1125,7 @@ sbr_status run_paths(sbr_context* c, Call& call, sbr_path* out, int64_t capacity
             if (!call.grids_built) call.ms_launch = 0.0f;
             HIPCHK(c, hipEventElapsedTime(&call.ms_trace, c->ev[7], c->ev[2]));
         }
-        if (hc->err)
-            return fail(c, SBR_E_INTERNAL, (hc->err & 2) ? "refinement work queue did not drain"
-                                                          : "traversal stack overflow");
+        if (hc->err) return fail(c, SBR_E_INTERNAL, "%s", device_error(hc->err));
         P = hc->n_paths;
         U = hc->n_unique;
         *n_out = P;
@@ -964,9 +1138,7 @@ sbr_status run_paths(sbr_context* c, Call& call, sbr_path* out, int64_t capacity
                               c->scan.p, st));
         HIPCHK(c, hipMemcpyAsync(hc, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipStreamSynchronize(st));
-        if (hc->err)
-            return fail(c, SBR_E_INTERNAL, (hc->err & 2) ? "refinement work queue did not drain"
-                                                          : "traversal stack overflow");
+        if (hc->err) return fail(c, SBR_E_INTERNAL, "%s", device_error(hc->err));
         P = hc->n_paths;
         *n_out = P;
         if (P > capacity)
@@ -1011,6 +1183,17 @@ sbr_status run_paths(sbr_context* c, Call& call, sbr_path* out, int64_t capacity
 }
 
 // A call with one job on one scene.
+// After a completed single-job call with a fresh equiangular grid formed
+// before its trace (and no ray order made): its grid and trace times, which
+// decide whether later calls stream the grid (sbr_context::grid_times).
+void note_grid_times(sbr_context* c, const Call& call, const sbr_trace_params* p)
+{
+    if (!(p->flags & SBR_FLAG_FRESH_GRID) || p->launch != SBR_LAUNCH_EQUIANGULAR ||
+        call.jobs.size() != 1 || call.streamed || !call.grids_built || call.order_built)
+        return;
+    c->grid_times[p->launch * 100000 + p->division_n] = {call.ms_launch, call.ms_trace};
+}
+
 sbr_status single_call(sbr_scene* s, Call& call, const double* tx, const double* rx,
                        int32_t n_rx, const sbr_trace_params* p, int64_t ray_begin,
                        int64_t ray_count)
@@ -1130,6 +1313,9 @@ sbr_status sbr_context_create(int32_t device, void* hip_stream, sbr_context** ou
         c->seg_tail = env_int("SBR_SEG_TAIL", 10, 0, 200);
         c->la3_lds = env_int("SBR_LA3_LDS", 1, 0, 1) != 0;
         c->ray_order = env_int("SBR_RAY_ORDER", 1, 0, 1);
+        c->grid_stream_mode = env_int("SBR_GRID_STREAM", 1, 0, 2);
+        c->grid_order = env_int("SBR_GRID_ORDER", 2, 0, 2);
+        c->grid_prefix = env_int("SBR_GRID_PREFIX", 35, 0, 100);
         if (refine_la3_set_lds_limit(c->lds_max - 2048) != hipSuccess) {
             (void)hipGetLastError();
             c->la3_lds = false;
@@ -1209,8 +1395,14 @@ sbr_status sbr_context_destroy(sbr_context* c)
     if (c->n_scenes > 0) return fail(c, SBR_E_INVALID_ARG, "%d scene(s) still alive", c->n_scenes);
     (void)use_device(c->device);
     (void)hipStreamSynchronize(c->stream);
+    if (c->grid_stream) (void)hipStreamSynchronize(c->grid_stream);
     for (auto& kv : c->grids) release(kv.second);
     for (auto& kv : c->orders) release(kv.second);
+    for (auto& kv : c->orders_stream) release(kv.second);
+    release(c->gprog);
+    if (c->ev_grid_fork) (void)hipEventDestroy(c->ev_grid_fork);
+    if (c->ev_grid_join) (void)hipEventDestroy(c->ev_grid_join);
+    if (c->grid_stream) (void)hipStreamDestroy(c->grid_stream);
     DevBuf* bufs[] = {&c->grid_scratch, &c->rx,    &c->rx32,  &c->cand,  &c->idx,  &c->flags,
                       &c->offs,         &c->scan,  &c->uniq,  &c->refine, &c->paths,
                       &c->keep,         &c->outp,  &c->counters, &c->rays_tri, &c->rays_t, &c->tally,
@@ -1559,7 +1751,9 @@ sbr_status sbr_trace(sbr_scene* s, const double tx[3], const double* rx, int32_t
     if (r) return r;
     r = run_front(c, call, true, nullptr, nullptr, nullptr);
     if (r) return r;
-    return run_paths(c, call, out, capacity, n_out, stats);
+    r = run_paths(c, call, out, capacity, n_out, stats);
+    if (!r) note_grid_times(c, call, p);
+    return r;
 }
 
 // ---------------------------------------------------------------------------
@@ -2046,6 +2240,7 @@ sbr_status sbr_trace_device(sbr_scene* s, const double tx[3], const double* rx, 
     } else if (!r) {
         c->spec_events = call.n_cand;
     }
+    if (!r) note_grid_times(c, call, p);
     if (r || !want_graph || !call.small) return r;
     // capture for the next calls of this shape, with room for twice this
     // call's paths

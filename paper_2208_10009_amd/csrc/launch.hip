@@ -7,6 +7,7 @@
 #include <math.h>
 
 #include "geom.h"
+#include "grid.h"
 #include "internal.h"
 
 namespace sbr {
@@ -14,20 +15,6 @@ namespace sbr {
 // ===========================================================================
 // Launch grid (Sec. II.B)
 // ===========================================================================
-// Icosahedron: the 12 cyclic permutations of (0, +-1, +-phi), normalized, in a
-// fixed order; edges are the 30 pairs i < j of adjacent vertices (positive
-// dot product), listed lexicographically; faces are the 20 mutually adjacent
-// triples i < j < k, lexicographically, wound counter-clockwise seen from
-// outside (clockwise seen from the launch point, the paper's ordering).
-struct GridHdr {
-    d3 V[12];
-    int32_t e[30][2];
-    int32_t f[20][3];
-    int32_t nv, ne, nf;
-};
-
-__host__ __device__ static inline int64_t ring_cap(int32_t n) { return n / 3 + 2; }
-
 // Scratch layout: the header; ring corners [20][cap][3] (d3); the angle each
 // ring side subtends, [20][cap][3] (double); the angle of each icosahedron
 // edge, [30] (double).
@@ -35,11 +22,6 @@ size_t grid_scratch_bytes(int32_t n)
 {
     return sizeof(GridHdr) + (sizeof(d3) + sizeof(double)) * 3 * 20 * (size_t)ring_cap(n) +
            sizeof(double) * 30;
-}
-
-__host__ __device__ static inline double* side_angles(char* scratch, int32_t n)
-{
-    return (double*)(scratch + sizeof(GridHdr) + sizeof(d3) * 3 * 20 * (size_t)ring_cap(n));
 }
 
 __device__ static void ico_build(GridHdr* H)
@@ -121,77 +103,59 @@ __device__ static d3 proj_face(d3 p, d3 g)
 // plane, and the third wave projects the corners, so the new corners need one
 // more step only.  The side angles are kept for k_grid_dirs.
 
-// Accept v (a normalized double-double, |v - exact| <= e) when both ends of
-// [v - 2e, v + 2e] round to v.hi + v.lo.  The factor 2 covers the rounding of
-// v.lo +- 2e, given e >= 2^-100 |v|.
-__device__ static inline bool rounds_safely(dd v, double e)
+// Stores of the setup's results: plain, or, when the setup publishes its
+// progress to kernels running beside it, device-scope relaxed atomic stores.
+// Those are written through to the device's coherence point (the consumers'
+// device-scope atomic loads read them there), so publishing them needs only
+// their completion: wave 0, which makes all of them, waits for its stores
+// before it stores the progress word (no L2 write-back, which a release
+// fence would add and which the trace's own stores would make slow).
+__device__ static inline void grid_st(double* p, double v, bool atomic)
 {
-    const double r = v.hi + v.lo, e2 = 2.0 * e;
-    return v.hi + (v.lo + e2) == r && v.hi + (v.lo - e2) == r;
+    if (atomic)
+        __hip_atomic_store((unsigned long long*)p, (unsigned long long)__double_as_longlong(v),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        *p = v;
 }
 
-// Coefficients of one lane's series, chosen once per lane: the double-double
-// series of cos (role 0) or sin (roles 1, 2), and the double series of the
-// other function.
-struct LaneSeries {
-    dd head[5];       // 1/k! for the first five terms of the double-double series
-    double tail[9];   // 1/k! for the next nine terms
-    double e_tail, e_trunc;  // 1/k! of the first tail term and of the first omitted term
-    double other[11]; // 1/k! of the double series
-    bool cosine;
-};
-
-__device__ static LaneSeries lane_series(bool cosine)
+__device__ static inline void grid_st3(d3* p, d3 v, bool atomic)
 {
-    const int o = cosine ? 0 : 1;
-    LaneSeries L;
-    L.cosine = cosine;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) L.head[k] = cosine ? kInvFact[2 * k] : kInvFact[2 * k + 1];
-#pragma unroll
-    for (int j = 0; j < 9; ++j)
-        L.tail[j] = cosine ? kInvFact[2 * j + 10].hi : kInvFact[2 * j + 11].hi;
-    L.e_tail = kInvFact[10 + o].hi;
-    L.e_trunc = kInvFact[28 + o].hi;
-#pragma unroll
-    for (int k = 0; k < 11; ++k)
-        L.other[k] = cosine ? kInvFact[2 * k + 1].hi : kInvFact[2 * k].hi;
-    return L;
+    double* q = (double*)p;
+    grid_st(q, v.x, atomic);
+    grid_st(q + 1, v.y, atomic);
+    grid_st(q + 2, v.z, atomic);
 }
 
-// Short series for 0 <= y <= 1.2: cos y (cosine lanes) or sin y with the terms up to y^8/8! (y^9/9!) in double-double (Horner's
-// rule in t = y^2, exact as two_prod(y, y)) and the next nine terms in
-// double, folded into the innermost coefficient.  *err bounds the error: the
-// double-double steps (< 2^-100 relative to values below 1), the double tail
-// (relative error below 5 ulp; 2^-47 t^5/10! (/11!) is 16 times that), and
-// the omitted terms (alternating and decreasing: below t^14/28! (y t^14/29!)).
-// *other is the other function in double (Taylor series to y^20/20!
-// (y^21/21!), about 1e-16 relative).
-__device__ static dd series_fast(const LaneSeries& L, double y, double* err, double* other)
-{
-    const double ym = L.cosine ? 1.0 : y;
-    const dd t = two_prod(y, y);
-    const double td = t.hi;
-    double q = L.tail[8];
-#pragma unroll
-    for (int j = 7; j >= 0; --j) q = fma(-td, q, L.tail[j]);
-    dd h = dd_sub(L.head[4], dd{td * q, 0.0});
-#pragma unroll
-    for (int k = 3; k >= 0; --k) h = dd_sub(L.head[k], dd_mul(t, h));
-    const double t2 = td * td, t4 = t2 * t2, t5 = t4 * td, t14 = t4 * t4 * t4 * t2;
-    *err = ym * (0x1p-96 + 0x1p-47 * t5 * L.e_tail + t14 * L.e_trunc);
-    double p = L.other[10];
-#pragma unroll
-    for (int k = 9; k >= 0; --k) p = fma(-td, p, L.other[k]);
-    *other = L.cosine ? y * p : p;
-    return dd_mul(dd{ym, 0.0}, h);
-}
-
-__global__ __launch_bounds__(192) void k_grid_setup(int32_t n, char* scratch, int32_t check_log2)
+// With prog: *prog = epoch << 32 | k publishes the setup's progress k (see
+// grid_need): 0 on entry, 1 once the header and the edge angles are stored,
+// 2 + a after iteration a of the layer loop.
+__global__ __launch_bounds__(192) void k_grid_setup(int32_t n, char* scratch, int32_t check_log2,
+                                                    unsigned long long* prog, uint32_t epoch)
 {
     GridHdr* H = (GridHdr*)scratch;
     d3* rings = (d3*)(scratch + sizeof(GridHdr));
     double* ths = side_angles(scratch, n);
+    const bool pub = prog != nullptr;
+    const unsigned long long tag = (unsigned long long)epoch << 32;
+    auto publish = [&](uint32_t k) {
+        // wave 0 made every store being published
+        if (pub && threadIdx.x < 64) {
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            __builtin_amdgcn_s_waitcnt(0);  // every counter, stores included
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            if (threadIdx.x == 0)
+                __hip_atomic_store(prog, tag | k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    };
+    if (pub) {
+        // the setup shares its CU's SIMDs with trace waves, and its serial
+        // chain would otherwise get a fifth of their issue slots: its waves
+        // issue first whenever they have an instruction ready
+        __builtin_amdgcn_s_setprio(3);
+        if (threadIdx.x == 0)
+            __hip_atomic_store(prog, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     __shared__ GridHdr sh;
     __shared__ d3 W[20][3];
     __shared__ d3 PP[20][3][2];   // the two step points next to each corner, projected
@@ -201,12 +165,23 @@ __global__ __launch_bounds__(192) void k_grid_setup(int32_t n, char* scratch, in
     __shared__ double SN[60][2];  // sin a, sin b
     __shared__ int wave_bad[3];   // a value of the wave failed its rounding test
     const int t = threadIdx.x;
-    if (t == 0) {
-        ico_build(&sh);
-        *H = sh;
-    }
+    if (t == 0) ico_build(&sh);
     __syncthreads();
-    if (t < 30) ths[3 * 20 * ring_cap(n) + t] = acos_cr(dot(sh.V[sh.e[t][0]], sh.V[sh.e[t][1]]));
+    if (t < 64) {
+        // the header as 64-bit words (GridHdr is a multiple of 8 bytes)
+        const unsigned long long* src = (const unsigned long long*)&sh;
+        unsigned long long* dst = (unsigned long long*)H;
+        for (int w = t; w < (int)(sizeof(GridHdr) / 8); w += 64) {
+            if (pub)
+                __hip_atomic_store(dst + w, src[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else
+                dst[w] = src[w];
+        }
+    }
+    if (t < 30)
+        grid_st(ths + edge_angle_index(n) + t, acos_cr(dot(sh.V[sh.e[t][0]], sh.V[sh.e[t][1]])),
+                pub);
+    publish(1);
     if (t < 60) W[t / 3][t % 3] = sh.V[sh.f[t / 3][t % 3]];
     __syncthreads();
     const int side = t & 63, role = t >> 6;
@@ -286,17 +261,21 @@ __global__ __launch_bounds__(192) void k_grid_setup(int32_t n, char* scratch, in
             __syncthreads();
             if (!(wave_bad[0] | wave_bad[1] | wave_bad[2])) break;
         }
-        if (act && role == 0 && a > 0) ths[(size_t)fs * cap3 + 3 * (a - 1) + ss] = th;
-        if (mp < 0) break;
+        if (act && role == 0 && a > 0) grid_st(ths + (size_t)fs * cap3 + 3 * (a - 1) + ss, th, pub);
+        if (mp < 0) {
+            publish(2 + a);
+            break;
+        }
         if (mp == 0) {
             if (t < 20) {
                 d3 A = sh.V[sh.f[t][0]], B = sh.V[sh.f[t][1]], C = sh.V[sh.f[t][2]];
                 d3 c = normalize(add(add(A, B), C));
                 d3* out = rings + (size_t)t * cap3 + 3 * a;
-                out[0] = c;
-                out[1] = c;
-                out[2] = c;
+                grid_st3(out, c, pub);
+                grid_st3(out + 1, c, pub);
+                grid_st3(out + 2, c, pub);
             }
+            publish(2 + a);
             break;
         }
         if (act) {
@@ -313,92 +292,22 @@ __global__ __launch_bounds__(192) void k_grid_setup(int32_t n, char* scratch, in
         __syncthreads();
         if (t < 60) {
             const d3 Wn = normalize(sub(add(PP[fs][ss][0], PP[fs][ss][1]), PW[fs][ss]));
-            rings[(size_t)fs * cap3 + 3 * a + ss] = Wn;
+            grid_st3(rings + (size_t)fs * cap3 + 3 * a + ss, Wn, pub);
             W[fs][ss] = Wn;
         }
+        publish(2 + a);
         __syncthreads();
         m = mp;
     }
 }
 
-// Correctly rounded sin y for 0 <= y <= 1.2: the short series of the grid
-// setup when its error bound (times scale >= 1) proves the rounding (all but
-// about two values in a million), else the full double-double series.
-__device__ static double sin_rounded(double y, double scale)
-{
-    const LaneSeries L = lane_series(false);
-    double err, c;
-    const dd s = series_fast(L, y, &err, &c);
-    if (y <= 1.2 && rounds_safely(s, err * scale)) return s.hi + s.lo;
-    return sin_cr(y);
-}
-
-// Point k of m equal-angle steps from P to Q along their great circle, th
-// being the angle P and Q subtend (acos_cr(P.Q)): the angles subtended at
-// the centre by consecutive points are equal (eq. (1)).  Direction
-// sin((m-k) th/m) P + sin(k th/m) Q, normalized.
-__device__ static d3 arc_point_th(d3 P, d3 Q, double th, int64_t k, int64_t m, double scale)
-{
-    double a = ((double)k * th) / (double)m;
-    double b = ((double)(m - k) * th) / (double)m;
-    double sa = sin_rounded(a, scale), sb = sin_rounded(b, scale);
-    return normalize(add(scl(sb, P), scl(sa, Q)));
-}
-
-// Ray order: the 12 vertex rays; then edge interiors, edge by edge, steps
-// 1..n-1 from the lower to the higher vertex index; then face interiors, face
-// by face, layer by layer, each ring starting at the corner that descends
-// from the face's first vertex and following the winding.  n <= 10000, so
-// every index fits in 32 bits.
 __global__ void k_grid_dirs(int32_t n, int64_t N, const char* __restrict__ scratch,
                             double* __restrict__ dir, int32_t check_log2)
 {
     const double scale = ldexp(1.0, check_log2);
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    const GridHdr* H = (const GridHdr*)scratch;
-    const d3* rings = (const d3*)(scratch + sizeof(GridHdr));
-    const double* ths = side_angles((char*)scratch, n);
-    const uint32_t un = (uint32_t)n;
-    d3 r;
-    uint32_t idx = (uint32_t)i;
-    if (idx < 12) {
-        r = H->V[idx];
-    } else {
-        idx -= 12;
-        if (idx < 30 * (un - 1)) {
-            const uint32_t e = idx / (un - 1), k = idx % (un - 1) + 1;
-            r = arc_point_th(H->V[H->e[e][0]], H->V[H->e[e][1]], ths[3 * 20 * ring_cap(n) + e], k,
-                             n, scale);
-        } else {
-            idx -= 30 * (un - 1);
-            const uint32_t per_face = (un - 1) * (un - 2) / 2;
-            const uint32_t f = idx / per_face;
-            const int64_t q = idx % per_face;
-            // Ring a starts at S(a) = 3a(n-3) - 9a(a-1)/2 (the rings before it
-            // have sides n-3, n-6, ... > 0); the last ring, of side 0, is the
-            // face centre.  Estimate a from the quadratic, then settle it.
-            const int64_t c1 = 3 * (int64_t)(n - 3);
-            const double hb = (double)c1 + 4.5;
-            const double disc = hb * hb - 18.0 * (double)q;
-            int64_t a = (int64_t)((hb - sqrt(disc > 0.0 ? disc : 0.0)) / 9.0);
-            if (a < 0) a = 0;
-            while (a > 0 && a * c1 - 9 * a * (a - 1) / 2 > q) --a;
-            while (n - 3 - 3 * (a + 1) >= 0 && (a + 1) * c1 - 9 * (a + 1) * a / 2 <= q) ++a;
-            const int64_t m = n - 3 - 3 * a;
-            const uint32_t qq = (uint32_t)(q - (a * c1 - 9 * a * (a - 1) / 2));
-            const d3* W = rings + (size_t)f * 3 * ring_cap(n) + 3 * a;
-            if (m == 0) {
-                r = W[0];
-            } else {
-                const uint32_t s = qq / (uint32_t)m, k = qq % (uint32_t)m;
-                r = k == 0 ? W[s]
-                           : arc_point_th(W[s], W[(s + 1) % 3],
-                                          ths[(size_t)f * 3 * ring_cap(n) + 3 * a + s], k, m,
-                                          scale);
-            }
-        }
-    }
+    const d3 r = grid_dir_of<GridPlainLoads>(n, scratch, (uint32_t)i, scale);
     dir[i] = r.x;
     dir[N + i] = r.y;
     dir[2 * N + i] = r.z;
@@ -543,10 +452,46 @@ hipError_t launch_grid(GridDev g, hipStream_t s, void* scratch, int32_t check_lo
                            (const char*)scratch, g.dir);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(192), 0, s, g.n, (char*)scratch, check_log2);
+    hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(192), 0, s, g.n, (char*)scratch, check_log2,
+                       (unsigned long long*)nullptr, 0u);
     int64_t blocks = (g.N + 255) / 256;
     hipLaunchKernelGGL(k_grid_dirs, dim3((unsigned)blocks), dim3(256), 0, s, g.n, g.N,
                        (const char*)scratch, g.dir, check_log2);
+    return hipGetLastError();
+}
+
+// The ring setup alone, publishing its progress at prog for a trace that
+// forms its rays' directions itself (equiangular grids only).
+hipError_t launch_grid_setup_streamed(int32_t n, void* scratch, int32_t check_log2,
+                                      unsigned long long* prog, uint32_t epoch, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(192), 0, s, n, (char*)scratch, check_log2,
+                       prog, epoch);
+    return hipGetLastError();
+}
+
+// Wait (one lane, bounded) until the setup of this epoch has started, so that
+// the trace launched after it cannot take the slot the setup needs.
+__global__ void k_grid_wait_started(const unsigned long long* prog, uint32_t epoch,
+                                    int32_t* err)
+{
+    if (threadIdx.x != 0) return;
+    for (uint32_t spin = 0;; ++spin) {
+        const unsigned long long v =
+            __hip_atomic_load(prog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((uint32_t)(v >> 32) == epoch) return;
+        if (spin > (1u << 20)) {
+            atomicOr(err, 8);
+            return;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
+
+hipError_t launch_grid_wait_started(const unsigned long long* prog, uint32_t epoch, int32_t* err,
+                                    hipStream_t s)
+{
+    hipLaunchKernelGGL(k_grid_wait_started, dim3(1), dim3(64), 0, s, prog, epoch, err);
     return hipGetLastError();
 }
 

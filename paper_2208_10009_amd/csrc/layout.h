@@ -148,6 +148,16 @@ struct CallDev {
     int32_t n_jobs;
     int32_t chunk;          // 64-ray groups per packet
     int64_t n_packets;
+    // Streamed launch grid (single-job calls over a whole equiangular grid):
+    // the ring setup runs beside the trace, publishing its progress at gprog
+    // (epoch << 32 | progress), and the trace forms each packet's directions
+    // from the setup's scratch gscr into the job's dir once the progress its
+    // rays need is out.  gscr NULL: the directions are there beforehand.
+    const char* gscr;
+    const unsigned long long* gprog;
+    uint32_t gepoch;
+    int32_t gn;           // the grid's division n
+    int32_t gcheck;       // the grid's check_log2
 };
 
 }  // namespace sbr

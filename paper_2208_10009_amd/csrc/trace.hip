@@ -11,6 +11,7 @@
 
 #include <algorithm>
 
+#include "grid.h"
 #include "internal.h"
 #include "traverse.h"
 
@@ -219,6 +220,73 @@ __device__ static inline void receive(const JobDev& J, const double* __restrict_
     receive_at(J, R, t, gx, rx, cand, cap, ccount, events, count);
 }
 
+// The directions of the rays next..pend-1 of a streamed grid (see CallDev):
+// the wave waits (lane 0, bounded) until the ring setup has published the
+// progress the packet's rays need, then forms their directions with the
+// setup's arithmetic (bit-identical to k_grid_dirs) and stores them in the
+// job's direction array, from which the lanes then start their rays.
+// The streamed grid's arguments, kept in LDS for the whole launch so that
+// they take no scalar registers in the trace loop.
+struct StreamArgs {
+    const char* scr;
+    const unsigned long long* prog;
+    uint32_t epoch;
+    int32_t n, check;
+};
+
+__device__ static void stream_dirs(const StreamArgs& sa, uint32_t* seen, const JobDev& J,
+                                   int64_t next, int64_t pend, int lane, int32_t* err)
+{
+    uint32_t need = 0;
+    for (int64_t b = next; b < pend; b += 64) {
+        const int64_t i = b + lane;
+        if (i < pend) {
+            const int64_t r = J.order ? (int64_t)gld((const int32_t*)J.order + i) : i;
+            need = max(need, grid_need(sa.n, r));
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) need = max(need, (uint32_t)__shfl_xor((int)need, off));
+    // The progress word is read only when the packet needs more than the
+    // workgroup has already seen (*seen, in LDS): every wave of the machine
+    // reading one word for every packet would queue them all at the memory
+    // channel that holds it.
+    if (need > *seen && lane == 0) {
+        // once one wave has timed out, the others no longer wait (the call
+        // reports the error)
+        const bool late =
+            (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 4) != 0;
+        for (uint32_t spin = 0; !late; ++spin) {
+            const unsigned long long v =
+                __hip_atomic_load(sa.prog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((uint32_t)(v >> 32) == sa.epoch && (uint32_t)v >= need) {
+                atomicMax(seen, (uint32_t)v);
+                break;
+            }
+            if (spin > (1u << 20)) {
+                atomicOr(err, 4);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    const double scale = ldexp(1.0, sa.check);
+    CoefPtr F = coef_table();
+    asm volatile("" : "+s"(F));  // keeps the coefficient loads in this branch
+    double* dir = (double*)J.dir;
+    for (int64_t b = next; b < pend; b += 64) {
+        const int64_t i = b + lane;
+        if (i < pend) {
+            const int64_t r = J.order ? (int64_t)gld((const int32_t*)J.order + i) : i;
+            const d3 d = grid_dir_of<GridAtomicLoads>(sa.n, sa.scr, (uint32_t)r, scale, F);
+            dir[r] = d.x;
+            dir[J.N + r] = d.y;
+            dir[2 * J.N + r] = d.z;
+        }
+    }
+    // lanes start rays whose directions other lanes of the wave stored
+    __threadfence_block();
+}
+
 // Persistent trace.  A wave takes a packet of 64 x chunk consecutive launch
 // rays of one job and hands them out to its lanes; each round, every busy
 // lane traces one segment (closest hit), runs the reception test of its
@@ -227,7 +295,7 @@ __device__ static inline void receive(const JobDev& J, const double* __restrict_
 // lengths (escaping at once or bouncing K times) share a wave.  The wave
 // takes a new packet only when all its lanes are idle, so the job and its
 // scene stay uniform across the wave.
-template <bool COUNT, bool LDS>
+template <bool COUNT, bool LDS, bool STREAM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 void k_trace(CallDev call, LdsPlan L, SceneDev s0,
                                                uint32_t* __restrict__ queue,
@@ -238,6 +306,15 @@ void k_trace(CallDev call, LdsPlan L, SceneDev s0,
                                                int32_t* __restrict__ err,
                                                unsigned long long* __restrict__ tallies)
 {
+    __shared__ StreamArgs s_stream;
+    __shared__ uint32_t s_seen;  // the setup progress this workgroup has seen
+    if (STREAM) {
+        if (threadIdx.x == 0) {
+            s_stream = StreamArgs{call.gscr, call.gprog, call.gepoch, call.gn, call.gcheck};
+            s_seen = 0;
+        }
+        if (!LDS) __syncthreads();
+    }
     if (LDS) stage_scene(s0, L);
     const int lane = threadIdx.x & 63;
     const uint64_t below = (1ull << lane) - 1ull;
@@ -275,6 +352,14 @@ void k_trace(CallDev call, LdsPlan L, SceneDev s0,
             box = rx_box(call.rx32, J.rx_first, J.n_rx);
             next = J.ray_begin + ((int64_t)pk - J.packet_first) * 64 * call.chunk;
             pend = min(next + 64 * (int64_t)call.chunk, J.ray_begin + J.ray_count);
+            if (STREAM) {
+                // every lane is idle: its ray state is dead here, which frees its
+                // registers for forming the directions
+                R = RayState{};
+                R.r = -1;
+                StreamArgs sa = s_stream;
+                stream_dirs(sa, &s_seen, J, next, pend, lane, err);
+            }
             continue;
         }
         if (R.r < 0) continue;
@@ -372,13 +457,13 @@ void k_trace(CallDev call, LdsPlan L, SceneDev s0,
     }
 }
 
-template <bool COUNT, bool LDS>
+template <bool COUNT, bool LDS, bool STREAM>
 static void launch_trace_t(const CallDev& call, const LdsPlan& L, const SceneDev& s0, int blocks,
                            uint32_t* queue, sbr_candidate* cand, int64_t cap,
                            unsigned long long* cand_count, int32_t* out_tri, double* out_t,
                            int32_t* err_flag, hipStream_t s, unsigned long long* tallies)
 {
-    hipLaunchKernelGGL((k_trace<COUNT, LDS>), dim3((unsigned)blocks), dim3(L.block),
+    hipLaunchKernelGGL((k_trace<COUNT, LDS, STREAM>), dim3((unsigned)blocks), dim3(L.block),
                        LDS ? L.bytes : 0, s, call, L, s0, queue, cand, cap, cand_count, out_tri,
                        out_t, err_flag, tallies);
 }
@@ -390,27 +475,39 @@ hipError_t launch_trace(const CallDev& call, const LdsPlan& L, const SceneDev& s
 {
     if (call.n_packets <= 0 || blocks <= 0) return hipSuccess;
     const bool lds = L.bytes > 0;
-    if (tallies && lds)
-        launch_trace_t<true, true>(call, L, s0, blocks, queue, cand, cap, cand_count, out_tri,
-                                   out_t, err_flag, s, tallies);
+    // a streamed grid is never combined with the counting instance (the
+    // library makes counting calls with their directions in place)
+    if (call.gscr && tallies) return hipErrorInvalidValue;
+    if (call.gscr && lds)
+        launch_trace_t<false, true, true>(call, L, s0, blocks, queue, cand, cap, cand_count,
+                                          out_tri, out_t, err_flag, s, tallies);
+    else if (call.gscr)
+        launch_trace_t<false, false, true>(call, L, s0, blocks, queue, cand, cap, cand_count,
+                                           out_tri, out_t, err_flag, s, tallies);
+    else if (tallies && lds)
+        launch_trace_t<true, true, false>(call, L, s0, blocks, queue, cand, cap, cand_count,
+                                          out_tri, out_t, err_flag, s, tallies);
     else if (tallies)
-        launch_trace_t<true, false>(call, L, s0, blocks, queue, cand, cap, cand_count, out_tri,
-                                    out_t, err_flag, s, tallies);
+        launch_trace_t<true, false, false>(call, L, s0, blocks, queue, cand, cap, cand_count,
+                                           out_tri, out_t, err_flag, s, tallies);
     else if (lds)
-        launch_trace_t<false, true>(call, L, s0, blocks, queue, cand, cap, cand_count, out_tri,
-                                    out_t, err_flag, s, tallies);
+        launch_trace_t<false, true, false>(call, L, s0, blocks, queue, cand, cap, cand_count,
+                                           out_tri, out_t, err_flag, s, tallies);
     else
-        launch_trace_t<false, false>(call, L, s0, blocks, queue, cand, cap, cand_count, out_tri,
-                                     out_t, err_flag, s, tallies);
+        launch_trace_t<false, false, false>(call, L, s0, blocks, queue, cand, cap, cand_count,
+                                            out_tri, out_t, err_flag, s, tallies);
     return hipGetLastError();
 }
 
 hipError_t trace_set_lds_limit(int bytes)
 {
-    hipError_t e = hipFuncSetAttribute((const void*)k_trace<true, true>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_trace<true, true, false>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)k_trace<false, true>,
+    e = hipFuncSetAttribute((const void*)k_trace<false, true, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_trace<false, true, false>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 

@@ -156,6 +156,38 @@ def test_large_city_refinement_kernels_agree(gpu, city, city_run):
         gpu.set_tuning(**base)
 
 
+def test_large_city_streamed_grid(city, city_run, orc):
+    """At full size, with the grid streamed (its ring setup beside the
+    trace, the trace forming the directions): the same paths as the call
+    whose grid was formed first, byte for byte, and seeded directions equal
+    to the oracle's."""
+    import os
+    from paper_2208_10009_amd import sbr
+    cfg, _ = city
+    old = os.environ.get("SBR_GRID_STREAM")
+    os.environ["SBR_GRID_STREAM"] = "2"
+    try:
+        ctx = sbr.Context(0)
+    finally:
+        if old is None:
+            os.environ.pop("SBR_GRID_STREAM", None)
+        else:
+            os.environ["SBR_GRID_STREAM"] = old
+    sc = ctx.scene(cfg["scene"])
+    try:
+        n = cfg["params"]["division_n"]
+        a, sa = sc.trace(cfg["tx"], cfg["rx"], keep_invalid=True, fresh_grid=True, **cfg["params"])
+        b, sb = sc.trace(cfg["tx"], cfg["rx"], keep_invalid=True, fresh_grid=True, **cfg["params"])
+        ids = np.random.default_rng(5).choice(10 * n * n + 2, 4096, replace=False)
+        d = ctx.launch_grid(n)[ids]
+    finally:
+        sc.close()
+        ctx.close()
+    assert sa["ms_launch"] > 0 and sb["ms_launch"] == 0
+    assert a.tobytes() == b.tobytes() == city_run[1].tobytes()
+    assert np.array_equal(bits(d), bits(orc.launch_dirs(n, ids)))
+
+
 def test_rx_tree_matches_linear_and_oracle(gpu, orc):
     """1024 receivers on the Manhattan grid: reception through the receiver
     ball tree and by testing every receiver give byte-identical events and

@@ -372,6 +372,67 @@ def test_deterministic_reruns(gpu):
     assert a.tobytes() == b.tobytes()
 
 
+def _context_with_env(env):
+    """A library context created with the environment overrides `env` (the
+    context reads its SBR_* settings when it is created)."""
+    import os
+    from paper_2208_10009_amd import sbr
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        return sbr.Context(0)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+@pytest.mark.parametrize("n", [3, 4, 5, 6, 7, 20, 200])
+def test_streamed_grid(orc, n):
+    """A fresh equiangular grid whose ray orders exist is streamed (here
+    whenever possible): its ring setup runs on a second stream beside the
+    trace, which forms each packet's directions itself once the setup has
+    published the layers they need.  The directions it leaves are the
+    oracle's bit for bit (n = 3..7 cover the innermost layer cases), and the
+    paths equal those of the first call, whose grid was formed before its
+    trace, through both entry points."""
+    import torch
+    ctx = _context_with_env({"SBR_GRID_STREAM": "2"})
+    cfg = scenes.manhattan_config(1, n_rx=16)
+    prm = dict(cfg["params"], division_n=n)
+    sc = ctx.scene(cfg["scene"])
+    try:
+        a, sa = sc.trace(cfg["tx"], cfg["rx"], fresh_grid=True, **prm)
+        b, sb = sc.trace(cfg["tx"], cfg["rx"], fresh_grid=True, **prm)
+        rx = torch.as_tensor(cfg["rx"], device="cuda")
+        c, sc_ = sc.trace_device(cfg["tx"], rx, fresh_grid=True, **prm)
+        d = ctx.launch_grid(n)
+    finally:
+        sc.close()
+        ctx.close()
+    # the first call formed the grid (and the orders); the others streamed it
+    assert sa["ms_launch"] > 0 and sb["ms_launch"] == 0 and sc_["ms_launch"] == 0
+    assert a.tobytes() == b.tobytes() == c.cpu().numpy().tobytes()
+    assert np.array_equal(bits(d), bits(orc.launch_dirs(n)))
+
+
+def test_streamed_grid_automatic_choice(gpu):
+    """By default a grid is streamed only once a fresh call of it has shown
+    a trace at least three times as long as its grid: never for a 12-triangle
+    room at n = 60 (the trace is short), the same paths either way."""
+    cfg = scenes.shoebox_config(2)
+    prm = dict(cfg["params"], division_n=60)
+    sc = gpu.scene(cfg["scene"])
+    try:
+        runs = [sc.trace(cfg["tx"], cfg["rx"], fresh_grid=True, **prm) for _ in range(4)]
+    finally:
+        sc.close()
+    assert all(st["ms_launch"] > 0 for _, st in runs)
+    assert all(p.tobytes() == runs[0][0].tobytes() for p, _ in runs)
+
+
 def _trace_with_env(env, cfg, **prm):
     import os
     from paper_2208_10009_amd import sbr
