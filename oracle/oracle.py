@@ -186,6 +186,8 @@ def lib():
                                            C.c_int64, dp]
         L.orc_exact_path.argtypes = [dp, ip, ip, C.c_int64, dp, dp, dp, dp, C.c_int32, ip,
                                      C.c_double, C.c_double, dp, dp, dp, ip]
+        L.orc_path_jacobian.argtypes = [dp, ip, ip, C.c_int64, dp, dp, C.c_int32, dp, dp,
+                                        C.c_int32, ip, C.c_double, C.c_double, dp, dp]
     return _lib
 
 
@@ -403,6 +405,25 @@ def exact_path(scene, tx, rx, faces, freq_hz=28e9, tx_power_dbm=0.0):
     if rc:
         raise ValueError("orc_exact_path failed (%d)" % rc)
     return pts[:k], L.value, P.value, bool(V.value)
+
+
+def path_jacobian(scene, tx, rx, faces, freq_hz=28e9, tx_power_dbm=0.0):
+    """Image-method path quantities of one face sequence and their analytic
+    Jacobian: (values [8] = delay, AOD (3), AOA (3), power;
+    jac [8][6 + 2 M] over Tx (3), Rx (3), (re, im) of each material)."""
+    tri_v, face, mat, er, ei = _scene_arrays(scene)
+    faces = np.ascontiguousarray(faces, dtype=np.int32)
+    k = len(faces)
+    val = np.zeros(8, np.float64)
+    jac = np.zeros((8, 6 + 2 * len(er)), np.float64)
+    txa = np.ascontiguousarray(tx, dtype=np.float64)
+    rxa = np.ascontiguousarray(rx, dtype=np.float64)
+    rc = lib().orc_path_jacobian(_d(tri_v), _i(face), _i(mat), len(face), _d(er), _d(ei),
+                                 len(er), _d(txa), _d(rxa), k, _i(faces) if k else None,
+                                 freq_hz, tx_power_dbm, _d(val), _d(jac))
+    if rc:
+        raise ValueError("orc_path_jacobian failed (%d)" % rc)
+    return val, jac
 
 
 def wedges(scene):

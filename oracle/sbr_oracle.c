@@ -951,6 +951,203 @@ int orc_exact_path(const double* tri_v, const int32_t* face_id, const int32_t* m
 }
 
 /* ======================================================================== */
+/* Analytic Jacobian of the image-method path quantities                     */
+/* ======================================================================== */
+/* For a face sequence f_0..f_{k-1} with unit normals n_j and offsets c_j
+ * (n_j . x = c_j), the mirror across plane j is x -> H_j x + 2 c_j n_j with
+ * the Householder matrix H_j = I - 2 n_j n_j^T.  Unfolding:
+ *   - the image of Tx, I = M Tx + b with M = H_{k-1} ... H_0, lies on the
+ *     straight line through Rx and the last reflection point, so the length
+ *     is L = |I - Rx| and the arrival direction AOA = u = (I - Rx) / L;
+ *   - the image of Rx across the planes in reverse order, J = M^T Rx + b',
+ *     lies on the line of the first segment, so AOD = w = (J - Tx) / D
+ *     (D = |J - Tx| = L);
+ *   - the segment arriving at reflection j has direction
+ *     d_j = H_{j-1} ... H_0 w, incidence cosine cos_j = |d_j . n_j|.
+ * Values (as orc_exact_path): delay L / c0, AOD, AOA and
+ * P = P_t + 20 log10(lambda / (4 pi L)) + sum_j 10 log10 R_j(cos_j, er_j).
+ * Derivatives (x = Tx or Rx), with P_v = I - v v^T:
+ *   dL/dTx = M^T u,  dL/dRx = -u,
+ *   dAOA/dTx = P_u M / L,  dAOA/dRx = -P_u / L,
+ *   dAOD/dTx = -P_w / D,  dAOD/dRx = P_w M^T / D,
+ *   dcos_j/dx = sign(d_j . n_j) n_j^T (H_{j-1} ... H_0) dw/dx,
+ *   dP/dx = -20 / (ln 10 L) dL/dx + 10 / ln 10 sum_j (dR_j/dcos_j) / R_j dcos_j/dx,
+ *   dP/d(re, im) of material m = 10 / ln 10 sum_{j of m} (dR_j/d(re, im)) / R_j.
+ * R = (|G_s|^2 + |G_p|^2) / 2 with r = sqrt(er - 1 + c^2),
+ * G_s = (c - r) / (c + r), G_p = (er c - r) / (er c + r); by the quotient rule
+ *   dG_s = 2 (r dc - c dr) / (c + r)^2,
+ *   dG_p = 2 (r d(er c) - er c dr) / (er c + r)^2,
+ * with dr = (2 c dc + d er) / (2 r), d(er c) = er dc + c d er, d|G|^2 =
+ * 2 Re(conj(G) dG), and d er = 1 for the real part, j for the imaginary. */
+static void fresnel_derivs(double c, double complex er, double* R, double* dRdc,
+                           double* dRdre, double* dRdim)
+{
+    double complex r = csqrt(er - (1.0 - c * c));
+    double complex gs = (c - r) / (c + r), gp = (er * c - r) / (er * c + r);
+    *R = 0.5 * (cabs(gs) * cabs(gs) + cabs(gp) * cabs(gp));
+    /* three directions of (dc, d er): (1, 0), (0, 1), (0, j) */
+    const double complex dcs[3] = {1.0, 0.0, 0.0};
+    const double complex des[3] = {0.0, 1.0, I};
+    double out[3];
+    for (int q = 0; q < 3; ++q) {
+        double complex dc = dcs[q], de = des[q];
+        double complex dr = (2.0 * c * dc + de) / (2.0 * r);
+        double complex dgs = 2.0 * (r * dc - c * dr) / ((c + r) * (c + r));
+        double complex dec = er * dc + c * de;
+        double complex dgp = 2.0 * (r * dec - er * c * dr) / ((er * c + r) * (er * c + r));
+        out[q] = 0.5 * (2.0 * creal(conj(gs) * dgs) + 2.0 * creal(conj(gp) * dgp));
+    }
+    *dRdc = out[0];
+    *dRdre = out[1];
+    *dRdim = out[2];
+}
+
+typedef struct { double a[3][3]; } m3;
+
+static m3 m3_id(void)
+{
+    m3 A;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) A.a[i][j] = i == j ? 1.0 : 0.0;
+    return A;
+}
+
+static m3 m3_mul(m3 A, m3 B)
+{
+    m3 C;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+            for (int l = 0; l < 3; ++l) s += A.a[i][l] * B.a[l][j];
+            C.a[i][j] = s;
+        }
+    return C;
+}
+
+static m3 m3_t(m3 A)
+{
+    m3 C;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) C.a[i][j] = A.a[j][i];
+    return C;
+}
+
+static m3 householder(v3 n)
+{
+    const double v[3] = {n.x, n.y, n.z};
+    m3 H;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) H.a[i][j] = (i == j ? 1.0 : 0.0) - 2.0 * v[i] * v[j];
+    return H;
+}
+
+static m3 proj_perp(v3 u)  /* I - u u^T */
+{
+    return householder(scl(sqrt(0.5), u));
+}
+
+static v3 m3_apply(m3 A, v3 x)
+{
+    return mk(A.a[0][0] * x.x + A.a[0][1] * x.y + A.a[0][2] * x.z,
+              A.a[1][0] * x.x + A.a[1][1] * x.y + A.a[1][2] * x.z,
+              A.a[2][0] * x.x + A.a[2][1] * x.y + A.a[2][2] * x.z);
+}
+
+int orc_path_jacobian(const double* tri_v, const int32_t* face_id, const int32_t* mat_id,
+                      int64_t n_tri, const double* eps_re, const double* eps_im, int32_t n_mat,
+                      const double tx[3], const double rx[3], int32_t order,
+                      const int32_t* faces, double freq_hz, double ptx, double* val,
+                      double* jac)
+{
+    if (order < 0 || order > ORC_MAX_ORDER || n_mat < 0) return -1;
+    scene_t S;
+    if (scene_init(&S, tri_v, face_id, mat_id, n_tri)) { scene_free(&S); return -1; }
+    for (int j = 0; j < order; ++j)
+        if (faces[j] < 0 || faces[j] >= S.F || S.fmat[faces[j]] < 0 ||
+            S.fmat[faces[j]] >= n_mat) {
+            scene_free(&S);
+            return -1;
+        }
+    const int ncol = 6 + 2 * n_mat;
+    v3 T = ld3(tx), Rx = ld3(rx);
+    /* images and the product of the mirrors */
+    m3 H[ORC_MAX_ORDER], M = m3_id();
+    v3 img = T;
+    for (int j = 0; j < order; ++j) {
+        v3 n = S.fn[faces[j]];
+        H[j] = householder(n);
+        M = m3_mul(H[j], M);
+        img = sub(img, scl(2.0 * (dot(n, img) - S.fc[faces[j]]), n));
+    }
+    v3 jr = Rx;
+    for (int j = order - 1; j >= 0; --j) {
+        v3 n = S.fn[faces[j]];
+        jr = sub(jr, scl(2.0 * (dot(n, jr) - S.fc[faces[j]]), n));
+    }
+    const m3 Mt = m3_t(M);
+    v3 du = sub(img, Rx), dw = sub(jr, T);
+    const double L = norm(du), D = norm(dw);
+    const v3 u = scl(1.0 / L, du), w = scl(1.0 / D, dw);
+    const m3 Pu = proj_perp(u), Pw = proj_perp(w);
+    /* dw/dTx = -Pw / D, dw/dRx = Pw M^T / D; dL/dTx = M^T u, dL/dRx = -u */
+    m3 dw_t, dw_r = m3_mul(Pw, Mt);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            dw_t.a[i][j] = -Pw.a[i][j] / D;
+            dw_r.a[i][j] /= D;
+        }
+    const v3 dL_t = m3_apply(Mt, u), dL_r = scl(-1.0, u);
+    const m3 dA_t = m3_mul(Pu, M);
+    for (int c = 0; c < 8 * ncol; ++c) jac[c] = 0.0;
+    /* values */
+    val[0] = L / C0;
+    val[1] = w.x; val[2] = w.y; val[3] = w.z;
+    val[4] = u.x; val[5] = u.y; val[6] = u.z;
+    const double lambda = C0 / freq_hz, k10 = 10.0 / log(10.0);
+    double P = ptx + 20.0 * log10(lambda / (4.0 * PI_D * L));
+    /* delay, AOD, AOA rows */
+    const double dLv_t[3] = {dL_t.x, dL_t.y, dL_t.z}, dLv_r[3] = {dL_r.x, dL_r.y, dL_r.z};
+    for (int a = 0; a < 3; ++a) {
+        jac[0 * ncol + a] = dLv_t[a] / C0;
+        jac[0 * ncol + 3 + a] = dLv_r[a] / C0;
+        for (int i = 0; i < 3; ++i) {
+            jac[(1 + i) * ncol + a] = dw_t.a[i][a];
+            jac[(1 + i) * ncol + 3 + a] = dw_r.a[i][a];
+            jac[(4 + i) * ncol + a] = dA_t.a[i][a] / L;
+            jac[(4 + i) * ncol + 3 + a] = -Pu.a[i][a] / L;
+        }
+        /* Friis */
+        jac[7 * ncol + a] = -2.0 * k10 / L * dLv_t[a];
+        jac[7 * ncol + 3 + a] = -2.0 * k10 / L * dLv_r[a];
+    }
+    /* reflections */
+    m3 A = m3_id();  /* H_{j-1} ... H_0 */
+    for (int j = 0; j < order; ++j) {
+        const v3 n = S.fn[faces[j]];
+        const v3 d = m3_apply(A, w);
+        const double dn = dot(d, n), cj = fabs(dn), sg = dn >= 0.0 ? 1.0 : -1.0;
+        const int32_t m = S.fmat[faces[j]];
+        double Rj, dRdc, dRdre, dRdim;
+        fresnel_derivs(cj, CMPLX(eps_re[m], eps_im[m]), &Rj, &dRdc, &dRdre, &dRdim);
+        P += 10.0 * log10(Rj);
+        /* n^T A, then times dw/dx */
+        const v3 g = m3_apply(m3_t(A), n);
+        for (int a = 0; a < 3; ++a) {
+            const double dct = sg * (g.x * dw_t.a[0][a] + g.y * dw_t.a[1][a] + g.z * dw_t.a[2][a]);
+            const double dcr = sg * (g.x * dw_r.a[0][a] + g.y * dw_r.a[1][a] + g.z * dw_r.a[2][a]);
+            jac[7 * ncol + a] += k10 * dRdc / Rj * dct;
+            jac[7 * ncol + 3 + a] += k10 * dRdc / Rj * dcr;
+        }
+        jac[7 * ncol + 6 + 2 * m] += k10 * dRdre / Rj;
+        jac[7 * ncol + 6 + 2 * m + 1] += k10 * dRdim / Rj;
+        A = m3_mul(H[j], A);
+    }
+    val[7] = P;
+    scene_free(&S);
+    return 0;
+}
+
+/* ======================================================================== */
 /* Whole method                                                              */
 /* ======================================================================== */
 typedef struct { orc_candidate* a; int64_t n, cap; } cvec;

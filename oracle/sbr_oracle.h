@@ -136,6 +136,17 @@ int orc_exact_path(const double* tri_v, const int32_t* face_id, const int32_t* m
                    double* points /* [order][3] */, double* length_m,
                    double* power_dbm, int32_t* valid);
 
+/* Values and analytic Jacobian of the image-method path quantities for one
+ * face sequence: val[8] = delay (s), AOD (3), AOA (3), power (dBm) as
+ * orc_exact_path computes them; jac[8][6 + 2 n_mat] = d val / d(Tx (3), Rx
+ * (3), (re, im) of each material's permittivity).  Returns -1 on bad
+ * arguments (order, face ids, materials). */
+int orc_path_jacobian(const double* tri_v, const int32_t* face_id, const int32_t* mat_id,
+                      int64_t n_tri, const double* eps_re, const double* eps_im, int32_t n_mat,
+                      const double tx[3], const double rx[3], int32_t order,
+                      const int32_t* faces, double freq_hz, double ptx, double* val,
+                      double* jac);
+
 /* ---- Order-1 diffraction (Sec. III.A wedges, Sec. III.B, Sec. IV) ---- */
 /* Wedges: out [cap][17] = a[3], b[3], e[3], u0[3], u1[3], f0, f1 (as doubles);
  * returns the number of wedges (all of them even when cap is smaller). */

@@ -111,6 +111,72 @@ def test_gradients_match_oracle_central_differences(city, orc):
     assert np.abs(geps).max() > 1e-3  # materials are exercised
 
 
+def _vjp_against_oracle_jacobian(gpu, orc, scene, tx, rows):
+    """Gradients of sum_i w_i . values_i from the adjoint kernel against the
+    same contraction of the oracle's analytic Jacobians (both analytic and
+    FP64: they agree to rounding)."""
+    import torch
+    from paper_2208_10009_amd import diff
+    rng = np.random.default_rng(11)
+    n = len(rows)
+    M = len(scene["eps_r"])
+    rx = np.array([r for r, _ in rows], float)
+    order = np.array([len(f) for _, f in rows], np.int32)
+    faces = np.full((n, 8), -1, np.int32)
+    for i, (_, f) in enumerate(rows):
+        faces[i, :len(f)] = f
+    w = rng.normal(size=(n, 8)) * np.array([1e7, 1, 1, 1, 1, 1, 1, 0.1])
+    want_t, want_r, want_e = np.zeros((n, 3)), np.zeros((n, 3)), np.zeros((M, 2))
+    vals = np.zeros((n, 8))
+    for i, (r, f) in enumerate(rows):
+        v, J = orc.path_jacobian(scene, tx, r, f)
+        vals[i] = v
+        g = w[i] @ J
+        want_t[i], want_r[i] = g[0:3], g[3:6]
+        want_e += g[6:].reshape(M, 2)
+    sc = gpu.scene(scene)
+    try:
+        T = torch.as_tensor(np.repeat(np.asarray(tx, float)[None], n, 0), device="cuda")
+        R = torch.as_tensor(rx, device="cuda")
+        E = torch.as_tensor(np.stack([scene["eps_r"].real, scene["eps_r"].imag], 1), device="cuda")
+        T.requires_grad_(True)
+        R.requires_grad_(True)
+        E.requires_grad_(True)
+        v = diff.path_quantities(sc, T, R, E, torch.as_tensor(order, device="cuda"),
+                                 torch.as_tensor(faces, device="cuda"))
+        (v * torch.as_tensor(w, device="cuda")).sum().backward()
+        got_v = v.detach().cpu().numpy()
+        gt, gr, ge = T.grad.cpu().numpy(), R.grad.cpu().numpy(), E.grad.cpu().numpy()
+    finally:
+        sc.close()
+    assert np.allclose(got_v[:, 0], vals[:, 0], rtol=1e-12, atol=0)
+    assert np.abs(got_v[:, 1:7] - vals[:, 1:7]).max() <= 1e-12
+    assert np.abs(got_v[:, 7] - vals[:, 7]).max() <= 1e-9
+    for got, want in ((gt, want_t), (gr, want_r), (ge, want_e)):
+        assert np.allclose(got, want, rtol=1e-9, atol=1e-9 * np.abs(want).max()), \
+            np.abs(got - want).max()
+
+
+def test_gradients_match_oracle_jacobian(gpu, orc, city):
+    """The four-material Manhattan paths of the fixture (orders 0-4)."""
+    cfg, _, paths, _ = city
+    rows = [(cfg["rx"][q["rx"]], list(q["face"][: q["order"]])) for q in paths]
+    _vjp_against_oracle_jacobian(gpu, orc, cfg["scene"], cfg["tx"], rows)
+
+
+def test_gradients_match_oracle_jacobian_non_orthogonal_faces(gpu, orc):
+    """Faces whose normals are not orthogonal, so that the mirror products
+    depend on their order (axis-aligned walls commute)."""
+    from test_oracle_gradients import _skew_room, _valid_paths
+    sc = _skew_room()
+    tx = np.array([1.0, 2.0, 2.0])
+    rx = np.array([[4.0, -3.0, 1.5], [-2.0, 5.0, 3.0]])
+    paths = _valid_paths(orc, {"scene": sc, "tx": tx}, rx, 3, 30, 6)
+    rows = [(rx[x], f) for x, f in paths]
+    assert {len(f) for _, f in rows} == {0, 1, 2, 3}
+    _vjp_against_oracle_jacobian(gpu, orc, sc, tx, rows)
+
+
 def test_closed_form_gradients(gpu):
     """Line of sight and the two-ray ground reflection: delay gradients are the
     unit vectors of the (unfolded) path divided by c; the LOS power gradient
