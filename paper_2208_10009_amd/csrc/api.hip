@@ -603,6 +603,19 @@ struct Call {
 // bound: the caller runs the call again without speculation.
 constexpr sbr_status kSpecMiss = (sbr_status)1000;
 
+// Returned when a streamed launch grid's setup did not publish in time (for
+// instance when a tool serializes the streams' kernels, so that the setup
+// cannot run beside the trace): streaming is then switched off for the
+// context and the caller runs the call again, its grid formed before its
+// trace.
+constexpr sbr_status kGridStreamMiss = (sbr_status)1001;
+
+sbr_status grid_stream_missed(sbr_context* c)
+{
+    c->grid_stream_mode = 0;
+    return kGridStreamMiss;
+}
+
 // Ball tree over the receivers perm[lo, hi) (global indices into rx), built
 // in preorder by median splits on the widest axis; returns the node index.
 int32_t build_rx_tree(const double* rx, std::vector<int32_t>& perm, int32_t lo, int32_t hi,
@@ -940,10 +953,12 @@ sbr_status run_front(sbr_context* c, Call& call, bool need_unique, int32_t* out_
         if (pass > 0)  // upload_call zeroed them for the first pass
             HIPCHK(c, hipMemsetAsync(c->counters.p, 0, sizeof(Counters), st));
         if (tallies) HIPCHK(c, hipMemsetAsync(tallies, 0, 10 * sizeof(unsigned long long), st));
+        const bool streamed = call.stream_grid;
         sbr_status r2 = trace_launch(c, call, cap, out_tri, out_t, tallies);
         if (r2) return r2;
         HIPCHK(c, hipMemcpyAsync(hc, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipStreamSynchronize(st));
+        if (streamed && (hc->err & 12)) return grid_stream_missed(c);
         if (hc->err) return fail(c, SBR_E_INTERNAL, "%s", device_error(hc->err));
         if ((int64_t)hc->cand <= cap) break;
         if (hc->cand >= (1ull << 31))
@@ -1119,12 +1134,14 @@ sbr_status run_paths(sbr_context* c, Call& call, sbr_path* out, int64_t capacity
         if (call.spec) {
             if ((hc->err & 2) != 0)
                 return fail(c, SBR_E_INTERNAL, "refinement work queue did not drain");
+            if (call.streamed && (hc->err & 12)) return grid_stream_missed(c);
             if (hc->err || (int64_t)hc->cand > call.n_cand) return kSpecMiss;
             call.n_cand = (int64_t)hc->cand;
             HIPCHK(c, hipEventElapsedTime(&call.ms_launch, c->ev[0], c->ev[1]));
             if (!call.grids_built) call.ms_launch = 0.0f;
             HIPCHK(c, hipEventElapsedTime(&call.ms_trace, c->ev[7], c->ev[2]));
         }
+        if (call.streamed && (hc->err & 12)) return grid_stream_missed(c);
         if (hc->err) return fail(c, SBR_E_INTERNAL, "%s", device_error(hc->err));
         P = hc->n_paths;
         U = hc->n_unique;
@@ -1746,14 +1763,17 @@ sbr_status sbr_trace(sbr_scene* s, const double tx[3], const double* rx, int32_t
     if (r) return r;
     sbr_context* c = s->ctx;
     HIPCHK(c, use_device(c->device));
-    Call call;
-    r = single_call(s, call, tx, rx, n_rx, p, 0, -1);
-    if (r) return r;
-    r = run_front(c, call, true, nullptr, nullptr, nullptr);
-    if (r) return r;
-    r = run_paths(c, call, out, capacity, n_out, stats);
-    if (!r) note_grid_times(c, call, p);
-    return r;
+    for (int attempt = 0;; ++attempt) {
+        Call call;
+        r = single_call(s, call, tx, rx, n_rx, p, 0, -1);
+        if (r) return r;
+        r = run_front(c, call, true, nullptr, nullptr, nullptr);
+        if (r == SBR_OK) r = run_paths(c, call, out, capacity, n_out, stats);
+        if (r == kGridStreamMiss && attempt == 0) continue;  // again, grid formed first
+        if (r == kGridStreamMiss) return fail(c, SBR_E_INTERNAL, "%s", device_error(12));
+        if (!r) note_grid_times(c, call, p);
+        return r;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -2229,8 +2249,9 @@ sbr_status sbr_trace_device(sbr_scene* s, const double tx[3], const double* rx, 
         r = single_call(s, call, tx, rx_host.empty() ? nullptr : rx_host.data(), n_rx, p, 0, -1);
         if (r) return r;
         r = run_front(c, call, true, nullptr, nullptr, nullptr, attempt == 0);
-        if (r) return r;
-        r = run_paths(c, call, out, capacity, n_out, stats, true);
+        if (r == SBR_OK) r = run_paths(c, call, out, capacity, n_out, stats, true);
+        if (r == kGridStreamMiss && attempt < 3) continue;  // again, grid formed first
+        if (r == kGridStreamMiss) return fail(c, SBR_E_INTERNAL, "%s", device_error(12));
         if (r != kSpecMiss) break;
         c->spec_events = -1;  // more events than predicted: again, reading the count
     }

@@ -480,7 +480,7 @@ __global__ void k_grid_wait_started(const unsigned long long* prog, uint32_t epo
         const unsigned long long v =
             __hip_atomic_load(prog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if ((uint32_t)(v >> 32) == epoch) return;
-        if (spin > (1u << 20)) {
+        if (spin > (1u << 16)) {  // the setup starts within microseconds when it can
             atomicOr(err, 8);
             return;
         }
