@@ -159,6 +159,10 @@ struct sbr_context {
     hipEvent_t ev_grid_fork = nullptr, ev_grid_join = nullptr;
     DevBuf gprog;
     uint32_t grid_epoch = 0;
+    // failure injection for tests (SBR_GRID_STREAM_MISS=1): the trace and the
+    // start wait expect an epoch the setup never writes and give up after a
+    // few polls, so the call takes the fallback path
+    bool grid_stream_miss = false;
     // second stream (default priority) for the exact solve beside the
     // refinement, and the events that fork to it and join back
     hipStream_t stream2 = nullptr;
@@ -881,12 +885,17 @@ sbr_status trace_launch(sbr_context* c, Call& call, int64_t cap, int32_t* out_tr
         HIPCHK(c, launch_grid_setup_streamed(call.stream_n, c->grid_scratch.p, c->grid_check_log2,
                                              prog, c->grid_epoch, c->grid_stream));
         HIPCHK(c, hipEventRecord(c->ev_grid_join, c->grid_stream));
-        HIPCHK(c, launch_grid_wait_started(prog, c->grid_epoch, &dc->err, st));
+        // the setup starts within microseconds when it can; a wave waits at
+        // most about a second for a layer
+        const uint32_t want = c->grid_epoch + (c->grid_stream_miss ? 1u : 0u);
+        HIPCHK(c, launch_grid_wait_started(prog, want, &dc->err,
+                                           c->grid_stream_miss ? 16u : (1u << 16), st));
         call.dev.gscr = (const char*)c->grid_scratch.p;
         call.dev.gprog = prog;
-        call.dev.gepoch = c->grid_epoch;
+        call.dev.gepoch = want;
         call.dev.gn = call.stream_n;
         call.dev.gcheck = c->grid_check_log2;
+        call.dev.gspin = c->grid_stream_miss ? 16u : (1u << 20);
     }
     HIPCHK(c, hipEventRecord(c->ev[7], st));
     HIPCHK(c, launch_trace(call.dev, call.lp, call.s0, trace_blocks(c, call), &dc->queue,
@@ -1331,6 +1340,7 @@ sbr_status sbr_context_create(int32_t device, void* hip_stream, sbr_context** ou
         c->la3_lds = env_int("SBR_LA3_LDS", 1, 0, 1) != 0;
         c->ray_order = env_int("SBR_RAY_ORDER", 1, 0, 1);
         c->grid_stream_mode = env_int("SBR_GRID_STREAM", 1, 0, 2);
+        c->grid_stream_miss = env_int("SBR_GRID_STREAM_MISS", 0, 0, 1) != 0;
         c->grid_order = env_int("SBR_GRID_ORDER", 2, 0, 2);
         c->grid_prefix = env_int("SBR_GRID_PREFIX", 35, 0, 100);
         if (refine_la3_set_lds_limit(c->lds_max - 2048) != hipSuccess) {

@@ -22,12 +22,12 @@ hipError_t launch_grid(GridDev g, hipStream_t s, void* scratch, int32_t check_lo
 size_t grid_scratch_bytes(int32_t n);
 // The equiangular ring setup alone, publishing its progress at prog (see
 // grid_need in grid.h) for a trace that forms its rays' directions itself;
-// and a one-lane wait (bounded; err |= 8 on time-out) until the setup of
-// this epoch has started.
+// and a one-lane wait (at most max_spin polls; err |= 8 on time-out) until the
+// setup of this epoch has started.
 hipError_t launch_grid_setup_streamed(int32_t n, void* scratch, int32_t check_log2,
                                       unsigned long long* prog, uint32_t epoch, hipStream_t s);
 hipError_t launch_grid_wait_started(const unsigned long long* prog, uint32_t epoch, int32_t* err,
-                                    hipStream_t s);
+                                    uint32_t max_spin, hipStream_t s);
 // cell[i] = the cube-map cell (R x R per cube face, Z order) of ray i's
 // direction, R a power of two <= 8192.
 hipError_t launch_ray_cells(const double* dir, int64_t N, int32_t R, uint32_t* cell,

@@ -473,14 +473,14 @@ hipError_t launch_grid_setup_streamed(int32_t n, void* scratch, int32_t check_lo
 // Wait (one lane, bounded) until the setup of this epoch has started, so that
 // the trace launched after it cannot take the slot the setup needs.
 __global__ void k_grid_wait_started(const unsigned long long* prog, uint32_t epoch,
-                                    int32_t* err)
+                                    int32_t* err, uint32_t max_spin)
 {
     if (threadIdx.x != 0) return;
     for (uint32_t spin = 0;; ++spin) {
         const unsigned long long v =
             __hip_atomic_load(prog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if ((uint32_t)(v >> 32) == epoch) return;
-        if (spin > (1u << 16)) {  // the setup starts within microseconds when it can
+        if (spin > max_spin) {
             atomicOr(err, 8);
             return;
         }
@@ -489,9 +489,9 @@ __global__ void k_grid_wait_started(const unsigned long long* prog, uint32_t epo
 }
 
 hipError_t launch_grid_wait_started(const unsigned long long* prog, uint32_t epoch, int32_t* err,
-                                    hipStream_t s)
+                                    uint32_t max_spin, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_grid_wait_started, dim3(1), dim3(64), 0, s, prog, epoch, err);
+    hipLaunchKernelGGL(k_grid_wait_started, dim3(1), dim3(64), 0, s, prog, epoch, err, max_spin);
     return hipGetLastError();
 }
 

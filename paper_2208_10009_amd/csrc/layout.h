@@ -158,6 +158,7 @@ struct CallDev {
     uint32_t gepoch;
     int32_t gn;           // the grid's division n
     int32_t gcheck;       // the grid's check_log2
+    uint32_t gspin;       // polls before a wave gives up waiting for the setup (sets err 4)
 };
 
 }  // namespace sbr

@@ -232,6 +232,7 @@ struct StreamArgs {
     const unsigned long long* prog;
     uint32_t epoch;
     int32_t n, check;
+    uint32_t spin;
 };
 
 __device__ static void stream_dirs(const StreamArgs& sa, uint32_t* seen, const JobDev& J,
@@ -262,7 +263,7 @@ __device__ static void stream_dirs(const StreamArgs& sa, uint32_t* seen, const J
                 atomicMax(seen, (uint32_t)v);
                 break;
             }
-            if (spin > (1u << 20)) {
+            if (spin > sa.spin) {
                 atomicOr(err, 4);
                 break;
             }
@@ -310,7 +311,8 @@ void k_trace(CallDev call, LdsPlan L, SceneDev s0,
     __shared__ uint32_t s_seen;  // the setup progress this workgroup has seen
     if (STREAM) {
         if (threadIdx.x == 0) {
-            s_stream = StreamArgs{call.gscr, call.gprog, call.gepoch, call.gn, call.gcheck};
+            s_stream = StreamArgs{call.gscr, call.gprog, call.gepoch, call.gn, call.gcheck,
+                                  call.gspin};
             s_seen = 0;
         }
         if (!LDS) __syncthreads();

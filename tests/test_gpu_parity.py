@@ -418,6 +418,39 @@ def test_streamed_grid(orc, n):
     assert np.array_equal(bits(d), bits(orc.launch_dirs(n)))
 
 
+@pytest.mark.parametrize("device_api", [False, True])
+def test_streamed_grid_fallback(orc, device_api):
+    """A streamed grid whose setup does not publish in time (forced from the
+    host: the trace and the start wait expect an epoch the setup never
+    writes, and give up after a few polls) switches streaming off for the
+    context; the call runs again with its grid formed first and returns the
+    same paths."""
+    import torch
+    ctx = _context_with_env({"SBR_GRID_STREAM": "2", "SBR_GRID_STREAM_MISS": "1"})
+    cfg = scenes.manhattan_config(1, n_rx=16)
+    prm = dict(cfg["params"], division_n=20)
+    sc = ctx.scene(cfg["scene"])
+    rx = torch.as_tensor(cfg["rx"], device="cuda")
+    try:
+        runs = []
+        for _ in range(3):
+            if device_api:
+                p, st = sc.trace_device(cfg["tx"], rx, fresh_grid=True, **prm)
+                runs.append((p.cpu().numpy().tobytes(), st))
+            else:
+                p, st = sc.trace(cfg["tx"], cfg["rx"], fresh_grid=True, **prm)
+                runs.append((p.tobytes(), st))
+        d = ctx.launch_grid(20)
+    finally:
+        sc.close()
+        ctx.close()
+    assert all(b == runs[0][0] for b, _ in runs)
+    # every call formed its grid before its trace: the first by rule, the
+    # second on its retry, the third with streaming switched off
+    assert all(st["ms_launch"] > 0 for _, st in runs)
+    assert np.array_equal(bits(d), bits(orc.launch_dirs(20)))
+
+
 def test_streamed_grid_automatic_choice(gpu):
     """By default a grid is streamed only once a fresh call of it has shown
     a trace at least three times as long as its grid: never for a 12-triangle
