@@ -85,7 +85,16 @@ typedef struct {
 #define SBR_LAUNCH_EQUIDISTANT_OCTA 2
 
 #define SBR_FLAG_KEEP_INVALID 1u /* keep paths that fail path test 2 (flag INVALID) */
-#define SBR_FLAG_FRESH_GRID 2u   /* recompute the launch directions even when cached */
+#define SBR_FLAG_FRESH_GRID 2u   /* recompute the launch directions even when cached.
+                                    sbr_trace and sbr_trace_device may then run the
+                                    equiangular ring setup on a second stream of the
+                                    context beside the trace, which forms the directions
+                                    itself (the same values; a call whose setup cannot
+                                    run concurrently is redone with the grid formed
+                                    first).  Environment at context creation:
+                                    SBR_GRID_STREAM=1 (default) when a previous fresh
+                                    call of that grid traced at least three times as long
+                                    as it formed the grid, 2 always, 0 never */
 #define SBR_FLAG_GRAPH 4u        /* sbr_trace_device, sbr_trace_batch: capture the call as
                                     a HIP graph and replay it on later calls of the same
                                     shape */
