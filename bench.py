@@ -51,10 +51,22 @@ EVENT_BYTES = 56    # reception event record written
 # combines, the overlap compare); a ray-triangle test is the FP64
 # Moller-Trumbore of 50 (two cross products of 9, four dot products of 5,
 # o - v0, three divisions, six compares and the u + v add); a segment is the
-# specular reflection and the move to the hit point (19).
+# specular reflection and the move to the hit point (19).  Reception (eq. (3),
+# fused into the same kernel): a receiver-tree box tested against a segment's
+# reception cone is 39 (c - o; the largest foot parameter over the box, a dot
+# product and three |d_i| h_i terms; its minimum with t; the cone radius
+# there; per axis the widened half-extent, the two slab bounds, their two
+# products with 1/d_i and the running maximum and minimum; the final
+# compare); a receiver tested on a segment is 25 (rx - o, t* = (rx - o).d,
+# 0 < t* <= t, the perpendicular f, D + t*, |f|^2 against
+# (theta_launch (D + t*))^2).
 NODE_OPS = 60
 TRI_OPS = 50
 SEG_OPS = 19
+RX_NODE_OPS = 39
+RX_TEST_OPS = 25
+RX_NODE_BYTES = 64  # receiver-tree node: box centre and half-extents, first/count/skip
+RX_BYTES = 16       # FP32 receiver copy read by the pre-test
 # Peak VALU lane operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 # (one wave64 instruction per SIMD every 4 cycles, FP32 and FP64 alike; twice
 # this in flops is the published 78.6 TFLOP/s FP64 vector peak).
@@ -107,9 +119,11 @@ def trace_roofline(counts, n_rays, kernel_ms, workload):
     launch over its mean HIP-event time, against the VALU peak; beside it the
     measured HBM traffic and its fraction of 8 TB/s, the bytes the traversal
     touches (served from LDS, L1 and L2, not HBM) and the VALU counters."""
-    ops = counts["nodes"] * NODE_OPS + counts["tris"] * TRI_OPS + counts["segments"] * SEG_OPS
+    ops = (counts["nodes"] * NODE_OPS + counts["tris"] * TRI_OPS + counts["segments"] * SEG_OPS
+           + counts.get("rx_nodes", 0) * RX_NODE_OPS + counts.get("rx_tests", 0) * RX_TEST_OPS)
     touched = (counts["nodes"] * NODE_BYTES + counts["tris"] * TRI_BYTES + n_rays * RAY_BYTES
-               + counts["events"] * EVENT_BYTES)
+               + counts["events"] * EVENT_BYTES + counts.get("rx_nodes", 0) * RX_NODE_BYTES
+               + counts.get("rx_tests", 0) * RX_BYTES)
     sec = kernel_ms * 1e-3
     ach = ops / sec / 1e9
     mc = measured_counters(workload)
@@ -119,7 +133,8 @@ def trace_roofline(counts, n_rays, kernel_ms, workload):
         "peak": VALU_PEAK_GOPS, "unit": "Gop/s", "frac": round(ach / VALU_PEAK_GOPS, 5),
         "traffic": traffic,
         "ops_per_launch": int(ops),
-        "ops_per_unit": {"node_visit": NODE_OPS, "triangle_test": TRI_OPS, "segment": SEG_OPS},
+        "ops_per_unit": {"node_visit": NODE_OPS, "triangle_test": TRI_OPS, "segment": SEG_OPS,
+                         "rx_node_test": RX_NODE_OPS, "rx_test": RX_TEST_OPS},
         "kernel_ms": round(kernel_ms, 5),
         "hbm": {"achieved_gbs": round(traffic / sec / 1e9, 1) if traffic else None,
                 "frac": round(traffic / sec / 1e9 / HBM_PEAK_GBS, 5) if traffic else None},
@@ -133,6 +148,9 @@ def trace_roofline(counts, n_rays, kernel_ms, workload):
         if counts.get("wave_tri_steps") else None,
         "segment_loop_lanes": round(counts["segments"] / (64 * counts["wave_seg_steps"]), 4)
         if counts.get("wave_seg_steps") else None,
+        "rx_loop_lanes": round((counts.get("rx_nodes", 0) + counts.get("rx_tests", 0)) /
+                               (64 * counts["wave_rx_steps"]), 4)
+        if counts.get("wave_rx_steps") else None,
         "wave_steps": {k: counts.get(k) for k in ("wave_node_steps", "wave_tri_steps",
                                                    "wave_seg_steps", "wave_rx_steps")},
     }

@@ -173,7 +173,7 @@ typedef struct {
  * iteration's sub-rays, so every path runs its own number of iterations
  * without a relaunch (calls whose queue would exceed 256 MiB use depth 1).
  * A job with at least rx_tree_min receivers tests reception through
- * a ball tree over its receivers (a conservative cull before the exact test
+ * a box tree over its receivers (a conservative cull before the exact test
  * of eq. (3)) instead of testing every receiver on every segment.  The
  * equiangular grid's setup takes a value from short series when its error
  * bound, scaled by 2^grid_check_log2, proves the rounding, and otherwise
@@ -446,10 +446,14 @@ sbr_status sbr_diff_candidates(sbr_scene* scene, const double tx[3], const doubl
  * triangle loop, segment loop and receiver loops (one per wave and pass in
  * which any lane visits a node, tests a triangle, traces a segment, tests a
  * receiver or receiver-tree node), so that counts[1] / (64 counts[5]) is the
- * share of lanes busy in the node loop; counts[9] is 0.  counts[0..3]
- * define the algorithmic work of the trace kernel for its roofline. */
+ * share of lanes busy in the node loop; counts[9] receiver-tree nodes (boxes)
+ * tested against a segment's reception cone, counts[10] receivers tested on
+ * a segment (eq. (3): every receiver of a segment that can reach the
+ * receivers' box, or of a tree leaf whose box passed); counts[11] is 0.
+ * counts[0..2], [9] and [10] define the algorithmic work of the trace
+ * kernel for its roofline. */
 sbr_status sbr_trace_counters(sbr_scene* scene, const double tx[3], const double* rx,
-                              int32_t n_rx, const sbr_trace_params* params, int64_t counts[10]);
+                              int32_t n_rx, const sbr_trace_params* params, int64_t counts[12]);
 
 const char* sbr_status_string(sbr_status status);
 /* Message of the last failing call on ctx (empty if none); valid until the

@@ -620,8 +620,10 @@ sbr_status grid_stream_missed(sbr_context* c)
     return kGridStreamMiss;
 }
 
-// Ball tree over the receivers perm[lo, hi) (global indices into rx), built
+// Box tree over the receivers perm[lo, hi) (global indices into rx), built
 // in preorder by median splits on the widest axis; returns the node index.
+// Each node's box c +- h holds its receivers (h widened by 1e-12 relative
+// and 1e-300 over the largest offset from c).
 int32_t build_rx_tree(const double* rx, std::vector<int32_t>& perm, int32_t lo, int32_t hi,
                       std::vector<RxNode>& nodes)
 {
@@ -634,14 +636,12 @@ int32_t build_rx_tree(const double* rx, std::vector<int32_t>& perm, int32_t lo, 
             bh[a] = std::max(bh[a], rx[3 * perm[i] + a]);
         }
     RxNode nd{};
-    for (int a = 0; a < 3; ++a) nd.c[a] = 0.5 * (bl[a] + bh[a]);
-    double r2 = 0.0;
-    for (int32_t i = lo; i < hi; ++i) {
-        double dx = rx[3 * perm[i]] - nd.c[0], dy = rx[3 * perm[i] + 1] - nd.c[1],
-               dz = rx[3 * perm[i] + 2] - nd.c[2];
-        r2 = std::max(r2, dx * dx + dy * dy + dz * dz);
+    for (int a = 0; a < 3; ++a) {
+        nd.c[a] = 0.5 * (bl[a] + bh[a]);
+        double e = 0.0;
+        for (int32_t i = lo; i < hi; ++i) e = std::max(e, fabs(rx[3 * perm[i] + a] - nd.c[a]));
+        nd.h[a] = e * (1.0 + 1e-12) + 1e-300;
     }
-    nd.rho = std::sqrt(r2) * (1.0 + 1e-12);
     if (hi - lo <= kRxLeaf) {
         nd.first = lo;
         nd.count = hi - lo;
@@ -961,7 +961,7 @@ sbr_status run_front(sbr_context* c, Call& call, bool need_unique, int32_t* out_
         HIPCHK(c, ensure(c->cand, sizeof(sbr_candidate) * (size_t)cap));
         if (pass > 0)  // upload_call zeroed them for the first pass
             HIPCHK(c, hipMemsetAsync(c->counters.p, 0, sizeof(Counters), st));
-        if (tallies) HIPCHK(c, hipMemsetAsync(tallies, 0, 10 * sizeof(unsigned long long), st));
+        if (tallies) HIPCHK(c, hipMemsetAsync(tallies, 0, 12 * sizeof(unsigned long long), st));
         const bool streamed = call.stream_grid;
         sbr_status r2 = trace_launch(c, call, cap, out_tri, out_t, tallies);
         if (r2) return r2;
@@ -1753,15 +1753,15 @@ sbr_status sbr_trace_counters(sbr_scene* s, const double tx[3], const double* rx
     sbr_context* c = s->ctx;
     if (!counts) return fail(c, SBR_E_INVALID_ARG, "counts is NULL");
     HIPCHK(c, use_device(c->device));
-    HIPCHK(c, ensure(c->tally, 10 * sizeof(unsigned long long)));
+    HIPCHK(c, ensure(c->tally, 12 * sizeof(unsigned long long)));
     Call call;
     r = single_call(s, call, tx, rx, n_rx, p, 0, -1);
     if (r) return r;
     r = run_front(c, call, false, nullptr, nullptr, c->tally.as<unsigned long long>());
     if (r) return r;
-    unsigned long long h[10];
+    unsigned long long h[12];
     HIPCHK(c, hipMemcpy(h, c->tally.p, sizeof h, hipMemcpyDeviceToHost));
-    for (int i = 0; i < 10; ++i) counts[i] = (int64_t)h[i];
+    for (int i = 0; i < 12; ++i) counts[i] = (int64_t)h[i];
     return SBR_OK;
 }
 

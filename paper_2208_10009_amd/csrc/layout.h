@@ -103,17 +103,17 @@ inline int64_t num_rays(int32_t launch, int32_t n)
     return (launch == SBR_LAUNCH_EQUIDISTANT_OCTA ? 4 : 10) * (int64_t)n * n + 2;
 }
 
-// Ball-tree node over receivers (48 B), in depth-first preorder: the ball
-// (centre c, radius rho) holds every receiver below.  count > 0: a leaf of
-// the receivers perm[first .. first + count) (global receiver indices);
-// count == 0: an inner node whose left child is the next node.  skip is the
-// node after this subtree, where a walk goes when the ball is rejected.
+// Receiver-tree node (64 B), in depth-first preorder: the box c +- h holds
+// every receiver below.  count > 0: a leaf of the receivers perm[first ..
+// first + count) (global receiver indices); count == 0: an inner node whose
+// left child is the next node.  skip is the node after this subtree, where a
+// walk goes when the box is rejected.
 struct RxNode {
     double c[3];
-    double rho;
+    double h[3];
     int32_t first, count, skip, pad;
 };
-static_assert(sizeof(RxNode) == 48, "RxNode layout");
+static_assert(sizeof(RxNode) == 64, "RxNode layout");
 constexpr int kRxLeaf = 4;
 
 // One job of a trace call: a transmitter, its receivers (a slice of the

@@ -1,7 +1,7 @@
 // trace.hip -- SBR tracing and reception (Sec. III.A): closest hit per
 // segment, specular reflection up to K bounces, and the cone reception test
 // of every receiver on every segment (eq. (3)), fused, one lane per launch
-// ray.  Jobs with many receivers walk a ball tree over them and run the
+// ray.  Jobs with many receivers walk a box tree over them and run the
 // exact test only where a conservative cull lets a receiver through.  The
 // kernel is persistent: waves take packets of 64 x chunk rays from a device
 // queue until it is empty, so jobs of uneven size are balanced over the
@@ -320,7 +320,7 @@ void k_trace(CallDev call, LdsPlan L, SceneDev s0,
     if (LDS) stage_scene(s0, L);
     const int lane = threadIdx.x & 63;
     const uint64_t below = (1ull << lane) - 1ull;
-    Tally tl{0u, 0u, 0u, 0u, 0u, 0u, 0u};
+    Tally tl{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
     uint32_t segs = 0, events = 0;
     JobDev J{};
     SceneDev S = s0;
@@ -382,8 +382,10 @@ void k_trace(CallDev call, LdsPlan L, SceneDev s0,
             // FP32 pre-test of every receiver (wave-uniform, scalar loads),
             // the FP64 test for the few it lets through; skipped when no
             // busy lane's segment can reach the receivers' box
-            if (__ballot(rx_box_may(g32, box)) != 0) {
+            const bool mine = rx_box_may(g32, box);
+            if (__ballot(mine) != 0) {
                 if (COUNT && first_active_lane()) tl.wave_rx += (uint32_t)J.n_rx;
+                if (COUNT && mine) tl.rx_tests += (uint32_t)J.n_rx;
                 for (int x = 0; x < J.n_rx; ++x) {
                     const int32_t gx = J.rx_first + x;
                     if (rx_may_capture32(g32, cld4(call.rx32 + gx)))
@@ -395,27 +397,25 @@ void k_trace(CallDev call, LdsPlan L, SceneDev s0,
             // segment cannot reach the receivers' box skip it)
             int32_t nd = J.rx_root;
             const int32_t end = call.rx_nodes[nd].skip;
+            const d3 inv = mk(1.0 / R.d.x, 1.0 / R.d.y, 1.0 / R.d.z);
             while (nd != end) {
                 if (COUNT && first_active_lane()) tl.wave_rx += 1;
+                if (COUNT) tl.rx_nodes += 1;
                 const double2* q = (const double2*)(call.rx_nodes + nd);
-                const double2 c01 = gld(q), c2r = gld(q + 1), m = gld(q + 2);
+                const double2 c01 = gld(q), c2h0 = gld(q + 1), h12 = gld(q + 2), m = gld(q + 3);
                 RxNode N;
-                N.c[0] = c01.x;
-                N.c[1] = c01.y;
-                N.c[2] = c2r.x;
-                N.rho = c2r.y;
-                const long long w0 = __double_as_longlong(m.x), w1 = __double_as_longlong(m.y);
-                N.first = (int32_t)(w0 & 0xffffffffll);
-                N.count = (int32_t)(w0 >> 32);
-                N.skip = (int32_t)(w1 & 0xffffffffll);
-                if (!rx_ball_may_capture(R.o, R.d, R.D, t, mk(N.c[0], N.c[1], N.c[2]), N.rho,
-                                         J.thl)) {
+                N.first = (int32_t)(__double_as_longlong(m.x) & 0xffffffffll);
+                N.count = (int32_t)(__double_as_longlong(m.x) >> 32);
+                N.skip = (int32_t)(__double_as_longlong(m.y) & 0xffffffffll);
+                if (!rx_box_may_capture(R.o, R.d, inv, R.D, t, mk(c01.x, c01.y, c2h0.x),
+                                        mk(c2h0.y, h12.x, h12.y), J.thl)) {
                     nd = N.skip;
                 } else if (N.count == 0) {
                     nd = nd + 1;
                 } else {
                     for (int q = 0; q < N.count; ++q) {
                         if (COUNT && first_active_lane()) tl.wave_rx += 1;
+                        if (COUNT) tl.rx_tests += 1;
                         const int32_t gx = gld(call.rx_perm + N.first + q);
                         if (rx_may_capture32(g32, gld(call.rx32 + gx)))
                             receive(J, call.rx, R, t, gx, cand, cap, ccount, &events, COUNT);
@@ -456,6 +456,8 @@ void k_trace(CallDev call, LdsPlan L, SceneDev s0,
         atomicAdd(&tallies[6], (unsigned long long)tl.wave_tris);
         atomicAdd(&tallies[7], (unsigned long long)tl.wave_segs);
         atomicAdd(&tallies[8], (unsigned long long)tl.wave_rx);
+        atomicAdd(&tallies[9], (unsigned long long)tl.rx_nodes);
+        atomicAdd(&tallies[10], (unsigned long long)tl.rx_tests);
     }
 }
 

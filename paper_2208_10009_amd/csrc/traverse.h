@@ -143,6 +143,7 @@ struct HitRec {
 // / (64 wave_nodes) is the share of lanes busy in the node loop).
 struct Tally {
     uint32_t nodes, tris, fp64_tris, wave_nodes, wave_tris, wave_segs, wave_rx;
+    uint32_t rx_nodes, rx_tests;  // receiver-tree nodes tested, receivers tested (per lane)
 };
 
 // Whether this lane is the lowest active lane of its wave (counts once per
@@ -420,26 +421,47 @@ __device__ static inline bool capture(d3 o, d3 d, double D, double t, d3 rx, dou
     return true;
 }
 
-// Can any receiver inside the ball (c, rho) of a receiver-tree node pass the
-// reception test of the segment (o, d, D, t)?  For x in the ball, t*(x)
-// differs from t*(c) by at most rho |d|, and the distance from x to the ray
-// line from that of c by at most rho (x -> (x - o) - ((x - o).d) d has norm 1
-// for |d| = 1 + O(eps)).  So a capture needs 0 < t*(c) + rho |d|,
-// t*(c) - rho |d| <= t and d_perp(c) <= thl (D + t*(c) + rho |d|) + rho.  The
-// radius r used here widens rho by 1e-6 relative and by 1e-9 of the lengths
-// involved, far above the rounding of this test or of capture(), so the cull
-// never drops a receiver that capture() accepts.
-__device__ static inline bool rx_ball_may_capture(d3 o, d3 d, double D, double t, d3 c,
-                                                  double rho, double thl)
+// Can any receiver inside the box c +- h of a receiver-tree node pass the
+// reception test of the segment (o, d, D, t)?  A receiver x that passes has
+// foot parameter t*(x) = (x - o).d in (0, t] and lies within
+// thl (D + t*(x)) of o + t*(x) d.  Over the box t*(x) <= T = (c - o).d +
+// sum_i h_i |d_i|, so o + t*(x) d, with t*(x) in (0, min(t, T)], lies inside
+// the box widened by rho = thl (D + min(t, T)) on every side: the segment's
+// parameter range [0, min(t, T)] meets every axis's slab of the widened box
+// (parameters by the inverse direction inv; an axis with d_i = 0 needs o_i in
+// its slab).  rho is widened by 1e-6 relative and by m = 1e-9 of the lengths
+// involved, and the range by m, far above the rounding of this test or of
+// capture(), so the cull never drops a receiver that capture() accepts.  For
+// receivers spread over a plane a box stays flat where a ball around the same
+// receivers would reach far above and below it.
+__device__ static inline bool rx_box_may_capture(d3 o, d3 d, d3 inv, double D, double t, d3 c,
+                                                 d3 h, double thl)
 {
-    d3 v = sub(c, o);
-    double tc = dot(v, d);
-    double r = rho * (1.0 + 1e-6) + 1e-9 * (D + (fabs(v.x) + fabs(v.y) + fabs(v.z)));
-    if (tc + r <= 0.0) return false;
-    if (tc - r > t) return false;
-    d3 w = sub(v, scl(tc, d));
-    double A = thl * (D + tc + r) + r;
-    return dot(w, w) <= A * A;
+    const d3 v = sub(c, o);
+    const double T = dot(v, d) + (h.x * fabs(d.x) + h.y * fabs(d.y) + h.z * fabs(d.z));
+    const double m = 1e-9 * (D + fabs(o.x) + fabs(o.y) + fabs(o.z) + fabs(c.x) + fabs(c.y) +
+                             fabs(c.z) + h.x + h.y + h.z);
+    if (T + m <= 0.0) return false;
+    const double s1 = fmin(t, T) + m;
+    const double rho = thl * (D + s1) * (1.0 + 1e-6) + m;
+    double slo = -m, shi = s1;
+    const double vv[3] = {v.x, v.y, v.z}, hh[3] = {h.x, h.y, h.z}, dd[3] = {d.x, d.y, d.z},
+                 ii[3] = {inv.x, inv.y, inv.z};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        // o_a + s d_a in [c_a - h_a - rho, c_a + h_a + rho]
+        const double e = hh[a] + rho, lo = vv[a] - e, hi = vv[a] + e;
+        if (dd[a] > 0.0) {
+            slo = fmax(slo, lo * ii[a]);
+            shi = fmin(shi, hi * ii[a]);
+        } else if (dd[a] < 0.0) {
+            slo = fmax(slo, hi * ii[a]);
+            shi = fmin(shi, lo * ii[a]);
+        } else if (lo > 0.0 || hi < 0.0) {
+            return false;
+        }
+    }
+    return slo <= shi;
 }
 
 }  // namespace sbr

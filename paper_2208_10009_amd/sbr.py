@@ -482,15 +482,16 @@ class Scene:
     def trace_counters(self, tx, rx, **params):
         """sbr_trace_counters: dict of segments, nodes, tris, events,
         tris_run, wave_node_steps, wave_tri_steps, wave_seg_steps,
-        wave_rx_steps."""
+        wave_rx_steps, rx_nodes, rx_tests."""
         txa = np.ascontiguousarray(tx, np.float64).reshape(3)
         rxa = np.ascontiguousarray(rx, np.float64).reshape(-1, 3)
         prm = make_params(**params)
-        out = np.zeros(10, np.int64)
+        out = np.zeros(12, np.int64)
         self.ctx._check(lib().sbr_trace_counters(self.h, _d(txa), _d(rxa), len(rxa), C.byref(prm),
                                                  out.ctypes.data_as(C.POINTER(C.c_int64))))
         return dict(zip(("segments", "nodes", "tris", "events", "tris_run", "wave_node_steps",
-                         "wave_tri_steps", "wave_seg_steps", "wave_rx_steps"),
+                         "wave_tri_steps", "wave_seg_steps", "wave_rx_steps", "rx_nodes",
+                         "rx_tests"),
                         (int(v) for v in out)))
 
     def close(self):

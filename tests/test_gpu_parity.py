@@ -587,8 +587,32 @@ def test_trace_counters_are_consistent(gpu):
                          ("segments", "wave_seg_steps")):
         assert c[steps] <= c[lanes] <= 64 * c[steps], (lanes, c)
     assert c["tris_run"] <= c["tris"] and c["wave_rx_steps"] > 0
-    for k in ("segments", "nodes", "tris", "events", "tris_run"):
+    rx_lanes = c["rx_nodes"] + c["rx_tests"]
+    assert c["wave_rx_steps"] <= rx_lanes <= 64 * c["wave_rx_steps"], c
+    assert c["rx_nodes"] == 0 and c["rx_tests"] > 0  # 32 receivers: tested one by one
+    for k in ("segments", "nodes", "tris", "events", "tris_run", "rx_nodes", "rx_tests"):
         assert c2[k] == c[k], k
+
+
+def test_trace_counters_receiver_tree(gpu):
+    """Through the receiver ball tree: balls and receivers tested, each wave
+    pass of the receiver walk serving 1 to 64 lanes, and the same events as
+    testing every receiver."""
+    cfg = scenes.manhattan_config(2, n_rx=256)
+    prm = dict(cfg["params"], division_n=100)
+    sc = gpu.scene(cfg["scene"])
+    base = gpu.tuning()
+    try:
+        gpu.set_tuning(**dict(base, rx_tree_min=16))
+        t = sc.trace_counters(cfg["tx"], cfg["rx"], **prm)
+        gpu.set_tuning(**dict(base, rx_tree_min=1 << 30))
+        lin = sc.trace_counters(cfg["tx"], cfg["rx"], **prm)
+    finally:
+        gpu.set_tuning(**base)
+        sc.close()
+    assert t["rx_nodes"] > 0 and 0 < t["rx_tests"] < lin["rx_tests"]
+    assert t["wave_rx_steps"] <= t["rx_nodes"] + t["rx_tests"] <= 64 * t["wave_rx_steps"]
+    assert t["events"] == lin["events"] and t["segments"] == lin["segments"]
 
 
 def test_lds_staged_traversal_matches(gpu, orc):
