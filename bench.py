@@ -444,8 +444,6 @@ def large_city_leg(ctx, scenes, torch, steps, warmup, tuning=None):
     t0 = time.perf_counter()
     sc = ctx.scene(cfg["scene"])
     build_s = time.perf_counter() - t0
-    counts = sc.trace_counters(cfg["tx"], cfg["rx"], **prm)
-    log("large city counts", counts)
     rx_tune = torch.as_tensor(cfg["rx"], device="cuda")
     if tuning:
         ctx.set_tuning(**dict(ctx.tuning(), **tuning))
@@ -457,6 +455,9 @@ def large_city_leg(ctx, scenes, torch, steps, warmup, tuning=None):
                    "rx_tree_min": [16, 1 << 30], "lds_budget": [65536, 0, 24 * 4 * 256],
                    "stack_depth": [24]}, warmup=1, steps=2)
     log("large city tuning", best)
+    # work counts in the timed tuning (the receiver tree depends on it)
+    counts = sc.trace_counters(cfg["tx"], cfg["rx"], **prm)
+    log("large city counts", counts)
     out_buf = torch.empty((8192, sbr.PATH_DTYPE.itemsize), dtype=torch.uint8, device="cuda")
     paths, wall, stage, stats = timed_device(sc, cfg, torch, steps, warmup, out_buf,
                                              fresh_grid=True, **prm)
@@ -501,7 +502,6 @@ def manhattan_leg(ctx, scenes, torch, args):
     prm = cfg["params"]
     sc = ctx.scene(cfg["scene"])
     n_rays = 10 * prm["division_n"] ** 2 + 2
-    counts = sc.trace_counters(cfg["tx"], cfg["rx"], **prm)
     rx_tune = torch.as_tensor(cfg["rx"], device="cuda")
     entry = ctx.tuning()
     if args.tuning:
@@ -515,6 +515,7 @@ def manhattan_leg(ctx, scenes, torch, args):
                    "lookahead_max_paths": [4096], "rx_tree_min": [16, 1 << 30]}, warmup=1,
             steps=5)
     log("manhattan tuning", best)
+    counts = sc.trace_counters(cfg["tx"], cfg["rx"], **prm)
     out_buf = torch.empty((4096, sbr.PATH_DTYPE.itemsize), dtype=torch.uint8, device="cuda")
     steps, warmup = args.steps, args.warmup
     paths, wall, stage, stats = timed_device(sc, cfg, torch, steps, warmup, out_buf,

@@ -141,7 +141,7 @@ typedef struct {
     int64_t lds_bytes, lds_nodes, lds_tris, lds_max;
 } sbr_trace_stats;
 
-/* BVH build options; NULL means defaults (leaf size 4, 32 SAH bins, no
+/* BVH build options; NULL means defaults (leaf size 4, 64 SAH bins, no
  * split references).  With split_pct > 0 a triangle whose box is large next
  * to the scene's median triangle box may enter the hierarchy as several
  * references, each bounding the part of the triangle in one cell of a

@@ -70,7 +70,7 @@ struct Counters {
 }  // namespace
 
 // BVH defaults when sbr_bvh_build gets no parameters.
-constexpr int kDefaultSahBins = 32;
+constexpr int kDefaultSahBins = 64;
 constexpr int kDefaultSplitPct = 0;
 
 // Device memory of sbr_trace_device_noalloc: everything that entry point needs
@@ -1745,7 +1745,7 @@ sbr_status sbr_candidates(sbr_scene* s, const double tx[3], const double* rx, in
 }
 
 sbr_status sbr_trace_counters(sbr_scene* s, const double tx[3], const double* rx, int32_t n_rx,
-                              const sbr_trace_params* p, int64_t counts[10])
+                              const sbr_trace_params* p, int64_t counts[12])
 {
     int64_t dummy;
     sbr_status r = check_trace_inputs(s, tx, rx, n_rx, p, 0, nullptr, &dummy);

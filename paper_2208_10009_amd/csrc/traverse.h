@@ -128,7 +128,13 @@ __device__ static inline TriD tri_at(const SceneDev& S, const LdsPlan& L, int32_
         return make_tri(q[0], q[1], q[2], q[3], q[4]);
     }
     const double2* q = (const double2*)(S.tris + i);
-    return make_tri(gld(q), gld(q + 1), gld(q + 2), gld(q + 3), gld(q + 4));
+    const double2 a = gld(q), b = gld(q + 1), c = gld(q + 2), d = gld(q + 3), e = gld(q + 4);
+    // An empty statement that takes all five pieces: the compiler must issue
+    // the five loads together here, instead of loading the face word first
+    // and the rest only after the face test (two dependent memory trips).
+    asm volatile("" ::"v"(a.x), "v"(a.y), "v"(b.x), "v"(b.y), "v"(c.x), "v"(c.y), "v"(d.x),
+                 "v"(d.y), "v"(e.x), "v"(e.y));
+    return make_tri(a, b, c, d, e);
 }
 
 struct HitRec {

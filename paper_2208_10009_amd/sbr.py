@@ -275,7 +275,7 @@ class Context:
         t = Tuning(**cur)
         self._check(lib().sbr_context_set_tuning(self.h, C.byref(t)))
 
-    def scene(self, scene: dict, max_leaf_size: int = 4, sah_bins: int = 32,
+    def scene(self, scene: dict, max_leaf_size: int = 4, sah_bins: int = 64,
               split_pct: int = 0) -> "Scene":
         return Scene(self, scene, max_leaf_size, sah_bins, split_pct)
 
@@ -321,7 +321,7 @@ class Context:
 class Scene:
     """sbr_scene_upload + sbr_bvh_build of a scene dict (see scenes.py)."""
 
-    def __init__(self, ctx: Context, scene: dict, max_leaf_size=4, sah_bins=32, split_pct=0):
+    def __init__(self, ctx: Context, scene: dict, max_leaf_size=4, sah_bins=64, split_pct=0):
         self.ctx = ctx
         xyz = np.ascontiguousarray(scene["xyz"], np.float64).reshape(-1, 3)
         tri = np.ascontiguousarray(scene["tri"], np.int32).reshape(-1, 3)
