@@ -50,7 +50,7 @@ int main(int argc, char** argv)
     fclose(f);
     const int split = atoi(argv[2]);
     const int samples = atoi(argv[3]);
-    build_bvh(v.data(), T, 4, 32, split, argc > 4, g_nodes, g_perm);
+    build_bvh(v.data(), T, 4, 64, split, argc > 4, g_nodes, g_perm);
     std::vector<int32_t> nref((size_t)T, 0);
     for (int32_t t : g_perm) nref[t] += 1;
     int64_t split_tris = 0, checked = 0, bad = 0;
