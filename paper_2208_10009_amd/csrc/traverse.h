@@ -49,10 +49,12 @@ __device__ static inline bool mt_hit(const TriD& T, d3 o, d3 d, double t_lo, dou
     d3 e1 = mk(T.e1x, T.e1y, T.e1z), e2 = mk(T.e2x, T.e2y, T.e2z);
     d3 p = cross(d, e2);
     double det = dot(e1, p);
-    if (det == 0.0) return false;
+    // the first test needs every part of the record (u is discarded when
+    // det = 0), so the compiler issues the record's loads together rather
+    // than loading v0 only after the det test
     d3 s = sub(o, mk(T.v0x, T.v0y, T.v0z));
     double u = dot(s, p) / det;
-    if (!(u >= 0.0)) return false;
+    if ((det == 0.0) | !(u >= 0.0)) return false;
     d3 q = cross(s, e1);
     double v = dot(d, q) / det;
     if (!(v >= 0.0) || !(u + v <= 1.0)) return false;
@@ -128,13 +130,7 @@ __device__ static inline TriD tri_at(const SceneDev& S, const LdsPlan& L, int32_
         return make_tri(q[0], q[1], q[2], q[3], q[4]);
     }
     const double2* q = (const double2*)(S.tris + i);
-    const double2 a = gld(q), b = gld(q + 1), c = gld(q + 2), d = gld(q + 3), e = gld(q + 4);
-    // An empty statement that takes all five pieces: the compiler must issue
-    // the five loads together here, instead of loading the face word first
-    // and the rest only after the face test (two dependent memory trips).
-    asm volatile("" ::"v"(a.x), "v"(a.y), "v"(b.x), "v"(b.y), "v"(c.x), "v"(c.y), "v"(d.x),
-                 "v"(d.y), "v"(e.x), "v"(e.y));
-    return make_tri(a, b, c, d, e);
+    return make_tri(gld(q), gld(q + 1), gld(q + 2), gld(q + 3), gld(q + 4));
 }
 
 struct HitRec {
@@ -299,10 +295,12 @@ __device__ static int32_t traverse(const SceneDev& S, const LdsPlan& L, d3 o, d3
                     tally->tris += 1;
                     if (first_active_lane()) tally->wave_tris += 1;
                 }
-                if (T.face == xa || T.face == xb) continue;
-                if (COUNT) tally->fp64_tris += 1;
+                // the face test joins the result rather than guarding the
+                // test, which would load the face word before the rest
+                const bool skip = (T.face == xa) | (T.face == xb);
+                if (COUNT && !skip) tally->fp64_tris += 1;
                 double t;
-                if (!mt_hit(T, o, d, t_lo, t_hi, &t)) continue;
+                if (!mt_hit(T, o, d, t_lo, t_hi, &t) | skip) continue;
                 if (ANY) {
                     h->pos = i;
                     h->t = t;
