@@ -549,8 +549,9 @@ def test_bvh_options_do_not_change_paths(gpu, orc):
     cfg = scenes.manhattan_config(4, n_rx=24)
     prm = dict(cfg["params"], division_n=90)
     ref_p = ref_t = None
-    for opt in (dict(), dict(max_leaf_size=1, sah_bins=16), dict(sah_bins=64, split_pct=100),
-                dict(max_leaf_size=8, split_pct=400), dict(split_pct=50)):
+    for opt in (dict(), dict(max_leaf_size=1, sah_bins=16), dict(sah_bins=32, split_pct=100),
+                dict(max_leaf_size=8, split_pct=400), dict(split_pct=50),
+                dict(max_leaf_size=3, sah_bins=48)):
         sc = gpu.scene(cfg["scene"], **opt)
         try:
             p, _ = sc.trace(cfg["tx"], cfg["rx"], **prm)
