@@ -186,6 +186,13 @@ struct sbr_context {
     // path before the paths still running move to 512-lane workgroups
     // (SBR_SEG_TAIL; 0: never)
     int32_t seg_tail = 10;
+    // The receiver tree of the last single-job call, kept for the next call
+    // over the same receivers (compared bytewise); rxt_on_device: d_rxnodes
+    // and d_rxperm hold it.
+    std::vector<double> rxt_rx;
+    std::vector<RxNode> rxt_nodes;
+    std::vector<int32_t> rxt_perm;
+    bool rxt_on_device = false;
     int32_t grid_check_log2 = 0;
     bool la3_lds = true;  // stage the scene in LDS for the three-level refinement
     // event and path counts of the last device-memory call, which predict
@@ -577,6 +584,7 @@ struct Call {
     std::vector<int32_t> rx_job;
     std::vector<RxNode> rx_nodes;  // receiver trees of the jobs that have one
     std::vector<int32_t> rx_perm;  // receiver indices in tree-leaf order
+    bool rx_tree_cached = false;   // rx_nodes / rx_perm are the context's kept tree
     const double* rx = nullptr;      // host [n_rx][3] (NULL with only device receivers)
     const double* rx_dev = nullptr;  // device [n_rx][3] when the caller passed device memory
     int32_t n_rx = 0;
@@ -738,11 +746,31 @@ sbr_status add_job(sbr_context* c, Call& call, int32_t scene_idx, const double* 
     J.rx_first = rx_first;
     J.n_rx = n_rx;
     if (n_rx > 0 && n_rx >= c->rx_tree_min) {
-        if (call.rx_perm.size() != (size_t)call.n_rx) {
-            call.rx_perm.resize((size_t)call.n_rx);
-            for (int32_t x = 0; x < call.n_rx; ++x) call.rx_perm[x] = x;
+        // a call whose only receivers are this job's may reuse (or keep) the
+        // tree: it depends on the receivers alone
+        const bool single = rx_first == 0 && n_rx == call.n_rx && call.rx_nodes.empty();
+        const size_t nb = sizeof(double) * 3 * (size_t)n_rx;
+        if (single && c->rxt_rx.size() == 3 * (size_t)n_rx &&
+            memcmp(c->rxt_rx.data(), call.rx, nb) == 0) {
+            call.rx_perm = c->rxt_perm;
+            call.rx_nodes = c->rxt_nodes;
+            call.rx_tree_cached = true;
+            J.rx_root = 0;
+        } else {
+            if (call.rx_perm.size() != (size_t)call.n_rx) {
+                call.rx_perm.resize((size_t)call.n_rx);
+                for (int32_t x = 0; x < call.n_rx; ++x) call.rx_perm[x] = x;
+            }
+            J.rx_root =
+                build_rx_tree(call.rx, call.rx_perm, rx_first, rx_first + n_rx, call.rx_nodes);
+            if (single) {
+                c->rxt_rx.assign(call.rx, call.rx + 3 * (size_t)n_rx);
+                c->rxt_nodes = call.rx_nodes;
+                c->rxt_perm = call.rx_perm;
+                c->rxt_on_device = false;
+                call.rx_tree_cached = true;
+            }
         }
-        J.rx_root = build_rx_tree(call.rx, call.rx_perm, rx_first, rx_first + n_rx, call.rx_nodes);
     }
     const int64_t per = 64 * (int64_t)call.chunk;
     call.n_packets += (ray_count + per - 1) / per;
@@ -800,12 +828,19 @@ sbr_status upload_call(sbr_context* c, Call& call)
     call.dev.rx_nodes = nullptr;
     call.dev.rx_perm = nullptr;
     if (!call.rx_nodes.empty()) {
-        HIPCHK(c, ensure(c->d_rxnodes, sizeof(RxNode) * call.rx_nodes.size()));
-        HIPCHK(c, ensure(c->d_rxperm, sizeof(int32_t) * call.rx_perm.size()));
-        HIPCHK(c, hipMemcpyAsync(c->d_rxnodes.p, call.rx_nodes.data(),
-                                 sizeof(RxNode) * call.rx_nodes.size(), hipMemcpyHostToDevice, st));
-        HIPCHK(c, hipMemcpyAsync(c->d_rxperm.p, call.rx_perm.data(),
-                                 sizeof(int32_t) * call.rx_perm.size(), hipMemcpyHostToDevice, st));
+        // the kept tree is uploaded once; any other tree replaces it there
+        if (!(call.rx_tree_cached && c->rxt_on_device)) {
+            c->rxt_on_device = false;
+            HIPCHK(c, ensure(c->d_rxnodes, sizeof(RxNode) * call.rx_nodes.size()));
+            HIPCHK(c, ensure(c->d_rxperm, sizeof(int32_t) * call.rx_perm.size()));
+            HIPCHK(c, hipMemcpyAsync(c->d_rxnodes.p, call.rx_nodes.data(),
+                                     sizeof(RxNode) * call.rx_nodes.size(), hipMemcpyHostToDevice,
+                                     st));
+            HIPCHK(c, hipMemcpyAsync(c->d_rxperm.p, call.rx_perm.data(),
+                                     sizeof(int32_t) * call.rx_perm.size(), hipMemcpyHostToDevice,
+                                     st));
+            c->rxt_on_device = call.rx_tree_cached;
+        }
         call.dev.rx_nodes = c->d_rxnodes.as<const RxNode>();
         call.dev.rx_perm = c->d_rxperm.as<const int32_t>();
     }

@@ -596,7 +596,7 @@ def test_trace_counters_are_consistent(gpu):
 
 
 def test_trace_counters_receiver_tree(gpu):
-    """Through the receiver ball tree: balls and receivers tested, each wave
+    """Through the receiver box tree: boxes and receivers tested, each wave
     pass of the receiver walk serving 1 to 64 lanes, and the same events as
     testing every receiver."""
     cfg = scenes.manhattan_config(2, n_rx=256)
@@ -614,6 +614,44 @@ def test_trace_counters_receiver_tree(gpu):
     assert t["rx_nodes"] > 0 and 0 < t["rx_tests"] < lin["rx_tests"]
     assert t["wave_rx_steps"] <= t["rx_nodes"] + t["rx_tests"] <= 64 * t["wave_rx_steps"]
     assert t["events"] == lin["events"] and t["segments"] == lin["segments"]
+
+
+def test_receiver_tree_kept_across_calls(gpu):
+    """The context keeps the last single-job call's receiver tree for the next
+    call over the same receivers: calls that alternate between two receiver
+    sets of the same size, a two-job batch over a third (which replaces the
+    tree on the device), and host-array calls all give the bytes of testing
+    every receiver."""
+    import torch
+    from paper_2208_10009_amd import sbr
+    cfg = scenes.manhattan_config(5, n_rx=128)
+    prm = dict(cfg["params"], division_n=60)
+    rng = np.random.default_rng(3)
+    rx_a = np.asarray(cfg["rx"], np.float64)
+    rx_b = rx_a + rng.uniform(-3.0, 3.0, size=rx_a.shape) * np.array([1.0, 1.0, 0.0])
+    base = gpu.tuning()
+    sc = gpu.scene(cfg["scene"])
+    try:
+        gpu.set_tuning(**dict(base, rx_tree_min=1 << 30))
+        ref = {k: sc.trace(cfg["tx"], r, **prm)[0].tobytes() for k, r in (("a", rx_a), ("b", rx_b))}
+        gpu.set_tuning(**dict(base, rx_tree_min=16))
+        jobs = [dict(prm, scene=0, tx=cfg["tx"], rx_first=0, n_rx=64),
+                dict(prm, scene=0, tx=cfg["tx"], rx_first=64, n_rx=64)]
+        for k, use in (("a", "dev"), ("a", "dev"), ("b", "dev"), ("a", "dev"), ("a", "batch"),
+                       ("a", "dev"), ("b", "host"), ("b", "dev"), ("a", "host")):
+            r = rx_a if k == "a" else rx_b
+            if use == "batch":
+                gpu.trace_batch([sc], jobs, rx_b)
+                continue
+            if use == "dev":
+                got, _ = sc.trace_device(cfg["tx"], torch.as_tensor(r, device="cuda"), **prm)
+                got = got.cpu().numpy().reshape(-1).view(sbr.PATH_DTYPE)
+            else:
+                got, _ = sc.trace(cfg["tx"], r, **prm)
+            assert got.tobytes() == ref[k], (k, use)
+    finally:
+        gpu.set_tuning(**base)
+        sc.close()
 
 
 def test_lds_staged_traversal_matches(gpu, orc):
